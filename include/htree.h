@@ -1,0 +1,163 @@
+/*
+ * htree — block-step force evaluation of the tree/Hermite scheme on gfx950.
+ *
+ * Operation (Fukushige & Kawai, Section 2, tree-Hermite steps 1, 4a and 5):
+ * the host builds, at every multiple of the tree interval, a tree whose nodes
+ * are pseudo-particles (mass, centre-of-mass position, velocity, acceleration
+ * and jerk), groups of neighbouring particles, and one interaction list per
+ * group.  Particles and nodes live in one combined memory: indices [0, N) are
+ * particles, [N, N+M) are nodes.  At every block step the caller updates the
+ * corrected particles (step 6), predicts the whole memory to the block time
+ * (step 5, predictor of the 4th-order Hermite scheme), and asks for the
+ * acceleration, jerk and potential of the active particles, each summed over
+ * the list of its group (steps 4a and 5).  ht_force_direct sums over all
+ * particles instead (the original Hermite scheme, same section).
+ *
+ * Pair interaction with Plummer softening (r = x_j - x_i, w = v_j - v_i,
+ * s = r.r + eps^2):  a += m r s^-3/2;  jerk += m (w s^-3/2 - 3 (r.w) r s^-5/2);
+ * pot -= m s^-1/2.  A particle never interacts with itself.
+ *
+ * Precision forms:
+ *   HT_PREC_FP64  — everything in FP64.
+ *   HT_PREC_MIXED — FP64 for times, positions, prediction, x_j - x_i,
+ *                   s = r.r + eps^2 and the acceleration sum; FP32 for
+ *                   s^-1/2, s^-3/2, velocity differences, the jerk terms and
+ *                   the potential, whose FP32 partial sums are folded into
+ *                   FP64 every 32 pairs.  Stored a, jerk and m are FP32.
+ *
+ * Conventions for every entry point:
+ *   - Return HT_OK (0) or a negative ht_status; ht_last_error() then holds a
+ *     message for the calling thread.  Arguments are validated before any
+ *     device work is queued; on error nothing is modified.
+ *   - Host arrays belong to the caller and are never retained after return.
+ *     Vectors are row-major [n][3] doubles.
+ *   - Device memory for the context is one workspace, either supplied by the
+ *     caller (any device allocation of at least ht_workspace_bytes() bytes,
+ *     256-byte aligned) or allocated by the library when NULL is passed.
+ *   - Work is queued on the context's stream.  Calls that return results to
+ *     host arrays synchronise that stream; *_async calls do not.
+ *   - A context is not thread-safe; distinct contexts may be used from
+ *     distinct threads.
+ */
+#ifndef HTREE_H
+#define HTREE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ht_ctx ht_ctx;
+
+typedef enum {
+    HT_OK = 0,
+    HT_EINVAL = -1,  /* malformed argument (sizes, order, NULL, duplicates) */
+    HT_ERANGE = -2,  /* index outside the valid range or over a capacity   */
+    HT_ENOMEM = -3,  /* allocation failed                                   */
+    HT_ESTATE = -4,  /* call out of order (e.g. force before lists/predict) */
+    HT_EHIP = -5     /* HIP runtime error; message names it                 */
+} ht_status;
+
+typedef enum { HT_PREC_FP64 = 0, HT_PREC_MIXED = 1 } ht_precision;
+
+/* How ht_predict is carried out.  FUSED: ht_predict only records t and each
+ * force kernel predicts every j-particle and node it gathers, in registers.
+ * EAGER: ht_predict runs a kernel that predicts the whole combined memory
+ * into separate arrays that force kernels then read. */
+typedef enum { HT_PREDICT_FUSED = 0, HT_PREDICT_EAGER = 1 } ht_predict_mode;
+
+typedef struct {
+    int32_t device;        /* HIP device ordinal                                 */
+    int32_t precision;     /* ht_precision                                       */
+    int32_t predict_mode;  /* ht_predict_mode                                    */
+    int32_t n_max;         /* capacity: particles                                */
+    int32_t node_max;      /* capacity: tree nodes                               */
+    int32_t group_max;     /* capacity: groups (= interaction lists)             */
+    int64_t list_max;      /* capacity: total list entries over all groups      */
+    int32_t active_max;    /* capacity: active particles per force call         */
+    double eps2;           /* softening length squared (>= 0)                    */
+    void *stream;          /* hipStream_t to queue on; NULL = library's own      */
+} ht_config;
+
+/* Bytes of device workspace a context with this configuration needs. */
+int ht_workspace_bytes(const ht_config *cfg, size_t *bytes);
+
+/* Create a context.  d_workspace may be NULL (library allocates) or a device
+ * pointer of at least ht_workspace_bytes() bytes that outlives the context. */
+int ht_create(ht_ctx **out, const ht_config *cfg, void *d_workspace, size_t workspace_bytes);
+int ht_destroy(ht_ctx *ctx);
+
+/* Step 1 / step 6: particles into j-memory.
+ * idx == NULL: full upload of particles 0..n-1; sets N = n, and when N changes
+ *              drops the nodes and lists (they must be set again).
+ * idx != NULL: update particles idx[0..n-1] (each < N, no repeats).
+ * t0[n]: time of each particle's data; m[n]; x, v, a, jerk: [n][3]. */
+int ht_set_j_particles(ht_ctx *ctx, int32_t n, const int32_t *idx, const double *t0, const double *m,
+                       const double *x, const double *v, const double *a, const double *jerk);
+
+/* Same as ht_set_j_particles with idx != NULL, but every pointer is device
+ * memory (same layouts) and the call is asynchronous on the stream. */
+int ht_set_j_particles_async(ht_ctx *ctx, int32_t n, const int32_t *d_idx, const double *d_t0,
+                             const double *d_m, const double *d_x, const double *d_v, const double *d_a,
+                             const double *d_jerk);
+
+/* Step 1: tree nodes as pseudo-particles at combined indices N..N+M-1, all
+ * valid at t_tree.  m[M]; x, v, a, jerk: [M][3].  Invalidates the lists. */
+int ht_set_nodes(ht_ctx *ctx, int32_t n_nodes, double t_tree, const double *m, const double *x,
+                 const double *v, const double *a, const double *jerk);
+
+/* Step 1: groups and their lists.  group_first[G+1] is a strictly increasing
+ * cover of [0, N) (group g holds particles group_first[g]..group_first[g+1]-1);
+ * list_off[G+1] is non-decreasing from 0; entries[list_off[G]] are combined
+ * indices in [0, N+M).  Requires particles and nodes to be set. */
+int ht_set_interaction_lists(ht_ctx *ctx, int32_t n_groups, const int64_t *group_first,
+                             const int64_t *list_off, const int32_t *entries);
+
+/* Step 5 (predictor): predict particles and nodes to block time t. */
+int ht_predict(ht_ctx *ctx, double t);
+
+/* Steps 4a and 5: acc, jerk ([n][3]) and pot ([n]) of the particles
+ * active_ids[0..n-1] (strictly increasing, each < N), summed over their
+ * groups' lists at the predicted time.  n_active == 0 is a no-op. */
+int ht_force(ht_ctx *ctx, int32_t n_active, const int32_t *active_ids, double *acc, double *jerk,
+             double *pot);
+
+/* As ht_force with results written to device arrays, asynchronously. */
+int ht_force_async(ht_ctx *ctx, int32_t n_active, const int32_t *active_ids, double *d_acc,
+                   double *d_jerk, double *d_pot);
+
+/* Direct summation over all N particles (nodes and lists unused). */
+int ht_force_direct(ht_ctx *ctx, int32_t n_active, const int32_t *active_ids, double *acc, double *jerk,
+                    double *pot);
+int ht_force_direct_async(ht_ctx *ctx, int32_t n_active, const int32_t *active_ids, double *d_acc,
+                          double *d_jerk, double *d_pot);
+
+/* Predicted position and velocity ([n][3]) of combined indices idx[0..n-1]
+ * at the current block time, computed by the device predictor. */
+int ht_get_predicted(ht_ctx *ctx, int32_t n, const int32_t *idx, double *xp, double *vp);
+
+/* Force on the active particles of several contexts in one launch (the
+ * batched block step).  All contexts must be on one device with one
+ * precision, predicted, with lists set; results go to device arrays per
+ * context.  Work is queued on ctxs[0]'s stream; each context's result is the
+ * same as from its own ht_force_async call. */
+int ht_force_batch_async(int32_t n_ctx, ht_ctx *const *ctxs, const int32_t *n_active,
+                         const int32_t *const *active_ids, double *const *d_acc, double *const *d_jerk,
+                         double *const *d_pot);
+
+/* Block until the context's queued work has finished. */
+int ht_sync(ht_ctx *ctx);
+
+/* Pair interactions the last force call summed (list entries x active
+ * particles, self pairs included) and the number of work items it used. */
+int ht_last_stats(const ht_ctx *ctx, int64_t *pairs, int32_t *work_items);
+
+/* Message for the last failure on the calling thread ("" if none). */
+const char *ht_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HTREE_H */

@@ -1,0 +1,367 @@
+"""Thin ctypes binding over the native libraries (argument marshalling only).
+
+``libhtree.so`` (include/htree.h) runs every step of the block-step force
+evaluation on the GPU; ``libhtree_host.so`` (include/htree_host.h) builds the
+tree, groups and lists and runs the host's Hermite bookkeeping.  Both must
+have been built in-tree (``python -m paper_1602_02832_amd.build``): there is
+no fallback, a missing library raises.
+
+Names follow the C entry points: ``Context.set_j_particles`` calls
+``ht_set_j_particles`` and so on.  Host arrays are numpy; device arrays are
+torch CUDA tensors (PyTorch provides device memory and streams only).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+__all__ = ["HTError", "Context", "HostTree", "force_batch_async", "hilbert_keys", "next_block",
+           "correct", "initial_steps", "device_lib", "host_lib"]
+
+HT_PREC = {"fp64": 0, "mixed": 1}
+HT_PREDICT = {"fused": 0, "eager": 1}
+
+_c_i32p = ctypes.POINTER(ctypes.c_int32)
+_c_i64p = ctypes.POINTER(ctypes.c_int64)
+_c_u32p = ctypes.POINTER(ctypes.c_uint32)
+_c_u64p = ctypes.POINTER(ctypes.c_uint64)
+_c_dp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+
+
+class HTError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"htree error {code}: {message}")
+        self.code = code
+
+
+class HtConfig(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("precision", ctypes.c_int32), ("predict_mode", ctypes.c_int32),
+                ("n_max", ctypes.c_int32), ("node_max", ctypes.c_int32), ("group_max", ctypes.c_int32),
+                ("list_max", ctypes.c_int64), ("active_max", ctypes.c_int32), ("eps2", ctypes.c_double),
+                ("stream", ctypes.c_void_p)]
+
+
+_dev = None
+_host = None
+
+
+def _load(path):
+    if not os.path.exists(path):
+        raise RuntimeError(f"{os.path.basename(path)} is not built; run `python -m paper_1602_02832_amd.build`")
+    return ctypes.CDLL(path)
+
+
+def device_lib():
+    global _dev
+    if _dev is None:
+        L = _load(_build.DEVICE_LIB)
+        i, i64, d = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        sig = {
+            "ht_workspace_bytes": [ctypes.POINTER(HtConfig), ctypes.POINTER(ctypes.c_size_t)],
+            "ht_create": [ctypes.POINTER(_vp), ctypes.POINTER(HtConfig), _vp, ctypes.c_size_t],
+            "ht_destroy": [_vp],
+            "ht_set_j_particles": [_vp, i, _c_i32p, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp],
+            "ht_set_j_particles_async": [_vp, i, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+            "ht_set_nodes": [_vp, i, d, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp],
+            "ht_set_interaction_lists": [_vp, i, _c_i64p, _c_i64p, _c_i32p],
+            "ht_predict": [_vp, d],
+            "ht_force": [_vp, i, _c_i32p, _c_dp, _c_dp, _c_dp],
+            "ht_force_async": [_vp, i, _c_i32p, _vp, _vp, _vp],
+            "ht_force_direct": [_vp, i, _c_i32p, _c_dp, _c_dp, _c_dp],
+            "ht_force_direct_async": [_vp, i, _c_i32p, _vp, _vp, _vp],
+            "ht_get_predicted": [_vp, i, _c_i32p, _c_dp, _c_dp],
+            "ht_force_batch_async": [i, ctypes.POINTER(_vp), _c_i32p, ctypes.POINTER(_c_i32p),
+                                     ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp)],
+            "ht_sync": [_vp],
+            "ht_last_stats": [_vp, _c_i64p, _c_i32p],
+            "ht_last_error": [],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_char_p if name == "ht_last_error" else ctypes.c_int
+        _ = i64
+        _dev = L
+    return _dev
+
+
+def host_lib():
+    global _host
+    if _host is None:
+        L = _load(_build.HOST_LIB)
+        i, i64, d = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        sig = {
+            "htb_build": [ctypes.POINTER(_vp), i64, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp, i, i, d],
+            "htb_sizes": [_vp, _c_i64p, _c_i64p, _c_i64p],
+            "htb_get": [_vp, _c_i64p, _c_u64p, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp, _c_i32p, _c_i64p, _c_i64p,
+                        _c_i64p, _c_i64p, _c_i32p],
+            "htb_free": [_vp],
+            "htb_hilbert_keys": [i64, _c_u32p, _c_u64p],
+            "htb_next_block": [i64, _c_dp, _c_dp, _c_dp, _c_i32p, _c_i64p],
+            "htb_correct": [i64, _c_i32p, d, d, d, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp],
+            "htb_initial_steps": [i64, d, d, _c_dp, _c_dp, _c_dp],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = None if name == "htb_free" else ctypes.c_int
+        _host = L
+    return _host
+
+
+def _check(rc: int):
+    if rc != 0:
+        msg = device_lib().ht_last_error()
+        raise HTError(rc, msg.decode() if msg else "")
+
+
+def _arr(a, dtype, shape=None):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype)) if a is not None else None
+
+
+def _dptr(t):
+    """Device address of a torch tensor (or an int address, or None)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+# --------------------------------------------------------------------------------------------- device
+class Context:
+    """One cluster's j-memory, lists and work buffers on one GPU (ht_ctx)."""
+
+    def __init__(self, *, n_max, node_max, group_max, list_max, active_max, eps2, precision="fp64",
+                 predict_mode="fused", device=0, stream=None, torch_workspace=True):
+        L = device_lib()
+        self.cfg = HtConfig(device, HT_PREC[precision], HT_PREDICT[predict_mode], int(n_max), int(node_max),
+                            int(group_max), int(list_max), int(active_max), float(eps2),
+                            None if stream is None else int(stream))
+        self.precision = precision
+        nbytes = ctypes.c_size_t()
+        _check(L.ht_workspace_bytes(ctypes.byref(self.cfg), ctypes.byref(nbytes)))
+        self.workspace_bytes = nbytes.value
+        self._ws = None
+        ws_ptr = None
+        if torch_workspace:
+            import torch
+            self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=f"cuda:{device}")
+            ws_ptr = self._ws.data_ptr()
+        h = _vp()
+        _check(L.ht_create(ctypes.byref(h), ctypes.byref(self.cfg), ws_ptr, self.workspace_bytes))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            device_lib().ht_destroy(self._h)
+            self._h = None
+            self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_j_particles(self, t0, m, x, v, a, jerk, idx=None):
+        m = _arr(m, np.float64)
+        n = m.shape[0]
+        t0 = _arr(np.broadcast_to(t0, (n,)), np.float64)
+        x, v, a, jerk = (_arr(u, np.float64, (n, 3)) for u in (x, v, a, jerk))
+        idx = None if idx is None else _arr(idx, np.int32)
+        d = ctypes.c_double
+        _check(device_lib().ht_set_j_particles(self._h, n, _ptr(idx, ctypes.c_int32), _ptr(t0, d), _ptr(m, d),
+                                               _ptr(x, d), _ptr(v, d), _ptr(a, d), _ptr(jerk, d)))
+
+    def set_j_particles_async(self, n, d_idx, d_t0, d_m, d_x, d_v, d_a, d_jerk):
+        _check(device_lib().ht_set_j_particles_async(self._h, int(n), *(_dptr(t) for t in
+                                                                         (d_idx, d_t0, d_m, d_x, d_v, d_a, d_jerk))))
+
+    def set_nodes(self, t_tree, m, x, v, a, jerk):
+        m = _arr(m, np.float64)
+        n = m.shape[0]
+        x, v, a, jerk = (_arr(u, np.float64, (n, 3)) for u in (x, v, a, jerk))
+        d = ctypes.c_double
+        _check(device_lib().ht_set_nodes(self._h, n, float(t_tree), _ptr(m, d), _ptr(x, d), _ptr(v, d), _ptr(a, d),
+                                         _ptr(jerk, d)))
+
+    def set_interaction_lists(self, group_first, list_off, entries):
+        gf = _arr(group_first, np.int64)
+        lo = _arr(list_off, np.int64)
+        en = _arr(entries, np.int32)
+        _check(device_lib().ht_set_interaction_lists(self._h, gf.shape[0] - 1, _ptr(gf, ctypes.c_int64),
+                                                     _ptr(lo, ctypes.c_int64), _ptr(en, ctypes.c_int32)))
+
+    def predict(self, t):
+        _check(device_lib().ht_predict(self._h, float(t)))
+
+    def _force_host(self, fn, active):
+        active = _arr(active, np.int32)
+        k = active.shape[0]
+        acc = np.empty((k, 3))
+        jerk = np.empty((k, 3))
+        pot = np.empty(k)
+        d = ctypes.c_double
+        _check(fn(self._h, k, _ptr(active, ctypes.c_int32), _ptr(acc, d), _ptr(jerk, d), _ptr(pot, d)))
+        return acc, jerk, pot
+
+    def force(self, active):
+        return self._force_host(device_lib().ht_force, active)
+
+    def force_direct(self, active):
+        return self._force_host(device_lib().ht_force_direct, active)
+
+    def force_async(self, active, d_acc, d_jerk, d_pot):
+        active = _arr(active, np.int32)
+        _check(device_lib().ht_force_async(self._h, active.shape[0], _ptr(active, ctypes.c_int32), _dptr(d_acc),
+                                           _dptr(d_jerk), _dptr(d_pot)))
+
+    def force_direct_async(self, active, d_acc, d_jerk, d_pot):
+        active = _arr(active, np.int32)
+        _check(device_lib().ht_force_direct_async(self._h, active.shape[0], _ptr(active, ctypes.c_int32),
+                                                  _dptr(d_acc), _dptr(d_jerk), _dptr(d_pot)))
+
+    def get_predicted(self, idx):
+        idx = _arr(idx, np.int32)
+        n = idx.shape[0]
+        xp = np.empty((n, 3))
+        vp = np.empty((n, 3))
+        d = ctypes.c_double
+        _check(device_lib().ht_get_predicted(self._h, n, _ptr(idx, ctypes.c_int32), _ptr(xp, d), _ptr(vp, d)))
+        return xp, vp
+
+    def sync(self):
+        _check(device_lib().ht_sync(self._h))
+
+    def last_stats(self):
+        p = ctypes.c_int64()
+        w = ctypes.c_int32()
+        _check(device_lib().ht_last_stats(self._h, ctypes.byref(p), ctypes.byref(w)))
+        return p.value, w.value
+
+
+def force_batch_async(ctxs, actives, d_accs, d_jerks, d_pots):
+    """ht_force_batch_async over several contexts sharing one stream."""
+    n = len(ctxs)
+    acts = [_arr(a, np.int32) for a in actives]
+    H = (_vp * n)(*[c.handle for c in ctxs])
+    N = (ctypes.c_int32 * n)(*[a.shape[0] for a in acts])
+    P = (_c_i32p * n)(*[_ptr(a, ctypes.c_int32) for a in acts])
+    A = (_vp * n)(*[_dptr(t) for t in d_accs])
+    J = (_vp * n)(*[_dptr(t) for t in d_jerks])
+    Q = (_vp * n)(*[_dptr(t) for t in d_pots])
+    _check(device_lib().ht_force_batch_async(n, H, N, P, A, J, Q))
+    return acts  # keep host arrays alive until the caller syncs
+
+
+# ----------------------------------------------------------------------------------------------- host
+class HostTree:
+    """Tree, node moments, groups and lists (htb_build), copied into numpy arrays."""
+
+    def __init__(self, x, v, a, jerk, m, n_leaf: int, n_crit: int, theta: float):
+        L = host_lib()
+        x = _arr(x, np.float64, (-1, 3))
+        n = x.shape[0]
+        v, a, jerk = (_arr(u, np.float64, (n, 3)) for u in (v, a, jerk))
+        m = _arr(m, np.float64, (n,))
+        d = ctypes.c_double
+        h = _vp()
+        rc = L.htb_build(ctypes.byref(h), n, _ptr(x, d), _ptr(v, d), _ptr(a, d), _ptr(jerk, d), _ptr(m, d),
+                         int(n_leaf), int(n_crit), float(theta))
+        if rc != 0:
+            raise HTError(rc, "htb_build failed")
+        try:
+            M, G, E = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+            L.htb_sizes(h, ctypes.byref(M), ctypes.byref(G), ctypes.byref(E))
+            M, G, E = M.value, G.value, E.value
+            self.n, self.n_node, self.n_group, self.n_entries = n, M, G, E
+            self.perm = np.empty(n, np.int64)
+            self.keys = np.empty(n, np.uint64)
+            self.node_m = np.empty(M)
+            self.node_x, self.node_v, self.node_a, self.node_j = (np.empty((M, 3)) for _ in range(4))
+            self.node_level = np.empty(M, np.int32)
+            self.node_begin = np.empty(M, np.int64)
+            self.node_end = np.empty(M, np.int64)
+            self.group_first = np.empty(G + 1, np.int64)
+            self.list_off = np.empty(G + 1, np.int64)
+            self.entries = np.empty(E, np.int32)
+            L.htb_get(h, _ptr(self.perm, ctypes.c_int64), _ptr(self.keys, ctypes.c_uint64), _ptr(self.node_m, d),
+                      _ptr(self.node_x, d), _ptr(self.node_v, d), _ptr(self.node_a, d), _ptr(self.node_j, d),
+                      _ptr(self.node_level, ctypes.c_int32), _ptr(self.node_begin, ctypes.c_int64),
+                      _ptr(self.node_end, ctypes.c_int64), _ptr(self.group_first, ctypes.c_int64),
+                      _ptr(self.list_off, ctypes.c_int64), _ptr(self.entries, ctypes.c_int32))
+        finally:
+            L.htb_free(h)
+
+    def list_of(self, g):
+        return self.entries[self.list_off[g]:self.list_off[g + 1]]
+
+
+def hilbert_keys(q):
+    q = _arr(q, np.uint32, (-1, 3))
+    out = np.empty(q.shape[0], np.uint64)
+    rc = host_lib().htb_hilbert_keys(q.shape[0], _ptr(q, ctypes.c_uint32), _ptr(out, ctypes.c_uint64))
+    if rc:
+        raise HTError(rc, "htb_hilbert_keys failed")
+    return out
+
+
+def next_block(t0, dt, out=None):
+    """(t_next, active ids) of the next block step; t0, dt float64 [n]."""
+    n = t0.shape[0]
+    out = np.empty(n, np.int32) if out is None else out
+    tn = ctypes.c_double()
+    k = ctypes.c_int64()
+    d = ctypes.c_double
+    rc = host_lib().htb_next_block(n, _ptr(t0, d), _ptr(dt, d), ctypes.byref(tn), _ptr(out, ctypes.c_int32),
+                                   ctypes.byref(k))
+    if rc:
+        raise HTError(rc, "htb_next_block failed")
+    return tn.value, out[:k.value]
+
+
+def correct(ids, t1, eta, dt_tree, t0, dt, x, v, a, jerk, acc1, jerk1):
+    """Hermite corrector + block step for particles ids (arrays updated in place)."""
+    ids = _arr(ids, np.int32)
+    acc1 = _arr(acc1, np.float64, (-1, 3))
+    jerk1 = _arr(jerk1, np.float64, (-1, 3))
+    for arr in (t0, dt, x, v, a, jerk):
+        assert arr.dtype == np.float64 and arr.flags.c_contiguous
+    d = ctypes.c_double
+    rc = host_lib().htb_correct(ids.shape[0], _ptr(ids, ctypes.c_int32), float(t1), float(eta), float(dt_tree),
+                                _ptr(t0, d), _ptr(dt, d), _ptr(x, d), _ptr(v, d), _ptr(a, d), _ptr(jerk, d),
+                                _ptr(acc1, d), _ptr(jerk1, d))
+    if rc == -2:
+        raise FloatingPointError("block step below 2^-40")
+    if rc:
+        raise HTError(rc, "htb_correct failed")
+
+
+def initial_steps(eta, dt_tree, a, jerk):
+    a = _arr(a, np.float64, (-1, 3))
+    jerk = _arr(jerk, np.float64, (-1, 3))
+    dt = np.empty(a.shape[0])
+    d = ctypes.c_double
+    rc = host_lib().htb_initial_steps(a.shape[0], float(eta), float(dt_tree), _ptr(a, d), _ptr(jerk, d), _ptr(dt, d))
+    if rc == -2:
+        raise FloatingPointError("initial block step below 2^-40")
+    if rc:
+        raise HTError(rc, "htb_initial_steps failed")
+    return dt

@@ -1,0 +1,56 @@
+"""Compile the native libraries in-tree.
+
+  libhtree.so       HIP kernels + C-ABI (include/htree.h), gfx950 only
+  libhtree_host.so  host tree/list builder and Hermite corrector (include/htree_host.h)
+
+Run ``python -m paper_1602_02832_amd.build``.  Every call recompiles.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+
+DEVICE_LIB = os.path.join(PKG, "libhtree.so")
+HOST_LIB = os.path.join(PKG, "libhtree_host.so")
+
+# packed FP32 instructions are never generated (build policy for this device)
+HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}", "-Wall",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", f"-I{INCLUDE}"]
+HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-Wall", f"-I{INCLUDE}"]
+
+
+def _run(cmd, verbose):
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+
+
+def build_device(verbose: bool = False) -> str:
+    tmp = DEVICE_LIB + ".tmp"
+    _run([HIPCC, *HIP_FLAGS, "-o", tmp, os.path.join(CSRC, "htree.hip")], verbose)
+    os.replace(tmp, DEVICE_LIB)
+    return DEVICE_LIB
+
+
+def build_host(verbose: bool = False) -> str:
+    tmp = HOST_LIB + ".tmp"
+    _run(["g++", *HOST_FLAGS, "-o", tmp, os.path.join(CSRC, "hosttree.cpp")], verbose)
+    os.replace(tmp, HOST_LIB)
+    return HOST_LIB
+
+
+def build(verbose: bool = False) -> None:
+    build_host(verbose)
+    build_device(verbose)
+
+
+if __name__ == "__main__":
+    build(verbose="-q" not in sys.argv)

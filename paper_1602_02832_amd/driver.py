@@ -1,0 +1,178 @@
+"""Tree/Hermite block-step integration with the force evaluated on the GPU.
+
+The procedure is the paper's tree-Hermite loop (Section 2, steps 1-7):
+
+  1. at every multiple of the tree interval (and at t = 0) the host builds
+     the tree, groups and lists and sends particles, nodes and lists;
+  2. the host selects the particles due at the next block time;
+  4/4a/5. the device predicts particles and nodes and sums each active
+     particle's list;
+  6. the host corrects the active particles, picks their new block steps and
+     sends them back (j-memory update);
+  7. time advances.
+
+All particles are synchronised at multiples of the tree interval because
+the largest block step equals that interval, so every rebuild happens at an
+all-active step, after it has been corrected.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+from . import binding as B
+
+
+class Simulation:
+    def __init__(self, x, v, m, *, eps2, dt_tree, eta, theta=0.5, n_crit=64, n_leaf=1, precision="mixed",
+                 predict_mode="fused", mode="tree", device=0, stream=None, list_headroom=1.5):
+        if mode not in ("tree", "direct"):
+            raise ValueError(mode)
+        if not (dt_tree > 0 and math.frexp(dt_tree)[0] == 0.5):
+            raise ValueError("dt_tree must be a power of two")
+        self.x = np.ascontiguousarray(x, np.float64).reshape(-1, 3).copy()
+        self.n = self.x.shape[0]
+        self.v = np.ascontiguousarray(v, np.float64).reshape(self.n, 3).copy()
+        self.m = np.ascontiguousarray(m, np.float64).reshape(self.n).copy()
+        self.a = np.zeros((self.n, 3))
+        self.j = np.zeros((self.n, 3))
+        self.t0 = np.zeros(self.n)
+        self.dt = np.zeros(self.n)
+        self.ids = np.arange(self.n)
+        self.pot = np.zeros(self.n)
+        self.eps2, self.dt_tree, self.eta = float(eps2), float(dt_tree), float(eta)
+        self.theta, self.n_crit, self.n_leaf = float(theta), int(n_crit), int(n_leaf)
+        self.precision, self.predict_mode, self.mode = precision, predict_mode, mode
+        self.device, self.stream, self.list_headroom = device, stream, list_headroom
+        self.t = 0.0
+        self.t_tree = 0.0
+        self.ctx = None
+        self.tree = None
+        self._ectx = None
+        self._act_buf = np.empty(self.n, np.int32)
+        self.n_block_steps = 0
+        self.n_particle_steps = 0
+        self.n_interactions = 0
+        self.timers = {"tree": 0.0, "force": 0.0, "host": 0.0, "comm": 0.0}
+        self._build_and_send()
+        everyone = np.arange(self.n, dtype=np.int32)
+        self.ctx.predict(0.0)
+        acc, jerk, pot = self._force(everyone)
+        self.a, self.j, self.pot = acc, jerk, pot
+        self._build_and_send()           # nodes now carry a and jerk; order unchanged
+        self.dt = B.initial_steps(self.eta, self.dt_tree, self.a, self.j)
+
+    # ------------------------------------------------------------------ context
+    def _make_ctx(self, node_max, group_max, list_max):
+        if self.ctx is not None:
+            self.ctx.close()
+        self.ctx = B.Context(n_max=self.n, node_max=node_max, group_max=group_max, list_max=list_max,
+                             active_max=self.n, eps2=self.eps2, precision=self.precision,
+                             predict_mode=self.predict_mode, device=self.device, stream=self.stream)
+        self._caps = (node_max, group_max, list_max)
+
+    # ------------------------------------------------------------------ step 1
+    def _build_and_send(self):
+        t_start = time.perf_counter()
+        if self.mode == "tree":
+            tr = B.HostTree(self.x, self.v, self.a, self.j, self.m, self.n_leaf, self.n_crit, self.theta)
+            p = tr.perm
+            if not np.array_equal(p, np.arange(self.n)):
+                for name in ("x", "v", "a", "j", "m", "t0", "dt", "ids", "pot"):
+                    setattr(self, name, np.ascontiguousarray(getattr(self, name)[p]))
+            self.tree = tr
+            need = (tr.n_node, tr.n_group, tr.n_entries)
+        else:
+            self.tree = None
+            need = (0, 1, 1)
+        self.t_tree = self.t
+        self.timers["tree"] += time.perf_counter() - t_start
+        t_start = time.perf_counter()
+        caps = getattr(self, "_caps", None)
+        if caps is None or any(n > c for n, c in zip(need, caps)):
+            h = self.list_headroom
+            self._make_ctx(max(int(need[0] * h), 64), max(int(need[1] * h), 16), max(int(need[2] * h), 1024))
+        ctx = self.ctx
+        ctx.set_j_particles(self.t0, self.m, self.x, self.v, self.a, self.j)
+        if self.mode == "tree":
+            tr = self.tree
+            ctx.set_nodes(self.t_tree, tr.node_m, tr.node_x, tr.node_v, tr.node_a, tr.node_j)
+            ctx.set_interaction_lists(tr.group_first, tr.list_off, tr.entries)
+        else:
+            ctx.set_nodes(self.t_tree, np.zeros(0), np.zeros((0, 3)), np.zeros((0, 3)), np.zeros((0, 3)),
+                          np.zeros((0, 3)))
+        self.timers["comm"] += time.perf_counter() - t_start
+
+    # ------------------------------------------------------------------ steps 4a/5
+    def _force(self, active):
+        t_start = time.perf_counter()
+        if self.mode == "tree":
+            out = self.ctx.force(active)
+        else:
+            out = self.ctx.force_direct(active)
+        pairs, _ = self.ctx.last_stats()
+        self.n_interactions += pairs
+        self.timers["force"] += time.perf_counter() - t_start
+        return out
+
+    def next_time(self):
+        return float(np.min(self.t0 + self.dt))
+
+    def step(self):
+        """One block step; returns (t, active ids)."""
+        t_start = time.perf_counter()
+        tn, active = B.next_block(self.t0, self.dt, self._act_buf)
+        active = active.copy()
+        self.timers["host"] += time.perf_counter() - t_start
+        self.ctx.predict(tn)
+        acc, jerk, pot = self._force(active)
+        t_start = time.perf_counter()
+        B.correct(active, tn, self.eta, self.dt_tree, self.t0, self.dt, self.x, self.v, self.a, self.j, acc, jerk)
+        self.pot[active] = pot
+        self.timers["host"] += time.perf_counter() - t_start
+        self.t = tn
+        self.n_block_steps += 1
+        self.n_particle_steps += active.size
+        if math.fmod(tn, self.dt_tree) == 0.0:
+            if not np.all(self.t0 == tn):
+                raise AssertionError("particles not synchronised at a tree time")
+            self._build_and_send()
+        else:
+            t_start = time.perf_counter()
+            self.ctx.set_j_particles(self.t0[active], self.m[active], self.x[active], self.v[active],
+                                     self.a[active], self.j[active], idx=active)
+            self.timers["comm"] += time.perf_counter() - t_start
+        return tn, active
+
+    def run(self, t_end, on_step=None):
+        while self.next_time() <= t_end:
+            tn, act = self.step()
+            if on_step is not None:
+                on_step(self, tn, act)
+        return self
+
+    # ------------------------------------------------------------------ diagnostics
+    def energy(self):
+        """Total energy at the current (synchronised) time: kinetic on the host,
+        potential by direct summation on the GPU in FP64 (Section 3 computes
+        the potential energy directly, not with the tree)."""
+        if not np.all(self.t0 == self.t):
+            raise ValueError("energy needs all particles at the same time")
+        if self._ectx is None:
+            self._ectx = B.Context(n_max=self.n, node_max=0, group_max=1, list_max=1, active_max=self.n,
+                                   eps2=self.eps2, precision="fp64", device=self.device)
+        z = np.zeros((self.n, 3))
+        self._ectx.set_j_particles(self.t0, self.m, self.x, self.v, z, z)
+        self._ectx.predict(self.t)
+        _, _, pot = self._ectx.force_direct(np.arange(self.n, dtype=np.int32))
+        K = 0.5 * float(np.sum(self.m * np.einsum("ij,ij->i", self.v, self.v)))
+        W = 0.5 * float(np.sum(self.m * pot))
+        return K + W
+
+    def close(self):
+        for c in (self.ctx, self._ectx):
+            if c is not None:
+                c.close()
+        self.ctx = self._ectx = None

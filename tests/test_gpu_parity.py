@@ -1,0 +1,341 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 oracle.
+
+The oracle integrates; at each block step the j-memory state it used (its
+particles, its nodes, lists rebuilt by the product builder and checked
+bit-identical to the oracle's) is loaded into GPU contexts, predicted and
+summed, and compared element by element with the oracle's forces.
+
+Tolerances (per particle, relative to that particle's own magnitude):
+  FP64 form   acc, jerk, pot <= 1e-12
+  mixed form  acc <= 2e-6, jerk <= 1e-5, pot <= 1e-6
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1602_02832_amd import binding as B
+from paper_1602_02832_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": (1e-12, 1e-12, 1e-12), "mixed": (2e-6, 1e-5, 1e-6)}
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel_rows(got, want):
+    got = np.asarray(got).reshape(len(want), -1)
+    want = np.asarray(want).reshape(len(want), -1)
+    return np.linalg.norm(got - want, axis=1) / np.maximum(np.linalg.norm(want, axis=1), 1e-300)
+
+
+def errors(got, want):
+    return tuple(float(rel_rows(g, w).max()) if len(w) else 0.0 for g, w in zip(got, want))
+
+
+def assert_close(tag, prec, got, want):
+    ea, ej, ep = errors(got, want)
+    ta, tj, tp = TOL[prec]
+    assert ea <= ta and ej <= tj and ep <= tp, f"{tag} {prec}: acc {ea:.3g} jerk {ej:.3g} pot {ep:.3g}"
+    return ea, ej, ep
+
+
+def make_ctx(prec, n, node_max, group_max, list_max, eps2, mode="fused"):
+    return B.Context(n_max=n, node_max=node_max, group_max=group_max, list_max=list_max, active_max=n, eps2=eps2,
+                     precision=prec, predict_mode=mode)
+
+
+class Replayer:
+    """Loads an oracle run's j-memory into GPU contexts and checks each step."""
+
+    def __init__(self, oracle, sim, precs, modes=("fused",), list_max=None):
+        self.O, self.sim = oracle, sim
+        n = sim.n
+        lm = list_max or max(4 * sim.tree.n_entries, 4096)
+        self.ctxs = {(p, md): make_ctx(p, n, 4 * n + 64, n, lm, sim.eps2, md) for p in precs for md in modes}
+        self.tree_seen = None
+        self.worst = {k: (0.0, 0.0, 0.0) for k in self.ctxs}
+        self.steps = 0
+        self.sync_tree()
+
+    def sync_tree(self):
+        sim = self.sim
+        if sim.tree is self.tree_seen:
+            return
+        got = B.HostTree(sim.x, sim.v, sim.a, sim.j, sim.m, sim.n_leaf, sim.n_crit, sim.theta)
+        assert np.array_equal(got.perm, np.arange(sim.n))
+        for f in ("node_m", "node_x", "node_v", "node_a", "node_j", "group_first", "list_off", "entries"):
+            assert np.array_equal(getattr(got, f), getattr(sim.tree, f)), f"product {f} differs at t={sim.t}"
+        for c in self.ctxs.values():
+            c.set_j_particles(sim.t0, sim.m, sim.x, sim.v, sim.a, sim.j)
+            c.set_nodes(sim.t_tree, got.node_m, got.node_x, got.node_v, got.node_a, got.node_j)
+            c.set_interaction_lists(got.group_first, got.list_off, got.entries)
+        self.tree_seen = sim.tree
+
+    def hook(self, sim, rec):
+        want = (rec["acc"], rec["jerk"], rec["pot"])
+        for (p, md), c in self.ctxs.items():
+            c.set_j_particles(sim.t0, sim.m, sim.x, sim.v, sim.a, sim.j)
+            c.predict(rec["t"])
+            got = c.force(rec["active"])
+            e = assert_close(f"t={rec['t']} n_active={rec['active'].size}", p, got, want)
+            self.worst[(p, md)] = tuple(max(a, b) for a, b in zip(self.worst[(p, md)], e))
+        self.steps += 1
+
+    def run(self, t_end):
+        while self.sim.next_time() <= t_end:
+            self.sim.step()
+            self.sync_tree()
+        return self
+
+
+# ------------------------------------------------------------------------------------------ predictor
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_predictor_matches_oracle(oracle, prec):
+    say(f"predictor {prec}")
+    n = 5000
+    x, v, m = W.plummer(n, 31)
+    t_now = 37.0 / 256
+    t0, a, j = W.random_block_state(n, 32, t_now)
+    if prec == "mixed":   # the mixed form stores a and jerk in FP32
+        a, j = a.astype(np.float32).astype(np.float64), j.astype(np.float32).astype(np.float64)
+    c = make_ctx(prec, n, 16, 1, 16, 1e-4)
+    c.set_j_particles(t0, m, x, v, a, j)
+    c.set_nodes(0.0, np.zeros(0), *(np.zeros((0, 3)) for _ in range(4)))
+    c.predict(t_now)
+    xp, vp = c.get_predicted(np.arange(n, dtype=np.int32))
+    wx, wv = oracle.predict(t_now, t0, x, v, a, j)
+    assert np.max(np.abs(xp - wx)) <= 1e-15 * np.max(np.abs(wx)) * 4
+    assert np.max(np.abs(vp - wv)) <= 1e-15 * np.max(np.abs(wv)) * 4
+
+
+# ------------------------------------------------------------------------------------------ C1, every step
+def test_parity_plummer2k_every_block_step(oracle):
+    c = W.config("plummer2k")
+    say(f"plummer2k every block step to t={c.t_end}")
+    x, v, m = W.make_initial_conditions(c)
+    rp = {}
+
+    def hook(sim, rec):
+        rp["r"].hook(sim, rec)
+
+    sim = oracle.TreeHermite(x, v, m, eps2=c.eps2, dt_tree=c.dt_tree, eta=c.eta, theta=c.theta, n_crit=c.n_crit,
+                             on_step=hook)
+    rp["r"] = Replayer(oracle, sim, ("fp64", "mixed"), modes=("fused", "eager"))
+    rp["r"].run(c.t_end)
+    say(f"steps {rp['r'].steps} worst {rp['r'].worst}")
+    assert rp["r"].steps > 100 and sim.t == c.t_end
+
+
+# ------------------------------------------------------------------------------------------ C2, first tree interval
+def test_parity_plummer16k_first_tree_interval(oracle):
+    c = W.config("plummer16k")
+    say("plummer16k first two tree intervals")
+    x, v, m = W.make_initial_conditions(c)
+    rp = {}
+
+    def hook(sim, rec):
+        rp["r"].hook(sim, rec)
+
+    sim = oracle.TreeHermite(x, v, m, eps2=c.eps2, dt_tree=c.dt_tree, eta=c.eta, theta=c.theta, n_crit=c.n_crit,
+                             on_step=hook)
+    rp["r"] = Replayer(oracle, sim, ("fp64", "mixed"))
+    rp["r"].run(2 * c.dt_tree)
+    say(f"steps {rp['r'].steps} worst {rp['r'].worst}")
+    assert rp["r"].steps > 5
+
+
+# ------------------------------------------------------------------------------------------ direct
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_direct_matches_oracle(oracle, prec):
+    say(f"direct {prec}")
+    n = 3000
+    x, v, m = W.plummer(n, 41)
+    m = W.salpeter_masses(n, 42)
+    t0, a, j = W.random_block_state(n, 43, 0.25)
+    c = make_ctx(prec, n, 16, 1, 16, 1e-5)
+    c.set_j_particles(t0, m, x, v, a, j)
+    c.set_nodes(0.0, np.zeros(0), *(np.zeros((0, 3)) for _ in range(4)))
+    c.predict(0.25)
+    if prec == "mixed":
+        a, j = a.astype(np.float32).astype(np.float64), j.astype(np.float32).astype(np.float64)
+        m32 = m.astype(np.float32).astype(np.float64)
+    else:
+        m32 = m
+    xp, vp = oracle.predict(0.25, t0, x, v, a, j)
+    for ids in (np.arange(n), np.array([0]), np.arange(5, 3000, 7), np.arange(1, 258), np.array([n - 1])):
+        ids = ids.astype(np.int32)
+        got = c.force_direct(ids)
+        want = oracle.force_direct(ids, xp, vp, m32, 1e-5)
+        assert_close(f"direct n_active={ids.size}", prec, got, want)
+
+
+# ------------------------------------------------------------------------------------------ tiles and edges
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_ragged_tiles_and_sparse_sets(oracle, prec):
+    """Active sets whose per-group counts hit every tile size and its edges."""
+    say(f"ragged tiles {prec}")
+    n = 6000
+    x, v, m = W.plummer(n, 51)
+    z = np.zeros((n, 3))
+    tr = oracle.Tree(x, v, z, z, m, 1, 700, 0.6)
+    x, v, m = x[tr.perm], v[tr.perm], m[tr.perm]
+    t0, a, j = W.random_block_state(n, 52, 5.0 / 128)
+    ptr = B.HostTree(x, v, z, z, m, 1, 700, 0.6)
+    assert np.array_equal(ptr.entries, tr.entries)
+    c = make_ctx(prec, n, 2 * n, n, 2 * tr.n_entries, 1e-4)
+    c.set_j_particles(t0, m, x, v, a, j)
+    c.set_nodes(0.0, ptr.node_m, ptr.node_x, ptr.node_v, ptr.node_a, ptr.node_j)
+    c.set_interaction_lists(ptr.group_first, ptr.list_off, ptr.entries)
+    c.predict(5.0 / 128)
+    if prec == "mixed":
+        a, j = a.astype(np.float32).astype(np.float64), j.astype(np.float32).astype(np.float64)
+        mj = np.concatenate([m, ptr.node_m]).astype(np.float32).astype(np.float64)
+        na = ptr.node_a.astype(np.float32).astype(np.float64)
+        nj = ptr.node_j.astype(np.float32).astype(np.float64)
+    else:
+        mj = np.concatenate([m, ptr.node_m])
+        na, nj = ptr.node_a, ptr.node_j
+    xp, vp = oracle.predict(5.0 / 128, t0, x, v, a, j)
+    nxp, nvp = oracle.predict(5.0 / 128, 0.0, ptr.node_x, ptr.node_v, na, nj)
+    XP, VP = np.vstack([xp, nxp]), np.vstack([vp, nvp])
+    gf = ptr.group_first
+    rng = np.random.default_rng(9)
+    counts = [1, 2, 3, 5, 15, 17, 31, 33, 63, 64, 65, 127, 129, 255, 256, 257, 511, 513]
+    sel = []
+    for g in range(ptr.n_group):
+        size = gf[g + 1] - gf[g]
+        k = min(size, counts[g % len(counts)])
+        sel.append(np.sort(rng.choice(np.arange(gf[g], gf[g + 1]), k, replace=False)))
+    for ids in (np.concatenate(sel), np.arange(n), np.array([17]), np.arange(0, n, 97)):
+        ids = ids.astype(np.int32)
+        got = c.force(ids)
+        want = oracle.force_list(ids, XP, VP, mj, 1e-4, gf, ptr.list_off, ptr.entries)
+        assert_close(f"ragged n_active={ids.size}", prec, got, want)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_tiny_systems(oracle, prec):
+    """N = 1 (no partner), N = 2 (exact two-body) and coincident particles."""
+    say(f"tiny systems {prec}")
+    for name, x in (("n1", np.array([[0.1, 0.2, 0.3]])), ("n2", np.array([[0.0, 0.0, 0.0], [0.5, 0.25, -0.125]])),
+                    ("coincident", np.array([[0.0, 0, 0], [0.0, 0, 0], [1.0, 0, 0], [1.0, 0, 0], [0.5, 0.5, 0.5]]))):
+        n = x.shape[0]
+        v = np.arange(3 * n, dtype=np.float64).reshape(n, 3) * 0.125
+        m = np.full(n, 0.5)
+        z = np.zeros((n, 3))
+        ptr = B.HostTree(x, v, z, z, m, 1, 2, 0.5)
+        xs, vs = x[ptr.perm], v[ptr.perm]
+        c = make_ctx(prec, n, 8 * n + 64, n, 64, 0.01)
+        c.set_j_particles(0.0, m, xs, vs, z, z)
+        c.set_nodes(0.0, ptr.node_m, ptr.node_x, ptr.node_v, ptr.node_a, ptr.node_j)
+        c.set_interaction_lists(ptr.group_first, ptr.list_off, ptr.entries)
+        c.predict(0.0)
+        ids = np.arange(n, dtype=np.int32)
+        got = c.force(ids)
+        XP = np.vstack([xs, ptr.node_x])
+        VP = np.vstack([vs, ptr.node_v])
+        want = oracle.force_list(ids, XP, VP, np.concatenate([m, ptr.node_m]), 0.01, ptr.group_first, ptr.list_off,
+                                 ptr.entries)
+        if name == "n1":
+            for g in got:
+                assert np.all(g == 0.0)
+        else:
+            assert_close(name, prec, got, want)
+        assert all(np.all(np.isfinite(g)) for g in got)
+
+
+def test_zero_softening_two_body(oracle):
+    say("eps = 0 two body")
+    x = np.array([[-0.25, 0, 0], [0.25, 0, 0]])
+    v = np.array([[0, -0.5, 0], [0, 0.5, 0.0]])
+    m = np.array([0.5, 0.5])
+    z = np.zeros((2, 3))
+    for prec in ("fp64", "mixed"):
+        c = make_ctx(prec, 2, 64, 2, 64, 0.0)
+        c.set_j_particles(0.0, m, x, v, z, z)
+        c.set_nodes(0.0, np.zeros(0), *(np.zeros((0, 3)) for _ in range(4)))
+        c.set_interaction_lists([0, 2], [0, 2], [0, 1])
+        c.predict(0.0)
+        acc, jerk, pot = c.force(np.array([0, 1], dtype=np.int32))
+        assert np.allclose(acc, [[2.0, 0, 0], [-2.0, 0, 0]], rtol=1e-6)
+        assert np.allclose(pot, [-1.0, -1.0], rtol=1e-6)
+
+
+def test_api_errors():
+    say("api errors")
+    n = 64
+    x, v, m = W.plummer(n, 3)
+    z = np.zeros((n, 3))
+    c = make_ctx("fp64", n, 4 * n, n, 8192, 1e-4)
+    with pytest.raises(B.HTError) as e:
+        c.predict(0.0)
+    assert e.value.code == -4
+    c.set_j_particles(0.0, m, x, v, z, z)
+    with pytest.raises(B.HTError) as e:
+        c.force(np.array([0], dtype=np.int32))
+    assert e.value.code == -4
+    ptr = B.HostTree(x, v, z, z, m, 1, 8, 0.5)
+    c.set_j_particles(0.0, m[ptr.perm], x[ptr.perm], v[ptr.perm], z, z)
+    c.set_nodes(0.0, ptr.node_m, ptr.node_x, ptr.node_v, ptr.node_a, ptr.node_j)
+    bad = ptr.entries.copy()
+    bad[3] = n + ptr.n_node
+    with pytest.raises(B.HTError) as e:
+        c.set_interaction_lists(ptr.group_first, ptr.list_off, bad)
+    assert e.value.code == -2
+    c.set_interaction_lists(ptr.group_first, ptr.list_off, ptr.entries)
+    with pytest.raises(B.HTError) as e:
+        c.force(np.array([0], dtype=np.int32))   # not predicted yet
+    assert e.value.code == -4
+    c.predict(0.0)
+    for ids, code in (([3, 2], -1), ([1, 1], -1), ([n], -1), ([-1], -1)):
+        with pytest.raises(B.HTError) as e:
+            c.force(np.array(ids, dtype=np.int32))
+        assert e.value.code == code
+    acc, jerk, pot = c.force(np.zeros(0, dtype=np.int32))
+    assert acc.shape == (0, 3)
+    with pytest.raises(B.HTError) as e:
+        c.set_j_particles(0.0, m[:2], x[:2], v[:2], z[:2], z[:2], idx=np.array([5, 5], dtype=np.int32))
+    assert e.value.code == -1
+    with pytest.raises(B.HTError) as e:
+        c.set_interaction_lists(ptr.group_first[::-1].copy(), ptr.list_off, ptr.entries)
+    assert e.value.code == -1
+
+
+# ------------------------------------------------------------------------------------------ batch
+def test_batch_equals_alone(oracle):
+    """Several clusters in one launch give bit-identical results to each alone."""
+    import torch
+    say("batched launch vs alone")
+    s = torch.cuda.Stream()
+    sizes = [300, 1000, 2500, 64]
+    ctxs, acts, state = [], [], []
+    for k, n in enumerate(sizes):
+        x, v, m = W.plummer(n, 60 + k)
+        z = np.zeros((n, 3))
+        ptr = B.HostTree(x, v, z, z, m, 1, 64, 0.5)
+        x, v, m = x[ptr.perm], v[ptr.perm], m[ptr.perm]
+        t0, a, j = W.random_block_state(n, 70 + k, 0.125)
+        c = B.Context(n_max=n, node_max=2 * n, group_max=n, list_max=2 * ptr.n_entries + 64, active_max=n,
+                      eps2=1e-4, precision="mixed", stream=s.cuda_stream)
+        c.set_j_particles(t0, m, x, v, a, j)
+        c.set_nodes(0.0, ptr.node_m, ptr.node_x, ptr.node_v, ptr.node_a, ptr.node_j)
+        c.set_interaction_lists(ptr.group_first, ptr.list_off, ptr.entries)
+        c.predict(0.125)
+        ctxs.append(c)
+        acts.append(np.sort(np.random.default_rng(k).choice(n, max(1, n // (k + 2)), replace=False)).astype(np.int32))
+    alone = [c.force(a) for c, a in zip(ctxs, acts)]
+    outs = [(torch.empty((a.size, 3), dtype=torch.float64, device="cuda"),
+             torch.empty((a.size, 3), dtype=torch.float64, device="cuda"),
+             torch.empty(a.size, dtype=torch.float64, device="cuda")) for a in acts]
+    keep = B.force_batch_async(ctxs, acts, [o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs])
+    ctxs[0].sync()
+    del keep
+    for (a1, j1, p1), (a2, j2, p2) in zip(alone, outs):
+        assert np.array_equal(a1, a2.cpu().numpy())
+        assert np.array_equal(j1, j2.cpu().numpy())
+        assert np.array_equal(p1, p2.cpu().numpy())

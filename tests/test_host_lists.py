@@ -1,0 +1,134 @@
+"""The product host builder (libhtree_host.so) against the oracle: keys,
+order, node moments, groups and interaction lists must be bit-identical.
+The two share no code; both follow the tree/group/list rules of Section 2
+step 1 as read in the oracle's header."""
+import numpy as np
+import pytest
+
+from paper_1602_02832_amd import binding as B
+from paper_1602_02832_amd import workloads as W
+
+FIELDS = ["perm", "keys", "node_m", "node_x", "node_v", "node_a", "node_j", "node_level", "node_begin",
+          "node_end", "group_first", "list_off", "entries"]
+
+
+def assert_same_tree(oracle, x, v, a, j, m, n_leaf, n_crit, theta):
+    ref = oracle.Tree(x, v, a, j, m, n_leaf, n_crit, theta)
+    got = B.HostTree(x, v, a, j, m, n_leaf, n_crit, theta)
+    assert (got.n_node, got.n_group, got.n_entries) == (ref.n_node, ref.n_group, ref.n_entries)
+    for f in FIELDS:
+        g, r = getattr(got, f), getattr(ref, f)
+        assert g.dtype == r.dtype and g.shape == r.shape, f
+        assert np.array_equal(g, r), f
+    return got
+
+
+def test_hilbert_keys_match_oracle(oracle):
+    rng = np.random.default_rng(1)
+    q = rng.integers(0, 1 << 21, (1_000_000, 3)).astype(np.uint32)
+    q[:8] = [[0, 0, 0], [(1 << 21) - 1] * 3, [1, 0, 0], [0, 1, 0], [0, 0, 1], [7, 7, 7], [1 << 20] * 3, [5, 1 << 20, 9]]
+    assert np.array_equal(B.hilbert_keys(q), oracle.hilbert_keys(q))
+
+
+@pytest.mark.parametrize("cfg", ["plummer2k", "plummer16k"])
+def test_lists_bit_exact_on_workloads(oracle, cfg):
+    c = W.config(cfg)
+    x, v, m = W.make_initial_conditions(c)
+    rng = np.random.default_rng(c.seed + 100)
+    a, j = rng.normal(size=(2, c.n, 3))
+    t = assert_same_tree(oracle, x, v, a, j, m, c.n_leaf, c.n_crit, c.theta)
+    assert t.n_group > 10 and t.n_node > c.n // 4
+
+
+def _degenerate():
+    rng = np.random.default_rng(7)
+    out = []
+    out.append(("n1", rng.normal(size=(1, 3)), 1, 4, 0.5))
+    out.append(("n2", rng.normal(size=(2, 3)), 1, 1, 0.5))
+    x = rng.normal(size=(40, 3))
+    x[5] = x[6] = x[30]
+    out.append(("coincident", x, 1, 4, 0.5))
+    out.append(("all_same", np.ones((17, 3)), 1, 4, 0.5))
+    out.append(("theta0", rng.normal(size=(300, 3)), 1, 16, 0.0))
+    out.append(("theta_large", rng.normal(size=(300, 3)), 1, 16, 50.0))
+    out.append(("ncrit1", rng.normal(size=(200, 3)), 1, 1, 0.6))
+    out.append(("ncrit_all", rng.normal(size=(200, 3)), 1, 10000, 0.6))
+    out.append(("leaf4", rng.normal(size=(500, 3)), 4, 32, 0.5))
+    out.append(("flat", np.column_stack([rng.normal(size=(256, 2)), np.zeros(256)]), 1, 16, 0.5))
+    out.append(("line", np.column_stack([rng.normal(size=256), np.zeros(256), np.zeros(256)]), 1, 16, 0.5))
+    out.append(("tiny_scale", rng.normal(size=(256, 3)) * 1e-200, 1, 16, 0.5))
+    return out
+
+
+@pytest.mark.parametrize("name,x,n_leaf,n_crit,theta", _degenerate(), ids=[d[0] for d in _degenerate()])
+def test_lists_bit_exact_degenerate(oracle, name, x, n_leaf, n_crit, theta):
+    n = x.shape[0]
+    rng = np.random.default_rng(n)
+    v, a, j = rng.normal(size=(3, n, 3))
+    m = rng.uniform(0.5, 1.5, n) / n
+    assert_same_tree(oracle, x, v, a, j, m, n_leaf, n_crit, theta)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_lists_bit_exact_random_small(oracle, seed):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(3, 3000))
+    x = rng.standard_cauchy(size=(n, 3)) * 0.1
+    v, a, j = rng.normal(size=(3, n, 3))
+    m = rng.uniform(0.1, 1.0, n)
+    assert_same_tree(oracle, x, v, a, j, m, int(rng.integers(1, 5)), int(rng.integers(1, 200)),
+                     float(rng.uniform(0.2, 1.0)))
+
+
+def test_lists_bit_exact_after_integration(oracle):
+    """Rebuilds during an oracle tree/Hermite run see evolved, unsorted-looking
+    states; the product builder must reproduce every one."""
+    c = W.config("plummer2k")
+    x, v, m = W.make_initial_conditions(c)
+    states = []
+
+    def hook(sim, rec):
+        if np.fmod(rec["t"], c.dt_tree) == 0.0:
+            states.append(None)
+
+    sim = oracle.TreeHermite(x, v, m, eps2=c.eps2, dt_tree=c.dt_tree, eta=c.eta, theta=c.theta, n_crit=c.n_crit)
+    for _ in range(3):
+        t_next = sim.t + c.dt_tree
+        while sim.next_time() <= t_next:
+            sim.step()
+        got = B.HostTree(sim.x, sim.v, sim.a, sim.j, sim.m, c.n_leaf, c.n_crit, c.theta)
+        # the oracle has just rebuilt from this same (already sorted) state
+        assert np.array_equal(got.perm, np.arange(c.n))
+        for f in ("node_m", "node_x", "node_v", "node_a", "node_j", "group_first", "list_off", "entries"):
+            assert np.array_equal(getattr(got, f), getattr(sim.tree, f)), f
+
+
+def test_host_corrector_matches_oracle(oracle):
+    """Product host corrector + block step vs the oracle's, same inputs."""
+    rng = np.random.default_rng(3)
+    n = 500
+    t1 = 3.0 / 64
+    dt_old = 2.0 ** -rng.integers(6, 10, n)
+    t0 = t1 - dt_old
+    x, v, a, j = rng.normal(size=(4, n, 3))
+    a1 = a + rng.normal(scale=1e-2, size=(n, 3))
+    j1 = j + rng.normal(scale=1e-2, size=(n, 3))
+    ids = np.arange(n, dtype=np.int32)
+    xp, vp = oracle.predict(t1, t0, x, v, a, j)
+    x1, v1, dta = oracle.correct(t1, t0, xp, vp, a, j, a1, j1, 0.01)
+    want_dt = np.array([oracle.block_step(dta[k], t1, 1 / 64, dt_old[k]) for k in range(n)])
+    X, V, A, J, T0, DT = x.copy(), v.copy(), a.copy(), j.copy(), t0.copy(), dt_old.copy()
+    B.correct(ids, t1, 0.01, 1 / 64, T0, DT, X, V, A, J, a1, j1)
+    assert np.allclose(X, x1, rtol=1e-14, atol=1e-14) and np.allclose(V, v1, rtol=1e-13, atol=1e-13)
+    assert np.array_equal(DT, want_dt) and np.all(T0 == t1)
+    assert np.array_equal(A, a1) and np.array_equal(J, j1)
+
+
+def test_next_block_selects_minimum():
+    rng = np.random.default_rng(4)
+    n = 100000
+    dt = 2.0 ** -rng.integers(3, 12, n)
+    t0 = np.floor(rng.uniform(0, 1, n) / dt) * dt
+    tn, act = B.next_block(t0, dt)
+    want = np.flatnonzero(t0 + dt == (t0 + dt).min())
+    assert tn == (t0 + dt).min() and np.array_equal(act, want)
