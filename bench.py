@@ -1,0 +1,331 @@
+#!/usr/bin/env python3
+"""Block-step throughput of the tree/Hermite force evaluation on one MI355X.
+
+Workload (default "plummer1m_salpeter"): Plummer model of N = 2^20 particles
+with a Salpeter mass spectrum (m_max/m_min = 100, total mass 1), theta = 0.4,
+eps = 4/N, tree interval 1/512, Aarseth eta = 0.01, n_crit = 2048, mixed
+precision, fused prediction.  The run integrates through t = 1/512 (start-up,
+including the all-particle step and the tree rebuild there), records the next
+W + K block steps, then replays them from the same device state with inputs
+resident in HBM:
+
+  step k = j-memory update with the particles corrected at step k-1
+           -> predict(t_k) -> force on the active set of step k
+
+W steps warm up; K steps are timed (wall clock between synchronisations, and
+HIP events on the library's stream for step latency and kernel time).  The
+same K steps are then run with the direct N^2 sum (the original Hermite
+scheme) and with the FP64 form.  The all-particle step at t = 1/512 is timed
+separately.
+
+One JSON line on stdout; progress on stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FLOPS_PER_PAIR = 57          # Section 3 convention for force + jerk
+PEAK_VALU_TFLOPS = 78.6      # 256 CU x 64 FMA lanes x 2 flop x 2.4 GHz (no packed FP32)
+METRIC = "Hermite acc+jerk interactions/s at N=2^20 vs direct; p99 block-step latency"
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+class Recorded:
+    """Block steps recorded from a tree/Hermite run, ready for replay."""
+
+    def __init__(self, sim):
+        self.n = sim.n
+        self.snap = self._snapshot(sim)
+        self.steps = []   # (t, active, update tuple of host arrays)
+
+    @staticmethod
+    def _snapshot(sim):
+        tr = sim.tree
+        return dict(t0=sim.t0.copy(), m=sim.m.copy(), x=sim.x.copy(), v=sim.v.copy(), a=sim.a.copy(),
+                    j=sim.j.copy(), t_tree=sim.t_tree, node=(tr.node_m, tr.node_x, tr.node_v, tr.node_a, tr.node_j),
+                    lists=(tr.group_first, tr.list_off, tr.entries), n_node=tr.n_node, n_group=tr.n_group,
+                    n_entries=tr.n_entries)
+
+    def add(self, sim, t, act):
+        upd = (act.astype(np.int32), sim.t0[act].copy(), sim.m[act].copy(), sim.x[act].copy(), sim.v[act].copy(),
+               sim.a[act].copy(), sim.j[act].copy())
+        self.steps.append((t, act.astype(np.int32), upd))
+
+
+def make_ctx(B, snap, n, precision, eps2, stream, predict_mode="fused"):
+    ctx = B.Context(n_max=n, node_max=snap["n_node"] + 64, group_max=snap["n_group"] + 16,
+                    list_max=snap["n_entries"] + 1024, active_max=n, eps2=eps2, precision=precision,
+                    predict_mode=predict_mode, stream=stream)
+    load_snapshot(ctx, snap)
+    return ctx
+
+
+def load_snapshot(ctx, snap):
+    ctx.set_j_particles(snap["t0"], snap["m"], snap["x"], snap["v"], snap["a"], snap["j"])
+    ctx.set_nodes(snap["t_tree"], *snap["node"])
+    ctx.set_interaction_lists(*snap["lists"])
+
+
+def device_updates(torch, rec):
+    out = []
+    for _, _, upd in rec.steps:
+        out.append(tuple(torch.from_numpy(np.ascontiguousarray(u)).cuda() for u in upd))
+    return out
+
+
+def replay(torch, B, rec, ctx, stream, warmup, steps, direct=False):
+    """Replay recorded steps; returns timing dict for the last `steps` steps."""
+    dev_upd = device_updates(torch, rec)
+    kmax = max(a.size for _, a, _ in rec.steps)
+    acc = torch.empty((kmax, 3), dtype=torch.float64, device="cuda")
+    jrk = torch.empty((kmax, 3), dtype=torch.float64, device="cuda")
+    pot = torch.empty(kmax, dtype=torch.float64, device="cuda")
+    fn = ctx.force_direct_async if direct else ctx.force_async
+
+    def run_step(k):
+        if k > 0:
+            u = dev_upd[k - 1]
+            ctx.set_j_particles_async(u[0].shape[0], *u)
+        t, act, _ = rec.steps[k]
+        ctx.predict(t)
+        fn(act, acc, jrk, pot)
+
+    for k in range(warmup):
+        run_step(k)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    pairs = 0
+    t_wall = time.perf_counter()
+    for q, k in enumerate(range(warmup, warmup + steps)):
+        evs[q].record(stream)
+        run_step(k)
+        pairs += ctx.last_stats()[0]
+    evs[steps].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    kms, launches, kpairs = ctx.kernel_timing()
+    ctx.set_timing(False)
+    lat = np.array([evs[q].elapsed_time(evs[q + 1]) for q in range(steps)])
+    return dict(wall_s=wall, pairs=pairs, kernel_ms=kms, launches=launches, kernel_pairs=kpairs, lat_ms=lat)
+
+
+def cpu_baseline(W, cfg, seconds):
+    """Oracle list force (FP64, OpenMP) on a bounded sample of the workload:
+    whole groups of the t = 0 tree, the oracle's own tree and lists."""
+    from oracle import oracle as O
+
+    x, v, m = W.make_initial_conditions(cfg)
+    z = np.zeros_like(x)
+    tr = O.Tree(x, v, z, z, m, cfg.n_leaf, cfg.n_crit, cfg.theta)
+    xs, vs, ms = x[tr.perm], v[tr.perm], m[tr.perm]
+    XP, VP, MM = np.vstack([xs, tr.node_x]), np.vstack([vs, tr.node_v]), np.concatenate([ms, tr.node_m])
+    rng = np.random.default_rng(99)
+    order = rng.permutation(tr.n_group)
+    gf, lo = tr.group_first, tr.list_off
+    done_pairs, spent, used, k = 0, 0.0, 0, 0
+    while spent < seconds and k < len(order):
+        g = order[k]
+        k += 1
+        ids = np.arange(gf[g], gf[g + 1], dtype=np.int32)
+        t = time.perf_counter()
+        O.force_list(ids, XP, VP, MM, cfg.eps2, gf, lo, tr.entries)
+        spent += time.perf_counter() - t
+        done_pairs += ids.size * int(lo[g + 1] - lo[g])
+        used += ids.size
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    return dict(value=done_pairs / spent, unit="interactions/s", cores=threads, kind="oracle",
+                sample=f"list force on all {used} particles of {k} random groups of the t=0 tree "
+                       f"({done_pairs:.3g} pairs, {spent:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=64)
+    ap.add_argument("--warmup", type=int, default=8)
+    ap.add_argument("--workload", default="plummer1m_salpeter")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-direct", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-all-active", action="store_true")
+    ap.add_argument("--n", type=int, default=0, help="override N (testing only; not the benchmark)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md for how it "
+              "would shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU; WORLD_SIZE > 1 is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1602_02832_amd import binding as B
+    from paper_1602_02832_amd import driver
+    from paper_1602_02832_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    cfg = W.config(args.workload)
+    if args.n:
+        cfg = W.config(args.workload, n=args.n, eps=4.0 / args.n)
+    log(f"workload {cfg.name}: N={cfg.n} theta={cfg.theta} eps={cfg.eps:.3g} dt_tree={cfg.dt_tree} "
+        f"eta={cfg.eta} n_crit={cfg.n_crit}")
+    x, v, m = W.make_initial_conditions(cfg)
+    t0 = time.perf_counter()
+    sim = driver.Simulation(x, v, m, eps2=cfg.eps2, dt_tree=cfg.dt_tree, eta=cfg.eta, theta=cfg.theta,
+                            n_crit=cfg.n_crit, n_leaf=cfg.n_leaf, precision="mixed")
+    log(f"initial tree + force: {time.perf_counter() - t0:.1f} s; groups {sim.tree.n_group}, nodes "
+        f"{sim.tree.n_node}, list entries {sim.tree.n_entries}")
+    # start-up: everything before the all-particle step at t = dt_tree
+    t_start = time.perf_counter()
+    last = t_start
+    while sim.next_time() < cfg.dt_tree:
+        sim.step()
+        if time.perf_counter() - last > 10:
+            last = time.perf_counter()
+            log(f"start-up t={sim.t:.6g} block steps {sim.n_block_steps}")
+    rec_all = Recorded(sim)
+    t_all = sim.next_time()
+    sim.step()   # all particles active, then the rebuild
+    rec_all.steps.append((t_all, np.arange(sim.n, dtype=np.int32), None))
+    log(f"start-up done: {sim.n_block_steps} block steps, {sim.n_particle_steps} particle steps in "
+        f"{time.perf_counter() - t_start:.1f} s")
+    rec = Recorded(sim)
+    need = args.warmup + args.steps
+    while len(rec.steps) < need:
+        tn, act = sim.step()
+        if math.fmod(tn, cfg.dt_tree) == 0.0:
+            raise RuntimeError("a tree rebuild fell inside the measured window")
+        rec.add(sim, tn, act)
+    n_act = np.array([a.size for _, a, _ in rec.steps[args.warmup:]])
+    log(f"recorded {need} block steps: active per step min {n_act.min()} median {int(np.median(n_act))} "
+        f"max {n_act.max()}, t {rec.steps[0][0]:.8g} .. {rec.steps[-1][0]:.8g}")
+    sim.close()
+
+    stream = torch.cuda.Stream()
+    sh = stream.cuda_stream
+    out = {}
+    # ---- mixed tree (the headline)
+    ctx = make_ctx(B, rec.snap, rec.n, "mixed", cfg.eps2, sh)
+    mixed = replay(torch, B, rec, ctx, stream, args.warmup, args.steps)
+    log(f"mixed tree: {mixed['pairs'] / mixed['wall_s']:.4g} pairs/s, {1e3 * mixed['wall_s'] / args.steps:.3f} "
+        f"ms/step, kernel {mixed['kernel_ms']:.3f} ms over {mixed['launches']} launches")
+    ctx.close()
+    # ---- direct N^2 on the same steps
+    direct = None
+    if not args.no_direct:
+        ctx = make_ctx(B, rec.snap, rec.n, "mixed", cfg.eps2, sh)
+        direct = replay(torch, B, rec, ctx, stream, args.warmup, args.steps, direct=True)
+        log(f"mixed direct: {direct['pairs'] / direct['wall_s']:.4g} pairs/s, "
+            f"{1e3 * direct['wall_s'] / args.steps:.3f} ms/step")
+        ctx.close()
+    # ---- FP64 tree
+    fp64 = None
+    if not args.no_fp64:
+        ctx = make_ctx(B, rec.snap, rec.n, "fp64", cfg.eps2, sh)
+        fp64 = replay(torch, B, rec, ctx, stream, args.warmup, args.steps)
+        log(f"fp64 tree: {fp64['pairs'] / fp64['wall_s']:.4g} pairs/s, {1e3 * fp64['wall_s'] / args.steps:.3f} ms/step")
+        ctx.close()
+    # ---- the all-particle step at t = dt_tree
+    all_active = None
+    if not args.no_all_active:
+        ctx = make_ctx(B, rec_all.snap, rec_all.n, "mixed", cfg.eps2, sh)
+        ids = np.arange(rec_all.n, dtype=np.int32)
+        acc = torch.empty((rec_all.n, 3), dtype=torch.float64, device="cuda")
+        jrk = torch.empty_like(acc)
+        pot = torch.empty(rec_all.n, dtype=torch.float64, device="cuda")
+        ctx.predict(t_all)
+        ctx.force_async(ids, acc, jrk, pot)   # warm-up
+        torch.cuda.synchronize()
+        ctx.set_timing(True)
+        reps = 3
+        tw = time.perf_counter()
+        for _ in range(reps):
+            ctx.force_async(ids, acc, jrk, pot)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - tw) / reps
+        kms, nl, kp = ctx.kernel_timing()
+        ctx.set_timing(False)
+        pairs_all = kp / nl
+        all_active = dict(t=t_all, n_active=rec_all.n, pairs=int(pairs_all), ms=1e3 * wall,
+                          kernel_ms=kms / nl, interactions_per_s=pairs_all / wall,
+                          equivalent_interactions_per_s=rec_all.n * (rec_all.n - 1) / wall)
+        log(f"all-particle step: {1e3 * wall:.2f} ms, {pairs_all / wall:.4g} pairs/s, kernel {kms / nl:.2f} ms")
+        ctx.close()
+
+    # ---- CPU baseline (oracle on a bounded sample)
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: oracle list force for about {args.cpu_seconds:.0f} s")
+        cpu = cpu_baseline(W, cfg, args.cpu_seconds)
+        log(f"cpu baseline: {cpu['value']:.4g} interactions/s on {cpu['cores']} threads")
+
+    K = args.steps
+    value = mixed["pairs"] / mixed["wall_s"]
+    eq_pairs = int(sum(a.size for _, a, _ in rec.steps[args.warmup:]) * (rec.n - 1))
+    lat = mixed["lat_ms"]
+    kernel_avg_ms = mixed["kernel_ms"] / max(mixed["launches"], 1)
+    achieved = FLOPS_PER_PAIR * mixed["kernel_pairs"] / (mixed["kernel_ms"] * 1e-3) / 1e12
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * mixed["wall_s"] / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": cfg.name, "n": cfg.n, "theta": cfg.theta, "eps": cfg.eps, "dt_tree": cfg.dt_tree,
+                   "eta": cfg.eta, "n_crit": cfg.n_crit, "n_leaf": cfg.n_leaf, "masses": "salpeter 1:100",
+                   "window": f"{K} block steps after the rebuild at t={cfg.dt_tree}", "precision": "mixed",
+                   "predict": "fused"},
+        "p50_step_ms": float(np.percentile(lat, 50)),
+        "p99_step_ms": float(np.percentile(lat, 99)),
+        "active_per_step": {"min": int(n_act.min()), "median": float(np.median(n_act)), "max": int(n_act.max()),
+                            "mean": float(n_act.mean())},
+        "equivalent_interactions_per_s": eq_pairs / mixed["wall_s"],
+        "tflops_at_57": FLOPS_PER_PAIR * value / 1e12,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None,
+                     "kernel": "force_kernel<PrecMixed,false,false>", "avg_launch_ms": kernel_avg_ms,
+                     "pairs_per_launch": mixed["kernel_pairs"] / max(mixed["launches"], 1)},
+    }
+    if direct is not None:
+        result["direct_interactions_per_s"] = direct["pairs"] / direct["wall_s"]
+        result["direct_ms_per_step"] = 1e3 * direct["wall_s"] / K
+        result["speedup_vs_direct"] = direct["wall_s"] / mixed["wall_s"]
+    if fp64 is not None:
+        result["fp64_interactions_per_s"] = fp64["pairs"] / fp64["wall_s"]
+        result["fp64_ms_per_step"] = 1e3 * fp64["wall_s"] / K
+        result["fp64_p99_step_ms"] = float(np.percentile(fp64["lat_ms"], 99))
+    if all_active is not None:
+        result["all_active_step"] = all_active
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

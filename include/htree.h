@@ -154,6 +154,15 @@ int ht_sync(ht_ctx *ctx);
  * particles, self pairs included) and the number of work items it used. */
 int ht_last_stats(const ht_ctx *ctx, int64_t *pairs, int32_t *work_items);
 
+/* Timing of force-kernel launches: with timing enabled, every force launch
+ * on this context's stream (batched launches count on their first context)
+ * is bracketed by HIP events.  ht_kernel_timing synchronises the stream and
+ * returns the summed kernel time in milliseconds, the number of launches and
+ * the pair interactions they summed since timing was enabled or last read,
+ * then starts a new tally. */
+int ht_set_timing(ht_ctx *ctx, int32_t enable);
+int ht_kernel_timing(ht_ctx *ctx, double *force_ms, int64_t *launches, int64_t *pairs);
+
 /* Message for the last failure on the calling thread ("" if none). */
 const char *ht_last_error(void);
 

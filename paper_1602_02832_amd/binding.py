@@ -79,6 +79,8 @@ def device_lib():
                                      ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp)],
             "ht_sync": [_vp],
             "ht_last_stats": [_vp, _c_i64p, _c_i32p],
+            "ht_set_timing": [_vp, i],
+            "ht_kernel_timing": [_vp, _c_dp, _c_i64p, _c_i64p],
             "ht_last_error": [],
         }
         for name, args in sig.items():
@@ -249,6 +251,17 @@ class Context:
 
     def sync(self):
         _check(device_lib().ht_sync(self._h))
+
+    def set_timing(self, enable=True):
+        _check(device_lib().ht_set_timing(self._h, 1 if enable else 0))
+
+    def kernel_timing(self):
+        """(force kernel ms, launches, pairs) since timing was enabled or last read."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        p = ctypes.c_int64()
+        _check(device_lib().ht_kernel_timing(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(p)))
+        return ms.value, n.value, p.value
 
     def last_stats(self):
         p = ctypes.c_int64()

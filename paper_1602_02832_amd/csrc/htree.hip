@@ -586,6 +586,11 @@ struct ht_ctx {
     // last call statistics
     int64_t last_pairs = 0;
     int32_t last_items = 0;
+    // optional timing of force-kernel launches (events around each launch)
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    int64_t timed_pairs = 0;
     // scratch for planning
     std::vector<Item> items;
     std::vector<RTile> rtiles;
@@ -756,7 +761,8 @@ int upload_plan(ht_ctx* c, int32_t n_active, const int32_t* ids, double* acc, do
 }
 
 template <class P>
-int launch_force(ht_ctx* c0, const Entry* h_tab, int n_tab, int64_t n_items, int64_t n_rtiles, bool direct) {
+int launch_force(ht_ctx* c0, const Entry* h_tab, int n_tab, int64_t n_items, int64_t n_rtiles, bool direct,
+                 int64_t pairs) {
     // launch table through the first context's staging
     int rc = c0->stage_wait();
     if (rc) return rc;
@@ -764,8 +770,24 @@ int launch_force(ht_ctx* c0, const Entry* h_tab, int n_tab, int64_t n_items, int
     Entry* d_tab = c0->dev<Entry>(c0->L.off_tab);
     HT_HIP(hipMemcpyAsync(d_tab, c0->h_stage + c0->hs_tab, static_cast<size_t>(n_tab) * sizeof(Entry),
                           hipMemcpyHostToDevice, c0->stream));
+    // the staging buffer is free once these copies are done, not the kernels
+    rc = c0->stage_mark();
+    if (rc) return rc;
     const bool eager = c0->cfg.predict_mode == HT_PREDICT_EAGER;
     const int grid = grid_for(n_items);
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;
+    if (c0->timing) {
+        while (c0->ev_pool.size() < c0->ev_used + 2) {
+            hipEvent_t e;
+            HT_HIP(hipEventCreate(&e));
+            c0->ev_pool.push_back(e);
+        }
+        ev_a = c0->ev_pool[c0->ev_used];
+        ev_b = c0->ev_pool[c0->ev_used + 1];
+        c0->ev_used += 2;
+        HT_HIP(hipEventRecord(ev_a, c0->stream));
+        c0->timed_pairs += pairs;
+    }
     if (direct) {
         if (eager) force_kernel<P, true, true><<<grid, kWG, 0, c0->stream>>>(d_tab, n_tab, n_items);
         else force_kernel<P, false, true><<<grid, kWG, 0, c0->stream>>>(d_tab, n_tab, n_items);
@@ -774,11 +796,12 @@ int launch_force(ht_ctx* c0, const Entry* h_tab, int n_tab, int64_t n_items, int
         else force_kernel<P, false, false><<<grid, kWG, 0, c0->stream>>>(d_tab, n_tab, n_items);
     }
     HT_HIP(hipGetLastError());
+    if (ev_b) HT_HIP(hipEventRecord(ev_b, c0->stream));
     if (n_rtiles > 0) {
         reduce_kernel<<<grid_for(n_rtiles), kWG, 0, c0->stream>>>(d_tab, n_tab, n_rtiles);
         HT_HIP(hipGetLastError());
     }
-    return c0->stage_mark();
+    return HT_OK;
 }
 
 int force_common(ht_ctx* c, int32_t n_active, const int32_t* ids, double* d_acc, double* d_jerk, double* d_pot,
@@ -803,8 +826,8 @@ int force_common(ht_ctx* c, int32_t n_active, const int32_t* ids, double* d_acc,
     e.first_item = 0;
     e.first_rtile = 0;
     const int64_t ni = static_cast<int64_t>(c->items.size()), nr = static_cast<int64_t>(c->rtiles.size());
-    if (c->cfg.precision == HT_PREC_FP64) return launch_force<PrecFp64>(c, &e, 1, ni, nr, direct);
-    return launch_force<PrecMixed>(c, &e, 1, ni, nr, direct);
+    if (c->cfg.precision == HT_PREC_FP64) return launch_force<PrecFp64>(c, &e, 1, ni, nr, direct, c->last_pairs);
+    return launch_force<PrecMixed>(c, &e, 1, ni, nr, direct, c->last_pairs);
 }
 
 int force_to_host(ht_ctx* c, int32_t n_active, const int32_t* ids, double* acc, double* jerk, double* pot,
@@ -948,6 +971,7 @@ int ht_destroy(ht_ctx* c) {
     // teardown: failures here cannot be acted on, so their codes are dropped
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     if (c->stage_free) (void)hipEventDestroy(c->stage_free);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->h_stage) (void)hipHostFree(c->h_stage);
     if (c->own_ws && c->ws) (void)hipFree(c->ws);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -1153,7 +1177,7 @@ int ht_force_batch_async(int32_t n_ctx, ht_ctx* const* ctxs, const int32_t* n_ac
     }
     std::vector<Entry> tab;
     tab.reserve(n_ctx);
-    int64_t n_items = 0, n_rtiles = 0;
+    int64_t n_items = 0, n_rtiles = 0, pairs = 0;
     for (int32_t k = 0; k < n_ctx; ++k) {
         ht_ctx* c = ctxs[k];
         if (n_active[k] == 0) {
@@ -1170,6 +1194,7 @@ int ht_force_batch_async(int32_t n_ctx, ht_ctx* const* ctxs, const int32_t* n_ac
         e.first_rtile = n_rtiles;
         n_items += static_cast<int64_t>(c->items.size());
         n_rtiles += static_cast<int64_t>(c->rtiles.size());
+        pairs += c->last_pairs;
         tab.push_back(e);
         if (c != c0) {
             int rc2 = c->stage_mark();
@@ -1178,14 +1203,40 @@ int ht_force_batch_async(int32_t n_ctx, ht_ctx* const* ctxs, const int32_t* n_ac
     }
     if (tab.empty()) return HT_OK;
     if (c0->cfg.precision == HT_PREC_FP64)
-        return launch_force<PrecFp64>(c0, tab.data(), static_cast<int>(tab.size()), n_items, n_rtiles, false);
-    return launch_force<PrecMixed>(c0, tab.data(), static_cast<int>(tab.size()), n_items, n_rtiles, false);
+        return launch_force<PrecFp64>(c0, tab.data(), static_cast<int>(tab.size()), n_items, n_rtiles, false, pairs);
+    return launch_force<PrecMixed>(c0, tab.data(), static_cast<int>(tab.size()), n_items, n_rtiles, false, pairs);
 }
 
 int ht_sync(ht_ctx* c) {
     if (!c) return fail(HT_EINVAL, "ctx is NULL");
     HT_HIP(hipStreamSynchronize(c->stream));
     c->stage_pending = false;
+    return HT_OK;
+}
+
+int ht_set_timing(ht_ctx* c, int32_t enable) {
+    if (!c) return fail(HT_EINVAL, "ctx is NULL");
+    c->timing = enable != 0;
+    c->ev_used = 0;
+    c->timed_pairs = 0;
+    return HT_OK;
+}
+
+int ht_kernel_timing(ht_ctx* c, double* force_ms, int64_t* launches, int64_t* pairs) {
+    if (!c || !force_ms || !launches || !pairs) return fail(HT_EINVAL, "NULL argument");
+    HT_HIP(hipStreamSynchronize(c->stream));
+    c->stage_pending = false;
+    double total = 0.0;
+    for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
+        float ms = 0.0f;
+        HT_HIP(hipEventElapsedTime(&ms, c->ev_pool[k], c->ev_pool[k + 1]));
+        total += ms;
+    }
+    *force_ms = total;
+    *launches = static_cast<int64_t>(c->ev_used / 2);
+    *pairs = c->timed_pairs;
+    c->ev_used = 0;
+    c->timed_pairs = 0;
     return HT_OK;
 }
 
