@@ -134,6 +134,14 @@ int ht_force_direct(ht_ctx *ctx, int32_t n_active, const int32_t *active_ids, do
 int ht_force_direct_async(ht_ctx *ctx, int32_t n_active, const int32_t *active_ids, double *d_acc,
                           double *d_jerk, double *d_pot);
 
+/* One block step in one call, asynchronously: the j-memory update of
+ * ht_set_j_particles_async (n_upd rows, device arrays; n_upd = 0 skips it),
+ * then ht_predict(t), then ht_force_async on active_ids (host array). */
+int ht_step_async(ht_ctx *ctx, int32_t n_upd, const int32_t *d_idx, const double *d_t0, const double *d_m,
+                  const double *d_x, const double *d_v, const double *d_a, const double *d_jerk, double t,
+                  int32_t n_active, const int32_t *active_ids, double *d_acc, double *d_jerk_out,
+                  double *d_pot);
+
 /* Predicted position and velocity ([n][3]) of combined indices idx[0..n-1]
  * at the current block time, computed by the device predictor. */
 int ht_get_predicted(ht_ctx *ctx, int32_t n, const int32_t *idx, double *xp, double *vp);

@@ -64,28 +64,39 @@ constexpr int kRound = 256;   // list entries staged per round (one per thread)
 constexpr int kFold = 32;     // mixed form: FP32 pairs summed before folding into FP64
 constexpr int kOut = 7;       // acc[3], jerk[3], pot
 
+// j-memory record of one particle or node: everything the predictor needs in
+// one 128-byte line, so a list-indexed gather touches a single cache line
+// (lists reach nodes in scattered order; a field-per-array layout would touch
+// one line per field).
+struct alignas(128) RecFp64 {
+    double x, y, z, t0;
+    double vx, vy, vz, m;
+    double ax, ay, az, pad0;
+    double jx, jy, jz, pad1;
+};
+struct alignas(128) RecMixed {
+    double x, y, z, t0;
+    double vx, vy, vz;
+    float m, ax, ay, az, jx, jy, jz;
+    float pad[9];
+};
+// Eagerly predicted state (EAGER mode): 64 bytes per entry.
+struct alignas(64) PRecFp64 {
+    double x, y, z, m;
+    double vx, vy, vz, pad;
+};
+struct alignas(64) PRecMixed {
+    double x, y, z;
+    float vx, vy, vz, m;
+    double pad[3];
+};
+static_assert(sizeof(RecFp64) == 128 && sizeof(RecMixed) == 128, "record size");
+static_assert(sizeof(PRecFp64) == 64 && sizeof(PRecMixed) == 64, "predicted record size");
+
 // Everything a kernel needs to know about one cluster (context) for one call.
 struct Desc {
-    const double* t0;
-    const double* x;
-    const double* y;
-    const double* z;
-    const double* vx;
-    const double* vy;
-    const double* vz;
-    const void* ax;
-    const void* ay;
-    const void* az;
-    const void* jx;
-    const void* jy;
-    const void* jz;
-    const void* m;
-    const double* px;   // eagerly predicted positions (EAGER mode)
-    const double* py;
-    const double* pz;
-    const void* pvx;    // eagerly predicted velocities (EAGER mode)
-    const void* pvy;
-    const void* pvz;
+    const void* rec;    // [N+M] raw records (RecFp64 or RecMixed)
+    void* prec;         // [N+M] predicted records (EAGER mode)
     const int32_t* entries;
     const int32_t* active;
     double* acc;        // [n_active][3]
@@ -128,11 +139,15 @@ struct Entry {
 struct PrecFp64 {
     using Stored = double;  // stored a, jerk, m
     using Vel = double;     // predicted velocity used in the pair
+    using Rec = RecFp64;
+    using PRec = PRecFp64;
     static constexpr bool kMixed = false;
 };
 struct PrecMixed {
     using Stored = float;
     using Vel = float;
+    using Rec = RecMixed;
+    using PRec = PRecMixed;
     static constexpr bool kMixed = true;
 };
 
@@ -153,43 +168,43 @@ union LdsAll {
 // ------------------------------------------------------------------------------------------------
 // predictor (4th-order Hermite, Section 1/2): Taylor series to the jerk, FP64.
 template <class P>
-__device__ __forceinline__ void predict_j(const Desc& c, int j, double& x, double& y, double& z, double& vx,
-                                          double& vy, double& vz) {
-    using S = typename P::Stored;
-    const double dt = c.t - c.t0[j];
+__device__ __forceinline__ void predict_rec(const typename P::Rec& r, double t, double& x, double& y, double& z,
+                                            double& vx, double& vy, double& vz) {
+    const double dt = t - r.t0;
     const double h2 = 0.5 * dt, h3 = dt * (1.0 / 3.0);
-    const double a0 = static_cast<double>(static_cast<const S*>(c.ax)[j]);
-    const double a1 = static_cast<double>(static_cast<const S*>(c.ay)[j]);
-    const double a2 = static_cast<double>(static_cast<const S*>(c.az)[j]);
-    const double j0 = static_cast<double>(static_cast<const S*>(c.jx)[j]);
-    const double j1 = static_cast<double>(static_cast<const S*>(c.jy)[j]);
-    const double j2 = static_cast<double>(static_cast<const S*>(c.jz)[j]);
-    const double v0 = c.vx[j], v1 = c.vy[j], v2 = c.vz[j];
-    x = c.x[j] + dt * (v0 + h2 * (a0 + h3 * j0));
-    y = c.y[j] + dt * (v1 + h2 * (a1 + h3 * j1));
-    z = c.z[j] + dt * (v2 + h2 * (a2 + h3 * j2));
-    vx = v0 + dt * (a0 + h2 * j0);
-    vy = v1 + dt * (a1 + h2 * j1);
-    vz = v2 + dt * (a2 + h2 * j2);
+    const double a0 = static_cast<double>(r.ax), a1 = static_cast<double>(r.ay), a2 = static_cast<double>(r.az);
+    const double j0 = static_cast<double>(r.jx), j1 = static_cast<double>(r.jy), j2 = static_cast<double>(r.jz);
+    x = r.x + dt * (r.vx + h2 * (a0 + h3 * j0));
+    y = r.y + dt * (r.vy + h2 * (a1 + h3 * j1));
+    z = r.z + dt * (r.vz + h2 * (a2 + h3 * j2));
+    vx = r.vx + dt * (a0 + h2 * j0);
+    vy = r.vy + dt * (a1 + h2 * j1);
+    vz = r.vz + dt * (a2 + h2 * j2);
 }
 
+// Position, velocity (in the pair's precision) and mass of entry j at the block time.
 template <class P, bool EAGER>
 __device__ __forceinline__ void load_state(const Desc& c, int j, double& x, double& y, double& z,
-                                           typename P::Vel& vx, typename P::Vel& vy, typename P::Vel& vz) {
+                                           typename P::Vel& vx, typename P::Vel& vy, typename P::Vel& vz,
+                                           typename P::Stored& m) {
     using V = typename P::Vel;
     if constexpr (EAGER) {
-        x = c.px[j];
-        y = c.py[j];
-        z = c.pz[j];
-        vx = static_cast<const V*>(c.pvx)[j];
-        vy = static_cast<const V*>(c.pvy)[j];
-        vz = static_cast<const V*>(c.pvz)[j];
+        const typename P::PRec r = static_cast<const typename P::PRec*>(c.prec)[j];
+        x = r.x;
+        y = r.y;
+        z = r.z;
+        vx = r.vx;
+        vy = r.vy;
+        vz = r.vz;
+        m = r.m;
     } else {
+        const typename P::Rec r = static_cast<const typename P::Rec*>(c.rec)[j];
         double dvx, dvy, dvz;
-        predict_j<P>(c, j, x, y, z, dvx, dvy, dvz);
+        predict_rec<P>(r, c.t, x, y, z, dvx, dvy, dvz);
         vx = static_cast<V>(dvx);
         vy = static_cast<V>(dvy);
         vz = static_cast<V>(dvz);
+        m = r.m;
     }
 }
 
@@ -257,6 +272,17 @@ __device__ __forceinline__ void pair_mixed(double xi, double yi, double zi, floa
 }
 
 // ------------------------------------------------------------------------------------------------
+__device__ __forceinline__ void write_out(const Desc& c, int64_t o, const double* v) {
+    c.acc[3 * o + 0] = v[0];
+    c.acc[3 * o + 1] = v[1];
+    c.acc[3 * o + 2] = v[2];
+    c.jerk[3 * o + 0] = v[3];
+    c.jerk[3 * o + 1] = v[4];
+    c.jerk[3 * o + 2] = v[5];
+    c.pot[o] = v[6];
+}
+
+// ------------------------------------------------------------------------------------------------
 // one work item with tile size T
 template <class P, bool EAGER, bool DIRECT, int T>
 __device__ __forceinline__ void run_item(const Desc& c, const Item& it, LdsAll<P>& lds) {
@@ -270,7 +296,9 @@ __device__ __forceinline__ void run_item(const Desc& c, const Item& it, LdsAll<P
 
     double xi, yi, zi;
     typename P::Vel vxi, vyi, vzi;
-    load_state<P, EAGER>(c, i, xi, yi, zi, vxi, vyi, vzi);
+    typename P::Stored mi;
+    load_state<P, EAGER>(c, i, xi, yi, zi, vxi, vyi, vzi, mi);
+    (void)mi;
 
     Acc64 A;
 #pragma unroll
@@ -284,14 +312,15 @@ __device__ __forceinline__ void run_item(const Desc& c, const Item& it, LdsAll<P
             const int j = DIRECT ? static_cast<int>(base + tid) : c.entries[base + tid];
             double xj, yj, zj;
             typename P::Vel vxj, vyj, vzj;
-            load_state<P, EAGER>(c, j, xj, yj, zj, vxj, vyj, vzj);
+            typename P::Stored mj;
+            load_state<P, EAGER>(c, j, xj, yj, zj, vxj, vyj, vzj, mj);
             lds.j.x[tid] = xj;
             lds.j.y[tid] = yj;
             lds.j.z[tid] = zj;
             lds.j.vx[tid] = vxj;
             lds.j.vy[tid] = vyj;
             lds.j.vz[tid] = vzj;
-            lds.j.m[tid] = static_cast<const typename P::Stored*>(c.m)[j];
+            lds.j.m[tid] = mj;
             lds.j.idx[tid] = j;
         }
         __syncthreads();
@@ -304,7 +333,7 @@ __device__ __forceinline__ void run_item(const Desc& c, const Item& it, LdsAll<P
                     Acc32 B;
 #pragma unroll
                     for (int q = 3; q < kOut; ++q) B.v[q] = 0.0f;
-#pragma unroll 8
+#pragma unroll 4
                     for (int u = 0; u < F; ++u)
                         pair_mixed(xi, yi, zi, vxi, vyi, vzi, i, lds.j, stream + (f + u) * S, eps2, A, B);
 #pragma unroll
@@ -354,14 +383,7 @@ __device__ __forceinline__ void run_item(const Desc& c, const Item& it, LdsAll<P
     }
     if (stream == 0 && has_i) {
         if (it.out < 0) {
-            const int64_t o = it.act_begin + islot;
-            c.acc[3 * o + 0] = A.v[0];
-            c.acc[3 * o + 1] = A.v[1];
-            c.acc[3 * o + 2] = A.v[2];
-            c.jerk[3 * o + 0] = A.v[3];
-            c.jerk[3 * o + 1] = A.v[4];
-            c.jerk[3 * o + 2] = A.v[5];
-            c.pot[o] = A.v[6];
+            write_out(c, it.act_begin + islot, A.v);
         } else {
             double* p = c.partial + (it.out + islot) * kOut;
 #pragma unroll
@@ -380,8 +402,14 @@ __device__ __forceinline__ int find_entry(const Entry* tab, int n_tab, int64_t g
     return lo;
 }
 
+// Register budget: the mixed form fits 128 VGPRs (4 waves per SIMD) without
+// spilling; the FP64 form needs a little more and runs 3 waves per SIMD.
+template <class P>
+struct WavesPerSimd { static constexpr int value = P::kMixed ? 4 : 3; };
+
 template <class P, bool EAGER, bool DIRECT>
-__global__ __launch_bounds__(kWG) void force_kernel(const Entry* __restrict__ tab, int n_tab, int64_t n_items) {
+__global__ __launch_bounds__(kWG, WavesPerSimd<P>::value) void force_kernel(const Entry* __restrict__ tab, int n_tab,
+                                                                          int64_t n_items) {
     __shared__ LdsAll<P> lds;
     for (int64_t g = blockIdx.x; g < n_items; g += gridDim.x) {
         const int cl = find_entry(tab, n_tab, g, false);
@@ -402,7 +430,9 @@ __global__ __launch_bounds__(kWG) void force_kernel(const Entry* __restrict__ ta
     }
 }
 
-// Sum the split partials of each i-slot in split order.
+// Sum the split partials of each i-slot in split order (a separate launch:
+// the kernel boundary makes every partial visible, with no device-wide
+// fences in the force kernel).
 __global__ __launch_bounds__(kWG) void reduce_kernel(const Entry* __restrict__ tab, int n_tab, int64_t n_rtiles) {
     for (int64_t g = blockIdx.x; g < n_rtiles; g += gridDim.x) {
         const int cl = find_entry(tab, n_tab, g, true);
@@ -418,32 +448,30 @@ __global__ __launch_bounds__(kWG) void reduce_kernel(const Entry* __restrict__ t
 #pragma unroll
                 for (int q = 0; q < kOut; ++q) A[q] += pb[q];
             }
-            const int64_t o = rt.act_begin + s;
-            c.acc[3 * o + 0] = A[0];
-            c.acc[3 * o + 1] = A[1];
-            c.acc[3 * o + 2] = A[2];
-            c.jerk[3 * o + 0] = A[3];
-            c.jerk[3 * o + 1] = A[4];
-            c.jerk[3 * o + 2] = A[5];
-            c.pot[o] = A[6];
+            write_out(c, rt.act_begin + s, A);
         }
     }
 }
 
-// Predict the whole combined memory into the EAGER arrays.
+// Predict the whole combined memory into the EAGER records.
 template <class P>
-__global__ __launch_bounds__(kWG) void predict_all_kernel(Desc c, double* px, double* py, double* pz,
-                                                          typename P::Vel* pvx, typename P::Vel* pvy,
-                                                          typename P::Vel* pvz, int n_total) {
+__global__ __launch_bounds__(kWG) void predict_all_kernel(Desc c, int n_total) {
+    using V = typename P::Vel;
+    const typename P::Rec* rec = static_cast<const typename P::Rec*>(c.rec);
+    typename P::PRec* prec = static_cast<typename P::PRec*>(c.prec);
     for (int j = blockIdx.x * kWG + threadIdx.x; j < n_total; j += gridDim.x * kWG) {
+        const typename P::Rec r = rec[j];
         double x, y, z, vx, vy, vz;
-        predict_j<P>(c, j, x, y, z, vx, vy, vz);
-        px[j] = x;
-        py[j] = y;
-        pz[j] = z;
-        pvx[j] = static_cast<typename P::Vel>(vx);
-        pvy[j] = static_cast<typename P::Vel>(vy);
-        pvz[j] = static_cast<typename P::Vel>(vz);
+        predict_rec<P>(r, c.t, x, y, z, vx, vy, vz);
+        typename P::PRec o{};
+        o.x = x;
+        o.y = y;
+        o.z = z;
+        o.vx = static_cast<V>(vx);
+        o.vy = static_cast<V>(vy);
+        o.vz = static_cast<V>(vz);
+        o.m = r.m;
+        prec[j] = o;
     }
 }
 
@@ -451,9 +479,10 @@ __global__ __launch_bounds__(kWG) void predict_all_kernel(Desc c, double* px, do
 template <class P>
 __global__ __launch_bounds__(kWG) void predict_some_kernel(Desc c, const int32_t* idx, int n, double* out_x,
                                                            double* out_v) {
+    const typename P::Rec* rec = static_cast<const typename P::Rec*>(c.rec);
     for (int k = blockIdx.x * kWG + threadIdx.x; k < n; k += gridDim.x * kWG) {
         double x, y, z, vx, vy, vz;
-        predict_j<P>(c, idx[k], x, y, z, vx, vy, vz);
+        predict_rec<P>(rec[idx[k]], c.t, x, y, z, vx, vy, vz);
         out_x[3 * k] = x;
         out_x[3 * k + 1] = y;
         out_x[3 * k + 2] = z;
@@ -463,43 +492,33 @@ __global__ __launch_bounds__(kWG) void predict_some_kernel(Desc c, const int32_t
     }
 }
 
-// j-memory update (steps 1 and 6): rows [n][3] scattered into the SoA arrays.
+// j-memory update (steps 1 and 6): rows [n][3] written into records.
 // idx == nullptr: row k goes to base + k.  t0 == nullptr: every t0 = t0_all.
-template <class S>
+template <class P>
 __global__ __launch_bounds__(kWG) void scatter_kernel(Desc dst, int n, const int32_t* idx, int base,
                                                       const double* t0, double t0_all, const double* m,
                                                       const double* x, const double* v, const double* a,
                                                       const double* jerk) {
-    double* dt0 = const_cast<double*>(dst.t0);
-    double* dx = const_cast<double*>(dst.x);
-    double* dy = const_cast<double*>(dst.y);
-    double* dz = const_cast<double*>(dst.z);
-    double* dvx = const_cast<double*>(dst.vx);
-    double* dvy = const_cast<double*>(dst.vy);
-    double* dvz = const_cast<double*>(dst.vz);
-    S* dax = static_cast<S*>(const_cast<void*>(dst.ax));
-    S* day = static_cast<S*>(const_cast<void*>(dst.ay));
-    S* daz = static_cast<S*>(const_cast<void*>(dst.az));
-    S* djx = static_cast<S*>(const_cast<void*>(dst.jx));
-    S* djy = static_cast<S*>(const_cast<void*>(dst.jy));
-    S* djz = static_cast<S*>(const_cast<void*>(dst.jz));
-    S* dm = static_cast<S*>(const_cast<void*>(dst.m));
+    using S = typename P::Stored;
+    typename P::Rec* rec = static_cast<typename P::Rec*>(const_cast<void*>(dst.rec));
     for (int k = blockIdx.x * kWG + threadIdx.x; k < n; k += gridDim.x * kWG) {
         const int j = idx ? idx[k] : base + k;
-        dt0[j] = t0 ? t0[k] : t0_all;
-        dm[j] = static_cast<S>(m[k]);
-        dx[j] = x[3 * k];
-        dy[j] = x[3 * k + 1];
-        dz[j] = x[3 * k + 2];
-        dvx[j] = v[3 * k];
-        dvy[j] = v[3 * k + 1];
-        dvz[j] = v[3 * k + 2];
-        dax[j] = static_cast<S>(a[3 * k]);
-        day[j] = static_cast<S>(a[3 * k + 1]);
-        daz[j] = static_cast<S>(a[3 * k + 2]);
-        djx[j] = static_cast<S>(jerk[3 * k]);
-        djy[j] = static_cast<S>(jerk[3 * k + 1]);
-        djz[j] = static_cast<S>(jerk[3 * k + 2]);
+        typename P::Rec r{};
+        r.x = x[3 * k];
+        r.y = x[3 * k + 1];
+        r.z = x[3 * k + 2];
+        r.t0 = t0 ? t0[k] : t0_all;
+        r.vx = v[3 * k];
+        r.vy = v[3 * k + 1];
+        r.vz = v[3 * k + 2];
+        r.m = static_cast<S>(m[k]);
+        r.ax = static_cast<S>(a[3 * k]);
+        r.ay = static_cast<S>(a[3 * k + 1]);
+        r.az = static_cast<S>(a[3 * k + 2]);
+        r.jx = static_cast<S>(jerk[3 * k]);
+        r.jy = static_cast<S>(jerk[3 * k + 1]);
+        r.jz = static_cast<S>(jerk[3 * k + 2]);
+        rec[j] = r;
     }
 }
 
@@ -518,10 +537,10 @@ constexpr int kStageRows = 1 << 16;  // rows per host->device upload chunk
 
 struct Layout {
     size_t jcap, stored, vel;
-    size_t off_t0, off_x[3], off_v[3], off_a[3], off_j[3], off_m;
-    size_t off_px[3], off_pv[3];
-    size_t off_entries, off_active, off_items, off_rtiles, off_partial, off_out, off_stage, off_tab;
+    size_t off_rec, off_prec;
+    size_t off_entries, off_plan, off_partial, off_out, off_stage;
     int64_t items_max, partial_max;
+    size_t plan_bytes;  // launch table + items + reduce tiles + active ids, packed per call
     size_t total;
 };
 
@@ -539,25 +558,19 @@ bool layout_of(const ht_config& c, Layout& L) {
         o = align_up(o + bytes);
         return at;
     };
-    L.off_t0 = take(L.jcap * 8);
-    for (int d = 0; d < 3; ++d) L.off_x[d] = take(L.jcap * 8);
-    for (int d = 0; d < 3; ++d) L.off_v[d] = take(L.jcap * 8);
-    for (int d = 0; d < 3; ++d) L.off_a[d] = take(L.jcap * L.stored);
-    for (int d = 0; d < 3; ++d) L.off_j[d] = take(L.jcap * L.stored);
-    L.off_m = take(L.jcap * L.stored);
+    L.off_rec = take(L.jcap * 128);
     const bool eager = c.predict_mode == HT_PREDICT_EAGER;
-    for (int d = 0; d < 3; ++d) L.off_px[d] = take(eager ? L.jcap * 8 : 0);
-    for (int d = 0; d < 3; ++d) L.off_pv[d] = take(eager ? L.jcap * L.vel : 0);
+    L.off_prec = take(eager ? L.jcap * 64 : 0);
     L.off_entries = take(static_cast<size_t>(c.list_max) * 4);
-    L.off_active = take(static_cast<size_t>(c.active_max) * 4);
     L.items_max = 4 * (static_cast<int64_t>(c.group_max) + c.active_max / 256 + 1) + 4096;
     L.partial_max = 2 * static_cast<int64_t>(c.active_max) + 65536;
-    L.off_items = take(static_cast<size_t>(L.items_max) * sizeof(Item));
-    L.off_rtiles = take(static_cast<size_t>(L.items_max) * sizeof(RTile));
+    L.plan_bytes = align_up(kMaxBatch * sizeof(Entry)) + align_up(static_cast<size_t>(L.items_max) * sizeof(Item)) +
+                   align_up(static_cast<size_t>(L.items_max) * sizeof(RTile)) +
+                   align_up(static_cast<size_t>(c.active_max) * 4) + 256;
+    L.off_plan = take(L.plan_bytes);
     L.off_partial = take(static_cast<size_t>(L.partial_max) * kOut * 8);
     L.off_out = take(static_cast<size_t>(c.active_max) * kOut * 8);
     L.off_stage = take(static_cast<size_t>(kStageRows) * (4 + 8 + 8 + 4 * 24));
-    L.off_tab = take(kMaxBatch * sizeof(Entry));
     L.total = o;
     return true;
 }
@@ -571,10 +584,11 @@ struct ht_ctx {
     bool own_stream = false;
     char* ws = nullptr;
     bool own_ws = false;
-    // host pinned staging: active ids, items, rtiles, launch table, results
+    // host pinned staging: the packed plan (mirrors the device plan region at
+    // offset 0) followed by room for results read back to the host
     char* h_stage = nullptr;
     size_t h_stage_bytes = 0;
-    size_t hs_active = 0, hs_items = 0, hs_rtiles = 0, hs_tab = 0, hs_out = 0;
+    size_t hs_out = 0;
     hipEvent_t stage_free = nullptr;  // recorded after the last copy that reads h_stage
     bool stage_pending = false;
     // j-memory state
@@ -600,28 +614,9 @@ struct ht_ctx {
 
     Desc desc() const {
         Desc d{};
-        d.t0 = dev<double>(L.off_t0);
-        d.x = dev<double>(L.off_x[0]);
-        d.y = dev<double>(L.off_x[1]);
-        d.z = dev<double>(L.off_x[2]);
-        d.vx = dev<double>(L.off_v[0]);
-        d.vy = dev<double>(L.off_v[1]);
-        d.vz = dev<double>(L.off_v[2]);
-        d.ax = ws + L.off_a[0];
-        d.ay = ws + L.off_a[1];
-        d.az = ws + L.off_a[2];
-        d.jx = ws + L.off_j[0];
-        d.jy = ws + L.off_j[1];
-        d.jz = ws + L.off_j[2];
-        d.m = ws + L.off_m;
-        d.px = dev<double>(L.off_px[0]);
-        d.py = dev<double>(L.off_px[1]);
-        d.pz = dev<double>(L.off_px[2]);
-        d.pvx = ws + L.off_pv[0];
-        d.pvy = ws + L.off_pv[1];
-        d.pvz = ws + L.off_pv[2];
+        d.rec = ws + L.off_rec;
+        d.prec = ws + L.off_prec;
         d.entries = dev<int32_t>(L.off_entries);
-        d.active = dev<int32_t>(L.off_active);
         d.partial = dev<double>(L.off_partial);
         d.t = t_pred;
         d.eps2 = cfg.eps2;
@@ -655,68 +650,81 @@ bool check_vectors(const double* const* ptrs, int count) {
     return true;
 }
 
-// Split policy: rounds of the list per item, by tile size.  Large tiles do
-// enough arithmetic per round to hide the gather; small tiles are split so a
-// sparse block step still spreads over many work-groups.
-int64_t rounds_per_item(int tile_log2) {
-    const int64_t t = int64_t(1) << tile_log2;
-    return std::max<int64_t>(4, t / 4);
-}
+// Work plan of one force call.  The active particles of one group (ids are
+// strictly increasing, groups are contiguous ranges) form i-tiles of up to 256
+// with T the next power of two.  A tile's cost is modelled as
+//   rounds * (kGatherCost + T),  rounds = ceil(list length / 256),
+// i.e. per round of 256 entries one gather-and-predict (worth about
+// kGatherCost pairs of arithmetic per lane) plus T pairs per lane.  Tiles are
+// only split (into list ranges whose partials are summed afterwards) when the
+// call has too little work to fill the chip: each tile gets about
+// cost / (total / kTargetItems) items.  The plan depends only on this
+// context's lists and active set, so a context gives the same bits alone and
+// in a batched launch.
+constexpr double kGatherCost = 32.0;
+constexpr double kTargetItems = 2048.0;
 
-// Build the work items of one force call.  ids are strictly increasing.
-// direct: one implicit list 0..n-1 for everybody.
+struct Tile {
+    int64_t jb, je;
+    int32_t tb, ni;
+    int tl;
+    double cost;
+};
+
 int plan(ht_ctx* c, int32_t n_active, const int32_t* ids, bool direct) {
     auto& items = c->items;
     auto& rtiles = c->rtiles;
+    static thread_local std::vector<Tile> tiles;
+    tiles.clear();
     int64_t pairs = 0;
-    for (int scale_shift = 0;; ++scale_shift) {
+    double total = 0.0;
+    size_t g = 0;
+    int32_t k = 0;
+    while (k < n_active) {
+        int64_t ge = c->n, jb = 0, je = c->n;
+        if (!direct) {
+            while (c->group_first[g + 1] <= ids[k]) ++g;
+            ge = c->group_first[g + 1];
+            jb = c->list_off[g];
+            je = c->list_off[g + 1];
+        }
+        int32_t e = k;
+        while (e < n_active && ids[e] < ge) ++e;
+        for (int32_t tb = k; tb < e; tb += 256) {
+            const int32_t ni = std::min<int32_t>(256, e - tb);
+            const int tl = ceil_log2(ni);
+            const int64_t rounds = (je - jb + kRound - 1) / kRound;
+            const double cost = static_cast<double>(rounds) * (kGatherCost + static_cast<double>(1 << tl));
+            tiles.push_back(Tile{jb, je, tb, ni, tl, cost});
+            total += cost;
+            pairs += static_cast<int64_t>(ni) * (je - jb);
+        }
+        k = e;
+    }
+    double quantum = total / kTargetItems;
+    for (int attempt = 0;; ++attempt) {
         items.clear();
         rtiles.clear();
-        pairs = 0;
         int64_t pslots = 0;
-        bool no_split = scale_shift > 40;
-        size_t g = 0;
-        int32_t k = 0;
-        while (k < n_active) {
-            int64_t gb = 0, ge = c->n, jb = 0, je = c->n;
-            if (!direct) {
-                while (c->group_first[g + 1] <= ids[k]) ++g;
-                gb = c->group_first[g];
-                ge = c->group_first[g + 1];
-                jb = c->list_off[g];
-                je = c->list_off[g + 1];
+        for (const Tile& t : tiles) {
+            const int64_t rounds = (t.je - t.jb + kRound - 1) / kRound;
+            int64_t ns = attempt > 60 ? 1 : static_cast<int64_t>(std::ceil(t.cost / quantum));
+            ns = std::max<int64_t>(1, std::min<int64_t>(ns, rounds));
+            if (ns == 1) {
+                items.push_back(Item{t.jb, t.je, -1, t.tb, static_cast<int16_t>(t.ni), static_cast<int16_t>(t.tl)});
+                continue;
             }
-            (void)gb;
-            int32_t e = k;
-            while (e < n_active && ids[e] < ge) ++e;
-            // tiles of this group's run [k, e)
-            for (int32_t tb = k; tb < e; tb += 256) {
-                const int32_t ni = std::min<int32_t>(256, e - tb);
-                const int tl = ceil_log2(ni);
-                const int64_t len = je - jb;
-                const int64_t span = no_split ? len : (rounds_per_item(tl) * kRound) << scale_shift;
-                const int64_t ns = std::max<int64_t>(1, (len + span - 1) / std::max<int64_t>(span, 1));
-                pairs += static_cast<int64_t>(ni) * len;
-                if (ns == 1) {
-                    items.push_back(Item{jb, je, -1, tb, static_cast<int16_t>(ni), static_cast<int16_t>(tl)});
-                } else {
-                    const int64_t per = ((len + ns - 1) / ns + kRound - 1) / kRound * kRound;
-                    int64_t nsu = 0;
-                    for (int64_t s = 0; s < ns; ++s) {
-                        const int64_t b = jb + s * per;
-                        if (b >= je) break;
-                        items.push_back(Item{b, std::min(je, b + per), pslots + s * ni, tb, static_cast<int16_t>(ni),
-                                             static_cast<int16_t>(tl)});
-                        ++nsu;
-                    }
-                    rtiles.push_back(RTile{pslots, tb, ni, static_cast<int32_t>(nsu), 0});
-                    pslots += nsu * ni;
-                }
-            }
-            k = e;
+            const int64_t per = (rounds + ns - 1) / ns * kRound;   // entries per split, whole rounds
+            int32_t nsu = 0;
+            for (int64_t b = t.jb; b < t.je; b += per, ++nsu)
+                items.push_back(Item{b, std::min(t.je, b + per), pslots + static_cast<int64_t>(nsu) * t.ni, t.tb,
+                                     static_cast<int16_t>(t.ni), static_cast<int16_t>(t.tl)});
+            rtiles.push_back(RTile{pslots, t.tb, t.ni, nsu, 0});
+            pslots += static_cast<int64_t>(nsu) * t.ni;
         }
         if (static_cast<int64_t>(items.size()) <= c->L.items_max && pslots <= c->L.partial_max) break;
-        if (no_split) return fail(HT_ERANGE, "work plan exceeds the context's item capacity");
+        if (attempt > 60) return fail(HT_ERANGE, "work plan exceeds the context's item capacity");
+        quantum *= 2.0;
     }
     c->last_pairs = pairs;
     c->last_items = static_cast<int32_t>(items.size());
@@ -734,45 +742,42 @@ int validate_active(const ht_ctx* c, int32_t n_active, const int32_t* ids) {
     return HT_OK;
 }
 
-// Copy ids and items of one context into its device buffers through its
-// pinned staging; fill its launch entry.
-int upload_plan(ht_ctx* c, int32_t n_active, const int32_t* ids, double* acc, double* jerk, double* pot,
-                Entry& e) {
-    int rc = c->stage_wait();
-    if (rc) return rc;
+// Pack one context's items, reduce tiles and active ids into its pinned
+// staging from byte offset `at` on (the device plan region mirrors that
+// staging byte for byte); point the launch entry at the device copies.
+// Returns the end of the packed bytes.
+size_t pack_plan(ht_ctx* c, size_t at, int32_t n_active, const int32_t* ids, double* acc, double* jerk, double* pot,
+                 Entry& e) {
     char* hs = c->h_stage;
-    std::memcpy(hs + c->hs_active, ids, static_cast<size_t>(n_active) * 4);
-    std::memcpy(hs + c->hs_items, c->items.data(), c->items.size() * sizeof(Item));
-    std::memcpy(hs + c->hs_rtiles, c->rtiles.data(), c->rtiles.size() * sizeof(RTile));
-    HT_HIP(hipMemcpyAsync(c->ws + c->L.off_active, hs + c->hs_active, static_cast<size_t>(n_active) * 4,
-                          hipMemcpyHostToDevice, c->stream));
-    HT_HIP(hipMemcpyAsync(c->ws + c->L.off_items, hs + c->hs_items, c->items.size() * sizeof(Item),
-                          hipMemcpyHostToDevice, c->stream));
-    if (!c->rtiles.empty())
-        HT_HIP(hipMemcpyAsync(c->ws + c->L.off_rtiles, hs + c->hs_rtiles, c->rtiles.size() * sizeof(RTile),
-                              hipMemcpyHostToDevice, c->stream));
+    char* dv = c->ws + c->L.off_plan;
+    const size_t o_items = align_up(at);
+    const size_t b_items = c->items.size() * sizeof(Item);
+    const size_t o_rt = align_up(o_items + b_items);
+    const size_t b_rt = c->rtiles.size() * sizeof(RTile);
+    const size_t o_act = align_up(o_rt + b_rt);
+    std::memcpy(hs + o_items, c->items.data(), b_items);
+    if (b_rt) std::memcpy(hs + o_rt, c->rtiles.data(), b_rt);
+    std::memcpy(hs + o_act, ids, static_cast<size_t>(n_active) * 4);
     e.d = c->desc();
+    e.d.active = reinterpret_cast<const int32_t*>(dv + o_act);
     e.d.acc = acc;
     e.d.jerk = jerk;
     e.d.pot = pot;
-    e.items = c->dev<Item>(c->L.off_items);
-    e.rtiles = c->dev<RTile>(c->L.off_rtiles);
-    return HT_OK;
+    e.items = reinterpret_cast<const Item*>(dv + o_items);
+    e.rtiles = reinterpret_cast<const RTile*>(dv + o_rt);
+    return o_act + static_cast<size_t>(n_active) * 4;
+}
+
+// One host-to-device copy of the packed prefix [0, end) of the plan.
+int copy_plan(ht_ctx* c, size_t end) {
+    HT_HIP(hipMemcpyAsync(c->ws + c->L.off_plan, c->h_stage, end, hipMemcpyHostToDevice, c->stream));
+    // the staging buffer is free once this copy is done, not the kernels
+    return c->stage_mark();
 }
 
 template <class P>
-int launch_force(ht_ctx* c0, const Entry* h_tab, int n_tab, int64_t n_items, int64_t n_rtiles, bool direct,
+int launch_force(ht_ctx* c0, const Entry* d_tab, int n_tab, int64_t n_items, int64_t n_rtiles, bool direct,
                  int64_t pairs) {
-    // launch table through the first context's staging
-    int rc = c0->stage_wait();
-    if (rc) return rc;
-    std::memcpy(c0->h_stage + c0->hs_tab, h_tab, static_cast<size_t>(n_tab) * sizeof(Entry));
-    Entry* d_tab = c0->dev<Entry>(c0->L.off_tab);
-    HT_HIP(hipMemcpyAsync(d_tab, c0->h_stage + c0->hs_tab, static_cast<size_t>(n_tab) * sizeof(Entry),
-                          hipMemcpyHostToDevice, c0->stream));
-    // the staging buffer is free once these copies are done, not the kernels
-    rc = c0->stage_mark();
-    if (rc) return rc;
     const bool eager = c0->cfg.predict_mode == HT_PREDICT_EAGER;
     const int grid = grid_for(n_items);
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
@@ -820,14 +825,19 @@ int force_common(ht_ctx* c, int32_t n_active, const int32_t* ids, double* d_acc,
     if (!d_acc || !d_jerk || !d_pot) return fail(HT_EINVAL, "output pointer is NULL");
     rc = plan(c, n_active, ids, direct);
     if (rc) return rc;
-    Entry e{};
-    rc = upload_plan(c, n_active, ids, d_acc, d_jerk, d_pot, e);
+    rc = c->stage_wait();
     if (rc) return rc;
+    Entry e{};
+    const size_t end = pack_plan(c, sizeof(Entry), n_active, ids, d_acc, d_jerk, d_pot, e);
     e.first_item = 0;
     e.first_rtile = 0;
+    std::memcpy(c->h_stage, &e, sizeof(Entry));
+    rc = copy_plan(c, end);
+    if (rc) return rc;
+    const Entry* d_tab = reinterpret_cast<const Entry*>(c->ws + c->L.off_plan);
     const int64_t ni = static_cast<int64_t>(c->items.size()), nr = static_cast<int64_t>(c->rtiles.size());
-    if (c->cfg.precision == HT_PREC_FP64) return launch_force<PrecFp64>(c, &e, 1, ni, nr, direct, c->last_pairs);
-    return launch_force<PrecMixed>(c, &e, 1, ni, nr, direct, c->last_pairs);
+    if (c->cfg.precision == HT_PREC_FP64) return launch_force<PrecFp64>(c, d_tab, 1, ni, nr, direct, c->last_pairs);
+    return launch_force<PrecMixed>(c, d_tab, 1, ni, nr, direct, c->last_pairs);
 }
 
 int force_to_host(ht_ctx* c, int32_t n_active, const int32_t* ids, double* acc, double* jerk, double* pot,
@@ -876,10 +886,10 @@ int upload_rows(ht_ctx* c, int32_t n, const int32_t* idx, int base, const double
         HT_HIP(hipMemcpyAsync(s_j, jerk + 3 * static_cast<size_t>(k0), r3, hipMemcpyHostToDevice, c->stream));
         const int grid = (cnt + kWG - 1) / kWG;
         if (c->cfg.precision == HT_PREC_FP64)
-            scatter_kernel<double><<<grid, kWG, 0, c->stream>>>(d, cnt, idx ? s_idx : nullptr, base + k0,
+            scatter_kernel<PrecFp64><<<grid, kWG, 0, c->stream>>>(d, cnt, idx ? s_idx : nullptr, base + k0,
                                                                 t0 ? s_t0 : nullptr, t0_all, s_m, s_x, s_v, s_a, s_j);
         else
-            scatter_kernel<float><<<grid, kWG, 0, c->stream>>>(d, cnt, idx ? s_idx : nullptr, base + k0,
+            scatter_kernel<PrecMixed><<<grid, kWG, 0, c->stream>>>(d, cnt, idx ? s_idx : nullptr, base + k0,
                                                                t0 ? s_t0 : nullptr, t0_all, s_m, s_x, s_v, s_a, s_j);
         HT_HIP(hipGetLastError());
         // the staging area is reused by the next chunk: copies are ordered on the stream, and
@@ -951,10 +961,7 @@ int ht_create(ht_ctx** out, const ht_config* cfg, void* d_workspace, size_t work
         o = align_up(o + b);
         return at;
     };
-    c->hs_active = take(static_cast<size_t>(cfg->active_max) * 4);
-    c->hs_items = take(static_cast<size_t>(L.items_max) * sizeof(Item));
-    c->hs_rtiles = take(static_cast<size_t>(L.items_max) * sizeof(RTile));
-    c->hs_tab = take(kMaxBatch * sizeof(Entry));
+    take(L.plan_bytes);
     c->hs_out = take(static_cast<size_t>(cfg->active_max) * kOut * 8);
     c->h_stage_bytes = o;
     if (hipHostMalloc(reinterpret_cast<void**>(&c->h_stage), o, hipHostMallocDefault) != hipSuccess)
@@ -1021,9 +1028,9 @@ int ht_set_j_particles_async(ht_ctx* c, int32_t n, const int32_t* d_idx, const d
     const Desc d = c->desc();
     const int grid = (n + kWG - 1) / kWG;
     if (c->cfg.precision == HT_PREC_FP64)
-        scatter_kernel<double><<<grid, kWG, 0, c->stream>>>(d, n, d_idx, 0, d_t0, 0.0, d_m, d_x, d_v, d_a, d_jerk);
+        scatter_kernel<PrecFp64><<<grid, kWG, 0, c->stream>>>(d, n, d_idx, 0, d_t0, 0.0, d_m, d_x, d_v, d_a, d_jerk);
     else
-        scatter_kernel<float><<<grid, kWG, 0, c->stream>>>(d, n, d_idx, 0, d_t0, 0.0, d_m, d_x, d_v, d_a, d_jerk);
+        scatter_kernel<PrecMixed><<<grid, kWG, 0, c->stream>>>(d, n, d_idx, 0, d_t0, 0.0, d_m, d_x, d_v, d_a, d_jerk);
     HT_HIP(hipGetLastError());
     return HT_OK;
 }
@@ -1093,15 +1100,9 @@ int ht_predict(ht_ctx* c, double t) {
         const Desc d = c->desc();
         const int grid = std::min((total + kWG - 1) / kWG, 8192);
         if (c->cfg.precision == HT_PREC_FP64)
-            predict_all_kernel<PrecFp64><<<grid, kWG, 0, c->stream>>>(
-                d, const_cast<double*>(d.px), const_cast<double*>(d.py), const_cast<double*>(d.pz),
-                static_cast<double*>(const_cast<void*>(d.pvx)), static_cast<double*>(const_cast<void*>(d.pvy)),
-                static_cast<double*>(const_cast<void*>(d.pvz)), total);
+            predict_all_kernel<PrecFp64><<<grid, kWG, 0, c->stream>>>(d, total);
         else
-            predict_all_kernel<PrecMixed><<<grid, kWG, 0, c->stream>>>(
-                d, const_cast<double*>(d.px), const_cast<double*>(d.py), const_cast<double*>(d.pz),
-                static_cast<float*>(const_cast<void*>(d.pvx)), static_cast<float*>(const_cast<void*>(d.pvy)),
-                static_cast<float*>(const_cast<void*>(d.pvz)), total);
+            predict_all_kernel<PrecMixed><<<grid, kWG, 0, c->stream>>>(d, total);
         HT_HIP(hipGetLastError());
     }
     c->predicted = true;
@@ -1123,6 +1124,20 @@ int ht_force_direct(ht_ctx* c, int32_t n_active, const int32_t* ids, double* acc
 int ht_force_direct_async(ht_ctx* c, int32_t n_active, const int32_t* ids, double* d_acc, double* d_jerk,
                           double* d_pot) {
     return force_common(c, n_active, ids, d_acc, d_jerk, d_pot, true);
+}
+
+int ht_step_async(ht_ctx* c, int32_t n_upd, const int32_t* d_idx, const double* d_t0, const double* d_m,
+                  const double* d_x, const double* d_v, const double* d_a, const double* d_jerk, double t,
+                  int32_t n_active, const int32_t* ids, double* d_acc, double* d_jerk_out, double* d_pot) {
+    if (!c) return fail(HT_EINVAL, "ctx is NULL");
+    if (!c->have_lists) return fail(HT_ESTATE, "interaction lists not set");
+    int rc = validate_active(c, n_active, ids);
+    if (rc) return rc;
+    rc = ht_set_j_particles_async(c, n_upd, d_idx, d_t0, d_m, d_x, d_v, d_a, d_jerk);
+    if (rc) return rc;
+    rc = ht_predict(c, t);
+    if (rc) return rc;
+    return force_common(c, n_active, ids, d_acc, d_jerk_out, d_pot, false);
 }
 
 int ht_get_predicted(ht_ctx* c, int32_t n, const int32_t* idx, double* xp, double* vp) {
@@ -1178,6 +1193,10 @@ int ht_force_batch_async(int32_t n_ctx, ht_ctx* const* ctxs, const int32_t* n_ac
     std::vector<Entry> tab;
     tab.reserve(n_ctx);
     int64_t n_items = 0, n_rtiles = 0, pairs = 0;
+    int rc = c0->stage_wait();
+    if (rc) return rc;
+    const size_t tab_bytes = static_cast<size_t>(n_ctx) * sizeof(Entry);
+    size_t end0 = tab_bytes;
     for (int32_t k = 0; k < n_ctx; ++k) {
         ht_ctx* c = ctxs[k];
         if (n_active[k] == 0) {
@@ -1185,26 +1204,33 @@ int ht_force_batch_async(int32_t n_ctx, ht_ctx* const* ctxs, const int32_t* n_ac
             c->last_items = 0;
             continue;
         }
-        int rc = plan(c, n_active[k], ids[k], false);
+        rc = plan(c, n_active[k], ids[k], false);
         if (rc) return rc;
         Entry e{};
-        rc = upload_plan(c, n_active[k], ids[k], d_acc[k], d_jerk[k], d_pot[k], e);
-        if (rc) return rc;
+        if (c == c0) {
+            end0 = pack_plan(c, tab_bytes, n_active[k], ids[k], d_acc[k], d_jerk[k], d_pot[k], e);
+        } else {
+            rc = c->stage_wait();
+            if (rc) return rc;
+            rc = copy_plan(c, pack_plan(c, 0, n_active[k], ids[k], d_acc[k], d_jerk[k], d_pot[k], e));
+            if (rc) return rc;
+        }
         e.first_item = n_items;
         e.first_rtile = n_rtiles;
         n_items += static_cast<int64_t>(c->items.size());
         n_rtiles += static_cast<int64_t>(c->rtiles.size());
         pairs += c->last_pairs;
         tab.push_back(e);
-        if (c != c0) {
-            int rc2 = c->stage_mark();
-            if (rc2) return rc2;
-        }
     }
     if (tab.empty()) return HT_OK;
+    std::memcpy(c0->h_stage, tab.data(), tab.size() * sizeof(Entry));
+    rc = copy_plan(c0, end0);
+    if (rc) return rc;
+    const Entry* d_tab = reinterpret_cast<const Entry*>(c0->ws + c0->L.off_plan);
+    const int nt = static_cast<int>(tab.size());
     if (c0->cfg.precision == HT_PREC_FP64)
-        return launch_force<PrecFp64>(c0, tab.data(), static_cast<int>(tab.size()), n_items, n_rtiles, false, pairs);
-    return launch_force<PrecMixed>(c0, tab.data(), static_cast<int>(tab.size()), n_items, n_rtiles, false, pairs);
+        return launch_force<PrecFp64>(c0, d_tab, nt, n_items, n_rtiles, false, pairs);
+    return launch_force<PrecMixed>(c0, d_tab, nt, n_items, n_rtiles, false, pairs);
 }
 
 int ht_sync(ht_ctx* c) {

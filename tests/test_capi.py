@@ -34,8 +34,8 @@ def test_workspace_size_and_config_validation():
     cfg = B.HtConfig(0, 1, 0, 1 << 20, 1 << 20, 4096, 40_000_000, 1 << 20, 1e-11, None)
     n = ctypes.c_size_t()
     assert L.ht_workspace_bytes(ctypes.byref(cfg), ctypes.byref(n)) == 0
-    # mixed SoA j-memory alone is 84 bytes per particle or node
-    assert n.value > 84 * (2 << 20) + 4 * 40_000_000
+    # j-memory records alone are 128 bytes per particle or node
+    assert n.value > 128 * (2 << 20) + 4 * 40_000_000
     bad = B.HtConfig(0, 7, 0, 10, 10, 10, 10, 10, 0.0, None)
     assert L.ht_workspace_bytes(ctypes.byref(bad), ctypes.byref(n)) == -1
     assert b"invalid configuration" in L.ht_last_error()
@@ -43,15 +43,18 @@ def test_workspace_size_and_config_validation():
     assert L.ht_workspace_bytes(ctypes.byref(bad), ctypes.byref(n)) == -1
 
 
-def test_fp64_workspace_is_larger_than_mixed():
+def test_workspace_holds_one_record_line_per_entry():
+    """Every particle and node owns one 128-byte j-memory record (one cache
+    line per list-indexed gather), whatever the precision form."""
     L = B.device_lib()
-    sizes = []
     for prec in (0, 1):
-        cfg = B.HtConfig(0, prec, 0, 100000, 100000, 1000, 1000000, 100000, 1e-4, None)
-        n = ctypes.c_size_t()
-        assert L.ht_workspace_bytes(ctypes.byref(cfg), ctypes.byref(n)) == 0
-        sizes.append(n.value)
-    assert sizes[0] > sizes[1]
+        sizes = []
+        for n in (100000, 200000):
+            cfg = B.HtConfig(0, prec, 0, n, n, 1000, 1000000, n, 1e-4, None)
+            b = ctypes.c_size_t()
+            assert L.ht_workspace_bytes(ctypes.byref(cfg), ctypes.byref(b)) == 0
+            sizes.append(b.value)
+        assert sizes[1] - sizes[0] >= 128 * 200000
 
 
 @pytest.mark.skipif(gpu_available(), reason="checks the no-device error path")

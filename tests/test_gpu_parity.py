@@ -339,3 +339,50 @@ def test_batch_equals_alone(oracle):
         assert np.array_equal(a1, a2.cpu().numpy())
         assert np.array_equal(j1, j2.cpu().numpy())
         assert np.array_equal(p1, p2.cpu().numpy())
+
+
+def test_step_async_equals_separate_calls(oracle):
+    """ht_step_async (update + predict + force in one call) gives the same bits
+    as the three separate calls, and matches the oracle."""
+    import torch
+    say("step_async vs separate calls")
+    n = 4000
+    x, v, m = W.plummer(n, 81)
+    z = np.zeros((n, 3))
+    ptr = B.HostTree(x, v, z, z, m, 1, 128, 0.5)
+    x, v, m = x[ptr.perm], v[ptr.perm], m[ptr.perm]
+    t0, a, j = W.random_block_state(n, 82, 0.25)
+    ctxs = []
+    for _ in range(2):
+        c = make_ctx("mixed", n, 2 * n, n, 2 * ptr.n_entries, 1e-4)
+        c.set_j_particles(t0, m, x, v, a, j)
+        c.set_nodes(0.0, ptr.node_m, ptr.node_x, ptr.node_v, ptr.node_a, ptr.node_j)
+        c.set_interaction_lists(ptr.group_first, ptr.list_off, ptr.entries)
+        ctxs.append(c)
+    rng = np.random.default_rng(83)
+    upd_ids = np.sort(rng.choice(n, 300, replace=False)).astype(np.int32)
+    nt0 = np.full(300, 0.25)
+    nx = x[upd_ids] + 1e-3
+    dev = lambda u: torch.from_numpy(np.ascontiguousarray(u)).cuda()  # noqa: E731
+    upd = (300, dev(upd_ids), dev(nt0), dev(m[upd_ids]), dev(nx), dev(v[upd_ids]), dev(a[upd_ids]), dev(j[upd_ids]))
+    act = np.sort(rng.choice(n, 700, replace=False)).astype(np.int32)
+    outs = [tuple(torch.empty(s, dtype=torch.float64, device="cuda") for s in ((700, 3), (700, 3), (700,)))
+            for _ in range(2)]
+    ctxs[0].step_async(upd, 0.3125, act, *outs[0])
+    ctxs[0].sync()
+    ctxs[1].set_j_particles_async(*upd)
+    ctxs[1].predict(0.3125)
+    ctxs[1].force_async(act, *outs[1])
+    ctxs[1].sync()
+    for p, q in zip(outs[0], outs[1]):
+        assert torch.equal(p, q)
+    # against the oracle on the updated state
+    t0u, xu = t0.copy(), x.copy()
+    t0u[upd_ids] = 0.25
+    xu[upd_ids] = nx
+    f32 = lambda u: u.astype(np.float32).astype(np.float64)  # noqa: E731
+    xp, vp = oracle.predict(0.3125, t0u, xu, v, f32(a), f32(j))
+    nxp, nvp = oracle.predict(0.3125, 0.0, ptr.node_x, ptr.node_v, f32(ptr.node_a), f32(ptr.node_j))
+    want = oracle.force_list(act, np.vstack([xp, nxp]), np.vstack([vp, nvp]), f32(np.concatenate([m, ptr.node_m])),
+                             1e-4, ptr.group_first, ptr.list_off, ptr.entries)
+    assert_close("step_async", "mixed", tuple(o.cpu().numpy() for o in outs[0]), want)
