@@ -81,6 +81,7 @@ def device_lib():
             "ht_sync": [_vp],
             "ht_last_stats": [_vp, _c_i64p, _c_i32p],
             "ht_set_timing": [_vp, i],
+            "ht_set_tuning": [_vp, d, d],
             "ht_kernel_timing": [_vp, _c_dp, _c_i64p, _c_i64p],
             "ht_last_error": [],
         }
@@ -262,6 +263,9 @@ class Context:
 
     def sync(self):
         _check(device_lib().ht_sync(self._h))
+
+    def set_tuning(self, gather_cost=32.0, target_items=2048.0):
+        _check(device_lib().ht_set_tuning(self._h, float(gather_cost), float(target_items)))
 
     def set_timing(self, enable=True):
         _check(device_lib().ht_set_timing(self._h, 1 if enable else 0))

@@ -366,19 +366,25 @@ __device__ __forceinline__ void run_item(const Desc& c, const Item& it, LdsAll<P
         }
     }
 
-    // reduce the S j-streams of each i-slot, in stream order
+    // reduce the S j-streams of each i-slot: a fixed pairwise tree in LDS
+    // (stream r += stream r + h for h = S/2, S/4, ..., 1), so the order never
+    // depends on timing and the depth is log2(S)
     if constexpr (S > 1) {
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < kOut; ++q) lds.red[q * kWG + tid] = A.v[q];
+#pragma unroll
+        for (int h = S / 2; h >= 1; h /= 2) {
+            __syncthreads();
+            if (stream < h) {
+#pragma unroll
+                for (int q = 0; q < kOut; ++q) lds.red[q * kWG + tid] += lds.red[q * kWG + tid + h * T];
+            }
+        }
         __syncthreads();
         if (stream == 0) {
 #pragma unroll
-            for (int q = 0; q < kOut; ++q) {
-                double s = lds.red[q * kWG + islot];
-                for (int r = 1; r < S; ++r) s += lds.red[q * kWG + r * T + islot];
-                A.v[q] = s;
-            }
+            for (int q = 0; q < kOut; ++q) A.v[q] = lds.red[q * kWG + islot];
         }
     }
     if (stream == 0 && has_i) {
@@ -432,19 +438,30 @@ __global__ __launch_bounds__(kWG, WavesPerSimd<P>::value) void force_kernel(cons
 
 // Sum the split partials of each i-slot in split order (a separate launch:
 // the kernel boundary makes every partial visible, with no device-wide
-// fences in the force kernel).
+// fences in the force kernel).  A tile's partials are first loaded into LDS
+// by all threads at once, so the dependent adds read LDS, not memory.
+constexpr int kRedLds = 6144;   // doubles of LDS for one tile's partials
+
 __global__ __launch_bounds__(kWG) void reduce_kernel(const Entry* __restrict__ tab, int n_tab, int64_t n_rtiles) {
+    __shared__ double buf[kRedLds];
     for (int64_t g = blockIdx.x; g < n_rtiles; g += gridDim.x) {
         const int cl = find_entry(tab, n_tab, g, true);
         const Desc& c = tab[cl].d;
         const RTile rt = tab[cl].rtiles[g - tab[cl].first_rtile];
+        const int64_t nval = static_cast<int64_t>(rt.nsplit) * rt.n_i * kOut;
+        const double* src = c.partial + rt.pbase * kOut;
+        if (nval <= kRedLds) {
+            __syncthreads();
+            for (int k = threadIdx.x; k < nval; k += kWG) buf[k] = src[k];
+            __syncthreads();
+        }
         for (int s = threadIdx.x; s < rt.n_i; s += kWG) {
+            const double* p = nval <= kRedLds ? buf : src;
             double A[kOut];
-            const double* p = c.partial + (rt.pbase + s) * kOut;
 #pragma unroll
-            for (int q = 0; q < kOut; ++q) A[q] = p[q];
+            for (int q = 0; q < kOut; ++q) A[q] = p[static_cast<int64_t>(s) * kOut + q];
             for (int b = 1; b < rt.nsplit; ++b) {
-                const double* pb = c.partial + (rt.pbase + static_cast<int64_t>(b) * rt.n_i + s) * kOut;
+                const double* pb = p + (static_cast<int64_t>(b) * rt.n_i + s) * kOut;
 #pragma unroll
                 for (int q = 0; q < kOut; ++q) A[q] += pb[q];
             }
@@ -533,6 +550,8 @@ int ceil_log2(int64_t v) {
 }
 
 constexpr int kMaxBatch = 1024;   // clusters per batched launch
+constexpr double kGatherCostDefault = 32.0;    // work-plan cost of one round's gather, in pairs per lane
+constexpr double kTargetItemsDefault = 2048.0; // work items a call is split towards (2 per resident slot)
 constexpr int kStageRows = 1 << 16;  // rows per host->device upload chunk
 
 struct Layout {
@@ -584,13 +603,16 @@ struct ht_ctx {
     bool own_stream = false;
     char* ws = nullptr;
     bool own_ws = false;
-    // host pinned staging: the packed plan (mirrors the device plan region at
-    // offset 0) followed by room for results read back to the host
-    char* h_stage = nullptr;
-    size_t h_stage_bytes = 0;
-    size_t hs_out = 0;
-    hipEvent_t stage_free = nullptr;  // recorded after the last copy that reads h_stage
-    bool stage_pending = false;
+    // Host pinned staging: a ring of plan slots (each mirrors the device plan
+    // region byte for byte) so the host can plan several calls ahead of the
+    // device, then room for results read back to host arrays.  A slot is
+    // reused once the copy that read it has completed.
+    static constexpr int kPlanSlots = 4;
+    char* h_pinned = nullptr;
+    char* h_out = nullptr;
+    hipEvent_t slot_free[kPlanSlots] = {};
+    bool slot_pending[kPlanSlots] = {};
+    int slot = 0;
     // j-memory state
     int32_t n = 0, n_nodes = 0, n_groups = 0;
     int64_t n_entries = 0;
@@ -605,6 +627,9 @@ struct ht_ctx {
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     int64_t timed_pairs = 0;
+    // work-plan tuning (see plan())
+    double gather_cost = kGatherCostDefault;
+    double target_items = kTargetItemsDefault;
     // scratch for planning
     std::vector<Item> items;
     std::vector<RTile> rtiles;
@@ -623,18 +648,25 @@ struct ht_ctx {
         return d;
     }
 
-    // Wait until the pinned staging buffer may be overwritten.
-    int stage_wait() {
-        if (stage_pending) {
-            HT_HIP(hipEventSynchronize(stage_free));
-            stage_pending = false;
+    char* plan_host() const { return h_pinned + static_cast<size_t>(slot) * L.plan_bytes; }
+    // Wait until the current plan slot may be overwritten.
+    int slot_acquire() {
+        if (slot_pending[slot]) {
+            HT_HIP(hipEventSynchronize(slot_free[slot]));
+            slot_pending[slot] = false;
         }
         return HT_OK;
     }
-    int stage_mark() {
-        HT_HIP(hipEventRecord(stage_free, stream));
-        stage_pending = true;
+    // The copy reading the current slot is queued: mark it and move on.
+    int slot_release() {
+        HT_HIP(hipEventRecord(slot_free[slot], stream));
+        slot_pending[slot] = true;
+        slot = (slot + 1) % kPlanSlots;
         return HT_OK;
+    }
+    // After a stream synchronisation every slot is free.
+    void slots_all_free() {
+        for (int k = 0; k < kPlanSlots; ++k) slot_pending[k] = false;
     }
 };
 
@@ -658,11 +690,11 @@ bool check_vectors(const double* const* ptrs, int count) {
 // kGatherCost pairs of arithmetic per lane) plus T pairs per lane.  Tiles are
 // only split (into list ranges whose partials are summed afterwards) when the
 // call has too little work to fill the chip: each tile gets about
-// cost / (total / kTargetItems) items.  The plan depends only on this
-// context's lists and active set, so a context gives the same bits alone and
-// in a batched launch.
-constexpr double kGatherCost = 32.0;
-constexpr double kTargetItems = 2048.0;
+// cost / (total / target_items) items.  Items are then ordered by decreasing
+// cost: the hardware hands work-groups out in index order as slots free up,
+// which makes that a longest-first schedule.  The plan depends only on this
+// context's lists, active set and tuning, so a context gives the same bits
+// alone and in a batched launch.
 
 struct Tile {
     int64_t jb, je;
@@ -694,14 +726,14 @@ int plan(ht_ctx* c, int32_t n_active, const int32_t* ids, bool direct) {
             const int32_t ni = std::min<int32_t>(256, e - tb);
             const int tl = ceil_log2(ni);
             const int64_t rounds = (je - jb + kRound - 1) / kRound;
-            const double cost = static_cast<double>(rounds) * (kGatherCost + static_cast<double>(1 << tl));
+            const double cost = static_cast<double>(rounds) * (c->gather_cost + static_cast<double>(1 << tl));
             tiles.push_back(Tile{jb, je, tb, ni, tl, cost});
             total += cost;
             pairs += static_cast<int64_t>(ni) * (je - jb);
         }
         k = e;
     }
-    double quantum = total / kTargetItems;
+    double quantum = total / c->target_items;
     for (int attempt = 0;; ++attempt) {
         items.clear();
         rtiles.clear();
@@ -726,6 +758,13 @@ int plan(ht_ctx* c, int32_t n_active, const int32_t* ids, bool direct) {
         if (attempt > 60) return fail(HT_ERANGE, "work plan exceeds the context's item capacity");
         quantum *= 2.0;
     }
+    // longest first; ties keep plan order so the plan stays deterministic
+    auto cost_of = [c](const Item& it) {
+        return static_cast<double>((it.j_end - it.j_begin + kRound - 1) / kRound) *
+               (c->gather_cost + static_cast<double>(1 << it.tile_log2));
+    };
+    std::stable_sort(items.begin(), items.end(),
+                     [&](const Item& a, const Item& b) { return cost_of(a) > cost_of(b); });
     c->last_pairs = pairs;
     c->last_items = static_cast<int32_t>(items.size());
     return HT_OK;
@@ -748,7 +787,7 @@ int validate_active(const ht_ctx* c, int32_t n_active, const int32_t* ids) {
 // Returns the end of the packed bytes.
 size_t pack_plan(ht_ctx* c, size_t at, int32_t n_active, const int32_t* ids, double* acc, double* jerk, double* pot,
                  Entry& e) {
-    char* hs = c->h_stage;
+    char* hs = c->plan_host();
     char* dv = c->ws + c->L.off_plan;
     const size_t o_items = align_up(at);
     const size_t b_items = c->items.size() * sizeof(Item);
@@ -770,9 +809,9 @@ size_t pack_plan(ht_ctx* c, size_t at, int32_t n_active, const int32_t* ids, dou
 
 // One host-to-device copy of the packed prefix [0, end) of the plan.
 int copy_plan(ht_ctx* c, size_t end) {
-    HT_HIP(hipMemcpyAsync(c->ws + c->L.off_plan, c->h_stage, end, hipMemcpyHostToDevice, c->stream));
-    // the staging buffer is free once this copy is done, not the kernels
-    return c->stage_mark();
+    HT_HIP(hipMemcpyAsync(c->ws + c->L.off_plan, c->plan_host(), end, hipMemcpyHostToDevice, c->stream));
+    // the slot is free once this copy is done, not the kernels
+    return c->slot_release();
 }
 
 template <class P>
@@ -825,13 +864,13 @@ int force_common(ht_ctx* c, int32_t n_active, const int32_t* ids, double* d_acc,
     if (!d_acc || !d_jerk || !d_pot) return fail(HT_EINVAL, "output pointer is NULL");
     rc = plan(c, n_active, ids, direct);
     if (rc) return rc;
-    rc = c->stage_wait();
+    rc = c->slot_acquire();
     if (rc) return rc;
     Entry e{};
     const size_t end = pack_plan(c, sizeof(Entry), n_active, ids, d_acc, d_jerk, d_pot, e);
     e.first_item = 0;
     e.first_rtile = 0;
-    std::memcpy(c->h_stage, &e, sizeof(Entry));
+    std::memcpy(c->plan_host(), &e, sizeof(Entry));
     rc = copy_plan(c, end);
     if (rc) return rc;
     const Entry* d_tab = reinterpret_cast<const Entry*>(c->ws + c->L.off_plan);
@@ -849,13 +888,13 @@ int force_to_host(ht_ctx* c, int32_t n_active, const int32_t* ids, double* acc, 
     double* dpot = djerk + 3 * static_cast<size_t>(c->cfg.active_max);
     int rc = force_common(c, n_active, ids, dacc, djerk, dpot, direct);
     if (rc || n_active == 0) return rc;
-    char* h = c->h_stage + c->hs_out;
+    char* h = c->h_out;
     const size_t n3 = 3 * static_cast<size_t>(n_active) * 8, n1 = static_cast<size_t>(n_active) * 8;
     HT_HIP(hipMemcpyAsync(h, dacc, n3, hipMemcpyDeviceToHost, c->stream));
     HT_HIP(hipMemcpyAsync(h + n3, djerk, n3, hipMemcpyDeviceToHost, c->stream));
     HT_HIP(hipMemcpyAsync(h + 2 * n3, dpot, n1, hipMemcpyDeviceToHost, c->stream));
     HT_HIP(hipStreamSynchronize(c->stream));
-    c->stage_pending = false;
+    c->slots_all_free();
     std::memcpy(acc, h, n3);
     std::memcpy(jerk, h + n3, n3);
     std::memcpy(pot, h + 2 * n3, n1);
@@ -961,13 +1000,14 @@ int ht_create(ht_ctx** out, const ht_config* cfg, void* d_workspace, size_t work
         o = align_up(o + b);
         return at;
     };
-    take(L.plan_bytes);
-    c->hs_out = take(static_cast<size_t>(cfg->active_max) * kOut * 8);
-    c->h_stage_bytes = o;
-    if (hipHostMalloc(reinterpret_cast<void**>(&c->h_stage), o, hipHostMallocDefault) != hipSuccess)
+    take(ht_ctx::kPlanSlots * L.plan_bytes);
+    const size_t out_at = take(static_cast<size_t>(cfg->active_max) * kOut * 8);
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->h_pinned), o, hipHostMallocDefault) != hipSuccess)
         return cleanup(fail(HT_ENOMEM, "hipHostMalloc of %zu bytes failed", o));
-    if (hipEventCreateWithFlags(&c->stage_free, hipEventDisableTiming) != hipSuccess)
-        return cleanup(fail(HT_EHIP, "hipEventCreate failed"));
+    c->h_out = c->h_pinned + out_at;
+    for (int k = 0; k < ht_ctx::kPlanSlots; ++k)
+        if (hipEventCreateWithFlags(&c->slot_free[k], hipEventDisableTiming) != hipSuccess)
+            return cleanup(fail(HT_EHIP, "hipEventCreate failed"));
     c->items.reserve(1024);
     *out = c;
     return HT_OK;
@@ -977,9 +1017,10 @@ int ht_destroy(ht_ctx* c) {
     if (!c) return HT_OK;
     // teardown: failures here cannot be acted on, so their codes are dropped
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    if (c->stage_free) (void)hipEventDestroy(c->stage_free);
+    for (hipEvent_t e : c->slot_free)
+        if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
-    if (c->h_stage) (void)hipHostFree(c->h_stage);
+    if (c->h_pinned) (void)hipHostFree(c->h_pinned);
     if (c->own_ws && c->ws) (void)hipFree(c->ws);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
@@ -1184,6 +1225,8 @@ int ht_force_batch_async(int32_t n_ctx, ht_ctx* const* ctxs, const int32_t* n_ac
             c->cfg.predict_mode != c0->cfg.predict_mode)
             return fail(HT_EINVAL, "ctx %d differs in device, precision or predict mode", k);
         if (c->stream != c0->stream) return fail(HT_EINVAL, "ctx %d does not share the stream of ctx 0", k);
+        for (int32_t q = 0; q < k; ++q)
+            if (ctxs[q] == c) return fail(HT_EINVAL, "ctx %d appears twice in the batch", k);
         if (!c->have_particles || !c->have_lists) return fail(HT_ESTATE, "ctx %d: lists not set", k);
         if (!c->predicted) return fail(HT_ESTATE, "ctx %d: not predicted", k);
         int rc = validate_active(c, n_active[k], ids[k]);
@@ -1193,7 +1236,7 @@ int ht_force_batch_async(int32_t n_ctx, ht_ctx* const* ctxs, const int32_t* n_ac
     std::vector<Entry> tab;
     tab.reserve(n_ctx);
     int64_t n_items = 0, n_rtiles = 0, pairs = 0;
-    int rc = c0->stage_wait();
+    int rc = c0->slot_acquire();
     if (rc) return rc;
     const size_t tab_bytes = static_cast<size_t>(n_ctx) * sizeof(Entry);
     size_t end0 = tab_bytes;
@@ -1210,7 +1253,7 @@ int ht_force_batch_async(int32_t n_ctx, ht_ctx* const* ctxs, const int32_t* n_ac
         if (c == c0) {
             end0 = pack_plan(c, tab_bytes, n_active[k], ids[k], d_acc[k], d_jerk[k], d_pot[k], e);
         } else {
-            rc = c->stage_wait();
+            rc = c->slot_acquire();
             if (rc) return rc;
             rc = copy_plan(c, pack_plan(c, 0, n_active[k], ids[k], d_acc[k], d_jerk[k], d_pot[k], e));
             if (rc) return rc;
@@ -1223,7 +1266,7 @@ int ht_force_batch_async(int32_t n_ctx, ht_ctx* const* ctxs, const int32_t* n_ac
         tab.push_back(e);
     }
     if (tab.empty()) return HT_OK;
-    std::memcpy(c0->h_stage, tab.data(), tab.size() * sizeof(Entry));
+    std::memcpy(c0->plan_host(), tab.data(), tab.size() * sizeof(Entry));
     rc = copy_plan(c0, end0);
     if (rc) return rc;
     const Entry* d_tab = reinterpret_cast<const Entry*>(c0->ws + c0->L.off_plan);
@@ -1236,7 +1279,7 @@ int ht_force_batch_async(int32_t n_ctx, ht_ctx* const* ctxs, const int32_t* n_ac
 int ht_sync(ht_ctx* c) {
     if (!c) return fail(HT_EINVAL, "ctx is NULL");
     HT_HIP(hipStreamSynchronize(c->stream));
-    c->stage_pending = false;
+    c->slots_all_free();
     return HT_OK;
 }
 
@@ -1251,7 +1294,7 @@ int ht_set_timing(ht_ctx* c, int32_t enable) {
 int ht_kernel_timing(ht_ctx* c, double* force_ms, int64_t* launches, int64_t* pairs) {
     if (!c || !force_ms || !launches || !pairs) return fail(HT_EINVAL, "NULL argument");
     HT_HIP(hipStreamSynchronize(c->stream));
-    c->stage_pending = false;
+    c->slots_all_free();
     double total = 0.0;
     for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
         float ms = 0.0f;
@@ -1263,6 +1306,15 @@ int ht_kernel_timing(ht_ctx* c, double* force_ms, int64_t* launches, int64_t* pa
     *pairs = c->timed_pairs;
     c->ev_used = 0;
     c->timed_pairs = 0;
+    return HT_OK;
+}
+
+int ht_set_tuning(ht_ctx* c, double gather_cost, double target_items) {
+    if (!c) return fail(HT_EINVAL, "ctx is NULL");
+    if (!(gather_cost >= 0.0 && gather_cost < 1e6) || !(target_items >= 1.0 && target_items < 1e8))
+        return fail(HT_EINVAL, "tuning values out of range");
+    c->gather_cost = gather_cost;
+    c->target_items = target_items;
     return HT_OK;
 }
 
