@@ -155,6 +155,53 @@ int ht_force_batch_async(int32_t n_ctx, ht_ctx *const *ctxs, const int32_t *n_ac
                          const int32_t *const *active_ids, double *const *d_acc, double *const *d_jerk,
                          double *const *d_pot);
 
+/* ---------------------------------------------------------------------------
+ * Batched engine step (many clusters, one launch per phase).
+ *
+ * A batch owns device staging for the updates and work plans of all clusters
+ * in one engine step.  Its contexts must share the batch's stream, device,
+ * precision and predict mode; each keeps its own j-memory, lists and block
+ * time (set by ht_predict on that context).  Work plans are made per context,
+ * so every cluster gets bit-identical results alone and in any batch.
+ * Capacities: max_clusters <= 1024 contexts per call; max_items work items and
+ * max_active active particles summed over the contexts of one force call;
+ * max_rows update rows summed over one update call.
+ */
+typedef struct ht_batch ht_batch;
+
+/* One corrected particle for a j-memory update (step 6): row-major doubles. */
+typedef struct {
+    int32_t idx;     /* particle index in [0, N) of its context */
+    int32_t pad;
+    double t0;       /* time the data below refer to */
+    double m;
+    double x[3], v[3], a[3], jerk[3];
+} ht_row;
+
+int ht_batch_workspace_bytes(int32_t max_clusters, int64_t max_items, int64_t max_active, int64_t max_rows,
+                             size_t *bytes);
+/* stream must be the hipStream_t the contexts share; d_workspace as for ht_create. */
+int ht_batch_create(ht_batch **out, int32_t device, void *stream, int32_t max_clusters, int64_t max_items,
+                    int64_t max_active, int64_t max_rows, void *d_workspace, size_t workspace_bytes);
+int ht_batch_destroy(ht_batch *b);
+
+/* Step 6 for several contexts: rows[k][0..n_rows[k]-1] (host) go to ctxs[k]
+ * (indices distinct within a context).  One copy and one kernel for all;
+ * asynchronous; the contexts must be predicted again afterwards. */
+int ht_batch_update_async(ht_batch *b, int32_t n_ctx, ht_ctx *const *ctxs, const int32_t *n_rows,
+                          const ht_row *const *rows);
+
+/* Steps 4a-5 for several predicted contexts in one launch: as ht_force_async
+ * per context, active ids from host arrays, results to device arrays. */
+int ht_batch_force_async(ht_batch *b, int32_t n_ctx, ht_ctx *const *ctxs, const int32_t *n_active,
+                         const int32_t *const *active_ids, double *const *d_acc, double *const *d_jerk,
+                         double *const *d_pot);
+
+int ht_batch_sync(ht_batch *b);
+int ht_batch_set_timing(ht_batch *b, int32_t enable);
+int ht_batch_kernel_timing(ht_batch *b, double *force_ms, int64_t *launches, int64_t *pairs);
+int ht_batch_last_stats(const ht_batch *b, int64_t *pairs, int32_t *work_items);
+
 /* Block until the context's queued work has finished. */
 int ht_sync(ht_ctx *ctx);
 

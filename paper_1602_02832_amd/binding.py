@@ -19,8 +19,8 @@ import numpy as np
 
 from . import build as _build
 
-__all__ = ["HTError", "Context", "HostTree", "force_batch_async", "hilbert_keys", "next_block",
-           "correct", "initial_steps", "device_lib", "host_lib"]
+__all__ = ["HTError", "Context", "Batch", "HT_ROW", "make_rows", "HostTree", "force_batch_async", "hilbert_keys",
+           "next_block", "correct", "initial_steps", "device_lib", "host_lib"]
 
 HT_PREC = {"fp64": 0, "mixed": 1}
 HT_PREDICT = {"fused": 0, "eager": 1}
@@ -44,6 +44,28 @@ class HtConfig(ctypes.Structure):
                 ("n_max", ctypes.c_int32), ("node_max", ctypes.c_int32), ("group_max", ctypes.c_int32),
                 ("list_max", ctypes.c_int64), ("active_max", ctypes.c_int32), ("eps2", ctypes.c_double),
                 ("stream", ctypes.c_void_p)]
+
+
+# ht_row (include/htree.h): one corrected particle for a j-memory update
+HT_ROW = np.dtype([("idx", np.int32), ("pad", np.int32), ("t0", np.float64), ("m", np.float64),
+                   ("x", np.float64, 3), ("v", np.float64, 3), ("a", np.float64, 3), ("jerk", np.float64, 3)],
+                  align=True)
+assert HT_ROW.itemsize == 120
+
+
+def make_rows(idx, t0, m, x, v, a, jerk):
+    """Pack corrected particles into ht_row records (host)."""
+    idx = np.asarray(idx)
+    r = np.empty(idx.shape[0], HT_ROW)
+    r["idx"] = idx
+    r["pad"] = 0
+    r["t0"] = t0
+    r["m"] = m
+    r["x"] = x
+    r["v"] = v
+    r["a"] = a
+    r["jerk"] = jerk
+    return r
 
 
 _dev = None
@@ -84,6 +106,16 @@ def device_lib():
             "ht_set_tuning": [_vp, d, d],
             "ht_kernel_timing": [_vp, _c_dp, _c_i64p, _c_i64p],
             "ht_last_error": [],
+            "ht_batch_workspace_bytes": [i, i64, i64, i64, ctypes.POINTER(ctypes.c_size_t)],
+            "ht_batch_create": [ctypes.POINTER(_vp), i, _vp, i, i64, i64, i64, _vp, ctypes.c_size_t],
+            "ht_batch_destroy": [_vp],
+            "ht_batch_update_async": [_vp, i, ctypes.POINTER(_vp), _c_i32p, ctypes.POINTER(_vp)],
+            "ht_batch_force_async": [_vp, i, ctypes.POINTER(_vp), _c_i32p, ctypes.POINTER(_c_i32p),
+                                     ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp)],
+            "ht_batch_sync": [_vp],
+            "ht_batch_set_timing": [_vp, i],
+            "ht_batch_kernel_timing": [_vp, _c_dp, _c_i64p, _c_i64p],
+            "ht_batch_last_stats": [_vp, _c_i64p, _c_i32p],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -297,6 +329,80 @@ def force_batch_async(ctxs, actives, d_accs, d_jerks, d_pots):
     Q = (_vp * n)(*[_dptr(t) for t in d_pots])
     _check(device_lib().ht_force_batch_async(n, H, N, P, A, J, Q))
     return acts  # keep host arrays alive until the caller syncs
+
+
+class Batch:
+    """Batched engine object (ht_batch): one update copy + one scatter and one
+    plan copy + one force launch per engine step for all member contexts."""
+
+    def __init__(self, *, stream, max_clusters, max_items, max_active, max_rows, device=0, torch_workspace=True):
+        L = device_lib()
+        nbytes = ctypes.c_size_t()
+        _check(L.ht_batch_workspace_bytes(int(max_clusters), int(max_items), int(max_active), int(max_rows),
+                                          ctypes.byref(nbytes)))
+        self.workspace_bytes = nbytes.value
+        self._ws = None
+        ws_ptr = None
+        if torch_workspace:
+            import torch
+            self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=f"cuda:{device}")
+            ws_ptr = self._ws.data_ptr()
+        h = _vp()
+        _check(L.ht_batch_create(ctypes.byref(h), int(device), int(stream), int(max_clusters), int(max_items),
+                                 int(max_active), int(max_rows), ws_ptr, self.workspace_bytes))
+        self._h = h
+        self._keep = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            device_lib().ht_batch_destroy(self._h)
+            self._h = None
+            self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def update_async(self, ctxs, rows_list):
+        n = len(ctxs)
+        rows_list = [np.ascontiguousarray(r, dtype=HT_ROW) for r in rows_list]
+        H = (_vp * n)(*[c.handle for c in ctxs])
+        N = (ctypes.c_int32 * n)(*[r.shape[0] for r in rows_list])
+        R = (_vp * n)(*[r.ctypes.data if r.shape[0] else None for r in rows_list])
+        _check(device_lib().ht_batch_update_async(self._h, n, H, N, R))
+        self._keep = rows_list   # pinned copy is taken before return; kept for clarity
+
+    def force_async(self, ctxs, actives, d_accs, d_jerks, d_pots):
+        n = len(ctxs)
+        acts = [_arr(a, np.int32) for a in actives]
+        H = (_vp * n)(*[c.handle for c in ctxs])
+        N = (ctypes.c_int32 * n)(*[a.shape[0] for a in acts])
+        P = (_c_i32p * n)(*[_ptr(a, ctypes.c_int32) for a in acts])
+        A = (_vp * n)(*[_dptr(t) for t in d_accs])
+        J = (_vp * n)(*[_dptr(t) for t in d_jerks])
+        Q = (_vp * n)(*[_dptr(t) for t in d_pots])
+        _check(device_lib().ht_batch_force_async(self._h, n, H, N, P, A, J, Q))
+
+    def sync(self):
+        _check(device_lib().ht_batch_sync(self._h))
+
+    def set_timing(self, enable=True):
+        _check(device_lib().ht_batch_set_timing(self._h, 1 if enable else 0))
+
+    def kernel_timing(self):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        p = ctypes.c_int64()
+        _check(device_lib().ht_batch_kernel_timing(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(p)))
+        return ms.value, n.value, p.value
+
+    def last_stats(self):
+        p = ctypes.c_int64()
+        w = ctypes.c_int32()
+        _check(device_lib().ht_batch_last_stats(self._h, ctypes.byref(p), ctypes.byref(w)))
+        return p.value, w.value
 
 
 # ----------------------------------------------------------------------------------------------- host

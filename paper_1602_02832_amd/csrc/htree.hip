@@ -539,6 +539,49 @@ __global__ __launch_bounds__(kWG) void scatter_kernel(Desc dst, int n, const int
     }
 }
 
+// Batched j-memory update: rows of several clusters in one launch.
+struct UpdEntry {
+    void* rec;          // the cluster's records
+    int64_t first_row;  // its first row in the launch
+};
+
+__device__ __forceinline__ int find_upd(const UpdEntry* tab, int n_tab, int64_t r) {
+    int lo = 0, hi = n_tab;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tab[mid].first_row <= r) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+template <class P>
+__global__ __launch_bounds__(kWG) void scatter_rows_kernel(const UpdEntry* __restrict__ tab, int n_tab,
+                                                           const ht_row* __restrict__ rows, int64_t total) {
+    using S = typename P::Stored;
+    for (int64_t r = blockIdx.x * static_cast<int64_t>(kWG) + threadIdx.x; r < total;
+         r += static_cast<int64_t>(gridDim.x) * kWG) {
+        const int k = find_upd(tab, n_tab, r);
+        typename P::Rec* rec = static_cast<typename P::Rec*>(tab[k].rec);
+        const ht_row& w = rows[r];
+        typename P::Rec o{};
+        o.x = w.x[0];
+        o.y = w.x[1];
+        o.z = w.x[2];
+        o.t0 = w.t0;
+        o.vx = w.v[0];
+        o.vy = w.v[1];
+        o.vz = w.v[2];
+        o.m = static_cast<S>(w.m);
+        o.ax = static_cast<S>(w.a[0]);
+        o.ay = static_cast<S>(w.a[1]);
+        o.az = static_cast<S>(w.a[2]);
+        o.jx = static_cast<S>(w.jerk[0]);
+        o.jy = static_cast<S>(w.jerk[1]);
+        o.jz = static_cast<S>(w.jerk[2]);
+        rec[w.idx] = o;
+    }
+}
+
 // ------------------------------------------------------------------------------------------------
 // host side
 size_t align_up(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
@@ -594,6 +637,27 @@ bool layout_of(const ht_config& c, Layout& L) {
     return true;
 }
 
+// Optional timing of force-kernel launches: HIP events around each launch.
+struct Timing {
+    bool enabled = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    int64_t pairs = 0;
+};
+
+// A ring of pinned host slots, each mirroring a device region byte for byte,
+// so the host can pack several calls ahead of the device.  A slot is reused
+// once the copy that read it has completed.
+struct PinnedRing {
+    static constexpr int kSlots = 4;
+    char* base = nullptr;
+    size_t slot_bytes = 0;
+    hipEvent_t ev[kSlots] = {};
+    bool pending[kSlots] = {};
+    int slot = 0;
+    char* host() const { return base + static_cast<size_t>(slot) * slot_bytes; }
+};
+
 }  // namespace
 
 struct ht_ctx {
@@ -622,11 +686,10 @@ struct ht_ctx {
     // last call statistics
     int64_t last_pairs = 0;
     int32_t last_items = 0;
-    // optional timing of force-kernel launches (events around each launch)
-    bool timing = false;
-    std::vector<hipEvent_t> ev_pool;
-    size_t ev_used = 0;
-    int64_t timed_pairs = 0;
+    Timing tm;
+    // per-call scratch: marks for repeated update indices (generation-stamped)
+    std::vector<uint32_t> mark;
+    uint32_t mark_gen = 0;
     // work-plan tuning (see plan())
     double gather_cost = kGatherCostDefault;
     double target_items = kTargetItemsDefault;
@@ -668,6 +731,25 @@ struct ht_ctx {
     void slots_all_free() {
         for (int k = 0; k < kPlanSlots; ++k) slot_pending[k] = false;
     }
+};
+
+// Batched engine object: its own plan and update regions, big enough for all
+// clusters of one engine step, so a step costs one update copy + one scatter
+// and one plan copy + one force launch (+ one reduce) for every cluster.
+struct ht_batch {
+    int32_t device = 0;
+    hipStream_t stream = nullptr;
+    int32_t max_clusters = 0;
+    int64_t max_items = 0, max_active = 0, max_rows = 0;
+    size_t plan_bytes = 0, rows_bytes = 0;
+    char* ws = nullptr;
+    bool own_ws = false;
+    PinnedRing plan_ring, rows_ring;
+    Timing tm;
+    int64_t last_pairs = 0;
+    int32_t last_items = 0;
+    std::vector<Entry> tab;
+    std::vector<UpdEntry> utab;
 };
 
 namespace {
@@ -785,10 +867,8 @@ int validate_active(const ht_ctx* c, int32_t n_active, const int32_t* ids) {
 // staging from byte offset `at` on (the device plan region mirrors that
 // staging byte for byte); point the launch entry at the device copies.
 // Returns the end of the packed bytes.
-size_t pack_plan(ht_ctx* c, size_t at, int32_t n_active, const int32_t* ids, double* acc, double* jerk, double* pot,
-                 Entry& e) {
-    char* hs = c->plan_host();
-    char* dv = c->ws + c->L.off_plan;
+size_t pack_plan_into(ht_ctx* c, char* hs, char* dv, size_t at, int32_t n_active, const int32_t* ids, double* acc,
+                      double* jerk, double* pot, Entry& e) {
     const size_t o_items = align_up(at);
     const size_t b_items = c->items.size() * sizeof(Item);
     const size_t o_rt = align_up(o_items + b_items);
@@ -807,6 +887,11 @@ size_t pack_plan(ht_ctx* c, size_t at, int32_t n_active, const int32_t* ids, dou
     return o_act + static_cast<size_t>(n_active) * 4;
 }
 
+size_t pack_plan(ht_ctx* c, size_t at, int32_t n_active, const int32_t* ids, double* acc, double* jerk, double* pot,
+                 Entry& e) {
+    return pack_plan_into(c, c->plan_host(), c->ws + c->L.off_plan, at, n_active, ids, acc, jerk, pot, e);
+}
+
 // One host-to-device copy of the packed prefix [0, end) of the plan.
 int copy_plan(ht_ctx* c, size_t end) {
     HT_HIP(hipMemcpyAsync(c->ws + c->L.off_plan, c->plan_host(), end, hipMemcpyHostToDevice, c->stream));
@@ -815,36 +900,51 @@ int copy_plan(ht_ctx* c, size_t end) {
 }
 
 template <class P>
-int launch_force(ht_ctx* c0, const Entry* d_tab, int n_tab, int64_t n_items, int64_t n_rtiles, bool direct,
-                 int64_t pairs) {
-    const bool eager = c0->cfg.predict_mode == HT_PREDICT_EAGER;
+int launch_force(hipStream_t stream, bool eager, Timing& tm, const Entry* d_tab, int n_tab, int64_t n_items,
+                 int64_t n_rtiles, bool direct, int64_t pairs) {
     const int grid = grid_for(n_items);
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
-    if (c0->timing) {
-        while (c0->ev_pool.size() < c0->ev_used + 2) {
+    if (tm.enabled) {
+        while (tm.pool.size() < tm.used + 2) {
             hipEvent_t e;
             HT_HIP(hipEventCreate(&e));
-            c0->ev_pool.push_back(e);
+            tm.pool.push_back(e);
         }
-        ev_a = c0->ev_pool[c0->ev_used];
-        ev_b = c0->ev_pool[c0->ev_used + 1];
-        c0->ev_used += 2;
-        HT_HIP(hipEventRecord(ev_a, c0->stream));
-        c0->timed_pairs += pairs;
+        ev_a = tm.pool[tm.used];
+        ev_b = tm.pool[tm.used + 1];
+        tm.used += 2;
+        HT_HIP(hipEventRecord(ev_a, stream));
+        tm.pairs += pairs;
     }
     if (direct) {
-        if (eager) force_kernel<P, true, true><<<grid, kWG, 0, c0->stream>>>(d_tab, n_tab, n_items);
-        else force_kernel<P, false, true><<<grid, kWG, 0, c0->stream>>>(d_tab, n_tab, n_items);
+        if (eager) force_kernel<P, true, true><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items);
+        else force_kernel<P, false, true><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items);
     } else {
-        if (eager) force_kernel<P, true, false><<<grid, kWG, 0, c0->stream>>>(d_tab, n_tab, n_items);
-        else force_kernel<P, false, false><<<grid, kWG, 0, c0->stream>>>(d_tab, n_tab, n_items);
+        if (eager) force_kernel<P, true, false><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items);
+        else force_kernel<P, false, false><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items);
     }
     HT_HIP(hipGetLastError());
-    if (ev_b) HT_HIP(hipEventRecord(ev_b, c0->stream));
+    if (ev_b) HT_HIP(hipEventRecord(ev_b, stream));
     if (n_rtiles > 0) {
-        reduce_kernel<<<grid_for(n_rtiles), kWG, 0, c0->stream>>>(d_tab, n_tab, n_rtiles);
+        reduce_kernel<<<grid_for(n_rtiles), kWG, 0, stream>>>(d_tab, n_tab, n_rtiles);
         HT_HIP(hipGetLastError());
     }
+    return HT_OK;
+}
+
+int read_timing(hipStream_t stream, Timing& tm, double* force_ms, int64_t* launches, int64_t* pairs) {
+    HT_HIP(hipStreamSynchronize(stream));
+    double total = 0.0;
+    for (size_t k = 0; k + 1 < tm.used; k += 2) {
+        float ms = 0.0f;
+        HT_HIP(hipEventElapsedTime(&ms, tm.pool[k], tm.pool[k + 1]));
+        total += ms;
+    }
+    *force_ms = total;
+    *launches = static_cast<int64_t>(tm.used / 2);
+    *pairs = tm.pairs;
+    tm.used = 0;
+    tm.pairs = 0;
     return HT_OK;
 }
 
@@ -875,8 +975,10 @@ int force_common(ht_ctx* c, int32_t n_active, const int32_t* ids, double* d_acc,
     if (rc) return rc;
     const Entry* d_tab = reinterpret_cast<const Entry*>(c->ws + c->L.off_plan);
     const int64_t ni = static_cast<int64_t>(c->items.size()), nr = static_cast<int64_t>(c->rtiles.size());
-    if (c->cfg.precision == HT_PREC_FP64) return launch_force<PrecFp64>(c, d_tab, 1, ni, nr, direct, c->last_pairs);
-    return launch_force<PrecMixed>(c, d_tab, 1, ni, nr, direct, c->last_pairs);
+    const bool eager = c->cfg.predict_mode == HT_PREDICT_EAGER;
+    if (c->cfg.precision == HT_PREC_FP64)
+        return launch_force<PrecFp64>(c->stream, eager, c->tm, d_tab, 1, ni, nr, direct, c->last_pairs);
+    return launch_force<PrecMixed>(c->stream, eager, c->tm, d_tab, 1, ni, nr, direct, c->last_pairs);
 }
 
 int force_to_host(ht_ctx* c, int32_t n_active, const int32_t* ids, double* acc, double* jerk, double* pot,
@@ -1019,7 +1121,7 @@ int ht_destroy(ht_ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (hipEvent_t e : c->slot_free)
         if (e) (void)hipEventDestroy(e);
-    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->tm.pool) (void)hipEventDestroy(e);
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
     if (c->own_ws && c->ws) (void)hipFree(c->ws);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -1271,10 +1373,309 @@ int ht_force_batch_async(int32_t n_ctx, ht_ctx* const* ctxs, const int32_t* n_ac
     if (rc) return rc;
     const Entry* d_tab = reinterpret_cast<const Entry*>(c0->ws + c0->L.off_plan);
     const int nt = static_cast<int>(tab.size());
+    const bool eager = c0->cfg.predict_mode == HT_PREDICT_EAGER;
     if (c0->cfg.precision == HT_PREC_FP64)
-        return launch_force<PrecFp64>(c0, d_tab, nt, n_items, n_rtiles, false, pairs);
-    return launch_force<PrecMixed>(c0, d_tab, nt, n_items, n_rtiles, false, pairs);
+        return launch_force<PrecFp64>(c0->stream, eager, c0->tm, d_tab, nt, n_items, n_rtiles, false, pairs);
+    return launch_force<PrecMixed>(c0->stream, eager, c0->tm, d_tab, nt, n_items, n_rtiles, false, pairs);
 }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------------------
+// batched engine object
+namespace {
+
+size_t batch_plan_bytes(int32_t max_clusters, int64_t max_items, int64_t max_active) {
+    return align_up(static_cast<size_t>(max_clusters) * sizeof(Entry)) +
+           align_up(static_cast<size_t>(max_items) * sizeof(Item)) +
+           align_up(static_cast<size_t>(max_items) * sizeof(RTile)) + align_up(static_cast<size_t>(max_active) * 4) +
+           static_cast<size_t>(max_clusters) * 3 * 256;
+}
+
+size_t batch_rows_bytes(int32_t max_clusters, int64_t max_rows) {
+    return align_up(static_cast<size_t>(max_clusters) * sizeof(UpdEntry)) + static_cast<size_t>(max_rows) * sizeof(ht_row);
+}
+
+bool batch_args_ok(int32_t max_clusters, int64_t max_items, int64_t max_active, int64_t max_rows) {
+    return max_clusters >= 1 && max_clusters <= kMaxBatch && max_items >= 1 && max_active >= 1 && max_rows >= 1 &&
+           max_items < (int64_t(1) << 31) && max_active < (int64_t(1) << 31) && max_rows < (int64_t(1) << 31);
+}
+
+int ring_init(PinnedRing& r, size_t slot_bytes) {
+    r.slot_bytes = align_up(slot_bytes);
+    if (hipHostMalloc(reinterpret_cast<void**>(&r.base), PinnedRing::kSlots * r.slot_bytes, hipHostMallocDefault) !=
+        hipSuccess)
+        return fail(HT_ENOMEM, "hipHostMalloc of %zu bytes failed", PinnedRing::kSlots * r.slot_bytes);
+    for (int k = 0; k < PinnedRing::kSlots; ++k)
+        if (hipEventCreateWithFlags(&r.ev[k], hipEventDisableTiming) != hipSuccess)
+            return fail(HT_EHIP, "hipEventCreate failed");
+    return HT_OK;
+}
+
+void ring_free(PinnedRing& r) {
+    for (hipEvent_t e : r.ev)
+        if (e) (void)hipEventDestroy(e);
+    if (r.base) (void)hipHostFree(r.base);
+    r.base = nullptr;
+}
+
+int ring_acquire(PinnedRing& r) {
+    if (r.pending[r.slot]) {
+        HT_HIP(hipEventSynchronize(r.ev[r.slot]));
+        r.pending[r.slot] = false;
+    }
+    return HT_OK;
+}
+
+int ring_release(PinnedRing& r, hipStream_t s) {
+    HT_HIP(hipEventRecord(r.ev[r.slot], s));
+    r.pending[r.slot] = true;
+    r.slot = (r.slot + 1) % PinnedRing::kSlots;
+    return HT_OK;
+}
+
+void ring_all_free(PinnedRing& r) {
+    for (bool& p : r.pending) p = false;
+}
+
+int check_member(const ht_batch* b, const ht_ctx* c, int32_t k, ht_ctx* const* ctxs) {
+    if (!c) return fail(HT_EINVAL, "ctx %d is NULL", k);
+    if (c->cfg.device != b->device) return fail(HT_EINVAL, "ctx %d is on another device", k);
+    if (c->stream != b->stream) return fail(HT_EINVAL, "ctx %d does not share the batch's stream", k);
+    if (c->cfg.precision != ctxs[0]->cfg.precision || c->cfg.predict_mode != ctxs[0]->cfg.predict_mode)
+        return fail(HT_EINVAL, "ctx %d differs in precision or predict mode", k);
+    for (int32_t q = 0; q < k; ++q)
+        if (ctxs[q] == c) return fail(HT_EINVAL, "ctx %d appears twice", k);
+    return HT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ht_batch_workspace_bytes(int32_t max_clusters, int64_t max_items, int64_t max_active, int64_t max_rows,
+                             size_t* bytes) {
+    if (!bytes || !batch_args_ok(max_clusters, max_items, max_active, max_rows))
+        return fail(HT_EINVAL, "invalid batch capacities");
+    *bytes = align_up(batch_plan_bytes(max_clusters, max_items, max_active)) +
+             align_up(batch_rows_bytes(max_clusters, max_rows));
+    return HT_OK;
+}
+
+int ht_batch_create(ht_batch** out, int32_t device, void* stream, int32_t max_clusters, int64_t max_items,
+                    int64_t max_active, int64_t max_rows, void* d_workspace, size_t workspace_bytes) {
+    if (!out) return fail(HT_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (!stream) return fail(HT_EINVAL, "a batch needs the stream its contexts share");
+    size_t need = 0;
+    int rc = ht_batch_workspace_bytes(max_clusters, max_items, max_active, max_rows, &need);
+    if (rc) return rc;
+    if (d_workspace && (workspace_bytes < need || (reinterpret_cast<uintptr_t>(d_workspace) & 255)))
+        return fail(HT_EINVAL, "workspace too small or not 256-byte aligned");
+    HT_HIP(hipSetDevice(device));
+    ht_batch* b = new ht_batch();
+    b->device = device;
+    b->stream = static_cast<hipStream_t>(stream);
+    b->max_clusters = max_clusters;
+    b->max_items = max_items;
+    b->max_active = max_active;
+    b->max_rows = max_rows;
+    b->plan_bytes = align_up(batch_plan_bytes(max_clusters, max_items, max_active));
+    b->rows_bytes = align_up(batch_rows_bytes(max_clusters, max_rows));
+    auto cleanup = [&](int code) {
+        ht_batch_destroy(b);
+        return code;
+    };
+    if (d_workspace) {
+        b->ws = static_cast<char*>(d_workspace);
+    } else {
+        if (hipMalloc(&b->ws, need) != hipSuccess) return cleanup(fail(HT_ENOMEM, "hipMalloc of %zu bytes failed", need));
+        b->own_ws = true;
+    }
+    rc = ring_init(b->plan_ring, b->plan_bytes);
+    if (rc) return cleanup(rc);
+    rc = ring_init(b->rows_ring, b->rows_bytes);
+    if (rc) return cleanup(rc);
+    b->tab.reserve(max_clusters);
+    b->utab.reserve(max_clusters);
+    *out = b;
+    return HT_OK;
+}
+
+int ht_batch_destroy(ht_batch* b) {
+    if (!b) return HT_OK;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    ring_free(b->plan_ring);
+    ring_free(b->rows_ring);
+    for (hipEvent_t e : b->tm.pool) (void)hipEventDestroy(e);
+    if (b->own_ws && b->ws) (void)hipFree(b->ws);
+    delete b;
+    return HT_OK;
+}
+
+int ht_batch_update_async(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs, const int32_t* n_rows,
+                          const ht_row* const* rows) {
+    if (!b) return fail(HT_EINVAL, "batch is NULL");
+    if (n_ctx < 0 || n_ctx > b->max_clusters) return fail(HT_EINVAL, "n_ctx = %d outside [0, %d]", n_ctx, b->max_clusters);
+    if (n_ctx == 0) return HT_OK;
+    if (!ctxs || !n_rows || !rows) return fail(HT_EINVAL, "NULL argument");
+    int64_t total = 0;
+    for (int32_t k = 0; k < n_ctx; ++k) {
+        ht_ctx* c = ctxs[k];
+        int rc = check_member(b, c, k, ctxs);
+        if (rc) return rc;
+        if (!c->have_particles) return fail(HT_ESTATE, "ctx %d: particles not set", k);
+        if (n_rows[k] < 0 || (n_rows[k] > 0 && !rows[k])) return fail(HT_EINVAL, "ctx %d: bad rows", k);
+        if (c->mark.size() != static_cast<size_t>(c->n)) c->mark.assign(static_cast<size_t>(c->n), 0u);
+        if (++c->mark_gen == 0) {
+            std::fill(c->mark.begin(), c->mark.end(), 0u);
+            c->mark_gen = 1;
+        }
+        for (int32_t r = 0; r < n_rows[k]; ++r) {
+            const int32_t j = rows[k][r].idx;
+            if (j < 0 || j >= c->n) return fail(HT_ERANGE, "ctx %d: row index %d outside [0, %d)", k, j, c->n);
+            if (c->mark[j] == c->mark_gen) return fail(HT_EINVAL, "ctx %d: particle %d updated twice", k, j);
+            c->mark[j] = c->mark_gen;
+        }
+        total += n_rows[k];
+    }
+    if (total > b->max_rows) return fail(HT_ERANGE, "%lld update rows over capacity %lld", (long long)total,
+                                         (long long)b->max_rows);
+    for (int32_t k = 0; k < n_ctx; ++k) ctxs[k]->predicted = false;
+    if (total == 0) return HT_OK;
+    int rc = ring_acquire(b->rows_ring);
+    if (rc) return rc;
+    char* hs = b->rows_ring.host();
+    char* dv = b->ws + b->plan_bytes;
+    b->utab.clear();
+    int64_t first = 0;
+    const size_t rows_at = align_up(static_cast<size_t>(n_ctx) * sizeof(UpdEntry));
+    for (int32_t k = 0; k < n_ctx; ++k) {
+        if (n_rows[k] == 0) continue;
+        b->utab.push_back(UpdEntry{ctxs[k]->ws + ctxs[k]->L.off_rec, first});
+        std::memcpy(hs + rows_at + static_cast<size_t>(first) * sizeof(ht_row), rows[k],
+                    static_cast<size_t>(n_rows[k]) * sizeof(ht_row));
+        first += n_rows[k];
+    }
+    std::memcpy(hs, b->utab.data(), b->utab.size() * sizeof(UpdEntry));
+    const size_t end = rows_at + static_cast<size_t>(total) * sizeof(ht_row);
+    HT_HIP(hipMemcpyAsync(dv, hs, end, hipMemcpyHostToDevice, b->stream));
+    rc = ring_release(b->rows_ring, b->stream);
+    if (rc) return rc;
+    const int grid = static_cast<int>(std::min<int64_t>((total + kWG - 1) / kWG, 65536));
+    const UpdEntry* d_tab = reinterpret_cast<const UpdEntry*>(dv);
+    const ht_row* d_rows = reinterpret_cast<const ht_row*>(dv + rows_at);
+    const int nt = static_cast<int>(b->utab.size());
+    if (ctxs[0]->cfg.precision == HT_PREC_FP64)
+        scatter_rows_kernel<PrecFp64><<<grid, kWG, 0, b->stream>>>(d_tab, nt, d_rows, total);
+    else
+        scatter_rows_kernel<PrecMixed><<<grid, kWG, 0, b->stream>>>(d_tab, nt, d_rows, total);
+    HT_HIP(hipGetLastError());
+    return HT_OK;
+}
+
+int ht_batch_force_async(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs, const int32_t* n_active,
+                         const int32_t* const* ids, double* const* d_acc, double* const* d_jerk, double* const* d_pot) {
+    if (!b) return fail(HT_EINVAL, "batch is NULL");
+    if (n_ctx < 0 || n_ctx > b->max_clusters) return fail(HT_EINVAL, "n_ctx = %d outside [0, %d]", n_ctx, b->max_clusters);
+    b->last_pairs = 0;
+    b->last_items = 0;
+    if (n_ctx == 0) return HT_OK;
+    if (!ctxs || !n_active || !ids || !d_acc || !d_jerk || !d_pot) return fail(HT_EINVAL, "NULL argument");
+    int64_t act_total = 0;
+    for (int32_t k = 0; k < n_ctx; ++k) {
+        ht_ctx* c = ctxs[k];
+        int rc = check_member(b, c, k, ctxs);
+        if (rc) return rc;
+        if (!c->have_particles || !c->have_lists) return fail(HT_ESTATE, "ctx %d: lists not set", k);
+        if (!c->predicted) return fail(HT_ESTATE, "ctx %d: not predicted", k);
+        rc = validate_active(c, n_active[k], ids[k]);
+        if (rc) return rc;
+        if (n_active[k] > 0 && (!d_acc[k] || !d_jerk[k] || !d_pot[k])) return fail(HT_EINVAL, "ctx %d: NULL output", k);
+        act_total += n_active[k];
+    }
+    if (act_total > b->max_active) return fail(HT_ERANGE, "%lld active particles over the batch capacity %lld",
+                                               (long long)act_total, (long long)b->max_active);
+    int rc = ring_acquire(b->plan_ring);
+    if (rc) return rc;
+    char* hs = b->plan_ring.host();
+    char* dv = b->ws;
+    b->tab.clear();
+    int64_t n_items = 0, n_rtiles = 0, pairs = 0;
+    size_t at = static_cast<size_t>(n_ctx) * sizeof(Entry);
+    for (int32_t k = 0; k < n_ctx; ++k) {
+        ht_ctx* c = ctxs[k];
+        if (n_active[k] == 0) {
+            c->last_pairs = 0;
+            c->last_items = 0;
+            continue;
+        }
+        rc = plan(c, n_active[k], ids[k], false);
+        if (rc) return rc;
+        if (n_items + static_cast<int64_t>(c->items.size()) > b->max_items ||
+            n_rtiles + static_cast<int64_t>(c->rtiles.size()) > b->max_items)
+            return fail(HT_ERANGE, "work items over the batch capacity %lld", (long long)b->max_items);
+        Entry e{};
+        at = pack_plan_into(c, hs, dv, at, n_active[k], ids[k], d_acc[k], d_jerk[k], d_pot[k], e);
+        e.first_item = n_items;
+        e.first_rtile = n_rtiles;
+        n_items += static_cast<int64_t>(c->items.size());
+        n_rtiles += static_cast<int64_t>(c->rtiles.size());
+        pairs += c->last_pairs;
+        b->tab.push_back(e);
+    }
+    if (b->tab.empty()) return HT_OK;
+    if (at > b->plan_bytes) return fail(HT_ERANGE, "batch plan over its capacity");
+    std::memcpy(hs, b->tab.data(), b->tab.size() * sizeof(Entry));
+    HT_HIP(hipMemcpyAsync(dv, hs, at, hipMemcpyHostToDevice, b->stream));
+    rc = ring_release(b->plan_ring, b->stream);
+    if (rc) return rc;
+    b->last_pairs = pairs;
+    b->last_items = static_cast<int32_t>(n_items);
+    const Entry* d_tab = reinterpret_cast<const Entry*>(dv);
+    const int nt = static_cast<int>(b->tab.size());
+    const bool eager = ctxs[0]->cfg.predict_mode == HT_PREDICT_EAGER;
+    if (ctxs[0]->cfg.precision == HT_PREC_FP64)
+        return launch_force<PrecFp64>(b->stream, eager, b->tm, d_tab, nt, n_items, n_rtiles, false, pairs);
+    return launch_force<PrecMixed>(b->stream, eager, b->tm, d_tab, nt, n_items, n_rtiles, false, pairs);
+}
+
+int ht_batch_sync(ht_batch* b) {
+    if (!b) return fail(HT_EINVAL, "batch is NULL");
+    HT_HIP(hipStreamSynchronize(b->stream));
+    ring_all_free(b->plan_ring);
+    ring_all_free(b->rows_ring);
+    return HT_OK;
+}
+
+int ht_batch_set_timing(ht_batch* b, int32_t enable) {
+    if (!b) return fail(HT_EINVAL, "batch is NULL");
+    b->tm.enabled = enable != 0;
+    b->tm.used = 0;
+    b->tm.pairs = 0;
+    return HT_OK;
+}
+
+int ht_batch_kernel_timing(ht_batch* b, double* force_ms, int64_t* launches, int64_t* pairs) {
+    if (!b || !force_ms || !launches || !pairs) return fail(HT_EINVAL, "NULL argument");
+    int rc = read_timing(b->stream, b->tm, force_ms, launches, pairs);
+    if (rc == HT_OK) {
+        ring_all_free(b->plan_ring);
+        ring_all_free(b->rows_ring);
+    }
+    return rc;
+}
+
+int ht_batch_last_stats(const ht_batch* b, int64_t* pairs, int32_t* work_items) {
+    if (!b) return fail(HT_EINVAL, "batch is NULL");
+    if (pairs) *pairs = b->last_pairs;
+    if (work_items) *work_items = b->last_items;
+    return HT_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
 
 int ht_sync(ht_ctx* c) {
     if (!c) return fail(HT_EINVAL, "ctx is NULL");
@@ -1285,28 +1686,17 @@ int ht_sync(ht_ctx* c) {
 
 int ht_set_timing(ht_ctx* c, int32_t enable) {
     if (!c) return fail(HT_EINVAL, "ctx is NULL");
-    c->timing = enable != 0;
-    c->ev_used = 0;
-    c->timed_pairs = 0;
+    c->tm.enabled = enable != 0;
+    c->tm.used = 0;
+    c->tm.pairs = 0;
     return HT_OK;
 }
 
 int ht_kernel_timing(ht_ctx* c, double* force_ms, int64_t* launches, int64_t* pairs) {
     if (!c || !force_ms || !launches || !pairs) return fail(HT_EINVAL, "NULL argument");
-    HT_HIP(hipStreamSynchronize(c->stream));
-    c->slots_all_free();
-    double total = 0.0;
-    for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
-        float ms = 0.0f;
-        HT_HIP(hipEventElapsedTime(&ms, c->ev_pool[k], c->ev_pool[k + 1]));
-        total += ms;
-    }
-    *force_ms = total;
-    *launches = static_cast<int64_t>(c->ev_used / 2);
-    *pairs = c->timed_pairs;
-    c->ev_used = 0;
-    c->timed_pairs = 0;
-    return HT_OK;
+    int rc = read_timing(c->stream, c->tm, force_ms, launches, pairs);
+    if (rc == HT_OK) c->slots_all_free();
+    return rc;
 }
 
 int ht_set_tuning(ht_ctx* c, double gather_cost, double target_items) {

@@ -107,6 +107,7 @@ class Simulation:
 
     # ------------------------------------------------------------------ steps 4a/5
     def _force(self, active):
+        """Steps 4a and 5 on this simulation's own context (host arrays)."""
         t_start = time.perf_counter()
         if self.mode == "tree":
             out = self.ctx.force(active)
@@ -120,14 +121,23 @@ class Simulation:
     def next_time(self):
         return float(np.min(self.t0 + self.dt))
 
-    def step(self):
-        """One block step; returns (t, active ids)."""
+    def begin_step(self):
+        """Steps 2 and 5 (prediction): pick the next block time and its active
+        particles and predict the context there.  Returns (t, active ids)."""
         t_start = time.perf_counter()
         tn, active = B.next_block(self.t0, self.dt, self._act_buf)
         active = active.copy()
         self.timers["host"] += time.perf_counter() - t_start
         self.ctx.predict(tn)
-        acc, jerk, pot = self._force(active)
+        self._pending = (tn, active)
+        return tn, active
+
+    def finish_step(self, acc, jerk, pot):
+        """Steps 6 and 7 for the forces of the step begun last: correct, pick
+        new steps, and either rebuild (at a tree time; everything re-sent) or
+        return the corrected particles as ht_row records for the j-memory."""
+        tn, active = self._pending
+        self._pending = None
         t_start = time.perf_counter()
         B.correct(active, tn, self.eta, self.dt_tree, self.t0, self.dt, self.x, self.v, self.a, self.j, acc, jerk)
         self.pot[active] = pot
@@ -139,10 +149,19 @@ class Simulation:
             if not np.all(self.t0 == tn):
                 raise AssertionError("particles not synchronised at a tree time")
             self._build_and_send()
-        else:
+            return None
+        return B.make_rows(active, self.t0[active], self.m[active], self.x[active], self.v[active], self.a[active],
+                           self.j[active])
+
+    def step(self):
+        """One block step; returns (t, active ids)."""
+        tn, active = self.begin_step()
+        acc, jerk, pot = self._force(active)
+        rows = self.finish_step(acc, jerk, pot)
+        if rows is not None:
             t_start = time.perf_counter()
-            self.ctx.set_j_particles(self.t0[active], self.m[active], self.x[active], self.v[active],
-                                     self.a[active], self.j[active], idx=active)
+            self.ctx.set_j_particles(rows["t0"], rows["m"], rows["x"], rows["v"], rows["a"], rows["jerk"],
+                                     idx=rows["idx"])
             self.timers["comm"] += time.perf_counter() - t_start
         return tn, active
 

@@ -1,0 +1,294 @@
+"""Batched and served tree/Hermite engines: many clusters, one launch per phase.
+
+Each cluster is an independent tree/Hermite simulation (``driver.Simulation``)
+with its own j-memory, lists and block times, on one shared stream.  An
+engine step advances every resident cluster by one of its own block steps:
+
+  1. one batched j-memory update with all clusters' corrected particles;
+  2. each cluster picks its next block time and active set (host) and is
+     predicted there;
+  3. one batched force launch over all clusters' work items (+ one split
+     reduction), results to one device buffer, one copy back;
+  4. each cluster corrects its particles on the host; clusters at a tree time
+     rebuild their tree and lists.
+
+Work plans are per cluster, so a cluster's forces are bit-identical alone and
+in any mix.  ``Server`` adds continuous batching: requests for whole cluster
+runs arrive over time and are admitted while device memory and batch slots
+allow; finished runs leave and free their slots.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import math
+import time
+
+import numpy as np
+
+from . import binding as B
+from . import driver
+from . import workloads as W
+
+
+@dataclasses.dataclass
+class RunSpec:
+    """A cluster run: a Plummer model of n particles, `steps` block steps."""
+
+    key: int
+    n: int
+    seed: int
+    steps: int
+    theta: float = 0.5
+    eta: float = 0.01
+    dt_tree: float = 1.0 / 256
+    n_crit: int = 256
+    eps: float | None = None        # default 4/n
+    mass_seed: int | None = None
+
+
+class Cluster:
+    """One cluster run: prepared on the host (initial conditions and the first
+    tree, which fix its device footprint), then activated (context, upload,
+    first forces) when it becomes resident."""
+
+    def __init__(self, spec: RunSpec, precision: str, stream, device: int = 0, list_headroom: float = 1.5):
+        self.spec, self.precision, self.stream, self.device = spec, precision, stream, device
+        self.list_headroom = list_headroom
+        x, v, m = W.plummer(spec.n, spec.seed)
+        if spec.mass_seed is not None:
+            m = W.salpeter_masses(spec.n, spec.mass_seed)
+        self._ics = (x, v, m)
+        z = np.zeros_like(x)
+        tr = B.HostTree(x, v, z, z, m, 1, spec.n_crit, spec.theta)
+        h = list_headroom
+        self.caps = (max(int(tr.n_node * h), 64), max(int(tr.n_group * h), 16), max(int(tr.n_entries * h), 1024))
+        self.reserve = workspace_bytes(spec.n, *self.caps, precision)
+        self.sim = None
+        self.pending_rows = None
+        self.steps_done = 0
+        self.active_sum = 0
+
+    def activate(self):
+        if self.sim is None:
+            spec = self.spec
+            eps = spec.eps if spec.eps is not None else 4.0 / spec.n
+            x, v, m = self._ics
+            self.sim = driver.Simulation(x, v, m, eps2=eps * eps, dt_tree=spec.dt_tree, eta=spec.eta,
+                                         theta=spec.theta, n_crit=spec.n_crit, precision=self.precision,
+                                         device=self.device, stream=self.stream, list_headroom=self.list_headroom)
+            self._ics = None
+
+    @property
+    def ctx(self):
+        return self.sim.ctx
+
+    @property
+    def done(self):
+        return self.steps_done >= self.spec.steps
+
+    def footprint(self):
+        """Device bytes this run holds (its context workspace)."""
+        return self.sim.ctx.workspace_bytes if self.sim is not None else self.reserve
+
+    def close(self):
+        if self.sim is not None:
+            self.sim.close()
+
+
+def workspace_bytes(n, node_max, group_max, list_max, precision="mixed"):
+    """ht_workspace_bytes of a context for one run."""
+    import ctypes
+
+    cfg = B.HtConfig(0, B.HT_PREC[precision], 0, int(n), int(node_max), int(group_max), int(list_max), int(n),
+                     1e-4, None)
+    out = ctypes.c_size_t()
+    if B.device_lib().ht_workspace_bytes(ctypes.byref(cfg), ctypes.byref(out)) != 0:
+        raise ValueError("bad context size")
+    return int(out.value)
+
+
+class Engine:
+    """Advances a set of clusters one block step each per engine step."""
+
+    def __init__(self, precision="mixed", device=0, max_clusters=256, max_active=1 << 21, max_items=1 << 20,
+                 max_rows=1 << 21):
+        import torch
+
+        self.torch = torch
+        self.precision, self.device = precision, device
+        self.stream = torch.cuda.Stream(device=device)
+        self.batch = B.Batch(stream=self.stream.cuda_stream, max_clusters=max_clusters, max_items=max_items,
+                             max_active=max_active, max_rows=max_rows, device=device)
+        self.max_clusters, self.max_active = max_clusters, max_active
+        self.clusters: list[Cluster] = []
+        dev = f"cuda:{device}"
+        # results of all clusters of a step, cluster k at rows offs[k]..; row slices stay contiguous
+        self.d_acc = torch.empty((max_active, 3), dtype=torch.float64, device=dev)
+        self.d_jerk = torch.empty((max_active, 3), dtype=torch.float64, device=dev)
+        self.d_pot = torch.empty(max_active, dtype=torch.float64, device=dev)
+        self.h_acc = torch.empty((max_active, 3), dtype=torch.float64, pin_memory=True)
+        self.h_jerk = torch.empty((max_active, 3), dtype=torch.float64, pin_memory=True)
+        self.h_pot = torch.empty(max_active, dtype=torch.float64, pin_memory=True)
+        self.step_ms = []
+        self.pairs = 0
+        self.equiv_pairs = 0
+        self.wall = 0.0
+
+    def new_cluster(self, spec: RunSpec) -> Cluster:
+        return Cluster(spec, self.precision, self.stream.cuda_stream, self.device)
+
+    def add(self, c: Cluster):
+        if len(self.clusters) >= self.max_clusters:
+            raise RuntimeError("engine is full")
+        c.activate()
+        self.clusters.append(c)
+
+    def remove(self, c: Cluster):
+        self.clusters.remove(c)
+
+    def step(self):
+        """One engine step over all resident clusters; returns the clusters
+        that finished their run in this step."""
+        t0 = time.perf_counter()
+        cl = [c for c in self.clusters if not c.done]
+        if not cl:
+            return []
+        ups = [c for c in cl if c.pending_rows is not None and c.pending_rows.shape[0]]
+        if ups:
+            self.batch.update_async([c.ctx for c in ups], [c.pending_rows for c in ups])
+        acts, offs = [], []
+        off = 0
+        for c in cl:
+            c.pending_rows = None
+            tn, act = c.sim.begin_step()
+            acts.append(act)
+            offs.append(off)
+            off += act.size
+        if off > self.max_active:
+            raise RuntimeError("active particles over the engine capacity")
+        self.batch.force_async([c.ctx for c in cl], acts, [self.d_acc[o:o + a.size] for o, a in zip(offs, acts)],
+                               [self.d_jerk[o:o + a.size] for o, a in zip(offs, acts)],
+                               [self.d_pot[o:o + a.size] for o, a in zip(offs, acts)])
+        pairs, _ = self.batch.last_stats()
+        with self.torch.cuda.stream(self.stream):
+            self.h_acc[:off].copy_(self.d_acc[:off], non_blocking=True)
+            self.h_jerk[:off].copy_(self.d_jerk[:off], non_blocking=True)
+            self.h_pot[:off].copy_(self.d_pot[:off], non_blocking=True)
+        self.stream.synchronize()
+        acc, jerk, pot = self.h_acc[:off].numpy(), self.h_jerk[:off].numpy(), self.h_pot[:off].numpy()
+        finished = []
+        for c, o, a in zip(cl, offs, acts):
+            sl = slice(o, o + a.size)
+            c.pending_rows = c.sim.finish_step(acc[sl], jerk[sl], pot[sl])
+            c.steps_done += 1
+            c.active_sum += a.size
+            if c.done:
+                finished.append(c)
+        dt = time.perf_counter() - t0
+        self.step_ms.append(1e3 * dt)
+        self.wall += dt
+        self.pairs += pairs
+        self.equiv_pairs += sum(a.size * (c.sim.n - 1) for c, a in zip(cl, acts))
+        return finished
+
+    def close(self):
+        for c in self.clusters:
+            c.close()
+        self.clusters = []
+        self.batch.close()
+
+
+@dataclasses.dataclass
+class Request:
+    spec: RunSpec
+    arrival: float                 # seconds after the start of the run
+    admitted: float = math.nan
+    finished: float = math.nan
+    cluster: Cluster | None = None
+    reserved: int = 0
+
+
+class Server:
+    """Continuous batching of cluster-run requests on one engine.
+
+    Requests wait in arrival order; the head of the queue is admitted as soon
+    as its device-memory reservation fits the budget and a batch slot is free
+    (no overtaking, so no request starves).  Every engine step advances all
+    resident runs; a run leaves the step it finishes and frees its memory.
+    """
+
+    def __init__(self, engine: Engine, hbm_budget: int, max_resident: int, keep_finished: bool = False):
+        self.engine, self.budget, self.max_resident = engine, int(hbm_budget), int(max_resident)
+        self.keep_finished = keep_finished
+        self.used = 0
+        self.resident: list[Request] = []
+        self.done: list[Request] = []
+        self.max_used = 0
+        self.max_waiting = 0
+
+    def _admit(self, req: Request, now: float):
+        self.engine.add(req.cluster)           # activates: context, upload, first forces
+        actual = req.cluster.footprint()       # equals the reservation: same tree, same headroom
+        self.used += actual - req.reserved
+        req.reserved = actual
+        req.admitted = now
+        self.resident.append(req)
+
+    def run(self, requests: list[Request], clock=time.perf_counter):
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        waiting: collections.deque[Request] = collections.deque()
+        t_start = clock()
+        while pending or waiting or self.resident:
+            now = clock() - t_start
+            while pending and pending[0].arrival <= now:
+                waiting.append(pending.popleft())
+            self.max_waiting = max(self.max_waiting, len(waiting))
+            while waiting and len(self.resident) < self.max_resident:
+                head = waiting[0]
+                if head.cluster is None:               # host preparation fixes the footprint
+                    head.cluster = self.engine.new_cluster(head.spec)
+                need = head.cluster.reserve
+                if self.used + need > self.budget and self.resident:
+                    break
+                waiting.popleft()
+                self.used += need
+                head.reserved = need
+                self._admit(head, clock() - t_start)
+            self.max_used = max(self.max_used, self.used)
+            if not self.resident:
+                if pending:
+                    delay = pending[0].arrival - (clock() - t_start)
+                    if delay > 0:
+                        time.sleep(min(delay, 0.05))
+                continue
+            finished = self.engine.step()
+            # a run whose lists outgrow their headroom gets a larger context at a rebuild
+            for r in self.resident:
+                grown = r.cluster.footprint()
+                if grown != r.reserved:
+                    self.used += grown - r.reserved
+                    r.reserved = grown
+            self.max_used = max(self.max_used, self.used)
+            now = clock() - t_start
+            for c in finished:
+                req = next(r for r in self.resident if r.cluster is c)
+                req.finished = now
+                self.resident.remove(req)
+                self.engine.remove(c)
+                self.used -= req.reserved
+                if not self.keep_finished:
+                    c.close()
+                    req.cluster = None
+                self.done.append(req)
+        return self.done
+
+
+def poisson_arrivals(count: int, rate: float, seed: int):
+    """Arrival times (seconds) of a Poisson process with the given rate."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.cumsum(rng.exponential(1.0 / rate, count))
+
+
+def percentile(values, q):
+    return float(np.percentile(np.asarray(values, dtype=np.float64), q)) if len(values) else math.nan

@@ -1,0 +1,119 @@
+"""Batched engine and continuous-batching server on the GPU.
+
+Work plans are made per cluster, so every cluster must come out bit-identical
+whether it runs alone or in a batch with others; the per-cluster forces are
+checked against the oracle in test_gpu_parity.py."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1602_02832_amd import binding as B
+from paper_1602_02832_amd import engine as E
+from paper_1602_02832_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("x", "v", "a", "j", "t0", "dt", "pot")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def state(sim):
+    order = np.argsort(sim.ids)
+    return {f: getattr(sim, f)[order].copy() for f in FIELDS}
+
+
+def run_engine(specs, steps, **kw):
+    eng = E.Engine(max_clusters=16, max_active=1 << 16, max_items=1 << 16, max_rows=1 << 16, **kw)
+    clusters = [eng.new_cluster(s) for s in specs]
+    for c in clusters:
+        eng.add(c)
+    for _ in range(steps):
+        eng.step()
+    out = [state(c.sim) for c in clusters]
+    stats = (eng.pairs, len(eng.step_ms))
+    eng.close()
+    return out, stats
+
+
+def test_batch_update_and_force_equal_per_context(oracle):
+    import torch
+    say("ht_batch update + force vs per-context calls")
+    s = torch.cuda.Stream()
+    batch = B.Batch(stream=s.cuda_stream, max_clusters=8, max_items=1 << 15, max_active=1 << 15, max_rows=1 << 15)
+    ctx_b, ctx_a, rows_l, act_l = [], [], [], []
+    for k, n in enumerate((700, 2000, 64)):
+        x, v, m = W.plummer(n, 90 + k)
+        z = np.zeros((n, 3))
+        tr = B.HostTree(x, v, z, z, m, 1, 64, 0.5)
+        x, v, m = x[tr.perm], v[tr.perm], m[tr.perm]
+        t0, a, j = W.random_block_state(n, 95 + k, 0.125)
+        pair = []
+        for _ in range(2):
+            c = B.Context(n_max=n, node_max=2 * n, group_max=n, list_max=2 * tr.n_entries + 64, active_max=n,
+                          eps2=1e-4, precision="mixed", stream=s.cuda_stream)
+            c.set_j_particles(t0, m, x, v, a, j)
+            c.set_nodes(0.0, tr.node_m, tr.node_x, tr.node_v, tr.node_a, tr.node_j)
+            c.set_interaction_lists(tr.group_first, tr.list_off, tr.entries)
+            pair.append(c)
+        ctx_b.append(pair[0])
+        ctx_a.append(pair[1])
+        rng = np.random.default_rng(k)
+        idx = np.sort(rng.choice(n, n // 3, replace=False)).astype(np.int32)
+        rows_l.append(B.make_rows(idx, np.full(idx.size, 0.125), m[idx], x[idx] + 1e-3, v[idx], a[idx] * 0.5,
+                                  j[idx] * 0.5))
+        act_l.append(np.sort(rng.choice(n, max(1, n // 2), replace=False)).astype(np.int32))
+    batch.update_async(ctx_b, rows_l)
+    outs = []
+    for c, a in zip(ctx_b, act_l):
+        c.predict(0.15625)
+        outs.append(tuple(torch.empty(sh, dtype=torch.float64, device="cuda") for sh in ((a.size, 3), (a.size, 3), (a.size,))))
+    batch.force_async(ctx_b, act_l, [o[0] for o in outs], [o[1] for o in outs], [o[2] for o in outs])
+    batch.sync()
+    for c, r, a, o in zip(ctx_a, rows_l, act_l, outs):
+        c.set_j_particles(r["t0"], r["m"], r["x"], r["v"], r["a"], r["jerk"], idx=r["idx"])
+        c.predict(0.15625)
+        want = c.force(a)
+        for p, q in zip(want, o):
+            assert np.array_equal(p, q.cpu().numpy())
+    with pytest.raises(B.HTError):
+        batch.update_async([ctx_b[0], ctx_b[0]], [rows_l[0], rows_l[0]])
+
+
+def test_engine_cluster_alone_equals_in_mix():
+    say("engine: three clusters alone vs together")
+    specs = [E.RunSpec(key=k, n=n, seed=300 + k, steps=10**9, n_crit=64) for k, n in enumerate((600, 1500, 3000))]
+    steps = 40
+    together, (pairs, nsteps) = run_engine(specs, steps)
+    assert nsteps == steps and pairs > 0
+    for k, s in enumerate(specs):
+        alone, _ = run_engine([s], steps)
+        for f in FIELDS:
+            assert np.array_equal(alone[0][f], together[k][f]), (k, f)
+
+
+def test_server_admission_respects_budget_and_results_match():
+    say("server: admission under a small device-memory budget")
+    specs = [E.RunSpec(key=k, n=n, seed=400 + k, steps=12, n_crit=64) for k, n in enumerate((800, 1200, 900, 2000, 700))]
+    eng = E.Engine(max_clusters=8, max_active=1 << 16, max_items=1 << 16, max_rows=1 << 16)
+    sizes = {s.key: eng.new_cluster(s).reserve for s in specs}
+    budget = sizes[3] + sizes[1]                   # room for about two runs at a time
+    srv = E.Server(eng, hbm_budget=budget, max_resident=8, keep_finished=True)
+    reqs = [E.Request(spec=s, arrival=0.0) for s in specs]
+    done = srv.run(reqs)
+    assert len(done) == len(specs)
+    assert srv.max_waiting >= 2                    # admission actually held requests back
+    assert srv.max_used <= budget
+    assert all(r.finished >= r.admitted >= r.arrival for r in done)
+    mixed = {r.spec.key: state(r.cluster.sim) for r in done}
+    for r in done:
+        r.cluster.close()
+    eng.close()
+    for s in specs[:3]:
+        alone, _ = run_engine([s], s.steps)
+        for f in FIELDS:
+            assert np.array_equal(alone[0][f], mixed[s.key][f]), (s.key, f)
