@@ -38,6 +38,8 @@ if ROOT not in sys.path:
 FLOPS_PER_PAIR = 57          # Section 3 convention for force + jerk
 PEAK_VALU_TFLOPS = 78.6      # 256 CU x 64 FMA lanes x 2 flop x 2.4 GHz (no packed FP32)
 METRIC = "Hermite acc+jerk interactions/s at N=2^20 vs direct; p99 block-step latency"
+METRIC_ENSEMBLE = "batched ensemble (64 Plummer clusters, N 4096-65536): Hermite acc+jerk interactions/s; p99 engine-step latency"
+METRIC_SERVED = "served stream of cluster runs (N 1024-262144, 256 block steps each): p50/p99 engine-step latency at 80% load"
 
 
 def log(msg):
@@ -160,6 +162,110 @@ def cpu_baseline(W, cfg, seconds):
                        f"({done_pairs:.3g} pairs, {spent:.1f} s)")
 
 
+def bench_ensemble(args, torch):
+    """64 independent clusters advanced together, one batched launch per engine step."""
+    from paper_1602_02832_amd import engine as E
+    from paper_1602_02832_amd import workloads as W
+
+    sizes = W.ensemble_sizes(64, 5, 4096, 65536)
+    specs = [E.RunSpec(key=k, n=int(n), seed=1000 + k, steps=10**9, theta=0.5, eta=0.01, dt_tree=1.0 / 256,
+                       n_crit=256) for k, n in enumerate(sizes)]
+    total_n = int(sizes.sum())
+    eng = E.Engine(precision="mixed", max_clusters=64, max_active=total_n, max_items=1 << 20, max_rows=total_n)
+    t0 = time.perf_counter()
+    for sp in specs:
+        eng.add(eng.new_cluster(sp))
+    log(f"ensemble: 64 clusters, {total_n} particles, set up in {time.perf_counter() - t0:.1f} s")
+    for _ in range(args.warmup):
+        eng.step()
+    eng.step_ms.clear()
+    eng.pairs = eng.equiv_pairs = 0
+    eng.wall = 0.0
+    eng.phase = {k: 0.0 for k in eng.phase}
+    eng.batch.set_timing(True)
+    torch.cuda.synchronize()
+    tw = time.perf_counter()
+    for _ in range(args.steps):
+        eng.step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - tw
+    kms, nl, kp = eng.batch.kernel_timing()
+    lat = np.array(eng.step_ms)
+    value = eng.pairs / wall
+    achieved = FLOPS_PER_PAIR * kp / (kms * 1e-3) / 1e12
+    log(f"ensemble: {value:.4g} pairs/s, {1e3 * wall / args.steps:.3f} ms/engine step, phases {eng.phase}")
+    res = {
+        "metric": METRIC_ENSEMBLE, "value": value, "unit": "interactions/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": "ensemble64", "clusters": 64, "n_range": [4096, 65536], "n_total": total_n,
+                   "theta": 0.5, "eps": "4/N", "dt_tree": 1.0 / 256, "eta": 0.01, "n_crit": 256, "precision": "mixed"},
+        "p50_step_ms": float(np.percentile(lat, 50)), "p99_step_ms": float(np.percentile(lat, 99)),
+        "equivalent_interactions_per_s": eng.equiv_pairs / wall,
+        "phase_s": eng.phase,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None,
+                     "kernel": "force_kernel<PrecMixed,false,false>", "avg_launch_ms": kms / max(nl, 1)},
+    }
+    eng.close()
+    print(json.dumps(res), flush=True)
+
+
+def bench_served(args, torch):
+    """Continuous batching of cluster runs: capacity first, then Poisson arrivals at 80% of it."""
+    from paper_1602_02832_amd import engine as E
+    from paper_1602_02832_amd import workloads as W
+
+    n_req = args.requests
+    sizes = W.ensemble_sizes(n_req, 8, 1024, 262144)
+    specs = [E.RunSpec(key=r, n=int(sizes[r]), seed=2000 + r, steps=256, theta=0.5, eta=0.01, dt_tree=1.0 / 256,
+                       n_crit=256) for r in range(n_req)]
+    budget = int(args.hbm_gb * 2**30)
+    cap_active = 1 << 23
+
+    def serve(reqs):
+        eng = E.Engine(precision="mixed", max_clusters=args.max_resident, max_active=cap_active, max_items=1 << 20,
+                       max_rows=cap_active)
+        srv = E.Server(eng, hbm_budget=budget, max_resident=args.max_resident)
+        t = time.perf_counter()
+        done = srv.run(reqs)
+        span = time.perf_counter() - t
+        out = dict(span=span, done=done, step_ms=list(eng.step_ms), pairs=eng.pairs, phase=dict(eng.phase),
+                   max_used=srv.max_used, max_waiting=srv.max_waiting)
+        eng.close()
+        return out
+
+    n_cap = min(n_req, 2 * args.max_resident)
+    cap_run = serve([E.Request(spec=specs[r], arrival=0.0) for r in range(n_cap)])
+    capacity = n_cap / cap_run["span"]
+    log(f"served: capacity {capacity:.3g} runs/s (closed loop, {n_cap} runs in {cap_run['span']:.1f} s)")
+    rate = 0.8 * capacity
+    arr = E.poisson_arrivals(n_req, rate, 7)
+    run = serve([E.Request(spec=specs[r], arrival=float(arr[r])) for r in range(n_req)])
+    done = run["done"]
+    lat = np.array(run["step_ms"])
+    resp = np.array([r.finished - r.arrival for r in done])
+    queue = np.array([r.admitted - r.arrival for r in done])
+    log(f"served: {len(done)} runs in {run['span']:.1f} s; engine step p50 {np.percentile(lat, 50):.2f} ms "
+        f"p99 {np.percentile(lat, 99):.2f} ms; phases {run['phase']}")
+    res = {
+        "metric": METRIC_SERVED, "value": float(np.percentile(lat, 99)), "unit": "ms", "n_gpus": 1,
+        "steps": len(lat), "warmup": 0, "ms_per_step": float(lat.mean()), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": "served", "requests": n_req, "n_range": [1024, 262144], "block_steps_per_run": 256,
+                   "theta": 0.5, "eps": "4/N", "dt_tree": 1.0 / 256, "eta": 0.01, "n_crit": 256,
+                   "arrival_rate_per_s": rate, "load": 0.8, "max_resident": args.max_resident,
+                   "hbm_budget_gb": args.hbm_gb, "precision": "mixed"},
+        "p50_step_ms": float(np.percentile(lat, 50)), "p99_step_ms": float(np.percentile(lat, 99)),
+        "capacity_runs_per_s": capacity, "throughput_runs_per_s": len(done) / run["span"],
+        "interactions_per_s": run["pairs"] / run["span"],
+        "request_latency_s": {"p50": float(np.percentile(resp, 50)), "p99": float(np.percentile(resp, 99))},
+        "queue_delay_s": {"p50": float(np.percentile(queue, 50)), "p99": float(np.percentile(queue, 99))},
+        "max_hbm_used_gb": run["max_used"] / 2**30, "max_waiting": run["max_waiting"], "phase_s": run["phase"],
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,6 +279,9 @@ def main():
     ap.add_argument("--no-all-active", action="store_true")
     ap.add_argument("--n", type=int, default=0, help="override N (testing only; not the benchmark)")
     ap.add_argument("--dump-steps", default="", help="write per-step (n_active, pairs, items, ms) JSON here")
+    ap.add_argument("--requests", type=int, default=200, help="served workload: number of cluster runs")
+    ap.add_argument("--max-resident", type=int, default=32, help="served workload: batch slots")
+    ap.add_argument("--hbm-gb", type=float, default=64.0, help="served workload: device-memory budget")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path; run with --gpus 1", file=sys.stderr)
@@ -190,6 +299,10 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.workload == "ensemble64":
+        return bench_ensemble(args, torch)
+    if args.workload == "served":
+        return bench_served(args, torch)
     cfg = W.config(args.workload)
     if args.n:
         cfg = W.config(args.workload, n=args.n, eps=4.0 / args.n)

@@ -118,6 +118,9 @@ int ht_set_interaction_lists(ht_ctx *ctx, int32_t n_groups, const int64_t *group
 /* Step 5 (predictor): predict particles and nodes to block time t. */
 int ht_predict(ht_ctx *ctx, double t);
 
+/* ht_predict(ctxs[k], t[k]) for k < n_ctx (arguments checked for all first). */
+int ht_predict_many(int32_t n_ctx, ht_ctx *const *ctxs, const double *t);
+
 /* Steps 4a and 5: acc, jerk ([n][3]) and pot ([n]) of the particles
  * active_ids[0..n-1] (strictly increasing, each < N), summed over their
  * groups' lists at the predicted time.  n_active == 0 is a no-op. */

@@ -67,6 +67,39 @@ int htb_correct(int64_t n_active, const int32_t *ids, double t1, double eta, dou
 /* Initial block steps from eta |a| / |jerk| (capped by dt_tree) at t = 0. */
 int htb_initial_steps(int64_t n, double eta, double dt_tree, const double *a, const double *jerk, double *dt);
 
+/* ---------------------------------------------------------------------------
+ * The same host steps for many clusters at once (batched engine): one call,
+ * OpenMP across clusters.  Each cluster is described by the caller's arrays
+ * (particles in tree order); the library only reads and writes through them.
+ */
+typedef struct {
+    int64_t n;          /* particles */
+    double eta;         /* Aarseth accuracy parameter */
+    double dt_tree;     /* tree interval (largest block step) */
+    double *t0, *dt;    /* [n] time of data, block step */
+    double *x, *v, *a, *jerk;   /* [n][3] */
+    const double *m;    /* [n] */
+    double *pot;        /* [n] last potential */
+    int32_t *active;    /* [n] scratch: active ids of the current step */
+    int64_t n_active;   /* out of htb_next_block_many */
+    double t_next;      /* out of htb_next_block_many */
+} htb_cluster;
+
+/* Step 2 for every cluster: t_next, n_active and active[] of each. */
+int htb_next_block_many(int32_t n_clusters, htb_cluster *cl);
+
+/* Step 6 for every cluster's current active set (from htb_next_block_many):
+ * forces of cluster k are rows off[k] .. off[k] + n_active - 1 of acc [*][3],
+ * jerk [*][3] and pot [*].  Then, unless the cluster has reached a tree time
+ * (t_next a multiple of dt_tree, where it must rebuild), its corrected
+ * particles are written as 120-byte update rows (layout of ht_row in htree.h:
+ * int32 idx, int32 pad, double t0, m, x[3], v[3], a[3], jerk[3]) at
+ * rows + row_off[k].  rebuild[k] is set to 1 for clusters at a tree time.
+ * Returns -2 if a step would fall below 2^-40. */
+int htb_correct_many(int32_t n_clusters, htb_cluster *cl, const int64_t *off, const double *acc,
+                     const double *jerk, const double *pot, const int64_t *row_off, void *rows,
+                     int32_t *rebuild);
+
 #ifdef __cplusplus
 }
 #endif

@@ -39,6 +39,14 @@ class HTError(RuntimeError):
         self.code = code
 
 
+class HtbCluster(ctypes.Structure):
+    """htb_cluster (include/htree_host.h): one cluster's host arrays."""
+    _fields_ = [("n", ctypes.c_int64), ("eta", ctypes.c_double), ("dt_tree", ctypes.c_double),
+                ("t0", _c_dp), ("dt", _c_dp), ("x", _c_dp), ("v", _c_dp), ("a", _c_dp), ("jerk", _c_dp),
+                ("m", _c_dp), ("pot", _c_dp), ("active", _c_i32p), ("n_active", ctypes.c_int64),
+                ("t_next", ctypes.c_double)]
+
+
 class HtConfig(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("precision", ctypes.c_int32), ("predict_mode", ctypes.c_int32),
                 ("n_max", ctypes.c_int32), ("node_max", ctypes.c_int32), ("group_max", ctypes.c_int32),
@@ -106,6 +114,7 @@ def device_lib():
             "ht_set_tuning": [_vp, d, d],
             "ht_kernel_timing": [_vp, _c_dp, _c_i64p, _c_i64p],
             "ht_last_error": [],
+            "ht_predict_many": [i, ctypes.POINTER(_vp), _c_dp],
             "ht_batch_workspace_bytes": [i, i64, i64, i64, ctypes.POINTER(ctypes.c_size_t)],
             "ht_batch_create": [ctypes.POINTER(_vp), i, _vp, i, i64, i64, i64, _vp, ctypes.c_size_t],
             "ht_batch_destroy": [_vp],
@@ -141,6 +150,8 @@ def host_lib():
             "htb_next_block": [i64, _c_dp, _c_dp, _c_dp, _c_i32p, _c_i64p],
             "htb_correct": [i64, _c_i32p, d, d, d, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp],
             "htb_initial_steps": [i64, d, d, _c_dp, _c_dp, _c_dp],
+            "htb_next_block_many": [i, ctypes.POINTER(HtbCluster)],
+            "htb_correct_many": [i, ctypes.POINTER(HtbCluster), _c_i64p, _c_dp, _c_dp, _c_dp, _c_i64p, _vp, _c_i32p],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -317,6 +328,13 @@ class Context:
         return p.value, w.value
 
 
+def predict_many(ctxs, t):
+    n = len(ctxs)
+    t = _arr(t, np.float64)
+    H = (_vp * n)(*[c.handle for c in ctxs])
+    _check(device_lib().ht_predict_many(n, H, _ptr(t, ctypes.c_double)))
+
+
 def force_batch_async(ctxs, actives, d_accs, d_jerks, d_pots):
     """ht_force_batch_async over several contexts sharing one stream."""
     n = len(ctxs)
@@ -486,6 +504,33 @@ def correct(ids, t1, eta, dt_tree, t0, dt, x, v, a, jerk, acc1, jerk1):
         raise FloatingPointError("block step below 2^-40")
     if rc:
         raise HTError(rc, "htb_correct failed")
+
+
+def cluster_struct(n, eta, dt_tree, t0, dt, x, v, a, jerk, m, pot, active):
+    """HtbCluster pointing at the given arrays (which must stay alive and in place)."""
+    for arr in (t0, dt, x, v, a, jerk, m, pot):
+        assert arr.dtype == np.float64 and arr.flags.c_contiguous
+    assert active.dtype == np.int32 and active.flags.c_contiguous
+    d = ctypes.c_double
+    return HtbCluster(int(n), float(eta), float(dt_tree), _ptr(t0, d), _ptr(dt, d), _ptr(x, d), _ptr(v, d), _ptr(a, d),
+                      _ptr(jerk, d), _ptr(m, d), _ptr(pot, d), _ptr(active, ctypes.c_int32), 0, 0.0)
+
+
+def next_block_many(structs):
+    rc = host_lib().htb_next_block_many(len(structs), structs)
+    if rc:
+        raise HTError(rc, "htb_next_block_many failed")
+
+
+def correct_many(structs, off, acc, jerk, pot, row_off, rows, rebuild):
+    d = ctypes.c_double
+    rc = host_lib().htb_correct_many(len(structs), structs, _ptr(off, ctypes.c_int64), _ptr(acc, d), _ptr(jerk, d),
+                                     _ptr(pot, d), _ptr(row_off, ctypes.c_int64), rows.ctypes.data,
+                                     _ptr(rebuild, ctypes.c_int32))
+    if rc == -2:
+        raise FloatingPointError("block step below 2^-40")
+    if rc:
+        raise HTError(rc, "htb_correct_many failed")
 
 
 def initial_steps(eta, dt_tree, a, jerk):

@@ -217,6 +217,55 @@ double quantise(double cap, double t1) {
     return h >= floor_h ? h : 0.0;
 }
 inline double len3(const double* u) { return std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]); }
+
+// Hermite corrector, Aarseth step and block quantisation for particle i
+// (forces acc1, jerk1 at t1); returns 1 if the step fell below the floor.
+inline int correct_one(int64_t i, double t1, double eta, double dt_tree, double* t0, double* dt, double* x, double* v,
+                       double* a, double* jerk, const double* acc1, const double* jerk1) {
+    const double D = t1 - t0[i];
+    const double h2 = 0.5 * D, h3 = D / 3.0;
+    double s2[3], s3[3], s2n[3];
+    const double D2 = D * D, D3 = D2 * D, D4 = D2 * D2, D5 = D4 * D;
+    for (int d = 0; d < 3; ++d) {
+        const int64_t q = 3 * i + d;
+        const double xp = x[q] + D * (v[q] + h2 * (a[q] + h3 * jerk[q]));
+        const double vp = v[q] + D * (a[q] + h2 * jerk[q]);
+        const double diff = a[q] - acc1[d];
+        s2[d] = (-6.0 * diff - D * (4.0 * jerk[q] + 2.0 * jerk1[d])) / D2;  // a'' at t0
+        s3[d] = (12.0 * diff + 6.0 * D * (jerk[q] + jerk1[d])) / D3;        // a'''
+        x[q] = xp + s2[d] * (D4 / 24.0) + s3[d] * (D5 / 120.0);
+        v[q] = vp + s2[d] * (D3 / 6.0) + s3[d] * (D4 / 24.0);
+        a[q] = acc1[d];
+        jerk[q] = jerk1[d];
+        s2n[d] = s2[d] + D * s3[d];                                          // a'' at t1
+    }
+    const double na = len3(acc1), nj = len3(jerk1);
+    const double n2 = len3(s2n), n3 = len3(s3);
+    const double den = nj * n3 + n2 * n2;
+    const double raw = den > 0.0 ? std::sqrt(eta * (na * n2 + nj * nj) / den) : dt_tree;
+    const double h = quantise(std::min(std::min(raw, dt_tree), 2.0 * dt[i]), t1);
+    t0[i] = t1;
+    dt[i] = h;
+    return h == 0.0 ? 1 : 0;
+}
+
+struct Row {  // ht_row layout
+    int32_t idx, pad;
+    double t0, m;
+    double x[3], v[3], a[3], jerk[3];
+};
+static_assert(sizeof(Row) == 120, "update row layout");
+
+int64_t next_block_one(htb_cluster& c) {
+    double tmin = std::numeric_limits<double>::infinity();
+    for (int64_t i = 0; i < c.n; ++i) tmin = std::min(tmin, c.t0[i] + c.dt[i]);
+    int64_t k = 0;
+    for (int64_t i = 0; i < c.n; ++i)
+        if (c.t0[i] + c.dt[i] == tmin) c.active[k++] = static_cast<int32_t>(i);
+    c.t_next = tmin;
+    c.n_active = k;
+    return k;
+}
 }  // namespace
 
 extern "C" {
@@ -417,34 +466,8 @@ int htb_correct(int64_t n_active, const int32_t* ids, double t1, double eta, dou
         return -1;
     int bad = 0;
 #pragma omp parallel for schedule(static) reduction(| : bad)
-    for (int64_t k = 0; k < n_active; ++k) {
-        const int64_t i = ids[k];
-        const double D = t1 - t0[i];
-        const double h2 = 0.5 * D, h3 = D / 3.0;
-        double s2[3], s3[3], s2n[3];
-        const double D2 = D * D, D3 = D2 * D, D4 = D2 * D2, D5 = D4 * D;
-        for (int d = 0; d < 3; ++d) {
-            const int64_t q = 3 * i + d, r = 3 * k + d;
-            const double xp = x[q] + D * (v[q] + h2 * (a[q] + h3 * jerk[q]));
-            const double vp = v[q] + D * (a[q] + h2 * jerk[q]);
-            const double diff = a[q] - acc1[r];
-            s2[d] = (-6.0 * diff - D * (4.0 * jerk[q] + 2.0 * jerk1[r])) / D2;  // a'' at t0
-            s3[d] = (12.0 * diff + 6.0 * D * (jerk[q] + jerk1[r])) / D3;        // a'''
-            x[q] = xp + s2[d] * (D4 / 24.0) + s3[d] * (D5 / 120.0);
-            v[q] = vp + s2[d] * (D3 / 6.0) + s3[d] * (D4 / 24.0);
-            a[q] = acc1[r];
-            jerk[q] = jerk1[r];
-            s2n[d] = s2[d] + D * s3[d];                                          // a'' at t1
-        }
-        const double na = len3(&acc1[3 * k]), nj = len3(&jerk1[3 * k]);
-        const double n2 = len3(s2n), n3 = len3(s3);
-        const double den = nj * n3 + n2 * n2;
-        const double raw = den > 0.0 ? std::sqrt(eta * (na * n2 + nj * nj) / den) : dt_tree;
-        const double h = quantise(std::min(std::min(raw, dt_tree), 2.0 * dt[i]), t1);
-        if (h == 0.0) bad = 1;
-        t0[i] = t1;
-        dt[i] = h;
-    }
+    for (int64_t k = 0; k < n_active; ++k)
+        bad |= correct_one(ids[k], t1, eta, dt_tree, t0, dt, x, v, a, jerk, acc1 + 3 * k, jerk1 + 3 * k);
     return bad ? -2 : 0;
 }
 
@@ -457,6 +480,51 @@ int htb_initial_steps(int64_t n, double eta, double dt_tree, const double* a, co
         const double raw = nj > 0.0 ? eta * na / nj : dt_tree;
         dt[i] = quantise(std::min(raw, dt_tree), 0.0);
         if (dt[i] == 0.0) bad = 1;
+    }
+    return bad ? -2 : 0;
+}
+
+int htb_next_block_many(int32_t n_clusters, htb_cluster* cl) {
+    if (n_clusters < 0 || (n_clusters > 0 && !cl)) return -1;
+    for (int32_t k = 0; k < n_clusters; ++k)
+        if (cl[k].n < 1 || !cl[k].t0 || !cl[k].dt || !cl[k].active) return -1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t k = 0; k < n_clusters; ++k) next_block_one(cl[k]);
+    return 0;
+}
+
+int htb_correct_many(int32_t n_clusters, htb_cluster* cl, const int64_t* off, const double* acc, const double* jerk,
+                     const double* pot, const int64_t* row_off, void* rows, int32_t* rebuild) {
+    if (n_clusters < 0 || (n_clusters > 0 && (!cl || !off || !acc || !jerk || !pot || !row_off || !rows || !rebuild)))
+        return -1;
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
+    for (int32_t k = 0; k < n_clusters; ++k) {
+        htb_cluster& c = cl[k];
+        const int64_t o = off[k];
+        for (int64_t q = 0; q < c.n_active; ++q) {
+            const int32_t id = c.active[q];
+            bad |= correct_one(id, c.t_next, c.eta, c.dt_tree, c.t0, c.dt, c.x, c.v, c.a, c.jerk, acc + 3 * (o + q),
+                               jerk + 3 * (o + q));
+            c.pot[id] = pot[o + q];
+        }
+        rebuild[k] = std::fmod(c.t_next, c.dt_tree) == 0.0 ? 1 : 0;
+        if (rebuild[k]) continue;
+        Row* r = static_cast<Row*>(rows) + row_off[k];
+        for (int64_t q = 0; q < c.n_active; ++q) {
+            const int32_t i = c.active[q];
+            Row& w = r[q];
+            w.idx = i;
+            w.pad = 0;
+            w.t0 = c.t0[i];
+            w.m = c.m[i];
+            for (int d = 0; d < 3; ++d) {
+                w.x[d] = c.x[3 * i + d];
+                w.v[d] = c.v[3 * i + d];
+                w.a[d] = c.a[3 * i + d];
+                w.jerk[d] = c.jerk[3 * i + d];
+            }
+        }
     }
     return bad ? -2 : 0;
 }

@@ -1252,6 +1252,20 @@ int ht_predict(ht_ctx* c, double t) {
     return HT_OK;
 }
 
+int ht_predict_many(int32_t n_ctx, ht_ctx* const* ctxs, const double* t) {
+    if (n_ctx < 0 || (n_ctx > 0 && (!ctxs || !t))) return fail(HT_EINVAL, "bad arguments");
+    for (int32_t k = 0; k < n_ctx; ++k) {
+        if (!ctxs[k]) return fail(HT_EINVAL, "ctx %d is NULL", k);
+        if (!ctxs[k]->have_particles) return fail(HT_ESTATE, "ctx %d: predict before particles", k);
+        if (!std::isfinite(t[k])) return fail(HT_EINVAL, "ctx %d: t not finite", k);
+    }
+    for (int32_t k = 0; k < n_ctx; ++k) {
+        int rc = ht_predict(ctxs[k], t[k]);
+        if (rc) return rc;
+    }
+    return HT_OK;
+}
+
 int ht_force(ht_ctx* c, int32_t n_active, const int32_t* ids, double* acc, double* jerk, double* pot) {
     return force_to_host(c, n_active, ids, acc, jerk, pot, false);
 }

@@ -20,6 +20,7 @@ allow; finished runs leave and free their slots.
 from __future__ import annotations
 
 import collections
+import concurrent.futures
 import dataclasses
 import math
 import time
@@ -68,6 +69,8 @@ class Cluster:
         self.pending_rows = None
         self.steps_done = 0
         self.active_sum = 0
+        self._struct = None
+        self._struct_arrays = ()
 
     def activate(self):
         if self.sim is None:
@@ -112,7 +115,7 @@ class Engine:
     """Advances a set of clusters one block step each per engine step."""
 
     def __init__(self, precision="mixed", device=0, max_clusters=256, max_active=1 << 21, max_items=1 << 20,
-                 max_rows=1 << 21):
+                 max_rows=1 << 21, rebuild_workers=4):
         import torch
 
         self.torch = torch
@@ -130,10 +133,19 @@ class Engine:
         self.h_acc = torch.empty((max_active, 3), dtype=torch.float64, pin_memory=True)
         self.h_jerk = torch.empty((max_active, 3), dtype=torch.float64, pin_memory=True)
         self.h_pot = torch.empty(max_active, dtype=torch.float64, pin_memory=True)
+        # corrected particles of every cluster, written by the native corrector, read by the next update
+        self._h_rows_t = torch.empty(max_active * B.HT_ROW.itemsize, dtype=torch.uint8, pin_memory=True)
+        self.h_rows = self._h_rows_t.numpy().view(B.HT_ROW)
         self.step_ms = []
         self.pairs = 0
         self.equiv_pairs = 0
         self.wall = 0.0
+        # where an engine step's time goes: host before the launch, waiting for the device, host after
+        self.phase = {"host_begin": 0.0, "device_wait": 0.0, "host_finish": 0.0}
+        # tree rebuilds run beside the engine loop; a rebuilding cluster sits out until it is resident again
+        self.pool = concurrent.futures.ThreadPoolExecutor(max_workers=rebuild_workers) if rebuild_workers else None
+        self.rebuilding = {}
+        self._ptr = (self.d_acc.data_ptr(), self.d_jerk.data_ptr(), self.d_pot.data_ptr())
 
     def new_cluster(self, spec: RunSpec) -> Cluster:
         return Cluster(spec, self.precision, self.stream.cuda_stream, self.device)
@@ -144,55 +156,108 @@ class Engine:
         c.activate()
         self.clusters.append(c)
 
-    def remove(self, c: Cluster):
-        self.clusters.remove(c)
+    def _struct(self, c: Cluster):
+        """The cluster's host arrays as an htb_cluster (rebuilt after a tree
+        rebuild, which replaces the arrays)."""
+        sim = c.sim
+        arrays = (sim.t0, sim.dt, sim.x, sim.v, sim.a, sim.j, sim.m, sim.pot, sim._act_buf)
+        if c._struct is None or any(p is not q for p, q in zip(c._struct_arrays, arrays)):
+            c._struct = B.cluster_struct(sim.n, sim.eta, sim.dt_tree, *arrays)
+            c._struct_arrays = arrays
+        return c._struct
+
+    def _collect_rebuilds(self, wait=False):
+        for c, fut in list(self.rebuilding.items()):
+            if wait or fut.done():
+                fut.result()
+                del self.rebuilding[c]
 
     def step(self):
         """One engine step over all resident clusters; returns the clusters
         that finished their run in this step."""
         t0 = time.perf_counter()
-        cl = [c for c in self.clusters if not c.done]
+        self._collect_rebuilds()
+        cl = [c for c in self.clusters if not c.done and c not in self.rebuilding]
         if not cl:
+            if self.rebuilding:
+                self._collect_rebuilds(wait=True)
             return []
+        # 1. j-memory updates from the previous step (one copy, one kernel)
         ups = [c for c in cl if c.pending_rows is not None and c.pending_rows.shape[0]]
         if ups:
             self.batch.update_async([c.ctx for c in ups], [c.pending_rows for c in ups])
-        acts, offs = [], []
-        off = 0
-        for c in cl:
-            c.pending_rows = None
-            tn, act = c.sim.begin_step()
-            acts.append(act)
-            offs.append(off)
-            off += act.size
-        if off > self.max_active:
+        # 2. next block time and active set of every cluster (one native call)
+        structs = (B.HtbCluster * len(cl))(*[self._struct(c) for c in cl])
+        B.next_block_many(structs)
+        t_next = np.array([structs[k].t_next for k in range(len(cl))])
+        n_act = np.array([structs[k].n_active for k in range(len(cl))], dtype=np.int64)
+        offs = np.zeros(len(cl), dtype=np.int64)
+        np.cumsum(n_act[:-1], out=offs[1:])
+        total = int(n_act.sum())
+        if total > self.max_active:
             raise RuntimeError("active particles over the engine capacity")
-        self.batch.force_async([c.ctx for c in cl], acts, [self.d_acc[o:o + a.size] for o, a in zip(offs, acts)],
-                               [self.d_jerk[o:o + a.size] for o, a in zip(offs, acts)],
-                               [self.d_pot[o:o + a.size] for o, a in zip(offs, acts)])
+        acts = [c.sim._act_buf[:n] for c, n in zip(cl, n_act)]
+        ctxs = [c.ctx for c in cl]
+        # 3-4. predict every cluster at its own block time, one force launch for all
+        B.predict_many(ctxs, t_next)
+        pa, pj, pp = self._ptr
+        self.batch.force_async(ctxs, acts, [pa + 24 * int(o) for o in offs], [pj + 24 * int(o) for o in offs],
+                               [pp + 8 * int(o) for o in offs])
         pairs, _ = self.batch.last_stats()
+        t1 = time.perf_counter()
         with self.torch.cuda.stream(self.stream):
-            self.h_acc[:off].copy_(self.d_acc[:off], non_blocking=True)
-            self.h_jerk[:off].copy_(self.d_jerk[:off], non_blocking=True)
-            self.h_pot[:off].copy_(self.d_pot[:off], non_blocking=True)
+            self.h_acc[:total].copy_(self.d_acc[:total], non_blocking=True)
+            self.h_jerk[:total].copy_(self.d_jerk[:total], non_blocking=True)
+            self.h_pot[:total].copy_(self.d_pot[:total], non_blocking=True)
         self.stream.synchronize()
-        acc, jerk, pot = self.h_acc[:off].numpy(), self.h_jerk[:off].numpy(), self.h_pot[:off].numpy()
+        t2 = time.perf_counter()
+        # 5. corrector, new steps and update rows of every cluster (one native call)
+        rebuild = np.zeros(len(cl), dtype=np.int32)
+        B.correct_many(structs, offs, self.h_acc[:total].numpy(), self.h_jerk[:total].numpy(),
+                       self.h_pot[:total].numpy(), offs, self.h_rows, rebuild)
         finished = []
-        for c, o, a in zip(cl, offs, acts):
-            sl = slice(o, o + a.size)
-            c.pending_rows = c.sim.finish_step(acc[sl], jerk[sl], pot[sl])
+        for k, c in enumerate(cl):
+            sim = c.sim
+            n = int(n_act[k])
+            sim.t = float(t_next[k])
+            sim.n_block_steps += 1
+            sim.n_particle_steps += n
             c.steps_done += 1
-            c.active_sum += a.size
+            c.active_sum += n
+            if rebuild[k]:
+                c.pending_rows = None          # tree time: new tree, lists, full upload
+                if self.pool is not None:
+                    self.rebuilding[c] = self.pool.submit(sim._build_and_send)
+                else:
+                    sim._build_and_send()
+            else:
+                c.pending_rows = self.h_rows[offs[k]:offs[k] + n]
             if c.done:
                 finished.append(c)
-        dt = time.perf_counter() - t0
+        t3 = time.perf_counter()
+        dt = t3 - t0
+        self.phase["host_begin"] += t1 - t0
+        self.phase["device_wait"] += t2 - t1
+        self.phase["host_finish"] += t3 - t2
         self.step_ms.append(1e3 * dt)
         self.wall += dt
         self.pairs += pairs
-        self.equiv_pairs += sum(a.size * (c.sim.n - 1) for c, a in zip(cl, acts))
+        self.equiv_pairs += int(sum(int(n) * (c.sim.n - 1) for c, n in zip(cl, n_act)))
         return finished
 
+    def drain(self):
+        """Wait for rebuilds in flight."""
+        self._collect_rebuilds(wait=True)
+
+    def remove(self, c: Cluster):
+        if c in self.rebuilding:
+            self.rebuilding.pop(c).result()
+        self.clusters.remove(c)
+
     def close(self):
+        self.drain()
+        if self.pool is not None:
+            self.pool.shutdown(wait=True)
         for c in self.clusters:
             c.close()
         self.clusters = []

@@ -27,15 +27,18 @@ def state(sim):
     return {f: getattr(sim, f)[order].copy() for f in FIELDS}
 
 
-def run_engine(specs, steps, **kw):
+def run_engine(specs, **kw):
+    """Run every cluster to its spec.steps block steps (rebuilds may make a
+    cluster sit out engine steps; its own sequence of steps never changes)."""
     eng = E.Engine(max_clusters=16, max_active=1 << 16, max_items=1 << 16, max_rows=1 << 16, **kw)
     clusters = [eng.new_cluster(s) for s in specs]
     for c in clusters:
         eng.add(c)
-    for _ in range(steps):
+    while not all(c.done for c in clusters):
         eng.step()
+    eng.drain()
     out = [state(c.sim) for c in clusters]
-    stats = (eng.pairs, len(eng.step_ms))
+    stats = (eng.pairs, len(eng.step_ms), [c.steps_done for c in clusters])
     eng.close()
     return out, stats
 
@@ -86,12 +89,11 @@ def test_batch_update_and_force_equal_per_context(oracle):
 
 def test_engine_cluster_alone_equals_in_mix():
     say("engine: three clusters alone vs together")
-    specs = [E.RunSpec(key=k, n=n, seed=300 + k, steps=10**9, n_crit=64) for k, n in enumerate((600, 1500, 3000))]
-    steps = 40
-    together, (pairs, nsteps) = run_engine(specs, steps)
-    assert nsteps == steps and pairs > 0
+    specs = [E.RunSpec(key=k, n=n, seed=300 + k, steps=40, n_crit=64) for k, n in enumerate((600, 1500, 3000))]
+    together, (pairs, nsteps, done) = run_engine(specs)
+    assert nsteps >= 40 and pairs > 0 and done == [40, 40, 40]
     for k, s in enumerate(specs):
-        alone, _ = run_engine([s], steps)
+        alone, _ = run_engine([s], rebuild_workers=0)
         for f in FIELDS:
             assert np.array_equal(alone[0][f], together[k][f]), (k, f)
 
@@ -114,6 +116,6 @@ def test_server_admission_respects_budget_and_results_match():
         r.cluster.close()
     eng.close()
     for s in specs[:3]:
-        alone, _ = run_engine([s], s.steps)
+        alone, _ = run_engine([s])
         for f in FIELDS:
             assert np.array_equal(alone[0][f], mixed[s.key][f]), (s.key, f)
