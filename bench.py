@@ -23,6 +23,7 @@ One JSON line on stdout; progress on stderr.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -39,7 +40,48 @@ FLOPS_PER_PAIR = 57          # Section 3 convention for force + jerk
 PEAK_VALU_TFLOPS = 78.6      # 256 CU x 64 FMA lanes x 2 flop x 2.4 GHz (no packed FP32)
 METRIC = "Hermite acc+jerk interactions/s at N=2^20 vs direct; p99 block-step latency"
 METRIC_ENSEMBLE = "batched ensemble (64 Plummer clusters, N 4096-65536): Hermite acc+jerk interactions/s; p99 engine-step latency"
+# HBM traffic of the timed force kernel, from two rocprofv3 --pmc passes over
+# this benchmark's default window (FETCH_SIZE, then WRITE_SIZE, KiB summed over
+# the L2 channels, mean over the 64 timed launches), each divided by what the
+# same counter reads per byte for a plain device copy (--calibrate-copy).  Valid
+# only for the kernel source it was taken on: any change to it makes the
+# figure null until the counters are taken again.
+TRAFFIC = {
+    "kernel_source_sha256": None,
+    "fetch_bytes_per_launch": None,
+    "write_bytes_per_launch": None,
+    "fetch_scale": None,
+    "write_scale": None,
+    "profile": "profiles/force_kernel_mixed_plummer1m_traffic.md",
+}
 METRIC_SERVED = "served stream of cluster runs (N 1024-262144, 256 block steps each): p50/p99 engine-step latency at 80% load"
+
+
+def kernel_source_sha256():
+    path = os.path.join(ROOT, "paper_1602_02832_amd", "csrc", "htree.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the timed kernel, or None when not measured on
+    the kernel source as it stands."""
+    if TRAFFIC["kernel_source_sha256"] != kernel_source_sha256() or TRAFFIC["fetch_bytes_per_launch"] is None:
+        return None
+    return TRAFFIC["fetch_bytes_per_launch"] + TRAFFIC["write_bytes_per_launch"]
+
+
+def calibrate_copy(torch, mib):
+    """A plain device copy of known size for scaling the L2 byte counters:
+    torch.neg reads mib MiB and writes mib MiB in one elementwise kernel."""
+    n = (mib << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    log(f"copy calibration: 3 launches, each reading and writing {mib} MiB")
 
 
 def log(msg):
@@ -119,10 +161,12 @@ def replay(torch, B, rec, ctx, stream, warmup, steps, direct=False):
     t_wall = time.perf_counter()
     for q, k in enumerate(range(warmup, warmup + steps)):
         evs[q].record(stream)
+        th = time.perf_counter()
         run_step(k)
+        th = time.perf_counter() - th
         p, w = ctx.last_stats()
         pairs += p
-        per_step.append((int(rec.steps[k][1].size), int(p), int(w)))
+        per_step.append((int(rec.steps[k][1].size), int(p), int(w), 1e6 * th))
     evs[steps].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall
@@ -282,6 +326,8 @@ def main():
     ap.add_argument("--requests", type=int, default=200, help="served workload: number of cluster runs")
     ap.add_argument("--max-resident", type=int, default=32, help="served workload: batch slots")
     ap.add_argument("--hbm-gb", type=float, default=64.0, help="served workload: device-memory budget")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (scale for the byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path; run with --gpus 1", file=sys.stderr)
@@ -299,6 +345,8 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.calibrate_copy:
+        return calibrate_copy(torch, args.calibrate_copy)
     if args.workload == "ensemble64":
         return bench_ensemble(args, torch)
     if args.workload == "served":
@@ -439,7 +487,8 @@ def main():
         "equivalent_interactions_per_s": eq_pairs / mixed["wall_s"],
         "tflops_at_57": FLOPS_PER_PAIR * value / 1e12,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_VALU_TFLOPS, "traffic": measured_traffic(),
+                     "traffic_unit": "bytes/launch",
                      "kernel": "force_kernel<PrecMixed,false,false>", "avg_launch_ms": kernel_avg_ms,
                      "pairs_per_launch": mixed["kernel_pairs"] / max(mixed["launches"], 1)},
     }

@@ -127,7 +127,10 @@ int ht_predict_many(int32_t n_ctx, ht_ctx *const *ctxs, const double *t);
 int ht_force(ht_ctx *ctx, int32_t n_active, const int32_t *active_ids, double *acc, double *jerk,
              double *pot);
 
-/* As ht_force with results written to device arrays, asynchronously. */
+/* As ht_force with results written to device arrays, asynchronously.  The
+ * work plan is packed into a pinned host slot (a ring of four, so the host can
+ * run ahead of the device) that the device reads directly; a slot is reused
+ * only after the launch that read it has completed. */
 int ht_force_async(ht_ctx *ctx, int32_t n_active, const int32_t *active_ids, double *d_acc,
                    double *d_jerk, double *d_pot);
 
@@ -139,7 +142,8 @@ int ht_force_direct_async(ht_ctx *ctx, int32_t n_active, const int32_t *active_i
 
 /* One block step in one call, asynchronously: the j-memory update of
  * ht_set_j_particles_async (n_upd rows, device arrays; n_upd = 0 skips it),
- * then ht_predict(t), then ht_force_async on active_ids (host array). */
+ * then ht_predict(t), then ht_force_async on active_ids (host array).  The
+ * update and the delivery of the work plan share one launch. */
 int ht_step_async(ht_ctx *ctx, int32_t n_upd, const int32_t *d_idx, const double *d_t0, const double *d_m,
                   const double *d_x, const double *d_v, const double *d_a, const double *d_jerk, double t,
                   int32_t n_active, const int32_t *active_ids, double *d_acc, double *d_jerk_out,
@@ -189,8 +193,10 @@ int ht_batch_create(ht_batch **out, int32_t device, void *stream, int32_t max_cl
 int ht_batch_destroy(ht_batch *b);
 
 /* Step 6 for several contexts: rows[k][0..n_rows[k]-1] (host) go to ctxs[k]
- * (indices distinct within a context).  One copy and one kernel for all;
- * asynchronous; the contexts must be predicted again afterwards. */
+ * (indices distinct within a context).  The rows are packed into pinned
+ * staging and one kernel reads them from there and writes every context's
+ * records (no separate copy); asynchronous; the contexts must be predicted
+ * again afterwards. */
 int ht_batch_update_async(ht_batch *b, int32_t n_ctx, ht_ctx *const *ctxs, const int32_t *n_rows,
                           const ht_row *const *rows);
 

@@ -89,6 +89,11 @@ def _load(path):
 def device_lib():
     global _dev
     if _dev is None:
+        # PyTorch brings its own HIP runtime.  Load it first so that the device
+        # library binds to that same runtime: streams and device pointers from
+        # torch are then valid in the library, and the process holds one HIP
+        # runtime instead of two.
+        import torch  # noqa: F401
         L = _load(_build.DEVICE_LIB)
         i, i64, d = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
         sig = {

@@ -63,6 +63,7 @@ constexpr int kWG = 256;      // threads per work-group
 constexpr int kRound = 256;   // list entries staged per round (one per thread)
 constexpr int kFold = 32;     // mixed form: FP32 pairs summed before folding into FP64
 constexpr int kOut = 7;       // acc[3], jerk[3], pot
+constexpr int kMaxBatch = 1024;   // clusters per batched launch
 
 // j-memory record of one particle or node: everything the predictor needs in
 // one 128-byte line, so a list-indexed gather touches a single cache line
@@ -509,6 +510,29 @@ __global__ __launch_bounds__(kWG) void predict_some_kernel(Desc c, const int32_t
     }
 }
 
+// One j-memory record from its parts (FP64 in, stored precision out).
+template <class P>
+__device__ __forceinline__ void store_rec(typename P::Rec* rec, int j, double t0, double m, const double* x,
+                                          const double* v, const double* a, const double* jerk) {
+    using S = typename P::Stored;
+    typename P::Rec r{};
+    r.x = x[0];
+    r.y = x[1];
+    r.z = x[2];
+    r.t0 = t0;
+    r.vx = v[0];
+    r.vy = v[1];
+    r.vz = v[2];
+    r.m = static_cast<S>(m);
+    r.ax = static_cast<S>(a[0]);
+    r.ay = static_cast<S>(a[1]);
+    r.az = static_cast<S>(a[2]);
+    r.jx = static_cast<S>(jerk[0]);
+    r.jy = static_cast<S>(jerk[1]);
+    r.jz = static_cast<S>(jerk[2]);
+    rec[j] = r;
+}
+
 // j-memory update (steps 1 and 6): rows [n][3] written into records.
 // idx == nullptr: row k goes to base + k.  t0 == nullptr: every t0 = t0_all.
 template <class P>
@@ -516,27 +540,50 @@ __global__ __launch_bounds__(kWG) void scatter_kernel(Desc dst, int n, const int
                                                       const double* t0, double t0_all, const double* m,
                                                       const double* x, const double* v, const double* a,
                                                       const double* jerk) {
-    using S = typename P::Stored;
     typename P::Rec* rec = static_cast<typename P::Rec*>(const_cast<void*>(dst.rec));
-    for (int k = blockIdx.x * kWG + threadIdx.x; k < n; k += gridDim.x * kWG) {
-        const int j = idx ? idx[k] : base + k;
-        typename P::Rec r{};
-        r.x = x[3 * k];
-        r.y = x[3 * k + 1];
-        r.z = x[3 * k + 2];
-        r.t0 = t0 ? t0[k] : t0_all;
-        r.vx = v[3 * k];
-        r.vy = v[3 * k + 1];
-        r.vz = v[3 * k + 2];
-        r.m = static_cast<S>(m[k]);
-        r.ax = static_cast<S>(a[3 * k]);
-        r.ay = static_cast<S>(a[3 * k + 1]);
-        r.az = static_cast<S>(a[3 * k + 2]);
-        r.jx = static_cast<S>(jerk[3 * k]);
-        r.jy = static_cast<S>(jerk[3 * k + 1]);
-        r.jz = static_cast<S>(jerk[3 * k + 2]);
-        rec[j] = r;
+    for (int k = blockIdx.x * kWG + threadIdx.x; k < n; k += gridDim.x * kWG)
+        store_rec<P>(rec, idx ? idx[k] : base + k, t0 ? t0[k] : t0_all, m[k], x + 3 * k, v + 3 * k, a + 3 * k,
+                     jerk + 3 * k);
+}
+
+// Read an 8-byte word of pinned host memory written by the host since the
+// last launch: a system-scope load, so no GPU cache can answer it with an
+// older copy of a reused staging slot.
+__device__ __forceinline__ uint64_t host_word(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// A packed work plan in pinned host memory and where it goes on the device.
+struct PlanCopy {
+    const uint64_t* src;
+    uint64_t* dst;
+    int64_t n8;        // 8-byte words
+    int copy_blocks;   // leading work-groups that copy; the rest scatter
+};
+
+// Update rows in device arrays (the form of ht_set_j_particles_async).
+struct DevRows {
+    int n;
+    const int32_t* idx;
+    const double *t0, *m, *x, *v, *a, *jerk;
+};
+
+// Everything a force launch needs before it, in one launch on the compute
+// queue: the work plan is pulled from pinned host memory by the first
+// copy_blocks work-groups (no copy-engine transfer and no cross-engine wait),
+// and the remaining work-groups write the step's update rows into records.
+template <class P>
+__global__ __launch_bounds__(kWG) void prep_kernel(PlanCopy pc, void* rec_base, DevRows u) {
+    if (static_cast<int>(blockIdx.x) < pc.copy_blocks) {
+        const int64_t stride = static_cast<int64_t>(pc.copy_blocks) * kWG;
+        for (int64_t k = blockIdx.x * static_cast<int64_t>(kWG) + threadIdx.x; k < pc.n8; k += stride)
+            pc.dst[k] = host_word(pc.src + k);
+        return;
     }
+    typename P::Rec* rec = static_cast<typename P::Rec*>(rec_base);
+    const int b = blockIdx.x - pc.copy_blocks, nb = gridDim.x - pc.copy_blocks;
+    for (int k = b * kWG + threadIdx.x; k < u.n; k += nb * kWG)
+        store_rec<P>(rec, u.idx[k], u.t0[k], u.m[k], u.x + 3 * k, u.v + 3 * k, u.a + 3 * k, u.jerk + 3 * k);
 }
 
 // Batched j-memory update: rows of several clusters in one launch.
@@ -554,31 +601,31 @@ __device__ __forceinline__ int find_upd(const UpdEntry* tab, int n_tab, int64_t 
     return lo;
 }
 
+// The launch table and the rows are read straight from the pinned host
+// staging slot (system-scope loads, see host_word), so an update costs one
+// launch and no copy; every work-group keeps the table in LDS.
 template <class P>
 __global__ __launch_bounds__(kWG) void scatter_rows_kernel(const UpdEntry* __restrict__ tab, int n_tab,
                                                            const ht_row* __restrict__ rows, int64_t total) {
-    using S = typename P::Stored;
+    static_assert(sizeof(ht_row) == 15 * 8, "ht_row is 15 words");
+    static_assert(sizeof(UpdEntry) == 16, "UpdEntry is 2 words");
+    __shared__ UpdEntry stab[kMaxBatch];
+    for (int q = threadIdx.x; q < 2 * n_tab; q += kWG)
+        reinterpret_cast<uint64_t*>(stab)[q] = host_word(reinterpret_cast<const uint64_t*>(tab) + q);
+    __syncthreads();
     for (int64_t r = blockIdx.x * static_cast<int64_t>(kWG) + threadIdx.x; r < total;
          r += static_cast<int64_t>(gridDim.x) * kWG) {
-        const int k = find_upd(tab, n_tab, r);
-        typename P::Rec* rec = static_cast<typename P::Rec*>(tab[k].rec);
-        const ht_row& w = rows[r];
-        typename P::Rec o{};
-        o.x = w.x[0];
-        o.y = w.x[1];
-        o.z = w.x[2];
-        o.t0 = w.t0;
-        o.vx = w.v[0];
-        o.vy = w.v[1];
-        o.vz = w.v[2];
-        o.m = static_cast<S>(w.m);
-        o.ax = static_cast<S>(w.a[0]);
-        o.ay = static_cast<S>(w.a[1]);
-        o.az = static_cast<S>(w.a[2]);
-        o.jx = static_cast<S>(w.jerk[0]);
-        o.jy = static_cast<S>(w.jerk[1]);
-        o.jz = static_cast<S>(w.jerk[2]);
-        rec[w.idx] = o;
+        const int k = find_upd(stab, n_tab, r);
+        const uint64_t* w = reinterpret_cast<const uint64_t*>(rows + r);
+        uint64_t raw[15];
+#pragma unroll
+        for (int q = 0; q < 15; ++q) raw[q] = host_word(w + q);
+        double f[14];
+#pragma unroll
+        for (int q = 0; q < 14; ++q) f[q] = __builtin_bit_cast(double, raw[q + 1]);
+        const int32_t idx = static_cast<int32_t>(static_cast<uint32_t>(raw[0]));
+        // f: t0, m, x[3], v[3], a[3], jerk[3]
+        store_rec<P>(static_cast<typename P::Rec*>(stab[k].rec), idx, f[0], f[1], f + 2, f + 5, f + 8, f + 11);
     }
 }
 
@@ -592,7 +639,6 @@ int ceil_log2(int64_t v) {
     return l;
 }
 
-constexpr int kMaxBatch = 1024;   // clusters per batched launch
 constexpr double kGatherCostDefault = 32.0;    // work-plan cost of one round's gather, in pairs per lane
 constexpr double kTargetItemsDefault = 2048.0; // work items a call is split towards (2 per resident slot)
 constexpr int kStageRows = 1 << 16;  // rows per host->device upload chunk
@@ -892,6 +938,26 @@ size_t pack_plan(ht_ctx* c, size_t at, int32_t n_active, const int32_t* ids, dou
     return pack_plan_into(c, c->plan_host(), c->ws + c->L.off_plan, at, n_active, ids, acc, jerk, pot, e);
 }
 
+// Pull `bytes` of a packed plan from pinned host memory into the device plan
+// region and write update rows `u`, in one prep_kernel launch.
+template <class P>
+int launch_prep(hipStream_t stream, const char* h_src, char* d_dst, size_t bytes, void* rec, const DevRows& u) {
+    PlanCopy pc{reinterpret_cast<const uint64_t*>(h_src), reinterpret_cast<uint64_t*>(d_dst),
+                static_cast<int64_t>((bytes + 7) / 8), 0};
+    pc.copy_blocks = static_cast<int>(std::min<int64_t>((pc.n8 + kWG - 1) / kWG, 2048));
+    const int scatter_blocks = u.n > 0 ? std::min((u.n + kWG - 1) / kWG, 65536) : 0;
+    if (pc.copy_blocks + scatter_blocks == 0) return HT_OK;
+    prep_kernel<P><<<pc.copy_blocks + scatter_blocks, kWG, 0, stream>>>(pc, rec, u);
+    HT_HIP(hipGetLastError());
+    return HT_OK;
+}
+
+int launch_prep_any(int precision, hipStream_t stream, const char* h_src, char* d_dst, size_t bytes, void* rec,
+                    const DevRows& u) {
+    if (precision == HT_PREC_FP64) return launch_prep<PrecFp64>(stream, h_src, d_dst, bytes, rec, u);
+    return launch_prep<PrecMixed>(stream, h_src, d_dst, bytes, rec, u);
+}
+
 // One host-to-device copy of the packed prefix [0, end) of the plan.
 int copy_plan(ht_ctx* c, size_t end) {
     HT_HIP(hipMemcpyAsync(c->ws + c->L.off_plan, c->plan_host(), end, hipMemcpyHostToDevice, c->stream));
@@ -948,6 +1014,70 @@ int read_timing(hipStream_t stream, Timing& tm, double* force_ms, int64_t* launc
     return HT_OK;
 }
 
+// Eager mode: predict the whole combined memory into the predicted records.
+int launch_predict_all(ht_ctx* c) {
+    const int total = c->n + c->n_nodes;
+    const Desc d = c->desc();
+    const int grid = std::min((total + kWG - 1) / kWG, 8192);
+    if (c->cfg.precision == HT_PREC_FP64)
+        predict_all_kernel<PrecFp64><<<grid, kWG, 0, c->stream>>>(d, total);
+    else
+        predict_all_kernel<PrecMixed><<<grid, kWG, 0, c->stream>>>(d, total);
+    HT_HIP(hipGetLastError());
+    return HT_OK;
+}
+
+// Arguments of a device-side j-memory update (ht_set_j_particles_async).
+int check_dev_rows(const ht_ctx* c, int32_t n, const int32_t* d_idx, const double* d_t0, const double* d_m,
+                   const double* d_x, const double* d_v, const double* d_a, const double* d_jerk) {
+    if (!c->have_particles) return fail(HT_ESTATE, "partial update before a full upload");
+    if (n < 0 || n > c->n) return fail(HT_EINVAL, "n = %d outside [0, N]", n);
+    const double* vec[] = {d_t0, d_m, d_x, d_v, d_a, d_jerk};
+    if (n > 0 && (!d_idx || !check_vectors(vec, 6))) return fail(HT_EINVAL, "NULL device array");
+    return HT_OK;
+}
+
+// Plan, pack and launch one force call on the context's stream.  Update rows
+// `u` (u.n == 0: none) are written into the records by the same launch that
+// delivers the plan; with `predict_eager` the whole combined memory is then
+// predicted (eager mode) before the force launch.
+int enqueue_step(ht_ctx* c, const DevRows& u, bool predict_eager, int32_t n_active, const int32_t* ids,
+                 double* d_acc, double* d_jerk, double* d_pot, bool direct) {
+    size_t end = 0;
+    if (n_active > 0) {
+        int rc = plan(c, n_active, ids, direct);
+        if (rc) return rc;
+        rc = c->slot_acquire();
+        if (rc) return rc;
+        Entry e{};
+        end = pack_plan(c, sizeof(Entry), n_active, ids, d_acc, d_jerk, d_pot, e);
+        e.first_item = 0;
+        e.first_rtile = 0;
+        std::memcpy(c->plan_host(), &e, sizeof(Entry));
+    } else {
+        c->last_pairs = 0;
+        c->last_items = 0;
+    }
+    int rc = launch_prep_any(c->cfg.precision, c->stream, c->plan_host(), c->ws + c->L.off_plan, end,
+                             c->ws + c->L.off_rec, u);
+    if (rc) return rc;
+    if (end > 0) {
+        rc = c->slot_release();   // the prep launch is the slot's last reader
+        if (rc) return rc;
+    }
+    if (predict_eager) {
+        rc = launch_predict_all(c);
+        if (rc) return rc;
+    }
+    if (n_active == 0) return HT_OK;
+    const Entry* d_tab = reinterpret_cast<const Entry*>(c->ws + c->L.off_plan);
+    const int64_t ni = static_cast<int64_t>(c->items.size()), nr = static_cast<int64_t>(c->rtiles.size());
+    const bool eager = c->cfg.predict_mode == HT_PREDICT_EAGER;
+    if (c->cfg.precision == HT_PREC_FP64)
+        return launch_force<PrecFp64>(c->stream, eager, c->tm, d_tab, 1, ni, nr, direct, c->last_pairs);
+    return launch_force<PrecMixed>(c->stream, eager, c->tm, d_tab, 1, ni, nr, direct, c->last_pairs);
+}
+
 int force_common(ht_ctx* c, int32_t n_active, const int32_t* ids, double* d_acc, double* d_jerk, double* d_pot,
                  bool direct) {
     if (!c) return fail(HT_EINVAL, "ctx is NULL");
@@ -956,29 +1086,8 @@ int force_common(ht_ctx* c, int32_t n_active, const int32_t* ids, double* d_acc,
     if (!c->predicted) return fail(HT_ESTATE, "ht_predict not called since the last j-memory change");
     int rc = validate_active(c, n_active, ids);
     if (rc) return rc;
-    if (n_active == 0) {
-        c->last_pairs = 0;
-        c->last_items = 0;
-        return HT_OK;
-    }
-    if (!d_acc || !d_jerk || !d_pot) return fail(HT_EINVAL, "output pointer is NULL");
-    rc = plan(c, n_active, ids, direct);
-    if (rc) return rc;
-    rc = c->slot_acquire();
-    if (rc) return rc;
-    Entry e{};
-    const size_t end = pack_plan(c, sizeof(Entry), n_active, ids, d_acc, d_jerk, d_pot, e);
-    e.first_item = 0;
-    e.first_rtile = 0;
-    std::memcpy(c->plan_host(), &e, sizeof(Entry));
-    rc = copy_plan(c, end);
-    if (rc) return rc;
-    const Entry* d_tab = reinterpret_cast<const Entry*>(c->ws + c->L.off_plan);
-    const int64_t ni = static_cast<int64_t>(c->items.size()), nr = static_cast<int64_t>(c->rtiles.size());
-    const bool eager = c->cfg.predict_mode == HT_PREDICT_EAGER;
-    if (c->cfg.precision == HT_PREC_FP64)
-        return launch_force<PrecFp64>(c->stream, eager, c->tm, d_tab, 1, ni, nr, direct, c->last_pairs);
-    return launch_force<PrecMixed>(c->stream, eager, c->tm, d_tab, 1, ni, nr, direct, c->last_pairs);
+    if (n_active > 0 && (!d_acc || !d_jerk || !d_pot)) return fail(HT_EINVAL, "output pointer is NULL");
+    return enqueue_step(c, DevRows{}, false, n_active, ids, d_acc, d_jerk, d_pot, direct);
 }
 
 int force_to_host(ht_ctx* c, int32_t n_active, const int32_t* ids, double* acc, double* jerk, double* pot,
@@ -1162,10 +1271,8 @@ int ht_set_j_particles(ht_ctx* c, int32_t n, const int32_t* idx, const double* t
 int ht_set_j_particles_async(ht_ctx* c, int32_t n, const int32_t* d_idx, const double* d_t0, const double* d_m,
                              const double* d_x, const double* d_v, const double* d_a, const double* d_jerk) {
     if (!c) return fail(HT_EINVAL, "ctx is NULL");
-    if (!c->have_particles) return fail(HT_ESTATE, "partial update before a full upload");
-    if (n < 0 || n > c->n) return fail(HT_EINVAL, "n = %d outside [0, N]", n);
-    const double* vec[] = {d_t0, d_m, d_x, d_v, d_a, d_jerk};
-    if (n > 0 && (!d_idx || !check_vectors(vec, 6))) return fail(HT_EINVAL, "NULL device array");
+    int rc = check_dev_rows(c, n, d_idx, d_t0, d_m, d_x, d_v, d_a, d_jerk);
+    if (rc) return rc;
     c->predicted = false;
     if (n == 0) return HT_OK;
     const Desc d = c->desc();
@@ -1239,14 +1346,8 @@ int ht_predict(ht_ctx* c, double t) {
     if (!std::isfinite(t)) return fail(HT_EINVAL, "t not finite");
     c->t_pred = t;
     if (c->cfg.predict_mode == HT_PREDICT_EAGER) {
-        const int total = c->n + c->n_nodes;
-        const Desc d = c->desc();
-        const int grid = std::min((total + kWG - 1) / kWG, 8192);
-        if (c->cfg.precision == HT_PREC_FP64)
-            predict_all_kernel<PrecFp64><<<grid, kWG, 0, c->stream>>>(d, total);
-        else
-            predict_all_kernel<PrecMixed><<<grid, kWG, 0, c->stream>>>(d, total);
-        HT_HIP(hipGetLastError());
+        int rc = launch_predict_all(c);
+        if (rc) return rc;
     }
     c->predicted = true;
     return HT_OK;
@@ -1288,13 +1389,17 @@ int ht_step_async(ht_ctx* c, int32_t n_upd, const int32_t* d_idx, const double* 
                   int32_t n_active, const int32_t* ids, double* d_acc, double* d_jerk_out, double* d_pot) {
     if (!c) return fail(HT_EINVAL, "ctx is NULL");
     if (!c->have_lists) return fail(HT_ESTATE, "interaction lists not set");
-    int rc = validate_active(c, n_active, ids);
+    int rc = check_dev_rows(c, n_upd, d_idx, d_t0, d_m, d_x, d_v, d_a, d_jerk);
     if (rc) return rc;
-    rc = ht_set_j_particles_async(c, n_upd, d_idx, d_t0, d_m, d_x, d_v, d_a, d_jerk);
+    rc = validate_active(c, n_active, ids);
     if (rc) return rc;
-    rc = ht_predict(c, t);
-    if (rc) return rc;
-    return force_common(c, n_active, ids, d_acc, d_jerk_out, d_pot, false);
+    if (!std::isfinite(t)) return fail(HT_EINVAL, "t not finite");
+    if (n_active > 0 && (!d_acc || !d_jerk_out || !d_pot)) return fail(HT_EINVAL, "output pointer is NULL");
+    c->t_pred = t;
+    c->predicted = true;
+    const DevRows u{n_upd, d_idx, d_t0, d_m, d_x, d_v, d_a, d_jerk};
+    return enqueue_step(c, u, c->cfg.predict_mode == HT_PREDICT_EAGER, n_active, ids, d_acc, d_jerk_out, d_pot,
+                        false);
 }
 
 int ht_get_predicted(ht_ctx* c, int32_t n, const int32_t* idx, double* xp, double* vp) {
@@ -1383,7 +1488,10 @@ int ht_force_batch_async(int32_t n_ctx, ht_ctx* const* ctxs, const int32_t* n_ac
     }
     if (tab.empty()) return HT_OK;
     std::memcpy(c0->plan_host(), tab.data(), tab.size() * sizeof(Entry));
-    rc = copy_plan(c0, end0);
+    rc = launch_prep_any(c0->cfg.precision, c0->stream, c0->plan_host(), c0->ws + c0->L.off_plan, end0, nullptr,
+                         DevRows{});
+    if (rc) return rc;
+    rc = c0->slot_release();
     if (rc) return rc;
     const Entry* d_tab = reinterpret_cast<const Entry*>(c0->ws + c0->L.off_plan);
     const int nt = static_cast<int>(tab.size());
@@ -1471,8 +1579,9 @@ int ht_batch_workspace_bytes(int32_t max_clusters, int64_t max_items, int64_t ma
                              size_t* bytes) {
     if (!bytes || !batch_args_ok(max_clusters, max_items, max_active, max_rows))
         return fail(HT_EINVAL, "invalid batch capacities");
-    *bytes = align_up(batch_plan_bytes(max_clusters, max_items, max_active)) +
-             align_up(batch_rows_bytes(max_clusters, max_rows));
+    // update rows are read by the scatter kernel from pinned host staging:
+    // the device workspace holds the work plan only
+    *bytes = align_up(batch_plan_bytes(max_clusters, max_items, max_active));
     return HT_OK;
 }
 
@@ -1560,7 +1669,6 @@ int ht_batch_update_async(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs, const
     int rc = ring_acquire(b->rows_ring);
     if (rc) return rc;
     char* hs = b->rows_ring.host();
-    char* dv = b->ws + b->plan_bytes;
     b->utab.clear();
     int64_t first = 0;
     const size_t rows_at = align_up(static_cast<size_t>(n_ctx) * sizeof(UpdEntry));
@@ -1572,20 +1680,16 @@ int ht_batch_update_async(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs, const
         first += n_rows[k];
     }
     std::memcpy(hs, b->utab.data(), b->utab.size() * sizeof(UpdEntry));
-    const size_t end = rows_at + static_cast<size_t>(total) * sizeof(ht_row);
-    HT_HIP(hipMemcpyAsync(dv, hs, end, hipMemcpyHostToDevice, b->stream));
-    rc = ring_release(b->rows_ring, b->stream);
-    if (rc) return rc;
     const int grid = static_cast<int>(std::min<int64_t>((total + kWG - 1) / kWG, 65536));
-    const UpdEntry* d_tab = reinterpret_cast<const UpdEntry*>(dv);
-    const ht_row* d_rows = reinterpret_cast<const ht_row*>(dv + rows_at);
+    const UpdEntry* h_tab = reinterpret_cast<const UpdEntry*>(hs);
+    const ht_row* h_rows = reinterpret_cast<const ht_row*>(hs + rows_at);
     const int nt = static_cast<int>(b->utab.size());
     if (ctxs[0]->cfg.precision == HT_PREC_FP64)
-        scatter_rows_kernel<PrecFp64><<<grid, kWG, 0, b->stream>>>(d_tab, nt, d_rows, total);
+        scatter_rows_kernel<PrecFp64><<<grid, kWG, 0, b->stream>>>(h_tab, nt, h_rows, total);
     else
-        scatter_rows_kernel<PrecMixed><<<grid, kWG, 0, b->stream>>>(d_tab, nt, d_rows, total);
+        scatter_rows_kernel<PrecMixed><<<grid, kWG, 0, b->stream>>>(h_tab, nt, h_rows, total);
     HT_HIP(hipGetLastError());
-    return HT_OK;
+    return ring_release(b->rows_ring, b->stream);   // the kernel is the slot's reader
 }
 
 int ht_batch_force_async(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs, const int32_t* n_active,
@@ -1641,7 +1745,8 @@ int ht_batch_force_async(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs, const 
     if (b->tab.empty()) return HT_OK;
     if (at > b->plan_bytes) return fail(HT_ERANGE, "batch plan over its capacity");
     std::memcpy(hs, b->tab.data(), b->tab.size() * sizeof(Entry));
-    HT_HIP(hipMemcpyAsync(dv, hs, at, hipMemcpyHostToDevice, b->stream));
+    rc = launch_prep_any(ctxs[0]->cfg.precision, b->stream, hs, dv, at, nullptr, DevRows{});
+    if (rc) return rc;
     rc = ring_release(b->plan_ring, b->stream);
     if (rc) return rc;
     b->last_pairs = pairs;
