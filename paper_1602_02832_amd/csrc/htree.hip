@@ -152,17 +152,22 @@ struct PrecMixed {
     static constexpr bool kMixed = true;
 };
 
+// One staged j of a round: predicted position and velocity, mass, combined
+// index.  Records (not one array per field) so that a thread reads an entry
+// with a few 16-byte LDS loads at immediate offsets from one address.
 template <class P>
-struct Lds {
-    double x[kRound], y[kRound], z[kRound];
-    typename P::Vel vx[kRound], vy[kRound], vz[kRound];
-    typename P::Stored m[kRound];
-    int32_t idx[kRound];
+struct alignas(16) JRec {
+    double x, y, z;
+    typename P::Vel vx, vy, vz;
+    typename P::Stored m;
+    int32_t idx;
 };
+static_assert(sizeof(JRec<PrecMixed>) == 48, "mixed staged record is 48 bytes");
+static_assert(sizeof(JRec<PrecFp64>) == 64, "FP64 staged record is 64 bytes");
 
 template <class P>
 union LdsAll {
-    Lds<P> j;
+    JRec<P> j[kRound];
     double red[kOut * kWG];
 };
 
@@ -220,14 +225,14 @@ struct Acc32 {
 };
 
 __device__ __forceinline__ void pair_fp64(double xi, double yi, double zi, double vxi, double vyi, double vzi,
-                                          int i, const Lds<PrecFp64>& L, int k, double eps2, Acc64& A) {
-    const double dx = L.x[k] - xi, dy = L.y[k] - yi, dz = L.z[k] - zi;
-    const double wx = L.vx[k] - vxi, wy = L.vy[k] - vyi, wz = L.vz[k] - vzi;
+                                          int i, const JRec<PrecFp64>& J, double eps2, Acc64& A) {
+    const double dx = J.x - xi, dy = J.y - yi, dz = J.z - zi;
+    const double wx = J.vx - vxi, wy = J.vy - vyi, wz = J.vz - vzi;
     const double s = dx * dx + dy * dy + dz * dz + eps2;
     double rinv = rsqrt(s);
-    rinv = (L.idx[k] == i) ? 0.0 : rinv;
+    rinv = (J.idx == i) ? 0.0 : rinv;
     const double rinv2 = rinv * rinv;
-    const double mr = L.m[k] * rinv;
+    const double mr = J.m * rinv;
     const double mr3 = mr * rinv2;
     const double alpha = 3.0 * (dx * wx + dy * wy + dz * wz) * rinv2;
     A.v[0] += mr3 * dx;
@@ -245,9 +250,9 @@ __device__ __forceinline__ void pair_fp64(double xi, double yi, double zi, doubl
 // s^-1/2, s^-3/2, the jerk terms and the potential, summed in FP32 over a few
 // pairs and folded into FP64 by the caller.
 __device__ __forceinline__ void pair_mixed(double xi, double yi, double zi, float vxi, float vyi, float vzi,
-                                           int i, const Lds<PrecMixed>& L, int k, double eps2, Acc64& A,
+                                           int i, const JRec<PrecMixed>& J, double eps2, Acc64& A,
                                            Acc32& B) {
-    const double dx = L.x[k] - xi, dy = L.y[k] - yi, dz = L.z[k] - zi;
+    const double dx = J.x - xi, dy = J.y - yi, dz = J.z - zi;
     const float s = static_cast<float>(fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2))));
     // v_rsq_f32 is good to about one ulp; one Newton step in residual form
     // (e = 1 - s y^2, y += y e / 2) makes it nearly correctly rounded, which
@@ -255,16 +260,16 @@ __device__ __forceinline__ void pair_mixed(double xi, double yi, double zi, floa
     float rinv = __builtin_amdgcn_rsqf(s);
     const float res = fmaf(-(s * rinv), rinv, 1.0f);
     rinv = fmaf(0.5f * rinv, res, rinv);
-    rinv = (L.idx[k] == i) ? 0.0f : rinv;
+    rinv = (J.idx == i) ? 0.0f : rinv;
     const float rinv2 = rinv * rinv;
-    const float mr = L.m[k] * rinv;
+    const float mr = J.m * rinv;
     const float mr3 = mr * rinv2;
     const double mr3d = static_cast<double>(mr3);
     A.v[0] = fma(mr3d, dx, A.v[0]);
     A.v[1] = fma(mr3d, dy, A.v[1]);
     A.v[2] = fma(mr3d, dz, A.v[2]);
     const float fx = static_cast<float>(dx), fy = static_cast<float>(dy), fz = static_cast<float>(dz);
-    const float wx = L.vx[k] - vxi, wy = L.vy[k] - vyi, wz = L.vz[k] - vzi;
+    const float wx = J.vx - vxi, wy = J.vy - vyi, wz = J.vz - vzi;
     const float alpha = 3.0f * fmaf(fz, wz, fmaf(fy, wy, fx * wx)) * rinv2;
     B.v[3] = fmaf(mr3, fmaf(-alpha, fx, wx), B.v[3]);
     B.v[4] = fmaf(mr3, fmaf(-alpha, fy, wy), B.v[4]);
@@ -315,14 +320,7 @@ __device__ __forceinline__ void run_item(const Desc& c, const Item& it, LdsAll<P
             typename P::Vel vxj, vyj, vzj;
             typename P::Stored mj;
             load_state<P, EAGER>(c, j, xj, yj, zj, vxj, vyj, vzj, mj);
-            lds.j.x[tid] = xj;
-            lds.j.y[tid] = yj;
-            lds.j.z[tid] = zj;
-            lds.j.vx[tid] = vxj;
-            lds.j.vy[tid] = vyj;
-            lds.j.vz[tid] = vzj;
-            lds.j.m[tid] = mj;
-            lds.j.idx[tid] = j;
+            lds.j[tid] = JRec<P>{xj, yj, zj, vxj, vyj, vzj, mj, j};
         }
         __syncthreads();
         if constexpr (P::kMixed) {
@@ -336,7 +334,7 @@ __device__ __forceinline__ void run_item(const Desc& c, const Item& it, LdsAll<P
                     for (int q = 3; q < kOut; ++q) B.v[q] = 0.0f;
 #pragma unroll 4
                     for (int u = 0; u < F; ++u)
-                        pair_mixed(xi, yi, zi, vxi, vyi, vzi, i, lds.j, stream + (f + u) * S, eps2, A, B);
+                        pair_mixed(xi, yi, zi, vxi, vyi, vzi, i, lds.j[stream + (f + u) * S], eps2, A, B);
 #pragma unroll
                     for (int q = 3; q < kOut; ++q) A.v[q] += static_cast<double>(B.v[q]);
                 }
@@ -349,7 +347,7 @@ __device__ __forceinline__ void run_item(const Desc& c, const Item& it, LdsAll<P
 #pragma unroll 1
                     for (int u = 0; u < F; ++u) {
                         const int k = stream + (f + u) * S;
-                        if (k < cnt) pair_mixed(xi, yi, zi, vxi, vyi, vzi, i, lds.j, k, eps2, A, B);
+                        if (k < cnt) pair_mixed(xi, yi, zi, vxi, vyi, vzi, i, lds.j[k], eps2, A, B);
                     }
 #pragma unroll
                     for (int q = 3; q < kOut; ++q) A.v[q] += static_cast<double>(B.v[q]);
@@ -359,10 +357,10 @@ __device__ __forceinline__ void run_item(const Desc& c, const Item& it, LdsAll<P
             const double eps2 = c.eps2;
             if (cnt == kRound) {
 #pragma unroll 4
-                for (int u = 0; u < PER; ++u) pair_fp64(xi, yi, zi, vxi, vyi, vzi, i, lds.j, stream + u * S, eps2, A);
+                for (int u = 0; u < PER; ++u) pair_fp64(xi, yi, zi, vxi, vyi, vzi, i, lds.j[stream + u * S], eps2, A);
             } else {
 #pragma unroll 1
-                for (int k = stream; k < cnt; k += S) pair_fp64(xi, yi, zi, vxi, vyi, vzi, i, lds.j, k, eps2, A);
+                for (int k = stream; k < cnt; k += S) pair_fp64(xi, yi, zi, vxi, vyi, vzi, i, lds.j[k], eps2, A);
             }
         }
     }
