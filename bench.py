@@ -12,8 +12,10 @@ resident in HBM:
   step k = j-memory update with the particles corrected at step k-1
            -> predict(t_k) -> force on the active set of step k
 
-W steps warm up; K steps are timed (wall clock between synchronisations, and
-HIP events on the library's stream for step latency and kernel time).  The
+W steps warm up; K steps are timed twice from the same snapshot: once with
+HIP events on the library's stream before every step (step latency) and
+around every force launch (kernel time), and once with nothing but the steps
+between two synchronisations, whose wall clock gives the throughput.  The
 same K steps are then run with the direct N^2 sum (the original Hermite
 scheme) and with the FP64 form.  The all-particle step at t = 1/512 is timed
 separately.
@@ -131,29 +133,42 @@ def device_updates(torch, rec):
     return out
 
 
-def replay(torch, B, rec, ctx, stream, warmup, steps, direct=False):
-    """Replay recorded steps; returns timing dict for the last `steps` steps."""
+def replay(torch, B, rec, ctx, stream, warmup, steps, direct=False, instrument=True):
+    """Replay recorded steps; returns a timing dict for the last `steps` steps.
+
+    instrument=False: nothing but the steps between the two synchronisations
+    (the throughput figure).  instrument=True: a HIP event on the stream
+    before every step (step latency) and kernel timing events around every
+    force launch (kernel time), at some cost in throughput."""
     dev_upd = device_updates(torch, rec)
     kmax = max(a.size for _, a, _ in rec.steps)
     acc = torch.empty((kmax, 3), dtype=torch.float64, device="cuda")
     jrk = torch.empty((kmax, 3), dtype=torch.float64, device="cuda")
     pot = torch.empty(kmax, dtype=torch.float64, device="cuda")
-    fn = ctx.force_direct_async if direct else ctx.force_async
+    out_ptrs = (acc.data_ptr(), jrk.data_ptr(), pot.data_ptr())
+    # device addresses of every step's update rows, taken before the timed loop
+    upd_ptrs = [None] + [(u[0].shape[0],) + tuple(x.data_ptr() for x in u) for u in dev_upd[:-1]]
 
     def run_step(k):
         t, act, _ = rec.steps[k]
-        upd = None if k == 0 else (dev_upd[k - 1][0].shape[0],) + dev_upd[k - 1]
+        upd = upd_ptrs[k]
         if direct:
             if upd is not None:
                 ctx.set_j_particles_async(*upd)
             ctx.predict(t)
-            fn(act, acc, jrk, pot)
+            ctx.force_direct_async(act, *out_ptrs)
         else:
-            ctx.step_async(upd, t, act, acc, jrk, pot)
+            ctx.step_async(upd, t, act, *out_ptrs)
 
     for k in range(warmup):
         run_step(k)
     torch.cuda.synchronize()
+    if not instrument:
+        t_wall = time.perf_counter()
+        for k in range(warmup, warmup + steps):
+            run_step(k)
+        torch.cuda.synchronize()
+        return dict(wall_s=time.perf_counter() - t_wall)
     ctx.set_timing(True)
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     pairs = 0
@@ -175,6 +190,25 @@ def replay(torch, B, rec, ctx, stream, warmup, steps, direct=False):
     lat = np.array([evs[q].elapsed_time(evs[q + 1]) for q in range(steps)])
     return dict(wall_s=wall, pairs=pairs, kernel_ms=kms, launches=launches, kernel_pairs=kpairs, lat_ms=lat,
                 per_step=per_step)
+
+
+def tile_mix(rec, warmup):
+    """Per recorded step: pairs by i-tile size T (active particles of a group
+    in tiles of up to 256, T the next power of two)."""
+    gf, lo = rec.snap["lists"][0], rec.snap["lists"][1]
+    out = []
+    for _, act, _ in rec.steps[warmup:]:
+        g = np.searchsorted(gf, act, side="right") - 1
+        ug, cnt = np.unique(g, return_counts=True)
+        mix = {}
+        for gg, c in zip(ug, cnt):
+            ln = int(lo[gg + 1] - lo[gg])
+            for t0 in range(0, int(c), 256):
+                ni = min(256, int(c) - t0)
+                T = 1 << (ni - 1).bit_length()
+                mix[T] = mix.get(T, 0) + ni * ln
+        out.append({str(k): v for k, v in sorted(mix.items())})
+    return out
 
 
 def cpu_baseline(W, cfg, seconds):
@@ -393,28 +427,35 @@ def main():
 
     stream = torch.cuda.Stream()
     sh = stream.cuda_stream
-    out = {}
+    def leg(precision, direct=False):
+        """The recorded steps once instrumented (latency, kernel time, pairs)
+        and once clean (throughput), each from a fresh copy of the snapshot."""
+        ctx = make_ctx(B, rec.snap, rec.n, precision, cfg.eps2, sh)
+        r = replay(torch, B, rec, ctx, stream, args.warmup, args.steps, direct=direct, instrument=True)
+        ctx.close()
+        ctx = make_ctx(B, rec.snap, rec.n, precision, cfg.eps2, sh)
+        r["instrumented_wall_s"] = r["wall_s"]
+        r["wall_s"] = replay(torch, B, rec, ctx, stream, args.warmup, args.steps, direct=direct,
+                             instrument=False)["wall_s"]
+        ctx.close()
+        return r
+
     # ---- mixed tree (the headline)
-    ctx = make_ctx(B, rec.snap, rec.n, "mixed", cfg.eps2, sh)
-    mixed = replay(torch, B, rec, ctx, stream, args.warmup, args.steps)
+    mixed = leg("mixed")
     log(f"mixed tree: {mixed['pairs'] / mixed['wall_s']:.4g} pairs/s, {1e3 * mixed['wall_s'] / args.steps:.3f} "
-        f"ms/step, kernel {mixed['kernel_ms']:.3f} ms over {mixed['launches']} launches")
-    ctx.close()
+        f"ms/step ({1e3 * mixed['instrumented_wall_s'] / args.steps:.3f} instrumented), kernel "
+        f"{mixed['kernel_ms']:.3f} ms over {mixed['launches']} launches")
     # ---- direct N^2 on the same steps
     direct = None
     if not args.no_direct:
-        ctx = make_ctx(B, rec.snap, rec.n, "mixed", cfg.eps2, sh)
-        direct = replay(torch, B, rec, ctx, stream, args.warmup, args.steps, direct=True)
+        direct = leg("mixed", direct=True)
         log(f"mixed direct: {direct['pairs'] / direct['wall_s']:.4g} pairs/s, "
             f"{1e3 * direct['wall_s'] / args.steps:.3f} ms/step")
-        ctx.close()
     # ---- FP64 tree
     fp64 = None
     if not args.no_fp64:
-        ctx = make_ctx(B, rec.snap, rec.n, "fp64", cfg.eps2, sh)
-        fp64 = replay(torch, B, rec, ctx, stream, args.warmup, args.steps)
+        fp64 = leg("fp64")
         log(f"fp64 tree: {fp64['pairs'] / fp64['wall_s']:.4g} pairs/s, {1e3 * fp64['wall_s'] / args.steps:.3f} ms/step")
-        ctx.close()
     # ---- the all-particle step at t = dt_tree
     all_active = None
     if not args.no_all_active:
@@ -451,7 +492,8 @@ def main():
 
     K = args.steps
     if args.dump_steps:
-        dump = {"mixed": [list(r) + [float(t)] for r, t in zip(mixed["per_step"], mixed["lat_ms"])]}
+        dump = {"mixed": [list(r) + [float(t)] for r, t in zip(mixed["per_step"], mixed["lat_ms"])],
+                "tile_pairs": tile_mix(rec, args.warmup)}
         if direct is not None:
             dump["direct"] = [list(r) + [float(t)] for r, t in zip(direct["per_step"], direct["lat_ms"])]
         if fp64 is not None:
@@ -471,6 +513,7 @@ def main():
         "steps": K,
         "warmup": args.warmup,
         "ms_per_step": 1e3 * mixed["wall_s"] / K,
+        "instrumented_ms_per_step": 1e3 * mixed["instrumented_wall_s"] / K,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

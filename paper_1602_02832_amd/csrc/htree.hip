@@ -60,7 +60,11 @@ int fail(int code, const char* fmt, ...) {
 // ------------------------------------------------------------------------------------------------
 // device data structures
 constexpr int kWG = 256;      // threads per work-group
-constexpr int kRound = 256;   // list entries staged per round (one per thread)
+constexpr int kRound = 256;   // list entries staged per round and entry multiple (one per thread)
+// Small tiles give a thread few pairs per staged entry, so their rounds are
+// latency-bound: for T <= 8 every thread gathers two entries per round.
+__host__ __device__ constexpr int round_mult(int T) { return T <= 8 ? 2 : 1; }
+constexpr int kRoundMax = 2 * kRound;
 constexpr int kFold = 32;     // mixed form: FP32 pairs summed before folding into FP64
 constexpr int kOut = 7;       // acc[3], jerk[3], pot
 constexpr int kMaxBatch = 1024;   // clusters per batched launch
@@ -167,7 +171,7 @@ static_assert(sizeof(JRec<PrecFp64>) == 64, "FP64 staged record is 64 bytes");
 
 template <class P>
 union LdsAll {
-    JRec<P> j[kRound];
+    JRec<P> j[kRoundMax];
     double red[kOut * kWG];
 };
 
@@ -292,8 +296,10 @@ __device__ __forceinline__ void write_out(const Desc& c, int64_t o, const double
 // one work item with tile size T
 template <class P, bool EAGER, bool DIRECT, int T>
 __device__ __forceinline__ void run_item(const Desc& c, const Item& it, LdsAll<P>& lds) {
+    constexpr int G = round_mult(T);    // entries gathered per thread and round
+    constexpr int R = kRound * G;       // entries per round
     constexpr int S = kWG / T;          // j-streams
-    constexpr int PER = kRound / S;     // pairs per thread in a full round (= T)
+    constexpr int PER = R / S;          // pairs per thread in a full round (= G T)
     const int tid = threadIdx.x;
     const int islot = tid & (T - 1);
     const int stream = tid / T;
@@ -309,53 +315,76 @@ __device__ __forceinline__ void run_item(const Desc& c, const Item& it, LdsAll<P
     Acc64 A;
 #pragma unroll
     for (int q = 0; q < kOut; ++q) A.v[q] = 0.0;
+    // Mixed form: FP32 partials of the jerk and potential, folded into A
+    // every kFold pairs of this thread (across rounds when a round gives a
+    // thread fewer than kFold pairs) and at the end of the item.
+    Acc32 B;
+#pragma unroll
+    for (int q = 3; q < kOut; ++q) B.v[q] = 0.0f;
+    auto fold = [&]() {
+#pragma unroll
+        for (int q = 3; q < kOut; ++q) {
+            A.v[q] += static_cast<double>(B.v[q]);
+            B.v[q] = 0.0f;
+        }
+    };
+    int since_fold = 0;   // full rounds since the last fold (PER < kFold)
 
-    for (int64_t base = it.j_begin; base < it.j_end; base += kRound) {
+    for (int64_t base = it.j_begin; base < it.j_end; base += R) {
         const int64_t rest = it.j_end - base;
-        const int cnt = rest < kRound ? static_cast<int>(rest) : kRound;
+        const int cnt = rest < R ? static_cast<int>(rest) : R;
         __syncthreads();  // the previous round is no longer read
-        if (tid < cnt) {
-            const int j = DIRECT ? static_cast<int>(base + tid) : c.entries[base + tid];
-            double xj, yj, zj;
-            typename P::Vel vxj, vyj, vzj;
-            typename P::Stored mj;
-            load_state<P, EAGER>(c, j, xj, yj, zj, vxj, vyj, vzj, mj);
-            lds.j[tid] = JRec<P>{xj, yj, zj, vxj, vyj, vzj, mj, j};
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int e = tid + g * kWG;
+            if (e < cnt) {
+                const int j = DIRECT ? static_cast<int>(base + e) : c.entries[base + e];
+                double xj, yj, zj;
+                typename P::Vel vxj, vyj, vzj;
+                typename P::Stored mj;
+                load_state<P, EAGER>(c, j, xj, yj, zj, vxj, vyj, vzj, mj);
+                lds.j[e] = JRec<P>{xj, yj, zj, vxj, vyj, vzj, mj, j};
+            }
         }
         __syncthreads();
         if constexpr (P::kMixed) {
             const double eps2 = c.eps2;
-            constexpr int F = PER < kFold ? PER : kFold;
-            if (cnt == kRound) {
+            if (cnt == R) {
+                if constexpr (PER >= kFold) {
 #pragma unroll 1
-                for (int f = 0; f < PER; f += F) {
-                    Acc32 B;
-#pragma unroll
-                    for (int q = 3; q < kOut; ++q) B.v[q] = 0.0f;
+                    for (int f = 0; f < PER; f += kFold) {
 #pragma unroll 4
-                    for (int u = 0; u < F; ++u)
-                        pair_mixed(xi, yi, zi, vxi, vyi, vzi, i, lds.j[stream + (f + u) * S], eps2, A, B);
-#pragma unroll
-                    for (int q = 3; q < kOut; ++q) A.v[q] += static_cast<double>(B.v[q]);
+                        for (int u = 0; u < kFold; ++u)
+                            pair_mixed(xi, yi, zi, vxi, vyi, vzi, i, lds.j[stream + (f + u) * S], eps2, A, B);
+                        fold();
+                    }
+                } else {
+#pragma unroll 4
+                    for (int u = 0; u < PER; ++u)
+                        pair_mixed(xi, yi, zi, vxi, vyi, vzi, i, lds.j[stream + u * S], eps2, A, B);
+                    if (++since_fold == kFold / PER) {
+                        fold();
+                        since_fold = 0;
+                    }
                 }
             } else {
+                // the last, partial round of the item: at most PER pairs per thread
+                fold();
+                since_fold = 0;
+                constexpr int F = PER < kFold ? PER : kFold;
 #pragma unroll 1
                 for (int f = 0; f * S < cnt; f += F) {
-                    Acc32 B;
-#pragma unroll
-                    for (int q = 3; q < kOut; ++q) B.v[q] = 0.0f;
 #pragma unroll 1
                     for (int u = 0; u < F; ++u) {
                         const int k = stream + (f + u) * S;
                         if (k < cnt) pair_mixed(xi, yi, zi, vxi, vyi, vzi, i, lds.j[k], eps2, A, B);
                     }
-#pragma unroll
-                    for (int q = 3; q < kOut; ++q) A.v[q] += static_cast<double>(B.v[q]);
+                    fold();
                 }
             }
         } else {
             const double eps2 = c.eps2;
-            if (cnt == kRound) {
+            if (cnt == R) {
 #pragma unroll 4
                 for (int u = 0; u < PER; ++u) pair_fp64(xi, yi, zi, vxi, vyi, vzi, i, lds.j[stream + u * S], eps2, A);
             } else {
@@ -365,10 +394,34 @@ __device__ __forceinline__ void run_item(const Desc& c, const Item& it, LdsAll<P
         }
     }
 
-    // reduce the S j-streams of each i-slot: a fixed pairwise tree in LDS
-    // (stream r += stream r + h for h = S/2, S/4, ..., 1), so the order never
-    // depends on timing and the depth is log2(S)
-    if constexpr (S > 1) {
+    if constexpr (P::kMixed) fold();
+
+    // Reduce the S j-streams of each i-slot in a fixed order, so results never
+    // depend on timing.  T < 64: the 64 / T streams of a wave first, by a
+    // pairwise tree of lane shuffles (stream s += stream s + h, h = 32/T, ...,
+    // 1), then the four waves in order through LDS.  T >= 64 (at most four
+    // streams, whole waves each): a pairwise tree in LDS.
+    if constexpr (T < 64) {
+        constexpr int W = 64 / T;   // streams per wave
+#pragma unroll
+        for (int h = W / 2; h >= 1; h /= 2) {
+#pragma unroll
+            for (int q = 0; q < kOut; ++q) A.v[q] += __shfl_down(A.v[q], h * T, 64);
+        }
+        const int lane = tid & 63, wave = tid >> 6;
+        __syncthreads();
+        if (lane < T) {
+#pragma unroll
+            for (int q = 0; q < kOut; ++q) lds.red[q * kWG + wave * T + lane] = A.v[q];
+        }
+        __syncthreads();
+        if (tid < T) {
+#pragma unroll
+            for (int q = 0; q < kOut; ++q)
+                A.v[q] = ((lds.red[q * kWG + islot] + lds.red[q * kWG + T + islot]) + lds.red[q * kWG + 2 * T + islot]) +
+                         lds.red[q * kWG + 3 * T + islot];
+        }
+    } else if constexpr (S > 1) {
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < kOut; ++q) lds.red[q * kWG + tid] = A.v[q];
@@ -737,9 +790,12 @@ struct ht_ctx {
     // work-plan tuning (see plan())
     double gather_cost = kGatherCostDefault;
     double target_items = kTargetItemsDefault;
+    int8_t first_tile[257] = {};   // least-cost tiling for the gather cost (tile_table)
     // scratch for planning
     std::vector<Item> items;
     std::vector<RTile> rtiles;
+    std::vector<Item> sort_items;
+    std::vector<uint32_t> sort_keys, sort_count;
 
     template <class T>
     T* dev(size_t off) const { return reinterpret_cast<T*>(ws + off); }
@@ -809,11 +865,14 @@ bool check_vectors(const double* const* ptrs, int count) {
 }
 
 // Work plan of one force call.  The active particles of one group (ids are
-// strictly increasing, groups are contiguous ranges) form i-tiles of up to 256
-// with T the next power of two.  A tile's cost is modelled as
-//   rounds * (kGatherCost + T),  rounds = ceil(list length / 256),
+// strictly increasing, groups are contiguous ranges) form i-tiles of T = 1,
+// 2, 4, ..., 256 slots.  A tile's cost is modelled as
+//   rounds * (gather_cost + T),  rounds = ceil(list length / 256),
 // i.e. per round of 256 entries one gather-and-predict (worth about
-// kGatherCost pairs of arithmetic per lane) plus T pairs per lane.  Tiles are
+// gather_cost pairs of arithmetic per lane) plus T pairs per lane, idle slots
+// included.  A group's n active particles are covered by the tiles of least
+// total cost: 140 becomes 128 + 16 (cost 2 gc + 144) rather than one part-
+// filled 256 (gc + 256), while 3 stays one tile of 4.  Tiles are
 // only split (into list ranges whose partials are summed afterwards) when the
 // call has too little work to fill the chip: each tile gets about
 // cost / (total / target_items) items.  Items are then ordered by decreasing
@@ -828,6 +887,31 @@ struct Tile {
     int tl;
     double cost;
 };
+
+// first_tile[r] (r = 1..256): log2 of the first tile in the least-cost cover
+// of r active particles by power-of-two tiles, the cost of a tile being
+// gather_cost + T.  Either one tile of the next power of two holds all r, or
+// a full tile of the largest power of two below r is followed by the best
+// cover of the rest.
+void tile_table(double gather_cost, int8_t* first_tile) {
+    double best[257];
+    best[0] = 0.0;
+    for (int r = 1; r <= 256; ++r) {
+        const int up = ceil_log2(r);
+        double b = gather_cost + static_cast<double>(1 << up);
+        int8_t f = static_cast<int8_t>(up);
+        const int down = (1 << up) == r ? up : up - 1;
+        if ((1 << down) < r) {
+            const double alt = gather_cost + static_cast<double>(1 << down) + best[r - (1 << down)];
+            if (alt < b) {
+                b = alt;
+                f = static_cast<int8_t>(down);
+            }
+        }
+        best[r] = b;
+        first_tile[r] = f;
+    }
+}
 
 int plan(ht_ctx* c, int32_t n_active, const int32_t* ids, bool direct) {
     auto& items = c->items;
@@ -848,14 +932,16 @@ int plan(ht_ctx* c, int32_t n_active, const int32_t* ids, bool direct) {
         }
         int32_t e = k;
         while (e < n_active && ids[e] < ge) ++e;
-        for (int32_t tb = k; tb < e; tb += 256) {
-            const int32_t ni = std::min<int32_t>(256, e - tb);
-            const int tl = ceil_log2(ni);
+        for (int32_t tb = k; tb < e;) {
+            const int32_t r = e - tb;
+            const int tl = r >= 256 ? 8 : c->first_tile[r];
+            const int32_t ni = std::min<int32_t>(r, 1 << tl);
             const int64_t rounds = (je - jb + kRound - 1) / kRound;
             const double cost = static_cast<double>(rounds) * (c->gather_cost + static_cast<double>(1 << tl));
             tiles.push_back(Tile{jb, je, tb, ni, tl, cost});
             total += cost;
             pairs += static_cast<int64_t>(ni) * (je - jb);
+            tb += ni;
         }
         k = e;
     }
@@ -865,14 +951,15 @@ int plan(ht_ctx* c, int32_t n_active, const int32_t* ids, bool direct) {
         rtiles.clear();
         int64_t pslots = 0;
         for (const Tile& t : tiles) {
-            const int64_t rounds = (t.je - t.jb + kRound - 1) / kRound;
+            const int64_t rsz = static_cast<int64_t>(kRound) * round_mult(1 << t.tl);   // the kernel's round
+            const int64_t rounds = (t.je - t.jb + rsz - 1) / rsz;
             int64_t ns = attempt > 60 ? 1 : static_cast<int64_t>(std::ceil(t.cost / quantum));
             ns = std::max<int64_t>(1, std::min<int64_t>(ns, rounds));
             if (ns == 1) {
                 items.push_back(Item{t.jb, t.je, -1, t.tb, static_cast<int16_t>(t.ni), static_cast<int16_t>(t.tl)});
                 continue;
             }
-            const int64_t per = (rounds + ns - 1) / ns * kRound;   // entries per split, whole rounds
+            const int64_t per = (rounds + ns - 1) / ns * rsz;   // entries per split, whole rounds
             int32_t nsu = 0;
             for (int64_t b = t.jb; b < t.je; b += per, ++nsu)
                 items.push_back(Item{b, std::min(t.je, b + per), pslots + static_cast<int64_t>(nsu) * t.ni, t.tb,
@@ -884,13 +971,33 @@ int plan(ht_ctx* c, int32_t n_active, const int32_t* ids, bool direct) {
         if (attempt > 60) return fail(HT_ERANGE, "work plan exceeds the context's item capacity");
         quantum *= 2.0;
     }
-    // longest first; ties keep plan order so the plan stays deterministic
-    auto cost_of = [c](const Item& it) {
-        return static_cast<double>((it.j_end - it.j_begin + kRound - 1) / kRound) *
-               (c->gather_cost + static_cast<double>(1 << it.tile_log2));
-    };
-    std::stable_sort(items.begin(), items.end(),
-                     [&](const Item& a, const Item& b) { return cost_of(a) > cost_of(b); });
+    // Longest first, to 1/8 of an octave: a counting sort on the sign,
+    // exponent and top three mantissa bits of the modelled cost (monotone in
+    // the cost for positive doubles), equal keys in plan order, so the order
+    // is deterministic and linear in the number of items.
+    auto& keys = c->sort_keys;
+    keys.resize(items.size());
+    uint32_t kmin = UINT32_MAX, kmax = 0;
+    for (size_t q = 0; q < items.size(); ++q) {
+        const Item& it = items[q];
+        const double cost = static_cast<double>((it.j_end - it.j_begin + kRound - 1) / kRound) *
+                            (c->gather_cost + static_cast<double>(1 << it.tile_log2));
+        uint64_t bits;
+        std::memcpy(&bits, &cost, 8);
+        keys[q] = static_cast<uint32_t>(bits >> 49);
+        kmin = std::min(kmin, keys[q]);
+        kmax = std::max(kmax, keys[q]);
+    }
+    if (items.size() > 1 && kmax > kmin) {
+        auto& count = c->sort_count;
+        count.assign(static_cast<size_t>(kmax - kmin) + 2, 0);
+        for (uint32_t k : keys) ++count[kmax - k + 1];   // bucket 0 = largest cost
+        for (size_t b = 1; b < count.size(); ++b) count[b] += count[b - 1];
+        auto& out = c->sort_items;
+        out.resize(items.size());
+        for (size_t q = 0; q < items.size(); ++q) out[count[kmax - keys[q]]++] = items[q];
+        items.swap(out);
+    }
     c->last_pairs = pairs;
     c->last_items = static_cast<int32_t>(items.size());
     return HT_OK;
@@ -1218,6 +1325,7 @@ int ht_create(ht_ctx** out, const ht_config* cfg, void* d_workspace, size_t work
         if (hipEventCreateWithFlags(&c->slot_free[k], hipEventDisableTiming) != hipSuccess)
             return cleanup(fail(HT_EHIP, "hipEventCreate failed"));
     c->items.reserve(1024);
+    tile_table(c->gather_cost, c->first_tile);
     *out = c;
     return HT_OK;
 }
@@ -1822,6 +1930,7 @@ int ht_set_tuning(ht_ctx* c, double gather_cost, double target_items) {
         return fail(HT_EINVAL, "tuning values out of range");
     c->gather_cost = gather_cost;
     c->target_items = target_items;
+    tile_table(gather_cost, c->first_tile);
     return HT_OK;
 }
 
