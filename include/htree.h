@@ -214,12 +214,13 @@ int ht_batch_last_stats(const ht_batch *b, int64_t *pairs, int32_t *work_items);
 /* Block until the context's queued work has finished. */
 int ht_sync(ht_ctx *ctx);
 
-/* Work-plan tuning.  The active particles of a group form i-tiles of T <= 256
- * particles; a tile over a list of L entries is costed rounds*(gather_cost+T)
- * with rounds = ceil(L/256), and tiles are split into list ranges only while
- * the call has fewer than about target_items items.  Defaults: 32, 2048.
- * Results stay within the stated tolerances for any values (only the
- * summation order changes). */
+/* Work-plan tuning.  The active particles of a group are covered by i-tiles
+ * of T = 1, 2, 4, ..., 256 slots; a tile over a list of L entries is costed
+ * rounds*(gather_cost+T) with rounds = ceil(L/256), a group gets the tiles of
+ * least total cost, and tiles are split into list ranges only while the call
+ * has fewer than about target_items items.  Defaults: 12, 2048.  Results
+ * stay within the stated tolerances for any values (only the summation order
+ * changes). */
 int ht_set_tuning(ht_ctx *ctx, double gather_cost, double target_items);
 
 /* Pair interactions the last force call summed (list entries x active

@@ -313,7 +313,7 @@ class Context:
     def sync(self):
         _check(device_lib().ht_sync(self._h))
 
-    def set_tuning(self, gather_cost=32.0, target_items=2048.0):
+    def set_tuning(self, gather_cost=12.0, target_items=2048.0):
         _check(device_lib().ht_set_tuning(self._h, float(gather_cost), float(target_items)))
 
     def set_timing(self, enable=True):

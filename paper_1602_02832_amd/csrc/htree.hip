@@ -690,7 +690,7 @@ int ceil_log2(int64_t v) {
     return l;
 }
 
-constexpr double kGatherCostDefault = 32.0;    // work-plan cost of one round's gather, in pairs per lane
+constexpr double kGatherCostDefault = 12.0;    // work-plan cost of one round's gather, in pairs per lane (measured best 8-16)
 constexpr double kTargetItemsDefault = 2048.0; // work items a call is split towards (2 per resident slot)
 constexpr int kStageRows = 1 << 16;  // rows per host->device upload chunk
 
@@ -1166,10 +1166,6 @@ int enqueue_step(ht_ctx* c, const DevRows& u, bool predict_eager, int32_t n_acti
     int rc = launch_prep_any(c->cfg.precision, c->stream, c->plan_host(), c->ws + c->L.off_plan, end,
                              c->ws + c->L.off_rec, u);
     if (rc) return rc;
-    if (end > 0) {
-        rc = c->slot_release();   // the prep launch is the slot's last reader
-        if (rc) return rc;
-    }
     if (predict_eager) {
         rc = launch_predict_all(c);
         if (rc) return rc;
@@ -1178,9 +1174,13 @@ int enqueue_step(ht_ctx* c, const DevRows& u, bool predict_eager, int32_t n_acti
     const Entry* d_tab = reinterpret_cast<const Entry*>(c->ws + c->L.off_plan);
     const int64_t ni = static_cast<int64_t>(c->items.size()), nr = static_cast<int64_t>(c->rtiles.size());
     const bool eager = c->cfg.predict_mode == HT_PREDICT_EAGER;
-    if (c->cfg.precision == HT_PREC_FP64)
-        return launch_force<PrecFp64>(c->stream, eager, c->tm, d_tab, 1, ni, nr, direct, c->last_pairs);
-    return launch_force<PrecMixed>(c->stream, eager, c->tm, d_tab, 1, ni, nr, direct, c->last_pairs);
+    rc = c->cfg.precision == HT_PREC_FP64
+             ? launch_force<PrecFp64>(c->stream, eager, c->tm, d_tab, 1, ni, nr, direct, c->last_pairs)
+             : launch_force<PrecMixed>(c->stream, eager, c->tm, d_tab, 1, ni, nr, direct, c->last_pairs);
+    if (rc) return rc;
+    // The prep launch is the slot's only reader; marking the slot after the
+    // whole step keeps the step's launches back to back on the host.
+    return c->slot_release();
 }
 
 int force_common(ht_ctx* c, int32_t n_active, const int32_t* ids, double* d_acc, double* d_jerk, double* d_pot,
