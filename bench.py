@@ -49,13 +49,19 @@ METRIC_ENSEMBLE = "batched ensemble (64 Plummer clusters, N 4096-65536): Hermite
 # only for the kernel source it was taken on: any change to it makes the
 # figure null until the counters are taken again.
 TRAFFIC = {
-    "kernel_source_sha256": None,
-    "fetch_bytes_per_launch": None,
-    "write_bytes_per_launch": None,
-    "fetch_scale": None,
-    "write_scale": None,
+    "kernel_source_sha256": "7d4ef6ffea280fa82d034fc2a8b3d2c5a46a368d8a833f019ccbdfdd3c234368",
+    "fetch_bytes_per_launch": 1.441e8,     # FETCH_SIZE 70376.6 KiB x 2.000
+    "write_bytes_per_launch": 5.465e5,     # WRITE_SIZE 533.7 KiB x 1.000
+    "fetch_scale": 2.000,                  # 1 GiB read by a plain copy reads 524295 KiB
+    "write_scale": 1.000,                  # 1 GiB written reads 1048576 KiB
     "profile": "profiles/force_kernel_mixed_plummer1m_traffic.md",
 }
+# Bytes the force evaluation needs at least, per launch: every distinct
+# j-entry of the active groups' lists once (the mixed record's payload: x, y,
+# z, t0, vx, vy, vz in FP64, m, a, jerk in FP32), each active group's list
+# indices once, and per active particle its id and outputs (acc, jerk, pot).
+REC_PAYLOAD_BYTES = 7 * 8 + 7 * 4
+OUT_BYTES = 7 * 8
 METRIC_SERVED = "served stream of cluster runs (N 1024-262144, 256 block steps each): p50/p99 engine-step latency at 80% load"
 
 
@@ -190,6 +196,23 @@ def replay(torch, B, rec, ctx, stream, warmup, steps, direct=False, instrument=T
     lat = np.array([evs[q].elapsed_time(evs[q + 1]) for q in range(steps)])
     return dict(wall_s=wall, pairs=pairs, kernel_ms=kms, launches=launches, kernel_pairs=kpairs, lat_ms=lat,
                 per_step=per_step)
+
+
+def algorithmic_bytes(rec, warmup):
+    """Mean over the timed steps of the minimal bytes one force launch moves."""
+    gf, lo, entries = rec.snap["lists"]
+    n_j = rec.n + rec.snap["n_node"]
+    mark = np.zeros(n_j, bool)
+    total = 0.0
+    for _, act, _ in rec.steps[warmup:]:
+        groups = np.unique(np.searchsorted(gf, act, side="right") - 1)
+        mark[:] = False
+        n_idx = 0
+        for g in groups:
+            mark[entries[lo[g]:lo[g + 1]]] = True
+            n_idx += int(lo[g + 1] - lo[g])
+        total += int(mark.sum()) * REC_PAYLOAD_BYTES + 4 * n_idx + act.size * (4 + OUT_BYTES)
+    return total / max(len(rec.steps) - warmup, 1)
 
 
 def tile_mix(rec, warmup):
@@ -505,6 +528,7 @@ def main():
     lat = mixed["lat_ms"]
     kernel_avg_ms = mixed["kernel_ms"] / max(mixed["launches"], 1)
     achieved = FLOPS_PER_PAIR * mixed["kernel_pairs"] / (mixed["kernel_ms"] * 1e-3) / 1e12
+    alg_bytes = algorithmic_bytes(rec, args.warmup)
     result = {
         "metric": METRIC,
         "value": value,
@@ -531,7 +555,7 @@ def main():
         "tflops_at_57": FLOPS_PER_PAIR * value / 1e12,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_VALU_TFLOPS, "traffic": measured_traffic(),
-                     "traffic_unit": "bytes/launch",
+                     "traffic_unit": "bytes/launch", "algorithmic_bytes": alg_bytes,
                      "kernel": "force_kernel<PrecMixed,false,false>", "avg_launch_ms": kernel_avg_ms,
                      "pairs_per_launch": mixed["kernel_pairs"] / max(mixed["launches"], 1)},
     }
