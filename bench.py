@@ -25,6 +25,7 @@ One JSON line on stdout; progress on stderr.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import math
@@ -277,6 +278,10 @@ def bench_ensemble(args, torch):
     for sp in specs:
         eng.add(eng.new_cluster(sp))
     log(f"ensemble: 64 clusters, {total_n} particles, set up in {time.perf_counter() - t0:.1f} s")
+    # plan tuning chosen on the clusters themselves (untimed; the clusters advance)
+    tuning, scores = eng.autotune()
+    log(f"ensemble: autotuned (gather_cost, target_items) = {tuning}; ms per 1e9 interactions "
+        f"{ {str(k): round(v, 3) for k, v in scores.items()} }")
     for _ in range(args.warmup):
         eng.step()
     eng.step_ms.clear()
@@ -304,6 +309,8 @@ def bench_ensemble(args, torch):
         "p50_step_ms": float(np.percentile(lat, 50)), "p99_step_ms": float(np.percentile(lat, 99)),
         "equivalent_interactions_per_s": eng.equiv_pairs / wall,
         "phase_s": eng.phase,
+        "autotuned": {"gather_cost": tuning[0], "target_items": tuning[1],
+                      "kernel_ms_per_1e9_interactions": {str(k): v for k, v in scores.items()}},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None,
                      "kernel": "force_kernel<PrecMixed,false,false>", "avg_launch_ms": kms / max(nl, 1)},
@@ -379,6 +386,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-all-active", action="store_true")
     ap.add_argument("--n", type=int, default=0, help="override N (testing only; not the benchmark)")
+    ap.add_argument("--n-crit", type=int, default=0, help="override the group size bound n_crit (sweeps)")
     ap.add_argument("--dump-steps", default="", help="write per-step (n_active, pairs, items, ms) JSON here")
     ap.add_argument("--requests", type=int, default=200, help="served workload: number of cluster runs")
     ap.add_argument("--max-resident", type=int, default=32, help="served workload: batch slots")
@@ -411,6 +419,8 @@ def main():
     cfg = W.config(args.workload)
     if args.n:
         cfg = W.config(args.workload, n=args.n, eps=4.0 / args.n)
+    if args.n_crit:
+        cfg = dataclasses.replace(cfg, n_crit=args.n_crit)
     log(f"workload {cfg.name}: N={cfg.n} theta={cfg.theta} eps={cfg.eps:.3g} dt_tree={cfg.dt_tree} "
         f"eta={cfg.eta} n_crit={cfg.n_crit}")
     x, v, m = W.make_initial_conditions(cfg)
@@ -544,7 +554,8 @@ def main():
         "dtype": "f64+f32",
         "data": "synthetic",
         "config": {"workload": cfg.name, "n": cfg.n, "theta": cfg.theta, "eps": cfg.eps, "dt_tree": cfg.dt_tree,
-                   "eta": cfg.eta, "n_crit": cfg.n_crit, "n_leaf": cfg.n_leaf, "masses": "salpeter 1:100",
+                   "eta": cfg.eta, "n_crit": cfg.n_crit, "n_leaf": cfg.n_leaf,
+                   "masses": f"salpeter 1:{cfg.mass_ratio:g}" if cfg.mass_seed is not None else "equal",
                    "window": f"{K} block steps after the rebuild at t={cfg.dt_tree}", "precision": "mixed",
                    "predict": "fused"},
         "p50_step_ms": float(np.percentile(lat, 50)),

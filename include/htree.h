@@ -201,7 +201,9 @@ int ht_batch_update_async(ht_batch *b, int32_t n_ctx, ht_ctx *const *ctxs, const
                           const ht_row *const *rows);
 
 /* Steps 4a-5 for several predicted contexts in one launch: as ht_force_async
- * per context, active ids from host arrays, results to device arrays. */
+ * per context, active ids from host arrays.  Results go to arrays the device
+ * can write: device memory, or pinned host memory (hipHostMalloc), which the
+ * host may read once the stream has been synchronised. */
 int ht_batch_force_async(ht_batch *b, int32_t n_ctx, ht_ctx *const *ctxs, const int32_t *n_active,
                          const int32_t *const *active_ids, double *const *d_acc, double *const *d_jerk,
                          double *const *d_pot);

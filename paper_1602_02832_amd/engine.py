@@ -8,7 +8,7 @@ engine step advances every resident cluster by one of its own block steps:
   2. each cluster picks its next block time and active set (host) and is
      predicted there;
   3. one batched force launch over all clusters' work items (+ one split
-     reduction), results to one device buffer, one copy back;
+     reduction), results written straight into pinned host memory;
   4. each cluster corrects its particles on the host; clusters at a tree time
      rebuild their tree and lists.
 
@@ -127,9 +127,8 @@ class Engine:
         self.clusters: list[Cluster] = []
         dev = f"cuda:{device}"
         # results of all clusters of a step, cluster k at rows offs[k]..; row slices stay contiguous
-        self.d_acc = torch.empty((max_active, 3), dtype=torch.float64, device=dev)
-        self.d_jerk = torch.empty((max_active, 3), dtype=torch.float64, device=dev)
-        self.d_pot = torch.empty(max_active, dtype=torch.float64, device=dev)
+        # The force launch writes its results straight into pinned host memory (the host
+        # corrects from them next), so an engine step has no device-to-host copy.
         self.h_acc = torch.empty((max_active, 3), dtype=torch.float64, pin_memory=True)
         self.h_jerk = torch.empty((max_active, 3), dtype=torch.float64, pin_memory=True)
         self.h_pot = torch.empty(max_active, dtype=torch.float64, pin_memory=True)
@@ -145,7 +144,9 @@ class Engine:
         # tree rebuilds run beside the engine loop; a rebuilding cluster sits out until it is resident again
         self.pool = concurrent.futures.ThreadPoolExecutor(max_workers=rebuild_workers) if rebuild_workers else None
         self.rebuilding = {}
-        self._ptr = (self.d_acc.data_ptr(), self.d_jerk.data_ptr(), self.d_pot.data_ptr())
+        self._ptr = (self.h_acc.data_ptr(), self.h_jerk.data_ptr(), self.h_pot.data_ptr())
+        self.tuning = None      # (gather_cost, target_items) for every cluster, None = library defaults
+        del dev
 
     def new_cluster(self, spec: RunSpec) -> Cluster:
         return Cluster(spec, self.precision, self.stream.cuda_stream, self.device)
@@ -154,7 +155,38 @@ class Engine:
         if len(self.clusters) >= self.max_clusters:
             raise RuntimeError("engine is full")
         c.activate()
+        if self.tuning is not None:
+            c.ctx.set_tuning(*self.tuning)
         self.clusters.append(c)
+
+    def set_tuning(self, gather_cost: float, target_items: float):
+        """Work-plan tuning (ht_set_tuning) for every resident and future cluster."""
+        self.tuning = (float(gather_cost), float(target_items))
+        for c in self.clusters:
+            c.ctx.set_tuning(*self.tuning)
+
+    def autotune(self, candidates=((8, 2048), (12, 2048), (16, 2048), (32, 2048), (12, 1024), (12, 4096)),
+                 steps: int = 4, rounds: int = 2):
+        """Pick the work-plan tuning with the least force-kernel time per
+        interaction on the engine's own clusters.  Each candidate runs `steps`
+        engine steps per round; rounds interleave the candidates so the drift of
+        the step mix averages out.  Advances the clusters; returns the choice
+        and the measured ms per 1e9 interactions of every candidate."""
+        score = {tuple(c): [0.0, 0] for c in candidates}
+        self.batch.set_timing(True)
+        for _ in range(rounds):
+            for cand in score:
+                self.set_tuning(*cand)
+                for _ in range(steps):
+                    self.step()
+                ms, _, pairs = self.batch.kernel_timing()
+                score[cand][0] += ms
+                score[cand][1] += pairs
+        self.batch.set_timing(False)
+        per = {c: 1e9 * v[0] / max(v[1], 1) for c, v in score.items()}
+        best = min(per, key=per.get)
+        self.set_tuning(*best)
+        return best, per
 
     def _struct(self, c: Cluster):
         """The cluster's host arrays as an htb_cluster (rebuilt after a tree
@@ -205,10 +237,6 @@ class Engine:
                                [pp + 8 * int(o) for o in offs])
         pairs, _ = self.batch.last_stats()
         t1 = time.perf_counter()
-        with self.torch.cuda.stream(self.stream):
-            self.h_acc[:total].copy_(self.d_acc[:total], non_blocking=True)
-            self.h_jerk[:total].copy_(self.d_jerk[:total], non_blocking=True)
-            self.h_pot[:total].copy_(self.d_pot[:total], non_blocking=True)
         self.stream.synchronize()
         t2 = time.perf_counter()
         # 5. corrector, new steps and update rows of every cluster (one native call)
