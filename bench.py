@@ -288,6 +288,7 @@ def bench_ensemble(args, torch):
     eng.pairs = eng.equiv_pairs = 0
     eng.wall = 0.0
     eng.phase = {k: 0.0 for k in eng.phase}
+    eng.subphase.clear()
     eng.batch.set_timing(True)
     torch.cuda.synchronize()
     tw = time.perf_counter()
@@ -308,7 +309,7 @@ def bench_ensemble(args, torch):
                    "theta": 0.5, "eps": "4/N", "dt_tree": 1.0 / 256, "eta": 0.01, "n_crit": 256, "precision": "mixed"},
         "p50_step_ms": float(np.percentile(lat, 50)), "p99_step_ms": float(np.percentile(lat, 99)),
         "equivalent_interactions_per_s": eng.equiv_pairs / wall,
-        "phase_s": eng.phase,
+        "phase_s": eng.phase, "host_subphase_s": dict(eng.subphase),
         "autotuned": {"gather_cost": tuning[0], "target_items": tuning[1],
                       "kernel_ms_per_1e9_interactions": {str(k): v for k, v in scores.items()}},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",

@@ -200,6 +200,13 @@ int ht_batch_destroy(ht_batch *b);
 int ht_batch_update_async(ht_batch *b, int32_t n_ctx, ht_ctx *const *ctxs, const int32_t *n_rows,
                           const ht_row *const *rows);
 
+/* As ht_batch_update_async, but the kernel reads the caller's rows in place:
+ * each rows[k] must be pinned host memory (hipHostMalloc) and must stay
+ * unchanged until the batch's stream has passed this call (for example until
+ * the next ht_batch_sync).  Saves the copy into the batch's staging. */
+int ht_batch_update_pinned_async(ht_batch *b, int32_t n_ctx, ht_ctx *const *ctxs, const int32_t *n_rows,
+                                 const ht_row *const *rows);
+
 /* Steps 4a-5 for several predicted contexts in one launch: as ht_force_async
  * per context, active ids from host arrays.  Results go to arrays the device
  * can write: device memory, or pinned host memory (hipHostMalloc), which the

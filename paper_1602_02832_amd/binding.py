@@ -166,6 +166,22 @@ def host_lib():
     return _host
 
 
+_raw_fns = {}
+
+
+def _raw(name, nargs):
+    """The device library's entry point `name` with every argument passed as a
+    plain integer (addresses included): for callers that keep handles and
+    pointers in numpy arrays."""
+    f = _raw_fns.get(name)
+    if f is None:
+        f = device_lib()[name]
+        f.argtypes = [ctypes.c_void_p] * nargs
+        f.restype = ctypes.c_int
+        _raw_fns[name] = f
+    return f
+
+
 def _check(rc: int):
     if rc != 0:
         msg = device_lib().ht_last_error()
@@ -341,6 +357,11 @@ def predict_many(ctxs, t):
     _check(device_lib().ht_predict_many(n, H, _ptr(t, ctypes.c_double)))
 
 
+def predict_many_raw(n, handles, t):
+    """ht_predict_many with the handle and time arrays given by address."""
+    _check(_raw("ht_predict_many", 3)(n, handles, t))
+
+
 def force_batch_async(ctxs, actives, d_accs, d_jerks, d_pots):
     """ht_force_batch_async over several contexts sharing one stream."""
     n = len(ctxs)
@@ -397,6 +418,18 @@ class Batch:
         R = (_vp * n)(*[r.ctypes.data if r.shape[0] else None for r in rows_list])
         _check(device_lib().ht_batch_update_async(self._h, n, H, N, R))
         self._keep = rows_list   # pinned copy is taken before return; kept for clarity
+
+    def update_async_raw(self, n, handles, n_rows, rows, pinned=False):
+        """ht_batch_update_async (pinned: ht_batch_update_pinned_async) with
+        every array given by address (handles and row pointers: arrays of n
+        addresses; n_rows: n int32)."""
+        name = "ht_batch_update_pinned_async" if pinned else "ht_batch_update_async"
+        _check(_raw(name, 5)(self._h.value, n, handles, n_rows, rows))
+
+    def force_async_raw(self, n, handles, n_active, ids, d_accs, d_jerks, d_pots):
+        """ht_batch_force_async with every array given by address (n_active: n
+        int32; the others arrays of n addresses)."""
+        _check(_raw("ht_batch_force_async", 8)(self._h.value, n, handles, n_active, ids, d_accs, d_jerks, d_pots))
 
     def force_async(self, ctxs, actives, d_accs, d_jerks, d_pots):
         n = len(ctxs)

@@ -207,14 +207,20 @@ void group_list(const htb_tree& t, int64_t gb, int64_t ge, const double lo[3], c
 
 namespace {
 // Largest power of two h <= cap with t1 a multiple of h; 0 below 2^-40.
+// t1 = m 2^(e-53) with m a 53-bit integer is a multiple of 2^j exactly when j
+// is at most e - 53 + (trailing zero bits of m), so no trial division is needed.
 double quantise(double cap, double t1) {
     if (!(cap > 0.0)) return 0.0;
     int e;
     std::frexp(cap, &e);
-    double h = std::ldexp(1.0, e - 1);
-    const double floor_h = std::ldexp(1.0, -40);
-    while (h >= floor_h && std::fmod(t1, h) != 0.0) h = 0.5 * h;
-    return h >= floor_h ? h : 0.0;
+    int j = e - 1;  // 2^j <= cap < 2^(j+1)
+    if (t1 != 0.0) {
+        int et;
+        const double mt = std::frexp(std::fabs(t1), &et);
+        const uint64_t m = static_cast<uint64_t>(std::ldexp(mt, 53));
+        j = std::min(j, et - 53 + __builtin_ctzll(m));
+    }
+    return j >= -40 ? std::ldexp(1.0, j) : 0.0;
 }
 inline double len3(const double* u) { return std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]); }
 
@@ -256,12 +262,19 @@ struct Row {  // ht_row layout
 };
 static_assert(sizeof(Row) == 120, "update row layout");
 
+// One pass: the list of particles due at the smallest next time seen so far
+// restarts whenever a smaller one appears.
 int64_t next_block_one(htb_cluster& c) {
     double tmin = std::numeric_limits<double>::infinity();
-    for (int64_t i = 0; i < c.n; ++i) tmin = std::min(tmin, c.t0[i] + c.dt[i]);
     int64_t k = 0;
-    for (int64_t i = 0; i < c.n; ++i)
-        if (c.t0[i] + c.dt[i] == tmin) c.active[k++] = static_cast<int32_t>(i);
+    for (int64_t i = 0; i < c.n; ++i) {
+        const double t = c.t0[i] + c.dt[i];
+        if (t < tmin) {
+            tmin = t;
+            k = 0;
+        }
+        if (t == tmin) c.active[k++] = static_cast<int32_t>(i);
+    }
     c.t_next = tmin;
     c.n_active = k;
     return k;
@@ -497,33 +510,35 @@ int htb_correct_many(int32_t n_clusters, htb_cluster* cl, const int64_t* off, co
                      const double* pot, const int64_t* row_off, void* rows, int32_t* rebuild) {
     if (n_clusters < 0 || (n_clusters > 0 && (!cl || !off || !acc || !jerk || !pot || !row_off || !rows || !rebuild)))
         return -1;
-    int bad = 0;
-#pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
+    // One flat loop over every active particle of every cluster (clusters differ
+    // in size by orders of magnitude, so a loop over clusters would leave one
+    // thread with the largest); first[k] is cluster k's first flat index.
+    std::vector<int64_t> first(static_cast<size_t>(n_clusters) + 1, 0);
     for (int32_t k = 0; k < n_clusters; ++k) {
+        first[k + 1] = first[k] + cl[k].n_active;
+        rebuild[k] = std::fmod(cl[k].t_next, cl[k].dt_tree) == 0.0 ? 1 : 0;
+    }
+    const int64_t total = first[n_clusters];
+    int bad = 0;
+#pragma omp parallel for schedule(static, 256) reduction(| : bad)
+    for (int64_t f = 0; f < total; ++f) {
+        const int32_t k = static_cast<int32_t>(std::upper_bound(first.begin(), first.end(), f) - first.begin()) - 1;
         htb_cluster& c = cl[k];
-        const int64_t o = off[k];
-        for (int64_t q = 0; q < c.n_active; ++q) {
-            const int32_t id = c.active[q];
-            bad |= correct_one(id, c.t_next, c.eta, c.dt_tree, c.t0, c.dt, c.x, c.v, c.a, c.jerk, acc + 3 * (o + q),
-                               jerk + 3 * (o + q));
-            c.pot[id] = pot[o + q];
-        }
-        rebuild[k] = std::fmod(c.t_next, c.dt_tree) == 0.0 ? 1 : 0;
+        const int64_t q = f - first[k], o = off[k] + q;
+        const int32_t i = c.active[q];
+        bad |= correct_one(i, c.t_next, c.eta, c.dt_tree, c.t0, c.dt, c.x, c.v, c.a, c.jerk, acc + 3 * o, jerk + 3 * o);
+        c.pot[i] = pot[o];
         if (rebuild[k]) continue;
-        Row* r = static_cast<Row*>(rows) + row_off[k];
-        for (int64_t q = 0; q < c.n_active; ++q) {
-            const int32_t i = c.active[q];
-            Row& w = r[q];
-            w.idx = i;
-            w.pad = 0;
-            w.t0 = c.t0[i];
-            w.m = c.m[i];
-            for (int d = 0; d < 3; ++d) {
-                w.x[d] = c.x[3 * i + d];
-                w.v[d] = c.v[3 * i + d];
-                w.a[d] = c.a[3 * i + d];
-                w.jerk[d] = c.jerk[3 * i + d];
-            }
+        Row& w = static_cast<Row*>(rows)[row_off[k] + q];
+        w.idx = i;
+        w.pad = 0;
+        w.t0 = c.t0[i];
+        w.m = c.m[i];
+        for (int d = 0; d < 3; ++d) {
+            w.x[d] = c.x[3 * i + d];
+            w.v[d] = c.v[3 * i + d];
+            w.a[d] = c.a[3 * i + d];
+            w.jerk[d] = c.jerk[3 * i + d];
         }
     }
     return bad ? -2 : 0;

@@ -639,8 +639,10 @@ __global__ __launch_bounds__(kWG) void prep_kernel(PlanCopy pc, void* rec_base, 
 
 // Batched j-memory update: rows of several clusters in one launch.
 struct UpdEntry {
-    void* rec;          // the cluster's records
-    int64_t first_row;  // its first row in the launch
+    void* rec;            // the cluster's records
+    int64_t first_row;    // its first row in the launch
+    const ht_row* rows;   // its rows (pinned host memory)
+    int64_t pad;
 };
 
 __device__ __forceinline__ int find_upd(const UpdEntry* tab, int n_tab, int64_t r) {
@@ -652,22 +654,21 @@ __device__ __forceinline__ int find_upd(const UpdEntry* tab, int n_tab, int64_t 
     return lo;
 }
 
-// The launch table and the rows are read straight from the pinned host
-// staging slot (system-scope loads, see host_word), so an update costs one
-// launch and no copy; every work-group keeps the table in LDS.
+// The launch table and the rows are read straight from pinned host memory
+// (system-scope loads, see host_word), so an update costs one launch and no
+// device copy; every work-group keeps the table in LDS.
 template <class P>
-__global__ __launch_bounds__(kWG) void scatter_rows_kernel(const UpdEntry* __restrict__ tab, int n_tab,
-                                                           const ht_row* __restrict__ rows, int64_t total) {
+__global__ __launch_bounds__(kWG) void scatter_rows_kernel(const UpdEntry* __restrict__ tab, int n_tab, int64_t total) {
     static_assert(sizeof(ht_row) == 15 * 8, "ht_row is 15 words");
-    static_assert(sizeof(UpdEntry) == 16, "UpdEntry is 2 words");
+    static_assert(sizeof(UpdEntry) == 32, "UpdEntry is 4 words");
     __shared__ UpdEntry stab[kMaxBatch];
-    for (int q = threadIdx.x; q < 2 * n_tab; q += kWG)
+    for (int q = threadIdx.x; q < 4 * n_tab; q += kWG)
         reinterpret_cast<uint64_t*>(stab)[q] = host_word(reinterpret_cast<const uint64_t*>(tab) + q);
     __syncthreads();
     for (int64_t r = blockIdx.x * static_cast<int64_t>(kWG) + threadIdx.x; r < total;
          r += static_cast<int64_t>(gridDim.x) * kWG) {
         const int k = find_upd(stab, n_tab, r);
-        const uint64_t* w = reinterpret_cast<const uint64_t*>(rows + r);
+        const uint64_t* w = reinterpret_cast<const uint64_t*>(stab[k].rows + (r - stab[k].first_row));
         uint64_t raw[15];
 #pragma unroll
         for (int q = 0; q < 15; ++q) raw[q] = host_word(w + q);
@@ -1742,8 +1743,16 @@ int ht_batch_destroy(ht_batch* b) {
     return HT_OK;
 }
 
-int ht_batch_update_async(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs, const int32_t* n_rows,
-                          const ht_row* const* rows) {
+}  // extern "C"
+
+namespace {
+
+// Validate the rows of a batched update and launch the row scatter.  copy:
+// the rows are copied into the batch's pinned staging (the caller's arrays may
+// be anything and are free on return); otherwise the kernel reads the caller's
+// arrays, which must be pinned and stay unchanged until the stream passes.
+int batch_update(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs, const int32_t* n_rows, const ht_row* const* rows,
+                 bool copy) {
     if (!b) return fail(HT_EINVAL, "batch is NULL");
     if (n_ctx < 0 || n_ctx > b->max_clusters) return fail(HT_EINVAL, "n_ctx = %d outside [0, %d]", n_ctx, b->max_clusters);
     if (n_ctx == 0) return HT_OK;
@@ -1780,22 +1789,39 @@ int ht_batch_update_async(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs, const
     const size_t rows_at = align_up(static_cast<size_t>(n_ctx) * sizeof(UpdEntry));
     for (int32_t k = 0; k < n_ctx; ++k) {
         if (n_rows[k] == 0) continue;
-        b->utab.push_back(UpdEntry{ctxs[k]->ws + ctxs[k]->L.off_rec, first});
-        std::memcpy(hs + rows_at + static_cast<size_t>(first) * sizeof(ht_row), rows[k],
-                    static_cast<size_t>(n_rows[k]) * sizeof(ht_row));
+        const ht_row* src = rows[k];
+        if (copy) {
+            ht_row* dst = reinterpret_cast<ht_row*>(hs + rows_at) + first;
+            std::memcpy(dst, rows[k], static_cast<size_t>(n_rows[k]) * sizeof(ht_row));
+            src = dst;
+        }
+        b->utab.push_back(UpdEntry{ctxs[k]->ws + ctxs[k]->L.off_rec, first, src, 0});
         first += n_rows[k];
     }
     std::memcpy(hs, b->utab.data(), b->utab.size() * sizeof(UpdEntry));
     const int grid = static_cast<int>(std::min<int64_t>((total + kWG - 1) / kWG, 65536));
     const UpdEntry* h_tab = reinterpret_cast<const UpdEntry*>(hs);
-    const ht_row* h_rows = reinterpret_cast<const ht_row*>(hs + rows_at);
     const int nt = static_cast<int>(b->utab.size());
     if (ctxs[0]->cfg.precision == HT_PREC_FP64)
-        scatter_rows_kernel<PrecFp64><<<grid, kWG, 0, b->stream>>>(h_tab, nt, h_rows, total);
+        scatter_rows_kernel<PrecFp64><<<grid, kWG, 0, b->stream>>>(h_tab, nt, total);
     else
-        scatter_rows_kernel<PrecMixed><<<grid, kWG, 0, b->stream>>>(h_tab, nt, h_rows, total);
+        scatter_rows_kernel<PrecMixed><<<grid, kWG, 0, b->stream>>>(h_tab, nt, total);
     HT_HIP(hipGetLastError());
-    return ring_release(b->rows_ring, b->stream);   // the kernel is the slot's reader
+    return ring_release(b->rows_ring, b->stream);   // the kernel is the slot's last reader
+}
+
+}  // namespace
+
+extern "C" {
+
+int ht_batch_update_async(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs, const int32_t* n_rows,
+                          const ht_row* const* rows) {
+    return batch_update(b, n_ctx, ctxs, n_rows, rows, true);
+}
+
+int ht_batch_update_pinned_async(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs, const int32_t* n_rows,
+                                 const ht_row* const* rows) {
+    return batch_update(b, n_ctx, ctxs, n_rows, rows, false);
 }
 
 int ht_batch_force_async(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs, const int32_t* n_active,

@@ -21,6 +21,7 @@ from __future__ import annotations
 
 import collections
 import concurrent.futures
+import ctypes
 import dataclasses
 import math
 import time
@@ -30,6 +31,13 @@ import numpy as np
 from . import binding as B
 from . import driver
 from . import workloads as W
+
+
+# numpy view of htb_cluster (include/htree_host.h): every field is 8 bytes
+_HTB_CLUSTER = np.dtype([("n", np.int64), ("eta", np.float64), ("dt_tree", np.float64)] +
+                        [(f, np.uint64) for f in ("t0", "dt", "x", "v", "a", "jerk", "m", "pot", "active")] +
+                        [("n_active", np.int64), ("t_next", np.float64)])
+assert _HTB_CLUSTER.itemsize == ctypes.sizeof(B.HtbCluster)
 
 
 @dataclasses.dataclass
@@ -66,7 +74,7 @@ class Cluster:
         self.caps = (max(int(tr.n_node * h), 64), max(int(tr.n_group * h), 16), max(int(tr.n_entries * h), 1024))
         self.reserve = workspace_bytes(spec.n, *self.caps, precision)
         self.sim = None
-        self.pending_rows = None
+        self.pending = (0, 0)    # (first row, count) of its update rows in the engine's row buffer
         self.steps_done = 0
         self.active_sum = 0
         self._struct = None
@@ -135,12 +143,15 @@ class Engine:
         # corrected particles of every cluster, written by the native corrector, read by the next update
         self._h_rows_t = torch.empty(max_active * B.HT_ROW.itemsize, dtype=torch.uint8, pin_memory=True)
         self.h_rows = self._h_rows_t.numpy().view(B.HT_ROW)
+        self._rows_base = np.uint64(self._h_rows_t.data_ptr())
+        self._layout = None
         self.step_ms = []
         self.pairs = 0
         self.equiv_pairs = 0
         self.wall = 0.0
         # where an engine step's time goes: host before the launch, waiting for the device, host after
         self.phase = {"host_begin": 0.0, "device_wait": 0.0, "host_finish": 0.0}
+        self.subphase = collections.defaultdict(float)
         # tree rebuilds run beside the engine loop; a rebuilding cluster sits out until it is resident again
         self.pool = concurrent.futures.ThreadPoolExecutor(max_workers=rebuild_workers) if rebuild_workers else None
         self.rebuilding = {}
@@ -155,6 +166,7 @@ class Engine:
         if len(self.clusters) >= self.max_clusters:
             raise RuntimeError("engine is full")
         c.activate()
+        self._layout = None
         if self.tuning is not None:
             c.ctx.set_tuning(*self.tuning)
         self.clusters.append(c)
@@ -203,6 +215,22 @@ class Engine:
             if wait or fut.done():
                 fut.result()
                 del self.rebuilding[c]
+                self._layout = None     # new arrays, maybe a new context
+
+    def _step_layout(self, cl):
+        """Per-step arrays of the resident set, cached while it is unchanged:
+        the htb_cluster array for the native host steps (and a numpy view of
+        it), the contexts' handles and the addresses of their active-id
+        buffers."""
+        key = tuple(map(id, cl))
+        if self._layout is None or self._layout[0] != key:
+            structs = (B.HtbCluster * len(cl))(*[self._struct(c) for c in cl])
+            raw = (ctypes.c_char * ctypes.sizeof(structs)).from_address(ctypes.addressof(structs))
+            view = np.frombuffer(raw, dtype=_HTB_CLUSTER)
+            handles = np.array([c.ctx.handle.value for c in cl], dtype=np.uint64)
+            act_ptr = np.array([c.sim._act_buf.ctypes.data for c in cl], dtype=np.uint64)
+            self._layout = (key, structs, view, handles, act_ptr)
+        return self._layout[1:]
 
     def step(self):
         """One engine step over all resident clusters; returns the clusters
@@ -214,35 +242,48 @@ class Engine:
             if self.rebuilding:
                 self._collect_rebuilds(wait=True)
             return []
-        # 1. j-memory updates from the previous step (one copy, one kernel)
-        ups = [c for c in cl if c.pending_rows is not None and c.pending_rows.shape[0]]
-        if ups:
-            self.batch.update_async([c.ctx for c in ups], [c.pending_rows for c in ups])
+        structs, view, handles, act_ptr = self._step_layout(cl)
+        n_cl = len(cl)
+        # 1. j-memory updates from the previous step (one kernel reading pinned rows)
+        pend_n = np.fromiter((c.pending[1] for c in cl), dtype=np.int32, count=n_cl)
+        sel = np.flatnonzero(pend_n)
+        if sel.size:
+            pend_off = np.fromiter((c.pending[0] for c in cl), dtype=np.uint64, count=n_cl)
+            h = np.ascontiguousarray(handles[sel])
+            nr = np.ascontiguousarray(pend_n[sel])
+            rp = np.ascontiguousarray(self._rows_base + np.uint64(B.HT_ROW.itemsize) * pend_off[sel])
+            # the rows sit in pinned memory that is not rewritten before this step's synchronisation
+            self.batch.update_async_raw(sel.size, h.ctypes.data, nr.ctypes.data, rp.ctypes.data, pinned=True)
+        ta = time.perf_counter()
         # 2. next block time and active set of every cluster (one native call)
-        structs = (B.HtbCluster * len(cl))(*[self._struct(c) for c in cl])
+        tb = ta
         B.next_block_many(structs)
-        t_next = np.array([structs[k].t_next for k in range(len(cl))])
-        n_act = np.array([structs[k].n_active for k in range(len(cl))], dtype=np.int64)
-        offs = np.zeros(len(cl), dtype=np.int64)
+        tc = time.perf_counter()
+        t_next = np.ascontiguousarray(view["t_next"])
+        n_act = view["n_active"].astype(np.int64)
+        offs = np.zeros(n_cl, dtype=np.int64)
         np.cumsum(n_act[:-1], out=offs[1:])
         total = int(n_act.sum())
         if total > self.max_active:
             raise RuntimeError("active particles over the engine capacity")
-        acts = [c.sim._act_buf[:n] for c, n in zip(cl, n_act)]
-        ctxs = [c.ctx for c in cl]
         # 3-4. predict every cluster at its own block time, one force launch for all
-        B.predict_many(ctxs, t_next)
+        B.predict_many_raw(n_cl, handles.ctypes.data, t_next.ctypes.data)
+        td = time.perf_counter()
         pa, pj, pp = self._ptr
-        self.batch.force_async(ctxs, acts, [pa + 24 * int(o) for o in offs], [pj + 24 * int(o) for o in offs],
-                               [pp + 8 * int(o) for o in offs])
+        uo = offs.astype(np.uint64)
+        na32 = n_act.astype(np.int32)
+        outs = [np.ascontiguousarray(np.uint64(base) + np.uint64(w) * uo) for base, w in ((pa, 24), (pj, 24), (pp, 8))]
+        self.batch.force_async_raw(n_cl, handles.ctypes.data, na32.ctypes.data, act_ptr.ctypes.data,
+                                   outs[0].ctypes.data, outs[1].ctypes.data, outs[2].ctypes.data)
         pairs, _ = self.batch.last_stats()
         t1 = time.perf_counter()
         self.stream.synchronize()
         t2 = time.perf_counter()
         # 5. corrector, new steps and update rows of every cluster (one native call)
-        rebuild = np.zeros(len(cl), dtype=np.int32)
+        rebuild = np.zeros(n_cl, dtype=np.int32)
         B.correct_many(structs, offs, self.h_acc[:total].numpy(), self.h_jerk[:total].numpy(),
                        self.h_pot[:total].numpy(), offs, self.h_rows, rebuild)
+        te = time.perf_counter()
         finished = []
         for k, c in enumerate(cl):
             sim = c.sim
@@ -253,13 +294,14 @@ class Engine:
             c.steps_done += 1
             c.active_sum += n
             if rebuild[k]:
-                c.pending_rows = None          # tree time: new tree, lists, full upload
+                c.pending = (0, 0)          # tree time: new tree, lists, full upload
+                self._layout = None
                 if self.pool is not None:
                     self.rebuilding[c] = self.pool.submit(sim._build_and_send)
                 else:
                     sim._build_and_send()
             else:
-                c.pending_rows = self.h_rows[offs[k]:offs[k] + n]
+                c.pending = (int(offs[k]), n)
             if c.done:
                 finished.append(c)
         t3 = time.perf_counter()
@@ -267,6 +309,14 @@ class Engine:
         self.phase["host_begin"] += t1 - t0
         self.phase["device_wait"] += t2 - t1
         self.phase["host_finish"] += t3 - t2
+        sub = self.subphase
+        sub["update"] += ta - t0
+        sub["structs"] += tb - ta
+        sub["next_block"] += tc - tb
+        sub["predict"] += td - tc
+        sub["plan_launch"] += t1 - td
+        sub["correct"] += te - t2
+        sub["bookkeeping"] += t3 - te
         self.step_ms.append(1e3 * dt)
         self.wall += dt
         self.pairs += pairs
@@ -281,6 +331,7 @@ class Engine:
         if c in self.rebuilding:
             self.rebuilding.pop(c).result()
         self.clusters.remove(c)
+        self._layout = None
 
     def close(self):
         self.drain()

@@ -119,3 +119,29 @@ def test_server_admission_respects_budget_and_results_match():
         alone, _ = run_engine([s])
         for f in FIELDS:
             assert np.array_equal(alone[0][f], mixed[s.key][f]), (s.key, f)
+
+
+def test_engine_matches_single_cluster_simulation():
+    """The engine path (pinned row updates, results written to pinned memory,
+    the flat batched corrector) gives the same bits as stepping the cluster's
+    own Simulation (host-array force, per-cluster corrector)."""
+    from paper_1602_02832_amd import driver
+    say("engine vs Simulation.step on the same cluster")
+    spec = E.RunSpec(key=0, n=1500, seed=510, steps=30, n_crit=64)
+    eng = E.Engine(max_clusters=4, max_active=1 << 14, max_items=1 << 15, max_rows=1 << 14, rebuild_workers=0)
+    c = eng.new_cluster(spec)
+    eng.add(c)
+    while not c.done:
+        eng.step()
+    got = state(c.sim)
+    eng.close()
+    x, v, m = W.plummer(spec.n, spec.seed)
+    eps = 4.0 / spec.n
+    sim = driver.Simulation(x, v, m, eps2=eps * eps, dt_tree=spec.dt_tree, eta=spec.eta, theta=spec.theta,
+                            n_crit=spec.n_crit, precision="mixed")
+    for _ in range(spec.steps):
+        sim.step()
+    want = state(sim)
+    sim.close()
+    for f in FIELDS:
+        assert np.array_equal(got[f], want[f]), f
