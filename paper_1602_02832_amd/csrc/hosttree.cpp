@@ -262,23 +262,6 @@ struct Row {  // ht_row layout
 };
 static_assert(sizeof(Row) == 120, "update row layout");
 
-// One pass: the list of particles due at the smallest next time seen so far
-// restarts whenever a smaller one appears.
-int64_t next_block_one(htb_cluster& c) {
-    double tmin = std::numeric_limits<double>::infinity();
-    int64_t k = 0;
-    for (int64_t i = 0; i < c.n; ++i) {
-        const double t = c.t0[i] + c.dt[i];
-        if (t < tmin) {
-            tmin = t;
-            k = 0;
-        }
-        if (t == tmin) c.active[k++] = static_cast<int32_t>(i);
-    }
-    c.t_next = tmin;
-    c.n_active = k;
-    return k;
-}
 }  // namespace
 
 extern "C" {
@@ -501,8 +484,56 @@ int htb_next_block_many(int32_t n_clusters, htb_cluster* cl) {
     if (n_clusters < 0 || (n_clusters > 0 && !cl)) return -1;
     for (int32_t k = 0; k < n_clusters; ++k)
         if (cl[k].n < 1 || !cl[k].t0 || !cl[k].dt || !cl[k].active) return -1;
-#pragma omp parallel for schedule(dynamic, 1)
-    for (int32_t k = 0; k < n_clusters; ++k) next_block_one(cl[k]);
+    // Chunks of at most kChunk particles, so that the largest cluster does not
+    // set the time: pass 1 finds each chunk's earliest next time and how many
+    // particles share it; per cluster the earliest over its chunks is t_next;
+    // pass 2 writes the due particles of every chunk at its place in the
+    // cluster's ascending list.
+    constexpr int64_t kChunk = 8192;
+    struct Chunk {
+        int32_t k;
+        int64_t b, e;
+        double tmin;
+        int64_t cnt, at;
+    };
+    std::vector<Chunk> ch;
+    for (int32_t k = 0; k < n_clusters; ++k)
+        for (int64_t b = 0; b < cl[k].n; b += kChunk) ch.push_back(Chunk{k, b, std::min(cl[k].n, b + kChunk), 0.0, 0, 0});
+    const int64_t nch = static_cast<int64_t>(ch.size());
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t q = 0; q < nch; ++q) {
+        Chunk& h = ch[q];
+        const htb_cluster& c = cl[h.k];
+        double tmin = std::numeric_limits<double>::infinity();
+        int64_t cnt = 0;
+        for (int64_t i = h.b; i < h.e; ++i) {
+            const double t = c.t0[i] + c.dt[i];
+            if (t < tmin) {
+                tmin = t;
+                cnt = 0;
+            }
+            cnt += t == tmin;
+        }
+        h.tmin = tmin;
+        h.cnt = cnt;
+    }
+    for (int32_t k = 0; k < n_clusters; ++k) cl[k].t_next = std::numeric_limits<double>::infinity();
+    for (const Chunk& h : ch) cl[h.k].t_next = std::min(cl[h.k].t_next, h.tmin);
+    for (int32_t k = 0; k < n_clusters; ++k) cl[k].n_active = 0;
+    for (Chunk& h : ch) {
+        if (h.tmin != cl[h.k].t_next) continue;
+        h.at = cl[h.k].n_active;
+        cl[h.k].n_active += h.cnt;
+    }
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t q = 0; q < nch; ++q) {
+        const Chunk& h = ch[q];
+        const htb_cluster& c = cl[h.k];
+        if (h.tmin != c.t_next) continue;
+        int64_t w = h.at;
+        for (int64_t i = h.b; i < h.e; ++i)
+            if (c.t0[i] + c.dt[i] == c.t_next) c.active[w++] = static_cast<int32_t>(i);
+    }
     return 0;
 }
 

@@ -1764,16 +1764,25 @@ int batch_update(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs, const int32_t*
         if (rc) return rc;
         if (!c->have_particles) return fail(HT_ESTATE, "ctx %d: particles not set", k);
         if (n_rows[k] < 0 || (n_rows[k] > 0 && !rows[k])) return fail(HT_EINVAL, "ctx %d: bad rows", k);
-        if (c->mark.size() != static_cast<size_t>(c->n)) c->mark.assign(static_cast<size_t>(c->n), 0u);
-        if (++c->mark_gen == 0) {
-            std::fill(c->mark.begin(), c->mark.end(), 0u);
-            c->mark_gen = 1;
-        }
+        // indices in range and distinct: one sequential pass when they are
+        // increasing (the usual case: rows of an ascending active set), else marks
+        bool increasing = true;
         for (int32_t r = 0; r < n_rows[k]; ++r) {
             const int32_t j = rows[k][r].idx;
             if (j < 0 || j >= c->n) return fail(HT_ERANGE, "ctx %d: row index %d outside [0, %d)", k, j, c->n);
-            if (c->mark[j] == c->mark_gen) return fail(HT_EINVAL, "ctx %d: particle %d updated twice", k, j);
-            c->mark[j] = c->mark_gen;
+            if (r > 0 && j <= rows[k][r - 1].idx) increasing = false;
+        }
+        if (!increasing) {
+            if (c->mark.size() != static_cast<size_t>(c->n)) c->mark.assign(static_cast<size_t>(c->n), 0u);
+            if (++c->mark_gen == 0) {
+                std::fill(c->mark.begin(), c->mark.end(), 0u);
+                c->mark_gen = 1;
+            }
+            for (int32_t r = 0; r < n_rows[k]; ++r) {
+                const int32_t j = rows[k][r].idx;
+                if (c->mark[j] == c->mark_gen) return fail(HT_EINVAL, "ctx %d: particle %d updated twice", k, j);
+                c->mark[j] = c->mark_gen;
+            }
         }
         total += n_rows[k];
     }

@@ -132,3 +132,94 @@ def test_next_block_selects_minimum():
     tn, act = B.next_block(t0, dt)
     want = np.flatnonzero(t0 + dt == (t0 + dt).min())
     assert tn == (t0 + dt).min() and np.array_equal(act, want)
+
+
+@pytest.mark.parametrize("level", [0, 3, 7, 12, 20, 33])
+def test_host_block_steps_match_oracle_at_many_block_times(oracle, level):
+    """The host quantiser (largest power of two dividing t1, from its bits) gives
+    the oracle's block step (halving until t1 is a multiple) at block times with
+    many different binary valuations."""
+    rng = np.random.default_rng(40 + level)
+    n = 400
+    k = rng.integers(1, 1 << 12, n) | 1                    # odd multiples
+    t1 = float(np.ldexp(k[0], -level)) if level else 5.0
+    dt_old = np.ldexp(1.0, -rng.integers(max(level, 1), min(max(level, 1) + 10, 39), n))   # steps stay >= 2^-40
+    t0 = t1 - dt_old
+    x, v, a, j = rng.normal(size=(4, n, 3))
+    a1 = a + rng.normal(scale=10.0 ** rng.uniform(-6, 1), size=(n, 3))
+    j1 = j + rng.normal(scale=10.0 ** rng.uniform(-6, 1), size=(n, 3))
+    xp, vp = oracle.predict(t1, t0, x, v, a, j)
+    _, _, dta = oracle.correct(t1, t0, xp, vp, a, j, a1, j1, 0.02)
+    want = np.array([oracle.block_step(dta[q], t1, 1.0, dt_old[q]) for q in range(n)])
+    T0, DT = t0.copy(), dt_old.copy()
+    B.correct(np.arange(n, dtype=np.int32), t1, 0.02, 1.0, T0, DT, x.copy(), v.copy(), a.copy(), j.copy(), a1, j1)
+    assert np.array_equal(DT, want)
+
+
+def _clusters(sizes, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for n in sizes:
+        dt = np.ldexp(1.0, -rng.integers(3, 9, n))
+        t0 = np.floor(rng.uniform(0, 1, n) / dt) * dt
+        x, v, a, j = rng.normal(size=(4, n, 3))
+        m = rng.uniform(0.5, 1.5, n) / n
+        out.append(dict(n=n, t0=t0, dt=dt, x=x, v=v, a=a, j=j, m=m, pot=np.zeros(n), act=np.empty(n, np.int32)))
+    return out
+
+
+def _structs(cls):
+    return (B.HtbCluster * len(cls))(*[B.cluster_struct(c["n"], 0.01, 1.0 / 8, c["t0"], c["dt"], c["x"], c["v"],
+                                                        c["a"], c["j"], c["m"], c["pot"], c["act"]) for c in cls])
+
+
+SIZES = (1, 3, 50, 8191, 8192, 8193, 20000, 40000)
+
+
+def test_next_block_many_matches_definition():
+    """Batched next block (chunked across threads) vs the definition, per cluster:
+    t_next = min(t0 + dt), the due particles in ascending order."""
+    cls = _clusters(SIZES, 5)
+    S = _structs(cls)
+    B.next_block_many(S)
+    for k, c in enumerate(cls):
+        t = c["t0"] + c["dt"]
+        want = np.flatnonzero(t == t.min())
+        assert S[k].t_next == t.min()
+        assert S[k].n_active == want.size and np.array_equal(c["act"][:want.size], want)
+
+
+def test_correct_many_matches_per_cluster_corrector():
+    """Batched corrector (one loop over all clusters' particles) vs the
+    single-cluster corrector: same bits, rows of the corrected particles, and
+    rebuild flags at tree times."""
+    cls = _clusters(SIZES, 6)
+    ref = [{f: (c[f].copy() if isinstance(c[f], np.ndarray) else c[f]) for f in c} for c in cls]
+    S = _structs(cls)
+    B.next_block_many(S)
+    rng = np.random.default_rng(7)
+    n_act = np.array([S[k].n_active for k in range(len(cls))], dtype=np.int64)
+    off = np.zeros(len(cls), np.int64)
+    np.cumsum(n_act[:-1], out=off[1:])
+    total = int(n_act.sum())
+    acc = rng.normal(size=(total, 3))
+    jerk = rng.normal(size=(total, 3))
+    pot = rng.normal(size=total)
+    rows = np.zeros(total, B.HT_ROW)
+    rebuild = np.zeros(len(cls), np.int32)
+    B.correct_many(S, off, acc, jerk, pot, off, rows, rebuild)
+    for k, (c, r) in enumerate(zip(cls, ref)):
+        ids = c["act"][:n_act[k]].copy()
+        o, e = off[k], off[k] + n_act[k]
+        B.correct(ids, S[k].t_next, 0.01, 1.0 / 8, r["t0"], r["dt"], r["x"], r["v"], r["a"], r["j"], acc[o:e],
+                  jerk[o:e])
+        for f in ("t0", "dt", "x", "v", "a", "j"):
+            assert np.array_equal(c[f], r[f]), (k, f)
+        assert np.array_equal(c["pot"][ids], pot[o:e])
+        at_tree_time = S[k].t_next % (1.0 / 8) == 0.0
+        assert rebuild[k] == at_tree_time
+        if not at_tree_time:
+            w = rows[o:e]
+            assert np.array_equal(w["idx"], ids) and np.array_equal(w["x"], r["x"][ids])
+            assert np.array_equal(w["t0"], r["t0"][ids]) and np.array_equal(w["m"], r["m"][ids])
+            assert np.array_equal(w["jerk"], r["j"][ids])
