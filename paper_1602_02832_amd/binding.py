@@ -182,6 +182,18 @@ def _raw(name, nargs):
     return f
 
 
+def _raw_host(name, nargs):
+    """The host library's entry point `name` with every argument a plain integer."""
+    key = ("host", name)
+    f = _raw_fns.get(key)
+    if f is None:
+        f = host_lib()[name]
+        f.argtypes = [ctypes.c_void_p] * nargs
+        f.restype = ctypes.c_int
+        _raw_fns[key] = f
+    return f
+
+
 def _check(rc: int):
     if rc != 0:
         msg = device_lib().ht_last_error()
@@ -559,6 +571,22 @@ def next_block_many(structs):
     rc = host_lib().htb_next_block_many(len(structs), structs)
     if rc:
         raise HTError(rc, "htb_next_block_many failed")
+
+
+def next_block_many_raw(n, clusters):
+    """htb_next_block_many over n htb_cluster records at address `clusters`."""
+    rc = _raw_host("htb_next_block_many", 2)(n, clusters)
+    if rc:
+        raise HTError(rc, "htb_next_block_many failed")
+
+
+def correct_many_raw(n, clusters, off, acc, jerk, pot, row_off, rows, rebuild):
+    """htb_correct_many with every array given by address."""
+    rc = _raw_host("htb_correct_many", 9)(n, clusters, off, acc, jerk, pot, row_off, rows, rebuild)
+    if rc == -2:
+        raise FloatingPointError("block step below 2^-40")
+    if rc:
+        raise HTError(rc, "htb_correct_many failed")
 
 
 def correct_many(structs, off, acc, jerk, pot, row_off, rows, rebuild):

@@ -485,26 +485,27 @@ int htb_next_block_many(int32_t n_clusters, htb_cluster* cl) {
     for (int32_t k = 0; k < n_clusters; ++k)
         if (cl[k].n < 1 || !cl[k].t0 || !cl[k].dt || !cl[k].active) return -1;
     // Chunks of at most kChunk particles, so that the largest cluster does not
-    // set the time: pass 1 finds each chunk's earliest next time and how many
-    // particles share it; per cluster the earliest over its chunks is t_next;
-    // pass 2 writes the due particles of every chunk at its place in the
-    // cluster's ascending list.
+    // set the time.  One parallel pass: each chunk finds its earliest next time
+    // and lists its particles due then, in its own slice of the cluster's
+    // active array.  Then, per cluster, t_next is the earliest over its chunks
+    // and the lists of the chunks due at t_next are moved down, in order.
     constexpr int64_t kChunk = 8192;
     struct Chunk {
         int32_t k;
         int64_t b, e;
         double tmin;
-        int64_t cnt, at;
+        int64_t cnt;
     };
     std::vector<Chunk> ch;
     for (int32_t k = 0; k < n_clusters; ++k)
-        for (int64_t b = 0; b < cl[k].n; b += kChunk) ch.push_back(Chunk{k, b, std::min(cl[k].n, b + kChunk), 0.0, 0, 0});
+        for (int64_t b = 0; b < cl[k].n; b += kChunk) ch.push_back(Chunk{k, b, std::min(cl[k].n, b + kChunk), 0.0, 0});
     const int64_t nch = static_cast<int64_t>(ch.size());
-#pragma omp parallel for schedule(dynamic, 4)
+#pragma omp parallel for schedule(dynamic, 2)
     for (int64_t q = 0; q < nch; ++q) {
         Chunk& h = ch[q];
         const htb_cluster& c = cl[h.k];
         double tmin = std::numeric_limits<double>::infinity();
+        int32_t* out = c.active + h.b;
         int64_t cnt = 0;
         for (int64_t i = h.b; i < h.e; ++i) {
             const double t = c.t0[i] + c.dt[i];
@@ -512,27 +513,21 @@ int htb_next_block_many(int32_t n_clusters, htb_cluster* cl) {
                 tmin = t;
                 cnt = 0;
             }
-            cnt += t == tmin;
+            if (t == tmin) out[cnt++] = static_cast<int32_t>(i);
         }
         h.tmin = tmin;
         h.cnt = cnt;
     }
-    for (int32_t k = 0; k < n_clusters; ++k) cl[k].t_next = std::numeric_limits<double>::infinity();
-    for (const Chunk& h : ch) cl[h.k].t_next = std::min(cl[h.k].t_next, h.tmin);
-    for (int32_t k = 0; k < n_clusters; ++k) cl[k].n_active = 0;
-    for (Chunk& h : ch) {
-        if (h.tmin != cl[h.k].t_next) continue;
-        h.at = cl[h.k].n_active;
-        cl[h.k].n_active += h.cnt;
+    for (int32_t k = 0; k < n_clusters; ++k) {
+        cl[k].t_next = std::numeric_limits<double>::infinity();
+        cl[k].n_active = 0;
     }
-#pragma omp parallel for schedule(dynamic, 4)
-    for (int64_t q = 0; q < nch; ++q) {
-        const Chunk& h = ch[q];
-        const htb_cluster& c = cl[h.k];
+    for (const Chunk& h : ch) cl[h.k].t_next = std::min(cl[h.k].t_next, h.tmin);
+    for (const Chunk& h : ch) {   // chunks in ascending order, destinations never pass their sources
+        htb_cluster& c = cl[h.k];
         if (h.tmin != c.t_next) continue;
-        int64_t w = h.at;
-        for (int64_t i = h.b; i < h.e; ++i)
-            if (c.t0[i] + c.dt[i] == c.t_next) c.active[w++] = static_cast<int32_t>(i);
+        if (c.n_active != h.b) std::memmove(c.active + c.n_active, c.active + h.b, static_cast<size_t>(h.cnt) * 4);
+        c.n_active += h.cnt;
     }
     return 0;
 }

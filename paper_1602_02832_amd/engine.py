@@ -77,8 +77,7 @@ class Cluster:
         self.pending = (0, 0)    # (first row, count) of its update rows in the engine's row buffer
         self.steps_done = 0
         self.active_sum = 0
-        self._struct = None
-        self._struct_arrays = ()
+        self._cache = None       # (handle, t0 array, htb_cluster record, active-buffer address, context, arrays)
 
     def activate(self):
         if self.sim is None:
@@ -144,7 +143,6 @@ class Engine:
         self._h_rows_t = torch.empty(max_active * B.HT_ROW.itemsize, dtype=torch.uint8, pin_memory=True)
         self.h_rows = self._h_rows_t.numpy().view(B.HT_ROW)
         self._rows_base = np.uint64(self._h_rows_t.data_ptr())
-        self._layout = None
         self.step_ms = []
         self.pairs = 0
         self.equiv_pairs = 0
@@ -166,7 +164,6 @@ class Engine:
         if len(self.clusters) >= self.max_clusters:
             raise RuntimeError("engine is full")
         c.activate()
-        self._layout = None
         if self.tuning is not None:
             c.ctx.set_tuning(*self.tuning)
         self.clusters.append(c)
@@ -200,37 +197,23 @@ class Engine:
         self.set_tuning(*best)
         return best, per
 
-    def _struct(self, c: Cluster):
-        """The cluster's host arrays as an htb_cluster (rebuilt after a tree
-        rebuild, which replaces the arrays)."""
+    def _refresh(self, c: Cluster):
+        """The cluster's htb_cluster record, context handle and active-buffer
+        address, recomputed only when a rebuild replaced its arrays or context."""
         sim = c.sim
-        arrays = (sim.t0, sim.dt, sim.x, sim.v, sim.a, sim.j, sim.m, sim.pot, sim._act_buf)
-        if c._struct is None or any(p is not q for p, q in zip(c._struct_arrays, arrays)):
-            c._struct = B.cluster_struct(sim.n, sim.eta, sim.dt_tree, *arrays)
-            c._struct_arrays = arrays
-        return c._struct
+        cc = c._cache
+        # a rebuild replaces all of a cluster's host arrays at once (and may replace its context)
+        if cc is None or cc[1] is not sim.t0 or cc[4] is not sim.ctx:
+            arrays = (sim.t0, sim.dt, sim.x, sim.v, sim.a, sim.j, sim.m, sim.pot, sim._act_buf)
+            rec = (sim.n, sim.eta, sim.dt_tree) + tuple(a.ctypes.data for a in arrays) + (0, 0.0)
+            cc = c._cache = (sim.ctx.handle.value, sim.t0, rec, sim._act_buf.ctypes.data, sim.ctx, arrays)
+        return cc
 
     def _collect_rebuilds(self, wait=False):
         for c, fut in list(self.rebuilding.items()):
             if wait or fut.done():
                 fut.result()
                 del self.rebuilding[c]
-                self._layout = None     # new arrays, maybe a new context
-
-    def _step_layout(self, cl):
-        """Per-step arrays of the resident set, cached while it is unchanged:
-        the htb_cluster array for the native host steps (and a numpy view of
-        it), the contexts' handles and the addresses of their active-id
-        buffers."""
-        key = tuple(map(id, cl))
-        if self._layout is None or self._layout[0] != key:
-            structs = (B.HtbCluster * len(cl))(*[self._struct(c) for c in cl])
-            raw = (ctypes.c_char * ctypes.sizeof(structs)).from_address(ctypes.addressof(structs))
-            view = np.frombuffer(raw, dtype=_HTB_CLUSTER)
-            handles = np.array([c.ctx.handle.value for c in cl], dtype=np.uint64)
-            act_ptr = np.array([c.sim._act_buf.ctypes.data for c in cl], dtype=np.uint64)
-            self._layout = (key, structs, view, handles, act_ptr)
-        return self._layout[1:]
 
     def step(self):
         """One engine step over all resident clusters; returns the clusters
@@ -242,8 +225,11 @@ class Engine:
             if self.rebuilding:
                 self._collect_rebuilds(wait=True)
             return []
-        structs, view, handles, act_ptr = self._step_layout(cl)
         n_cl = len(cl)
+        caches = [self._refresh(c) for c in cl]
+        view = np.array([cc[2] for cc in caches], dtype=_HTB_CLUSTER)     # the htb_cluster records
+        handles = np.fromiter((cc[0] for cc in caches), dtype=np.uint64, count=n_cl)
+        act_ptr = np.fromiter((cc[3] for cc in caches), dtype=np.uint64, count=n_cl)
         # 1. j-memory updates from the previous step (one kernel reading pinned rows)
         pend_n = np.fromiter((c.pending[1] for c in cl), dtype=np.int32, count=n_cl)
         sel = np.flatnonzero(pend_n)
@@ -257,7 +243,7 @@ class Engine:
         ta = time.perf_counter()
         # 2. next block time and active set of every cluster (one native call)
         tb = ta
-        B.next_block_many(structs)
+        B.next_block_many_raw(n_cl, view.ctypes.data)
         tc = time.perf_counter()
         t_next = np.ascontiguousarray(view["t_next"])
         n_act = view["n_active"].astype(np.int64)
@@ -281,8 +267,8 @@ class Engine:
         t2 = time.perf_counter()
         # 5. corrector, new steps and update rows of every cluster (one native call)
         rebuild = np.zeros(n_cl, dtype=np.int32)
-        B.correct_many(structs, offs, self.h_acc[:total].numpy(), self.h_jerk[:total].numpy(),
-                       self.h_pot[:total].numpy(), offs, self.h_rows, rebuild)
+        B.correct_many_raw(n_cl, view.ctypes.data, offs.ctypes.data, self._ptr[0], self._ptr[1], self._ptr[2],
+                           offs.ctypes.data, int(self._rows_base), rebuild.ctypes.data)
         te = time.perf_counter()
         finished = []
         for k, c in enumerate(cl):
@@ -295,7 +281,6 @@ class Engine:
             c.active_sum += n
             if rebuild[k]:
                 c.pending = (0, 0)          # tree time: new tree, lists, full upload
-                self._layout = None
                 if self.pool is not None:
                     self.rebuilding[c] = self.pool.submit(sim._build_and_send)
                 else:
@@ -331,7 +316,6 @@ class Engine:
         if c in self.rebuilding:
             self.rebuilding.pop(c).result()
         self.clusters.remove(c)
-        self._layout = None
 
     def close(self):
         self.drain()
