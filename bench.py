@@ -140,7 +140,7 @@ def device_updates(torch, rec):
     return out
 
 
-def replay(torch, B, rec, ctx, stream, warmup, steps, direct=False, instrument=True):
+def replay(torch, B, rec, ctx, stream, warmup, steps, direct=False, instrument=True, graph=False):
     """Replay recorded steps; returns a timing dict for the last `steps` steps.
 
     instrument=False: nothing but the steps between the two synchronisations
@@ -164,6 +164,8 @@ def replay(torch, B, rec, ctx, stream, warmup, steps, direct=False, instrument=T
                 ctx.set_j_particles_async(*upd)
             ctx.predict(t)
             ctx.force_direct_async(act, *out_ptrs)
+        elif graph:
+            ctx.step_graph(upd, t, act, *out_ptrs)
         else:
             ctx.step_async(upd, t, act, *out_ptrs)
 
@@ -479,6 +481,11 @@ def main():
     log(f"mixed tree: {mixed['pairs'] / mixed['wall_s']:.4g} pairs/s, {1e3 * mixed['wall_s'] / args.steps:.3f} "
         f"ms/step ({1e3 * mixed['instrumented_wall_s'] / args.steps:.3f} instrumented), kernel "
         f"{mixed['kernel_ms']:.3f} ms over {mixed['launches']} launches")
+    # ---- the same steps replayed through the captured step graphs (ht_step_graph)
+    ctx = make_ctx(B, rec.snap, rec.n, "mixed", cfg.eps2, sh)
+    graph_wall = replay(torch, B, rec, ctx, stream, args.warmup, args.steps, instrument=False, graph=True)["wall_s"]
+    ctx.close()
+    log(f"mixed tree, graph replays: {mixed['pairs'] / graph_wall:.4g} pairs/s, {1e3 * graph_wall / args.steps:.3f} ms/step")
     # ---- direct N^2 on the same steps
     direct = None
     if not args.no_direct:
@@ -549,6 +556,7 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": 1e3 * mixed["wall_s"] / K,
         "instrumented_ms_per_step": 1e3 * mixed["instrumented_wall_s"] / K,
+        "graph_replay": {"interactions_per_s": mixed["pairs"] / graph_wall, "ms_per_step": 1e3 * graph_wall / K},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

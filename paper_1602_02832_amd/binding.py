@@ -111,6 +111,7 @@ def device_lib():
             "ht_force_direct_async": [_vp, i, _c_i32p, _vp, _vp, _vp],
             "ht_get_predicted": [_vp, i, _c_i32p, _c_dp, _c_dp],
             "ht_step_async": [_vp, i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, d, i, _vp, _vp, _vp, _vp],
+            "ht_step_graph": [_vp, i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, d, i, _vp, _vp, _vp, _vp],
             "ht_force_batch_async": [i, ctypes.POINTER(_vp), _c_i32p, ctypes.POINTER(_c_i32p),
                                      ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp)],
             "ht_sync": [_vp],
@@ -327,6 +328,16 @@ class Context:
         else:
             n_upd, ptrs = int(upd[0]), tuple(_dptr(u) for u in upd[1:])
         _check(device_lib().ht_step_async(self._h, n_upd, *ptrs, float(t), active.shape[0], active.ctypes.data,
+                                          _dptr(d_acc), _dptr(d_jerk), _dptr(d_pot)))
+
+    def step_graph(self, upd, t, active, d_acc, d_jerk, d_pot):
+        """ht_step_graph: as step_async, replayed through the context's HIP graphs."""
+        active = _arr(active, np.int32)
+        if upd is None:
+            n_upd, ptrs = 0, (None,) * 7
+        else:
+            n_upd, ptrs = int(upd[0]), tuple(_dptr(u) for u in upd[1:])
+        _check(device_lib().ht_step_graph(self._h, n_upd, *ptrs, float(t), active.shape[0], active.ctypes.data,
                                           _dptr(d_acc), _dptr(d_jerk), _dptr(d_pot)))
 
     def get_predicted(self, idx):

@@ -139,6 +139,8 @@ struct Entry {
     const RTile* rtiles;
     int64_t first_item;
     int64_t first_rtile;
+    int64_t n_items;    // entry 0: items and split tiles of the whole launch (graph replays
+    int64_t n_rtiles;   // read them here, their launch arguments being fixed)
 };
 
 struct PrecFp64 {
@@ -465,11 +467,23 @@ __device__ __forceinline__ int find_entry(const Entry* tab, int n_tab, int64_t g
 template <class P>
 struct WavesPerSimd { static constexpr int value = P::kMixed ? 4 : 3; };
 
-template <class P, bool EAGER, bool DIRECT>
+// QUEUE (graph replays): a fixed grid takes items from the counter *queue
+// (reset by the prep launch) until the launch's item count, read from the
+// table, is reached; otherwise the grid has one work-group per item.
+template <class P, bool EAGER, bool DIRECT, bool QUEUE = false>
 __global__ __launch_bounds__(kWG, WavesPerSimd<P>::value) void force_kernel(const Entry* __restrict__ tab, int n_tab,
-                                                                          int64_t n_items) {
+                                                                          int64_t n_items,
+                                                                          unsigned long long* queue) {
     __shared__ LdsAll<P> lds;
-    for (int64_t g = blockIdx.x; g < n_items; g += gridDim.x) {
+    __shared__ int64_t next;
+    int64_t g = blockIdx.x;
+    if constexpr (QUEUE) {
+        n_items = tab[0].n_items;
+        if (threadIdx.x == 0) next = static_cast<int64_t>(atomicAdd(queue, 1ull));
+        __syncthreads();
+        g = next;
+    }
+    while (g < n_items) {
         const int cl = find_entry(tab, n_tab, g, false);
         const Desc& c = tab[cl].d;
         const Item it = tab[cl].items[g - tab[cl].first_item];
@@ -485,6 +499,13 @@ __global__ __launch_bounds__(kWG, WavesPerSimd<P>::value) void force_kernel(cons
             default: run_item<P, EAGER, DIRECT, 1>(c, it, lds); break;
         }
         __syncthreads();
+        if constexpr (QUEUE) {
+            if (threadIdx.x == 0) next = static_cast<int64_t>(atomicAdd(queue, 1ull));
+            __syncthreads();
+            g = next;
+        } else {
+            g += gridDim.x;
+        }
     }
 }
 
@@ -494,8 +515,10 @@ __global__ __launch_bounds__(kWG, WavesPerSimd<P>::value) void force_kernel(cons
 // by all threads at once, so the dependent adds read LDS, not memory.
 constexpr int kRedLds = 6144;   // doubles of LDS for one tile's partials
 
+// n_rtiles < 0 (graph replays): the count is read from the table.
 __global__ __launch_bounds__(kWG) void reduce_kernel(const Entry* __restrict__ tab, int n_tab, int64_t n_rtiles) {
     __shared__ double buf[kRedLds];
+    if (n_rtiles < 0) n_rtiles = tab[0].n_rtiles;
     for (int64_t g = blockIdx.x; g < n_rtiles; g += gridDim.x) {
         const int cl = find_entry(tab, n_tab, g, true);
         const Desc& c = tab[cl].d;
@@ -637,6 +660,48 @@ __global__ __launch_bounds__(kWG) void prep_kernel(PlanCopy pc, void* rec_base, 
         store_rec<P>(rec, u.idx[k], u.t0[k], u.m[k], u.x + 3 * k, u.v + 3 * k, u.a + 3 * k, u.jerk + 3 * k);
 }
 
+// Parameters of a graph-replayed step, in a pinned host slot that the host
+// rewrites before each replay (the graph's launch arguments never change).
+struct GraphHdr {
+    int64_t n8;           // plan words to pull
+    const uint64_t* src;  // the packed plan (pinned host memory)
+    int64_t n_upd;        // update rows (device arrays below)
+    const int32_t* idx;
+    const double *t0, *m, *x, *v, *a, *jerk;
+};
+static_assert(sizeof(GraphHdr) == 10 * 8, "GraphHdr is 10 words");
+
+// prep_kernel for graph replays: everything it needs comes from the header;
+// it also resets the force launch's work counter.
+template <class P>
+__global__ __launch_bounds__(kWG) void prep_graph_kernel(const GraphHdr* hdr, uint64_t* dst, void* rec_base,
+                                                         int copy_blocks, unsigned long long* queue) {
+    uint64_t h[10];
+#pragma unroll
+    for (int q = 0; q < 10; ++q) h[q] = host_word(reinterpret_cast<const uint64_t*>(hdr) + q);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *queue = 0ull;
+    if (static_cast<int>(blockIdx.x) < copy_blocks) {
+        const int64_t n8 = static_cast<int64_t>(h[0]);
+        const uint64_t* src = reinterpret_cast<const uint64_t*>(h[1]);
+        const int64_t stride = static_cast<int64_t>(copy_blocks) * kWG;
+        for (int64_t k = blockIdx.x * static_cast<int64_t>(kWG) + threadIdx.x; k < n8; k += stride)
+            dst[k] = host_word(src + k);
+        return;
+    }
+    const int n = static_cast<int>(h[2]);
+    const int32_t* idx = reinterpret_cast<const int32_t*>(h[3]);
+    const double* t0 = reinterpret_cast<const double*>(h[4]);
+    const double* m = reinterpret_cast<const double*>(h[5]);
+    const double* x = reinterpret_cast<const double*>(h[6]);
+    const double* v = reinterpret_cast<const double*>(h[7]);
+    const double* a = reinterpret_cast<const double*>(h[8]);
+    const double* jerk = reinterpret_cast<const double*>(h[9]);
+    typename P::Rec* rec = static_cast<typename P::Rec*>(rec_base);
+    const int b = blockIdx.x - copy_blocks, nb = gridDim.x - copy_blocks;
+    for (int k = b * kWG + threadIdx.x; k < n; k += nb * kWG)
+        store_rec<P>(rec, idx[k], t0[k], m[k], x + 3 * k, v + 3 * k, a + 3 * k, jerk + 3 * k);
+}
+
 // Batched j-memory update: rows of several clusters in one launch.
 struct UpdEntry {
     void* rec;            // the cluster's records
@@ -698,7 +763,7 @@ constexpr int kStageRows = 1 << 16;  // rows per host->device upload chunk
 struct Layout {
     size_t jcap, stored, vel;
     size_t off_rec, off_prec;
-    size_t off_entries, off_plan, off_partial, off_out, off_stage;
+    size_t off_entries, off_plan, off_partial, off_out, off_queue, off_stage;
     int64_t items_max, partial_max;
     size_t plan_bytes;  // launch table + items + reduce tiles + active ids, packed per call
     size_t total;
@@ -730,6 +795,7 @@ bool layout_of(const ht_config& c, Layout& L) {
     L.off_plan = take(L.plan_bytes);
     L.off_partial = take(static_cast<size_t>(L.partial_max) * kOut * 8);
     L.off_out = take(static_cast<size_t>(c.active_max) * kOut * 8);
+    L.off_queue = take(8);
     L.off_stage = take(static_cast<size_t>(kStageRows) * (4 + 8 + 8 + 4 * 24));
     L.total = o;
     return true;
@@ -792,6 +858,15 @@ struct ht_ctx {
     double gather_cost = kGatherCostDefault;
     double target_items = kTargetItemsDefault;
     int8_t first_tile[257] = {};   // least-cost tiling for the gather cost (tile_table)
+    // ht_step_graph: two captured step graphs, one per pinned header slot, so the
+    // host fills one header while the other graph may still be running
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph[2] = {};
+    hipGraphExec_t gexec[2] = {};
+    hipEvent_t hdr_free[2] = {};
+    bool hdr_pending[2] = {};
+    int gslot = 0;
+    GraphHdr* h_hdr = nullptr;
     // scratch for planning
     std::vector<Item> items;
     std::vector<RTile> rtiles;
@@ -1089,11 +1164,11 @@ int launch_force(hipStream_t stream, bool eager, Timing& tm, const Entry* d_tab,
         tm.pairs += pairs;
     }
     if (direct) {
-        if (eager) force_kernel<P, true, true><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items);
-        else force_kernel<P, false, true><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items);
+        if (eager) force_kernel<P, true, true><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr);
+        else force_kernel<P, false, true><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr);
     } else {
-        if (eager) force_kernel<P, true, false><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items);
-        else force_kernel<P, false, false><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items);
+        if (eager) force_kernel<P, true, false><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr);
+        else force_kernel<P, false, false><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr);
     }
     HT_HIP(hipGetLastError());
     if (ev_b) HT_HIP(hipEventRecord(ev_b, stream));
@@ -1159,6 +1234,8 @@ int enqueue_step(ht_ctx* c, const DevRows& u, bool predict_eager, int32_t n_acti
         end = pack_plan(c, sizeof(Entry), n_active, ids, d_acc, d_jerk, d_pot, e);
         e.first_item = 0;
         e.first_rtile = 0;
+        e.n_items = static_cast<int64_t>(c->items.size());
+        e.n_rtiles = static_cast<int64_t>(c->rtiles.size());
         std::memcpy(c->plan_host(), &e, sizeof(Entry));
     } else {
         c->last_pairs = 0;
@@ -1338,6 +1415,13 @@ int ht_destroy(ht_ctx* c) {
     for (hipEvent_t e : c->slot_free)
         if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->tm.pool) (void)hipEventDestroy(e);
+    for (int k = 0; k < 2; ++k) {
+        if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+        if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
+        if (c->hdr_free[k]) (void)hipEventDestroy(c->hdr_free[k]);
+    }
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->h_hdr) (void)hipHostFree(c->h_hdr);
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
     if (c->own_ws && c->ws) (void)hipFree(c->ws);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -1509,6 +1593,125 @@ int ht_step_async(ht_ctx* c, int32_t n_upd, const int32_t* d_idx, const double* 
                         false);
 }
 
+}  // extern "C"
+
+namespace {
+
+constexpr int kGraphForceGrid = 1024;   // resident work-groups of the force kernel (4 per CU)
+constexpr int kGraphCopyBlocks = 256;
+constexpr int kGraphScatterBlocks = 256;
+constexpr int kGraphReduceGrid = 256;
+
+// Capture the step graph of header slot k: prep (plan pulled from the
+// header's slot, update rows written, work counter reset), force (fixed grid,
+// work queue), reduce (count read from the plan).
+template <class P>
+int build_step_graph(ht_ctx* c, int k) {
+    if (!c->cap_stream) HT_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    if (!c->h_hdr) {
+        HT_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_hdr), 2 * sizeof(GraphHdr), hipHostMallocDefault));
+        std::memset(c->h_hdr, 0, 2 * sizeof(GraphHdr));
+        for (int q = 0; q < 2; ++q) HT_HIP(hipEventCreateWithFlags(&c->hdr_free[q], hipEventDisableTiming));
+    }
+    uint64_t* d_plan = reinterpret_cast<uint64_t*>(c->ws + c->L.off_plan);
+    const Entry* d_tab = reinterpret_cast<const Entry*>(c->ws + c->L.off_plan);
+    auto* queue = reinterpret_cast<unsigned long long*>(c->ws + c->L.off_queue);
+    hipStream_t s = c->cap_stream;
+    HT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    prep_graph_kernel<P><<<kGraphCopyBlocks + kGraphScatterBlocks, kWG, 0, s>>>(c->h_hdr + k, d_plan,
+                                                                             c->ws + c->L.off_rec,
+                                                                             kGraphCopyBlocks, queue);
+    force_kernel<P, false, false, true><<<kGraphForceGrid, kWG, 0, s>>>(d_tab, 1, 0, queue);
+    reduce_kernel<<<kGraphReduceGrid, kWG, 0, s>>>(d_tab, 1, -1);
+    const hipError_t launch = hipGetLastError();
+    hipGraph_t g = nullptr;
+    const hipError_t end = hipStreamEndCapture(s, &g);
+    if (launch != hipSuccess || end != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(HT_EHIP, "capturing the step graph failed: %s",
+                    hipGetErrorString(launch != hipSuccess ? launch : end));
+    }
+    c->graph[k] = g;
+    HT_HIP(hipGraphInstantiate(&c->gexec[k], g, nullptr, nullptr, 0));
+    return HT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ht_step_graph(ht_ctx* c, int32_t n_upd, const int32_t* d_idx, const double* d_t0, const double* d_m,
+                  const double* d_x, const double* d_v, const double* d_a, const double* d_jerk, double t,
+                  int32_t n_active, const int32_t* ids, double* d_acc, double* d_jerk_out, double* d_pot) {
+    if (!c) return fail(HT_EINVAL, "ctx is NULL");
+    if (c->cfg.predict_mode != HT_PREDICT_FUSED) return fail(HT_EINVAL, "graph steps need fused prediction");
+    if (!c->have_lists) return fail(HT_ESTATE, "interaction lists not set");
+    int rc = check_dev_rows(c, n_upd, d_idx, d_t0, d_m, d_x, d_v, d_a, d_jerk);
+    if (rc) return rc;
+    rc = validate_active(c, n_active, ids);
+    if (rc) return rc;
+    if (!std::isfinite(t)) return fail(HT_EINVAL, "t not finite");
+    if (n_active > 0 && (!d_acc || !d_jerk_out || !d_pot)) return fail(HT_EINVAL, "output pointer is NULL");
+    if (n_active == 0) {   // nothing to replay: the update alone, as ht_step_async would do it
+        const DevRows u{n_upd, d_idx, d_t0, d_m, d_x, d_v, d_a, d_jerk};
+        c->t_pred = t;
+        c->predicted = true;
+        return enqueue_step(c, u, false, 0, ids, d_acc, d_jerk_out, d_pot, false);
+    }
+    c->t_pred = t;
+    c->predicted = true;
+    rc = plan(c, n_active, ids, false);
+    if (rc) return rc;
+    rc = c->slot_acquire();
+    if (rc) return rc;
+    Entry e{};
+    const size_t end = pack_plan(c, sizeof(Entry), n_active, ids, d_acc, d_jerk_out, d_pot, e);
+    e.first_item = 0;
+    e.first_rtile = 0;
+    e.n_items = static_cast<int64_t>(c->items.size());
+    e.n_rtiles = static_cast<int64_t>(c->rtiles.size());
+    std::memcpy(c->plan_host(), &e, sizeof(Entry));
+    const int k = c->gslot;
+    if (!c->gexec[k]) {
+        rc = c->cfg.precision == HT_PREC_FP64 ? build_step_graph<PrecFp64>(c, k) : build_step_graph<PrecMixed>(c, k);
+        if (rc) return rc;
+    }
+    if (c->hdr_pending[k]) {
+        HT_HIP(hipEventSynchronize(c->hdr_free[k]));
+        c->hdr_pending[k] = false;
+    }
+    GraphHdr& h = c->h_hdr[k];
+    h.n8 = static_cast<int64_t>((end + 7) / 8);
+    h.src = reinterpret_cast<const uint64_t*>(c->plan_host());
+    h.n_upd = n_upd;
+    h.idx = d_idx;
+    h.t0 = d_t0;
+    h.m = d_m;
+    h.x = d_x;
+    h.v = d_v;
+    h.a = d_a;
+    h.jerk = d_jerk;
+    Timing& tm = c->tm;
+    if (tm.enabled) {
+        while (tm.pool.size() < tm.used + 2) {
+            hipEvent_t ev;
+            HT_HIP(hipEventCreate(&ev));
+            tm.pool.push_back(ev);
+        }
+        HT_HIP(hipEventRecord(tm.pool[tm.used], c->stream));
+    }
+    HT_HIP(hipGraphLaunch(c->gexec[k], c->stream));
+    if (tm.enabled) {
+        HT_HIP(hipEventRecord(tm.pool[tm.used + 1], c->stream));
+        tm.used += 2;
+        tm.pairs += c->last_pairs;
+    }
+    HT_HIP(hipEventRecord(c->hdr_free[k], c->stream));
+    c->hdr_pending[k] = true;
+    c->gslot = 1 - k;
+    return c->slot_release();
+}
+
 int ht_get_predicted(ht_ctx* c, int32_t n, const int32_t* idx, double* xp, double* vp) {
     if (!c) return fail(HT_EINVAL, "ctx is NULL");
     if (!c->have_particles) return fail(HT_ESTATE, "particles not set");
@@ -1594,6 +1797,8 @@ int ht_force_batch_async(int32_t n_ctx, ht_ctx* const* ctxs, const int32_t* n_ac
         tab.push_back(e);
     }
     if (tab.empty()) return HT_OK;
+    tab[0].n_items = n_items;
+    tab[0].n_rtiles = n_rtiles;
     std::memcpy(c0->plan_host(), tab.data(), tab.size() * sizeof(Entry));
     rc = launch_prep_any(c0->cfg.precision, c0->stream, c0->plan_host(), c0->ws + c0->L.off_plan, end0, nullptr,
                          DevRows{});
@@ -1885,6 +2090,8 @@ int ht_batch_force_async(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs, const 
     }
     if (b->tab.empty()) return HT_OK;
     if (at > b->plan_bytes) return fail(HT_ERANGE, "batch plan over its capacity");
+    b->tab[0].n_items = n_items;
+    b->tab[0].n_rtiles = n_rtiles;
     std::memcpy(hs, b->tab.data(), b->tab.size() * sizeof(Entry));
     rc = launch_prep_any(ctxs[0]->cfg.precision, b->stream, hs, dv, at, nullptr, DevRows{});
     if (rc) return rc;

@@ -386,3 +386,58 @@ def test_step_async_equals_separate_calls(oracle):
     want = oracle.force_list(act, np.vstack([xp, nxp]), np.vstack([vp, nvp]), f32(np.concatenate([m, ptr.node_m])),
                              1e-4, ptr.group_first, ptr.list_off, ptr.entries)
     assert_close("step_async", "mixed", tuple(o.cpu().numpy() for o in outs[0]), want)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_step_graph_replays_equal_step_async(prec):
+    """ht_step_graph replays the captured step graphs (two, alternating) with a
+    new plan, update and active set every step; every replay must give the
+    bits of ht_step_async on the same sequence, with eager work and
+    synchronisations between replays, and sets from one particle to all of
+    them (many split tiles, none, a reduce launch that has nothing to do)."""
+    import torch
+    say(f"step_graph replays vs step_async ({prec})")
+    n = 6000
+    x, v, m = W.plummer(n, 91)
+    z = np.zeros((n, 3))
+    ptr = B.HostTree(x, v, z, z, m, 1, 128, 0.5)
+    x, v, m = x[ptr.perm], v[ptr.perm], m[ptr.perm]
+    t0, a, j = W.random_block_state(n, 92, 0.25)
+    ctxs = []
+    for _ in range(2):
+        c = make_ctx(prec, n, 2 * n, n, 2 * ptr.n_entries, 1e-4)
+        c.set_j_particles(t0, m, x, v, a, j)
+        c.set_nodes(0.0, ptr.node_m, ptr.node_x, ptr.node_v, ptr.node_a, ptr.node_j)
+        c.set_interaction_lists(ptr.group_first, ptr.list_off, ptr.entries)
+        ctxs.append(c)
+    rng = np.random.default_rng(93)
+    dev = lambda u: torch.from_numpy(np.ascontiguousarray(u)).cuda()  # noqa: E731
+    sizes = [1, 700, 3, n, 40, 2, 1500, 5, n // 2, 1, 90, 260]
+    t = 0.25
+    prev = None
+    for step, k in enumerate(sizes):
+        t += 1.0 / 64
+        act = np.sort(rng.choice(n, k, replace=False)).astype(np.int32)
+        outs = [tuple(torch.full(s, float("nan"), dtype=torch.float64, device="cuda") for s in ((k, 3), (k, 3), (k,)))
+                for _ in range(2)]
+        ctxs[0].step_async(prev, t, act, *outs[0])
+        ctxs[1].step_graph(prev, t, act, *outs[1])
+        if step % 3 == 0:
+            torch.cuda.synchronize()
+            scratch = torch.randn(1 << 20, device="cuda").sum()   # eager work between replays
+            del scratch
+        ctxs[0].sync()
+        ctxs[1].sync()
+        for p, q in zip(outs[0], outs[1]):
+            assert torch.equal(p, q), (step, k)
+        # this step's active particles, moved a little, are the next step's update
+        nu = act.size
+        upd_x = x[act] + 1e-4 * (step + 1)
+        prev = (nu, dev(act), dev(np.full(nu, t)), dev(m[act]), dev(upd_x), dev(v[act]), dev(a[act]), dev(j[act]))
+    with pytest.raises(B.HTError):
+        eager = make_ctx(prec, n, 2 * n, n, 2 * ptr.n_entries, 1e-4, mode="eager")
+        eager.set_j_particles(t0, m, x, v, a, j)
+        eager.set_nodes(0.0, ptr.node_m, ptr.node_x, ptr.node_v, ptr.node_a, ptr.node_j)
+        eager.set_interaction_lists(ptr.group_first, ptr.list_off, ptr.entries)
+        out = tuple(torch.empty(s, dtype=torch.float64, device="cuda") for s in ((1, 3), (1, 3), (1,)))
+        eager.step_graph(None, t, np.array([0], np.int32), *out)
