@@ -151,11 +151,11 @@ int ht_step_async(ht_ctx *ctx, int32_t n_upd, const int32_t *d_idx, const double
 
 /* ht_step_async replayed through a HIP graph: the same arguments and the same
  * results, bit for bit.  The step's three launches (plan delivery with the
- * update, force, split reduction) are captured once per context into two
- * graphs whose kernels read the step's sizes from memory (a pinned header the
- * host rewrites before each replay, the plan, a work counter), so every replay
- * is one hipGraphLaunch on the context's stream.  Needs HT_PREDICT_FUSED;
- * kernel timing (ht_set_timing) brackets the whole graph. */
+ * update, force, split reduction) are captured once per context into four
+ * graphs (one per header slot, used in turn) whose kernels read the step's sizes from memory (a pinned header the
+ * host rewrites before each replay, and the plan) and run on fixed grids, so
+ * every replay is one hipGraphLaunch on the context's stream.  Needs
+ * HT_PREDICT_FUSED; kernel timing (ht_set_timing) brackets the whole graph. */
 int ht_step_graph(ht_ctx *ctx, int32_t n_upd, const int32_t *d_idx, const double *d_t0, const double *d_m,
                   const double *d_x, const double *d_v, const double *d_a, const double *d_jerk, double t,
                   int32_t n_active, const int32_t *active_ids, double *d_acc, double *d_jerk_out,

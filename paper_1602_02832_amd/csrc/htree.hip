@@ -467,23 +467,17 @@ __device__ __forceinline__ int find_entry(const Entry* tab, int n_tab, int64_t g
 template <class P>
 struct WavesPerSimd { static constexpr int value = P::kMixed ? 4 : 3; };
 
-// QUEUE (graph replays): a fixed grid takes items from the counter *queue
-// (reset by the prep launch) until the launch's item count, read from the
-// table, is reached; otherwise the grid has one work-group per item.
-template <class P, bool EAGER, bool DIRECT, bool QUEUE = false>
+// Work-group g takes items g, g + grid, ...  The grid is normally the item
+// count; graph replays launch a fixed grid and pass n_items < 0, and the count
+// is read from the table.  (A shared atomic work counter was measured to cost
+// about 1 us per item: device-scope atomics on one address serialise across
+// the eight XCDs.)
+template <class P, bool EAGER, bool DIRECT>
 __global__ __launch_bounds__(kWG, WavesPerSimd<P>::value) void force_kernel(const Entry* __restrict__ tab, int n_tab,
-                                                                          int64_t n_items,
-                                                                          unsigned long long* queue) {
+                                                                          int64_t n_items) {
     __shared__ LdsAll<P> lds;
-    __shared__ int64_t next;
-    int64_t g = blockIdx.x;
-    if constexpr (QUEUE) {
-        n_items = tab[0].n_items;
-        if (threadIdx.x == 0) next = static_cast<int64_t>(atomicAdd(queue, 1ull));
-        __syncthreads();
-        g = next;
-    }
-    while (g < n_items) {
+    if (n_items < 0) n_items = tab[0].n_items;
+    for (int64_t g = blockIdx.x; g < n_items; g += gridDim.x) {
         const int cl = find_entry(tab, n_tab, g, false);
         const Desc& c = tab[cl].d;
         const Item it = tab[cl].items[g - tab[cl].first_item];
@@ -499,13 +493,6 @@ __global__ __launch_bounds__(kWG, WavesPerSimd<P>::value) void force_kernel(cons
             default: run_item<P, EAGER, DIRECT, 1>(c, it, lds); break;
         }
         __syncthreads();
-        if constexpr (QUEUE) {
-            if (threadIdx.x == 0) next = static_cast<int64_t>(atomicAdd(queue, 1ull));
-            __syncthreads();
-            g = next;
-        } else {
-            g += gridDim.x;
-        }
     }
 }
 
@@ -671,15 +658,13 @@ struct GraphHdr {
 };
 static_assert(sizeof(GraphHdr) == 10 * 8, "GraphHdr is 10 words");
 
-// prep_kernel for graph replays: everything it needs comes from the header;
-// it also resets the force launch's work counter.
+// prep_kernel for graph replays: everything it needs comes from the header.
 template <class P>
 __global__ __launch_bounds__(kWG) void prep_graph_kernel(const GraphHdr* hdr, uint64_t* dst, void* rec_base,
-                                                         int copy_blocks, unsigned long long* queue) {
-    uint64_t h[10];
-#pragma unroll
-    for (int q = 0; q < 10; ++q) h[q] = host_word(reinterpret_cast<const uint64_t*>(hdr) + q);
-    if (blockIdx.x == 0 && threadIdx.x == 0) *queue = 0ull;
+                                                         int copy_blocks) {
+    __shared__ uint64_t h[10];   // the header, fetched once per work-group
+    if (threadIdx.x < 10) h[threadIdx.x] = host_word(reinterpret_cast<const uint64_t*>(hdr) + threadIdx.x);
+    __syncthreads();
     if (static_cast<int>(blockIdx.x) < copy_blocks) {
         const int64_t n8 = static_cast<int64_t>(h[0]);
         const uint64_t* src = reinterpret_cast<const uint64_t*>(h[1]);
@@ -763,7 +748,7 @@ constexpr int kStageRows = 1 << 16;  // rows per host->device upload chunk
 struct Layout {
     size_t jcap, stored, vel;
     size_t off_rec, off_prec;
-    size_t off_entries, off_plan, off_partial, off_out, off_queue, off_stage;
+    size_t off_entries, off_plan, off_partial, off_out, off_stage;
     int64_t items_max, partial_max;
     size_t plan_bytes;  // launch table + items + reduce tiles + active ids, packed per call
     size_t total;
@@ -795,7 +780,6 @@ bool layout_of(const ht_config& c, Layout& L) {
     L.off_plan = take(L.plan_bytes);
     L.off_partial = take(static_cast<size_t>(L.partial_max) * kOut * 8);
     L.off_out = take(static_cast<size_t>(c.active_max) * kOut * 8);
-    L.off_queue = take(8);
     L.off_stage = take(static_cast<size_t>(kStageRows) * (4 + 8 + 8 + 4 * 24));
     L.total = o;
     return true;
@@ -858,13 +842,14 @@ struct ht_ctx {
     double gather_cost = kGatherCostDefault;
     double target_items = kTargetItemsDefault;
     int8_t first_tile[257] = {};   // least-cost tiling for the gather cost (tile_table)
-    // ht_step_graph: two captured step graphs, one per pinned header slot, so the
-    // host fills one header while the other graph may still be running
+    // ht_step_graph: captured step graphs, one per pinned header slot, so the
+    // host can fill headers while earlier replays are still running
     hipStream_t cap_stream = nullptr;
-    hipGraph_t graph[2] = {};
-    hipGraphExec_t gexec[2] = {};
-    hipEvent_t hdr_free[2] = {};
-    bool hdr_pending[2] = {};
+    static constexpr int kGraphSlots = 4;
+    hipGraph_t graph[kGraphSlots] = {};
+    hipGraphExec_t gexec[kGraphSlots] = {};
+    hipEvent_t hdr_free[kGraphSlots] = {};
+    bool hdr_pending[kGraphSlots] = {};
     int gslot = 0;
     GraphHdr* h_hdr = nullptr;
     // scratch for planning
@@ -1164,11 +1149,11 @@ int launch_force(hipStream_t stream, bool eager, Timing& tm, const Entry* d_tab,
         tm.pairs += pairs;
     }
     if (direct) {
-        if (eager) force_kernel<P, true, true><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr);
-        else force_kernel<P, false, true><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr);
+        if (eager) force_kernel<P, true, true><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items);
+        else force_kernel<P, false, true><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items);
     } else {
-        if (eager) force_kernel<P, true, false><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr);
-        else force_kernel<P, false, false><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr);
+        if (eager) force_kernel<P, true, false><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items);
+        else force_kernel<P, false, false><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items);
     }
     HT_HIP(hipGetLastError());
     if (ev_b) HT_HIP(hipEventRecord(ev_b, stream));
@@ -1415,7 +1400,7 @@ int ht_destroy(ht_ctx* c) {
     for (hipEvent_t e : c->slot_free)
         if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->tm.pool) (void)hipEventDestroy(e);
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < ht_ctx::kGraphSlots; ++k) {
         if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
         if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
         if (c->hdr_free[k]) (void)hipEventDestroy(c->hdr_free[k]);
@@ -1597,31 +1582,32 @@ int ht_step_async(ht_ctx* c, int32_t n_upd, const int32_t* d_idx, const double* 
 
 namespace {
 
-constexpr int kGraphForceGrid = 1024;   // resident work-groups of the force kernel (4 per CU)
+constexpr int kGraphForceGrid = 2048;   // fixed force grid of a replay (2 per resident work-group slot)
 constexpr int kGraphCopyBlocks = 256;
 constexpr int kGraphScatterBlocks = 256;
 constexpr int kGraphReduceGrid = 256;
 
 // Capture the step graph of header slot k: prep (plan pulled from the
-// header's slot, update rows written, work counter reset), force (fixed grid,
-// work queue), reduce (count read from the plan).
+// header's slot, update rows written), force and reduce (fixed grids, counts
+// read from the plan).
 template <class P>
 int build_step_graph(ht_ctx* c, int k) {
     if (!c->cap_stream) HT_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     if (!c->h_hdr) {
-        HT_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_hdr), 2 * sizeof(GraphHdr), hipHostMallocDefault));
-        std::memset(c->h_hdr, 0, 2 * sizeof(GraphHdr));
-        for (int q = 0; q < 2; ++q) HT_HIP(hipEventCreateWithFlags(&c->hdr_free[q], hipEventDisableTiming));
+        HT_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_hdr), ht_ctx::kGraphSlots * sizeof(GraphHdr),
+                             hipHostMallocDefault));
+        std::memset(c->h_hdr, 0, ht_ctx::kGraphSlots * sizeof(GraphHdr));
+        for (int q = 0; q < ht_ctx::kGraphSlots; ++q)
+            HT_HIP(hipEventCreateWithFlags(&c->hdr_free[q], hipEventDisableTiming));
     }
     uint64_t* d_plan = reinterpret_cast<uint64_t*>(c->ws + c->L.off_plan);
     const Entry* d_tab = reinterpret_cast<const Entry*>(c->ws + c->L.off_plan);
-    auto* queue = reinterpret_cast<unsigned long long*>(c->ws + c->L.off_queue);
     hipStream_t s = c->cap_stream;
     HT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     prep_graph_kernel<P><<<kGraphCopyBlocks + kGraphScatterBlocks, kWG, 0, s>>>(c->h_hdr + k, d_plan,
                                                                              c->ws + c->L.off_rec,
-                                                                             kGraphCopyBlocks, queue);
-    force_kernel<P, false, false, true><<<kGraphForceGrid, kWG, 0, s>>>(d_tab, 1, 0, queue);
+                                                                             kGraphCopyBlocks);
+    force_kernel<P, false, false><<<kGraphForceGrid, kWG, 0, s>>>(d_tab, 1, -1);
     reduce_kernel<<<kGraphReduceGrid, kWG, 0, s>>>(d_tab, 1, -1);
     const hipError_t launch = hipGetLastError();
     hipGraph_t g = nullptr;
@@ -1708,7 +1694,7 @@ int ht_step_graph(ht_ctx* c, int32_t n_upd, const int32_t* d_idx, const double* 
     }
     HT_HIP(hipEventRecord(c->hdr_free[k], c->stream));
     c->hdr_pending[k] = true;
-    c->gslot = 1 - k;
+    c->gslot = (k + 1) % ht_ctx::kGraphSlots;
     return c->slot_release();
 }
 
