@@ -306,6 +306,19 @@ __device__ __forceinline__ void run_item(const Desc& c, const Item& it, LdsAll<P
     const int islot = tid & (T - 1);
     const int stream = tid / T;
     const bool has_i = islot < it.n_i;
+    // List indices of the round about to be gathered, loaded one round ahead so
+    // that a round's gather waits on one memory access (the record) instead of
+    // two in a row (index, then record); the first round's are loaded beside
+    // the i-particle's own record.
+    int jn[G];
+    auto load_idx = [&](int64_t b) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int64_t e = b + tid + g * kWG;
+            jn[g] = e < it.j_end ? (DIRECT ? static_cast<int>(e) : c.entries[e]) : 0;
+        }
+    };
+    load_idx(it.j_begin);
     const int i = c.active[it.act_begin + (has_i ? islot : 0)];
 
     double xi, yi, zi;
@@ -340,7 +353,7 @@ __device__ __forceinline__ void run_item(const Desc& c, const Item& it, LdsAll<P
         for (int g = 0; g < G; ++g) {
             const int e = tid + g * kWG;
             if (e < cnt) {
-                const int j = DIRECT ? static_cast<int>(base + e) : c.entries[base + e];
+                const int j = jn[g];
                 double xj, yj, zj;
                 typename P::Vel vxj, vyj, vzj;
                 typename P::Stored mj;
@@ -348,6 +361,7 @@ __device__ __forceinline__ void run_item(const Desc& c, const Item& it, LdsAll<P
                 lds.j[e] = JRec<P>{xj, yj, zj, vxj, vyj, vzj, mj, j};
             }
         }
+        if (base + R < it.j_end) load_idx(base + R);   // in flight during this round's pairs
         __syncthreads();
         if constexpr (P::kMixed) {
             const double eps2 = c.eps2;
