@@ -242,9 +242,16 @@ def cpu_baseline(W, cfg, seconds):
     whole groups of the t = 0 tree, the oracle's own tree and lists."""
     from oracle import oracle as O
 
+    from paper_1602_02832_amd import binding as B
+
     x, v, m = W.make_initial_conditions(cfg)
     z = np.zeros_like(x)
+    t = time.perf_counter()
     tr = O.Tree(x, v, z, z, m, cfg.n_leaf, cfg.n_crit, cfg.theta)
+    t_oracle_tree = time.perf_counter() - t
+    t = time.perf_counter()
+    B.HostTree(x, v, z, z, m, cfg.n_leaf, cfg.n_crit, cfg.theta)
+    t_product_tree = time.perf_counter() - t
     xs, vs, ms = x[tr.perm], v[tr.perm], m[tr.perm]
     XP, VP, MM = np.vstack([xs, tr.node_x]), np.vstack([vs, tr.node_v]), np.concatenate([ms, tr.node_m])
     rng = np.random.default_rng(99)
@@ -261,9 +268,19 @@ def cpu_baseline(W, cfg, seconds):
         done_pairs += ids.size * int(lo[g + 1] - lo[g])
         used += ids.size
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-    return dict(value=done_pairs / spent, unit="interactions/s", cores=threads, kind="oracle",
+    # the direct sum on a random sample of 1024 particles, against all N
+    ids = np.sort(rng.choice(cfg.n, 1024, replace=False)).astype(np.int32)
+    t = time.perf_counter()
+    O.force_direct(ids, xs, vs, ms, cfg.eps2)
+    t_direct = time.perf_counter() - t
+    base = dict(value=done_pairs / spent, unit="interactions/s", cores=threads, kind="oracle",
                 sample=f"list force on all {used} particles of {k} random groups of the t=0 tree "
                        f"({done_pairs:.3g} pairs, {spent:.1f} s)")
+    extra = dict(direct_interactions_per_s=1024 * (cfg.n - 1) / t_direct,
+                 direct_sample=f"direct sum on 1024 random particles against all {cfg.n} ({t_direct:.2f} s)",
+                 tree_build_s={"oracle": t_oracle_tree, "product_host_builder": t_product_tree},
+                 cores=threads)
+    return base, extra
 
 
 def bench_ensemble(args, torch):
@@ -528,8 +545,9 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle list force for about {args.cpu_seconds:.0f} s")
-        cpu = cpu_baseline(W, cfg, args.cpu_seconds)
-        log(f"cpu baseline: {cpu['value']:.4g} interactions/s on {cpu['cores']} threads")
+        cpu, cpu_extra = cpu_baseline(W, cfg, args.cpu_seconds)
+        log(f"cpu baseline: {cpu['value']:.4g} interactions/s on {cpu['cores']} threads; direct "
+            f"{cpu_extra['direct_interactions_per_s']:.4g}; tree build {cpu_extra['tree_build_s']}")
 
     K = args.steps
     if args.dump_steps:
@@ -591,6 +609,7 @@ def main():
         result["all_active_step"] = all_active
     if cpu is not None:
         result["cpu_baseline"] = cpu
+        result["cpu_oracle_other"] = cpu_extra
     print(json.dumps(result), flush=True)
 
 
