@@ -405,6 +405,7 @@ def main():
     ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-all-active", action="store_true")
+    ap.add_argument("--no-resident", action="store_true", help="skip the device-resident integration leg")
     ap.add_argument("--n", type=int, default=0, help="override N (testing only; not the benchmark)")
     ap.add_argument("--n-crit", type=int, default=0, help="override the group size bound n_crit (sweeps)")
     ap.add_argument("--dump-steps", default="", help="write per-step (n_active, pairs, items, ms) JSON here")
@@ -460,12 +461,37 @@ def main():
         if time.perf_counter() - last > 10:
             last = time.perf_counter()
             log(f"start-up t={sim.t:.6g} block steps {sim.n_block_steps}")
+    t_host_startup = time.perf_counter() - t_start
+    steps_startup, psteps_startup = sim.n_block_steps, sim.n_particle_steps
     rec_all = Recorded(sim)
     t_all = sim.next_time()
     sim.step()   # all particles active, then the rebuild
     rec_all.steps.append((t_all, np.arange(sim.n, dtype=np.int32), None))
     log(f"start-up done: {sim.n_block_steps} block steps, {sim.n_particle_steps} particle steps in "
         f"{time.perf_counter() - t_start:.1f} s")
+    # the same start-up span again with the state resident on the device
+    # (scheduler and corrector there; the host only plans each step's work)
+    integ = None
+    if not args.no_resident:
+        rsim = driver.Simulation(x, v, m, eps2=cfg.eps2, dt_tree=cfg.dt_tree, eta=cfg.eta, theta=cfg.theta,
+                                 n_crit=cfg.n_crit, n_leaf=cfg.n_leaf, precision="mixed", predict_mode="eager",
+                                 resident=True)
+        torch.cuda.synchronize()
+        tr0 = time.perf_counter()
+        while rsim.next_time() < cfg.dt_tree:
+            rsim.step()
+        torch.cuda.synchronize()
+        t_res = time.perf_counter() - tr0
+        same = rsim.n_block_steps == steps_startup and rsim.n_particle_steps == psteps_startup
+        rsim.close()
+        integ = {"span": f"t = 0 to the all-particle step at t = {cfg.dt_tree} ({steps_startup} block steps, "
+                         f"{psteps_startup} particle steps)",
+                 "host_driven_s": t_host_startup, "resident_s": t_res, "same_steps": same,
+                 "block_steps_per_s": {"host_driven": steps_startup / t_host_startup, "resident": steps_startup / t_res},
+                 "particle_steps_per_s": {"host_driven": psteps_startup / t_host_startup,
+                                          "resident": psteps_startup / t_res}}
+        log(f"integration start-up: host-driven {t_host_startup:.2f} s, resident {t_res:.2f} s "
+            f"({steps_startup / t_res:.0f} block steps/s), same steps {same}")
     rec = Recorded(sim)
     need = args.warmup + args.steps
     while len(rec.steps) < need:
@@ -607,6 +633,8 @@ def main():
         result["fp64_p99_step_ms"] = float(np.percentile(fp64["lat_ms"], 99))
     if all_active is not None:
         result["all_active_step"] = all_active
+    if integ is not None:
+        result["integration"] = integ
     if cpu is not None:
         result["cpu_baseline"] = cpu
         result["cpu_oracle_other"] = cpu_extra

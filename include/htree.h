@@ -161,6 +161,35 @@ int ht_step_graph(ht_ctx *ctx, int32_t n_upd, const int32_t *d_idx, const double
                   int32_t n_active, const int32_t *active_ids, double *d_acc, double *d_jerk_out,
                   double *d_pot);
 
+/* ---------------------------------------------------------------------------
+ * Device-resident integration (steps 2 and 6 of Section 2 on the device; the
+ * host keeps the tree, the lists and the work plan).
+ *
+ * ht_state_enable allocates the context's FP64 particle state on the device
+ * (x, v, a, jerk [N][3], t0, dt, m, pot [N]).  ht_state_set uploads it from host
+ * arrays (the layouts of ht_set_j_particles; pot may be NULL for zeros) and
+ * rewrites the j-records; ht_state_get copies it back (any pointer may be NULL).
+ *
+ * ht_dev_next_block finds, on the device, the next block time t_next = min(t0 +
+ * dt) and the particles due then (ascending), and returns them; *active points
+ * into pinned memory owned by the context, valid until the next call.  It
+ * synchronises with the stream, and fails with HT_ERANGE if the previous
+ * step's corrector produced a block step below 2^-40.
+ *
+ * ht_dev_step then computes the force on that active set at t_next (as
+ * ht_force_async), and on the device applies the Hermite corrector, Aarseth's
+ * step with eta and the block quantisation (largest power of two <= min(step,
+ * dt_tree, 2 dt_old) of which t_next is a multiple), writes the new state,
+ * potential and j-records.  Asynchronous.  It gives the same bits as the host
+ * corrector (htb_correct) given the same forces.  At a tree time the caller
+ * copies the state back, rebuilds, and uploads it again. */
+int ht_state_enable(ht_ctx *ctx);
+int ht_state_set(ht_ctx *ctx, int32_t n, const double *t0, const double *dt, const double *m, const double *x,
+                 const double *v, const double *a, const double *jerk, const double *pot);
+int ht_state_get(ht_ctx *ctx, double *t0, double *dt, double *x, double *v, double *a, double *jerk, double *pot);
+int ht_dev_next_block(ht_ctx *ctx, double *t_next, int64_t *n_active, const int32_t **active);
+int ht_dev_step(ht_ctx *ctx, double eta, double dt_tree);
+
 /* Predicted position and velocity ([n][3]) of combined indices idx[0..n-1]
  * at the current block time, computed by the device predictor. */
 int ht_get_predicted(ht_ctx *ctx, int32_t n, const int32_t *idx, double *xp, double *vp);

@@ -112,6 +112,11 @@ def device_lib():
             "ht_get_predicted": [_vp, i, _c_i32p, _c_dp, _c_dp],
             "ht_step_async": [_vp, i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, d, i, _vp, _vp, _vp, _vp],
             "ht_step_graph": [_vp, i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, d, i, _vp, _vp, _vp, _vp],
+            "ht_state_enable": [_vp],
+            "ht_state_set": [_vp, i, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp],
+            "ht_state_get": [_vp, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp],
+            "ht_dev_next_block": [_vp, ctypes.POINTER(ctypes.c_double), _c_i64p, ctypes.POINTER(_c_i32p)],
+            "ht_dev_step": [_vp, d, d],
             "ht_force_batch_async": [i, ctypes.POINTER(_vp), _c_i32p, ctypes.POINTER(_c_i32p),
                                      ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp)],
             "ht_sync": [_vp],
@@ -339,6 +344,41 @@ class Context:
             n_upd, ptrs = int(upd[0]), tuple(_dptr(u) for u in upd[1:])
         _check(device_lib().ht_step_graph(self._h, n_upd, *ptrs, float(t), active.shape[0], active.ctypes.data,
                                           _dptr(d_acc), _dptr(d_jerk), _dptr(d_pot)))
+
+    # device-resident integration ------------------------------------------------
+    def state_enable(self):
+        _check(device_lib().ht_state_enable(self._h))
+
+    def state_set(self, t0, dt, m, x, v, a, jerk, pot=None):
+        """ht_state_set: full FP64 state (and the j-records) from host arrays."""
+        n = np.asarray(t0).shape[0]
+        d = ctypes.c_double
+        arrs = [_arr(t0, np.float64), _arr(dt, np.float64), _arr(m, np.float64), _arr(x, np.float64, (n, 3)),
+                _arr(v, np.float64, (n, 3)), _arr(a, np.float64, (n, 3)), _arr(jerk, np.float64, (n, 3))]
+        p = None if pot is None else _arr(pot, np.float64)
+        _check(device_lib().ht_state_set(self._h, n, *[_ptr(u, d) for u in arrs], _ptr(p, d)))
+
+    def state_get(self, n):
+        """ht_state_get: (t0, dt, x, v, a, jerk, pot) host copies of the device state."""
+        t0, dt, pot = np.empty(n), np.empty(n), np.empty(n)
+        x, v, a, j = (np.empty((n, 3)) for _ in range(4))
+        d = ctypes.c_double
+        _check(device_lib().ht_state_get(self._h, *[_ptr(u, d) for u in (t0, dt, x, v, a, j, pot)]))
+        return t0, dt, x, v, a, j, pot
+
+    def dev_next_block(self):
+        """ht_dev_next_block: (t_next, active ids) of the next block step, from the
+        device state (the ids are a copy)."""
+        t = ctypes.c_double()
+        k = ctypes.c_int64()
+        p = _c_i32p()
+        _check(device_lib().ht_dev_next_block(self._h, ctypes.byref(t), ctypes.byref(k), ctypes.byref(p)))
+        act = np.ctypeslib.as_array(p, shape=(k.value,)).copy() if k.value else np.empty(0, np.int32)
+        return t.value, act
+
+    def dev_step(self, eta, dt_tree):
+        """ht_dev_step: force, corrector and j-record update of the last next block, on the device."""
+        _check(device_lib().ht_dev_step(self._h, float(eta), float(dt_tree)))
 
     def get_predicted(self, idx):
         idx = _arr(idx, np.int32)

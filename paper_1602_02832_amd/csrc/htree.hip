@@ -701,6 +701,172 @@ __global__ __launch_bounds__(kWG) void prep_graph_kernel(const GraphHdr* hdr, ui
         store_rec<P>(rec, idx[k], t0[k], m[k], x + 3 * k, v + 3 * k, a + 3 * k, jerk + 3 * k);
 }
 
+// ------------------------------------------------------------------------------------------------
+// Device-resident integration: the FP64 particle state, the block scheduler
+// (step 2) and the Hermite corrector with Aarseth's step (step 6) on the device.
+
+struct DevState {
+    double *x, *v, *a, *j;        // [N][3] at t0
+    double *t0, *dt, *m, *pot;    // [N]
+    double *acc, *jerk, *fpot;    // this step's forces, in active order
+    int32_t* active;              // this step's active particles, ascending
+    double* bmin;                 // per scheduler block: earliest next time
+    int32_t* bcount;              // per scheduler block: particles due then
+};
+
+// What the scheduler hands the host, in pinned memory the device writes.
+struct DevOut {
+    double t_next;
+    int64_t n_active;
+    int32_t below_floor;   // a corrected step fell below 2^-40
+    int32_t pad;
+};
+
+constexpr int kSchedBlocks = 1024;   // most scheduler blocks (contiguous particle ranges)
+
+__device__ __forceinline__ double block_min(double v, double* red) {
+    for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_down(v, o, 64));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    return fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+}
+
+// pass 1: the earliest next time t0 + dt of every block's range
+__global__ __launch_bounds__(kWG) void sched_min_kernel(DevState s, int64_t n, int64_t chunk) {
+    __shared__ double red[4];
+    const int64_t lo = blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
+    double v = HUGE_VAL;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kWG) v = fmin(v, s.t0[i] + s.dt[i]);
+    v = block_min(v, red);
+    if (threadIdx.x == 0) s.bmin[blockIdx.x] = v;
+}
+
+// pass 2: every block finds t_next over all blocks and counts its particles due then
+__global__ __launch_bounds__(kWG) void sched_count_kernel(DevState s, int64_t n, int64_t chunk, int nb, DevOut* out) {
+    __shared__ double red[4];
+    __shared__ int cnt[4];
+    double v = HUGE_VAL;
+    for (int b = threadIdx.x; b < nb; b += kWG) v = fmin(v, s.bmin[b]);
+    const double t_next = block_min(v, red);
+    const int64_t lo = blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
+    int c = 0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kWG) c += s.t0[i] + s.dt[i] == t_next;
+    for (int o = 32; o >= 1; o >>= 1) c += __shfl_down(c, o, 64);
+    if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s.bcount[blockIdx.x] = cnt[0] + cnt[1] + cnt[2] + cnt[3];
+        if (blockIdx.x == 0) out->t_next = t_next;
+    }
+}
+
+// pass 3: every block writes its due particles, in order, after those of the
+// blocks before it, into the device list and the host's pinned copy
+__global__ __launch_bounds__(kWG) void sched_write_kernel(DevState s, int64_t n, int64_t chunk, int nb, DevOut* out,
+                                                          int32_t* active_host) {
+    __shared__ double red[4];
+    __shared__ int64_t part[4];
+    __shared__ int wsum[4];
+    double v = HUGE_VAL;
+    for (int b = threadIdx.x; b < nb; b += kWG) v = fmin(v, s.bmin[b]);
+    const double t_next = block_min(v, red);
+    int64_t before = 0;
+    for (int b = threadIdx.x; b < static_cast<int>(blockIdx.x); b += kWG) before += s.bcount[b];
+    for (int o = 32; o >= 1; o >>= 1) before += __shfl_down(before, o, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) part[wave] = before;
+    __syncthreads();
+    int64_t pos = part[0] + part[1] + part[2] + part[3];
+    const int64_t lo = blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
+    for (int64_t base = lo; base < hi; base += kWG) {
+        const int64_t i = base + threadIdx.x;
+        const bool due = i < hi && s.t0[i] + s.dt[i] == t_next;
+        const uint64_t mask = __ballot(due);
+        const int below = __popcll(mask & ((1ull << lane) - 1ull));
+        __syncthreads();
+        if (lane == 0) wsum[wave] = __popcll(mask);
+        __syncthreads();
+        int64_t at = pos + below;
+        for (int w = 0; w < wave; ++w) at += wsum[w];
+        if (due) {
+            s.active[at] = static_cast<int32_t>(i);
+            active_host[at] = static_cast<int32_t>(i);
+        }
+        pos += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    }
+    if (blockIdx.x == static_cast<unsigned>(nb - 1) && threadIdx.x == 0) out->n_active = pos;
+}
+
+// Step 6 on the device: the Hermite corrector from (a0, jerk0) at t0 to the
+// forces at t1, Aarseth's step with eta, and the block step (largest power of
+// two <= min(step, dt_tree, 2 dt_old) of which t1 is a multiple); then the new
+// j-record.  Same operations in the same order as the host corrector, with no
+// contraction into fused multiply-adds, so both give the same bits.
+__device__ __forceinline__ double dev_len3(double x, double y, double z) {
+#pragma clang fp contract(off)
+    return sqrt(x * x + y * y + z * z);
+}
+
+__device__ __forceinline__ double dev_quantise(double cap, double t1) {
+    if (!(cap > 0.0)) return 0.0;
+    int e;
+    frexp(cap, &e);
+    int jj = e - 1;
+    if (t1 != 0.0) {
+        int et;
+        const double mt = frexp(fabs(t1), &et);
+        const uint64_t mm = static_cast<uint64_t>(ldexp(mt, 53));
+        const int v = et - 53 + __builtin_ctzll(mm);
+        jj = v < jj ? v : jj;
+    }
+    return jj >= -40 ? ldexp(1.0, jj) : 0.0;
+}
+
+template <class P>
+__global__ __launch_bounds__(kWG) void dev_correct_kernel(DevState s, void* rec_base, int64_t n_active, double t1,
+                                                          double eta, double dt_tree, DevOut* out) {
+#pragma clang fp contract(off)
+    typename P::Rec* rec = static_cast<typename P::Rec*>(rec_base);
+    for (int64_t q = blockIdx.x * static_cast<int64_t>(kWG) + threadIdx.x; q < n_active;
+         q += static_cast<int64_t>(gridDim.x) * kWG) {
+        const int32_t i = s.active[q];
+        const double D = t1 - s.t0[i];
+        const double h2 = 0.5 * D, h3 = D / 3.0;
+        const double D2 = D * D, D3 = D2 * D, D4 = D2 * D2, D5 = D4 * D;
+        double s2[3], s3[3], s2n[3], a1[3], j1[3];
+        for (int d = 0; d < 3; ++d) {
+            const int64_t k = 3 * static_cast<int64_t>(i) + d;
+            a1[d] = s.acc[3 * q + d];
+            j1[d] = s.jerk[3 * q + d];
+            const double xp = s.x[k] + D * (s.v[k] + h2 * (s.a[k] + h3 * s.j[k]));
+            const double vp = s.v[k] + D * (s.a[k] + h2 * s.j[k]);
+            const double diff = s.a[k] - a1[d];
+            s2[d] = (-6.0 * diff - D * (4.0 * s.j[k] + 2.0 * j1[d])) / D2;
+            s3[d] = (12.0 * diff + 6.0 * D * (s.j[k] + j1[d])) / D3;
+            s.x[k] = xp + s2[d] * (D4 / 24.0) + s3[d] * (D5 / 120.0);
+            s.v[k] = vp + s2[d] * (D3 / 6.0) + s3[d] * (D4 / 24.0);
+            s.a[k] = a1[d];
+            s.j[k] = j1[d];
+            s2n[d] = s2[d] + D * s3[d];
+        }
+        const double na = dev_len3(a1[0], a1[1], a1[2]), nj = dev_len3(j1[0], j1[1], j1[2]);
+        const double n2 = dev_len3(s2n[0], s2n[1], s2n[2]), n3 = dev_len3(s3[0], s3[1], s3[2]);
+        const double den = nj * n3 + n2 * n2;
+        const double raw = den > 0.0 ? sqrt(eta * (na * n2 + nj * nj) / den) : dt_tree;
+        double cap = dt_tree < raw ? dt_tree : raw;   // std::min(raw, dt_tree), then with 2 dt_old
+        cap = 2.0 * s.dt[i] < cap ? 2.0 * s.dt[i] : cap;
+        const double h = dev_quantise(cap, t1);
+        if (h == 0.0) out->below_floor = 1;
+        s.t0[i] = t1;
+        s.dt[i] = h;
+        s.pot[i] = s.fpot[q];
+        const int64_t k = 3 * static_cast<int64_t>(i);
+        store_rec<P>(rec, i, t1, s.m[i], s.x + k, s.v + k, s.a + k, s.j + k);
+    }
+}
+
 // Batched j-memory update: rows of several clusters in one launch.
 struct UpdEntry {
     void* rec;            // the cluster's records
@@ -866,6 +1032,14 @@ struct ht_ctx {
     bool hdr_pending[kGraphSlots] = {};
     int gslot = 0;
     GraphHdr* h_hdr = nullptr;
+    // device-resident integration (ht_state_enable): FP64 state and scheduler
+    // buffers on the device, the scheduler's results in pinned host memory
+    DevState ds{};
+    char* ds_mem = nullptr;
+    DevOut* h_dout = nullptr;
+    int32_t* h_active = nullptr;
+    double dev_t_next = 0.0;
+    int64_t dev_n_active = -1;   // active set of the last ht_dev_next_block, -1 once stepped
     // scratch for planning
     std::vector<Item> items;
     std::vector<RTile> rtiles;
@@ -1421,6 +1595,9 @@ int ht_destroy(ht_ctx* c) {
     }
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->h_hdr) (void)hipHostFree(c->h_hdr);
+    if (c->ds_mem) (void)hipFree(c->ds_mem);
+    if (c->h_dout) (void)hipHostFree(c->h_dout);
+    if (c->h_active) (void)hipHostFree(c->h_active);
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
     if (c->own_ws && c->ws) (void)hipFree(c->ws);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -1710,6 +1887,129 @@ int ht_step_graph(ht_ctx* c, int32_t n_upd, const int32_t* d_idx, const double* 
     c->hdr_pending[k] = true;
     c->gslot = (k + 1) % ht_ctx::kGraphSlots;
     return c->slot_release();
+}
+
+// ------------------------------------------------------------------------------------------------
+// device-resident integration
+int ht_state_enable(ht_ctx* c) {
+    if (!c) return fail(HT_EINVAL, "ctx is NULL");
+    if (c->ds_mem) return HT_OK;
+    const size_t n = static_cast<size_t>(c->cfg.n_max);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    const size_t ox = take(n * 24), ov = take(n * 24), oa = take(n * 24), oj = take(n * 24);
+    const size_t ot0 = take(n * 8), odt = take(n * 8), om = take(n * 8), opot = take(n * 8);
+    const size_t oacc = take(n * 24), ojerk = take(n * 24), ofpot = take(n * 8), oact = take(n * 4);
+    const size_t obmin = take(kSchedBlocks * 8), obcnt = take(kSchedBlocks * 4);
+    if (hipMalloc(&c->ds_mem, o) != hipSuccess) {
+        c->ds_mem = nullptr;
+        return fail(HT_ENOMEM, "hipMalloc of %zu bytes for the device state failed", o);
+    }
+    char* b = c->ds_mem;
+    c->ds = DevState{reinterpret_cast<double*>(b + ox), reinterpret_cast<double*>(b + ov),
+                     reinterpret_cast<double*>(b + oa), reinterpret_cast<double*>(b + oj),
+                     reinterpret_cast<double*>(b + ot0), reinterpret_cast<double*>(b + odt),
+                     reinterpret_cast<double*>(b + om), reinterpret_cast<double*>(b + opot),
+                     reinterpret_cast<double*>(b + oacc), reinterpret_cast<double*>(b + ojerk),
+                     reinterpret_cast<double*>(b + ofpot), reinterpret_cast<int32_t*>(b + oact),
+                     reinterpret_cast<double*>(b + obmin), reinterpret_cast<int32_t*>(b + obcnt)};
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->h_dout), sizeof(DevOut), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&c->h_active), n * 4, hipHostMallocDefault) != hipSuccess)
+        return fail(HT_ENOMEM, "hipHostMalloc for the scheduler results failed");
+    std::memset(c->h_dout, 0, sizeof(DevOut));
+    return HT_OK;
+}
+
+int ht_state_set(ht_ctx* c, int32_t n, const double* t0, const double* dt, const double* m, const double* x,
+                 const double* v, const double* a, const double* jerk, const double* pot) {
+    if (!c) return fail(HT_EINVAL, "ctx is NULL");
+    if (!c->ds_mem) return fail(HT_ESTATE, "device state not enabled");
+    const double* vec[] = {t0, dt, m, x, v, a, jerk};
+    if (n < 1 || !check_vectors(vec, 7)) return fail(HT_EINVAL, "bad state arrays");
+    int rc = ht_set_j_particles(c, n, nullptr, t0, m, x, v, a, jerk);   // the j-records
+    if (rc) return rc;
+    const size_t n1 = static_cast<size_t>(n) * 8, n3 = 3 * n1;
+    HT_HIP(hipMemcpyAsync(c->ds.t0, t0, n1, hipMemcpyHostToDevice, c->stream));
+    HT_HIP(hipMemcpyAsync(c->ds.dt, dt, n1, hipMemcpyHostToDevice, c->stream));
+    HT_HIP(hipMemcpyAsync(c->ds.m, m, n1, hipMemcpyHostToDevice, c->stream));
+    HT_HIP(hipMemcpyAsync(c->ds.x, x, n3, hipMemcpyHostToDevice, c->stream));
+    HT_HIP(hipMemcpyAsync(c->ds.v, v, n3, hipMemcpyHostToDevice, c->stream));
+    HT_HIP(hipMemcpyAsync(c->ds.a, a, n3, hipMemcpyHostToDevice, c->stream));
+    HT_HIP(hipMemcpyAsync(c->ds.j, jerk, n3, hipMemcpyHostToDevice, c->stream));
+    if (pot) HT_HIP(hipMemcpyAsync(c->ds.pot, pot, n1, hipMemcpyHostToDevice, c->stream));
+    else HT_HIP(hipMemsetAsync(c->ds.pot, 0, n1, c->stream));
+    HT_HIP(hipStreamSynchronize(c->stream));   // pageable sources
+    c->slots_all_free();
+    c->dev_n_active = -1;
+    return HT_OK;
+}
+
+int ht_state_get(ht_ctx* c, double* t0, double* dt, double* x, double* v, double* a, double* jerk, double* pot) {
+    if (!c) return fail(HT_EINVAL, "ctx is NULL");
+    if (!c->ds_mem) return fail(HT_ESTATE, "device state not enabled");
+    const size_t n1 = static_cast<size_t>(c->n) * 8, n3 = 3 * n1;
+    const struct { double* dst; const double* src; size_t bytes; } cp[] = {
+        {t0, c->ds.t0, n1}, {dt, c->ds.dt, n1}, {x, c->ds.x, n3}, {v, c->ds.v, n3},
+        {a, c->ds.a, n3}, {jerk, c->ds.j, n3}, {pot, c->ds.pot, n1}};
+    for (const auto& k : cp)
+        if (k.dst) HT_HIP(hipMemcpyAsync(k.dst, k.src, k.bytes, hipMemcpyDeviceToHost, c->stream));
+    HT_HIP(hipStreamSynchronize(c->stream));
+    c->slots_all_free();
+    return HT_OK;
+}
+
+int ht_dev_next_block(ht_ctx* c, double* t_next, int64_t* n_active, const int32_t** active) {
+    if (!c || !t_next || !n_active || !active) return fail(HT_EINVAL, "NULL argument");
+    if (!c->ds_mem) return fail(HT_ESTATE, "device state not enabled");
+    if (c->n < 1) return fail(HT_ESTATE, "particles not set");
+    const int64_t n = c->n;
+    const int nb = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(kSchedBlocks, (n + 2047) / 2048)));
+    const int64_t chunk = (n + nb - 1) / nb;
+    sched_min_kernel<<<nb, kWG, 0, c->stream>>>(c->ds, n, chunk);
+    sched_count_kernel<<<nb, kWG, 0, c->stream>>>(c->ds, n, chunk, nb, c->h_dout);
+    sched_write_kernel<<<nb, kWG, 0, c->stream>>>(c->ds, n, chunk, nb, c->h_dout, c->h_active);
+    HT_HIP(hipGetLastError());
+    HT_HIP(hipStreamSynchronize(c->stream));
+    c->slots_all_free();
+    if (c->h_dout->below_floor) {
+        c->h_dout->below_floor = 0;
+        return fail(HT_ERANGE, "a corrected block step fell below 2^-40");
+    }
+    c->dev_t_next = c->h_dout->t_next;
+    c->dev_n_active = c->h_dout->n_active;
+    *t_next = c->dev_t_next;
+    *n_active = c->dev_n_active;
+    *active = c->h_active;
+    return HT_OK;
+}
+
+int ht_dev_step(ht_ctx* c, double eta, double dt_tree) {
+    if (!c) return fail(HT_EINVAL, "ctx is NULL");
+    if (!c->ds_mem) return fail(HT_ESTATE, "device state not enabled");
+    if (!c->have_lists) return fail(HT_ESTATE, "interaction lists not set");
+    if (c->dev_n_active < 1) return fail(HT_ESTATE, "ht_dev_next_block not called since the last step");
+    if (!(eta > 0.0) || !(dt_tree > 0.0)) return fail(HT_EINVAL, "eta and dt_tree must be positive");
+    const int32_t n_act = static_cast<int32_t>(c->dev_n_active);
+    c->t_pred = c->dev_t_next;
+    c->predicted = true;
+    int rc = enqueue_step(c, DevRows{}, c->cfg.predict_mode == HT_PREDICT_EAGER, n_act, c->h_active, c->ds.acc,
+                          c->ds.jerk, c->ds.fpot, false);
+    if (rc) return rc;
+    const int grid = static_cast<int>(std::min<int64_t>((n_act + kWG - 1) / kWG, 65536));
+    if (c->cfg.precision == HT_PREC_FP64)
+        dev_correct_kernel<PrecFp64><<<grid, kWG, 0, c->stream>>>(c->ds, c->ws + c->L.off_rec, n_act, c->dev_t_next,
+                                                                  eta, dt_tree, c->h_dout);
+    else
+        dev_correct_kernel<PrecMixed><<<grid, kWG, 0, c->stream>>>(c->ds, c->ws + c->L.off_rec, n_act, c->dev_t_next,
+                                                                   eta, dt_tree, c->h_dout);
+    HT_HIP(hipGetLastError());
+    c->dev_n_active = -1;
+    c->predicted = false;   // records changed
+    return HT_OK;
 }
 
 int ht_get_predicted(ht_ctx* c, int32_t n, const int32_t* idx, double* xp, double* vp) {

@@ -27,9 +27,11 @@ from . import binding as B
 
 class Simulation:
     def __init__(self, x, v, m, *, eps2, dt_tree, eta, theta=0.5, n_crit=64, n_leaf=1, precision="mixed",
-                 predict_mode="fused", mode="tree", device=0, stream=None, list_headroom=1.5):
+                 predict_mode="fused", mode="tree", device=0, stream=None, list_headroom=1.5, resident=False):
         if mode not in ("tree", "direct"):
             raise ValueError(mode)
+        if resident and mode != "tree":
+            raise ValueError("resident integration runs the tree scheme")
         if not (dt_tree > 0 and math.frexp(dt_tree)[0] == 0.5):
             raise ValueError("dt_tree must be a power of two")
         self.x = np.ascontiguousarray(x, np.float64).reshape(-1, 3).copy()
@@ -52,6 +54,11 @@ class Simulation:
         self.tree = None
         self._ectx = None
         self._act_buf = np.empty(self.n, np.int32)
+        # resident: the particle state lives on the device between tree rebuilds
+        # (scheduler and corrector there); the host arrays are current only after
+        # sync_state() and at tree times
+        self.resident = bool(resident)
+        self._pending_dev = None
         self.n_block_steps = 0
         self.n_particle_steps = 0
         self.n_interactions = 0
@@ -63,6 +70,9 @@ class Simulation:
         self.a, self.j, self.pot = acc, jerk, pot
         self._build_and_send()           # nodes now carry a and jerk; order unchanged
         self.dt = B.initial_steps(self.eta, self.dt_tree, self.a, self.j)
+        if self.resident:
+            self.ctx.state_enable()
+            self.ctx.state_set(self.t0, self.dt, self.m, self.x, self.v, self.a, self.j, self.pot)
 
     # ------------------------------------------------------------------ context
     def _make_ctx(self, node_max, group_max, list_max):
@@ -119,7 +129,16 @@ class Simulation:
         return out
 
     def next_time(self):
+        if self.resident:
+            if self._pending_dev is None:
+                self._pending_dev = self.ctx.dev_next_block()
+            return self._pending_dev[0]
         return float(np.min(self.t0 + self.dt))
+
+    def sync_state(self):
+        """Resident mode: copy the device state into the host arrays."""
+        if self.resident:
+            self.t0, self.dt, self.x, self.v, self.a, self.j, self.pot = self.ctx.state_get(self.n)
 
     def begin_step(self):
         """Steps 2 and 5 (prediction): pick the next block time and its active
@@ -153,8 +172,32 @@ class Simulation:
         return B.make_rows(active, self.t0[active], self.m[active], self.x[active], self.v[active], self.a[active],
                            self.j[active])
 
+    def _step_resident(self):
+        if self._pending_dev is None:
+            self._pending_dev = self.ctx.dev_next_block()
+        tn, active = self._pending_dev
+        self._pending_dev = None
+        t_start = time.perf_counter()
+        self.ctx.dev_step(self.eta, self.dt_tree)
+        pairs, _ = self.ctx.last_stats()
+        self.n_interactions += pairs
+        self.timers["force"] += time.perf_counter() - t_start
+        self.t = tn
+        self.n_block_steps += 1
+        self.n_particle_steps += active.size
+        if math.fmod(tn, self.dt_tree) == 0.0:
+            self.sync_state()
+            if not np.all(self.t0 == tn):
+                raise AssertionError("particles not synchronised at a tree time")
+            self._build_and_send()
+            self.ctx.state_enable()    # the rebuild may have made a larger context
+            self.ctx.state_set(self.t0, self.dt, self.m, self.x, self.v, self.a, self.j, self.pot)
+        return tn, active
+
     def step(self):
         """One block step; returns (t, active ids)."""
+        if self.resident:
+            return self._step_resident()
         tn, active = self.begin_step()
         acc, jerk, pot = self._force(active)
         rows = self.finish_step(acc, jerk, pot)
@@ -177,6 +220,7 @@ class Simulation:
         """Total energy at the current (synchronised) time: kinetic on the host,
         potential by direct summation on the GPU in FP64 (Section 3 computes
         the potential energy directly, not with the tree)."""
+        self.sync_state()
         if not np.all(self.t0 == self.t):
             raise ValueError("energy needs all particles at the same time")
         if self._ectx is None:
