@@ -256,6 +256,17 @@ int ht_batch_force_async(ht_batch *b, int32_t n_ctx, ht_ctx *const *ctxs, const 
                          const int32_t *const *active_ids, double *const *d_acc, double *const *d_jerk,
                          double *const *d_pot);
 
+/* Device-resident steps for several contexts (each with ht_state_enable):
+ * ht_batch_dev_next_block runs the scheduler of ht_dev_next_block for all of
+ * them in one set of launches and returns t_next[k], n_active[k] and active[k]
+ * (pinned, owned by ctxs[k]); ht_batch_dev_step then runs the force on all
+ * those active sets in one launch (as ht_batch_force_async) and the corrector
+ * for all of them in one more, with eta[k] and dt_tree[k] per context.  Same
+ * results per context as its own ht_dev_next_block / ht_dev_step. */
+int ht_batch_dev_next_block(ht_batch *b, int32_t n_ctx, ht_ctx *const *ctxs, double *t_next, int64_t *n_active,
+                            const int32_t **active);
+int ht_batch_dev_step(ht_batch *b, int32_t n_ctx, ht_ctx *const *ctxs, const double *eta, const double *dt_tree);
+
 int ht_batch_sync(ht_batch *b);
 int ht_batch_set_timing(ht_batch *b, int32_t enable);
 int ht_batch_kernel_timing(ht_batch *b, double *force_ms, int64_t *launches, int64_t *pairs);

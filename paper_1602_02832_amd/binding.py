@@ -494,6 +494,15 @@ class Batch:
         int32; the others arrays of n addresses)."""
         _check(_raw("ht_batch_force_async", 8)(self._h.value, n, handles, n_active, ids, d_accs, d_jerks, d_pots))
 
+    def dev_next_block_raw(self, n, handles, t_next, n_active, active):
+        """ht_batch_dev_next_block with every array given by address (t_next: n
+        float64, n_active: n int64, active: n addresses, all written)."""
+        _check(_raw("ht_batch_dev_next_block", 6)(self._h.value, n, handles, t_next, n_active, active))
+
+    def dev_step_raw(self, n, handles, eta, dt_tree):
+        """ht_batch_dev_step with every array given by address (eta, dt_tree: n float64)."""
+        _check(_raw("ht_batch_dev_step", 5)(self._h.value, n, handles, eta, dt_tree))
+
     def force_async(self, ctxs, actives, d_accs, d_jerks, d_pots):
         n = len(ctxs)
         acts = [_arr(a, np.int32) for a in actives]

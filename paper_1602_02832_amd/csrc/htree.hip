@@ -733,56 +733,91 @@ __device__ __forceinline__ double block_min(double v, double* red) {
     return fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
 }
 
-// pass 1: the earliest next time t0 + dt of every block's range
-__global__ __launch_bounds__(kWG) void sched_min_kernel(DevState s, int64_t n, int64_t chunk) {
-    __shared__ double red[4];
-    const int64_t lo = blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
-    double v = HUGE_VAL;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += kWG) v = fmin(v, s.t0[i] + s.dt[i]);
-    v = block_min(v, red);
-    if (threadIdx.x == 0) s.bmin[blockIdx.x] = v;
+// One context in a scheduler launch: its state, its blocks (contiguous ranges
+// of chunk particles) and where its results go.  A launch over one context
+// passes its entry by value; a batched launch passes a table in device memory
+// and every block finds its context by its first block.
+struct SchedEntry {
+    const double* t0;
+    const double* dt;
+    int32_t* active;
+    double* bmin;
+    int32_t* bcount;
+    int64_t n, chunk;
+    int32_t nb, first_block;
+    DevOut* out;
+    int32_t* active_host;
+};
+
+__device__ __forceinline__ const SchedEntry& sched_entry(const SchedEntry& e0, const SchedEntry* tab, int n_tab,
+                                                         int& b) {
+    b = blockIdx.x;
+    if (n_tab == 0) return e0;
+    int lo = 0, hi = n_tab;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tab[mid].first_block <= b) lo = mid; else hi = mid;
+    }
+    b -= tab[lo].first_block;
+    return tab[lo];
 }
 
-// pass 2: every block finds t_next over all blocks and counts its particles due then
-__global__ __launch_bounds__(kWG) void sched_count_kernel(DevState s, int64_t n, int64_t chunk, int nb, DevOut* out) {
+// pass 1: the earliest next time t0 + dt of every block's range
+__global__ __launch_bounds__(kWG) void sched_min_kernel(SchedEntry e0, const SchedEntry* tab, int n_tab) {
+    __shared__ double red[4];
+    int b;
+    const SchedEntry& e = sched_entry(e0, tab, n_tab, b);
+    const int64_t lo = b * e.chunk, hi = lo + e.chunk < e.n ? lo + e.chunk : e.n;
+    double v = HUGE_VAL;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kWG) v = fmin(v, e.t0[i] + e.dt[i]);
+    v = block_min(v, red);
+    if (threadIdx.x == 0) e.bmin[b] = v;
+}
+
+// pass 2: every block finds its context's t_next over all of that context's
+// blocks and counts its particles due then
+__global__ __launch_bounds__(kWG) void sched_count_kernel(SchedEntry e0, const SchedEntry* tab, int n_tab) {
     __shared__ double red[4];
     __shared__ int cnt[4];
+    int b;
+    const SchedEntry& e = sched_entry(e0, tab, n_tab, b);
     double v = HUGE_VAL;
-    for (int b = threadIdx.x; b < nb; b += kWG) v = fmin(v, s.bmin[b]);
+    for (int k = threadIdx.x; k < e.nb; k += kWG) v = fmin(v, e.bmin[k]);
     const double t_next = block_min(v, red);
-    const int64_t lo = blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
+    const int64_t lo = b * e.chunk, hi = lo + e.chunk < e.n ? lo + e.chunk : e.n;
     int c = 0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += kWG) c += s.t0[i] + s.dt[i] == t_next;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kWG) c += e.t0[i] + e.dt[i] == t_next;
     for (int o = 32; o >= 1; o >>= 1) c += __shfl_down(c, o, 64);
     if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = c;
     __syncthreads();
     if (threadIdx.x == 0) {
-        s.bcount[blockIdx.x] = cnt[0] + cnt[1] + cnt[2] + cnt[3];
-        if (blockIdx.x == 0) out->t_next = t_next;
+        e.bcount[b] = cnt[0] + cnt[1] + cnt[2] + cnt[3];
+        if (b == 0) e.out->t_next = t_next;
     }
 }
 
 // pass 3: every block writes its due particles, in order, after those of the
-// blocks before it, into the device list and the host's pinned copy
-__global__ __launch_bounds__(kWG) void sched_write_kernel(DevState s, int64_t n, int64_t chunk, int nb, DevOut* out,
-                                                          int32_t* active_host) {
+// earlier blocks of its context, into the device list and the host's copy
+__global__ __launch_bounds__(kWG) void sched_write_kernel(SchedEntry e0, const SchedEntry* tab, int n_tab) {
     __shared__ double red[4];
     __shared__ int64_t part[4];
     __shared__ int wsum[4];
+    int b;
+    const SchedEntry& e = sched_entry(e0, tab, n_tab, b);
     double v = HUGE_VAL;
-    for (int b = threadIdx.x; b < nb; b += kWG) v = fmin(v, s.bmin[b]);
+    for (int k = threadIdx.x; k < e.nb; k += kWG) v = fmin(v, e.bmin[k]);
     const double t_next = block_min(v, red);
     int64_t before = 0;
-    for (int b = threadIdx.x; b < static_cast<int>(blockIdx.x); b += kWG) before += s.bcount[b];
+    for (int k = threadIdx.x; k < b; k += kWG) before += e.bcount[k];
     for (int o = 32; o >= 1; o >>= 1) before += __shfl_down(before, o, 64);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) part[wave] = before;
     __syncthreads();
     int64_t pos = part[0] + part[1] + part[2] + part[3];
-    const int64_t lo = blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
+    const int64_t lo = b * e.chunk, hi = lo + e.chunk < e.n ? lo + e.chunk : e.n;
     for (int64_t base = lo; base < hi; base += kWG) {
         const int64_t i = base + threadIdx.x;
-        const bool due = i < hi && s.t0[i] + s.dt[i] == t_next;
+        const bool due = i < hi && e.t0[i] + e.dt[i] == t_next;
         const uint64_t mask = __ballot(due);
         const int below = __popcll(mask & ((1ull << lane) - 1ull));
         __syncthreads();
@@ -791,12 +826,12 @@ __global__ __launch_bounds__(kWG) void sched_write_kernel(DevState s, int64_t n,
         int64_t at = pos + below;
         for (int w = 0; w < wave; ++w) at += wsum[w];
         if (due) {
-            s.active[at] = static_cast<int32_t>(i);
-            active_host[at] = static_cast<int32_t>(i);
+            e.active[at] = static_cast<int32_t>(i);
+            e.active_host[at] = static_cast<int32_t>(i);
         }
         pos += wsum[0] + wsum[1] + wsum[2] + wsum[3];
     }
-    if (blockIdx.x == static_cast<unsigned>(nb - 1) && threadIdx.x == 0) out->n_active = pos;
+    if (b == e.nb - 1 && threadIdx.x == 0) e.out->n_active = pos;
 }
 
 // Step 6 on the device: the Hermite corrector from (a0, jerk0) at t0 to the
@@ -824,13 +859,36 @@ __device__ __forceinline__ double dev_quantise(double cap, double t1) {
     return jj >= -40 ? ldexp(1.0, jj) : 0.0;
 }
 
+// One context in a corrector launch: its state and records, its active set
+// (rows first_row .. first_row + n_active - 1 of the launch) and parameters.
+struct CorrEntry {
+    DevState s;
+    void* rec;
+    DevOut* out;
+    int64_t n_active, first_row;
+    double t1, eta, dt_tree;
+};
+
 template <class P>
-__global__ __launch_bounds__(kWG) void dev_correct_kernel(DevState s, void* rec_base, int64_t n_active, double t1,
-                                                          double eta, double dt_tree, DevOut* out) {
+__global__ __launch_bounds__(kWG) void dev_correct_kernel(CorrEntry e0, const CorrEntry* tab, int n_tab,
+                                                          int64_t total) {
 #pragma clang fp contract(off)
-    typename P::Rec* rec = static_cast<typename P::Rec*>(rec_base);
-    for (int64_t q = blockIdx.x * static_cast<int64_t>(kWG) + threadIdx.x; q < n_active;
-         q += static_cast<int64_t>(gridDim.x) * kWG) {
+    for (int64_t r = blockIdx.x * static_cast<int64_t>(kWG) + threadIdx.x; r < total;
+         r += static_cast<int64_t>(gridDim.x) * kWG) {
+        const CorrEntry* ep = &e0;
+        if (n_tab > 0) {
+            int lo = 0, hi = n_tab;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (tab[mid].first_row <= r) lo = mid; else hi = mid;
+            }
+            ep = tab + lo;
+        }
+        const CorrEntry& e = *ep;
+        const DevState& s = e.s;
+        typename P::Rec* rec = static_cast<typename P::Rec*>(e.rec);
+        const int64_t q = r - e.first_row;
+        const double t1 = e.t1;
         const int32_t i = s.active[q];
         const double D = t1 - s.t0[i];
         const double h2 = 0.5 * D, h3 = D / 3.0;
@@ -854,11 +912,11 @@ __global__ __launch_bounds__(kWG) void dev_correct_kernel(DevState s, void* rec_
         const double na = dev_len3(a1[0], a1[1], a1[2]), nj = dev_len3(j1[0], j1[1], j1[2]);
         const double n2 = dev_len3(s2n[0], s2n[1], s2n[2]), n3 = dev_len3(s3[0], s3[1], s3[2]);
         const double den = nj * n3 + n2 * n2;
-        const double raw = den > 0.0 ? sqrt(eta * (na * n2 + nj * nj) / den) : dt_tree;
-        double cap = dt_tree < raw ? dt_tree : raw;   // std::min(raw, dt_tree), then with 2 dt_old
+        const double raw = den > 0.0 ? sqrt(e.eta * (na * n2 + nj * nj) / den) : e.dt_tree;
+        double cap = e.dt_tree < raw ? e.dt_tree : raw;   // std::min(raw, dt_tree), then with 2 dt_old
         cap = 2.0 * s.dt[i] < cap ? 2.0 * s.dt[i] : cap;
         const double h = dev_quantise(cap, t1);
-        if (h == 0.0) out->below_floor = 1;
+        if (h == 0.0) e.out->below_floor = 1;
         s.t0[i] = t1;
         s.dt[i] = h;
         s.pot[i] = s.fpot[q];
@@ -1773,6 +1831,30 @@ int ht_step_async(ht_ctx* c, int32_t n_upd, const int32_t* d_idx, const double* 
 
 namespace {
 
+// The scheduler's table entry of a context whose blocks start at first_block.
+SchedEntry sched_entry_of(const ht_ctx* c, int32_t first_block) {
+    const int64_t n = c->n;
+    const int nb = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(kSchedBlocks, (n + 2047) / 2048)));
+    return SchedEntry{c->ds.t0, c->ds.dt, c->ds.active, c->ds.bmin, c->ds.bcount, n, (n + nb - 1) / nb, nb,
+                      first_block, c->h_dout, c->h_active};
+}
+
+// The corrector's table entry of a context's last active set, rows from first_row.
+CorrEntry corr_entry_of(const ht_ctx* c, int64_t first_row, double eta, double dt_tree) {
+    return CorrEntry{c->ds, c->ws + c->L.off_rec, c->h_dout, c->dev_n_active, first_row, c->dev_t_next, eta, dt_tree};
+}
+
+int launch_correct(int precision, hipStream_t stream, const CorrEntry& e0, const CorrEntry* tab, int n_tab,
+                   int64_t total) {
+    const int grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((total + kWG - 1) / kWG, 65536)));
+    if (precision == HT_PREC_FP64)
+        dev_correct_kernel<PrecFp64><<<grid, kWG, 0, stream>>>(e0, tab, n_tab, total);
+    else
+        dev_correct_kernel<PrecMixed><<<grid, kWG, 0, stream>>>(e0, tab, n_tab, total);
+    HT_HIP(hipGetLastError());
+    return HT_OK;
+}
+
 constexpr int kGraphForceGrid = 2048;   // fixed force grid of a replay (2 per resident work-group slot)
 constexpr int kGraphCopyBlocks = 256;
 constexpr int kGraphScatterBlocks = 256;
@@ -1966,12 +2048,10 @@ int ht_dev_next_block(ht_ctx* c, double* t_next, int64_t* n_active, const int32_
     if (!c || !t_next || !n_active || !active) return fail(HT_EINVAL, "NULL argument");
     if (!c->ds_mem) return fail(HT_ESTATE, "device state not enabled");
     if (c->n < 1) return fail(HT_ESTATE, "particles not set");
-    const int64_t n = c->n;
-    const int nb = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(kSchedBlocks, (n + 2047) / 2048)));
-    const int64_t chunk = (n + nb - 1) / nb;
-    sched_min_kernel<<<nb, kWG, 0, c->stream>>>(c->ds, n, chunk);
-    sched_count_kernel<<<nb, kWG, 0, c->stream>>>(c->ds, n, chunk, nb, c->h_dout);
-    sched_write_kernel<<<nb, kWG, 0, c->stream>>>(c->ds, n, chunk, nb, c->h_dout, c->h_active);
+    const SchedEntry e = sched_entry_of(c, 0);
+    sched_min_kernel<<<e.nb, kWG, 0, c->stream>>>(e, nullptr, 0);
+    sched_count_kernel<<<e.nb, kWG, 0, c->stream>>>(e, nullptr, 0);
+    sched_write_kernel<<<e.nb, kWG, 0, c->stream>>>(e, nullptr, 0);
     HT_HIP(hipGetLastError());
     HT_HIP(hipStreamSynchronize(c->stream));
     c->slots_all_free();
@@ -1999,14 +2079,9 @@ int ht_dev_step(ht_ctx* c, double eta, double dt_tree) {
     int rc = enqueue_step(c, DevRows{}, c->cfg.predict_mode == HT_PREDICT_EAGER, n_act, c->h_active, c->ds.acc,
                           c->ds.jerk, c->ds.fpot, false);
     if (rc) return rc;
-    const int grid = static_cast<int>(std::min<int64_t>((n_act + kWG - 1) / kWG, 65536));
-    if (c->cfg.precision == HT_PREC_FP64)
-        dev_correct_kernel<PrecFp64><<<grid, kWG, 0, c->stream>>>(c->ds, c->ws + c->L.off_rec, n_act, c->dev_t_next,
-                                                                  eta, dt_tree, c->h_dout);
-    else
-        dev_correct_kernel<PrecMixed><<<grid, kWG, 0, c->stream>>>(c->ds, c->ws + c->L.off_rec, n_act, c->dev_t_next,
-                                                                   eta, dt_tree, c->h_dout);
-    HT_HIP(hipGetLastError());
+    const CorrEntry e = corr_entry_of(c, 0, eta, dt_tree);
+    rc = launch_correct(c->cfg.precision, c->stream, e, nullptr, 0, n_act);
+    if (rc) return rc;
     c->dev_n_active = -1;
     c->predicted = false;   // records changed
     return HT_OK;
@@ -2120,10 +2195,11 @@ int ht_force_batch_async(int32_t n_ctx, ht_ctx* const* ctxs, const int32_t* n_ac
 namespace {
 
 size_t batch_plan_bytes(int32_t max_clusters, int64_t max_items, int64_t max_active) {
+    static_assert(sizeof(CorrEntry) <= 256 && sizeof(SchedEntry) <= 256, "per-cluster tables fit 256 bytes");
     return align_up(static_cast<size_t>(max_clusters) * sizeof(Entry)) +
            align_up(static_cast<size_t>(max_items) * sizeof(Item)) +
            align_up(static_cast<size_t>(max_items) * sizeof(RTile)) + align_up(static_cast<size_t>(max_active) * 4) +
-           static_cast<size_t>(max_clusters) * 3 * 256;
+           static_cast<size_t>(max_clusters) * 4 * 256;   // per-cluster alignment and the resident step's tables
 }
 
 size_t batch_rows_bytes(int32_t max_clusters, int64_t max_rows) {
@@ -2338,8 +2414,15 @@ int ht_batch_update_pinned_async(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs
     return batch_update(b, n_ctx, ctxs, n_rows, rows, false);
 }
 
-int ht_batch_force_async(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs, const int32_t* n_active,
-                         const int32_t* const* ids, double* const* d_acc, double* const* d_jerk, double* const* d_pot) {
+}  // extern "C"
+
+namespace {
+
+// The batched force launch; `extra` (extra_bytes) is appended to the packed
+// plan and reaches the device with it, at *extra_dev.
+int batch_force(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs, const int32_t* n_active, const int32_t* const* ids,
+                double* const* d_acc, double* const* d_jerk, double* const* d_pot, const void* extra,
+                size_t extra_bytes, char** extra_dev) {
     if (!b) return fail(HT_EINVAL, "batch is NULL");
     if (n_ctx < 0 || n_ctx > b->max_clusters) return fail(HT_EINVAL, "n_ctx = %d outside [0, %d]", n_ctx, b->max_clusters);
     b->last_pairs = 0;
@@ -2389,6 +2472,12 @@ int ht_batch_force_async(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs, const 
         b->tab.push_back(e);
     }
     if (b->tab.empty()) return HT_OK;
+    if (extra_bytes) {
+        at = align_up(at);
+        if (at + extra_bytes <= b->plan_bytes) std::memcpy(hs + at, extra, extra_bytes);
+        *extra_dev = dv + at;
+        at += extra_bytes;
+    }
     if (at > b->plan_bytes) return fail(HT_ERANGE, "batch plan over its capacity");
     b->tab[0].n_items = n_items;
     b->tab[0].n_rtiles = n_rtiles;
@@ -2405,6 +2494,107 @@ int ht_batch_force_async(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs, const 
     if (ctxs[0]->cfg.precision == HT_PREC_FP64)
         return launch_force<PrecFp64>(b->stream, eager, b->tm, d_tab, nt, n_items, n_rtiles, false, pairs);
     return launch_force<PrecMixed>(b->stream, eager, b->tm, d_tab, nt, n_items, n_rtiles, false, pairs);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ht_batch_force_async(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs, const int32_t* n_active,
+                         const int32_t* const* ids, double* const* d_acc, double* const* d_jerk, double* const* d_pot) {
+    return batch_force(b, n_ctx, ctxs, n_active, ids, d_acc, d_jerk, d_pot, nullptr, 0, nullptr);
+}
+
+// ------------------------------------------------------------------------------------------------
+// device-resident batched steps
+int ht_batch_dev_next_block(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs, double* t_next, int64_t* n_active,
+                            const int32_t** active) {
+    if (!b) return fail(HT_EINVAL, "batch is NULL");
+    if (n_ctx < 1 || n_ctx > b->max_clusters) return fail(HT_EINVAL, "n_ctx = %d outside [1, %d]", n_ctx, b->max_clusters);
+    if (!ctxs || !t_next || !n_active || !active) return fail(HT_EINVAL, "NULL argument");
+    std::vector<SchedEntry> tab;
+    tab.reserve(n_ctx);
+    int32_t blocks = 0;
+    for (int32_t k = 0; k < n_ctx; ++k) {
+        ht_ctx* c = ctxs[k];
+        int rc = check_member(b, c, k, ctxs);
+        if (rc) return rc;
+        if (!c->ds_mem) return fail(HT_ESTATE, "ctx %d: device state not enabled", k);
+        if (c->n < 1) return fail(HT_ESTATE, "ctx %d: particles not set", k);
+        tab.push_back(sched_entry_of(c, blocks));
+        blocks += tab.back().nb;
+    }
+    int rc = ring_acquire(b->plan_ring);
+    if (rc) return rc;
+    const size_t bytes = tab.size() * sizeof(SchedEntry);
+    std::memcpy(b->plan_ring.host(), tab.data(), bytes);
+    rc = launch_prep_any(ctxs[0]->cfg.precision, b->stream, b->plan_ring.host(), b->ws, bytes, nullptr, DevRows{});
+    if (rc) return rc;
+    rc = ring_release(b->plan_ring, b->stream);
+    if (rc) return rc;
+    const SchedEntry* d_tab = reinterpret_cast<const SchedEntry*>(b->ws);
+    const SchedEntry none{};
+    sched_min_kernel<<<blocks, kWG, 0, b->stream>>>(none, d_tab, n_ctx);
+    sched_count_kernel<<<blocks, kWG, 0, b->stream>>>(none, d_tab, n_ctx);
+    sched_write_kernel<<<blocks, kWG, 0, b->stream>>>(none, d_tab, n_ctx);
+    HT_HIP(hipGetLastError());
+    HT_HIP(hipStreamSynchronize(b->stream));
+    ring_all_free(b->plan_ring);
+    ring_all_free(b->rows_ring);
+    int bad = -1;
+    for (int32_t k = 0; k < n_ctx; ++k) {
+        ht_ctx* c = ctxs[k];
+        c->slots_all_free();
+        if (c->h_dout->below_floor) {
+            c->h_dout->below_floor = 0;
+            if (bad < 0) bad = k;
+        }
+        c->dev_t_next = c->h_dout->t_next;
+        c->dev_n_active = c->h_dout->n_active;
+        t_next[k] = c->dev_t_next;
+        n_active[k] = c->dev_n_active;
+        active[k] = c->h_active;
+    }
+    if (bad >= 0) return fail(HT_ERANGE, "ctx %d: a corrected block step fell below 2^-40", bad);
+    return HT_OK;
+}
+
+int ht_batch_dev_step(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs, const double* eta, const double* dt_tree) {
+    if (!b) return fail(HT_EINVAL, "batch is NULL");
+    if (n_ctx < 1 || n_ctx > b->max_clusters) return fail(HT_EINVAL, "n_ctx = %d outside [1, %d]", n_ctx, b->max_clusters);
+    if (!ctxs || !eta || !dt_tree) return fail(HT_EINVAL, "NULL argument");
+    std::vector<int32_t> n_act(n_ctx);
+    std::vector<const int32_t*> ids(n_ctx);
+    std::vector<double*> acc(n_ctx), jerk(n_ctx), pot(n_ctx);
+    std::vector<CorrEntry> corr(n_ctx);
+    int64_t rows = 0;
+    for (int32_t k = 0; k < n_ctx; ++k) {
+        ht_ctx* c = ctxs[k];
+        if (!c || !c->ds_mem) return fail(HT_ESTATE, "ctx %d: device state not enabled", k);
+        if (c->dev_n_active < 1) return fail(HT_ESTATE, "ctx %d: no next block since the last step", k);
+        if (!(eta[k] > 0.0) || !(dt_tree[k] > 0.0)) return fail(HT_EINVAL, "ctx %d: eta and dt_tree must be positive", k);
+        c->t_pred = c->dev_t_next;
+        c->predicted = true;
+        n_act[k] = static_cast<int32_t>(c->dev_n_active);
+        ids[k] = c->h_active;
+        acc[k] = c->ds.acc;
+        jerk[k] = c->ds.jerk;
+        pot[k] = c->ds.fpot;
+        corr[k] = corr_entry_of(c, rows, eta[k], dt_tree[k]);
+        rows += n_act[k];
+    }
+    char* d_corr = nullptr;
+    int rc = batch_force(b, n_ctx, ctxs, n_act.data(), ids.data(), acc.data(), jerk.data(), pot.data(), corr.data(),
+                         corr.size() * sizeof(CorrEntry), &d_corr);
+    if (rc) return rc;
+    rc = launch_correct(ctxs[0]->cfg.precision, b->stream, corr[0], reinterpret_cast<const CorrEntry*>(d_corr), n_ctx,
+                        rows);
+    if (rc) return rc;
+    for (int32_t k = 0; k < n_ctx; ++k) {
+        ctxs[k]->dev_n_active = -1;
+        ctxs[k]->predicted = false;
+    }
+    return HT_OK;
 }
 
 int ht_batch_sync(ht_batch* b) {

@@ -186,13 +186,18 @@ class Simulation:
         self.n_block_steps += 1
         self.n_particle_steps += active.size
         if math.fmod(tn, self.dt_tree) == 0.0:
-            self.sync_state()
-            if not np.all(self.t0 == tn):
-                raise AssertionError("particles not synchronised at a tree time")
-            self._build_and_send()
-            self.ctx.state_enable()    # the rebuild may have made a larger context
-            self.ctx.state_set(self.t0, self.dt, self.m, self.x, self.v, self.a, self.j, self.pot)
+            self.rebuild_resident()
         return tn, active
+
+    def rebuild_resident(self):
+        """Resident mode, at a tree time: state back to the host, new tree and
+        lists, state up again."""
+        self.sync_state()
+        if not np.all(self.t0 == self.t):
+            raise AssertionError("particles not synchronised at a tree time")
+        self._build_and_send()
+        self.ctx.state_enable()    # the rebuild may have made a larger context
+        self.ctx.state_set(self.t0, self.dt, self.m, self.x, self.v, self.a, self.j, self.pot)
 
     def step(self):
         """One block step; returns (t, active ids)."""

@@ -61,8 +61,10 @@ class Cluster:
     tree, which fix its device footprint), then activated (context, upload,
     first forces) when it becomes resident."""
 
-    def __init__(self, spec: RunSpec, precision: str, stream, device: int = 0, list_headroom: float = 1.5):
+    def __init__(self, spec: RunSpec, precision: str, stream, device: int = 0, list_headroom: float = 1.5,
+                 resident: bool = False):
         self.spec, self.precision, self.stream, self.device = spec, precision, stream, device
+        self.resident = resident
         self.list_headroom = list_headroom
         x, v, m = W.plummer(spec.n, spec.seed)
         if spec.mass_seed is not None:
@@ -72,7 +74,7 @@ class Cluster:
         tr = B.HostTree(x, v, z, z, m, 1, spec.n_crit, spec.theta)
         h = list_headroom
         self.caps = (max(int(tr.n_node * h), 64), max(int(tr.n_group * h), 16), max(int(tr.n_entries * h), 1024))
-        self.reserve = workspace_bytes(spec.n, *self.caps, precision)
+        self.reserve = workspace_bytes(spec.n, *self.caps, precision) + (state_bytes(spec.n) if resident else 0)
         self.sim = None
         self.pending = (0, 0)    # (first row, count) of its update rows in the engine's row buffer
         self.steps_done = 0
@@ -86,7 +88,8 @@ class Cluster:
             x, v, m = self._ics
             self.sim = driver.Simulation(x, v, m, eps2=eps * eps, dt_tree=spec.dt_tree, eta=spec.eta,
                                          theta=spec.theta, n_crit=spec.n_crit, precision=self.precision,
-                                         device=self.device, stream=self.stream, list_headroom=self.list_headroom)
+                                         device=self.device, stream=self.stream, list_headroom=self.list_headroom,
+                                         resident=self.resident)
             self._ics = None
 
     @property
@@ -98,8 +101,10 @@ class Cluster:
         return self.steps_done >= self.spec.steps
 
     def footprint(self):
-        """Device bytes this run holds (its context workspace)."""
-        return self.sim.ctx.workspace_bytes if self.sim is not None else self.reserve
+        """Device bytes this run holds (its context workspace, and its state when resident)."""
+        if self.sim is None:
+            return self.reserve
+        return self.sim.ctx.workspace_bytes + (state_bytes(self.spec.n) if self.resident else 0)
 
     def close(self):
         if self.sim is not None:
@@ -118,13 +123,24 @@ def workspace_bytes(n, node_max, group_max, list_max, precision="mixed"):
     return int(out.value)
 
 
+def state_bytes(n):
+    """Device bytes of a resident state (ht_state_enable): x, v, a, jerk, the
+    step's acc and jerk (24 B each), t0, dt, m, pot, the step's pot (8 B each),
+    the active list (4 B), per particle, plus the scheduler's block arrays and
+    the 256-byte alignment of each of the 14 arrays."""
+    return int(n) * (6 * 24 + 5 * 8 + 4) + 1024 * 12 + 14 * 256
+
+
 class Engine:
     """Advances a set of clusters one block step each per engine step."""
 
     def __init__(self, precision="mixed", device=0, max_clusters=256, max_active=1 << 21, max_items=1 << 20,
-                 max_rows=1 << 21, rebuild_workers=4):
+                 max_rows=1 << 21, rebuild_workers=4, resident=False):
         import torch
 
+        # resident: each cluster's particle state stays on the device; the block
+        # scheduler and the corrector of all clusters run there in batched launches
+        self.resident = bool(resident)
         self.torch = torch
         self.precision, self.device = precision, device
         self.stream = torch.cuda.Stream(device=device)
@@ -158,7 +174,7 @@ class Engine:
         del dev
 
     def new_cluster(self, spec: RunSpec) -> Cluster:
-        return Cluster(spec, self.precision, self.stream.cuda_stream, self.device)
+        return Cluster(spec, self.precision, self.stream.cuda_stream, self.device, resident=self.resident)
 
     def add(self, c: Cluster):
         if len(self.clusters) >= self.max_clusters:
@@ -226,6 +242,8 @@ class Engine:
                 self._collect_rebuilds(wait=True)
             return []
         n_cl = len(cl)
+        if self.resident:
+            return self._step_resident(cl, t0)
         caches = [self._refresh(c) for c in cl]
         view = np.array([cc[2] for cc in caches], dtype=_HTB_CLUSTER)     # the htb_cluster records
         handles = np.fromiter((cc[0] for cc in caches), dtype=np.uint64, count=n_cl)
@@ -302,6 +320,55 @@ class Engine:
         sub["plan_launch"] += t1 - td
         sub["correct"] += te - t2
         sub["bookkeeping"] += t3 - te
+        self.step_ms.append(1e3 * dt)
+        self.wall += dt
+        self.pairs += pairs
+        self.equiv_pairs += int(sum(int(n) * (c.sim.n - 1) for c, n in zip(cl, n_act)))
+        return finished
+
+    def _step_resident(self, cl, t0):
+        """Engine step with the clusters' state on the device: one batched
+        scheduler (and the step's one synchronisation), one batched force and
+        one batched corrector; the host only plans the work."""
+        n_cl = len(cl)
+        caches = [self._refresh(c) for c in cl]
+        handles = np.fromiter((cc[0] for cc in caches), dtype=np.uint64, count=n_cl)
+        t_next = np.empty(n_cl)
+        n_act = np.empty(n_cl, dtype=np.int64)
+        act_ptr = np.empty(n_cl, dtype=np.uint64)
+        self.batch.dev_next_block_raw(n_cl, handles.ctypes.data, t_next.ctypes.data, n_act.ctypes.data,
+                                      act_ptr.ctypes.data)
+        t1 = time.perf_counter()
+        eta = np.fromiter((c.sim.eta for c in cl), dtype=np.float64, count=n_cl)
+        dtt = np.fromiter((c.sim.dt_tree for c in cl), dtype=np.float64, count=n_cl)
+        self.batch.dev_step_raw(n_cl, handles.ctypes.data, eta.ctypes.data, dtt.ctypes.data)
+        pairs, _ = self.batch.last_stats()
+        t2 = time.perf_counter()
+        finished = []
+        for k, c in enumerate(cl):
+            sim = c.sim
+            n = int(n_act[k])
+            sim.t = float(t_next[k])
+            sim.n_block_steps += 1
+            sim.n_particle_steps += n
+            c.steps_done += 1
+            c.active_sum += n
+            if math.fmod(sim.t, sim.dt_tree) == 0.0:      # tree time: state back, rebuild, state up
+                if self.pool is not None:
+                    self.rebuilding[c] = self.pool.submit(sim.rebuild_resident)
+                else:
+                    sim.rebuild_resident()
+            if c.done:
+                finished.append(c)
+        t3 = time.perf_counter()
+        dt = t3 - t0
+        self.phase["host_begin"] += t1 - t0     # scheduler launches and the step's synchronisation
+        self.phase["device_wait"] += 0.0
+        self.phase["host_finish"] += t3 - t1   # planning, launches, bookkeeping
+        sub = self.subphase
+        sub["schedule_sync"] += t1 - t0
+        sub["plan_launch"] += t2 - t1
+        sub["bookkeeping"] += t3 - t2
         self.step_ms.append(1e3 * dt)
         self.wall += dt
         self.pairs += pairs

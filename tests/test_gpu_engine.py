@@ -23,6 +23,7 @@ def say(msg):
 
 
 def state(sim):
+    sim.sync_state()      # resident clusters keep their state on the device
     order = np.argsort(sim.ids)
     return {f: getattr(sim, f)[order].copy() for f in FIELDS}
 
@@ -145,3 +146,20 @@ def test_engine_matches_single_cluster_simulation():
     sim.close()
     for f in FIELDS:
         assert np.array_equal(got[f], want[f]), f
+
+
+def test_resident_engine_equals_host_engine():
+    """The engine with every cluster's state on the device (batched scheduler
+    and corrector launches) gives the bits of the host-driven engine, through
+    tree rebuilds, alone and in a mix."""
+    say("engine: resident vs host-driven, three clusters")
+    specs = [E.RunSpec(key=k, n=n, seed=600 + k, steps=60, n_crit=64) for k, n in enumerate((700, 2500, 5000))]
+    host, _ = run_engine(specs)
+    dev, (pairs, nsteps, done) = run_engine(specs, resident=True)
+    assert done == [60, 60, 60] and pairs > 0
+    for k in range(len(specs)):
+        for f in FIELDS:
+            assert np.array_equal(host[k][f], dev[k][f]), (k, f)
+    alone, _ = run_engine([specs[1]], resident=True, rebuild_workers=0)
+    for f in FIELDS:
+        assert np.array_equal(alone[0][f], dev[1][f]), f
