@@ -14,12 +14,14 @@ from __future__ import annotations
 
 import ctypes
 import os
+import types
 
 import numpy as np
 
 from . import build as _build
 
-__all__ = ["HTError", "Context", "Batch", "HT_ROW", "make_rows", "HostTree", "force_batch_async", "hilbert_keys",
+__all__ = ["HTError", "Context", "Batch", "HT_ROW", "make_rows", "HostTree", "DeviceTree", "force_batch_async",
+           "hilbert_keys",
            "next_block", "correct", "initial_steps", "device_lib", "host_lib"]
 
 HT_PREC = {"fp64": 0, "mixed": 1}
@@ -37,6 +39,13 @@ class HTError(RuntimeError):
     def __init__(self, code: int, message: str):
         super().__init__(f"htree error {code}: {message}")
         self.code = code
+
+
+class HtdView(ctypes.Structure):
+    """htd_view (include/htree_tree.h): device pointers to a device-built tree."""
+    _fields_ = [(name, ctypes.c_void_p) for name in
+                ("perm", "keys", "x", "v", "a", "jerk", "m", "node_m", "node_x", "node_v", "node_a", "node_j",
+                 "group_first", "list_off", "entries")]
 
 
 class HtbCluster(ctypes.Structure):
@@ -136,11 +145,21 @@ def device_lib():
             "ht_batch_set_timing": [_vp, i],
             "ht_batch_kernel_timing": [_vp, _c_dp, _c_i64p, _c_i64p],
             "ht_batch_last_stats": [_vp, _c_i64p, _c_i32p],
+            "htd_create": [ctypes.POINTER(_vp), i, _vp, i64],
+            "htd_destroy": [_vp],
+            "htd_build": [_vp, i64, _vp, _vp, _vp, _vp, _vp, i, i, d],
+            "htd_sizes": [_vp, _c_i64p, _c_i64p, _c_i64p, _c_i64p],
+            "htd_root": [_vp, _c_dp, _c_dp],
+            "htd_get": [_vp, _c_i64p, ctypes.POINTER(ctypes.c_uint64), _c_dp, _c_dp, _c_dp, _c_dp, _c_dp, _c_i32p,
+                        _c_i64p, _c_i64p, _c_i64p, _c_i64p, _c_i32p],
+            "htd_device_view": [_vp, ctypes.POINTER(HtdView)],
+            "htd_phase_ms": [_vp, _c_dp],
+            "htd_last_error": [],
         }
         for name, args in sig.items():
             f = getattr(L, name)
             f.argtypes = args
-            f.restype = ctypes.c_char_p if name == "ht_last_error" else ctypes.c_int
+            f.restype = ctypes.c_char_p if name in ("ht_last_error", "htd_last_error") else ctypes.c_int
         _ = i64
         _dev = L
     return _dev
@@ -575,6 +594,93 @@ class HostTree:
 
     def list_of(self, g):
         return self.entries[self.list_off[g]:self.list_off[g + 1]]
+
+
+def _check_tree(rc: int):
+    if rc != 0:
+        msg = device_lib().htd_last_error()
+        raise HTError(rc, msg.decode() if msg else "")
+
+
+class DeviceTree:
+    """Step 1 on the device (htd_*): keys, particle order, octree, node moments,
+    groups and lists from particles already in device memory.  `build` takes
+    contiguous float64 device tensors; `get` copies the results into numpy
+    arrays with the same names as HostTree's."""
+
+    PHASES = ("keys", "sort", "cells", "moments", "lists", "csr", "total")
+
+    def __init__(self, n_max: int, device: int = 0, stream=None):
+        self._h = _vp()
+        _check_tree(device_lib().htd_create(ctypes.byref(self._h), int(device), None if stream is None else int(stream),
+                                            int(n_max)))
+        self.n = 0
+
+    def build(self, x, v, a, jerk, m, n_leaf: int, n_crit: int, theta: float):
+        n = int(m.shape[0])
+        for t, shape in ((x, (n, 3)), (v, (n, 3)), (a, (n, 3)), (jerk, (n, 3)), (m, (n,))):
+            if tuple(t.shape) != shape or not t.is_cuda or not t.is_contiguous() or str(t.dtype) != "torch.float64":
+                raise ValueError("DeviceTree.build takes contiguous float64 device tensors of matching shapes")
+        _check_tree(device_lib().htd_build(self._h, n, _dptr(x), _dptr(v), _dptr(a), _dptr(jerk), _dptr(m),
+                                           int(n_leaf), int(n_crit), float(theta)))
+        self.n = n
+        return self.sizes()
+
+    def sizes(self):
+        M, G, E, C = (ctypes.c_int64() for _ in range(4))
+        _check_tree(device_lib().htd_sizes(self._h, ctypes.byref(M), ctypes.byref(G), ctypes.byref(E),
+                                           ctypes.byref(C)))
+        return M.value, G.value, E.value, C.value
+
+    def root(self):
+        lo = np.zeros(3)
+        side = np.zeros(1)
+        _check_tree(device_lib().htd_root(self._h, _ptr(lo, ctypes.c_double), _ptr(side, ctypes.c_double)))
+        return lo, float(side[0])
+
+    def get(self):
+        M, G, E, C = self.sizes()
+        n = self.n
+        r = types.SimpleNamespace(n=n, n_node=M, n_group=G, n_entries=E, n_cell=C)
+        r.perm = np.empty(n, np.int64)
+        r.keys = np.empty(n, np.uint64)
+        r.node_m = np.empty(M)
+        r.node_x, r.node_v, r.node_a, r.node_j = (np.empty((M, 3)) for _ in range(4))
+        r.node_level = np.empty(M, np.int32)
+        r.node_begin = np.empty(M, np.int64)
+        r.node_end = np.empty(M, np.int64)
+        r.group_first = np.empty(G + 1, np.int64)
+        r.list_off = np.empty(G + 1, np.int64)
+        r.entries = np.empty(E, np.int32)
+        d, i64 = ctypes.c_double, ctypes.c_int64
+        _check_tree(device_lib().htd_get(self._h, _ptr(r.perm, i64), _ptr(r.keys, ctypes.c_uint64), _ptr(r.node_m, d),
+                                         _ptr(r.node_x, d), _ptr(r.node_v, d), _ptr(r.node_a, d), _ptr(r.node_j, d),
+                                         _ptr(r.node_level, ctypes.c_int32), _ptr(r.node_begin, i64),
+                                         _ptr(r.node_end, i64), _ptr(r.group_first, i64), _ptr(r.list_off, i64),
+                                         _ptr(r.entries, ctypes.c_int32)))
+        r.lo, r.side = self.root()
+        return r
+
+    def view(self):
+        v = HtdView()
+        _check_tree(device_lib().htd_device_view(self._h, ctypes.byref(v)))
+        return v
+
+    def phase_ms(self):
+        ms = np.zeros(7)
+        _check_tree(device_lib().htd_phase_ms(self._h, _ptr(ms, ctypes.c_double)))
+        return dict(zip(self.PHASES, ms.tolist()))
+
+    def close(self):
+        if self._h:
+            device_lib().htd_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def hilbert_keys(q):
