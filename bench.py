@@ -237,6 +237,33 @@ def tile_mix(rec, warmup):
     return out
 
 
+def bench_tree_build(torch, B, x, v, m, cfg, reps=5):
+    """Step 1 (keys, order, tree, node moments, groups, lists) on the device
+    and with the host builder, from the same particles (a and jerk drawn at
+    random: the cost does not depend on their values)."""
+    rng = np.random.default_rng(6)
+    a, j = rng.standard_normal((2, len(m), 3))
+    dev = [torch.from_numpy(np.ascontiguousarray(u)).cuda() for u in (x, v, a, j, m)]
+    tree = B.DeviceTree(n_max=len(m))
+    tree.build(*dev, cfg.n_leaf, cfg.n_crit, cfg.theta)      # warm-up (allocations)
+    walls, phases = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tree.build(*dev, cfg.n_leaf, cfg.n_crit, cfg.theta)
+        walls.append(1e3 * (time.perf_counter() - t0))
+        phases.append(tree.phase_ms())
+    M, G, E, C = tree.sizes()
+    tree.close()
+    t0 = time.perf_counter()
+    B.HostTree(x, v, a, j, m, cfg.n_leaf, cfg.n_crit, cfg.theta)
+    host_ms = 1e3 * (time.perf_counter() - t0)
+    k = int(np.argsort(walls)[len(walls) // 2])
+    return {"n": int(len(m)), "nodes": M, "groups": G, "list_entries": E, "device_ms": walls[k],
+            "device_phases_ms": {p: round(q, 3) for p, q in phases[k].items()}, "host_builder_ms": host_ms,
+            "host_threads": os.cpu_count(), "speedup": host_ms / walls[k]}
+
+
 def cpu_baseline(W, cfg, seconds):
     """Oracle list force (FP64, OpenMP) on a bounded sample of the workload:
     whole groups of the t = 0 tree, the oracle's own tree and lists."""
@@ -409,6 +436,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-all-active", action="store_true")
     ap.add_argument("--no-resident", action="store_true", help="skip the device-resident integration leg")
+    ap.add_argument("--no-tree-build", action="store_true", help="skip the device tree-build leg")
     ap.add_argument("--host-engine", action="store_true",
                     help="ensemble/served: drive the clusters from the host (scheduler and corrector on the CPU)")
     ap.add_argument("--n", type=int, default=0, help="override N (testing only; not the benchmark)")
@@ -478,25 +506,45 @@ def main():
     # (scheduler and corrector there; the host only plans each step's work)
     integ = None
     if not args.no_resident:
-        rsim = driver.Simulation(x, v, m, eps2=cfg.eps2, dt_tree=cfg.dt_tree, eta=cfg.eta, theta=cfg.theta,
-                                 n_crit=cfg.n_crit, n_leaf=cfg.n_leaf, precision="mixed", predict_mode="eager",
-                                 resident=True)
-        torch.cuda.synchronize()
-        tr0 = time.perf_counter()
-        while rsim.next_time() < cfg.dt_tree:
-            rsim.step()
-        torch.cuda.synchronize()
-        t_res = time.perf_counter() - tr0
-        same = rsim.n_block_steps == steps_startup and rsim.n_particle_steps == psteps_startup
-        rsim.close()
+        def resident_run(device_tree):
+            """The start-up span resident on the device, then the all-particle step
+            at t = dt_tree and the rebuild there (host or device builder)."""
+            rs = driver.Simulation(x, v, m, eps2=cfg.eps2, dt_tree=cfg.dt_tree, eta=cfg.eta, theta=cfg.theta,
+                                   n_crit=cfg.n_crit, n_leaf=cfg.n_leaf, precision="mixed", predict_mode="eager",
+                                   resident=True, device_tree=device_tree)
+            torch.cuda.synchronize()
+            t0_ = time.perf_counter()
+            while rs.next_time() < cfg.dt_tree:
+                rs.step()
+            torch.cuda.synchronize()
+            span = time.perf_counter() - t0_
+            steps = (rs.n_block_steps, rs.n_particle_steps)
+            tree0 = rs.timers["tree"]
+            tb = time.perf_counter()
+            rs.step()                      # the all-particle step, then the rebuild
+            torch.cuda.synchronize()
+            with_rebuild = time.perf_counter() - tb
+            rebuild = rs.timers["tree"] - tree0
+            rs.sync_state()
+            state = (rs.x.copy(), rs.ids.copy())
+            rs.close()
+            return span, steps, with_rebuild, rebuild, state
+        t_res, st_res, tail_host, reb_host, s_host = resident_run(False)
+        _, _, tail_dev, reb_dev, s_dev = resident_run(True)
+        same = st_res == (steps_startup, psteps_startup)
+        same_tree = bool(np.array_equal(s_host[0], s_dev[0]) and np.array_equal(s_host[1], s_dev[1]))
         integ = {"span": f"t = 0 to the all-particle step at t = {cfg.dt_tree} ({steps_startup} block steps, "
                          f"{psteps_startup} particle steps)",
                  "host_driven_s": t_host_startup, "resident_s": t_res, "same_steps": same,
                  "block_steps_per_s": {"host_driven": steps_startup / t_host_startup, "resident": steps_startup / t_res},
                  "particle_steps_per_s": {"host_driven": psteps_startup / t_host_startup,
-                                          "resident": psteps_startup / t_res}}
+                                          "resident": psteps_startup / t_res},
+                 "all_particle_step_and_rebuild_s": {"host_builder": tail_host, "device_builder": tail_dev},
+                 "rebuild_s": {"host_builder": reb_host, "device_builder": reb_dev},
+                 "device_rebuild_same_state": same_tree}
         log(f"integration start-up: host-driven {t_host_startup:.2f} s, resident {t_res:.2f} s "
-            f"({steps_startup / t_res:.0f} block steps/s), same steps {same}")
+            f"({steps_startup / t_res:.0f} block steps/s), same steps {same}; rebuild at t={cfg.dt_tree}: host "
+            f"{reb_host * 1e3:.1f} ms, device {reb_dev * 1e3:.1f} ms, same state {same_tree}")
     rec = Recorded(sim)
     need = args.warmup + args.steps
     while len(rec.steps) < need:
@@ -572,6 +620,13 @@ def main():
         log(f"all-particle step: {1e3 * wall:.2f} ms, {pairs_all / wall:.4g} pairs/s, kernel {kms / nl:.2f} ms")
         ctx.close()
 
+    # ---- step 1 on the device (htd_build) against the host builder, same state
+    tree_build = None
+    if not args.no_tree_build:
+        tree_build = bench_tree_build(torch, B, x, v, m, cfg)
+        log(f"tree build: device {tree_build['device_ms']:.2f} ms (phases {tree_build['device_phases_ms']}), "
+            f"host builder {tree_build['host_builder_ms']:.1f} ms on {tree_build['host_threads']} threads")
+
     # ---- CPU baseline (oracle on a bounded sample)
     cpu = None
     if not args.no_cpu_baseline:
@@ -640,6 +695,8 @@ def main():
         result["all_active_step"] = all_active
     if integ is not None:
         result["integration"] = integ
+    if tree_build is not None:
+        result["tree_build"] = tree_build
     if cpu is not None:
         result["cpu_baseline"] = cpu
         result["cpu_oracle_other"] = cpu_extra

@@ -45,6 +45,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "htree_tree.h"
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -182,13 +184,28 @@ int ht_step_graph(ht_ctx *ctx, int32_t n_upd, const int32_t *d_idx, const double
  * dt_tree, 2 dt_old) of which t_next is a multiple), writes the new state,
  * potential and j-records.  Asynchronous.  It gives the same bits as the host
  * corrector (htb_correct) given the same forces.  At a tree time the caller
- * copies the state back, rebuilds, and uploads it again. */
+ * either copies the state back, rebuilds on the host and uploads it again, or
+ * calls ht_state_rebuild.
+ *
+ * ht_state_rebuild is step 1 on the device (Section 2, step 1) for a resident
+ * state at a tree time t_tree (every particle synchronised there; the caller
+ * guarantees it): the device tree builder t (include/htree_tree.h) builds
+ * keys, order, tree, node moments, groups and lists from the resident x, v,
+ * a, jerk, m; the state is reordered into the new key order (every t0 set to
+ * t_tree), particle and node records are rewritten, and the new lists replace
+ * the old ones.  perm (host, n entries, may be NULL) receives perm[new] = old.
+ * The result is bit-identical to copying the state back, building with
+ * htb_build and uploading it.  HT_ERANGE, with the context unchanged, if the
+ * tree needs more nodes, groups or list entries than the context holds.
+ * Synchronous. */
 int ht_state_enable(ht_ctx *ctx);
 int ht_state_set(ht_ctx *ctx, int32_t n, const double *t0, const double *dt, const double *m, const double *x,
                  const double *v, const double *a, const double *jerk, const double *pot);
 int ht_state_get(ht_ctx *ctx, double *t0, double *dt, double *x, double *v, double *a, double *jerk, double *pot);
 int ht_dev_next_block(ht_ctx *ctx, double *t_next, int64_t *n_active, const int32_t **active);
 int ht_dev_step(ht_ctx *ctx, double eta, double dt_tree);
+int ht_state_rebuild(ht_ctx *ctx, htd_tree *t, int32_t n_leaf, int32_t n_crit, double theta, double t_tree,
+                     int64_t *perm);
 
 /* Predicted position and velocity ([n][3]) of combined indices idx[0..n-1]
  * at the current block time, computed by the device predictor. */

@@ -126,6 +126,7 @@ def device_lib():
             "ht_state_get": [_vp, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp],
             "ht_dev_next_block": [_vp, ctypes.POINTER(ctypes.c_double), _c_i64p, ctypes.POINTER(_c_i32p)],
             "ht_dev_step": [_vp, d, d],
+            "ht_state_rebuild": [_vp, _vp, i, i, d, d, _c_i64p],
             "ht_force_batch_async": [i, ctypes.POINTER(_vp), _c_i32p, ctypes.POINTER(_c_i32p),
                                      ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp)],
             "ht_sync": [_vp],
@@ -398,6 +399,14 @@ class Context:
     def dev_step(self, eta, dt_tree):
         """ht_dev_step: force, corrector and j-record update of the last next block, on the device."""
         _check(device_lib().ht_dev_step(self._h, float(eta), float(dt_tree)))
+
+    def state_rebuild(self, tree, n, n_leaf, n_crit, theta, t_tree):
+        """ht_state_rebuild: step 1 on the device for the resident state with the
+        DeviceTree `tree`; returns perm (perm[new] = old)."""
+        perm = np.empty(n, np.int64)
+        _check(device_lib().ht_state_rebuild(self._h, tree._h, int(n_leaf), int(n_crit), float(theta),
+                                             float(t_tree), _ptr(perm, ctypes.c_int64)))
+        return perm
 
     def get_predicted(self, idx):
         idx = _arr(idx, np.int32)

@@ -432,23 +432,44 @@ __device__ inline void load_chunk(Chunk& c, int64_t k, int64_t e, const double* 
     }
 }
 
-__device__ inline void stage_chunk(const Chunk& c, double (*buf)[kMomentChunk + 1]) {
+// Rows are padded to 258 doubles: 16-byte aligned for paired reads, and the
+// 13 summing lanes start on different LDS banks.
+constexpr int kRow = kMomentChunk + 2;
+
+__device__ inline void stage_chunk(const Chunk& c, double (*buf)[kRow]) {
     const int t = threadIdx.x;
     buf[0][t] = c.v[0];
     for (int q = 1; q < 13; ++q) buf[q][t] = c.v[0] * c.v[q];
 }
 
-__device__ inline double sum_column(double acc, const double (*buf)[kMomentChunk + 1], int q, int cnt) {
-    const double* col = buf[q];
-    int i = 0;
-    for (; i + 4 <= cnt; i += 4) {
-        const double a0 = col[i], a1 = col[i + 1], a2 = col[i + 2], a3 = col[i + 3];
-        acc = acc + a0;
-        acc = acc + a1;
-        acc = acc + a2;
-        acc = acc + a3;
+// acc + col[0] + col[1] + ... + col[cnt-1], left to right.  Two register
+// batches of 16 alternate so that one batch's LDS reads are in flight while
+// the other batch is added.
+__device__ inline void read16(double2 (&r)[8], const double* col) {
+    for (int u = 0; u < 8; ++u) r[u] = *reinterpret_cast<const double2*>(col + 2 * u);
+}
+
+__device__ inline double add16(double acc, const double2 (&r)[8]) {
+    for (int u = 0; u < 8; ++u) {
+        acc = acc + r[u].x;
+        acc = acc + r[u].y;
     }
-    for (; i < cnt; ++i) acc = acc + col[i];
+    return acc;
+}
+
+__device__ inline double sum_column(double acc, const double (*buf)[kRow], int q, int cnt) {
+    const double* col = buf[q];
+    const int nb = cnt / 16;
+    double2 ra[8], rb[8];
+    if (nb > 0) read16(ra, col);
+    for (int b = 0; b < nb; b += 2) {
+        if (b + 1 < nb) read16(rb, col + 16 * (b + 1));
+        acc = add16(acc, ra);
+        if (b + 1 >= nb) break;
+        if (b + 2 < nb) read16(ra, col + 16 * (b + 2));
+        acc = add16(acc, rb);
+    }
+    for (int i = 16 * nb; i < cnt; ++i) acc = acc + col[i];
     return acc;
 }
 
@@ -464,7 +485,7 @@ __global__ __launch_bounds__(kMomentChunk) void moments_big_kernel(const int32_t
                                                                    double* __restrict__ om, double* __restrict__ ox,
                                                                    double* __restrict__ ov, double* __restrict__ oa,
                                                                    double* __restrict__ oj) {
-    __shared__ double buf[2][13][kMomentChunk + 1];
+    __shared__ __align__(16) double buf[2][13][kRow];
     __shared__ double mass;
     const int t = threadIdx.x;
     const int32_t nbig = tot->big_nodes;

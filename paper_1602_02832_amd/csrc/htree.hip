@@ -34,6 +34,7 @@
 #include <vector>
 
 #include "htree.h"
+#include "htree_tree.h"
 
 namespace {
 
@@ -619,6 +620,22 @@ __global__ __launch_bounds__(kWG) void scatter_kernel(Desc dst, int n, const int
     for (int k = blockIdx.x * kWG + threadIdx.x; k < n; k += gridDim.x * kWG)
         store_rec<P>(rec, idx ? idx[k] : base + k, t0 ? t0[k] : t0_all, m[k], x + 3 * k, v + 3 * k, a + 3 * k,
                      jerk + 3 * k);
+}
+
+// Resident rebuild: dt and pot in the new particle order.
+__global__ __launch_bounds__(kWG) void permute2_kernel(int n, const int64_t* __restrict__ perm,
+                                                       const double* __restrict__ a, const double* __restrict__ b,
+                                                       double* __restrict__ oa, double* __restrict__ ob) {
+    const int k = blockIdx.x * kWG + threadIdx.x;
+    if (k >= n) return;
+    const int64_t o = perm[k];
+    oa[k] = a[o];
+    ob[k] = b[o];
+}
+
+__global__ __launch_bounds__(kWG) void fill_kernel(int n, double* __restrict__ out, double value) {
+    const int k = blockIdx.x * kWG + threadIdx.x;
+    if (k < n) out[k] = value;
 }
 
 // Read an 8-byte word of pinned host memory written by the host since the
@@ -2041,6 +2058,75 @@ int ht_state_get(ht_ctx* c, double* t0, double* dt, double* x, double* v, double
         if (k.dst) HT_HIP(hipMemcpyAsync(k.dst, k.src, k.bytes, hipMemcpyDeviceToHost, c->stream));
     HT_HIP(hipStreamSynchronize(c->stream));
     c->slots_all_free();
+    return HT_OK;
+}
+
+int ht_state_rebuild(ht_ctx* c, htd_tree* t, int32_t n_leaf, int32_t n_crit, double theta, double t_tree,
+                     int64_t* perm) {
+    if (!c || !t) return fail(HT_EINVAL, "NULL argument");
+    if (!c->ds_mem) return fail(HT_ESTATE, "device state not enabled");
+    if (c->n < 1) return fail(HT_ESTATE, "particles not set");
+    if (!std::isfinite(t_tree)) return fail(HT_EINVAL, "t_tree not finite");
+    const int32_t n = c->n;
+    HT_HIP(hipStreamSynchronize(c->stream));   // the state is complete before the builder reads it
+    c->slots_all_free();
+    if (int rc = htd_build(t, n, c->ds.x, c->ds.v, c->ds.a, c->ds.j, c->ds.m, n_leaf, n_crit, theta))
+        return fail(rc == HTD_EINVAL ? HT_EINVAL : rc == HTD_ENOMEM ? HT_ENOMEM : HT_EHIP, "device tree build: %s",
+                    htd_last_error());
+    int64_t M = 0, G = 0, L = 0;
+    htd_view w{};
+    if (htd_sizes(t, &M, &G, &L, nullptr) || htd_device_view(t, &w)) return fail(HT_EHIP, "%s", htd_last_error());
+    if (M > c->cfg.node_max || G > c->cfg.group_max || L > c->cfg.list_max)
+        return fail(HT_ERANGE, "tree needs %lld nodes, %lld groups, %lld list entries; capacity %d, %d, %lld",
+                    (long long)M, (long long)G, (long long)L, c->cfg.node_max, c->cfg.group_max,
+                    (long long)c->cfg.list_max);
+    // the state in the new particle order: x, v, a, jerk, m come sorted from the builder;
+    // dt and pot are gathered through the permutation; every t0 is the tree time
+    const size_t n1 = static_cast<size_t>(n) * 8, n3 = 3 * n1;
+    const int grid = (n + kWG - 1) / kWG;
+    permute2_kernel<<<grid, kWG, 0, c->stream>>>(n, w.perm, c->ds.dt, c->ds.pot, c->ds.acc, c->ds.fpot);
+    HT_HIP(hipGetLastError());
+    HT_HIP(hipMemcpyAsync(c->ds.dt, c->ds.acc, n1, hipMemcpyDeviceToDevice, c->stream));
+    HT_HIP(hipMemcpyAsync(c->ds.pot, c->ds.fpot, n1, hipMemcpyDeviceToDevice, c->stream));
+    HT_HIP(hipMemcpyAsync(c->ds.x, w.x, n3, hipMemcpyDeviceToDevice, c->stream));
+    HT_HIP(hipMemcpyAsync(c->ds.v, w.v, n3, hipMemcpyDeviceToDevice, c->stream));
+    HT_HIP(hipMemcpyAsync(c->ds.a, w.a, n3, hipMemcpyDeviceToDevice, c->stream));
+    HT_HIP(hipMemcpyAsync(c->ds.j, w.jerk, n3, hipMemcpyDeviceToDevice, c->stream));
+    HT_HIP(hipMemcpyAsync(c->ds.m, w.m, n1, hipMemcpyDeviceToDevice, c->stream));
+    fill_kernel<<<grid, kWG, 0, c->stream>>>(n, c->ds.t0, t_tree);
+    HT_HIP(hipGetLastError());
+    // records: particles, then nodes at the tree time; then the lists
+    const Desc d = c->desc();
+    const int gn = (static_cast<int>(M) + kWG - 1) / kWG;
+    if (c->cfg.precision == HT_PREC_FP64) {
+        scatter_kernel<PrecFp64><<<grid, kWG, 0, c->stream>>>(d, n, nullptr, 0, nullptr, t_tree, c->ds.m, c->ds.x,
+                                                            c->ds.v, c->ds.a, c->ds.j);
+        if (M > 0)
+            scatter_kernel<PrecFp64><<<gn, kWG, 0, c->stream>>>(d, static_cast<int>(M), nullptr, n, nullptr, t_tree,
+                                                              w.node_m, w.node_x, w.node_v, w.node_a, w.node_j);
+    } else {
+        scatter_kernel<PrecMixed><<<grid, kWG, 0, c->stream>>>(d, n, nullptr, 0, nullptr, t_tree, c->ds.m, c->ds.x,
+                                                             c->ds.v, c->ds.a, c->ds.j);
+        if (M > 0)
+            scatter_kernel<PrecMixed><<<gn, kWG, 0, c->stream>>>(d, static_cast<int>(M), nullptr, n, nullptr, t_tree,
+                                                               w.node_m, w.node_x, w.node_v, w.node_a, w.node_j);
+    }
+    HT_HIP(hipGetLastError());
+    HT_HIP(hipMemcpyAsync(c->ws + c->L.off_entries, w.entries, static_cast<size_t>(L) * 4, hipMemcpyDeviceToDevice,
+                          c->stream));
+    c->group_first.resize(static_cast<size_t>(G) + 1);
+    c->list_off.resize(static_cast<size_t>(G) + 1);
+    HT_HIP(hipMemcpyAsync(c->group_first.data(), w.group_first, (G + 1) * 8, hipMemcpyDeviceToHost, c->stream));
+    HT_HIP(hipMemcpyAsync(c->list_off.data(), w.list_off, (G + 1) * 8, hipMemcpyDeviceToHost, c->stream));
+    if (perm) HT_HIP(hipMemcpyAsync(perm, w.perm, n1, hipMemcpyDeviceToHost, c->stream));
+    HT_HIP(hipStreamSynchronize(c->stream));
+    c->n_nodes = static_cast<int32_t>(M);
+    c->n_groups = static_cast<int32_t>(G);
+    c->n_entries = L;
+    c->have_nodes = true;
+    c->have_lists = true;
+    c->predicted = false;
+    c->dev_n_active = -1;
     return HT_OK;
 }
 

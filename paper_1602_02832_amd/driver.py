@@ -18,6 +18,7 @@ all-active step, after it has been corrected.
 from __future__ import annotations
 
 import math
+import types
 import time
 
 import numpy as np
@@ -27,11 +28,14 @@ from . import binding as B
 
 class Simulation:
     def __init__(self, x, v, m, *, eps2, dt_tree, eta, theta=0.5, n_crit=64, n_leaf=1, precision="mixed",
-                 predict_mode="fused", mode="tree", device=0, stream=None, list_headroom=1.5, resident=False):
+                 predict_mode="fused", mode="tree", device=0, stream=None, list_headroom=1.5, resident=False,
+                 device_tree=False):
         if mode not in ("tree", "direct"):
             raise ValueError(mode)
         if resident and mode != "tree":
             raise ValueError("resident integration runs the tree scheme")
+        if device_tree and not resident:
+            raise ValueError("the device tree builder serves the resident integration")
         if not (dt_tree > 0 and math.frexp(dt_tree)[0] == 0.5):
             raise ValueError("dt_tree must be a power of two")
         self.x = np.ascontiguousarray(x, np.float64).reshape(-1, 3).copy()
@@ -58,6 +62,12 @@ class Simulation:
         # (scheduler and corrector there); the host arrays are current only after
         # sync_state() and at tree times
         self.resident = bool(resident)
+        # resident: rebuild at tree times on the device (ht_state_rebuild), so the
+        # state never leaves it; the host path remains the fallback when the tree
+        # outgrows the context's capacities
+        self.device_tree = bool(device_tree)
+        self._dtree = None
+        self.n_device_rebuilds = 0
         self._pending_dev = None
         self.n_block_steps = 0
         self.n_particle_steps = 0
@@ -190,14 +200,35 @@ class Simulation:
         return tn, active
 
     def rebuild_resident(self):
-        """Resident mode, at a tree time: state back to the host, new tree and
-        lists, state up again."""
+        """Resident mode, at a tree time: a new tree and lists, on the device
+        (device_tree) or through the host (state back, host builder, state up)."""
+        if self.device_tree and self._rebuild_on_device():
+            return
         self.sync_state()
         if not np.all(self.t0 == self.t):
             raise AssertionError("particles not synchronised at a tree time")
         self._build_and_send()
         self.ctx.state_enable()    # the rebuild may have made a larger context
         self.ctx.state_set(self.t0, self.dt, self.m, self.x, self.v, self.a, self.j, self.pot)
+
+    def _rebuild_on_device(self):
+        t_start = time.perf_counter()
+        if self._dtree is None:
+            self._dtree = B.DeviceTree(n_max=self.n, device=self.device, stream=self.stream)
+        try:
+            perm = self.ctx.state_rebuild(self._dtree, self.n, self.n_leaf, self.n_crit, self.theta, self.t)
+        except B.HTError as e:
+            if e.code != -2:      # not a capacity shortfall
+                raise
+            return False
+        self.m = np.ascontiguousarray(self.m[perm])
+        self.ids = np.ascontiguousarray(self.ids[perm])
+        M, G, E, _ = self._dtree.sizes()
+        self.tree = types.SimpleNamespace(n_node=M, n_group=G, n_entries=E)
+        self.t_tree = self.t
+        self.n_device_rebuilds += 1
+        self.timers["tree"] += time.perf_counter() - t_start
+        return True
 
     def step(self):
         """One block step; returns (t, active ids)."""
@@ -240,7 +271,7 @@ class Simulation:
         return K + W
 
     def close(self):
-        for c in (self.ctx, self._ectx):
+        for c in (self.ctx, self._ectx, self._dtree):
             if c is not None:
                 c.close()
-        self.ctx = self._ectx = None
+        self.ctx = self._ectx = self._dtree = None

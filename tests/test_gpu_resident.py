@@ -66,3 +66,45 @@ def test_resident_integration_equals_host_driven(prec):
     assert e_host == e_dev
     for s in sims:
         s.close()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_device_rebuilds_equal_host_rebuilds(prec):
+    """Resident runs that rebuild on the device (ht_state_rebuild: tree, lists
+    and the reordered state never leave it) and through the host builder: the
+    same bits after 16 tree times, in the same particle order."""
+    c = W.config("plummer2k")
+    say(f"device vs host rebuilds ({prec}) to t={c.t_end}")
+    x, v, m = W.make_initial_conditions(c)
+    sims = [driver.Simulation(x, v, m, eps2=c.eps2, dt_tree=c.dt_tree, eta=c.eta, theta=c.theta, n_crit=c.n_crit,
+                              precision=prec, resident=True, device_tree=d) for d in (False, True)]
+    for s in sims:
+        s.run(c.t_end)
+        s.sync_state()
+    assert sims[1].n_device_rebuilds >= 16
+    assert sims[0].n_block_steps == sims[1].n_block_steps and sims[0].t == sims[1].t == c.t_end
+    assert np.array_equal(sims[0].ids, sims[1].ids)
+    for f in FIELDS + ("m",):
+        assert np.array_equal(getattr(sims[0], f), getattr(sims[1], f)), f
+    assert sims[0].energy() == sims[1].energy()
+    for s in sims:
+        s.close()
+
+
+def test_device_rebuilds_plummer16k_mixed():
+    """The same at 16384 particles (C2's model, n_crit 256) over four tree times."""
+    c = W.config("plummer16k")
+    t_end = 4 * c.dt_tree
+    say(f"device vs host rebuilds plummer16k to t={t_end}")
+    x, v, m = W.make_initial_conditions(c)
+    sims = [driver.Simulation(x, v, m, eps2=c.eps2, dt_tree=c.dt_tree, eta=c.eta, theta=c.theta, n_crit=c.n_crit,
+                              precision="mixed", resident=True, device_tree=d) for d in (False, True)]
+    for s in sims:
+        s.run(t_end)
+        s.sync_state()
+    assert sims[1].n_device_rebuilds == 4
+    assert np.array_equal(sims[0].ids, sims[1].ids)
+    for f in FIELDS + ("m",):
+        assert np.array_equal(getattr(sims[0], f), getattr(sims[1], f)), f
+    for s in sims:
+        s.close()
