@@ -357,7 +357,7 @@ __global__ __launch_bounds__(kWG) void cells_kernel(int64_t n, int n_leaf, const
             node_level[c.node] = l;
             node_begin[c.node] = k;
             node_end[c.node] = e;
-            node_big[c.node] = cnt > kSmallNode ? 1 : 0;
+            node_big[c.node] = (cnt > kSmallNode && c.node != 0) ? 1 : 0;   // the root has its own kernel
         }
     }
 }
@@ -473,6 +473,52 @@ __device__ inline double sum_column(double acc, const double (*buf)[kRow], int q
     return acc;
 }
 
+// Moments of the node with particles [b, e), written at index `node` of the
+// output arrays, by the whole work-group.
+__device__ inline void sum_node(int64_t b, int64_t e, int32_t node, const double* __restrict__ sm,
+                                const double* __restrict__ sx, const double* __restrict__ sv,
+                                const double* __restrict__ sa, const double* __restrict__ sj,
+                                double* __restrict__ om, double* __restrict__ ox, double* __restrict__ ov,
+                                double* __restrict__ oa, double* __restrict__ oj, double (*buf)[13][kRow],
+                                double* mass) {
+    const int t = threadIdx.x;
+    const int64_t nch = (e - b + kMomentChunk - 1) / kMomentChunk;
+    Chunk r0, r1;
+    load_chunk(r0, b + t, e, sm, sx, sv, sa, sj);
+    stage_chunk(r0, buf[0]);
+    if (nch > 1) load_chunk(r1, b + kMomentChunk + t, e, sm, sx, sv, sa, sj);
+    __syncthreads();
+    double acc = 0.0;
+    for (int64_t c = 0; c < nch; c += 2) {
+        // chunk c is staged in buf[0]; r1 holds chunk c + 1 (if any)
+        if (c + 2 < nch) load_chunk(r0, b + (c + 2) * kMomentChunk + t, e, sm, sx, sv, sa, sj);
+        if (t < 13) acc = sum_column(acc, buf[0], t, static_cast<int>(min<int64_t>(kMomentChunk, e - b - c * kMomentChunk)));
+        if (c + 1 >= nch) break;
+        stage_chunk(r1, buf[1]);
+        __syncthreads();
+        if (c + 3 < nch) load_chunk(r1, b + (c + 3) * kMomentChunk + t, e, sm, sx, sv, sa, sj);
+        if (t < 13)
+            acc = sum_column(acc, buf[1], t, static_cast<int>(min<int64_t>(kMomentChunk, e - b - (c + 1) * kMomentChunk)));
+        if (c + 2 >= nch) break;
+        __syncthreads();   // buf[0] is free again
+        stage_chunk(r0, buf[0]);
+        __syncthreads();
+    }
+    if (t == 0) {
+        *mass = acc;
+        om[node] = acc;
+    }
+    __syncthreads();
+    if (t >= 1 && t < 13) {
+        const double M = *mass;
+        const int q = t - 1, d = q % 3;
+        double* out = q < 3 ? ox : q < 6 ? ov : q < 9 ? oa : oj;
+        out[3 * node + d] = acc / M;
+    }
+    __syncthreads();
+}
+
+// Large nodes other than the root, one work-group each.
 __global__ __launch_bounds__(kMomentChunk) void moments_big_kernel(const int32_t* __restrict__ list,
                                                                    const Totals* tot,
                                                                    const int64_t* __restrict__ nb,
@@ -487,45 +533,37 @@ __global__ __launch_bounds__(kMomentChunk) void moments_big_kernel(const int32_t
                                                                    double* __restrict__ oj) {
     __shared__ __align__(16) double buf[2][13][kRow];
     __shared__ double mass;
-    const int t = threadIdx.x;
     const int32_t nbig = tot->big_nodes;
     for (int32_t w = blockIdx.x; w < nbig; w += gridDim.x) {
         const int32_t node = list[w];
-        const int64_t b = nb[node], e = ne[node];
-        const int64_t nch = (e - b + kMomentChunk - 1) / kMomentChunk;
-        Chunk r0, r1;
-        load_chunk(r0, b + t, e, sm, sx, sv, sa, sj);
-        stage_chunk(r0, buf[0]);
-        if (nch > 1) load_chunk(r1, b + kMomentChunk + t, e, sm, sx, sv, sa, sj);
-        __syncthreads();
-        double acc = 0.0;
-        for (int64_t c = 0; c < nch; c += 2) {
-            // chunk c is staged in buf[0]; r1 holds chunk c + 1 (if any)
-            if (c + 2 < nch) load_chunk(r0, b + (c + 2) * kMomentChunk + t, e, sm, sx, sv, sa, sj);
-            if (t < 13) acc = sum_column(acc, buf[0], t, static_cast<int>(min<int64_t>(kMomentChunk, e - b - c * kMomentChunk)));
-            if (c + 1 >= nch) break;
-            stage_chunk(r1, buf[1]);
-            __syncthreads();
-            if (c + 3 < nch) load_chunk(r1, b + (c + 3) * kMomentChunk + t, e, sm, sx, sv, sa, sj);
-            if (t < 13)
-                acc = sum_column(acc, buf[1], t, static_cast<int>(min<int64_t>(kMomentChunk, e - b - (c + 1) * kMomentChunk)));
-            if (c + 2 >= nch) break;
-            __syncthreads();   // buf[0] is free again
-            stage_chunk(r0, buf[0]);
-            __syncthreads();
-        }
-        if (t == 0) {
-            mass = acc;
-            om[node] = acc;
-        }
-        __syncthreads();
-        if (t >= 1 && t < 13) {
-            const double M = mass;
-            const int q = t - 1, d = q % 3;
-            double* out = q < 3 ? ox : q < 6 ? ov : q < 9 ? oa : oj;
-            out[3 * node + d] = acc / M;
-        }
-        __syncthreads();
+        sum_node(nb[node], ne[node], node, sm, sx, sv, sa, sj, om, ox, ov, oa, oj, buf, &mass);
+    }
+}
+
+// The root (all n particles): its sums form the longest sequential chain of
+// the build, and no opening test reads them (the root contains every group),
+// so they run on a second stream beside the rest of the build.  Out: 13
+// doubles (m, x[3], v[3], a[3], jerk[3]).
+__global__ __launch_bounds__(kMomentChunk) void moments_root_kernel(int64_t n, const double* __restrict__ sm,
+                                                                    const double* __restrict__ sx,
+                                                                    const double* __restrict__ sv,
+                                                                    const double* __restrict__ sa,
+                                                                    const double* __restrict__ sj,
+                                                                    double* __restrict__ out) {
+    __shared__ __align__(16) double buf[2][13][kRow];
+    __shared__ double mass;
+    sum_node(0, n, 0, sm, sx, sv, sa, sj, out, out + 1, out + 4, out + 7, out + 10, buf, &mass);
+}
+
+__global__ void root_store_kernel(const double* __restrict__ in, double* __restrict__ om, double* __restrict__ ox,
+                                  double* __restrict__ ov, double* __restrict__ oa, double* __restrict__ oj) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    om[0] = in[0];
+    for (int d = 0; d < 3; ++d) {
+        ox[d] = in[1 + d];
+        ov[d] = in[4 + d];
+        oa[d] = in[7 + d];
+        oj[d] = in[10 + d];
     }
 }
 #pragma clang fp contract(on)
@@ -800,8 +838,11 @@ struct htd_tree {
     DevBuf<int64_t> group_first, list_off, gstage, glen64;
     DevBuf<int32_t> glen, cut, stage, entries;
     DevBuf<Counters> ctr;
+    DevBuf<double> root_out;    // the root's moments, from the second stream
+    hipStream_t s2 = nullptr;   // second stream: the root's sums
+    hipEvent_t ev_gather = nullptr, ev_root = nullptr;
     int32_t cut_cap = 1 << 15;
-    int n_list_wg = 512;
+    int n_list_wg = 1024;
     // results of the last build
     int64_t n = 0, C = 0, M = 0, G = 0, L = 0;
     Root root_h{};
@@ -848,7 +889,8 @@ int grow_particles(htd_tree* t, int64_t n) {
         (rc = t->sj.grow(3 * n)) || (rc = t->sm.grow(n)) || (rc = t->lev.grow(n)) || (rc = t->ncell.grow(n)) ||
         (rc = t->cbase.grow(n)) || (rc = t->nnode.grow(n)) || (rc = t->nbase.grow(n)) || (rc = t->gflag.grow(n)) ||
         (rc = t->gbase.grow(n)) || (rc = t->part.grow(6 * 1024)) || (rc = t->root.grow(1)) || (rc = t->tot.grow(1)) ||
-        (rc = t->ctr.grow(1)) || (rc = t->group_first.grow(n + 1)) || (rc = t->list_off.grow(n + 1)) ||
+        (rc = t->ctr.grow(1)) || (rc = t->root_out.grow(13)) || (rc = t->group_first.grow(n + 1)) ||
+        (rc = t->list_off.grow(n + 1)) ||
         (rc = t->gstage.grow(n + 1)) || (rc = t->glen64.grow(n + 1)) || (rc = t->glen.grow(n + 1)))
         return rc;
     return 0;
@@ -876,6 +918,7 @@ int run_lists(htd_tree* t, const ListArgs& base, int32_t* max_cut, unsigned long
 int build(htd_tree* t, int64_t n, const double* x, const double* v, const double* a, const double* jerk,
           const double* m, int n_leaf, int n_crit, double theta) {
     hipStream_t s = t->stream;
+    HTD_HIP(hipStreamSynchronize(t->s2));   // nothing of an earlier (failed) build still reads the buffers
     if (int rc = grow_particles(t, n)) return rc;
     if (int rc = reserve_tmp(t, n)) return rc;
     HTD_HIP(hipEventRecord(t->ev[0], s));
@@ -894,6 +937,17 @@ int build(htd_tree* t, int64_t n, const double* x, const double* v, const double
     HTD_HIP(hipEventRecord(t->ev[2], s));
     gather_kernel<<<blocks_for(n, kWG), kWG, 0, s>>>(n, t->idx.p, t->key.p, x, v, a, jerk, m, t->perm.p, t->sx.p,
                                                      t->sv.p, t->sa.p, t->sj.p, t->sm.p, t->lev.p);
+    // the root's sums start now on the second stream (large builds only; a
+    // root of up to kSmallNode particles is summed with the other small nodes)
+    const bool root_apart = n > kSmallNode;
+    if (root_apart) {
+        HTD_HIP(hipEventRecord(t->ev_gather, s));
+        HTD_HIP(hipStreamWaitEvent(t->s2, t->ev_gather, 0));
+        moments_root_kernel<<<1, kMomentChunk, 0, t->s2>>>(n, t->sm.p, t->sx.p, t->sv.p, t->sa.p, t->sj.p,
+                                                            t->root_out.p);
+        HTD_HIP(hipGetLastError());
+        HTD_HIP(hipEventRecord(t->ev_root, t->s2));
+    }
     // 2. cells, nodes and groups
     count_kernel<<<blocks_for(n, kWG), kWG, 0, s>>>(n, n_leaf, n_crit, t->key.p, t->lev.p, t->ncell.p, t->nnode.p,
                                                     t->gflag.p);
@@ -982,6 +1036,11 @@ int build(htd_tree* t, int64_t n, const double* x, const double* v, const double
     if ((rc = t->entries.grow(std::max<int64_t>(t->L, 1)))) return rc;
     csr_kernel<<<std::min(Gi, 4096), kWG, 0, s>>>(Gi, t->list_off.p, t->gstage.p, t->stage.p, t->entries.p);
     HTD_HIP(hipGetLastError());
+    if (root_apart) {   // join: the root's moments into node 0
+        HTD_HIP(hipStreamWaitEvent(s, t->ev_root, 0));
+        root_store_kernel<<<1, 64, 0, s>>>(t->root_out.p, t->nm.p, t->nx.p, t->nv.p, t->na.p, t->nj.p);
+        HTD_HIP(hipGetLastError());
+    }
     HTD_HIP(hipEventRecord(t->ev[6], s));
     HTD_HIP(hipStreamSynchronize(s));
     for (int i = 0; i < 6; ++i) HTD_HIP(hipEventElapsedTime(&t->phase_ms[i], t->ev[i], t->ev[i + 1]));
@@ -1022,6 +1081,12 @@ int htd_create(htd_tree** out, int32_t device, void* stream, int64_t n_max) {
             htd_destroy(t);
             return fail(HTD_EHIP, "hipEventCreate failed");
         }
+    if (hipStreamCreateWithFlags(&t->s2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&t->ev_gather, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&t->ev_root, hipEventDisableTiming) != hipSuccess) {
+        htd_destroy(t);
+        return fail(HTD_EHIP, "stream or event creation failed");
+    }
     if (int rc = grow_particles(t, n_max)) {
         htd_destroy(t);
         return rc;
@@ -1035,8 +1100,15 @@ int htd_destroy(htd_tree* t) {
     (void)hipSetDevice(t->device);
     if (t->stream) (void)hipStreamSynchronize(t->stream);
     else (void)hipDeviceSynchronize();
+    if (t->s2) {
+        (void)hipStreamSynchronize(t->s2);
+        (void)hipStreamDestroy(t->s2);
+    }
     for (auto& e : t->ev)
         if (e) (void)hipEventDestroy(e);
+    if (t->ev_gather) (void)hipEventDestroy(t->ev_gather);
+    if (t->ev_root) (void)hipEventDestroy(t->ev_root);
+    t->root_out.release();
     t->key_in.release(); t->key.release(); t->idx_in.release(); t->idx.release(); t->perm.release();
     t->sx.release(); t->sv.release(); t->sa.release(); t->sj.release(); t->sm.release(); t->lev.release();
     t->ncell.release(); t->cbase.release(); t->nnode.release(); t->nbase.release(); t->gflag.release();

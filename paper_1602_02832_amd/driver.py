@@ -83,6 +83,8 @@ class Simulation:
         if self.resident:
             self.ctx.state_enable()
             self.ctx.state_set(self.t0, self.dt, self.m, self.x, self.v, self.a, self.j, self.pot)
+        if self.device_tree:
+            self._dtree = B.DeviceTree(n_max=self.n, device=self.device, stream=self.stream)
 
     # ------------------------------------------------------------------ context
     def _make_ctx(self, node_max, group_max, list_max):
