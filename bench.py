@@ -310,6 +310,16 @@ def cpu_baseline(W, cfg, seconds):
     return base, extra
 
 
+def engine_device_tree(args):
+    return not args.host_engine and not args.host_rebuild
+
+
+def engine_name(args):
+    if args.host_engine:
+        return "host-driven"
+    return "resident, host rebuilds" if args.host_rebuild else "resident, device rebuilds"
+
+
 def bench_ensemble(args, torch):
     """64 independent clusters advanced together, one batched launch per engine step."""
     from paper_1602_02832_amd import engine as E
@@ -320,7 +330,8 @@ def bench_ensemble(args, torch):
                        n_crit=256) for k, n in enumerate(sizes)]
     total_n = int(sizes.sum())
     eng = E.Engine(precision="mixed", max_clusters=64, max_active=total_n, max_items=1 << 20, max_rows=total_n,
-                   resident=not args.host_engine)
+                   resident=not args.host_engine, device_tree=engine_device_tree(args),
+                   tree_n_max=int(sizes.max()))
     t0 = time.perf_counter()
     for sp in specs:
         eng.add(eng.new_cluster(sp))
@@ -353,7 +364,7 @@ def bench_ensemble(args, torch):
         "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
         "config": {"workload": "ensemble64", "clusters": 64, "n_range": [4096, 65536], "n_total": total_n,
-                   "engine": "host-driven" if args.host_engine else "resident",
+                   "engine": engine_name(args),
                    "theta": 0.5, "eps": "4/N", "dt_tree": 1.0 / 256, "eta": 0.01, "n_crit": 256, "precision": "mixed"},
         "p50_step_ms": float(np.percentile(lat, 50)), "p99_step_ms": float(np.percentile(lat, 99)),
         "equivalent_interactions_per_s": eng.equiv_pairs / wall,
@@ -382,7 +393,8 @@ def bench_served(args, torch):
 
     def serve(reqs):
         eng = E.Engine(precision="mixed", max_clusters=args.max_resident, max_active=cap_active, max_items=1 << 20,
-                       max_rows=cap_active, resident=not args.host_engine)
+                       max_rows=cap_active, resident=not args.host_engine, device_tree=engine_device_tree(args),
+                       tree_n_max=int(sizes.max()))
         srv = E.Server(eng, hbm_budget=budget, max_resident=args.max_resident)
         t = time.perf_counter()
         done = srv.run(reqs)
@@ -413,7 +425,7 @@ def bench_served(args, torch):
                    "theta": 0.5, "eps": "4/N", "dt_tree": 1.0 / 256, "eta": 0.01, "n_crit": 256,
                    "arrival_rate_per_s": rate, "load": 0.8, "max_resident": args.max_resident,
                    "hbm_budget_gb": args.hbm_gb, "precision": "mixed",
-                   "engine": "host-driven" if args.host_engine else "resident"},
+                   "engine": engine_name(args)},
         "p50_step_ms": float(np.percentile(lat, 50)), "p99_step_ms": float(np.percentile(lat, 99)),
         "capacity_runs_per_s": capacity, "throughput_runs_per_s": len(done) / run["span"],
         "interactions_per_s": run["pairs"] / run["span"],
@@ -439,6 +451,8 @@ def main():
     ap.add_argument("--no-tree-build", action="store_true", help="skip the device tree-build leg")
     ap.add_argument("--host-engine", action="store_true",
                     help="ensemble/served: drive the clusters from the host (scheduler and corrector on the CPU)")
+    ap.add_argument("--host-rebuild", action="store_true",
+                    help="ensemble/served, resident engine: rebuild trees through the host instead of the device")
     ap.add_argument("--n", type=int, default=0, help="override N (testing only; not the benchmark)")
     ap.add_argument("--n-crit", type=int, default=0, help="override the group size bound n_crit (sweeps)")
     ap.add_argument("--dump-steps", default="", help="write per-step (n_active, pairs, items, ms) JSON here")

@@ -166,18 +166,37 @@ struct Root {
 
 // Final reduction and the root cube: side is the smallest power of two above
 // the largest extent (1 when all particles coincide).
-__global__ __launch_bounds__(64) void bbox_final_kernel(int nb, const double* __restrict__ part, Root* root) {
-    if (threadIdx.x != 0) return;
+__global__ __launch_bounds__(kWG) void bbox_final_kernel(int nb, const double* __restrict__ part, Root* root) {
+    __shared__ double s[6][kWG];
+    const int t = threadIdx.x;
     double lo[3], hi[3];
     for (int d = 0; d < 3; ++d) {
         lo[d] = part[d];
         hi[d] = part[3 + d];
     }
-    for (int b = 1; b < nb; ++b)
+    for (int b = t; b < nb; b += kWG)
         for (int d = 0; d < 3; ++d) {
             lo[d] = dmin(lo[d], part[6 * b + d]);
             hi[d] = dmax(hi[d], part[6 * b + 3 + d]);
         }
+    for (int d = 0; d < 3; ++d) {
+        s[d][t] = lo[d];
+        s[3 + d][t] = hi[d];
+    }
+    __syncthreads();
+    for (int w = kWG / 2; w > 0; w >>= 1) {
+        if (t < w)
+            for (int d = 0; d < 3; ++d) {
+                s[d][t] = dmin(s[d][t], s[d][t + w]);
+                s[3 + d][t] = dmax(s[3 + d][t], s[3 + d][t + w]);
+            }
+        __syncthreads();
+    }
+    if (t != 0) return;
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = s[d][0];
+        hi[d] = s[3 + d][0];
+    }
     const double ext = dmax(dmax(hi[0] - lo[0], hi[1] - lo[1]), hi[2] - lo[2]);
     double side = 1.0;
     if (ext > 0.0) {
@@ -925,7 +944,7 @@ int build(htd_tree* t, int64_t n, const double* x, const double* v, const double
     // 1. root cube, keys, sort, gather
     const int nb = static_cast<int>(std::min<int64_t>(1024, std::max<int64_t>(1, blocks_for(n, kWG))));
     bbox_partial_kernel<<<nb, kWG, 0, s>>>(n, x, t->part.p);
-    bbox_final_kernel<<<1, 64, 0, s>>>(nb, t->part.p, t->root.p);
+    bbox_final_kernel<<<1, kWG, 0, s>>>(nb, t->part.p, t->root.p);
     keys_kernel<<<blocks_for(n, kWG), kWG, 0, s>>>(n, x, t->root.p, t->key_in.p, t->idx_in.p);
     HTD_HIP(hipGetLastError());
     HTD_HIP(hipEventRecord(t->ev[1], s));

@@ -17,6 +17,7 @@ all-active step, after it has been corrected.
 """
 from __future__ import annotations
 
+import contextlib
 import math
 import types
 import time
@@ -29,7 +30,7 @@ from . import binding as B
 class Simulation:
     def __init__(self, x, v, m, *, eps2, dt_tree, eta, theta=0.5, n_crit=64, n_leaf=1, precision="mixed",
                  predict_mode="fused", mode="tree", device=0, stream=None, list_headroom=1.5, resident=False,
-                 device_tree=False):
+                 device_tree=False, tree=None, tree_lock=None):
         if mode not in ("tree", "direct"):
             raise ValueError(mode)
         if resident and mode != "tree":
@@ -65,8 +66,12 @@ class Simulation:
         # resident: rebuild at tree times on the device (ht_state_rebuild), so the
         # state never leaves it; the host path remains the fallback when the tree
         # outgrows the context's capacities
+        # (tree, tree_lock: a DeviceTree shared by several simulations and the lock
+        # that serialises its use; by default each simulation has its own)
         self.device_tree = bool(device_tree)
-        self._dtree = None
+        self._dtree = tree
+        self._own_dtree = tree is None
+        self._dtree_lock = tree_lock
         self.n_device_rebuilds = 0
         self._pending_dev = None
         self.n_block_steps = 0
@@ -83,7 +88,7 @@ class Simulation:
         if self.resident:
             self.ctx.state_enable()
             self.ctx.state_set(self.t0, self.dt, self.m, self.x, self.v, self.a, self.j, self.pot)
-        if self.device_tree:
+        if self.device_tree and self._dtree is None:
             self._dtree = B.DeviceTree(n_max=self.n, device=self.device, stream=self.stream)
 
     # ------------------------------------------------------------------ context
@@ -215,17 +220,17 @@ class Simulation:
 
     def _rebuild_on_device(self):
         t_start = time.perf_counter()
-        if self._dtree is None:
-            self._dtree = B.DeviceTree(n_max=self.n, device=self.device, stream=self.stream)
-        try:
-            perm = self.ctx.state_rebuild(self._dtree, self.n, self.n_leaf, self.n_crit, self.theta, self.t)
-        except B.HTError as e:
-            if e.code != -2:      # not a capacity shortfall
-                raise
-            return False
+        lock = self._dtree_lock if self._dtree_lock is not None else contextlib.nullcontext()
+        with lock:
+            try:
+                perm = self.ctx.state_rebuild(self._dtree, self.n, self.n_leaf, self.n_crit, self.theta, self.t)
+            except B.HTError as e:
+                if e.code != -2:      # not a capacity shortfall
+                    raise
+                return False
+            M, G, E, _ = self._dtree.sizes()
         self.m = np.ascontiguousarray(self.m[perm])
         self.ids = np.ascontiguousarray(self.ids[perm])
-        M, G, E, _ = self._dtree.sizes()
         self.tree = types.SimpleNamespace(n_node=M, n_group=G, n_entries=E)
         self.t_tree = self.t
         self.n_device_rebuilds += 1
@@ -273,7 +278,7 @@ class Simulation:
         return K + W
 
     def close(self):
-        for c in (self.ctx, self._ectx, self._dtree):
+        for c in (self.ctx, self._ectx, self._dtree if self._own_dtree else None):
             if c is not None:
                 c.close()
         self.ctx = self._ectx = self._dtree = None

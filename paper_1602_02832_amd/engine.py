@@ -24,6 +24,7 @@ import concurrent.futures
 import ctypes
 import dataclasses
 import math
+import threading
 import time
 
 import numpy as np
@@ -62,9 +63,11 @@ class Cluster:
     first forces) when it becomes resident."""
 
     def __init__(self, spec: RunSpec, precision: str, stream, device: int = 0, list_headroom: float = 1.5,
-                 resident: bool = False):
+                 resident: bool = False, tree=None, tree_lock=None):
         self.spec, self.precision, self.stream, self.device = spec, precision, stream, device
         self.resident = resident
+        # a shared device tree builder for rebuilds on the device (resident runs it fits)
+        self.tree, self.tree_lock = tree, tree_lock
         self.list_headroom = list_headroom
         x, v, m = W.plummer(spec.n, spec.seed)
         if spec.mass_seed is not None:
@@ -89,7 +92,8 @@ class Cluster:
             self.sim = driver.Simulation(x, v, m, eps2=eps * eps, dt_tree=spec.dt_tree, eta=spec.eta,
                                          theta=spec.theta, n_crit=spec.n_crit, precision=self.precision,
                                          device=self.device, stream=self.stream, list_headroom=self.list_headroom,
-                                         resident=self.resident)
+                                         resident=self.resident, device_tree=self.tree is not None, tree=self.tree,
+                                         tree_lock=self.tree_lock)
             self._ics = None
 
     @property
@@ -135,12 +139,25 @@ class Engine:
     """Advances a set of clusters one block step each per engine step."""
 
     def __init__(self, precision="mixed", device=0, max_clusters=256, max_active=1 << 21, max_items=1 << 20,
-                 max_rows=1 << 21, rebuild_workers=4, resident=False):
+                 max_rows=1 << 21, rebuild_workers=4, resident=False, device_tree=False, tree_n_max=0):
         import torch
 
         # resident: each cluster's particle state stays on the device; the block
         # scheduler and the corrector of all clusters run there in batched launches
         self.resident = bool(resident)
+        # device_tree (resident only): tree times rebuild on the device with one
+        # builder shared by all clusters of up to tree_n_max particles (larger
+        # ones rebuild through the host); rebuild workers take turns on it
+        self.tree = None
+        self.tree_lock = threading.Lock()
+        if device_tree:
+            if not resident:
+                raise ValueError("device rebuilds need the resident engine")
+            if tree_n_max < 1:
+                raise ValueError("tree_n_max must be positive")
+            self._tree_stream = torch.cuda.Stream(device=device)
+            self.tree = B.DeviceTree(n_max=int(tree_n_max), device=device, stream=self._tree_stream.cuda_stream)
+            self.tree_n_max = int(tree_n_max)
         self.torch = torch
         self.precision, self.device = precision, device
         self.stream = torch.cuda.Stream(device=device)
@@ -174,7 +191,9 @@ class Engine:
         del dev
 
     def new_cluster(self, spec: RunSpec) -> Cluster:
-        return Cluster(spec, self.precision, self.stream.cuda_stream, self.device, resident=self.resident)
+        shared = self.tree is not None and spec.n <= self.tree_n_max
+        return Cluster(spec, self.precision, self.stream.cuda_stream, self.device, resident=self.resident,
+                       tree=self.tree if shared else None, tree_lock=self.tree_lock if shared else None)
 
     def add(self, c: Cluster):
         if len(self.clusters) >= self.max_clusters:
@@ -392,6 +411,9 @@ class Engine:
             c.close()
         self.clusters = []
         self.batch.close()
+        if self.tree is not None:
+            self.tree.close()
+            self.tree = None
 
 
 @dataclasses.dataclass

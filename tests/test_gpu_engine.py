@@ -163,3 +163,11 @@ def test_resident_engine_equals_host_engine():
     alone, _ = run_engine([specs[1]], resident=True, rebuild_workers=0)
     for f in FIELDS:
         assert np.array_equal(alone[0][f], dev[1][f]), f
+    # rebuilds on the device, one builder shared by the clusters (the largest
+    # cluster does not fit it and rebuilds through the host)
+    say("engine: resident with device rebuilds")
+    dtree, (_, _, done) = run_engine(specs, resident=True, device_tree=True, tree_n_max=2500)
+    assert done == [60, 60, 60]
+    for k in range(len(specs)):
+        for f in FIELDS:
+            assert np.array_equal(host[k][f], dtree[k][f]), (k, f)
