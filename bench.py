@@ -449,6 +449,8 @@ def main():
     ap.add_argument("--no-all-active", action="store_true")
     ap.add_argument("--no-resident", action="store_true", help="skip the device-resident integration leg")
     ap.add_argument("--no-tree-build", action="store_true", help="skip the device tree-build leg")
+    ap.add_argument("--tree-build-only", action="store_true",
+                    help="only time step 1 (device builder and host builder) on the workload's initial state")
     ap.add_argument("--host-engine", action="store_true",
                     help="ensemble/served: drive the clusters from the host (scheduler and corrector on the CPU)")
     ap.add_argument("--host-rebuild", action="store_true",
@@ -492,6 +494,10 @@ def main():
     log(f"workload {cfg.name}: N={cfg.n} theta={cfg.theta} eps={cfg.eps:.3g} dt_tree={cfg.dt_tree} "
         f"eta={cfg.eta} n_crit={cfg.n_crit}")
     x, v, m = W.make_initial_conditions(cfg)
+    if args.tree_build_only:
+        tb = bench_tree_build(torch, B, x, v, m, cfg)
+        print(json.dumps({"workload": cfg.name, "tree_build": tb}), flush=True)
+        return
     t0 = time.perf_counter()
     # The start-up runs the eagerly-predicting kernel (bit-identical predicted
     # values, another instantiation) so that in a kernel trace every launch of
