@@ -522,16 +522,19 @@ def main():
     rec_all.steps.append((t_all, np.arange(sim.n, dtype=np.int32), None))
     log(f"start-up done: {sim.n_block_steps} block steps, {sim.n_particle_steps} particle steps in "
         f"{time.perf_counter() - t_start:.1f} s")
-    # the same start-up span again with the state resident on the device
-    # (scheduler and corrector there; the host only plans each step's work)
+    # the same start-up span integrated three ways with the fused kernel (what a
+    # run uses; the recording run above predicts eagerly only to keep the fused
+    # kernel's launches in a trace to the measured replay): host-driven, and
+    # resident on the device with the tree time rebuilt through the host or on
+    # the device
     integ = None
     if not args.no_resident:
-        def resident_run(device_tree):
-            """The start-up span resident on the device, then the all-particle step
-            at t = dt_tree and the rebuild there (host or device builder)."""
+        def integrate(resident, device_tree=False):
+            """t = 0 up to the all-particle step at t = dt_tree, then that step and
+            the rebuild there."""
             rs = driver.Simulation(x, v, m, eps2=cfg.eps2, dt_tree=cfg.dt_tree, eta=cfg.eta, theta=cfg.theta,
-                                   n_crit=cfg.n_crit, n_leaf=cfg.n_leaf, precision="mixed", predict_mode="eager",
-                                   resident=True, device_tree=device_tree)
+                                   n_crit=cfg.n_crit, n_leaf=cfg.n_leaf, precision="mixed", predict_mode="fused",
+                                   resident=resident, device_tree=device_tree)
             torch.cuda.synchronize()
             t0_ = time.perf_counter()
             while rs.next_time() < cfg.dt_tree:
@@ -543,28 +546,33 @@ def main():
             tb = time.perf_counter()
             rs.step()                      # the all-particle step, then the rebuild
             torch.cuda.synchronize()
-            with_rebuild = time.perf_counter() - tb
+            tail = time.perf_counter() - tb
             rebuild = rs.timers["tree"] - tree0
             rs.sync_state()
             state = (rs.x.copy(), rs.ids.copy())
             rs.close()
-            return span, steps, with_rebuild, rebuild, state
-        t_res, st_res, tail_host, reb_host, s_host = resident_run(False)
-        _, _, tail_dev, reb_dev, s_dev = resident_run(True)
-        same = st_res == (steps_startup, psteps_startup)
-        same_tree = bool(np.array_equal(s_host[0], s_dev[0]) and np.array_equal(s_host[1], s_dev[1]))
+            return span, steps, tail, rebuild, state
+        t_host, st_host, tail_hd, reb_hd, s_hd = integrate(False)
+        t_res, st_res, tail_host, reb_host, s_host = integrate(True)
+        _, st_dev, tail_dev, reb_dev, s_dev = integrate(True, device_tree=True)
+        same = st_host == st_res == st_dev == (steps_startup, psteps_startup)
+        same_state = all(bool(np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]))
+                         for a, b in ((s_hd, s_host), (s_hd, s_dev)))
         integ = {"span": f"t = 0 to the all-particle step at t = {cfg.dt_tree} ({steps_startup} block steps, "
-                         f"{psteps_startup} particle steps)",
-                 "host_driven_s": t_host_startup, "resident_s": t_res, "same_steps": same,
-                 "block_steps_per_s": {"host_driven": steps_startup / t_host_startup, "resident": steps_startup / t_res},
-                 "particle_steps_per_s": {"host_driven": psteps_startup / t_host_startup,
+                         f"{psteps_startup} particle steps), fused kernel",
+                 "host_driven_s": t_host, "resident_s": t_res, "same_steps": same,
+                 "block_steps_per_s": {"host_driven": steps_startup / t_host, "resident": steps_startup / t_res},
+                 "particle_steps_per_s": {"host_driven": psteps_startup / t_host,
                                           "resident": psteps_startup / t_res},
-                 "all_particle_step_and_rebuild_s": {"host_builder": tail_host, "device_builder": tail_dev},
-                 "rebuild_s": {"host_builder": reb_host, "device_builder": reb_dev},
-                 "device_rebuild_same_state": same_tree}
-        log(f"integration start-up: host-driven {t_host_startup:.2f} s, resident {t_res:.2f} s "
-            f"({steps_startup / t_res:.0f} block steps/s), same steps {same}; rebuild at t={cfg.dt_tree}: host "
-            f"{reb_host * 1e3:.1f} ms, device {reb_dev * 1e3:.1f} ms, same state {same_tree}")
+                 "all_particle_step_and_rebuild_s": {"host_driven": tail_hd, "resident_host_builder": tail_host,
+                                                     "resident_device_builder": tail_dev},
+                 "rebuild_s": {"host_driven": reb_hd, "resident_host_builder": reb_host,
+                               "resident_device_builder": reb_dev},
+                 "same_state_after_rebuild": same_state}
+        log(f"integration start-up (fused): host-driven {t_host:.2f} s, resident {t_res:.2f} s "
+            f"({steps_startup / t_res:.0f} block steps/s), same steps {same}; rebuild at t={cfg.dt_tree}: host-driven "
+            f"{reb_hd * 1e3:.1f} ms, resident via host {reb_host * 1e3:.1f} ms, on the device "
+            f"{reb_dev * 1e3:.1f} ms, same state {same_state}")
     rec = Recorded(sim)
     need = args.warmup + args.steps
     while len(rec.steps) < need:

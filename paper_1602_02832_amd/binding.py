@@ -400,10 +400,13 @@ class Context:
         """ht_dev_step: force, corrector and j-record update of the last next block, on the device."""
         _check(device_lib().ht_dev_step(self._h, float(eta), float(dt_tree)))
 
-    def state_rebuild(self, tree, n, n_leaf, n_crit, theta, t_tree):
+    def state_rebuild(self, tree, n, n_leaf, n_crit, theta, t_tree, out=None):
         """ht_state_rebuild: step 1 on the device for the resident state with the
-        DeviceTree `tree`; returns perm (perm[new] = old)."""
-        perm = np.empty(n, np.int64)
+        DeviceTree `tree`; returns perm (perm[new] = old), in `out` if given
+        (int64, n entries; pinned memory makes the copy faster)."""
+        perm = np.empty(n, np.int64) if out is None else out
+        if perm.dtype != np.int64 or perm.shape != (n,) or not perm.flags.c_contiguous:
+            raise ValueError("out must be a contiguous int64 array of n entries")
         _check(device_lib().ht_state_rebuild(self._h, tree._h, int(n_leaf), int(n_crit), float(theta),
                                              float(t_tree), _ptr(perm, ctypes.c_int64)))
         return perm

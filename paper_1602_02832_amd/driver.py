@@ -72,6 +72,8 @@ class Simulation:
         self._dtree = tree
         self._own_dtree = tree is None
         self._dtree_lock = tree_lock
+        self._perm_pin = None       # pinned landing buffer of a device rebuild's permutation
+        self._perms = []            # permutations not yet applied to the host's m and ids
         self.n_device_rebuilds = 0
         self._pending_dev = None
         self.n_block_steps = 0
@@ -88,8 +90,16 @@ class Simulation:
         if self.resident:
             self.ctx.state_enable()
             self.ctx.state_set(self.t0, self.dt, self.m, self.x, self.v, self.a, self.j, self.pot)
-        if self.device_tree and self._dtree is None:
-            self._dtree = B.DeviceTree(n_max=self.n, device=self.device, stream=self.stream)
+        if self.device_tree:
+            import torch
+            if self._dtree is None:
+                self._dtree = B.DeviceTree(n_max=self.n, device=self.device, stream=self.stream)
+            self._perm_pin = torch.empty(self.n, dtype=torch.int64, pin_memory=True)
+            # one device rebuild now, at t = 0 where every particle is synchronised and
+            # already in key order (the same tree, bit for bit), sizes the builder's
+            # arrays so that later rebuilds allocate nothing
+            self._rebuild_on_device()
+            self.n_device_rebuilds = 0
 
     # ------------------------------------------------------------------ context
     def _make_ctx(self, node_max, group_max, list_max):
@@ -152,9 +162,18 @@ class Simulation:
             return self._pending_dev[0]
         return float(np.min(self.t0 + self.dt))
 
+    def _apply_perms(self):
+        """Device rebuilds reorder the particles on the device; the host's masses
+        and identities follow here, when they are needed."""
+        for p in self._perms:
+            self.m = np.ascontiguousarray(self.m[p])
+            self.ids = np.ascontiguousarray(self.ids[p])
+        self._perms = []
+
     def sync_state(self):
         """Resident mode: copy the device state into the host arrays."""
         if self.resident:
+            self._apply_perms()
             self.t0, self.dt, self.x, self.v, self.a, self.j, self.pot = self.ctx.state_get(self.n)
 
     def begin_step(self):
@@ -223,14 +242,14 @@ class Simulation:
         lock = self._dtree_lock if self._dtree_lock is not None else contextlib.nullcontext()
         with lock:
             try:
-                perm = self.ctx.state_rebuild(self._dtree, self.n, self.n_leaf, self.n_crit, self.theta, self.t)
+                perm = self.ctx.state_rebuild(self._dtree, self.n, self.n_leaf, self.n_crit, self.theta, self.t,
+                                              out=self._perm_pin.numpy())
             except B.HTError as e:
                 if e.code != -2:      # not a capacity shortfall
                     raise
                 return False
             M, G, E, _ = self._dtree.sizes()
-        self.m = np.ascontiguousarray(self.m[perm])
-        self.ids = np.ascontiguousarray(self.ids[perm])
+        self._perms.append(perm.copy())
         self.tree = types.SimpleNamespace(n_node=M, n_group=G, n_entries=E)
         self.t_tree = self.t
         self.n_device_rebuilds += 1
