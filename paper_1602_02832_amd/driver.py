@@ -74,6 +74,7 @@ class Simulation:
         self._dtree_lock = tree_lock
         self._perm_pin = None       # pinned landing buffer of a device rebuild's permutation
         self._perms = []            # permutations not yet applied to the host's m and ids
+        self.n_host_rebuilds = 0    # resident rebuilds that went through the host
         self.n_device_rebuilds = 0
         self._pending_dev = None
         self.n_block_steps = 0
@@ -230,6 +231,7 @@ class Simulation:
         (device_tree) or through the host (state back, host builder, state up)."""
         if self.device_tree and self._rebuild_on_device():
             return
+        self.n_host_rebuilds += 1
         self.sync_state()
         if not np.all(self.t0 == self.t):
             raise AssertionError("particles not synchronised at a tree time")

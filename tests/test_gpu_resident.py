@@ -108,3 +108,27 @@ def test_device_rebuilds_plummer16k_mixed():
         assert np.array_equal(getattr(sims[0], f), getattr(sims[1], f)), f
     for s in sims:
         s.close()
+
+
+def test_device_rebuild_falls_back_when_the_tree_outgrows_the_context():
+    """With no list headroom, a tree time whose tree outgrows the context (nodes,
+    groups or list entries) makes ht_state_rebuild refuse (HT_ERANGE, context
+    unchanged) and the driver take the host path with a larger context; the
+    run still equals host rebuilds."""
+    c = W.config("plummer2k")
+    say("device rebuild fallback to the host path")
+    x, v, m = W.make_initial_conditions(c)
+    sims = [driver.Simulation(x, v, m, eps2=c.eps2, dt_tree=c.dt_tree, eta=c.eta, theta=c.theta, n_crit=c.n_crit,
+                              precision="mixed", resident=True, device_tree=d, list_headroom=1.0)
+            for d in (False, True)]
+    for s in sims:
+        s.run(c.t_end)
+        s.sync_state()
+    dev = sims[1]
+    assert dev.n_host_rebuilds >= 1 and dev.n_host_rebuilds + dev.n_device_rebuilds == 16, \
+        (dev.n_host_rebuilds, dev.n_device_rebuilds)
+    assert np.array_equal(sims[0].ids, dev.ids)
+    for f in FIELDS + ("m",):
+        assert np.array_equal(getattr(sims[0], f), getattr(dev, f)), f
+    for s in sims:
+        s.close()
