@@ -529,22 +529,28 @@ def main():
     # the device
     integ = None
     if not args.no_resident:
-        def integrate(resident, device_tree=False):
+        def integrate(resident, device_tree=False, device_loop=False):
             """t = 0 up to the all-particle step at t = dt_tree, then that step and
             the rebuild there."""
             rs = driver.Simulation(x, v, m, eps2=cfg.eps2, dt_tree=cfg.dt_tree, eta=cfg.eta, theta=cfg.theta,
                                    n_crit=cfg.n_crit, n_leaf=cfg.n_leaf, precision="mixed", predict_mode="fused",
-                                   resident=resident, device_tree=device_tree)
+                                   resident=resident, device_tree=device_tree, device_loop=device_loop)
             torch.cuda.synchronize()
             t0_ = time.perf_counter()
-            while rs.next_time() < cfg.dt_tree:
-                rs.step()
+            if device_loop:
+                rs.run(cfg.dt_tree - math.ldexp(1.0, -41))   # every block time before dt_tree
+            else:
+                while rs.next_time() < cfg.dt_tree:
+                    rs.step()
             torch.cuda.synchronize()
             span = time.perf_counter() - t0_
             steps = (rs.n_block_steps, rs.n_particle_steps)
             tree0 = rs.timers["tree"]
             tb = time.perf_counter()
-            rs.step()                      # the all-particle step, then the rebuild
+            if device_loop:
+                rs.run(cfg.dt_tree)        # the all-particle step, then the rebuild
+            else:
+                rs.step()
             torch.cuda.synchronize()
             tail = time.perf_counter() - tb
             rebuild = rs.timers["tree"] - tree0
@@ -555,22 +561,26 @@ def main():
         t_host, st_host, tail_hd, reb_hd, s_hd = integrate(False)
         t_res, st_res, tail_host, reb_host, s_host = integrate(True)
         _, st_dev, tail_dev, reb_dev, s_dev = integrate(True, device_tree=True)
-        same = st_host == st_res == st_dev == (steps_startup, psteps_startup)
+        t_loop, st_loop, tail_loop, _, s_loop = integrate(True, device_tree=True, device_loop=True)
+        same = st_host == st_res == st_dev == st_loop == (steps_startup, psteps_startup)
         same_state = all(bool(np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]))
-                         for a, b in ((s_hd, s_host), (s_hd, s_dev)))
+                         for a, b in ((s_hd, s_host), (s_hd, s_dev), (s_hd, s_loop)))
         integ = {"span": f"t = 0 to the all-particle step at t = {cfg.dt_tree} ({steps_startup} block steps, "
                          f"{psteps_startup} particle steps), fused kernel",
-                 "host_driven_s": t_host, "resident_s": t_res, "same_steps": same,
-                 "block_steps_per_s": {"host_driven": steps_startup / t_host, "resident": steps_startup / t_res},
+                 "host_driven_s": t_host, "resident_s": t_res, "device_loop_s": t_loop, "same_steps": same,
+                 "block_steps_per_s": {"host_driven": steps_startup / t_host, "resident": steps_startup / t_res,
+                                       "device_loop": steps_startup / t_loop},
                  "particle_steps_per_s": {"host_driven": psteps_startup / t_host,
-                                          "resident": psteps_startup / t_res},
+                                          "resident": psteps_startup / t_res,
+                                          "device_loop": psteps_startup / t_loop},
                  "all_particle_step_and_rebuild_s": {"host_driven": tail_hd, "resident_host_builder": tail_host,
                                                      "resident_device_builder": tail_dev},
                  "rebuild_s": {"host_driven": reb_hd, "resident_host_builder": reb_host,
                                "resident_device_builder": reb_dev},
                  "same_state_after_rebuild": same_state}
         log(f"integration start-up (fused): host-driven {t_host:.2f} s, resident {t_res:.2f} s "
-            f"({steps_startup / t_res:.0f} block steps/s), same steps {same}; rebuild at t={cfg.dt_tree}: host-driven "
+            f"({steps_startup / t_res:.0f} block steps/s), device loop {t_loop:.3f} s "
+            f"({steps_startup / t_loop:.0f} block steps/s), same steps {same}; rebuild at t={cfg.dt_tree}: host-driven "
             f"{reb_hd * 1e3:.1f} ms, resident via host {reb_host * 1e3:.1f} ms, on the device "
             f"{reb_dev * 1e3:.1f} ms, same state {same_state}")
     rec = Recorded(sim)

@@ -204,6 +204,24 @@ int ht_state_set(ht_ctx *ctx, int32_t n, const double *t0, const double *dt, con
 int ht_state_get(ht_ctx *ctx, double *t0, double *dt, double *x, double *v, double *a, double *jerk, double *pot);
 int ht_dev_next_block(ht_ctx *ctx, double *t_next, int64_t *n_active, const int32_t **active);
 int ht_dev_step(ht_ctx *ctx, double eta, double dt_tree);
+/* The same step for the direct Hermite scheme (Section 2's comparison): the
+ * force on the active set over all N particles (as ht_force_direct_async);
+ * needs no nodes or lists, and no rebuild at tree times. */
+int ht_dev_step_direct(ht_ctx *ctx, double eta, double dt_tree);
+/* Resident mode: up to max_steps block steps (Section 2, steps 2 and 4a-6)
+ * queued back to back with no host round trip between them.  Each step runs
+ * the scheduler, a device work planner that builds the host planner's work
+ * items (so the forces, and the run, have the same bits as step-by-step
+ * ht_dev_next_block + ht_dev_step), the force and reduce launches on fixed
+ * grids, and the corrector.  The loop stops before the first block time after
+ * t_stop, and after the step at t_stop (a tree time, where the caller
+ * rebuilds).  Synchronises once, at the end; *steps, *t_last (block time of
+ * the last step taken) and *particle_steps report what was done.  Needs fused
+ * prediction and a whole-number gather cost (HT_EINVAL otherwise).
+ * HT_ERANGE if a plan exceeded the context's capacity or a step fell below
+ * 2^-40: the steps before it stand and the state is consistent. */
+int ht_dev_run(ht_ctx *ctx, double eta, double dt_tree, double t_stop, int32_t max_steps, int32_t *steps,
+               double *t_last, int64_t *particle_steps);
 int ht_state_rebuild(ht_ctx *ctx, htd_tree *t, int32_t n_leaf, int32_t n_crit, double theta, double t_tree,
                      int64_t *perm);
 

@@ -126,6 +126,8 @@ def device_lib():
             "ht_state_get": [_vp, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp],
             "ht_dev_next_block": [_vp, ctypes.POINTER(ctypes.c_double), _c_i64p, ctypes.POINTER(_c_i32p)],
             "ht_dev_step": [_vp, d, d],
+            "ht_dev_step_direct": [_vp, d, d],
+            "ht_dev_run": [_vp, d, d, d, i, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double), _c_i64p],
             "ht_state_rebuild": [_vp, _vp, i, i, d, d, _c_i64p],
             "ht_force_batch_async": [i, ctypes.POINTER(_vp), _c_i32p, ctypes.POINTER(_c_i32p),
                                      ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp)],
@@ -399,6 +401,18 @@ class Context:
     def dev_step(self, eta, dt_tree):
         """ht_dev_step: force, corrector and j-record update of the last next block, on the device."""
         _check(device_lib().ht_dev_step(self._h, float(eta), float(dt_tree)))
+
+    def dev_run(self, eta, dt_tree, t_stop, max_steps):
+        """ht_dev_run: up to max_steps block steps on the device, stopping at t_stop;
+        returns (steps, block time of the last step, particle steps)."""
+        k, t, p = ctypes.c_int32(), ctypes.c_double(), ctypes.c_int64()
+        _check(device_lib().ht_dev_run(self._h, float(eta), float(dt_tree), float(t_stop), int(max_steps),
+                                       ctypes.byref(k), ctypes.byref(t), ctypes.byref(p)))
+        return k.value, t.value, p.value
+
+    def dev_step_direct(self, eta, dt_tree):
+        """ht_dev_step_direct: as dev_step with the force over all particles (the direct scheme)."""
+        _check(device_lib().ht_dev_step_direct(self._h, float(eta), float(dt_tree)))
 
     def state_rebuild(self, tree, n, n_leaf, n_crit, theta, t_tree, out=None):
         """ht_state_rebuild: step 1 on the device for the resident state with the

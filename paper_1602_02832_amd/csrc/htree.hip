@@ -763,7 +763,8 @@ struct SchedEntry {
     int64_t n, chunk;
     int32_t nb, first_block;
     DevOut* out;
-    int32_t* active_host;
+    int32_t* active_host;     // nullptr: no host copy (device loop)
+    const int32_t* halt;      // device loop: nonzero once the loop has stopped; else nullptr
 };
 
 __device__ __forceinline__ const SchedEntry& sched_entry(const SchedEntry& e0, const SchedEntry* tab, int n_tab,
@@ -784,6 +785,7 @@ __global__ __launch_bounds__(kWG) void sched_min_kernel(SchedEntry e0, const Sch
     __shared__ double red[4];
     int b;
     const SchedEntry& e = sched_entry(e0, tab, n_tab, b);
+    if (e.halt && *e.halt) return;
     const int64_t lo = b * e.chunk, hi = lo + e.chunk < e.n ? lo + e.chunk : e.n;
     double v = HUGE_VAL;
     for (int64_t i = lo + threadIdx.x; i < hi; i += kWG) v = fmin(v, e.t0[i] + e.dt[i]);
@@ -798,6 +800,7 @@ __global__ __launch_bounds__(kWG) void sched_count_kernel(SchedEntry e0, const S
     __shared__ int cnt[4];
     int b;
     const SchedEntry& e = sched_entry(e0, tab, n_tab, b);
+    if (e.halt && *e.halt) return;
     double v = HUGE_VAL;
     for (int k = threadIdx.x; k < e.nb; k += kWG) v = fmin(v, e.bmin[k]);
     const double t_next = block_min(v, red);
@@ -821,6 +824,7 @@ __global__ __launch_bounds__(kWG) void sched_write_kernel(SchedEntry e0, const S
     __shared__ int wsum[4];
     int b;
     const SchedEntry& e = sched_entry(e0, tab, n_tab, b);
+    if (e.halt && *e.halt) return;
     double v = HUGE_VAL;
     for (int k = threadIdx.x; k < e.nb; k += kWG) v = fmin(v, e.bmin[k]);
     const double t_next = block_min(v, red);
@@ -844,7 +848,7 @@ __global__ __launch_bounds__(kWG) void sched_write_kernel(SchedEntry e0, const S
         for (int w = 0; w < wave; ++w) at += wsum[w];
         if (due) {
             e.active[at] = static_cast<int32_t>(i);
-            e.active_host[at] = static_cast<int32_t>(i);
+            if (e.active_host) e.active_host[at] = static_cast<int32_t>(i);
         }
         pos += wsum[0] + wsum[1] + wsum[2] + wsum[3];
     }
@@ -878,18 +882,31 @@ __device__ __forceinline__ double dev_quantise(double cap, double t1) {
 
 // One context in a corrector launch: its state and records, its active set
 // (rows first_row .. first_row + n_active - 1 of the launch) and parameters.
+// Device loop state (ht_dev_run): the step in progress and the counts so far.
+struct DevLoop {
+    double t_cur;        // block time of the step in progress
+    int64_t n_corr;      // particles the corrector takes this step (0 once stopped)
+    int64_t steps, psteps, pairs;
+    int32_t halt;        // nonzero: every later kernel of the loop does nothing
+    int32_t stop_after;  // the step in progress is at the stop time
+    int32_t err;         // the device plan did not fit the context
+    int32_t pad;
+};
+
 struct CorrEntry {
     DevState s;
     void* rec;
     DevOut* out;
     int64_t n_active, first_row;
     double t1, eta, dt_tree;
+    const DevLoop* loop;   // device loop: count and block time read from it; else nullptr
 };
 
 template <class P>
 __global__ __launch_bounds__(kWG) void dev_correct_kernel(CorrEntry e0, const CorrEntry* tab, int n_tab,
                                                           int64_t total) {
 #pragma clang fp contract(off)
+    if (total < 0) total = e0.loop->n_corr;   // device loop (a single entry)
     for (int64_t r = blockIdx.x * static_cast<int64_t>(kWG) + threadIdx.x; r < total;
          r += static_cast<int64_t>(gridDim.x) * kWG) {
         const CorrEntry* ep = &e0;
@@ -905,7 +922,7 @@ __global__ __launch_bounds__(kWG) void dev_correct_kernel(CorrEntry e0, const Co
         const DevState& s = e.s;
         typename P::Rec* rec = static_cast<typename P::Rec*>(e.rec);
         const int64_t q = r - e.first_row;
-        const double t1 = e.t1;
+        const double t1 = e.loop ? e.loop->t_cur : e.t1;
         const int32_t i = s.active[q];
         const double D = t1 - s.t0[i];
         const double h2 = 0.5 * D, h3 = D / 3.0;
@@ -939,6 +956,271 @@ __global__ __launch_bounds__(kWG) void dev_correct_kernel(CorrEntry e0, const Co
         s.pot[i] = s.fpot[q];
         const int64_t k = 3 * static_cast<int64_t>(i);
         store_rec<P>(rec, i, t1, s.m[i], s.x + k, s.v + k, s.a + k, s.j + k);
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Device loop (ht_dev_run): block steps queued back to back with no host
+// round trip.  Per step: the three scheduler passes, loop_gate_kernel,
+// dev_plan_kernel, the force and reduce kernels (fixed grids, counts read from
+// the plan) and the corrector (count and block time read from the loop).
+
+// After the scheduler: take the step if its block time is at most the stop
+// time, else stop the loop (and every later kernel with it).
+__global__ void loop_gate_kernel(DevLoop* L, const DevOut* o, double t_stop, int64_t max_steps) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (L->halt) {
+        L->n_corr = 0;
+        return;
+    }
+    const double t = o->t_next;
+    const int64_t na = o->n_active;
+    if (L->stop_after || o->below_floor || !(t <= t_stop) || L->steps >= max_steps || na < 1) {
+        L->halt = 1;
+        L->n_corr = 0;
+        return;
+    }
+    L->t_cur = t;
+    L->n_corr = na;
+    L->steps += 1;
+    L->psteps += na;
+    if (t == t_stop) L->stop_after = 1;
+}
+
+// One tile of the device plan.
+struct DTile {
+    int64_t jb, je;
+    int32_t tb, ni;
+    int32_t tl, pad;
+    double cost;
+};
+
+struct PlanArgs {
+    DevLoop* loop;
+    const int32_t* active;     // this step's active particles, ascending (the scheduler's list)
+    const int64_t* gfirst;     // [n_groups + 1] first particle of each group, then N
+    const int64_t* loff;       // [n_groups + 1] list offsets
+    int32_t n_groups;
+    int32_t pad;
+    int32_t* gk;               // scratch: group of each active particle
+    int32_t* qk;               // scratch: first active position of each active group, then n_active
+    int32_t* qg;               // scratch: group of each active group
+    DTile* tiles;              // scratch
+    Entry* tab;                // out: the launch table (one entry)
+    Item* items;               // out
+    RTile* rtiles;             // out
+    int64_t items_max, partial_max;
+    double gather_cost, target_items;
+    Desc d;                    // the context's descriptor (t, active and outputs set here)
+    int8_t first_tile[257];
+};
+
+constexpr int kPlanWG = 512;
+
+// Exclusive prefix sum over the work-group (kPlanWG threads); returns the total.
+template <class V>
+__device__ inline V plan_scan(V v, V* excl, V* s_wave) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    V x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const V y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_wave[wave] = x;
+    __syncthreads();
+    V before = 0, total = 0;
+    for (int w = 0; w < kPlanWG / 64; ++w) {
+        const V sw = s_wave[w];
+        if (w < wave) before += sw;
+        total += sw;
+    }
+    *excl = before + x - v;
+    __syncthreads();
+    return total;
+}
+
+// The host planner's work items (plan()), built on the device by one
+// work-group: active groups, least-cost tiles, cost-based splits with the same
+// quantum (the costs are whole numbers when the gather cost is, so their sum
+// does not depend on the order of addition), in group order.  The order of the
+// items does not change any result.
+__global__ __launch_bounds__(kPlanWG) void dev_plan_kernel(PlanArgs A) {
+    __shared__ int64_t s_w64[kPlanWG / 64];
+    __shared__ double s_wd[kPlanWG / 64];
+    __shared__ int8_t s_ft[260];   // the tile table, indexed per thread
+    const int t = threadIdx.x;
+    if (t < 257) s_ft[t] = A.first_tile[t];
+    __syncthreads();
+    DevLoop* L = A.loop;
+    if (L->halt) {
+        if (t == 0) {
+            A.tab->n_items = 0;
+            A.tab->n_rtiles = 0;
+        }
+        return;
+    }
+    const int64_t n = L->n_corr;
+    // 1. the group of every active particle
+    for (int64_t k = t; k < n; k += kPlanWG) {
+        const int64_t id = A.active[k];
+        int lo = 0, hi = A.n_groups;   // gfirst[lo] <= id < gfirst[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (A.gfirst[mid] <= id) lo = mid; else hi = mid;
+        }
+        A.gk[k] = lo;
+    }
+    __syncthreads();
+    // 2. active groups: first active position and group, in order
+    int64_t nq = 0;
+    for (int64_t base = 0; base < n; base += kPlanWG) {
+        const int64_t k = base + t;
+        const int64_t f = (k < n && (k == 0 || A.gk[k] != A.gk[k - 1])) ? 1 : 0;
+        int64_t ex;
+        const int64_t tot = plan_scan<int64_t>(f, &ex, s_w64);
+        if (f) {
+            A.qk[nq + ex] = static_cast<int32_t>(k);
+            A.qg[nq + ex] = A.gk[k];
+        }
+        nq += tot;
+    }
+    if (t == 0) A.qk[nq] = static_cast<int32_t>(n);
+    __syncthreads();
+    // 3. tiles: the least-cost cover of each group's active particles
+    int64_t ntile = 0;
+    double total = 0.0;
+    int64_t pairs = 0;
+    for (int64_t base = 0; base < nq; base += kPlanWG) {
+        const int64_t q = base + t;
+        int64_t cnt = 0;
+        if (q < nq)
+            for (int64_t r = A.qk[q + 1] - A.qk[q]; r > 0;) {
+                const int tl = r >= 256 ? 8 : s_ft[r];
+                r -= r < (int64_t(1) << tl) ? r : (int64_t(1) << tl);
+                ++cnt;
+            }
+        int64_t ex;
+        const int64_t tot = plan_scan<int64_t>(cnt, &ex, s_w64);
+        if (q < nq) {
+            const int32_t g = A.qg[q];
+            const int64_t jb = A.loff[g], je = A.loff[g + 1];
+            const int64_t rounds = (je - jb + kRound - 1) / kRound;
+            int64_t at = ntile + ex;
+            int64_t tb = A.qk[q];
+            for (int64_t r = A.qk[q + 1] - A.qk[q]; r > 0; ++at) {
+                const int tl = r >= 256 ? 8 : s_ft[r];
+                const int64_t ni = r < (int64_t(1) << tl) ? r : (int64_t(1) << tl);
+                const double cost = static_cast<double>(rounds) * (A.gather_cost + static_cast<double>(1 << tl));
+                A.tiles[at] = DTile{jb, je, static_cast<int32_t>(tb), static_cast<int32_t>(ni), tl, 0, cost};
+                total += cost;
+                pairs += ni * (je - jb);
+                tb += ni;
+                r -= ni;
+            }
+        }
+        ntile += tot;
+    }
+    {   // whole-number costs: the sum is exact in any order
+        double ex;
+        total = plan_scan<double>(total, &ex, s_wd);
+        int64_t ep;
+        pairs = plan_scan<int64_t>(pairs, &ep, s_w64);
+    }
+    __syncthreads();
+    // 4. splits: the quantum doubles until the plan fits, as on the host
+    double quantum = total / A.target_items;
+    int attempt = 0;
+    int64_t n_items = 0, n_parts = 0;
+    for (;; ++attempt) {
+        int64_t ci = 0, cp = 0;
+        for (int64_t q = t; q < ntile; q += kPlanWG) {
+            const DTile T = A.tiles[q];
+            const int64_t rsz = int64_t(kRound) * round_mult(1 << T.tl);
+            const int64_t rounds = (T.je - T.jb + rsz - 1) / rsz;
+            int64_t ns = (attempt > 60 || !(quantum > 0.0)) ? 1 : static_cast<int64_t>(ceil(T.cost / quantum));
+            ns = ns < rounds ? ns : rounds;
+            ns = ns > 1 ? ns : 1;
+            if (ns == 1) {
+                ci += 1;
+            } else {
+                const int64_t per = (rounds + ns - 1) / ns * rsz;
+                const int64_t nsu = (T.je - T.jb + per - 1) / per;
+                ci += nsu;
+                cp += nsu * T.ni;
+            }
+        }
+        int64_t ex;
+        n_items = plan_scan<int64_t>(ci, &ex, s_w64);
+        n_parts = plan_scan<int64_t>(cp, &ex, s_w64);
+        if (n_items <= A.items_max && n_parts <= A.partial_max) break;
+        if (attempt > 60) {   // does not fit: stop the loop before this step's force
+            if (t == 0) {
+                L->err = 1;
+                L->halt = 1;
+                L->steps -= 1;
+                L->psteps -= n;
+                L->n_corr = 0;
+                A.tab->n_items = 0;
+                A.tab->n_rtiles = 0;
+            }
+            return;
+        }
+        quantum *= 2.0;
+    }
+    // 5. items and split tiles, in tile order
+    int64_t io = 0, po = 0, ro = 0;
+    for (int64_t base = 0; base < ntile; base += kPlanWG) {
+        const int64_t q = base + t;
+        int64_t ci = 0, cp = 0, cr = 0, ns = 1, per = 0, nsu = 1;
+        DTile T{};
+        if (q < ntile) {
+            T = A.tiles[q];
+            const int64_t rsz = int64_t(kRound) * round_mult(1 << T.tl);
+            const int64_t rounds = (T.je - T.jb + rsz - 1) / rsz;
+            ns = (attempt > 60 || !(quantum > 0.0)) ? 1 : static_cast<int64_t>(ceil(T.cost / quantum));
+            ns = ns < rounds ? ns : rounds;
+            ns = ns > 1 ? ns : 1;
+            if (ns == 1) {
+                ci = 1;
+            } else {
+                per = (rounds + ns - 1) / ns * rsz;
+                nsu = (T.je - T.jb + per - 1) / per;
+                ci = nsu;
+                cp = nsu * T.ni;
+                cr = 1;
+            }
+        }
+        int64_t ei, ep, er;
+        const int64_t ti = plan_scan<int64_t>(ci, &ei, s_w64);
+        const int64_t tp = plan_scan<int64_t>(cp, &ep, s_w64);
+        const int64_t tr = plan_scan<int64_t>(cr, &er, s_w64);
+        if (q < ntile) {
+            const int16_t ni = static_cast<int16_t>(T.ni), tl = static_cast<int16_t>(T.tl);
+            if (ns == 1) {
+                A.items[io + ei] = Item{T.jb, T.je, -1, T.tb, ni, tl};
+            } else {
+                const int64_t pb = po + ep;
+                int64_t s = 0;
+                for (int64_t b = T.jb; b < T.je; b += per, ++s)
+                    A.items[io + ei + s] = Item{b, b + per < T.je ? b + per : T.je, pb + s * T.ni, T.tb, ni, tl};
+                A.rtiles[ro + er] = RTile{pb, T.tb, T.ni, static_cast<int32_t>(nsu), 0};
+            }
+        }
+        io += ti;
+        po += tp;
+        ro += tr;
+    }
+    if (t == 0) {
+        Entry& e = *A.tab;
+        e.d = A.d;
+        e.d.t = L->t_cur;
+        e.items = A.items;
+        e.rtiles = A.rtiles;
+        e.first_item = 0;
+        e.first_rtile = 0;
+        e.n_items = io;
+        e.n_rtiles = ro;
+        L->pairs += pairs;
     }
 }
 
@@ -1111,6 +1393,14 @@ struct ht_ctx {
     // buffers on the device, the scheduler's results in pinned host memory
     DevState ds{};
     char* ds_mem = nullptr;
+    // device loop (ht_dev_run): its state, the scheduler's results in device
+    // memory, the group and list offsets and the planner's scratch
+    DevLoop* d_loop = nullptr;
+    DevOut* d_dout = nullptr;
+    int64_t* d_gfirst = nullptr;
+    int64_t* d_loff = nullptr;
+    int32_t *d_gk = nullptr, *d_qk = nullptr, *d_qg = nullptr;
+    DTile* d_tiles = nullptr;
     DevOut* h_dout = nullptr;
     int32_t* h_active = nullptr;
     double dev_t_next = 0.0;
@@ -1747,6 +2037,10 @@ int ht_set_nodes(ht_ctx* c, int32_t n_nodes, double t_tree, const double* m, con
     return HT_OK;
 }
 
+namespace {
+int upload_group_offsets(ht_ctx* c);
+}  // namespace
+
 int ht_set_interaction_lists(ht_ctx* c, int32_t n_groups, const int64_t* group_first, const int64_t* list_off,
                              const int32_t* entries) {
     if (!c) return fail(HT_EINVAL, "ctx is NULL");
@@ -1779,6 +2073,7 @@ int ht_set_interaction_lists(ht_ctx* c, int32_t n_groups, const int64_t* group_f
     c->n_groups = n_groups;
     c->n_entries = L;
     c->have_lists = true;
+    if (c->ds_mem) return upload_group_offsets(c);
     return HT_OK;
 }
 
@@ -1853,12 +2148,13 @@ SchedEntry sched_entry_of(const ht_ctx* c, int32_t first_block) {
     const int64_t n = c->n;
     const int nb = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(kSchedBlocks, (n + 2047) / 2048)));
     return SchedEntry{c->ds.t0, c->ds.dt, c->ds.active, c->ds.bmin, c->ds.bcount, n, (n + nb - 1) / nb, nb,
-                      first_block, c->h_dout, c->h_active};
+                      first_block, c->h_dout, c->h_active, nullptr};
 }
 
 // The corrector's table entry of a context's last active set, rows from first_row.
 CorrEntry corr_entry_of(const ht_ctx* c, int64_t first_row, double eta, double dt_tree) {
-    return CorrEntry{c->ds, c->ws + c->L.off_rec, c->h_dout, c->dev_n_active, first_row, c->dev_t_next, eta, dt_tree};
+    return CorrEntry{c->ds, c->ws + c->L.off_rec, c->h_dout, c->dev_n_active, first_row, c->dev_t_next, eta, dt_tree,
+                     nullptr};
 }
 
 int launch_correct(int precision, hipStream_t stream, const CorrEntry& e0, const CorrEntry* tab, int n_tab,
@@ -1990,6 +2286,17 @@ int ht_step_graph(ht_ctx* c, int32_t n_upd, const int32_t* d_idx, const double* 
 
 // ------------------------------------------------------------------------------------------------
 // device-resident integration
+namespace {
+// The group and list offsets for the device planner (resident state only).
+int upload_group_offsets(ht_ctx* c) {
+    const size_t b = (static_cast<size_t>(c->n_groups) + 1) * 8;
+    HT_HIP(hipMemcpyAsync(c->d_gfirst, c->group_first.data(), b, hipMemcpyHostToDevice, c->stream));
+    HT_HIP(hipMemcpyAsync(c->d_loff, c->list_off.data(), b, hipMemcpyHostToDevice, c->stream));
+    HT_HIP(hipStreamSynchronize(c->stream));   // pageable sources
+    return HT_OK;
+}
+}  // namespace
+
 int ht_state_enable(ht_ctx* c) {
     if (!c) return fail(HT_EINVAL, "ctx is NULL");
     if (c->ds_mem) return HT_OK;
@@ -2004,6 +2311,9 @@ int ht_state_enable(ht_ctx* c) {
     const size_t ot0 = take(n * 8), odt = take(n * 8), om = take(n * 8), opot = take(n * 8);
     const size_t oacc = take(n * 24), ojerk = take(n * 24), ofpot = take(n * 8), oact = take(n * 4);
     const size_t obmin = take(kSchedBlocks * 8), obcnt = take(kSchedBlocks * 4);
+    const size_t g1 = static_cast<size_t>(c->cfg.group_max) + 1;
+    const size_t oloop = take(sizeof(DevLoop)), odout = take(sizeof(DevOut)), ogf = take(g1 * 8), olo = take(g1 * 8);
+    const size_t ogk = take(n * 4), oqk = take((n + 1) * 4), oqg = take(n * 4), otl = take(n * sizeof(DTile));
     if (hipMalloc(&c->ds_mem, o) != hipSuccess) {
         c->ds_mem = nullptr;
         return fail(HT_ENOMEM, "hipMalloc of %zu bytes for the device state failed", o);
@@ -2016,6 +2326,18 @@ int ht_state_enable(ht_ctx* c) {
                      reinterpret_cast<double*>(b + oacc), reinterpret_cast<double*>(b + ojerk),
                      reinterpret_cast<double*>(b + ofpot), reinterpret_cast<int32_t*>(b + oact),
                      reinterpret_cast<double*>(b + obmin), reinterpret_cast<int32_t*>(b + obcnt)};
+    c->d_loop = reinterpret_cast<DevLoop*>(b + oloop);
+    c->d_dout = reinterpret_cast<DevOut*>(b + odout);
+    c->d_gfirst = reinterpret_cast<int64_t*>(b + ogf);
+    c->d_loff = reinterpret_cast<int64_t*>(b + olo);
+    c->d_gk = reinterpret_cast<int32_t*>(b + ogk);
+    c->d_qk = reinterpret_cast<int32_t*>(b + oqk);
+    c->d_qg = reinterpret_cast<int32_t*>(b + oqg);
+    c->d_tiles = reinterpret_cast<DTile*>(b + otl);
+    if (c->have_lists) {   // lists set before the state: their offsets for the device planner
+        int rc = upload_group_offsets(c);
+        if (rc) return rc;
+    }
     if (hipHostMalloc(reinterpret_cast<void**>(&c->h_dout), sizeof(DevOut), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&c->h_active), n * 4, hipHostMallocDefault) != hipSuccess)
         return fail(HT_ENOMEM, "hipHostMalloc for the scheduler results failed");
@@ -2118,6 +2440,8 @@ int ht_state_rebuild(ht_ctx* c, htd_tree* t, int32_t n_leaf, int32_t n_crit, dou
     c->list_off.resize(static_cast<size_t>(G) + 1);
     HT_HIP(hipMemcpyAsync(c->group_first.data(), w.group_first, (G + 1) * 8, hipMemcpyDeviceToHost, c->stream));
     HT_HIP(hipMemcpyAsync(c->list_off.data(), w.list_off, (G + 1) * 8, hipMemcpyDeviceToHost, c->stream));
+    HT_HIP(hipMemcpyAsync(c->d_gfirst, w.group_first, (G + 1) * 8, hipMemcpyDeviceToDevice, c->stream));
+    HT_HIP(hipMemcpyAsync(c->d_loff, w.list_off, (G + 1) * 8, hipMemcpyDeviceToDevice, c->stream));
     if (perm) HT_HIP(hipMemcpyAsync(perm, w.perm, n1, hipMemcpyDeviceToHost, c->stream));
     HT_HIP(hipStreamSynchronize(c->stream));
     c->n_nodes = static_cast<int32_t>(M);
@@ -2153,23 +2477,118 @@ int ht_dev_next_block(ht_ctx* c, double* t_next, int64_t* n_active, const int32_
     return HT_OK;
 }
 
-int ht_dev_step(ht_ctx* c, double eta, double dt_tree) {
+namespace {
+// Step 4a-6 for the active set of the last ht_dev_next_block: force over the
+// lists (or over all particles: the direct scheme), then the corrector.
+int dev_step(ht_ctx* c, double eta, double dt_tree, bool direct) {
     if (!c) return fail(HT_EINVAL, "ctx is NULL");
     if (!c->ds_mem) return fail(HT_ESTATE, "device state not enabled");
-    if (!c->have_lists) return fail(HT_ESTATE, "interaction lists not set");
+    if (!direct && !c->have_lists) return fail(HT_ESTATE, "interaction lists not set");
     if (c->dev_n_active < 1) return fail(HT_ESTATE, "ht_dev_next_block not called since the last step");
     if (!(eta > 0.0) || !(dt_tree > 0.0)) return fail(HT_EINVAL, "eta and dt_tree must be positive");
     const int32_t n_act = static_cast<int32_t>(c->dev_n_active);
     c->t_pred = c->dev_t_next;
     c->predicted = true;
     int rc = enqueue_step(c, DevRows{}, c->cfg.predict_mode == HT_PREDICT_EAGER, n_act, c->h_active, c->ds.acc,
-                          c->ds.jerk, c->ds.fpot, false);
+                          c->ds.jerk, c->ds.fpot, direct);
     if (rc) return rc;
     const CorrEntry e = corr_entry_of(c, 0, eta, dt_tree);
     rc = launch_correct(c->cfg.precision, c->stream, e, nullptr, 0, n_act);
     if (rc) return rc;
     c->dev_n_active = -1;
     c->predicted = false;   // records changed
+    return HT_OK;
+}
+}  // namespace
+
+int ht_dev_step(ht_ctx* c, double eta, double dt_tree) { return dev_step(c, eta, dt_tree, false); }
+
+int ht_dev_step_direct(ht_ctx* c, double eta, double dt_tree) { return dev_step(c, eta, dt_tree, true); }
+
+constexpr int kLoopCorrGrid = 1024;   // fixed corrector grid of the device loop (grid-stride)
+
+int ht_dev_run(ht_ctx* c, double eta, double dt_tree, double t_stop, int32_t max_steps, int32_t* steps,
+               double* t_last, int64_t* particle_steps) {
+    if (!c || !steps || !t_last || !particle_steps) return fail(HT_EINVAL, "NULL argument");
+    if (!c->ds_mem) return fail(HT_ESTATE, "device state not enabled");
+    if (!c->have_lists) return fail(HT_ESTATE, "interaction lists not set");
+    if (c->cfg.predict_mode != HT_PREDICT_FUSED) return fail(HT_EINVAL, "the device loop needs fused prediction");
+    if (c->gather_cost != std::floor(c->gather_cost))
+        return fail(HT_EINVAL, "the device loop plans with a whole-number gather cost (ht_set_tuning)");
+    if (!(eta > 0.0) || !(dt_tree > 0.0) || !std::isfinite(t_stop)) return fail(HT_EINVAL, "bad eta, dt_tree or t_stop");
+    if (max_steps < 1) return fail(HT_EINVAL, "max_steps < 1");
+    *steps = 0;
+    *t_last = c->dev_t_next;
+    *particle_steps = 0;
+    c->dev_n_active = -1;
+    HT_HIP(hipMemsetAsync(c->d_loop, 0, sizeof(DevLoop), c->stream));
+    HT_HIP(hipMemsetAsync(c->d_dout, 0, sizeof(DevOut), c->stream));
+    SchedEntry se = sched_entry_of(c, 0);
+    se.out = c->d_dout;
+    se.active_host = nullptr;
+    se.halt = &c->d_loop->halt;
+    CorrEntry ce = corr_entry_of(c, 0, eta, dt_tree);
+    ce.out = c->d_dout;
+    ce.loop = c->d_loop;
+    PlanArgs pa{};
+    pa.loop = c->d_loop;
+    pa.active = c->ds.active;
+    pa.gfirst = c->d_gfirst;
+    pa.loff = c->d_loff;
+    pa.n_groups = c->n_groups;
+    pa.gk = c->d_gk;
+    pa.qk = c->d_qk;
+    pa.qg = c->d_qg;
+    pa.tiles = c->d_tiles;
+    char* plan = c->ws + c->L.off_plan;
+    pa.tab = reinterpret_cast<Entry*>(plan);
+    pa.items = reinterpret_cast<Item*>(plan + align_up(kMaxBatch * sizeof(Entry)));
+    pa.rtiles = reinterpret_cast<RTile*>(plan + align_up(kMaxBatch * sizeof(Entry)) +
+                                         align_up(static_cast<size_t>(c->L.items_max) * sizeof(Item)));
+    pa.items_max = c->L.items_max;
+    pa.partial_max = c->L.partial_max;
+    pa.gather_cost = c->gather_cost;
+    pa.target_items = c->target_items;
+    pa.d = c->desc();
+    pa.d.active = c->ds.active;
+    pa.d.acc = c->ds.acc;
+    pa.d.jerk = c->ds.jerk;
+    pa.d.pot = c->ds.fpot;
+    std::memcpy(pa.first_tile, c->first_tile, sizeof(pa.first_tile));
+    const Entry* d_tab = pa.tab;
+    c->slots_all_free();
+    for (int32_t k = 0; k < max_steps; ++k) {
+        sched_min_kernel<<<se.nb, kWG, 0, c->stream>>>(se, nullptr, 0);
+        sched_count_kernel<<<se.nb, kWG, 0, c->stream>>>(se, nullptr, 0);
+        sched_write_kernel<<<se.nb, kWG, 0, c->stream>>>(se, nullptr, 0);
+        loop_gate_kernel<<<1, 64, 0, c->stream>>>(c->d_loop, c->d_dout, t_stop, max_steps);
+        dev_plan_kernel<<<1, kPlanWG, 0, c->stream>>>(pa);
+        if (c->cfg.precision == HT_PREC_FP64) {
+            force_kernel<PrecFp64, false, false><<<kGraphForceGrid, kWG, 0, c->stream>>>(d_tab, 1, -1);
+            reduce_kernel<<<kGraphReduceGrid, kWG, 0, c->stream>>>(d_tab, 1, -1);
+            dev_correct_kernel<PrecFp64><<<kLoopCorrGrid, kWG, 0, c->stream>>>(ce, nullptr, 0, -1);
+        } else {
+            force_kernel<PrecMixed, false, false><<<kGraphForceGrid, kWG, 0, c->stream>>>(d_tab, 1, -1);
+            reduce_kernel<<<kGraphReduceGrid, kWG, 0, c->stream>>>(d_tab, 1, -1);
+            dev_correct_kernel<PrecMixed><<<kLoopCorrGrid, kWG, 0, c->stream>>>(ce, nullptr, 0, -1);
+        }
+        HT_HIP(hipGetLastError());
+    }
+    DevLoop L{};
+    DevOut o{};
+    HT_HIP(hipMemcpyAsync(&L, c->d_loop, sizeof L, hipMemcpyDeviceToHost, c->stream));
+    HT_HIP(hipMemcpyAsync(&o, c->d_dout, sizeof o, hipMemcpyDeviceToHost, c->stream));
+    HT_HIP(hipStreamSynchronize(c->stream));
+    *steps = static_cast<int32_t>(L.steps);
+    *particle_steps = L.psteps;
+    if (L.steps > 0) {
+        *t_last = L.t_cur;
+        c->dev_t_next = L.t_cur;
+    }
+    c->last_pairs = L.pairs;
+    c->predicted = false;
+    if (o.below_floor) return fail(HT_ERANGE, "a corrected block step fell below 2^-40");
+    if (L.err) return fail(HT_ERANGE, "a device work plan exceeded the context's capacity");
     return HT_OK;
 }
 

@@ -30,13 +30,13 @@ from . import binding as B
 class Simulation:
     def __init__(self, x, v, m, *, eps2, dt_tree, eta, theta=0.5, n_crit=64, n_leaf=1, precision="mixed",
                  predict_mode="fused", mode="tree", device=0, stream=None, list_headroom=1.5, resident=False,
-                 device_tree=False, tree=None, tree_lock=None):
+                 device_tree=False, tree=None, tree_lock=None, device_loop=False):
         if mode not in ("tree", "direct"):
             raise ValueError(mode)
-        if resident and mode != "tree":
-            raise ValueError("resident integration runs the tree scheme")
-        if device_tree and not resident:
-            raise ValueError("the device tree builder serves the resident integration")
+        if device_tree and not (resident and mode == "tree"):
+            raise ValueError("the device tree builder serves the resident tree integration")
+        if device_loop and not (resident and mode == "tree" and predict_mode == "fused"):
+            raise ValueError("the device loop runs the resident tree integration with fused prediction")
         if not (dt_tree > 0 and math.frexp(dt_tree)[0] == 0.5):
             raise ValueError("dt_tree must be a power of two")
         self.x = np.ascontiguousarray(x, np.float64).reshape(-1, 3).copy()
@@ -69,11 +69,14 @@ class Simulation:
         # (tree, tree_lock: a DeviceTree shared by several simulations and the lock
         # that serialises its use; by default each simulation has its own)
         self.device_tree = bool(device_tree)
+        # device_loop: run() queues the block steps up to each tree time on the
+        # device with no host round trip between them (ht_dev_run)
+        self.device_loop = bool(device_loop)
         self._dtree = tree
         self._own_dtree = tree is None
         self._dtree_lock = tree_lock
         self._perm_pin = None       # pinned landing buffer of a device rebuild's permutation
-        self._perms = []            # permutations not yet applied to the host's m and ids
+        self._perm_pending = None   # composite of the permutations not yet applied to the host's m and ids
         self.n_host_rebuilds = 0    # resident rebuilds that went through the host
         self.n_device_rebuilds = 0
         self._pending_dev = None
@@ -166,10 +169,11 @@ class Simulation:
     def _apply_perms(self):
         """Device rebuilds reorder the particles on the device; the host's masses
         and identities follow here, when they are needed."""
-        for p in self._perms:
+        p = self._perm_pending
+        if p is not None:
             self.m = np.ascontiguousarray(self.m[p])
             self.ids = np.ascontiguousarray(self.ids[p])
-        self._perms = []
+            self._perm_pending = None
 
     def sync_state(self):
         """Resident mode: copy the device state into the host arrays."""
@@ -215,15 +219,18 @@ class Simulation:
         tn, active = self._pending_dev
         self._pending_dev = None
         t_start = time.perf_counter()
-        self.ctx.dev_step(self.eta, self.dt_tree)
+        if self.mode == "tree":
+            self.ctx.dev_step(self.eta, self.dt_tree)
+        else:
+            self.ctx.dev_step_direct(self.eta, self.dt_tree)
         pairs, _ = self.ctx.last_stats()
         self.n_interactions += pairs
         self.timers["force"] += time.perf_counter() - t_start
         self.t = tn
         self.n_block_steps += 1
         self.n_particle_steps += active.size
-        if math.fmod(tn, self.dt_tree) == 0.0:
-            self.rebuild_resident()
+        if math.fmod(tn, self.dt_tree) == 0.0 and self.mode == "tree":
+            self.rebuild_resident()   # the direct scheme's state needs nothing at tree times
         return tn, active
 
     def rebuild_resident(self):
@@ -251,7 +258,8 @@ class Simulation:
                     raise
                 return False
             M, G, E, _ = self._dtree.sizes()
-        self._perms.append(perm.copy())
+        # one pending composite, so a long run between syncs holds one array
+        self._perm_pending = perm.copy() if self._perm_pending is None else self._perm_pending[perm]
         self.tree = types.SimpleNamespace(n_node=M, n_group=G, n_entries=E)
         self.t_tree = self.t
         self.n_device_rebuilds += 1
@@ -273,11 +281,33 @@ class Simulation:
         return tn, active
 
     def run(self, t_end, on_step=None):
+        if self.device_loop and on_step is None:
+            return self._run_device_loop(t_end)
         while self.next_time() <= t_end:
             tn, act = self.step()
             if on_step is not None:
                 on_step(self, tn, act)
         return self
+
+    def _run_device_loop(self, t_end, chunk=512):
+        """Block steps up to t_end, each tree interval queued on the device in
+        chunks of up to `chunk` steps; the host only rebuilds at tree times."""
+        while True:
+            t_tree_next = (math.floor(self.t / self.dt_tree) + 1.0) * self.dt_tree
+            t_stop = min(t_end, t_tree_next)
+            t_start = time.perf_counter()
+            k, t_last, psteps = self.ctx.dev_run(self.eta, self.dt_tree, t_stop, chunk)
+            self._pending_dev = None
+            pairs, _ = self.ctx.last_stats()
+            self.n_interactions += pairs
+            self.timers["force"] += time.perf_counter() - t_start
+            if k == 0:
+                return self       # the next block time lies beyond t_end
+            self.t = t_last
+            self.n_block_steps += k
+            self.n_particle_steps += psteps
+            if t_last == t_tree_next:
+                self.rebuild_resident()
 
     # ------------------------------------------------------------------ diagnostics
     def energy(self):

@@ -8,8 +8,8 @@ tree interval 1/64) at a size and span that run in minutes on one GPU.
     python -m paper_1602_02832_amd.energy_study [--n 16384] [--t-end 1.0] [--out file.json]
         [--resident] [--direct-t-end T]
 
---resident runs the tree integrations resident on the device, tree times
-rebuilt there too (the direct scheme always runs host-driven).
+--resident runs the integrations resident on the device (scheduler, force and
+corrector there; tree times rebuilt there too).
 
 Prints one JSON object: per run the relative energy error |E(t) - E(0)| / |E(0)|
 at every multiple of 1/8 (all particles synchronised there), block steps,
@@ -30,9 +30,9 @@ from . import workloads as W
 
 
 def run(x, v, m, *, mode, theta, eps, eta, dt_tree, n_crit, t_end, precision, every=0.125, resident=False):
-    res = resident and mode == "tree"
+    res = bool(resident)
     sim = driver.Simulation(x, v, m, eps2=eps * eps, dt_tree=dt_tree, eta=eta, theta=theta, n_crit=n_crit,
-                            precision=precision, mode=mode, resident=res, device_tree=res)
+                            precision=precision, mode=mode, resident=res, device_tree=res and mode == "tree")
     e0 = sim.energy()
     errs = []
     wall = time.perf_counter()
@@ -61,7 +61,7 @@ def main():
     ap.add_argument("--thetas", default="0.3,0.5,0.75")
     ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--out", default="")
-    ap.add_argument("--resident", action="store_true", help="tree runs resident on the device")
+    ap.add_argument("--resident", action="store_true", help="runs resident on the device")
     ap.add_argument("--direct-t-end", type=float, default=0.0, help="end of the direct run (default: --t-end)")
     args = ap.parse_args()
     if not (args.t_end > 0 and math.isfinite(args.t_end)):
@@ -72,7 +72,8 @@ def main():
     for th in (float(t) for t in args.thetas.split(",") if t):
         runs.append(run(x, v, m, mode="tree", theta=th, t_end=args.t_end, resident=args.resident, **common))
     if not args.no_direct:
-        runs.append(run(x, v, m, mode="direct", theta=0.0, t_end=args.direct_t_end or args.t_end, **common))
+        runs.append(run(x, v, m, mode="direct", theta=0.0, t_end=args.direct_t_end or args.t_end,
+                        resident=args.resident, **common))
     res = dict(n=args.n, seed=args.seed, t_end=args.t_end, eps=1.0 / args.n, eta=0.01, dt_tree=1.0 / 64,
                n_crit=args.n_crit, precision=args.precision, runs=runs)
     text = json.dumps(res)

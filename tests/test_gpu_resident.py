@@ -132,3 +132,47 @@ def test_device_rebuild_falls_back_when_the_tree_outgrows_the_context():
         assert np.array_equal(getattr(sims[0], f), getattr(dev, f)), f
     for s in sims:
         s.close()
+
+
+def test_resident_direct_equals_host_driven_direct():
+    """The direct Hermite scheme resident on the device (ht_dev_step_direct)
+    gives the bits of the host-driven direct run."""
+    c = W.config("plummer2k")
+    say(f"resident vs host-driven direct scheme to t={c.t_end}")
+    x, v, m = W.make_initial_conditions(c)
+    sims = [driver.Simulation(x, v, m, eps2=c.eps2, dt_tree=c.dt_tree, eta=c.eta, theta=c.theta, n_crit=c.n_crit,
+                              precision="mixed", mode="direct", resident=r) for r in (False, True)]
+    for s in sims:
+        s.run(c.t_end)
+        s.sync_state()
+    assert sims[0].n_block_steps == sims[1].n_block_steps and sims[0].t == sims[1].t == c.t_end
+    assert np.array_equal(sims[0].ids, sims[1].ids)
+    for f in FIELDS:
+        assert np.array_equal(getattr(sims[0], f), getattr(sims[1], f)), f
+    for s in sims:
+        s.close()
+
+
+@pytest.mark.parametrize("name,t_end", [("plummer2k", None), ("plummer16k", 4.0 / 256)])
+def test_device_loop_equals_step_by_step(name, t_end):
+    """Block steps queued on the device (ht_dev_run: device scheduler, device
+    work planner, force, corrector, no host round trip until each tree time)
+    give the bits of the step-by-step resident run, through the rebuilds."""
+    c = W.config(name)
+    t_end = c.t_end if t_end is None else t_end
+    say(f"device loop vs step by step: {name} to t={t_end}")
+    x, v, m = W.make_initial_conditions(c)
+    sims = [driver.Simulation(x, v, m, eps2=c.eps2, dt_tree=c.dt_tree, eta=c.eta, theta=c.theta, n_crit=c.n_crit,
+                              precision="mixed", resident=True, device_tree=True, device_loop=d)
+            for d in (False, True)]
+    for s in sims:
+        s.run(t_end)
+        s.sync_state()
+    assert sims[0].n_block_steps == sims[1].n_block_steps and sims[0].t == sims[1].t
+    assert sims[0].n_particle_steps == sims[1].n_particle_steps
+    assert sims[0].n_interactions == sims[1].n_interactions
+    assert np.array_equal(sims[0].ids, sims[1].ids)
+    for f in FIELDS:
+        assert np.array_equal(getattr(sims[0], f), getattr(sims[1], f)), f
+    for s in sims:
+        s.close()
