@@ -891,6 +891,9 @@ struct DevLoop {
     int32_t stop_after;  // the step in progress is at the stop time
     int32_t err;         // the device plan did not fit the context
     int32_t pad;
+    // the call's parameters, so that the captured launches never change
+    double t_stop, eta, dt_tree;
+    int64_t max_steps;
 };
 
 struct CorrEntry {
@@ -900,6 +903,12 @@ struct CorrEntry {
     int64_t n_active, first_row;
     double t1, eta, dt_tree;
     const DevLoop* loop;   // device loop: count and block time read from it; else nullptr
+    // device loop: the split partials are summed here (in split order, as
+    // reduce_kernel does) instead of in a launch of their own.  qmap[q] is the
+    // split tile of active position q, or -1 when the force wrote q directly.
+    const int32_t* qmap;
+    const RTile* rtiles;
+    const double* partial;
 };
 
 template <class P>
@@ -928,6 +937,24 @@ __global__ __launch_bounds__(kWG) void dev_correct_kernel(CorrEntry e0, const Co
         const double h2 = 0.5 * D, h3 = D / 3.0;
         const double D2 = D * D, D3 = D2 * D, D4 = D2 * D2, D5 = D4 * D;
         double s2[3], s3[3], s2n[3], a1[3], j1[3];
+        double fp = s.fpot[q];
+        const int32_t rq = e.qmap ? e.qmap[q] : -1;
+        if (rq >= 0) {   // the split partials of q, summed in split order
+            const RTile rt = e.rtiles[rq];
+            const int64_t slot = q - rt.act_begin;
+            double A[kOut];
+            const double* p0 = e.partial + (rt.pbase + slot) * kOut;
+            for (int u = 0; u < kOut; ++u) A[u] = p0[u];
+            for (int b = 1; b < rt.nsplit; ++b) {
+                const double* pb = e.partial + (rt.pbase + static_cast<int64_t>(b) * rt.n_i + slot) * kOut;
+                for (int u = 0; u < kOut; ++u) A[u] += pb[u];
+            }
+            for (int d = 0; d < 3; ++d) {
+                s.acc[3 * q + d] = A[d];
+                s.jerk[3 * q + d] = A[3 + d];
+            }
+            fp = A[6];
+        }
         for (int d = 0; d < 3; ++d) {
             const int64_t k = 3 * static_cast<int64_t>(i) + d;
             a1[d] = s.acc[3 * q + d];
@@ -946,14 +973,15 @@ __global__ __launch_bounds__(kWG) void dev_correct_kernel(CorrEntry e0, const Co
         const double na = dev_len3(a1[0], a1[1], a1[2]), nj = dev_len3(j1[0], j1[1], j1[2]);
         const double n2 = dev_len3(s2n[0], s2n[1], s2n[2]), n3 = dev_len3(s3[0], s3[1], s3[2]);
         const double den = nj * n3 + n2 * n2;
-        const double raw = den > 0.0 ? sqrt(e.eta * (na * n2 + nj * nj) / den) : e.dt_tree;
-        double cap = e.dt_tree < raw ? e.dt_tree : raw;   // std::min(raw, dt_tree), then with 2 dt_old
+        const double eta = e.loop ? e.loop->eta : e.eta, dt_tree = e.loop ? e.loop->dt_tree : e.dt_tree;
+        const double raw = den > 0.0 ? sqrt(eta * (na * n2 + nj * nj) / den) : dt_tree;
+        double cap = dt_tree < raw ? dt_tree : raw;   // std::min(raw, dt_tree), then with 2 dt_old
         cap = 2.0 * s.dt[i] < cap ? 2.0 * s.dt[i] : cap;
         const double h = dev_quantise(cap, t1);
         if (h == 0.0) e.out->below_floor = 1;
         s.t0[i] = t1;
         s.dt[i] = h;
-        s.pot[i] = s.fpot[q];
+        s.pot[i] = fp;
         const int64_t k = 3 * static_cast<int64_t>(i);
         store_rec<P>(rec, i, t1, s.m[i], s.x + k, s.v + k, s.a + k, s.j + k);
     }
@@ -961,14 +989,16 @@ __global__ __launch_bounds__(kWG) void dev_correct_kernel(CorrEntry e0, const Co
 
 // ------------------------------------------------------------------------------------------------
 // Device loop (ht_dev_run): block steps queued back to back with no host
-// round trip.  Per step: the three scheduler passes, loop_gate_kernel,
-// dev_plan_kernel, the force and reduce kernels (fixed grids, counts read from
-// the plan) and the corrector (count and block time read from the loop).
+// round trip.  Per step: the three scheduler passes, dev_plan_kernel (which
+// first takes the step or stops the loop), the force kernel (fixed grid, counts
+// read from the plan) and the corrector (count and block time read from the
+// loop; it also sums the split partials, so the step needs no reduce launch).
 
-// After the scheduler: take the step if its block time is at most the stop
-// time, else stop the loop (and every later kernel with it).
-__global__ void loop_gate_kernel(DevLoop* L, const DevOut* o, double t_stop, int64_t max_steps) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Take the step if its block time is at most the stop time, else stop the
+// loop (and every later kernel with it).
+__device__ inline void loop_gate(DevLoop* L, const DevOut* o) {
+    const double t_stop = L->t_stop;
+    const int64_t max_steps = L->max_steps;
     if (L->halt) {
         L->n_corr = 0;
         return;
@@ -987,6 +1017,19 @@ __global__ void loop_gate_kernel(DevLoop* L, const DevOut* o, double t_stop, int
     if (t == t_stop) L->stop_after = 1;
 }
 
+// Start of a device-loop call: its parameters, counts cleared.
+__global__ void loop_init_kernel(DevLoop* L, DevOut* o, double t_stop, int64_t max_steps, double eta,
+                                 double dt_tree) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    DevLoop z{};
+    z.t_stop = t_stop;
+    z.max_steps = max_steps;
+    z.eta = eta;
+    z.dt_tree = dt_tree;
+    *L = z;
+    *o = DevOut{};
+}
+
 // One tile of the device plan.
 struct DTile {
     int64_t jb, je;
@@ -995,14 +1038,27 @@ struct DTile {
     double cost;
 };
 
+// The group of every particle, from the group offsets (after each change of the lists).
+__global__ __launch_bounds__(kWG) void group_of_kernel(int64_t n, const int64_t* __restrict__ gfirst, int32_t n_groups,
+                                                       int32_t* __restrict__ pgroup) {
+    const int64_t i = blockIdx.x * int64_t(kWG) + threadIdx.x;
+    if (i >= n) return;
+    int lo = 0, hi = n_groups;   // gfirst[lo] <= i < gfirst[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (gfirst[mid] <= i) lo = mid; else hi = mid;
+    }
+    pgroup[i] = lo;
+}
+
 struct PlanArgs {
     DevLoop* loop;
+    const DevOut* dout;        // the scheduler's results (block time, count)
     const int32_t* active;     // this step's active particles, ascending (the scheduler's list)
-    const int64_t* gfirst;     // [n_groups + 1] first particle of each group, then N
-    const int64_t* loff;       // [n_groups + 1] list offsets
-    int32_t n_groups;
-    int32_t pad;
+    const int32_t* pgroup;     // [N] group of every particle
+    const int64_t* loff;       // [groups + 1] list offsets
     int32_t* gk;               // scratch: group of each active particle
+    int32_t* qmap;             // out: split tile of each active position or -1 (may alias gk)
     int32_t* qk;               // scratch: first active position of each active group, then n_active
     int32_t* qg;               // scratch: group of each active group
     DTile* tiles;              // scratch
@@ -1050,8 +1106,9 @@ __global__ __launch_bounds__(kPlanWG) void dev_plan_kernel(PlanArgs A) {
     __shared__ int8_t s_ft[260];   // the tile table, indexed per thread
     const int t = threadIdx.x;
     if (t < 257) s_ft[t] = A.first_tile[t];
-    __syncthreads();
     DevLoop* L = A.loop;
+    if (t == 0) loop_gate(L, A.dout);   // take this step or stop the loop
+    __syncthreads();
     if (L->halt) {
         if (t == 0) {
             A.tab->n_items = 0;
@@ -1061,15 +1118,7 @@ __global__ __launch_bounds__(kPlanWG) void dev_plan_kernel(PlanArgs A) {
     }
     const int64_t n = L->n_corr;
     // 1. the group of every active particle
-    for (int64_t k = t; k < n; k += kPlanWG) {
-        const int64_t id = A.active[k];
-        int lo = 0, hi = A.n_groups;   // gfirst[lo] <= id < gfirst[hi]
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (A.gfirst[mid] <= id) lo = mid; else hi = mid;
-        }
-        A.gk[k] = lo;
-    }
+    for (int64_t k = t; k < n; k += kPlanWG) A.gk[k] = A.pgroup[A.active[k]];
     __syncthreads();
     // 2. active groups: first active position and group, in order
     int64_t nq = 0;
@@ -1198,7 +1247,9 @@ __global__ __launch_bounds__(kPlanWG) void dev_plan_kernel(PlanArgs A) {
             const int16_t ni = static_cast<int16_t>(T.ni), tl = static_cast<int16_t>(T.tl);
             if (ns == 1) {
                 A.items[io + ei] = Item{T.jb, T.je, -1, T.tb, ni, tl};
+                for (int32_t u = 0; u < T.ni; ++u) A.qmap[T.tb + u] = -1;
             } else {
+                for (int32_t u = 0; u < T.ni; ++u) A.qmap[T.tb + u] = static_cast<int32_t>(ro + er);
                 const int64_t pb = po + ep;
                 int64_t s = 0;
                 for (int64_t b = T.jb; b < T.je; b += per, ++s)
@@ -1399,8 +1450,11 @@ struct ht_ctx {
     DevOut* d_dout = nullptr;
     int64_t* d_gfirst = nullptr;
     int64_t* d_loff = nullptr;
-    int32_t *d_gk = nullptr, *d_qk = nullptr, *d_qg = nullptr;
+    int32_t *d_gk = nullptr, *d_qk = nullptr, *d_qg = nullptr, *d_pgroup = nullptr;
     DTile* d_tiles = nullptr;
+    hipGraph_t loop_graph = nullptr;      // kLoopGraphSteps device-loop steps, captured once
+    hipGraphExec_t loop_exec = nullptr;
+    double loop_tuning[2] = {-1.0, -1.0}; // the tuning the graph's planner launches carry
     DevOut* h_dout = nullptr;
     int32_t* h_active = nullptr;
     double dev_t_next = 0.0;
@@ -1958,6 +2012,8 @@ int ht_destroy(ht_ctx* c) {
         if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
         if (c->hdr_free[k]) (void)hipEventDestroy(c->hdr_free[k]);
     }
+    if (c->loop_exec) (void)hipGraphExecDestroy(c->loop_exec);
+    if (c->loop_graph) (void)hipGraphDestroy(c->loop_graph);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->h_hdr) (void)hipHostFree(c->h_hdr);
     if (c->ds_mem) (void)hipFree(c->ds_mem);
@@ -2154,7 +2210,7 @@ SchedEntry sched_entry_of(const ht_ctx* c, int32_t first_block) {
 // The corrector's table entry of a context's last active set, rows from first_row.
 CorrEntry corr_entry_of(const ht_ctx* c, int64_t first_row, double eta, double dt_tree) {
     return CorrEntry{c->ds, c->ws + c->L.off_rec, c->h_dout, c->dev_n_active, first_row, c->dev_t_next, eta, dt_tree,
-                     nullptr};
+                     nullptr, nullptr, nullptr, nullptr};
 }
 
 int launch_correct(int precision, hipStream_t stream, const CorrEntry& e0, const CorrEntry* tab, int n_tab,
@@ -2292,6 +2348,8 @@ int upload_group_offsets(ht_ctx* c) {
     const size_t b = (static_cast<size_t>(c->n_groups) + 1) * 8;
     HT_HIP(hipMemcpyAsync(c->d_gfirst, c->group_first.data(), b, hipMemcpyHostToDevice, c->stream));
     HT_HIP(hipMemcpyAsync(c->d_loff, c->list_off.data(), b, hipMemcpyHostToDevice, c->stream));
+    group_of_kernel<<<(c->n + kWG - 1) / kWG, kWG, 0, c->stream>>>(c->n, c->d_gfirst, c->n_groups, c->d_pgroup);
+    HT_HIP(hipGetLastError());
     HT_HIP(hipStreamSynchronize(c->stream));   // pageable sources
     return HT_OK;
 }
@@ -2314,6 +2372,7 @@ int ht_state_enable(ht_ctx* c) {
     const size_t g1 = static_cast<size_t>(c->cfg.group_max) + 1;
     const size_t oloop = take(sizeof(DevLoop)), odout = take(sizeof(DevOut)), ogf = take(g1 * 8), olo = take(g1 * 8);
     const size_t ogk = take(n * 4), oqk = take((n + 1) * 4), oqg = take(n * 4), otl = take(n * sizeof(DTile));
+    const size_t opg = take(n * 4);
     if (hipMalloc(&c->ds_mem, o) != hipSuccess) {
         c->ds_mem = nullptr;
         return fail(HT_ENOMEM, "hipMalloc of %zu bytes for the device state failed", o);
@@ -2334,6 +2393,7 @@ int ht_state_enable(ht_ctx* c) {
     c->d_qk = reinterpret_cast<int32_t*>(b + oqk);
     c->d_qg = reinterpret_cast<int32_t*>(b + oqg);
     c->d_tiles = reinterpret_cast<DTile*>(b + otl);
+    c->d_pgroup = reinterpret_cast<int32_t*>(b + opg);
     if (c->have_lists) {   // lists set before the state: their offsets for the device planner
         int rc = upload_group_offsets(c);
         if (rc) return rc;
@@ -2442,6 +2502,8 @@ int ht_state_rebuild(ht_ctx* c, htd_tree* t, int32_t n_leaf, int32_t n_crit, dou
     HT_HIP(hipMemcpyAsync(c->list_off.data(), w.list_off, (G + 1) * 8, hipMemcpyDeviceToHost, c->stream));
     HT_HIP(hipMemcpyAsync(c->d_gfirst, w.group_first, (G + 1) * 8, hipMemcpyDeviceToDevice, c->stream));
     HT_HIP(hipMemcpyAsync(c->d_loff, w.list_off, (G + 1) * 8, hipMemcpyDeviceToDevice, c->stream));
+    group_of_kernel<<<grid, kWG, 0, c->stream>>>(n, c->d_gfirst, static_cast<int32_t>(G), c->d_pgroup);
+    HT_HIP(hipGetLastError());
     if (perm) HT_HIP(hipMemcpyAsync(perm, w.perm, n1, hipMemcpyDeviceToHost, c->stream));
     HT_HIP(hipStreamSynchronize(c->stream));
     c->n_nodes = static_cast<int32_t>(M);
@@ -2505,37 +2567,39 @@ int ht_dev_step(ht_ctx* c, double eta, double dt_tree) { return dev_step(c, eta,
 
 int ht_dev_step_direct(ht_ctx* c, double eta, double dt_tree) { return dev_step(c, eta, dt_tree, true); }
 
-constexpr int kLoopCorrGrid = 1024;   // fixed corrector grid of the device loop (grid-stride)
+constexpr int kLoopGraphSteps = 32;  // device-loop steps per captured graph
+constexpr int kLoopForceGrid = 1024;  // fixed force grid of the device loop (4 work-groups per CU, grid-stride)
+constexpr int kLoopCorrGrid = 256;    // fixed corrector grid of the device loop (grid-stride)
 
-int ht_dev_run(ht_ctx* c, double eta, double dt_tree, double t_stop, int32_t max_steps, int32_t* steps,
-               double* t_last, int64_t* particle_steps) {
-    if (!c || !steps || !t_last || !particle_steps) return fail(HT_EINVAL, "NULL argument");
-    if (!c->ds_mem) return fail(HT_ESTATE, "device state not enabled");
-    if (!c->have_lists) return fail(HT_ESTATE, "interaction lists not set");
-    if (c->cfg.predict_mode != HT_PREDICT_FUSED) return fail(HT_EINVAL, "the device loop needs fused prediction");
-    if (c->gather_cost != std::floor(c->gather_cost))
-        return fail(HT_EINVAL, "the device loop plans with a whole-number gather cost (ht_set_tuning)");
-    if (!(eta > 0.0) || !(dt_tree > 0.0) || !std::isfinite(t_stop)) return fail(HT_EINVAL, "bad eta, dt_tree or t_stop");
-    if (max_steps < 1) return fail(HT_EINVAL, "max_steps < 1");
-    *steps = 0;
-    *t_last = c->dev_t_next;
-    *particle_steps = 0;
-    c->dev_n_active = -1;
-    HT_HIP(hipMemsetAsync(c->d_loop, 0, sizeof(DevLoop), c->stream));
-    HT_HIP(hipMemsetAsync(c->d_dout, 0, sizeof(DevOut), c->stream));
+namespace {
+// Capture kLoopGraphSteps device-loop steps into one graph.  Every launch
+// argument is fixed for the context's life (the call's parameters sit in the
+// loop state in device memory), except the work-plan tuning, on whose change
+// the graph is captured again.
+int build_loop_graph(ht_ctx* c) {
+    if (c->loop_exec) {
+        (void)hipGraphExecDestroy(c->loop_exec);
+        c->loop_exec = nullptr;
+    }
+    if (c->loop_graph) {
+        (void)hipGraphDestroy(c->loop_graph);
+        c->loop_graph = nullptr;
+    }
+    if (!c->cap_stream) HT_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     SchedEntry se = sched_entry_of(c, 0);
     se.out = c->d_dout;
     se.active_host = nullptr;
     se.halt = &c->d_loop->halt;
-    CorrEntry ce = corr_entry_of(c, 0, eta, dt_tree);
+    CorrEntry ce = corr_entry_of(c, 0, 1.0, 1.0);   // eta and dt_tree come from the loop state
     ce.out = c->d_dout;
     ce.loop = c->d_loop;
     PlanArgs pa{};
     pa.loop = c->d_loop;
+    pa.dout = c->d_dout;
+    pa.qmap = c->d_gk;
     pa.active = c->ds.active;
-    pa.gfirst = c->d_gfirst;
+    pa.pgroup = c->d_pgroup;
     pa.loff = c->d_loff;
-    pa.n_groups = c->n_groups;
     pa.gk = c->d_gk;
     pa.qk = c->d_qk;
     pa.qg = c->d_qg;
@@ -2555,25 +2619,64 @@ int ht_dev_run(ht_ctx* c, double eta, double dt_tree, double t_stop, int32_t max
     pa.d.jerk = c->ds.jerk;
     pa.d.pot = c->ds.fpot;
     std::memcpy(pa.first_tile, c->first_tile, sizeof(pa.first_tile));
+    ce.qmap = pa.qmap;
+    ce.rtiles = pa.rtiles;
+    ce.partial = pa.d.partial;
     const Entry* d_tab = pa.tab;
-    c->slots_all_free();
-    for (int32_t k = 0; k < max_steps; ++k) {
-        sched_min_kernel<<<se.nb, kWG, 0, c->stream>>>(se, nullptr, 0);
-        sched_count_kernel<<<se.nb, kWG, 0, c->stream>>>(se, nullptr, 0);
-        sched_write_kernel<<<se.nb, kWG, 0, c->stream>>>(se, nullptr, 0);
-        loop_gate_kernel<<<1, 64, 0, c->stream>>>(c->d_loop, c->d_dout, t_stop, max_steps);
-        dev_plan_kernel<<<1, kPlanWG, 0, c->stream>>>(pa);
+    hipStream_t s = c->cap_stream;
+    HT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < kLoopGraphSteps; ++k) {
+        sched_min_kernel<<<se.nb, kWG, 0, s>>>(se, nullptr, 0);
+        sched_count_kernel<<<se.nb, kWG, 0, s>>>(se, nullptr, 0);
+        sched_write_kernel<<<se.nb, kWG, 0, s>>>(se, nullptr, 0);
+        dev_plan_kernel<<<1, kPlanWG, 0, s>>>(pa);   // takes the step (or stops the loop) and plans it
         if (c->cfg.precision == HT_PREC_FP64) {
-            force_kernel<PrecFp64, false, false><<<kGraphForceGrid, kWG, 0, c->stream>>>(d_tab, 1, -1);
-            reduce_kernel<<<kGraphReduceGrid, kWG, 0, c->stream>>>(d_tab, 1, -1);
-            dev_correct_kernel<PrecFp64><<<kLoopCorrGrid, kWG, 0, c->stream>>>(ce, nullptr, 0, -1);
+            force_kernel<PrecFp64, false, false><<<kLoopForceGrid, kWG, 0, s>>>(d_tab, 1, -1);
+            dev_correct_kernel<PrecFp64><<<kLoopCorrGrid, kWG, 0, s>>>(ce, nullptr, 0, -1);   // sums the splits too
         } else {
-            force_kernel<PrecMixed, false, false><<<kGraphForceGrid, kWG, 0, c->stream>>>(d_tab, 1, -1);
-            reduce_kernel<<<kGraphReduceGrid, kWG, 0, c->stream>>>(d_tab, 1, -1);
-            dev_correct_kernel<PrecMixed><<<kLoopCorrGrid, kWG, 0, c->stream>>>(ce, nullptr, 0, -1);
+            force_kernel<PrecMixed, false, false><<<kLoopForceGrid, kWG, 0, s>>>(d_tab, 1, -1);
+            dev_correct_kernel<PrecMixed><<<kLoopCorrGrid, kWG, 0, s>>>(ce, nullptr, 0, -1);
         }
-        HT_HIP(hipGetLastError());
     }
+    const hipError_t launch = hipGetLastError();
+    hipGraph_t g = nullptr;
+    const hipError_t end = hipStreamEndCapture(s, &g);
+    if (launch != hipSuccess || end != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(HT_EHIP, "capturing the device-loop graph failed: %s",
+                    hipGetErrorString(launch != hipSuccess ? launch : end));
+    }
+    c->loop_graph = g;
+    HT_HIP(hipGraphInstantiate(&c->loop_exec, g, nullptr, nullptr, 0));
+    c->loop_tuning[0] = c->gather_cost;
+    c->loop_tuning[1] = c->target_items;
+    return HT_OK;
+}
+}  // namespace
+
+
+int ht_dev_run(ht_ctx* c, double eta, double dt_tree, double t_stop, int32_t max_steps, int32_t* steps,
+               double* t_last, int64_t* particle_steps) {
+    if (!c || !steps || !t_last || !particle_steps) return fail(HT_EINVAL, "NULL argument");
+    if (!c->ds_mem) return fail(HT_ESTATE, "device state not enabled");
+    if (!c->have_lists) return fail(HT_ESTATE, "interaction lists not set");
+    if (c->cfg.predict_mode != HT_PREDICT_FUSED) return fail(HT_EINVAL, "the device loop needs fused prediction");
+    if (c->gather_cost != std::floor(c->gather_cost))
+        return fail(HT_EINVAL, "the device loop plans with a whole-number gather cost (ht_set_tuning)");
+    if (!(eta > 0.0) || !(dt_tree > 0.0) || !std::isfinite(t_stop)) return fail(HT_EINVAL, "bad eta, dt_tree or t_stop");
+    if (max_steps < 1) return fail(HT_EINVAL, "max_steps < 1");
+    *steps = 0;
+    *t_last = c->dev_t_next;
+    *particle_steps = 0;
+    c->dev_n_active = -1;
+    if (!c->loop_exec || c->loop_tuning[0] != c->gather_cost || c->loop_tuning[1] != c->target_items) {
+        int rc = build_loop_graph(c);
+        if (rc) return rc;
+    }
+    c->slots_all_free();
+    loop_init_kernel<<<1, 64, 0, c->stream>>>(c->d_loop, c->d_dout, t_stop, max_steps, eta, dt_tree);
+    HT_HIP(hipGetLastError());
+    for (int32_t k = 0; k < max_steps; k += kLoopGraphSteps) HT_HIP(hipGraphLaunch(c->loop_exec, c->stream));
     DevLoop L{};
     DevOut o{};
     HT_HIP(hipMemcpyAsync(&L, c->d_loop, sizeof L, hipMemcpyDeviceToHost, c->stream));

@@ -289,9 +289,10 @@ class Simulation:
                 on_step(self, tn, act)
         return self
 
-    def _run_device_loop(self, t_end, chunk=512):
-        """Block steps up to t_end, each tree interval queued on the device in
-        chunks of up to `chunk` steps; the host only rebuilds at tree times."""
+    def _run_device_loop(self, t_end, chunk=32):
+        """Block steps up to t_end, queued on the device `chunk` at a time (one
+        captured graph each; steps queued past the stop do nothing but still
+        cost their launches); the host only rebuilds at tree times."""
         while True:
             t_tree_next = (math.floor(self.t / self.dt_tree) + 1.0) * self.dt_tree
             t_stop = min(t_end, t_tree_next)
