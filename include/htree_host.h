@@ -10,7 +10,11 @@
  * by current index.  Cells split while they hold more than n_leaf particles
  * (down to level 21).  Nodes are the cells with at least two particles, in
  * pre-order; node k is combined index N + k and carries total mass and the
- * mass-weighted mean of position, velocity, acceleration and jerk.  Groups
+ * mass-weighted mean of position, velocity, acceleration and jerk, summed
+ * bottom-up: a cell's sums (m, m x, m v, m a, m jerk) start from zero and
+ * add, for a split cell, its children's sums in key order, otherwise its
+ * particles' rounded products in ascending order (no fused multiply-add);
+ * the means are these sums divided by the mass sum.  Groups
  * are the first cells on every root-to-leaf path with at most n_crit
  * particles (or that cannot split).  A group's list holds, in pre-order, the
  * nodes that pass the opening test  side^2 < theta^2 d^2  (d = distance from

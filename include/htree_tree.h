@@ -14,8 +14,9 @@
  *     (key, current index);
  *   - cells split while they hold more than n_leaf particles (down to level
  *     21); nodes are the cells with at least two particles, in pre-order, and
- *     carry total mass and mass-weighted means of x, v, a, jerk (sums in
- *     particle order, each product rounded before it is added);
+ *     carry total mass and mass-weighted means of x, v, a, jerk, summed
+ *     bottom-up (a split cell adds its children's sums in key order, a leaf
+ *     its particles' rounded products in ascending order);
  *   - groups are the first cells on each root-to-leaf path with at most
  *     n_crit particles (or that cannot split);
  *   - a group's list holds, in pre-order, the nodes with side^2 < theta^2 d^2

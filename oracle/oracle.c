@@ -204,28 +204,43 @@ static int64_t orc_build_cell(orc_tree *t, int level, int64_t b, int64_t e)
 
 /* Node moments (Section 2, step 1: tree nodes are pseudo-particles with       */
 /* position, velocity, acceleration and its derivative).  READING: monopole  */
-/* at the centre of mass; M = sum of m in ascending particle order; X = (sum  */
-/* of m*x)/M and the same for v, a and jerk, all at the tree time.            */
-static void orc_node_moments(orc_tree *t, int64_t nd)
+/* at the centre of mass, accumulated bottom-up as tree codes do.  A cell's  */
+/* sums S = (sum m, sum m*x, sum m*v, sum m*a, sum m*jerk) start from zero;   */
+/* a split cell adds its children's S in key order, an unsplit cell adds its */
+/* particles' rounded products m_k*x_k in ascending order.  A node's mass is */
+/* its sum of m, and X = (sum of m*x)/M, likewise for v, a and jerk, all at  */
+/* the tree time.  One pass from the root visits every cell once.            */
+static void orc_cell_sums(orc_tree *t, int64_t id, double s[13])
 {
-    const orc_cell *c = &t->cell[t->node_cell[nd]];
-    double M = 0.0, sx[3] = {0, 0, 0}, sv[3] = {0, 0, 0}, sa[3] = {0, 0, 0}, sj[3] = {0, 0, 0};
-    for (int64_t k = c->begin; k < c->end; k++) {
-        double mk = t->m[k];
-        M = M + mk;
-        for (int d = 0; d < 3; d++) {
-            sx[d] = sx[d] + mk * t->x[3 * k + d];
-            sv[d] = sv[d] + mk * t->v[3 * k + d];
-            sa[d] = sa[d] + mk * t->a[3 * k + d];
-            sj[d] = sj[d] + mk * t->j[3 * k + d];
+    const orc_cell *c = &t->cell[id];
+    for (int q = 0; q < 13; q++) s[q] = 0.0;
+    if (c->split) {
+        for (int64_t ch = c->first_child; ch >= 0; ch = t->cell[ch].next_sibling) {
+            double sc[13];
+            orc_cell_sums(t, ch, sc);
+            for (int q = 0; q < 13; q++) s[q] = s[q] + sc[q];
+        }
+    } else {
+        for (int64_t k = c->begin; k < c->end; k++) {
+            double mk = t->m[k];
+            s[0] = s[0] + mk;
+            for (int d = 0; d < 3; d++) {
+                s[1 + d] = s[1 + d] + mk * t->x[3 * k + d];
+                s[4 + d] = s[4 + d] + mk * t->v[3 * k + d];
+                s[7 + d] = s[7 + d] + mk * t->a[3 * k + d];
+                s[10 + d] = s[10 + d] + mk * t->j[3 * k + d];
+            }
         }
     }
-    t->nm[nd] = M;
-    for (int d = 0; d < 3; d++) {
-        t->nx[3 * nd + d] = sx[d] / M;
-        t->nv[3 * nd + d] = sv[d] / M;
-        t->na[3 * nd + d] = sa[d] / M;
-        t->nj[3 * nd + d] = sj[d] / M;
+    if (c->node >= 0) {
+        int64_t nd = c->node;
+        t->nm[nd] = s[0];
+        for (int d = 0; d < 3; d++) {
+            t->nx[3 * nd + d] = s[1 + d] / s[0];
+            t->nv[3 * nd + d] = s[4 + d] / s[0];
+            t->na[3 * nd + d] = s[7 + d] / s[0];
+            t->nj[3 * nd + d] = s[10 + d] / s[0];
+        }
     }
 }
 
@@ -360,8 +375,10 @@ orc_tree *orc_tree_build(int64_t n, const double *x, const double *v, const doub
     t->nv = (double *)malloc(nn * 3 * sizeof(double));
     t->na = (double *)malloc(nn * 3 * sizeof(double));
     t->nj = (double *)malloc(nn * 3 * sizeof(double));
-#pragma omp parallel for schedule(dynamic, 64)
-    for (int64_t nd = 0; nd < t->n_node; nd++) orc_node_moments(t, nd);
+    {
+        double s_root[13];
+        orc_cell_sums(t, 0, s_root);
+    }
     /* groups */
     int64_t ng = 0;
     orc_find_groups(t, 0, &ng);

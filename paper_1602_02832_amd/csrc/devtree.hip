@@ -14,9 +14,9 @@
 //      particle k are those of levels L_k ... E_k, and pre-order is the order
 //      of (first particle, level).  Per-particle counts and three prefix sums
 //      give every cell, node and group its pre-order number directly.
-//   3. node moments: one thread per small node, one work-group per large node
-//      (the sums stay sequential in particle order; the work-group stages the
-//      products in LDS and a lane per sum adds them in order).
+//   3. node moments, bottom-up: one launch per level from the deepest up, one
+//      thread per node of that level adding its children's sums (or a leaf's
+//      particles) in order, then the means.
 //   4. lists: one work-group per group keeps the group's current cut through
 //      the tree as an ordered array; every pass replaces each undecided cell
 //      by its decision (the node, its particles, or its children), in place
@@ -39,10 +39,8 @@ namespace {
 constexpr int kAxisBits = 21;      // bits per axis of the key
 constexpr int kDeepest = 21;       // deepest cell level
 constexpr int kNoCellLevel = 22;   // L_k of a particle whose key equals its predecessor's
-constexpr int kSmallNode = 256;    // nodes up to this size are summed by one thread
 constexpr int kWG = 256;
 constexpr int kListWG = 256;
-constexpr int kMomentChunk = 256;
 constexpr int64_t kMaxN = int64_t(1) << 26;   // every cell count fits in int32 (<= 22 N)
 
 thread_local std::string g_err;
@@ -74,7 +72,7 @@ struct Cell {
 static_assert(sizeof(Cell) == 32, "cell record");
 
 struct Totals {           // written by the device after the prefix sums
-    int32_t cells, nodes, groups, big_nodes;
+    int32_t cells, nodes, groups, pad;
 };
 
 struct Counters {         // list phase
@@ -341,7 +339,7 @@ __global__ void totals_kernel(int64_t n, const int32_t* __restrict__ n_cells, co
     t->cells = cbase[n - 1] + n_cells[n - 1];
     t->nodes = nbase[n - 1] + n_nodes[n - 1];
     t->groups = gbase[n - 1] + gflag[n - 1];
-    t->big_nodes = 0;
+    t->pad = 0;
 }
 
 __global__ __launch_bounds__(kWG) void cells_kernel(int64_t n, int n_leaf, const uint64_t* __restrict__ key,
@@ -352,7 +350,7 @@ __global__ __launch_bounds__(kWG) void cells_kernel(int64_t n, int n_leaf, const
                                                     const int32_t* __restrict__ gbase, const Totals* tot,
                                                     Cell* __restrict__ cell, int32_t* __restrict__ node_level,
                                                     int64_t* __restrict__ node_begin, int64_t* __restrict__ node_end,
-                                                    int32_t* __restrict__ node_big, int64_t* __restrict__ group_first) {
+                                                    int32_t* __restrict__ node_cell, int64_t* __restrict__ group_first) {
     const int64_t k = blockIdx.x * int64_t(kWG) + threadIdx.x;
     if (k == 0) group_first[tot->groups] = n;
     if (k >= n) return;
@@ -376,213 +374,79 @@ __global__ __launch_bounds__(kWG) void cells_kernel(int64_t n, int n_leaf, const
             node_level[c.node] = l;
             node_begin[c.node] = k;
             node_end[c.node] = e;
-            node_big[c.node] = (cnt > kSmallNode && c.node != 0) ? 1 : 0;   // the root has its own kernel
+            node_cell[c.node] = cbase[k] + (l - L);
         }
     }
 }
 
-__global__ __launch_bounds__(kWG) void big_list_kernel(int32_t m, const int32_t* __restrict__ flag,
-                                                       const int32_t* __restrict__ pos, int32_t* __restrict__ list,
-                                                       Totals* tot) {
-    const int32_t i = blockIdx.x * kWG + threadIdx.x;
-    if (i == 0) tot->big_nodes = pos[m - 1] + flag[m - 1];
-    if (i < m && flag[i]) list[pos[i]] = i;
-}
-
-// Node moments: total mass and the mass-weighted means of x, v, a, jerk, with
-// every sum taken in particle order and each product rounded before it is
-// added (no fused multiply-add), as the host builder computes them.
+// Node moments, bottom-up, as the host builder defines them: a node's sums
+// S = (m, m x[3], m v[3], m a[3], m jerk[3]) start from zero and add, for a
+// split node, its children's S in key order (a single-particle child's S is
+// 0 + its rounded products), otherwise its particles' rounded products in
+// ascending order.  No fused multiply-add anywhere, so the bits match.  A
+// child is one level deeper than its parent, so one launch per level, from
+// the deepest up, sums every node of that level (at most eight children
+// each, or the particles of a leaf).  raw holds S, 13 doubles per node.
 #pragma clang fp contract(off)
-__global__ __launch_bounds__(kWG) void moments_small_kernel(int32_t m_nodes, const int64_t* __restrict__ nb,
-                                                            const int64_t* __restrict__ ne,
-                                                            const double* __restrict__ sm,
-                                                            const double* __restrict__ sx,
-                                                            const double* __restrict__ sv,
-                                                            const double* __restrict__ sa,
-                                                            const double* __restrict__ sj, double* __restrict__ om,
-                                                            double* __restrict__ ox, double* __restrict__ ov,
-                                                            double* __restrict__ oa, double* __restrict__ oj) {
-    const int32_t node = blockIdx.x * kWG + threadIdx.x;
-    if (node >= m_nodes) return;
-    const int64_t b = nb[node], e = ne[node];
-    if (e - b > kSmallNode) return;
-    double M = 0.0;
-    double s[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int64_t k = b; k < e; ++k) {
-        const double mk = sm[k];
-        M = M + mk;
-        for (int d = 0; d < 3; ++d) {
-            s[d] = s[d] + mk * sx[3 * k + d];
-            s[3 + d] = s[3 + d] + mk * sv[3 * k + d];
-            s[6 + d] = s[6 + d] + mk * sa[3 * k + d];
-            s[9 + d] = s[9 + d] + mk * sj[3 * k + d];
-        }
-    }
-    om[node] = M;
+__device__ inline void add_products(int64_t k, const double* __restrict__ sm, const double* __restrict__ sx,
+                                    const double* __restrict__ sv, const double* __restrict__ sa,
+                                    const double* __restrict__ sj, double (&u)[13]) {
+    const double mk = sm[k];
+    u[0] = u[0] + mk;
     for (int d = 0; d < 3; ++d) {
-        ox[3 * node + d] = s[d] / M;
-        ov[3 * node + d] = s[3 + d] / M;
-        oa[3 * node + d] = s[6 + d] / M;
-        oj[3 * node + d] = s[9 + d] / M;
+        u[1 + d] = u[1 + d] + mk * sx[3 * k + d];
+        u[4 + d] = u[4 + d] + mk * sv[3 * k + d];
+        u[7 + d] = u[7 + d] + mk * sa[3 * k + d];
+        u[10 + d] = u[10 + d] + mk * sj[3 * k + d];
     }
 }
 
-// One work-group per large node.  All threads load a chunk of particles and
-// form the 12 products m_k * component; lane q < 13 of the first wave then
-// adds column q of the chunk in particle order.  Two register sets keep the
-// next chunk's loads in flight while the sums run.
-struct Chunk {
-    double v[13];
-};
-
-__device__ inline void load_chunk(Chunk& c, int64_t k, int64_t e, const double* __restrict__ sm,
-                                  const double* __restrict__ sx, const double* __restrict__ sv,
-                                  const double* __restrict__ sa, const double* __restrict__ sj) {
-    if (k < e) {
-        c.v[0] = sm[k];
-        for (int d = 0; d < 3; ++d) {
-            c.v[1 + d] = sx[3 * k + d];
-            c.v[4 + d] = sv[3 * k + d];
-            c.v[7 + d] = sa[3 * k + d];
-            c.v[10 + d] = sj[3 * k + d];
+__global__ __launch_bounds__(kWG) void node_sums_kernel(int32_t level, int32_t m_nodes,
+                                                        const int32_t* __restrict__ node_level,
+                                                        const int32_t* __restrict__ node_cell,
+                                                        const Cell* __restrict__ cell, const double* __restrict__ sm,
+                                                        const double* __restrict__ sx, const double* __restrict__ sv,
+                                                        const double* __restrict__ sa, const double* __restrict__ sj,
+                                                        double* __restrict__ raw) {
+    const int32_t q = blockIdx.x * kWG + threadIdx.x;
+    if (q >= m_nodes || node_level[q] != level) return;
+    const int32_t ci = node_cell[q];
+    const Cell c = cell[ci];
+    double s[13];
+    for (int r = 0; r < 13; ++r) s[r] = 0.0;
+    if (c.split) {
+        for (int32_t ch = ci + 1; ch < c.skip;) {
+            const Cell cc = cell[ch];
+            double u[13];
+            if (cc.node >= 0) {
+                for (int r = 0; r < 13; ++r) u[r] = raw[13 * int64_t(cc.node) + r];
+            } else {
+                for (int r = 0; r < 13; ++r) u[r] = 0.0;
+                add_products(cc.begin, sm, sx, sv, sa, sj, u);
+            }
+            for (int r = 0; r < 13; ++r) s[r] = s[r] + u[r];
+            ch = cc.skip;
         }
     } else {
-        for (int q = 0; q < 13; ++q) c.v[q] = 0.0;
+        for (int64_t k = c.begin; k < c.end; ++k) add_products(k, sm, sx, sv, sa, sj, s);
     }
+    for (int r = 0; r < 13; ++r) raw[13 * int64_t(q) + r] = s[r];
 }
 
-// Rows are padded to 258 doubles: 16-byte aligned for paired reads, and the
-// 13 summing lanes start on different LDS banks.
-constexpr int kRow = kMomentChunk + 2;
-
-__device__ inline void stage_chunk(const Chunk& c, double (*buf)[kRow]) {
-    const int t = threadIdx.x;
-    buf[0][t] = c.v[0];
-    for (int q = 1; q < 13; ++q) buf[q][t] = c.v[0] * c.v[q];
-}
-
-// acc + col[0] + col[1] + ... + col[cnt-1], left to right.  Two register
-// batches of 16 alternate so that one batch's LDS reads are in flight while
-// the other batch is added.
-__device__ inline void read16(double2 (&r)[8], const double* col) {
-    for (int u = 0; u < 8; ++u) r[u] = *reinterpret_cast<const double2*>(col + 2 * u);
-}
-
-__device__ inline double add16(double acc, const double2 (&r)[8]) {
-    for (int u = 0; u < 8; ++u) {
-        acc = acc + r[u].x;
-        acc = acc + r[u].y;
-    }
-    return acc;
-}
-
-__device__ inline double sum_column(double acc, const double (*buf)[kRow], int q, int cnt) {
-    const double* col = buf[q];
-    const int nb = cnt / 16;
-    double2 ra[8], rb[8];
-    if (nb > 0) read16(ra, col);
-    for (int b = 0; b < nb; b += 2) {
-        if (b + 1 < nb) read16(rb, col + 16 * (b + 1));
-        acc = add16(acc, ra);
-        if (b + 1 >= nb) break;
-        if (b + 2 < nb) read16(ra, col + 16 * (b + 2));
-        acc = add16(acc, rb);
-    }
-    for (int i = 16 * nb; i < cnt; ++i) acc = acc + col[i];
-    return acc;
-}
-
-// Moments of the node with particles [b, e), written at index `node` of the
-// output arrays, by the whole work-group.
-__device__ inline void sum_node(int64_t b, int64_t e, int32_t node, const double* __restrict__ sm,
-                                const double* __restrict__ sx, const double* __restrict__ sv,
-                                const double* __restrict__ sa, const double* __restrict__ sj,
-                                double* __restrict__ om, double* __restrict__ ox, double* __restrict__ ov,
-                                double* __restrict__ oa, double* __restrict__ oj, double (*buf)[13][kRow],
-                                double* mass) {
-    const int t = threadIdx.x;
-    const int64_t nch = (e - b + kMomentChunk - 1) / kMomentChunk;
-    Chunk r0, r1;
-    load_chunk(r0, b + t, e, sm, sx, sv, sa, sj);
-    stage_chunk(r0, buf[0]);
-    if (nch > 1) load_chunk(r1, b + kMomentChunk + t, e, sm, sx, sv, sa, sj);
-    __syncthreads();
-    double acc = 0.0;
-    for (int64_t c = 0; c < nch; c += 2) {
-        // chunk c is staged in buf[0]; r1 holds chunk c + 1 (if any)
-        if (c + 2 < nch) load_chunk(r0, b + (c + 2) * kMomentChunk + t, e, sm, sx, sv, sa, sj);
-        if (t < 13) acc = sum_column(acc, buf[0], t, static_cast<int>(min<int64_t>(kMomentChunk, e - b - c * kMomentChunk)));
-        if (c + 1 >= nch) break;
-        stage_chunk(r1, buf[1]);
-        __syncthreads();
-        if (c + 3 < nch) load_chunk(r1, b + (c + 3) * kMomentChunk + t, e, sm, sx, sv, sa, sj);
-        if (t < 13)
-            acc = sum_column(acc, buf[1], t, static_cast<int>(min<int64_t>(kMomentChunk, e - b - (c + 1) * kMomentChunk)));
-        if (c + 2 >= nch) break;
-        __syncthreads();   // buf[0] is free again
-        stage_chunk(r0, buf[0]);
-        __syncthreads();
-    }
-    if (t == 0) {
-        *mass = acc;
-        om[node] = acc;
-    }
-    __syncthreads();
-    if (t >= 1 && t < 13) {
-        const double M = *mass;
-        const int q = t - 1, d = q % 3;
-        double* out = q < 3 ? ox : q < 6 ? ov : q < 9 ? oa : oj;
-        out[3 * node + d] = acc / M;
-    }
-    __syncthreads();
-}
-
-// Large nodes other than the root, one work-group each.
-__global__ __launch_bounds__(kMomentChunk) void moments_big_kernel(const int32_t* __restrict__ list,
-                                                                   const Totals* tot,
-                                                                   const int64_t* __restrict__ nb,
-                                                                   const int64_t* __restrict__ ne,
-                                                                   const double* __restrict__ sm,
-                                                                   const double* __restrict__ sx,
-                                                                   const double* __restrict__ sv,
-                                                                   const double* __restrict__ sa,
-                                                                   const double* __restrict__ sj,
-                                                                   double* __restrict__ om, double* __restrict__ ox,
-                                                                   double* __restrict__ ov, double* __restrict__ oa,
-                                                                   double* __restrict__ oj) {
-    __shared__ __align__(16) double buf[2][13][kRow];
-    __shared__ double mass;
-    const int32_t nbig = tot->big_nodes;
-    for (int32_t w = blockIdx.x; w < nbig; w += gridDim.x) {
-        const int32_t node = list[w];
-        sum_node(nb[node], ne[node], node, sm, sx, sv, sa, sj, om, ox, ov, oa, oj, buf, &mass);
-    }
-}
-
-// The root (all n particles): its sums form the longest sequential chain of
-// the build, and no opening test reads them (the root contains every group),
-// so they run on a second stream beside the rest of the build.  Out: 13
-// doubles (m, x[3], v[3], a[3], jerk[3]).
-__global__ __launch_bounds__(kMomentChunk) void moments_root_kernel(int64_t n, const double* __restrict__ sm,
-                                                                    const double* __restrict__ sx,
-                                                                    const double* __restrict__ sv,
-                                                                    const double* __restrict__ sa,
-                                                                    const double* __restrict__ sj,
-                                                                    double* __restrict__ out) {
-    __shared__ __align__(16) double buf[2][13][kRow];
-    __shared__ double mass;
-    sum_node(0, n, 0, sm, sx, sv, sa, sj, out, out + 1, out + 4, out + 7, out + 10, buf, &mass);
-}
-
-__global__ void root_store_kernel(const double* __restrict__ in, double* __restrict__ om, double* __restrict__ ox,
-                                  double* __restrict__ ov, double* __restrict__ oa, double* __restrict__ oj) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    om[0] = in[0];
+__global__ __launch_bounds__(kWG) void node_means_kernel(int32_t m_nodes, const double* __restrict__ raw,
+                                                         double* __restrict__ om, double* __restrict__ ox,
+                                                         double* __restrict__ ov, double* __restrict__ oa,
+                                                         double* __restrict__ oj) {
+    const int32_t q = blockIdx.x * kWG + threadIdx.x;
+    if (q >= m_nodes) return;
+    const double* u = raw + 13 * int64_t(q);
+    const double M = u[0];
+    om[q] = M;
     for (int d = 0; d < 3; ++d) {
-        ox[d] = in[1 + d];
-        ov[d] = in[4 + d];
-        oa[d] = in[7 + d];
-        oj[d] = in[10 + d];
+        ox[3 * q + d] = u[1 + d] / M;
+        ov[3 * q + d] = u[4 + d] / M;
+        oa[3 * q + d] = u[7 + d] / M;
+        oj[3 * q + d] = u[10 + d] / M;
     }
 }
 #pragma clang fp contract(on)
@@ -851,15 +715,13 @@ struct htd_tree {
     // cells and nodes
     DevBuf<Cell> cell;
     DevBuf<double> nm, nx, nv, na, nj;
-    DevBuf<int32_t> nlev, nbig, nbigpos, biglist;
+    DevBuf<int32_t> nlev, ncid;   // per node: level, cell index
+    DevBuf<double> nraw;            // per node: the 13 sums of its moments
     DevBuf<int64_t> nbeg, nend;
     // groups and lists
     DevBuf<int64_t> group_first, list_off, gstage, glen64;
     DevBuf<int32_t> glen, cut, stage, entries;
     DevBuf<Counters> ctr;
-    DevBuf<double> root_out;    // the root's moments, from the second stream
-    hipStream_t s2 = nullptr;   // second stream: the root's sums
-    hipEvent_t ev_gather = nullptr, ev_root = nullptr;
     int32_t cut_cap = 1 << 15;
     int n_list_wg = 1024;
     // results of the last build
@@ -908,7 +770,7 @@ int grow_particles(htd_tree* t, int64_t n) {
         (rc = t->sj.grow(3 * n)) || (rc = t->sm.grow(n)) || (rc = t->lev.grow(n)) || (rc = t->ncell.grow(n)) ||
         (rc = t->cbase.grow(n)) || (rc = t->nnode.grow(n)) || (rc = t->nbase.grow(n)) || (rc = t->gflag.grow(n)) ||
         (rc = t->gbase.grow(n)) || (rc = t->part.grow(6 * 1024)) || (rc = t->root.grow(1)) || (rc = t->tot.grow(1)) ||
-        (rc = t->ctr.grow(1)) || (rc = t->root_out.grow(13)) || (rc = t->group_first.grow(n + 1)) ||
+        (rc = t->ctr.grow(1)) || (rc = t->group_first.grow(n + 1)) ||
         (rc = t->list_off.grow(n + 1)) ||
         (rc = t->gstage.grow(n + 1)) || (rc = t->glen64.grow(n + 1)) || (rc = t->glen.grow(n + 1)))
         return rc;
@@ -937,7 +799,6 @@ int run_lists(htd_tree* t, const ListArgs& base, int32_t* max_cut, unsigned long
 int build(htd_tree* t, int64_t n, const double* x, const double* v, const double* a, const double* jerk,
           const double* m, int n_leaf, int n_crit, double theta) {
     hipStream_t s = t->stream;
-    HTD_HIP(hipStreamSynchronize(t->s2));   // nothing of an earlier (failed) build still reads the buffers
     if (int rc = grow_particles(t, n)) return rc;
     if (int rc = reserve_tmp(t, n)) return rc;
     HTD_HIP(hipEventRecord(t->ev[0], s));
@@ -956,17 +817,6 @@ int build(htd_tree* t, int64_t n, const double* x, const double* v, const double
     HTD_HIP(hipEventRecord(t->ev[2], s));
     gather_kernel<<<blocks_for(n, kWG), kWG, 0, s>>>(n, t->idx.p, t->key.p, x, v, a, jerk, m, t->perm.p, t->sx.p,
                                                      t->sv.p, t->sa.p, t->sj.p, t->sm.p, t->lev.p);
-    // the root's sums start now on the second stream (large builds only; a
-    // root of up to kSmallNode particles is summed with the other small nodes)
-    const bool root_apart = n > kSmallNode;
-    if (root_apart) {
-        HTD_HIP(hipEventRecord(t->ev_gather, s));
-        HTD_HIP(hipStreamWaitEvent(t->s2, t->ev_gather, 0));
-        moments_root_kernel<<<1, kMomentChunk, 0, t->s2>>>(n, t->sm.p, t->sx.p, t->sv.p, t->sa.p, t->sj.p,
-                                                            t->root_out.p);
-        HTD_HIP(hipGetLastError());
-        HTD_HIP(hipEventRecord(t->ev_root, t->s2));
-    }
     // 2. cells, nodes and groups
     count_kernel<<<blocks_for(n, kWG), kWG, 0, s>>>(n, n_leaf, n_crit, t->key.p, t->lev.p, t->ncell.p, t->nnode.p,
                                                     t->gflag.p);
@@ -988,25 +838,22 @@ int build(htd_tree* t, int64_t n, const double* x, const double* v, const double
     const int64_t M1 = std::max<int64_t>(t->M, 1);
     if ((rc = t->cell.grow(t->C)) || (rc = t->nm.grow(M1)) || (rc = t->nx.grow(3 * M1)) ||
         (rc = t->nv.grow(3 * M1)) || (rc = t->na.grow(3 * M1)) || (rc = t->nj.grow(3 * M1)) ||
-        (rc = t->nlev.grow(M1)) || (rc = t->nbig.grow(M1)) || (rc = t->nbigpos.grow(M1)) ||
-        (rc = t->biglist.grow(M1)) || (rc = t->nbeg.grow(M1)) || (rc = t->nend.grow(M1)))
+        (rc = t->nlev.grow(M1)) || (rc = t->ncid.grow(M1)) || (rc = t->nraw.grow(13 * M1)) ||
+        (rc = t->nbeg.grow(M1)) || (rc = t->nend.grow(M1)))
         return rc;
     cells_kernel<<<blocks_for(n, kWG), kWG, 0, s>>>(n, n_leaf, t->key.p, t->lev.p, t->cbase.p, t->nbase.p,
                                                     t->gflag.p, t->gbase.p, t->tot.p, t->cell.p, t->nlev.p,
-                                                    t->nbeg.p, t->nend.p, t->nbig.p, t->group_first.p);
+                                                    t->nbeg.p, t->nend.p, t->ncid.p, t->group_first.p);
     HTD_HIP(hipGetLastError());
     HTD_HIP(hipEventRecord(t->ev[3], s));
     // 3. node moments
     if (t->M > 0) {
         const int32_t Mi = static_cast<int32_t>(t->M);
-        moments_small_kernel<<<blocks_for(Mi, kWG), kWG, 0, s>>>(Mi, t->nbeg.p, t->nend.p, t->sm.p, t->sx.p,
-                                                                  t->sv.p, t->sa.p, t->sj.p, t->nm.p, t->nx.p,
-                                                                  t->nv.p, t->na.p, t->nj.p);
-        if ((rc = scan_i32(t, t->nbig.p, t->nbigpos.p, Mi))) return rc;
-        big_list_kernel<<<blocks_for(Mi, kWG), kWG, 0, s>>>(Mi, t->nbig.p, t->nbigpos.p, t->biglist.p, t->tot.p);
-        moments_big_kernel<<<2048, kMomentChunk, 0, s>>>(t->biglist.p, t->tot.p, t->nbeg.p, t->nend.p, t->sm.p,
-                                                         t->sx.p, t->sv.p, t->sa.p, t->sj.p, t->nm.p, t->nx.p,
-                                                         t->nv.p, t->na.p, t->nj.p);
+        for (int level = kDeepest; level >= 0; --level)
+            node_sums_kernel<<<blocks_for(Mi, kWG), kWG, 0, s>>>(level, Mi, t->nlev.p, t->ncid.p, t->cell.p, t->sm.p,
+                                                                 t->sx.p, t->sv.p, t->sa.p, t->sj.p, t->nraw.p);
+        node_means_kernel<<<blocks_for(Mi, kWG), kWG, 0, s>>>(Mi, t->nraw.p, t->nm.p, t->nx.p, t->nv.p, t->na.p,
+                                                              t->nj.p);
         HTD_HIP(hipGetLastError());
     }
     HTD_HIP(hipEventRecord(t->ev[4], s));
@@ -1055,11 +902,6 @@ int build(htd_tree* t, int64_t n, const double* x, const double* v, const double
     if ((rc = t->entries.grow(std::max<int64_t>(t->L, 1)))) return rc;
     csr_kernel<<<std::min(Gi, 4096), kWG, 0, s>>>(Gi, t->list_off.p, t->gstage.p, t->stage.p, t->entries.p);
     HTD_HIP(hipGetLastError());
-    if (root_apart) {   // join: the root's moments into node 0
-        HTD_HIP(hipStreamWaitEvent(s, t->ev_root, 0));
-        root_store_kernel<<<1, 64, 0, s>>>(t->root_out.p, t->nm.p, t->nx.p, t->nv.p, t->na.p, t->nj.p);
-        HTD_HIP(hipGetLastError());
-    }
     HTD_HIP(hipEventRecord(t->ev[6], s));
     HTD_HIP(hipStreamSynchronize(s));
     for (int i = 0; i < 6; ++i) HTD_HIP(hipEventElapsedTime(&t->phase_ms[i], t->ev[i], t->ev[i + 1]));
@@ -1100,12 +942,6 @@ int htd_create(htd_tree** out, int32_t device, void* stream, int64_t n_max) {
             htd_destroy(t);
             return fail(HTD_EHIP, "hipEventCreate failed");
         }
-    if (hipStreamCreateWithFlags(&t->s2, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&t->ev_gather, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&t->ev_root, hipEventDisableTiming) != hipSuccess) {
-        htd_destroy(t);
-        return fail(HTD_EHIP, "stream or event creation failed");
-    }
     if (int rc = grow_particles(t, n_max)) {
         htd_destroy(t);
         return rc;
@@ -1119,21 +955,14 @@ int htd_destroy(htd_tree* t) {
     (void)hipSetDevice(t->device);
     if (t->stream) (void)hipStreamSynchronize(t->stream);
     else (void)hipDeviceSynchronize();
-    if (t->s2) {
-        (void)hipStreamSynchronize(t->s2);
-        (void)hipStreamDestroy(t->s2);
-    }
     for (auto& e : t->ev)
         if (e) (void)hipEventDestroy(e);
-    if (t->ev_gather) (void)hipEventDestroy(t->ev_gather);
-    if (t->ev_root) (void)hipEventDestroy(t->ev_root);
-    t->root_out.release();
     t->key_in.release(); t->key.release(); t->idx_in.release(); t->idx.release(); t->perm.release();
     t->sx.release(); t->sv.release(); t->sa.release(); t->sj.release(); t->sm.release(); t->lev.release();
     t->ncell.release(); t->cbase.release(); t->nnode.release(); t->nbase.release(); t->gflag.release();
     t->gbase.release(); t->tmp.release(); t->part.release(); t->root.release(); t->tot.release();
     t->cell.release(); t->nm.release(); t->nx.release(); t->nv.release(); t->na.release(); t->nj.release();
-    t->nlev.release(); t->nbig.release(); t->nbigpos.release(); t->biglist.release(); t->nbeg.release();
+    t->nlev.release(); t->ncid.release(); t->nraw.release(); t->nbeg.release();
     t->nend.release(); t->group_first.release(); t->list_off.release(); t->gstage.release(); t->glen64.release();
     t->glen.release(); t->cut.release(); t->stage.release(); t->entries.release(); t->ctr.release();
     delete t;

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <memory>
 #include <new>
 #include <vector>
 
@@ -143,28 +144,41 @@ void build_cells(htb_tree& t, int n_leaf) {
     for (int64_t c = 0; c < nc; ++c) t.cell[c].skip = c + size[c];
 }
 
-void node_moments(const htb_tree& t, const Cell& c, const double* m, const double* x, const double* v,
-                  const double* a, const double* j, double* om, double* ox, double* ov, double* oa,
-                  double* oj) {
-    double M = 0.0;
-    double s[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int64_t k = c.begin; k < c.end; ++k) {
+// Node sums, bottom-up: S = (sum m, sum m*x, sum m*v, sum m*a, sum m*jerk)
+// starts from zero; a split node adds its children's S in key order (a
+// single-particle child's S is 0 + its rounded products), an unsplit node its
+// particles' rounded products in ascending order.  Children are one level
+// deeper, so the nodes of one level depend only on the level below.
+void node_sums(const htb_tree& t, int64_t q, const double* m, const double* x, const double* v, const double* a,
+               const double* j, double* raw) {
+    const int64_t ci = t.node_cell[q];
+    const Cell& c = t.cell[ci];
+    double s[13] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    auto products = [&](int64_t k, double* u) {   // u += the products of particle k
         const double mk = m[k];
-        M = M + mk;
+        u[0] = u[0] + mk;
         for (int d = 0; d < 3; ++d) {
-            s[d] = s[d] + mk * x[3 * k + d];
-            s[3 + d] = s[3 + d] + mk * v[3 * k + d];
-            s[6 + d] = s[6 + d] + mk * a[3 * k + d];
-            s[9 + d] = s[9 + d] + mk * j[3 * k + d];
+            u[1 + d] = u[1 + d] + mk * x[3 * k + d];
+            u[4 + d] = u[4 + d] + mk * v[3 * k + d];
+            u[7 + d] = u[7 + d] + mk * a[3 * k + d];
+            u[10 + d] = u[10 + d] + mk * j[3 * k + d];
         }
+    };
+    if (c.split) {
+        for (int64_t ch = ci + 1; ch < c.skip; ch = t.cell[ch].skip) {
+            const Cell& cc = t.cell[ch];
+            double u[13] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+            if (cc.node >= 0) {
+                for (int r = 0; r < 13; ++r) u[r] = raw[13 * cc.node + r];
+            } else {
+                products(cc.begin, u);
+            }
+            for (int r = 0; r < 13; ++r) s[r] = s[r] + u[r];
+        }
+    } else {
+        for (int64_t k = c.begin; k < c.end; ++k) products(k, s);
     }
-    *om = M;
-    for (int d = 0; d < 3; ++d) {
-        ox[d] = s[d] / M;
-        ov[d] = s[3 + d] / M;
-        oa[d] = s[6 + d] / M;
-        oj[d] = s[9 + d] / M;
-    }
+    for (int r = 0; r < 13; ++r) raw[13 * q + r] = s[r];
 }
 
 // Walk the pre-order cell array once for one group, without a stack.
@@ -329,20 +343,42 @@ int htb_build(htb_tree** out, int64_t n, const double* x, const double* v, const
         build_cells(*t, n_leaf);
         const int64_t nc = static_cast<int64_t>(t->cell.size());
         int64_t M = 0;
+        std::vector<int8_t> node_level;
         for (int64_t c = 0; c < nc; ++c)
             if (t->cell[c].end - t->cell[c].begin >= 2) {
                 t->cell[c].node = M++;
                 t->node_cell.push_back(c);
+                node_level.push_back(static_cast<int8_t>(t->cell[c].level));
             }
         t->nm.resize(M);
         t->nx.resize(3 * M);
         t->nv.resize(3 * M);
         t->na.resize(3 * M);
         t->nj.resize(3 * M);
+        {
+            std::unique_ptr<double[]> raw(new double[static_cast<size_t>(13 * std::max<int64_t>(M, 1))]);
+            std::vector<int64_t> at(kDeepest + 2, 0), by_level(static_cast<size_t>(M));
+            for (int64_t k = 0; k < M; ++k) at[node_level[k] + 1]++;
+            for (int l = 0; l <= kDeepest; ++l) at[l + 1] += at[l];
+            std::vector<int64_t> fill(at.begin(), at.end() - 1);
+            for (int64_t k = 0; k < M; ++k) by_level[fill[node_level[k]]++] = k;
+            for (int l = kDeepest; l >= 0; --l) {
 #pragma omp parallel for schedule(dynamic, 256)
-        for (int64_t k = 0; k < M; ++k)
-            node_moments(*t, t->cell[t->node_cell[k]], sm.data(), sx.data(), sv.data(), sa.data(), sj.data(),
-                         &t->nm[k], &t->nx[3 * k], &t->nv[3 * k], &t->na[3 * k], &t->nj[3 * k]);
+                for (int64_t r = at[l]; r < at[l + 1]; ++r)
+                    node_sums(*t, by_level[r], sm.data(), sx.data(), sv.data(), sa.data(), sj.data(), raw.get());
+            }
+#pragma omp parallel for schedule(static)
+            for (int64_t k = 0; k < M; ++k) {
+                const double* u = &raw[13 * k];
+                t->nm[k] = u[0];
+                for (int d = 0; d < 3; ++d) {
+                    t->nx[3 * k + d] = u[1 + d] / u[0];
+                    t->nv[3 * k + d] = u[4 + d] / u[0];
+                    t->na[3 * k + d] = u[7 + d] / u[0];
+                    t->nj[3 * k + d] = u[10 + d] / u[0];
+                }
+            }
+        }
         // groups: first cell on each path with <= n_crit particles or no split
         for (int64_t c = 0; c < nc;) {
             const Cell& cl = t->cell[c];
