@@ -247,6 +247,7 @@ class Simulation:
         self.ctx.state_set(self.t0, self.dt, self.m, self.x, self.v, self.a, self.j, self.pot)
 
     def _rebuild_on_device(self):
+        self.ctx.sync()   # the step's kernels end first, so the tree timer holds the rebuild alone
         t_start = time.perf_counter()
         lock = self._dtree_lock if self._dtree_lock is not None else contextlib.nullcontext()
         with lock:
