@@ -288,6 +288,59 @@ def test_lists_are_the_unique_barnes_hut_cover(oracle, tree2k):
             assert not np.any(acc & cont)
 
 
+def _bottom_up_mass_inputs():
+    rng = np.random.default_rng(21)
+    x, _, _ = W.plummer(4096, 5)
+    out = [("plummer4k", x, 1)]
+    out.append(("plummer4k_leaf3", x, 3))
+    xc = rng.normal(size=(600, 3))
+    xc[100:160] = xc[100]          # 60 coincident particles: a level-21 leaf
+    out.append(("coincident", xc, 1))
+    return out
+
+
+@pytest.mark.parametrize("name,x,n_leaf", _bottom_up_mass_inputs(), ids=[c[0] for c in _bottom_up_mass_inputs()])
+def test_node_mass_is_children_summed_in_key_order(oracle, name, x, n_leaf):
+    """The node-moment reading, bit for bit, from the oracle's outputs alone: a
+    split node's mass is 0 + its children's masses added left to right in key
+    order (a child node's mass, or a single particle's), and a leaf node's is
+    0 + its particles' masses in order.  Random masses make the order visible
+    in the last bits (a sequential sum over each node's own particles differs
+    for most nodes)."""
+    rng = np.random.default_rng(4)
+    n = len(x)
+    m = rng.uniform(0.5, 1.5, n) / n
+    v, a, j = rng.normal(size=(3, n, 3))
+    tr = oracle.Tree(x, v, a, j, m, n_leaf, 64, 0.5)
+    ms = m[tr.perm]
+    at = {(int(tr.node_level[q]), int(tr.node_begin[q])): q for q in range(tr.n_node)}
+    differs = 0
+    for q in range(tr.n_node):
+        L, b, e = int(tr.node_level[q]), int(tr.node_begin[q]), int(tr.node_end[q])
+        s = 0.0
+        if e - b > n_leaf and L < 21:      # split: children in key order
+            k = b
+            while k < e:
+                c = at.get((L + 1, k))
+                if c is not None:
+                    s = s + float(tr.node_m[c])
+                    k = int(tr.node_end[c])
+                else:
+                    s = s + (0.0 + float(ms[k]))
+                    k += 1
+        else:
+            for k in range(b, e):
+                s = s + float(ms[k])
+        assert tr.node_m[q] == s, (name, q, L, b, e)
+        seq = 0.0
+        for k in range(b, e):
+            seq = seq + float(ms[k])
+        differs += seq != s
+    assert tr.n_node > 100
+    if name.startswith("plummer"):
+        assert differs > tr.n_node // 10   # the check tells the two readings apart
+
+
 def test_node_prediction_is_mass_weighted_mean(oracle, tree2k):
     """A node predicted from its moments equals the mass-weighted mean of its
     members predicted from the same time (the predictor is linear)."""
