@@ -331,7 +331,7 @@ def bench_ensemble(args, torch):
     total_n = int(sizes.sum())
     eng = E.Engine(precision="mixed", max_clusters=64, max_active=total_n, max_items=1 << 20, max_rows=total_n,
                    resident=not args.host_engine, device_tree=engine_device_tree(args),
-                   tree_n_max=int(sizes.max()))
+                   tree_n_max=int(sizes.max()), lanes=args.lanes or None)
     t0 = time.perf_counter()
     for sp in specs:
         eng.add(eng.new_cluster(sp))
@@ -347,14 +347,14 @@ def bench_ensemble(args, torch):
     eng.wall = 0.0
     eng.phase = {k: 0.0 for k in eng.phase}
     eng.subphase.clear()
-    eng.batch.set_timing(True)
+    eng.set_timing(True)
     torch.cuda.synchronize()
     tw = time.perf_counter()
     for _ in range(args.steps):
         eng.step()
     torch.cuda.synchronize()
     wall = time.perf_counter() - tw
-    kms, nl, kp = eng.batch.kernel_timing()
+    kms, nl, kp = eng.kernel_timing()
     lat = np.array(eng.step_ms)
     value = eng.pairs / wall
     achieved = FLOPS_PER_PAIR * kp / (kms * 1e-3) / 1e12
@@ -364,7 +364,7 @@ def bench_ensemble(args, torch):
         "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
         "config": {"workload": "ensemble64", "clusters": 64, "n_range": [4096, 65536], "n_total": total_n,
-                   "engine": engine_name(args),
+                   "engine": engine_name(args), "lanes": eng.n_lanes,
                    "theta": 0.5, "eps": "4/N", "dt_tree": 1.0 / 256, "eta": 0.01, "n_crit": 256, "precision": "mixed"},
         "p50_step_ms": float(np.percentile(lat, 50)), "p99_step_ms": float(np.percentile(lat, 99)),
         "equivalent_interactions_per_s": eng.equiv_pairs / wall,
@@ -394,13 +394,13 @@ def bench_served(args, torch):
     def serve(reqs):
         eng = E.Engine(precision="mixed", max_clusters=args.max_resident, max_active=cap_active, max_items=1 << 20,
                        max_rows=cap_active, resident=not args.host_engine, device_tree=engine_device_tree(args),
-                       tree_n_max=int(sizes.max()))
+                       tree_n_max=int(sizes.max()), lanes=args.lanes or None)
         srv = E.Server(eng, hbm_budget=budget, max_resident=args.max_resident)
         t = time.perf_counter()
         done = srv.run(reqs)
         span = time.perf_counter() - t
         out = dict(span=span, done=done, step_ms=list(eng.step_ms), pairs=eng.pairs, phase=dict(eng.phase),
-                   max_used=srv.max_used, max_waiting=srv.max_waiting)
+                   max_used=srv.max_used, max_waiting=srv.max_waiting, lanes=eng.n_lanes)
         eng.close()
         return out
 
@@ -425,7 +425,7 @@ def bench_served(args, torch):
                    "theta": 0.5, "eps": "4/N", "dt_tree": 1.0 / 256, "eta": 0.01, "n_crit": 256,
                    "arrival_rate_per_s": rate, "load": 0.8, "max_resident": args.max_resident,
                    "hbm_budget_gb": args.hbm_gb, "precision": "mixed",
-                   "engine": engine_name(args)},
+                   "engine": engine_name(args), "lanes": run["lanes"]},
         "p50_step_ms": float(np.percentile(lat, 50)), "p99_step_ms": float(np.percentile(lat, 99)),
         "capacity_runs_per_s": capacity, "throughput_runs_per_s": len(done) / run["span"],
         "interactions_per_s": run["pairs"] / run["span"],
@@ -460,6 +460,9 @@ def main():
     ap.add_argument("--dump-steps", default="", help="write per-step (n_active, pairs, items, ms) JSON here")
     ap.add_argument("--requests", type=int, default=200, help="served workload: number of cluster runs")
     ap.add_argument("--max-resident", type=int, default=32, help="served workload: batch slots")
+    ap.add_argument("--lanes", type=int, default=0,
+                    help="resident engine workloads: cluster lanes stepped out of phase (0: the engine's "
+                         "default, one)")
     ap.add_argument("--hbm-gb", type=float, default=64.0, help="served workload: device-memory budget")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (scale for the byte counters)")

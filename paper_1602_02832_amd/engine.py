@@ -12,8 +12,14 @@ engine step advances every resident cluster by one of its own block steps:
   4. each cluster corrects its particles on the host; clusters at a tree time
      rebuild their tree and lists.
 
+The resident engine can split its clusters into lanes, each with a stream
+and a batch object of its own, stepped in turn: while the device works on
+one lane's step, the host waits for the next lane's scheduler and plans that
+lane, so host planning and device work overlap (one lane by default: every
+lane adds its own scheduler upload, synchronisation and launches).
+
 Work plans are per cluster, so a cluster's forces are bit-identical alone and
-in any mix.  ``Server`` adds continuous batching: requests for whole cluster
+in any mix (and in any lane).  ``Server`` adds continuous batching: requests for whole cluster
 runs arrive over time and are admitted while device memory and batch slots
 allow; finished runs leave and free their slots.
 """
@@ -139,7 +145,7 @@ class Engine:
     """Advances a set of clusters one block step each per engine step."""
 
     def __init__(self, precision="mixed", device=0, max_clusters=256, max_active=1 << 21, max_items=1 << 20,
-                 max_rows=1 << 21, rebuild_workers=4, resident=False, device_tree=False, tree_n_max=0):
+                 max_rows=1 << 21, rebuild_workers=4, resident=False, device_tree=False, tree_n_max=0, lanes=None):
         import torch
 
         # resident: each cluster's particle state stays on the device; the block
@@ -160,9 +166,15 @@ class Engine:
             self.tree_n_max = int(tree_n_max)
         self.torch = torch
         self.precision, self.device = precision, device
-        self.stream = torch.cuda.Stream(device=device)
-        self.batch = B.Batch(stream=self.stream.cuda_stream, max_clusters=max_clusters, max_items=max_items,
-                             max_active=max_active, max_rows=max_rows, device=device)
+        # lanes (resident only): groups of clusters on streams of their own, stepped out of phase
+        self.n_lanes = int(lanes) if lanes is not None else 1
+        if self.n_lanes < 1 or (self.n_lanes > 1 and not self.resident):
+            raise ValueError("more than one lane needs the resident engine")
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(self.n_lanes)]
+        self.batches = [B.Batch(stream=st.cuda_stream, max_clusters=max_clusters, max_items=max_items,
+                                max_active=max_active, max_rows=max_rows, device=device) for st in self.streams]
+        self.stream, self.batch = self.streams[0], self.batches[0]   # the host-driven engine's one lane
+        self._next_lane = 0
         self.max_clusters, self.max_active = max_clusters, max_active
         self.clusters: list[Cluster] = []
         dev = f"cuda:{device}"
@@ -192,8 +204,12 @@ class Engine:
 
     def new_cluster(self, spec: RunSpec) -> Cluster:
         shared = self.tree is not None and spec.n <= self.tree_n_max
-        return Cluster(spec, self.precision, self.stream.cuda_stream, self.device, resident=self.resident,
-                       tree=self.tree if shared else None, tree_lock=self.tree_lock if shared else None)
+        lane = self._next_lane                 # lanes in turn, fixed for the cluster's life
+        self._next_lane = (lane + 1) % self.n_lanes
+        c = Cluster(spec, self.precision, self.streams[lane].cuda_stream, self.device, resident=self.resident,
+                    tree=self.tree if shared else None, tree_lock=self.tree_lock if shared else None)
+        c.lane = lane
+        return c
 
     def add(self, c: Cluster):
         if len(self.clusters) >= self.max_clusters:
@@ -217,20 +233,33 @@ class Engine:
         the step mix averages out.  Advances the clusters; returns the choice
         and the measured ms per 1e9 interactions of every candidate."""
         score = {tuple(c): [0.0, 0] for c in candidates}
-        self.batch.set_timing(True)
+        self.set_timing(True)
         for _ in range(rounds):
             for cand in score:
                 self.set_tuning(*cand)
                 for _ in range(steps):
                     self.step()
-                ms, _, pairs = self.batch.kernel_timing()
+                ms, _, pairs = self.kernel_timing()
                 score[cand][0] += ms
                 score[cand][1] += pairs
-        self.batch.set_timing(False)
+        self.set_timing(False)
         per = {c: 1e9 * v[0] / max(v[1], 1) for c, v in score.items()}
         best = min(per, key=per.get)
         self.set_tuning(*best)
         return best, per
+
+    def set_timing(self, enable=True):
+        """Kernel timing of the force launches of every lane."""
+        for b in self.batches:
+            b.set_timing(enable)
+
+    def kernel_timing(self):
+        """(force-kernel ms, launches, pairs) since the last call, over all lanes."""
+        ms, launches, pairs = 0.0, 0, 0
+        for b in self.batches:
+            m_, l_, p_ = b.kernel_timing()
+            ms, launches, pairs = ms + m_, launches + l_, pairs + p_
+        return ms, launches, pairs
 
     def _refresh(self, c: Cluster):
         """The cluster's htb_cluster record, context handle and active-buffer
@@ -346,52 +375,65 @@ class Engine:
         return finished
 
     def _step_resident(self, cl, t0):
-        """Engine step with the clusters' state on the device: one batched
-        scheduler (and the step's one synchronisation), one batched force and
-        one batched corrector; the host only plans the work."""
-        n_cl = len(cl)
-        caches = [self._refresh(c) for c in cl]
-        handles = np.fromiter((cc[0] for cc in caches), dtype=np.uint64, count=n_cl)
-        t_next = np.empty(n_cl)
-        n_act = np.empty(n_cl, dtype=np.int64)
-        act_ptr = np.empty(n_cl, dtype=np.uint64)
-        self.batch.dev_next_block_raw(n_cl, handles.ctypes.data, t_next.ctypes.data, n_act.ctypes.data,
-                                      act_ptr.ctypes.data)
-        t1 = time.perf_counter()
-        eta = np.fromiter((c.sim.eta for c in cl), dtype=np.float64, count=n_cl)
-        dtt = np.fromiter((c.sim.dt_tree for c in cl), dtype=np.float64, count=n_cl)
-        self.batch.dev_step_raw(n_cl, handles.ctypes.data, eta.ctypes.data, dtt.ctypes.data)
-        pairs, _ = self.batch.last_stats()
-        t2 = time.perf_counter()
+        """Engine step with the clusters' state on the device, lane by lane:
+        one batched scheduler (and the lane's one synchronisation), one batched
+        force and one batched corrector per lane; the host only plans the work.
+        Lanes run on streams of their own, so the device works on one lane
+        while the host waits for and plans the next."""
         finished = []
-        for k, c in enumerate(cl):
-            sim = c.sim
-            n = int(n_act[k])
-            sim.t = float(t_next[k])
-            sim.n_block_steps += 1
-            sim.n_particle_steps += n
-            c.steps_done += 1
-            c.active_sum += n
-            if math.fmod(sim.t, sim.dt_tree) == 0.0:      # tree time: state back, rebuild, state up
-                if self.pool is not None:
-                    self.rebuilding[c] = self.pool.submit(sim.rebuild_resident)
-                else:
-                    sim.rebuild_resident()
-            if c.done:
-                finished.append(c)
+        pairs = 0
+        equiv = 0
+        t_sync = t_plan = 0.0
+        for lane, batch in enumerate(self.batches):
+            lc = [c for c in cl if c.lane == lane]
+            if not lc:
+                continue
+            ta = time.perf_counter()
+            n_cl = len(lc)
+            caches = [self._refresh(c) for c in lc]
+            handles = np.fromiter((cc[0] for cc in caches), dtype=np.uint64, count=n_cl)
+            t_next = np.empty(n_cl)
+            n_act = np.empty(n_cl, dtype=np.int64)
+            act_ptr = np.empty(n_cl, dtype=np.uint64)
+            batch.dev_next_block_raw(n_cl, handles.ctypes.data, t_next.ctypes.data, n_act.ctypes.data,
+                                     act_ptr.ctypes.data)
+            tb = time.perf_counter()
+            eta = np.fromiter((c.sim.eta for c in lc), dtype=np.float64, count=n_cl)
+            dtt = np.fromiter((c.sim.dt_tree for c in lc), dtype=np.float64, count=n_cl)
+            batch.dev_step_raw(n_cl, handles.ctypes.data, eta.ctypes.data, dtt.ctypes.data)
+            pairs += batch.last_stats()[0]
+            tc = time.perf_counter()
+            for k, c in enumerate(lc):
+                sim = c.sim
+                n = int(n_act[k])
+                sim.t = float(t_next[k])
+                sim.n_block_steps += 1
+                sim.n_particle_steps += n
+                c.steps_done += 1
+                c.active_sum += n
+                equiv += n * (sim.n - 1)
+                if math.fmod(sim.t, sim.dt_tree) == 0.0:      # tree time: state back, rebuild, state up
+                    if self.pool is not None:
+                        self.rebuilding[c] = self.pool.submit(sim.rebuild_resident)
+                    else:
+                        sim.rebuild_resident()
+                if c.done:
+                    finished.append(c)
+            t_sync += tb - ta
+            t_plan += tc - tb
         t3 = time.perf_counter()
         dt = t3 - t0
-        self.phase["host_begin"] += t1 - t0     # scheduler launches and the step's synchronisation
+        self.phase["host_begin"] += t_sync      # scheduler launches and the lanes' synchronisations
         self.phase["device_wait"] += 0.0
-        self.phase["host_finish"] += t3 - t1   # planning, launches, bookkeeping
+        self.phase["host_finish"] += dt - t_sync   # planning, launches, bookkeeping
         sub = self.subphase
-        sub["schedule_sync"] += t1 - t0
-        sub["plan_launch"] += t2 - t1
-        sub["bookkeeping"] += t3 - t2
+        sub["schedule_sync"] += t_sync
+        sub["plan_launch"] += t_plan
+        sub["bookkeeping"] += dt - t_sync - t_plan
         self.step_ms.append(1e3 * dt)
         self.wall += dt
         self.pairs += pairs
-        self.equiv_pairs += int(sum(int(n) * (c.sim.n - 1) for c, n in zip(cl, n_act)))
+        self.equiv_pairs += int(equiv)
         return finished
 
     def drain(self):
@@ -410,7 +452,8 @@ class Engine:
         for c in self.clusters:
             c.close()
         self.clusters = []
-        self.batch.close()
+        for b in self.batches:
+            b.close()
         if self.tree is not None:
             self.tree.close()
             self.tree = None

@@ -171,3 +171,20 @@ def test_resident_engine_equals_host_engine():
     for k in range(len(specs)):
         for f in FIELDS:
             assert np.array_equal(host[k][f], dtree[k][f]), (k, f)
+
+
+def test_resident_engine_lanes_give_the_same_bits():
+    """Clusters split into lanes (streams and batches of their own, stepped out
+    of phase) give the bits of one lane, also with device rebuilds on the
+    builder the lanes share."""
+    say("engine: one lane vs three lanes")
+    specs = [E.RunSpec(key=k, n=n, seed=700 + k, steps=50, n_crit=64)
+             for k, n in enumerate((600, 1700, 900, 2400, 1200))]
+    one, (_, _, done1) = run_engine(specs, resident=True, lanes=1)
+    three, (_, _, done3) = run_engine(specs, resident=True, lanes=3, device_tree=True, tree_n_max=2500)
+    assert done1 == done3 == [50] * 5
+    for k in range(len(specs)):
+        for f in FIELDS:
+            assert np.array_equal(one[k][f], three[k][f]), (k, f)
+    with pytest.raises(ValueError):
+        E.Engine(lanes=2)              # lanes need the resident engine
