@@ -370,7 +370,7 @@ def bench_ensemble(args, torch):
         "equivalent_interactions_per_s": eng.equiv_pairs / wall,
         "phase_s": eng.phase, "host_subphase_s": dict(eng.subphase),
         "autotuned": {"gather_cost": tuning[0], "target_items": tuning[1],
-                      "kernel_ms_per_1e9_interactions": {str(k): v for k, v in scores.items()}},
+                      "engine_ms_per_1e9_interactions": {str(k): v for k, v in scores.items()}},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None,
                      "kernel": "force_kernel<PrecMixed,false,false>", "avg_launch_ms": kms / max(nl, 1)},

@@ -225,24 +225,31 @@ class Engine:
         for c in self.clusters:
             c.ctx.set_tuning(*self.tuning)
 
-    def autotune(self, candidates=((8, 2048), (12, 2048), (16, 2048), (32, 2048), (12, 1024), (12, 4096)),
-                 steps: int = 4, rounds: int = 2):
-        """Pick the work-plan tuning with the least force-kernel time per
-        interaction on the engine's own clusters.  Each candidate runs `steps`
-        engine steps per round; rounds interleave the candidates so the drift of
-        the step mix averages out.  Advances the clusters; returns the choice
-        and the measured ms per 1e9 interactions of every candidate."""
+    def autotune(self, candidates=((12, 64), (12, 256), (12, 1024), (12, 2048), (8, 256), (16, 256), (16, 2048)),
+                 steps: int = 6, rounds: int = 2):
+        """Pick the work-plan tuning with the least engine wall time per
+        interaction on the engine's own clusters.  The wall time holds the
+        host's planning (every cluster plans towards its own item target, so a
+        batched launch over many clusters needs a far smaller target per
+        cluster than one cluster alone) as well as the device's work.  Each
+        candidate runs `steps` engine steps per round; rounds interleave the
+        candidates so the drift of the step mix averages out.  Advances the
+        clusters; returns the choice and the measured ms per 1e9 interactions
+        of every candidate."""
         score = {tuple(c): [0.0, 0] for c in candidates}
-        self.set_timing(True)
         for _ in range(rounds):
             for cand in score:
                 self.set_tuning(*cand)
+                self.step()                         # the first step after a change is not timed
+                for st in self.streams:
+                    st.synchronize()
+                p0, t0 = self.pairs, time.perf_counter()
                 for _ in range(steps):
                     self.step()
-                ms, _, pairs = self.kernel_timing()
-                score[cand][0] += ms
-                score[cand][1] += pairs
-        self.set_timing(False)
+                for st in self.streams:
+                    st.synchronize()
+                score[cand][0] += 1e3 * (time.perf_counter() - t0)
+                score[cand][1] += self.pairs - p0
         per = {c: 1e9 * v[0] / max(v[1], 1) for c, v in score.items()}
         best = min(per, key=per.get)
         self.set_tuning(*best)
