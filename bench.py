@@ -310,6 +310,12 @@ def cpu_baseline(W, cfg, seconds):
     return base, extra
 
 
+def parse_tuning(text):
+    """'gather_cost,target_items' -> (float, float)."""
+    gc, ti = (float(u) for u in text.split(","))
+    return gc, ti
+
+
 def engine_device_tree(args):
     return not args.host_engine and not args.host_rebuild
 
@@ -336,8 +342,12 @@ def bench_ensemble(args, torch):
     for sp in specs:
         eng.add(eng.new_cluster(sp))
     log(f"ensemble: 64 clusters, {total_n} particles, set up in {time.perf_counter() - t0:.1f} s")
-    # plan tuning chosen on the clusters themselves (untimed; the clusters advance)
-    tuning, scores = eng.autotune()
+    # plan tuning chosen on the clusters themselves (untimed; the clusters advance), unless given
+    if args.tuning:
+        tuning, scores = parse_tuning(args.tuning), {}
+        eng.set_tuning(*tuning)
+    else:
+        tuning, scores = eng.autotune()
     log(f"ensemble: autotuned (gather_cost, target_items) = {tuning}; ms per 1e9 interactions "
         f"{ {str(k): round(v, 3) for k, v in scores.items()} }")
     for _ in range(args.warmup):
@@ -395,6 +405,8 @@ def bench_served(args, torch):
         eng = E.Engine(precision="mixed", max_clusters=args.max_resident, max_active=cap_active, max_items=1 << 20,
                        max_rows=cap_active, resident=not args.host_engine, device_tree=engine_device_tree(args),
                        tree_n_max=int(sizes.max()), lanes=args.lanes or None)
+        if args.tuning:
+            eng.set_tuning(*parse_tuning(args.tuning))
         srv = E.Server(eng, hbm_budget=budget, max_resident=args.max_resident)
         t = time.perf_counter()
         done = srv.run(reqs)
@@ -425,7 +437,8 @@ def bench_served(args, torch):
                    "theta": 0.5, "eps": "4/N", "dt_tree": 1.0 / 256, "eta": 0.01, "n_crit": 256,
                    "arrival_rate_per_s": rate, "load": 0.8, "max_resident": args.max_resident,
                    "hbm_budget_gb": args.hbm_gb, "precision": "mixed",
-                   "engine": engine_name(args), "lanes": run["lanes"]},
+                   "engine": engine_name(args), "lanes": run["lanes"],
+                   "tuning": list(parse_tuning(args.tuning)) if args.tuning else "library default"},
         "p50_step_ms": float(np.percentile(lat, 50)), "p99_step_ms": float(np.percentile(lat, 99)),
         "capacity_runs_per_s": capacity, "throughput_runs_per_s": len(done) / run["span"],
         "interactions_per_s": run["pairs"] / run["span"],
@@ -460,6 +473,9 @@ def main():
     ap.add_argument("--dump-steps", default="", help="write per-step (n_active, pairs, items, ms) JSON here")
     ap.add_argument("--requests", type=int, default=200, help="served workload: number of cluster runs")
     ap.add_argument("--max-resident", type=int, default=32, help="served workload: batch slots")
+    ap.add_argument("--tuning", default="",
+                    help="engine workloads: plan tuning 'gather_cost,target_items' for every cluster "
+                         "(ensemble: instead of the autotune; default for served: the library's)")
     ap.add_argument("--lanes", type=int, default=0,
                     help="resident engine workloads: cluster lanes stepped out of phase (0: the engine's "
                          "default, one)")
