@@ -911,6 +911,8 @@ struct CorrEntry {
     const double* partial;
 };
 
+constexpr int kCorrBatch = 8;   // split partials loaded together by the corrector
+
 template <class P>
 __global__ __launch_bounds__(kWG) void dev_correct_kernel(CorrEntry e0, const CorrEntry* tab, int n_tab,
                                                           int64_t total) {
@@ -945,7 +947,18 @@ __global__ __launch_bounds__(kWG) void dev_correct_kernel(CorrEntry e0, const Co
             double A[kOut];
             const double* p0 = e.partial + (rt.pbase + slot) * kOut;
             for (int u = 0; u < kOut; ++u) A[u] = p0[u];
-            for (int b = 1; b < rt.nsplit; ++b) {
+            // kCorrBatch splits' loads in flight at once, then added in split order
+            int b = 1;
+            for (; b + kCorrBatch <= rt.nsplit; b += kCorrBatch) {
+                double v[kCorrBatch][kOut];
+                for (int w = 0; w < kCorrBatch; ++w) {
+                    const double* pb = e.partial + (rt.pbase + static_cast<int64_t>(b + w) * rt.n_i + slot) * kOut;
+                    for (int u = 0; u < kOut; ++u) v[w][u] = pb[u];
+                }
+                for (int w = 0; w < kCorrBatch; ++w)
+                    for (int u = 0; u < kOut; ++u) A[u] += v[w][u];
+            }
+            for (; b < rt.nsplit; ++b) {
                 const double* pb = e.partial + (rt.pbase + static_cast<int64_t>(b) * rt.n_i + slot) * kOut;
                 for (int u = 0; u < kOut; ++u) A[u] += pb[u];
             }
