@@ -198,6 +198,11 @@ class Engine:
         # tree rebuilds run beside the engine loop; a rebuilding cluster sits out until it is resident again
         self.pool = concurrent.futures.ThreadPoolExecutor(max_workers=rebuild_workers) if rebuild_workers else None
         self.rebuilding = {}
+        # the resident step's per-lane views (cluster lists and their arrays), rebuilt only when the
+        # set of stepping clusters changes: a cluster added, removed, finished, or in or out of a rebuild
+        self._gen = 0
+        self._views_gen = -1
+        self._views = []
         self._ptr = (self.h_acc.data_ptr(), self.h_jerk.data_ptr(), self.h_pot.data_ptr())
         self.tuning = None      # (gather_cost, target_items) for every cluster, None = library defaults
         del dev
@@ -218,6 +223,7 @@ class Engine:
         if self.tuning is not None:
             c.ctx.set_tuning(*self.tuning)
         self.clusters.append(c)
+        self._gen += 1
 
     def set_tuning(self, gather_cost: float, target_items: float):
         """Work-plan tuning (ht_set_tuning) for every resident and future cluster."""
@@ -285,20 +291,26 @@ class Engine:
             if wait or fut.done():
                 fut.result()
                 del self.rebuilding[c]
+                self._gen += 1
 
     def step(self):
         """One engine step over all resident clusters; returns the clusters
         that finished their run in this step."""
         t0 = time.perf_counter()
         self._collect_rebuilds()
+        if self.resident:
+            views = self._lane_views()
+            if not views:
+                if self.rebuilding:
+                    self._collect_rebuilds(wait=True)
+                return []
+            return self._step_resident(views, t0)
         cl = [c for c in self.clusters if not c.done and c not in self.rebuilding]
         if not cl:
             if self.rebuilding:
                 self._collect_rebuilds(wait=True)
             return []
         n_cl = len(cl)
-        if self.resident:
-            return self._step_resident(cl, t0)
         caches = [self._refresh(c) for c in cl]
         view = np.array([cc[2] for cc in caches], dtype=_HTB_CLUSTER)     # the htb_cluster records
         handles = np.fromiter((cc[0] for cc in caches), dtype=np.uint64, count=n_cl)
@@ -381,7 +393,28 @@ class Engine:
         self.equiv_pairs += int(sum(int(n) * (c.sim.n - 1) for c, n in zip(cl, n_act)))
         return finished
 
-    def _step_resident(self, cl, t0):
+    def _lane_views(self):
+        """Per lane with stepping clusters: (batch, clusters, context handles,
+        eta, dt_tree, N - 1, output buffers), cached until the set changes."""
+        if self._views_gen == self._gen:
+            return self._views
+        cl = [c for c in self.clusters if not c.done and c not in self.rebuilding]
+        views = []
+        for lane, batch in enumerate(self.batches):
+            lc = [c for c in cl if c.lane == lane]
+            if not lc:
+                continue
+            n_cl = len(lc)
+            handles = np.fromiter((self._refresh(c)[0] for c in lc), dtype=np.uint64, count=n_cl)
+            eta = np.fromiter((c.sim.eta for c in lc), dtype=np.float64, count=n_cl)
+            dtt = np.fromiter((c.sim.dt_tree for c in lc), dtype=np.float64, count=n_cl)
+            nm1 = np.fromiter((c.sim.n - 1 for c in lc), dtype=np.int64, count=n_cl)
+            outs = (np.empty(n_cl), np.empty(n_cl, dtype=np.int64), np.empty(n_cl, dtype=np.uint64))
+            views.append((batch, lc, handles, eta, dtt, nm1, outs))
+        self._views, self._views_gen = views, self._gen
+        return views
+
+    def _step_resident(self, views, t0):
         """Engine step with the clusters' state on the device, lane by lane:
         one batched scheduler (and the lane's one synchronisation), one batched
         force and one batched corrector per lane; the host only plans the work.
@@ -391,43 +424,38 @@ class Engine:
         pairs = 0
         equiv = 0
         t_sync = t_plan = 0.0
-        for lane, batch in enumerate(self.batches):
-            lc = [c for c in cl if c.lane == lane]
-            if not lc:
-                continue
+        changed = False
+        for batch, lc, handles, eta, dtt, nm1, (t_next, n_act, act_ptr) in views:
             ta = time.perf_counter()
             n_cl = len(lc)
-            caches = [self._refresh(c) for c in lc]
-            handles = np.fromiter((cc[0] for cc in caches), dtype=np.uint64, count=n_cl)
-            t_next = np.empty(n_cl)
-            n_act = np.empty(n_cl, dtype=np.int64)
-            act_ptr = np.empty(n_cl, dtype=np.uint64)
             batch.dev_next_block_raw(n_cl, handles.ctypes.data, t_next.ctypes.data, n_act.ctypes.data,
                                      act_ptr.ctypes.data)
             tb = time.perf_counter()
-            eta = np.fromiter((c.sim.eta for c in lc), dtype=np.float64, count=n_cl)
-            dtt = np.fromiter((c.sim.dt_tree for c in lc), dtype=np.float64, count=n_cl)
             batch.dev_step_raw(n_cl, handles.ctypes.data, eta.ctypes.data, dtt.ctypes.data)
             pairs += batch.last_stats()[0]
             tc = time.perf_counter()
-            for k, c in enumerate(lc):
+            equiv += int(np.dot(n_act, nm1))
+            for c, t, n in zip(lc, t_next.tolist(), n_act.tolist()):
                 sim = c.sim
-                n = int(n_act[k])
-                sim.t = float(t_next[k])
+                sim.t = t
                 sim.n_block_steps += 1
                 sim.n_particle_steps += n
                 c.steps_done += 1
                 c.active_sum += n
-                equiv += n * (sim.n - 1)
-                if math.fmod(sim.t, sim.dt_tree) == 0.0:      # tree time: state back, rebuild, state up
-                    if self.pool is not None:
-                        self.rebuilding[c] = self.pool.submit(sim.rebuild_resident)
-                    else:
-                        sim.rebuild_resident()
-                if c.done:
+                if c.steps_done >= c.spec.steps:
                     finished.append(c)
+                    changed = True
+            for k in np.flatnonzero(np.fmod(t_next, dtt) == 0.0).tolist():   # tree time: rebuild
+                c = lc[k]
+                changed = True
+                if self.pool is not None:
+                    self.rebuilding[c] = self.pool.submit(c.sim.rebuild_resident)
+                else:
+                    c.sim.rebuild_resident()
             t_sync += tb - ta
             t_plan += tc - tb
+        if changed:
+            self._gen += 1
         t3 = time.perf_counter()
         dt = t3 - t0
         self.phase["host_begin"] += t_sync      # scheduler launches and the lanes' synchronisations
@@ -440,7 +468,7 @@ class Engine:
         self.step_ms.append(1e3 * dt)
         self.wall += dt
         self.pairs += pairs
-        self.equiv_pairs += int(equiv)
+        self.equiv_pairs += equiv
         return finished
 
     def drain(self):
@@ -451,6 +479,7 @@ class Engine:
         if c in self.rebuilding:
             self.rebuilding.pop(c).result()
         self.clusters.remove(c)
+        self._gen += 1
 
     def close(self):
         self.drain()
