@@ -825,6 +825,7 @@ __global__ __launch_bounds__(kWG) void sched_write_kernel(SchedEntry e0, const S
     int b;
     const SchedEntry& e = sched_entry(e0, tab, n_tab, b);
     if (e.halt && *e.halt) return;
+    if (e.bcount[b] == 0 && b != e.nb - 1) return;   // nothing due here (the last block reports the count)
     double v = HUGE_VAL;
     for (int k = threadIdx.x; k < e.nb; k += kWG) v = fmin(v, e.bmin[k]);
     const double t_next = block_min(v, red);
@@ -836,21 +837,33 @@ __global__ __launch_bounds__(kWG) void sched_write_kernel(SchedEntry e0, const S
     __syncthreads();
     int64_t pos = part[0] + part[1] + part[2] + part[3];
     const int64_t lo = b * e.chunk, hi = lo + e.chunk < e.n ? lo + e.chunk : e.n;
-    for (int64_t base = lo; base < hi; base += kWG) {
-        const int64_t i = base + threadIdx.x;
-        const bool due = i < hi && e.t0[i] + e.dt[i] == t_next;
-        const uint64_t mask = __ballot(due);
-        const int below = __popcll(mask & ((1ull << lane) - 1ull));
-        __syncthreads();
-        if (lane == 0) wsum[wave] = __popcll(mask);
-        __syncthreads();
-        int64_t at = pos + below;
-        for (int w = 0; w < wave; ++w) at += wsum[w];
-        if (due) {
-            e.active[at] = static_cast<int32_t>(i);
-            if (e.active_host) e.active_host[at] = static_cast<int32_t>(i);
+    constexpr int kAhead = 4;   // rounds of due tests loaded together, then written in order
+    for (int64_t base0 = lo; base0 < hi; base0 += kAhead * kWG) {
+        bool dues[kAhead];
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u) {
+            const int64_t i = base0 + u * kWG + threadIdx.x;
+            dues[u] = i < hi && e.t0[i] + e.dt[i] == t_next;
         }
-        pos += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u) {
+            const int64_t base = base0 + u * kWG;
+            if (base >= hi) break;
+            const int64_t i = base + threadIdx.x;
+            const bool due = dues[u];
+            const uint64_t mask = __ballot(due);
+            const int below = __popcll(mask & ((1ull << lane) - 1ull));
+            __syncthreads();
+            if (lane == 0) wsum[wave] = __popcll(mask);
+            __syncthreads();
+            int64_t at = pos + below;
+            for (int w = 0; w < wave; ++w) at += wsum[w];
+            if (due) {
+                e.active[at] = static_cast<int32_t>(i);
+                if (e.active_host) e.active_host[at] = static_cast<int32_t>(i);
+            }
+            pos += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        }
     }
     if (b == e.nb - 1 && threadIdx.x == 0) e.out->n_active = pos;
 }
@@ -1070,8 +1083,7 @@ struct PlanArgs {
     const int32_t* active;     // this step's active particles, ascending (the scheduler's list)
     const int32_t* pgroup;     // [N] group of every particle
     const int64_t* loff;       // [groups + 1] list offsets
-    int32_t* gk;               // scratch: group of each active particle
-    int32_t* qmap;             // out: split tile of each active position or -1 (may alias gk)
+    int32_t* qmap;             // out: split tile of each active position or -1
     int32_t* qk;               // scratch: first active position of each active group, then n_active
     int32_t* qg;               // scratch: group of each active group
     DTile* tiles;              // scratch
@@ -1117,8 +1129,15 @@ __global__ __launch_bounds__(kPlanWG) void dev_plan_kernel(PlanArgs A) {
     __shared__ int64_t s_w64[kPlanWG / 64];
     __shared__ double s_wd[kPlanWG / 64];
     __shared__ int8_t s_ft[260];   // the tile table, indexed per thread
+    // up to kPlanWG active particles (the common small step): the active groups and
+    // the tiles stay in LDS instead of going through memory between the phases
+    __shared__ int32_t s_qk[kPlanWG + 1], s_qg[kPlanWG];
+    __shared__ DTile s_tiles[kPlanWG];
+    __shared__ int32_t s_g[kPlanWG];
+    __shared__ int32_t s_glast;
     const int t = threadIdx.x;
     if (t < 257) s_ft[t] = A.first_tile[t];
+    if (t == 0) s_glast = -1;
     DevLoop* L = A.loop;
     if (t == 0) loop_gate(L, A.dout);   // take this step or stop the loop
     __syncthreads();
@@ -1130,23 +1149,30 @@ __global__ __launch_bounds__(kPlanWG) void dev_plan_kernel(PlanArgs A) {
         return;
     }
     const int64_t n = L->n_corr;
-    // 1. the group of every active particle
-    for (int64_t k = t; k < n; k += kPlanWG) A.gk[k] = A.pgroup[A.active[k]];
-    __syncthreads();
-    // 2. active groups: first active position and group, in order
+    const bool small = n <= kPlanWG;
+    int32_t* QK = small ? s_qk : A.qk;
+    int32_t* QG = small ? s_qg : A.qg;
+    DTile* TL = small ? s_tiles : A.tiles;
+    // 1-2. the group of every active particle, and the active groups (first active
+    // position and group, in order); a particle's predecessor's group comes through LDS
     int64_t nq = 0;
     for (int64_t base = 0; base < n; base += kPlanWG) {
         const int64_t k = base + t;
-        const int64_t f = (k < n && (k == 0 || A.gk[k] != A.gk[k - 1])) ? 1 : 0;
+        const int32_t g = k < n ? A.pgroup[A.active[k]] : -1;
+        s_g[t] = g;
+        __syncthreads();
+        const int32_t gp = t > 0 ? s_g[t - 1] : s_glast;
+        const int64_t f = (k < n && (k == 0 || g != gp)) ? 1 : 0;
         int64_t ex;
         const int64_t tot = plan_scan<int64_t>(f, &ex, s_w64);
         if (f) {
-            A.qk[nq + ex] = static_cast<int32_t>(k);
-            A.qg[nq + ex] = A.gk[k];
+            QK[nq + ex] = static_cast<int32_t>(k);
+            QG[nq + ex] = g;
         }
+        if (t == kPlanWG - 1) s_glast = g;
         nq += tot;
     }
-    if (t == 0) A.qk[nq] = static_cast<int32_t>(n);
+    if (t == 0) QK[nq] = static_cast<int32_t>(n);
     __syncthreads();
     // 3. tiles: the least-cost cover of each group's active particles
     int64_t ntile = 0;
@@ -1156,7 +1182,7 @@ __global__ __launch_bounds__(kPlanWG) void dev_plan_kernel(PlanArgs A) {
         const int64_t q = base + t;
         int64_t cnt = 0;
         if (q < nq)
-            for (int64_t r = A.qk[q + 1] - A.qk[q]; r > 0;) {
+            for (int64_t r = QK[q + 1] - QK[q]; r > 0;) {
                 const int tl = r >= 256 ? 8 : s_ft[r];
                 r -= r < (int64_t(1) << tl) ? r : (int64_t(1) << tl);
                 ++cnt;
@@ -1164,16 +1190,16 @@ __global__ __launch_bounds__(kPlanWG) void dev_plan_kernel(PlanArgs A) {
         int64_t ex;
         const int64_t tot = plan_scan<int64_t>(cnt, &ex, s_w64);
         if (q < nq) {
-            const int32_t g = A.qg[q];
+            const int32_t g = QG[q];
             const int64_t jb = A.loff[g], je = A.loff[g + 1];
             const int64_t rounds = (je - jb + kRound - 1) / kRound;
             int64_t at = ntile + ex;
-            int64_t tb = A.qk[q];
-            for (int64_t r = A.qk[q + 1] - A.qk[q]; r > 0; ++at) {
+            int64_t tb = QK[q];
+            for (int64_t r = QK[q + 1] - QK[q]; r > 0; ++at) {
                 const int tl = r >= 256 ? 8 : s_ft[r];
                 const int64_t ni = r < (int64_t(1) << tl) ? r : (int64_t(1) << tl);
                 const double cost = static_cast<double>(rounds) * (A.gather_cost + static_cast<double>(1 << tl));
-                A.tiles[at] = DTile{jb, je, static_cast<int32_t>(tb), static_cast<int32_t>(ni), tl, 0, cost};
+                TL[at] = DTile{jb, je, static_cast<int32_t>(tb), static_cast<int32_t>(ni), tl, 0, cost};
                 total += cost;
                 pairs += ni * (je - jb);
                 tb += ni;
@@ -1196,7 +1222,7 @@ __global__ __launch_bounds__(kPlanWG) void dev_plan_kernel(PlanArgs A) {
     for (;; ++attempt) {
         int64_t ci = 0, cp = 0;
         for (int64_t q = t; q < ntile; q += kPlanWG) {
-            const DTile T = A.tiles[q];
+            const DTile T = TL[q];
             const int64_t rsz = int64_t(kRound) * round_mult(1 << T.tl);
             const int64_t rounds = (T.je - T.jb + rsz - 1) / rsz;
             int64_t ns = (attempt > 60 || !(quantum > 0.0)) ? 1 : static_cast<int64_t>(ceil(T.cost / quantum));
@@ -1236,7 +1262,7 @@ __global__ __launch_bounds__(kPlanWG) void dev_plan_kernel(PlanArgs A) {
         int64_t ci = 0, cp = 0, cr = 0, ns = 1, per = 0, nsu = 1;
         DTile T{};
         if (q < ntile) {
-            T = A.tiles[q];
+            T = TL[q];
             const int64_t rsz = int64_t(kRound) * round_mult(1 << T.tl);
             const int64_t rounds = (T.je - T.jb + rsz - 1) / rsz;
             ns = (attempt > 60 || !(quantum > 0.0)) ? 1 : static_cast<int64_t>(ceil(T.cost / quantum));
@@ -2613,7 +2639,6 @@ int build_loop_graph(ht_ctx* c) {
     pa.active = c->ds.active;
     pa.pgroup = c->d_pgroup;
     pa.loff = c->d_loff;
-    pa.gk = c->d_gk;
     pa.qk = c->d_qk;
     pa.qg = c->d_qg;
     pa.tiles = c->d_tiles;
