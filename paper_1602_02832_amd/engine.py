@@ -71,6 +71,7 @@ class Cluster:
     def __init__(self, spec: RunSpec, precision: str, stream, device: int = 0, list_headroom: float = 1.5,
                  resident: bool = False, tree=None, tree_lock=None):
         self.spec, self.precision, self.stream, self.device = spec, precision, stream, device
+        self.lane = 0            # the engine lane whose stream `stream` is (set by Engine.new_cluster)
         self.resident = resident
         # a shared device tree builder for rebuilds on the device (resident runs it fits)
         self.tree, self.tree_lock = tree, tree_lock
