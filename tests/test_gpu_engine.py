@@ -188,3 +188,17 @@ def test_resident_engine_lanes_give_the_same_bits():
             assert np.array_equal(one[k][f], three[k][f]), (k, f)
     with pytest.raises(ValueError):
         E.Engine(lanes=2)              # lanes need the resident engine
+
+
+@pytest.mark.parametrize("resident", [True, False], ids=["resident", "host"])
+def test_engine_many_clusters_alone_equals_in_batch(resident):
+    """Ten clusters in one batch give each cluster the bits it gets alone."""
+    say(f"engine: ten clusters, resident={resident}")
+    sizes = (300, 420, 510, 640, 380, 700, 450, 560, 330, 610)
+    specs = [E.RunSpec(key=k, n=n, seed=800 + k, steps=25, n_crit=32) for k, n in enumerate(sizes)]
+    together, (_, _, done) = run_engine(specs, resident=resident)
+    assert done == [25] * len(specs)
+    for k in (0, 3, 9):
+        alone, _ = run_engine([specs[k]], resident=resident)
+        for f in FIELDS:
+            assert np.array_equal(alone[0][f], together[k][f]), (k, f)
