@@ -1,0 +1,31 @@
+"""Host-side parts of bench.py that run without a GPU: the one-GPU contract and
+argument parsing."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.mark.parametrize("argv,env", [(["--gpus", "2"], {}), (["--gpus", "8"], {}), ([], {"WORLD_SIZE": "2"})],
+                         ids=["gpus2", "gpus8", "world_size2"])
+def test_more_than_one_gpu_exits_with_a_message(argv, env):
+    """There is no multi-GPU path: asked for one, bench.py says so and exits
+    before it touches a device."""
+    e = dict(os.environ, **env)
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *argv], env=e, capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_parse_tuning():
+    assert bench.parse_tuning("12,1024") == (12.0, 1024.0)
+    assert bench.parse_tuning("8.5, 256") == (8.5, 256.0)
+    with pytest.raises(ValueError):
+        bench.parse_tuning("12")
