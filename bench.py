@@ -50,8 +50,8 @@ METRIC_ENSEMBLE = "batched ensemble (64 Plummer clusters, N 4096-65536): Hermite
 # only for the kernel source it was taken on: any change to it makes the
 # figure null until the counters are taken again.
 TRAFFIC = {
-    "kernel_source_sha256": "69c1b104f411210806f9ea97e313e6a6f91b6bf4c349af25bb82cf994a5d092c",
-    "fetch_bytes_per_launch": 1.447e8,     # FETCH_SIZE 70660.7 KiB x 2.000
+    "kernel_source_sha256": "d05622ed237002b6ab9170233ffafc50d63804ad1cd6a6c78b72fd064732fe00",
+    "fetch_bytes_per_launch": 1.448e8,     # FETCH_SIZE 70685.2 KiB x 2.000
     "write_bytes_per_launch": 5.466e5,     # WRITE_SIZE 533.8 KiB x 1.000
     "fetch_scale": 2.000,                  # 1 GiB read by a plain copy reads 524300 KiB
     "write_scale": 1.000,                  # 1 GiB written reads 1048576 KiB

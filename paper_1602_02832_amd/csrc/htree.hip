@@ -3066,9 +3066,11 @@ namespace {
 
 // The batched force launch; `extra` (extra_bytes) is appended to the packed
 // plan and reaches the device with it, at *extra_dev.
+// own_lists: the active lists are the contexts' own scheduler results (ascending
+// and in range by construction), so only their sizes are checked, as dev_step does.
 int batch_force(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs, const int32_t* n_active, const int32_t* const* ids,
                 double* const* d_acc, double* const* d_jerk, double* const* d_pot, const void* extra,
-                size_t extra_bytes, char** extra_dev) {
+                size_t extra_bytes, char** extra_dev, bool own_lists = false) {
     if (!b) return fail(HT_EINVAL, "batch is NULL");
     if (n_ctx < 0 || n_ctx > b->max_clusters) return fail(HT_EINVAL, "n_ctx = %d outside [0, %d]", n_ctx, b->max_clusters);
     b->last_pairs = 0;
@@ -3082,8 +3084,14 @@ int batch_force(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs, const int32_t* 
         if (rc) return rc;
         if (!c->have_particles || !c->have_lists) return fail(HT_ESTATE, "ctx %d: lists not set", k);
         if (!c->predicted) return fail(HT_ESTATE, "ctx %d: not predicted", k);
-        rc = validate_active(c, n_active[k], ids[k]);
-        if (rc) return rc;
+        if (own_lists) {
+            if (n_active[k] < 0 || n_active[k] > c->cfg.active_max || (n_active[k] > 0 && !ids[k]))
+                return fail(HT_ERANGE, "ctx %d: active list of %d outside the capacity %d", k, n_active[k],
+                            c->cfg.active_max);
+        } else {
+            rc = validate_active(c, n_active[k], ids[k]);
+            if (rc) return rc;
+        }
         if (n_active[k] > 0 && (!d_acc[k] || !d_jerk[k] || !d_pot[k])) return fail(HT_EINVAL, "ctx %d: NULL output", k);
         act_total += n_active[k];
     }
@@ -3231,7 +3239,7 @@ int ht_batch_dev_step(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs, const dou
     }
     char* d_corr = nullptr;
     int rc = batch_force(b, n_ctx, ctxs, n_act.data(), ids.data(), acc.data(), jerk.data(), pot.data(), corr.data(),
-                         corr.size() * sizeof(CorrEntry), &d_corr);
+                         corr.size() * sizeof(CorrEntry), &d_corr, true);
     if (rc) return rc;
     rc = launch_correct(ctxs[0]->cfg.precision, b->stream, corr[0], reinterpret_cast<const CorrEntry*>(d_corr), n_ctx,
                         rows);
