@@ -176,3 +176,47 @@ def test_device_loop_equals_step_by_step(name, t_end):
         assert np.array_equal(getattr(sims[0], f), getattr(sims[1], f)), f
     for s in sims:
         s.close()
+
+
+def test_device_loop_step_cap_stop_time_and_arguments():
+    """ht_dev_run's contract: at most max_steps steps per call (chunks of 3 and
+    4 give the bits of 7 single steps), the loop ends after the step at t_stop,
+    and bad arguments are refused with the state left usable."""
+    c = W.config("plummer2k")
+    x, v, m = W.make_initial_conditions(c)
+    say("device loop: step cap, stop time, arguments")
+    mk = lambda: driver.Simulation(x, v, m, eps2=c.eps2, dt_tree=c.dt_tree, eta=c.eta, theta=c.theta,
+                                   n_crit=c.n_crit, precision="mixed", resident=True, device_tree=True)
+    single, chunked, stopped = mk(), mk(), mk()
+    times = []
+    for _ in range(7):
+        tn, _ = single.step()
+        times.append(tn)
+    assert times[-1] < c.dt_tree                      # all seven before the first tree time
+    far = c.dt_tree - 2.0**-41
+    k1, t1, _ = chunked.ctx.dev_run(c.eta, c.dt_tree, far, 3)
+    k2, t2, _ = chunked.ctx.dev_run(c.eta, c.dt_tree, far, 4)
+    assert (k1, k2) == (3, 4) and (t1, t2) == (times[2], times[6])
+    # the stop time: the loop takes the step at t_stop and stops before the next block time
+    k3, t3, _ = stopped.ctx.dev_run(c.eta, c.dt_tree, times[4], 1000)
+    assert (k3, t3) == (5, times[4])
+    # refused calls: nothing runs, and the next good call carries on where the state is
+    for args in ((-1.0, c.dt_tree, far, 4), (c.eta, 0.0, far, 4), (c.eta, c.dt_tree, float("nan"), 4),
+                 (c.eta, c.dt_tree, far, 0)):
+        with pytest.raises(B.HTError) as err:
+            stopped.ctx.dev_run(*args)
+        assert err.value.code == -1
+    stopped.ctx.set_tuning(12.5, 2048)                 # the device planner needs a whole-number gather cost
+    with pytest.raises(B.HTError):
+        stopped.ctx.dev_run(c.eta, c.dt_tree, far, 4)
+    stopped.ctx.set_tuning(12, 2048)
+    k4, t4, _ = stopped.ctx.dev_run(c.eta, c.dt_tree, far, 2)
+    assert (k4, t4) == (2, times[6])
+    chunked.sync_state()
+    stopped.sync_state()
+    single.sync_state()
+    for s in (chunked, stopped):
+        for f in FIELDS:
+            assert np.array_equal(getattr(s, f), getattr(single, f)), f
+    for s in (single, chunked, stopped):
+        s.close()
