@@ -392,6 +392,29 @@ def test_tree_force_approaches_direct(oracle):
     assert errs[0] < 1e-2 and errs[2] < errs[1] < errs[0], errs
 
 
+# ----------------------------------------------------------------------------- predictor
+def test_predictor_exact_on_cubic_orbits(oracle):
+    """The predictor is the Taylor series to the jerk: on a cubic trajectory
+    (constant jerk) it is exact, so x and v match the cubic evaluated in
+    rational arithmetic to rounding, for individual t0 and any t - t0."""
+    rng = np.random.default_rng(29)
+    n = 40
+    X0, V0, A0, J0 = rng.normal(size=(4, n, 3))
+    t0 = rng.integers(0, 64, n) / 64.0
+    t = 1.25
+    xp, vp = oracle.predict(t, t0, X0, V0, A0, J0)
+    F = Fraction
+    for i in range(n):
+        d = F(t) - F(float(t0[i]))
+        for k in range(3):
+            x = F(X0[i, k]) + F(V0[i, k]) * d + F(A0[i, k]) * d**2 / 2 + F(J0[i, k]) * d**3 / 6
+            v = F(V0[i, k]) + F(A0[i, k]) * d + F(J0[i, k]) * d**2 / 2
+            scale_x = abs(F(X0[i, k])) + abs(F(V0[i, k]) * d) + abs(F(A0[i, k]) * d**2 / 2) + abs(F(J0[i, k]) * d**3 / 6)
+            scale_v = abs(F(V0[i, k])) + abs(F(A0[i, k]) * d) + abs(F(J0[i, k]) * d**2 / 2)
+            assert abs(xp[i, k] - float(x)) <= 8e-16 * float(scale_x), (i, k)
+            assert abs(vp[i, k] - float(v)) <= 8e-16 * float(scale_v), (i, k)
+
+
 # ----------------------------------------------------------------------------- corrector / timestep
 def test_corrector_exact_on_quintic_orbit(oracle):
     """For a(t) cubic the Hermite interpolant is exact: the corrected x, v
