@@ -246,6 +246,76 @@ def test_groups_cover_and_sizes(oracle, tree2k):
     assert np.diff(gf).max() <= tr.n_crit
 
 
+def _cube_ids(x, lo, side, level):
+    """Integer id of every particle's cube at a tree level, from the root cube
+    alone (no keys, no tree): the level-L cube holds the points whose integer
+    coordinates agree in their top L of 21 bits."""
+    q = np.clip(np.floor((x - lo) * (2.0**21 / side)), 0, 2**21 - 1).astype(np.int64) >> (21 - level)
+    return (q[:, 0] << 42) | (q[:, 1] << 21) | q[:, 2]
+
+
+def _group_rule_inputs():
+    rng = np.random.default_rng(21)
+    x2k, _, _ = W.plummer(2048, 1)
+    out = [("plummer2k", x2k, 1, 64)]
+    # n_crit equal to the size of an actual cell, so that a cell of exactly
+    # n_crit particles exists and must be a group (<= versus < tells here)
+    lo, side = numpy_root_box(x2k)
+    for level, pick in ((3, 0), (4, 1), (5, 2)):
+        ids = _cube_ids(x2k, lo, side, level)
+        _, cnt = np.unique(ids, return_counts=True)
+        cand = np.sort(cnt[(cnt >= 8) & (cnt <= 400)])
+        out.append((f"plummer2k_ncrit_cell_L{level}", x2k, 1, int(cand[len(cand) * (pick + 1) // 4])))
+    # a pile of coincident points larger than n_crit: a group that cannot split
+    xc = rng.normal(size=(300, 3))
+    xc[:40] = xc[40]
+    out.append(("coincident_pile", xc, 1, 8))
+    out.append(("coincident_pile_leaf3", xc, 3, 8))
+    out.append(("leaf_above_ncrit", rng.normal(size=(500, 3)), 6, 4))
+    return out
+
+
+@pytest.mark.parametrize("name,x,n_leaf,n_crit", _group_rule_inputs(), ids=[c[0] for c in _group_rule_inputs()])
+def test_groups_follow_the_barnes_rule(oracle, name, x, n_leaf, n_crit):
+    """Groups (Section 2, the modified tree algorithm after Barnes 1990) are
+    the first cells on each path from the root that hold at most n_crit
+    particles or cannot be split, checked on cells found by brute force from
+    the integer coordinates: every group's members are exactly one cell's; every
+    strictly larger cell containing it holds more than n_crit particles and can
+    be split (so it is not a group); and a group holds more than n_crit
+    particles only when it cannot split (at most n_leaf particles, or points
+    that share the finest cell)."""
+    n = x.shape[0]
+    z = np.zeros_like(x)
+    tr = oracle.Tree(x, z, z, z, np.full(n, 1.0 / n), n_leaf, n_crit, 0.5)
+    lo, side = numpy_root_box(x)
+    assert np.array_equal(lo, tr.lo) and side == tr.side
+    levels = [_cube_ids(x, lo, side, L) for L in range(22)]
+    counts = []
+    for ids in levels:
+        u, inv, cnt = np.unique(ids, return_inverse=True, return_counts=True)
+        counts.append(cnt[inv])           # size of every particle's cell at this level
+    gf = tr.group_first
+    assert gf[0] == 0 and gf[-1] == n and np.all(np.diff(gf) > 0)
+    sizes = np.diff(gf)
+    for g in range(tr.n_group):
+        members = tr.perm[gf[g]:gf[g + 1]]
+        k0, size = members[0], members.size
+        chain = [L for L in range(22)
+                 if counts[L][k0] == size and np.all(levels[L][members] == levels[L][k0])]
+        assert chain, (name, g, "not a cell")
+        assert chain == list(range(chain[0], chain[-1] + 1))
+        for L in range(chain[0]):         # every strictly larger cell on the path
+            c = counts[L][k0]
+            assert c > size and c > n_crit and c > n_leaf, (name, g, L, c)
+        if size > n_crit:
+            assert size <= n_leaf or chain[-1] == 21, (name, g, size)
+    if name.startswith("plummer2k_ncrit_cell"):
+        assert np.any(sizes == n_crit), (name, n_crit)
+    if name.startswith("coincident_pile"):
+        assert np.any(sizes >= 41)
+
+
 def _mac_accepts(tr, nd, blo, bhi):
     X = tr.node_x[nd]
     gap = np.maximum(np.maximum(blo - X, X - bhi), 0.0)
@@ -529,3 +599,37 @@ def test_table1_list_length_ballpark(oracle):
         assert 1.4 < ours[(N, 0.3)] / ours[(N, 0.5)] < 2.6
     for th in (0.75, 0.5, 0.3):
         assert 1.0 < ours[(262144, th)] / ours[(65536, th)] < 1.5
+
+
+@pytest.mark.slow
+def test_table1_active_per_group_ballpark(oracle):
+    """Mean number of active particles per group per block step, n_i (Table 1),
+    from the oracle's own integration over one tree interval at Table 1's
+    parameters (equal-mass Plummer, N = 65536, n_crit = 4000, eta = 0.01,
+    eps = 1/N, dt_tree = 1/64): groups with no active particle in a block step
+    do not count.  The paper prints 28.6-29.3 for every theta and N; our value
+    is about 1.8 times larger (groups and block steps follow readings the
+    paper does not fix), so the pin is the magnitude (within a factor 2) and
+    that n_i does not depend on theta (the paper's rows agree within 3%;
+    the opening angle changes neither the groups nor, to rounding, the block
+    steps)."""
+    tab = json.load(open(os.path.join(GOLDEN, "table1.json")))
+    N = 65536
+    x, v, m = W.plummer(N, 11)
+    got = {}
+    for th in (0.75, 0.5):
+        tally = [0, 0]
+
+        def hook(sim, rec):
+            g = np.searchsorted(sim.tree.group_first, rec["active"], side="right") - 1
+            tally[0] += rec["active"].size
+            tally[1] += np.unique(g).size
+
+        sim = oracle.TreeHermite(x, v, m, eps2=(1.0 / N) ** 2, dt_tree=1.0 / 64, eta=0.01, theta=th,
+                                 n_crit=tab["n_crit"], on_step=hook)
+        sim.run(1.0 / 64)
+        got[th] = tally[0] / tally[1]
+    paper = {th: ni for n_, th, _, ni, *_ in tab["rows"] if n_ == N}
+    for th, ni in got.items():
+        assert 0.5 < ni / paper[th] < 2.0, (th, ni, paper[th])
+    assert abs(got[0.75] / got[0.5] - 1.0) < 0.05, got
