@@ -1,16 +1,17 @@
 """Batched engine and continuous-batching server on the GPU.
 
 Work plans are made per cluster, so every cluster must come out bit-identical
-whether it runs alone or in a batch with others; the per-cluster forces are
-checked against the oracle in test_gpu_parity.py."""
-import sys
-
+whether it runs alone or in a batch with others.  The batched forces are also
+checked against the FP64 oracle directly: the batched launch on set states,
+and engine steps (host-driven, resident, and inside the served stream) whose
+active particles' new accelerations, jerks and potentials are the step's
+forces, recomputed by the oracle from the state before the step."""
 import numpy as np
 import pytest
-
 from paper_1602_02832_amd import binding as B
 from paper_1602_02832_amd import engine as E
 from paper_1602_02832_amd import workloads as W
+from parity_util import assert_close, oracle_list_force
 
 pytestmark = pytest.mark.gpu
 
@@ -19,7 +20,46 @@ FIELDS = ("x", "v", "a", "j", "t0", "dt", "pot")
 
 def say(msg):
     print(msg, flush=True)
-    sys.stdout.flush()
+
+
+def snapshot(c):
+    """A cluster's state in its current particle order, and its tree."""
+    sim = c.sim
+    sim.sync_state()
+    return dict(t0=sim.t0.copy(), dt=sim.dt.copy(), x=sim.x.copy(), v=sim.v.copy(), a=sim.a.copy(),
+                j=sim.j.copy(), m=sim.m.copy(), tree=sim.tree, t_tree=sim.t_tree, eps2=sim.eps2,
+                dt_tree=sim.dt_tree)
+
+
+def oracle_checked_step(eng, oracle, tag, step=None):
+    """One engine step (``step``, default eng.step); every stepping cluster
+    whose block time is not a tree time (a rebuild reorders the state) has the
+    new a, jerk and pot of its active particles compared with the oracle's
+    list force on the state before the step.  Returns (clusters checked, the
+    step's finished clusters)."""
+    eng.drain()
+    before = {id(c): snapshot(c) for c in eng.clusters if not c.done}
+    finished = (step or eng.step)()
+    eng.drain()
+    checked = 0
+    for c in eng.clusters:
+        b = before.get(id(c))
+        if b is None:
+            continue
+        t = float(np.min(b["t0"] + b["dt"]))
+        if np.fmod(t, b["dt_tree"]) == 0.0:
+            continue
+        sim = c.sim
+        sim.sync_state()
+        act = np.flatnonzero(sim.t0 != b["t0"]).astype(np.int32)
+        assert act.size > 0 and np.all(sim.t0[act] == t)
+        assert np.array_equal(act, np.flatnonzero(b["t0"] + b["dt"] == t))
+        want = oracle_list_force(oracle, t, act, b["t0"], b["m"], b["x"], b["v"], b["a"], b["j"], b["tree"],
+                                 b["eps2"], t_tree=b["t_tree"])
+        assert_close(f"{tag}: cluster {c.spec.key} t={t} ({act.size} active)", "mixed",
+                     (sim.a[act], sim.j[act], sim.pot[act]), want)
+        checked += 1
+    return checked, finished
 
 
 def state(sim):
@@ -49,13 +89,14 @@ def test_batch_update_and_force_equal_per_context(oracle):
     say("ht_batch update + force vs per-context calls")
     s = torch.cuda.Stream()
     batch = B.Batch(stream=s.cuda_stream, max_clusters=8, max_items=1 << 15, max_active=1 << 15, max_rows=1 << 15)
-    ctx_b, ctx_a, rows_l, act_l = [], [], [], []
+    ctx_b, ctx_a, rows_l, act_l, states = [], [], [], [], []
     for k, n in enumerate((700, 2000, 64)):
         x, v, m = W.plummer(n, 90 + k)
         z = np.zeros((n, 3))
         tr = B.HostTree(x, v, z, z, m, 1, 64, 0.5)
         x, v, m = x[tr.perm], v[tr.perm], m[tr.perm]
         t0, a, j = W.random_block_state(n, 95 + k, 0.125)
+        states.append((t0, m, x, v, a, j, tr))
         pair = []
         for _ in range(2):
             c = B.Context(n_max=n, node_max=2 * n, group_max=n, list_max=2 * tr.n_entries + 64, active_max=n,
@@ -84,8 +125,42 @@ def test_batch_update_and_force_equal_per_context(oracle):
         want = c.force(a)
         for p, q in zip(want, o):
             assert np.array_equal(p, q.cpu().numpy())
+    # the batched update and force against the FP64 oracle on the updated state
+    for k, (st, r, a, o) in enumerate(zip(states, rows_l, act_l, outs)):
+        t0, m, x, v, acc0, j0, tr = (u.copy() if isinstance(u, np.ndarray) else u for u in st)
+        idx = r["idx"]
+        t0[idx], m[idx], x[idx], v[idx], acc0[idx], j0[idx] = r["t0"], r["m"], r["x"], r["v"], r["a"], r["jerk"]
+        want = oracle_list_force(oracle, 0.15625, a, t0, m, x, v, acc0, j0, tr, 1e-4)
+        assert_close(f"batched update + force, cluster {k}", "mixed", tuple(q.cpu().numpy() for q in o), want)
     with pytest.raises(B.HTError):
         batch.update_async([ctx_b[0], ctx_b[0]], [rows_l[0], rows_l[0]])
+
+
+@pytest.mark.parametrize("resident", [True, False], ids=["resident", "host"])
+def test_engine_steps_match_oracle(oracle, resident):
+    """Engine steps over a mix of clusters (one batched force launch per step)
+    checked cluster by cluster against the oracle, through a tree rebuild."""
+    say(f"engine steps vs oracle, resident={resident}")
+    specs = [E.RunSpec(key=k, n=n, seed=900 + k, steps=10**6, n_crit=64, mass_seed=(950 + k) if k % 2 else None)
+             for k, n in enumerate((500, 1800, 3300, 900))]
+    eng = E.Engine(max_clusters=8, max_active=1 << 15, max_items=1 << 15, max_rows=1 << 15, rebuild_workers=0,
+                   resident=resident)
+    for sp in specs:
+        eng.add(eng.new_cluster(sp))
+    checked = 0
+    rebuilt = False
+    for k in range(400):
+        t_tree = [c.sim.t_tree for c in eng.clusters]
+        if k % 3 == 0:
+            checked += oracle_checked_step(eng, oracle, f"engine step {k}")[0]
+        else:
+            eng.step()
+        rebuilt |= any(c.sim.t_tree != t for c, t in zip(eng.clusters, t_tree))
+        if checked >= 40 and rebuilt and k % 3 == 0:
+            break
+    eng.close()
+    say(f"engine steps vs oracle: {checked} cluster steps checked in {k + 1} engine steps")
+    assert checked >= 40 and rebuilt, (checked, rebuilt)
 
 
 def test_engine_cluster_alone_equals_in_mix():
@@ -99,7 +174,7 @@ def test_engine_cluster_alone_equals_in_mix():
             assert np.array_equal(alone[0][f], together[k][f]), (k, f)
 
 
-def test_server_admission_respects_budget_and_results_match():
+def test_server_admission_respects_budget_and_results_match(oracle):
     say("server: admission under a small device-memory budget")
     specs = [E.RunSpec(key=k, n=n, seed=400 + k, steps=12, n_crit=64) for k, n in enumerate((800, 1200, 900, 2000, 700))]
     eng = E.Engine(max_clusters=8, max_active=1 << 16, max_items=1 << 16, max_rows=1 << 16)
@@ -107,12 +182,25 @@ def test_server_admission_respects_budget_and_results_match():
     budget = sizes[3] + sizes[1]                   # room for about two runs at a time
     srv = E.Server(eng, hbm_budget=budget, max_resident=8, keep_finished=True)
     reqs = [E.Request(spec=s, arrival=0.0) for s in specs]
+    # every fourth served engine step is checked against the oracle
+    srv_checked, plain_step = [0, 0], eng.step
+
+    def step():
+        srv_checked[1] += 1
+        if srv_checked[1] % 4:
+            return plain_step()
+        n, fin = oracle_checked_step(eng, oracle, f"served engine step {srv_checked[1]}", step=plain_step)
+        srv_checked[0] += n
+        return fin
+
+    eng.step = step
     done = srv.run(reqs)
     assert len(done) == len(specs)
     assert srv.max_waiting >= 2                    # admission actually held requests back
     assert srv.max_used <= budget
     assert all(r.finished >= r.admitted >= r.arrival for r in done)
     mixed = {r.spec.key: state(r.cluster.sim) for r in done}
+    assert srv_checked[0] >= 4
     for r in done:
         r.cluster.close()
     eng.close()

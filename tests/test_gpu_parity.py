@@ -9,39 +9,14 @@ Tolerances (per particle, relative to that particle's own magnitude):
   FP64 form   acc, jerk, pot <= 1e-12
   mixed form  acc <= 2e-6, jerk <= 1e-5, pot <= 1e-6
 """
-import sys
-
 import numpy as np
 import pytest
-
 from paper_1602_02832_amd import binding as B
 from paper_1602_02832_amd import workloads as W
 
+from parity_util import TOL, assert_close, errors, oracle_list_force, rel_rows, say  # noqa: F401
+
 pytestmark = pytest.mark.gpu
-
-TOL = {"fp64": (1e-12, 1e-12, 1e-12), "mixed": (2e-6, 1e-5, 1e-6)}
-
-
-def say(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
-
-
-def rel_rows(got, want):
-    got = np.asarray(got).reshape(len(want), -1)
-    want = np.asarray(want).reshape(len(want), -1)
-    return np.linalg.norm(got - want, axis=1) / np.maximum(np.linalg.norm(want, axis=1), 1e-300)
-
-
-def errors(got, want):
-    return tuple(float(rel_rows(g, w).max()) if len(w) else 0.0 for g, w in zip(got, want))
-
-
-def assert_close(tag, prec, got, want):
-    ea, ej, ep = errors(got, want)
-    ta, tj, tp = TOL[prec]
-    assert ea <= ta and ej <= tj and ep <= tp, f"{tag} {prec}: acc {ea:.3g} jerk {ej:.3g} pot {ep:.3g}"
-    return ea, ej, ep
 
 
 def make_ctx(prec, n, node_max, group_max, list_max, eps2, mode="fused"):
@@ -58,6 +33,7 @@ class Replayer:
         lm = list_max or max(4 * sim.tree.n_entries, 4096)
         self.ctxs = {(p, md): make_ctx(p, n, 4 * n + 64, n, lm, sim.eps2, md) for p in precs for md in modes}
         self.tree_seen = None
+        self.pending = None
         self.worst = {k: (0.0, 0.0, 0.0) for k in self.ctxs}
         self.steps = 0
         self.sync_tree()
@@ -75,11 +51,19 @@ class Replayer:
             c.set_nodes(sim.t_tree, got.node_m, got.node_x, got.node_v, got.node_a, got.node_j)
             c.set_interaction_lists(got.group_first, got.list_off, got.entries)
         self.tree_seen = sim.tree
+        self.pending = None
 
     def hook(self, sim, rec):
         want = (rec["acc"], rec["jerk"], rec["pot"])
+        # the j-memory update of step 6: the particles the oracle corrected since
+        # the last step (a full upload follows every rebuild)
+        upd = self.pending
+        self.pending = rec["active"].copy()
         for (p, md), c in self.ctxs.items():
-            c.set_j_particles(sim.t0, sim.m, sim.x, sim.v, sim.a, sim.j)
+            if upd is None:
+                c.set_j_particles(sim.t0, sim.m, sim.x, sim.v, sim.a, sim.j)
+            else:
+                c.set_j_particles(sim.t0[upd], sim.m[upd], sim.x[upd], sim.v[upd], sim.a[upd], sim.j[upd], idx=upd)
             c.predict(rec["t"])
             got = c.force(rec["active"])
             e = assert_close(f"t={rec['t']} n_active={rec['active'].size}", p, got, want)
@@ -131,10 +115,12 @@ def test_parity_plummer2k_every_block_step(oracle):
     assert rp["r"].steps > 100 and sim.t == c.t_end
 
 
-# ------------------------------------------------------------------------------------------ C2, first tree interval
-def test_parity_plummer16k_first_tree_interval(oracle):
+# ------------------------------------------------------------------------------------------ C2, every step
+def test_parity_plummer16k_every_block_step(oracle):
+    """C2 over its whole span (t <= 1/4: 64 tree intervals, about 6200 block
+    steps): every block step of the oracle's run replayed in both forms."""
     c = W.config("plummer16k")
-    say("plummer16k first two tree intervals")
+    say(f"plummer16k every block step to t={c.t_end}")
     x, v, m = W.make_initial_conditions(c)
     rp = {}
 
@@ -144,9 +130,9 @@ def test_parity_plummer16k_first_tree_interval(oracle):
     sim = oracle.TreeHermite(x, v, m, eps2=c.eps2, dt_tree=c.dt_tree, eta=c.eta, theta=c.theta, n_crit=c.n_crit,
                              on_step=hook)
     rp["r"] = Replayer(oracle, sim, ("fp64", "mixed"))
-    rp["r"].run(2 * c.dt_tree)
+    rp["r"].run(c.t_end)
     say(f"steps {rp['r'].steps} worst {rp['r'].worst}")
-    assert rp["r"].steps > 5
+    assert sim.t == c.t_end and rp["r"].steps > 6000
 
 
 # ------------------------------------------------------------------------------------------ direct
@@ -306,6 +292,62 @@ def test_api_errors():
     assert e.value.code == -1
 
 
+@pytest.mark.parametrize("path", ["async", "step", "graph"])
+def test_device_rows_out_of_range_are_dropped_and_reported(path):
+    """Update rows whose particle indices sit in device memory are checked by
+    the kernel that writes them: rows naming an index outside [0, N) are
+    dropped, the others are written, and the next synchronising call returns
+    HT_ERANGE once.  The bad indices used here (N and N + M - 1, node
+    records) lie inside the records array, so even an unchecked write could
+    not leave the allocation."""
+    import torch
+    say(f"device update rows out of range ({path})")
+    n = 500
+    x, v, m = W.plummer(n, 7)
+    z = np.zeros((n, 3))
+    ptr = B.HostTree(x, v, z, z, m, 1, 32, 0.5)
+    x, v, m = x[ptr.perm], v[ptr.perm], m[ptr.perm]
+    t0, a, j = W.random_block_state(n, 8, 0.25)
+    ctxs = []
+    for _ in range(2):
+        c = make_ctx("mixed", n, 2 * n, n, 2 * ptr.n_entries, 1e-4)
+        c.set_j_particles(t0, m, x, v, a, j)
+        c.set_nodes(0.0, ptr.node_m, ptr.node_x, ptr.node_v, ptr.node_a, ptr.node_j)
+        c.set_interaction_lists(ptr.group_first, ptr.list_off, ptr.entries)
+        ctxs.append(c)
+    got_ctx, ref_ctx = ctxs
+    idx = np.array([3, n, 10, n + ptr.n_node - 1], dtype=np.int32)
+    good = np.array([0, 2])
+    ut0 = np.full(4, 0.25)
+    ux = x[np.minimum(idx, n - 1)] + 1e-3
+    dev = lambda u: torch.from_numpy(np.ascontiguousarray(u)).cuda()  # noqa: E731
+    upd = (4, dev(idx), dev(ut0), dev(m[:4]), dev(ux), dev(v[:4]), dev(a[:4]), dev(j[:4]))
+    act = np.array([0, 3, 10, 77], dtype=np.int32)
+    out = tuple(torch.empty(sh, dtype=torch.float64, device="cuda") for sh in ((4, 3), (4, 3), (4,)))
+    t = 0.28125
+    if path == "async":
+        got_ctx.set_j_particles_async(*upd)
+        got_ctx.predict(t)
+    elif path == "step":
+        got_ctx.step_async(upd, t, act, *out)
+    else:
+        got_ctx.step_graph(upd, t, act, *out)
+    with pytest.raises(B.HTError) as e:
+        got_ctx.sync()
+    assert e.value.code == -2
+    got_ctx.sync()                     # reported once
+    ref_ctx.set_j_particles(ut0[good], m[:4][good], ux[good], v[:4][good], a[:4][good], j[:4][good],
+                            idx=idx[good])
+    ref_ctx.predict(t)
+    probe = np.array([0, 3, 10, n - 1, n, n + ptr.n_node - 1], dtype=np.int32)
+    for p_got, p_ref in zip(got_ctx.get_predicted(probe), ref_ctx.get_predicted(probe)):
+        assert np.array_equal(p_got, p_ref)
+    if path != "async":
+        want = ref_ctx.force(act)
+        for g, w in zip(out, want):
+            assert np.array_equal(g.cpu().numpy(), w)
+
+
 # ------------------------------------------------------------------------------------------ batch
 def test_batch_equals_alone(oracle):
     """Several clusters in one launch give bit-identical results to each alone."""
@@ -316,10 +358,12 @@ def test_batch_equals_alone(oracle):
     ctxs, acts, state = [], [], []
     for k, n in enumerate(sizes):
         x, v, m = W.plummer(n, 60 + k)
+        m = W.salpeter_masses(n, 65 + k)
         z = np.zeros((n, 3))
         ptr = B.HostTree(x, v, z, z, m, 1, 64, 0.5)
         x, v, m = x[ptr.perm], v[ptr.perm], m[ptr.perm]
         t0, a, j = W.random_block_state(n, 70 + k, 0.125)
+        state.append((t0, m, x, v, a, j, ptr))
         c = B.Context(n_max=n, node_max=2 * n, group_max=n, list_max=2 * ptr.n_entries + 64, active_max=n,
                       eps2=1e-4, precision="mixed", stream=s.cuda_stream)
         c.set_j_particles(t0, m, x, v, a, j)
@@ -339,6 +383,11 @@ def test_batch_equals_alone(oracle):
         assert np.array_equal(a1, a2.cpu().numpy())
         assert np.array_equal(j1, j2.cpu().numpy())
         assert np.array_equal(p1, p2.cpu().numpy())
+    # each cluster's batched result against the FP64 oracle (unrounded inputs)
+    for k, ((t0, m, x, v, a, j, ptr), act, out) in enumerate(zip(state, acts, outs)):
+        want = oracle_list_force(oracle, 0.125, act, t0, m, x, v, a, j, ptr, 1e-4)
+        assert_close(f"batched cluster {k} (n={sizes[k]}, {act.size} active)", "mixed",
+                     tuple(o.cpu().numpy() for o in out), want)
 
 
 def test_step_async_equals_separate_calls(oracle):
