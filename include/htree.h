@@ -19,16 +19,26 @@
  *
  * Precision forms:
  *   HT_PREC_FP64  — everything in FP64.
- *   HT_PREC_MIXED — FP64 for times, positions, prediction, x_j - x_i,
- *                   s = r.r + eps^2 and the acceleration sum; FP32 for
- *                   s^-1/2, s^-3/2, velocity differences, the jerk terms and
- *                   the potential, whose FP32 partial sums are folded into
- *                   FP64 every 32 pairs.  Stored a, jerk and m are FP32.
+ *   HT_PREC_MIXED — the j-memory stores m, a and jerk in FP32 (times,
+ *                   positions and velocities in FP64); s^-1/2 starts from
+ *                   the FP32 reciprocal square root, refined by one Newton
+ *                   step in FP64 (relative error about 1e-13); prediction,
+ *                   x_j - x_i, the pair terms and every sum are FP64.  (With
+ *                   s^-3/2 and the jerk terms in FP32, particles whose jerk
+ *                   terms cancel to a few hundredths of their size missed
+ *                   the 1e-5 jerk tolerance.)
  *
  * Conventions for every entry point:
  *   - Return HT_OK (0) or a negative ht_status; ht_last_error() then holds a
  *     message for the calling thread.  Arguments are validated before any
  *     device work is queued; on error nothing is modified.
+ *   - Update rows whose particle indices sit in device memory (the *_async
+ *     updates, ht_step_async, ht_step_graph) cannot be checked before the
+ *     launch: the kernel drops every row whose index is outside [0, N),
+ *     writes the other rows, and the next call that synchronises the
+ *     context's stream (ht_sync, ht_force, ht_state_get, ht_dev_next_block,
+ *     ...) returns HT_ERANGE once for them.  Batched row updates are checked
+ *     the same way and reported by ht_batch_sync or ht_batch_dev_next_block.
  *   - Host arrays belong to the caller and are never retained after return.
  *     Vectors are row-major [n][3] doubles.
  *   - Device memory for the context is one workspace, either supplied by the

@@ -2,8 +2,8 @@
  * htree_tree — step 1 of the tree/Hermite scheme on the device (Fukushige &
  * Kawai, Section 2, step 1: the tree, the node data and the interaction
  * lists, rebuilt at every multiple of the tree interval; the paper builds them
- * on the host and its Section 5 names the tree time as the share that grows
- * when the tree interval shrinks).
+ * on the host, and its Section 3 notes that the tree time per particle step
+ * grows as the tree interval shrinks).
  *
  * The definitions are those of the host builder (include/htree_host.h) and
  * the results are bit-identical to its results: keys, particle order, node

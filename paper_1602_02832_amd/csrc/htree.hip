@@ -66,7 +66,6 @@ constexpr int kRound = 256;   // list entries staged per round and entry multipl
 // latency-bound: for T <= 8 every thread gathers two entries per round.
 __host__ __device__ constexpr int round_mult(int T) { return T <= 8 ? 2 : 1; }
 constexpr int kRoundMax = 2 * kRound;
-constexpr int kFold = 32;     // mixed form: FP32 pairs summed before folding into FP64
 constexpr int kOut = 7;       // acc[3], jerk[3], pot
 constexpr int kMaxBatch = 1024;   // clusters per batched launch
 
@@ -93,8 +92,9 @@ struct alignas(64) PRecFp64 {
 };
 struct alignas(64) PRecMixed {
     double x, y, z;
-    float vx, vy, vz, m;
-    double pad[3];
+    double vx, vy, vz;
+    float m, pad0;
+    double pad1;
 };
 static_assert(sizeof(RecFp64) == 128 && sizeof(RecMixed) == 128, "record size");
 static_assert(sizeof(PRecFp64) == 64 && sizeof(PRecMixed) == 64, "predicted record size");
@@ -153,24 +153,24 @@ struct PrecFp64 {
 };
 struct PrecMixed {
     using Stored = float;
-    using Vel = float;
+    using Vel = double;
     using Rec = RecMixed;
     using PRec = PRecMixed;
     static constexpr bool kMixed = true;
 };
 
-// One staged j of a round: predicted position and velocity, mass, combined
+// One staged j of a round: predicted position and velocity, mass (as
+// stored, widened to FP64 once here rather than once per pair), combined
 // index.  Records (not one array per field) so that a thread reads an entry
 // with a few 16-byte LDS loads at immediate offsets from one address.
 template <class P>
 struct alignas(16) JRec {
     double x, y, z;
     typename P::Vel vx, vy, vz;
-    typename P::Stored m;
+    double m;
     int32_t idx;
 };
-static_assert(sizeof(JRec<PrecMixed>) == 48, "mixed staged record is 48 bytes");
-static_assert(sizeof(JRec<PrecFp64>) == 64, "FP64 staged record is 64 bytes");
+static_assert(sizeof(JRec<PrecMixed>) == 64 && sizeof(JRec<PrecFp64>) == 64, "staged records are 64 bytes");
 
 template <class P>
 union LdsAll {
@@ -227,9 +227,6 @@ __device__ __forceinline__ void load_state(const Desc& c, int j, double& x, doub
 struct Acc64 {
     double v[kOut];
 };
-struct Acc32 {
-    float v[kOut];
-};
 
 __device__ __forceinline__ void pair_fp64(double xi, double yi, double zi, double vxi, double vyi, double vzi,
                                           int i, const JRec<PrecFp64>& J, double eps2, Acc64& A) {
@@ -251,37 +248,41 @@ __device__ __forceinline__ void pair_fp64(double xi, double yi, double zi, doubl
     A.v[6] -= mr;
 }
 
-// Mixed form.  FP64: x_j - x_i, s = r.r + eps^2 (FP64 FMAs run at the FP32
-// rate on this chip, and forming s in FP32 was the largest error where a
-// close neighbour's pull cancels the rest) and the acceleration sum.  FP32:
-// s^-1/2, s^-3/2, the jerk terms and the potential, summed in FP32 over a few
-// pairs and folded into FP64 by the caller.
-__device__ __forceinline__ void pair_mixed(double xi, double yi, double zi, float vxi, float vyi, float vzi,
-                                           int i, const JRec<PrecMixed>& J, double eps2, Acc64& A,
-                                           Acc32& B) {
+// Mixed form: the j-memory stores m, a and jerk in FP32 (the predictor reads
+// them), and s^-1/2 starts from the FP32 reciprocal square root (v_rsq_f32,
+// about one ulp) refined by one Newton step in FP64 in residual form
+// (e = 1 - s y^2, y += y e / 2), which leaves a relative error near 1e-13.
+// Everything else is FP64.  The jerk is a sum of terms that can cancel to a
+// few hundredths of their magnitudes; with s^-3/2 and the jerk terms in FP32
+// (a few ulp each) such particles missed the 1e-5 jerk target, so only the
+// seed is FP32.  FP64 FMAs issue at the non-packed FP32 rate on this chip.
+__device__ __forceinline__ void pair_mixed(double xi, double yi, double zi, double vxi, double vyi, double vzi,
+                                           int i, const JRec<PrecMixed>& J, double eps2, Acc64& A) {
     const double dx = J.x - xi, dy = J.y - yi, dz = J.z - zi;
-    const float s = static_cast<float>(fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2))));
-    // v_rsq_f32 is good to about one ulp; one Newton step in residual form
-    // (e = 1 - s y^2, y += y e / 2) makes it nearly correctly rounded, which
-    // the jerk sum needs where its terms cancel.
-    float rinv = __builtin_amdgcn_rsqf(s);
-    const float res = fmaf(-(s * rinv), rinv, 1.0f);
-    rinv = fmaf(0.5f * rinv, res, rinv);
-    rinv = (J.idx == i) ? 0.0f : rinv;
-    const float rinv2 = rinv * rinv;
-    const float mr = J.m * rinv;
-    const float mr3 = mr * rinv2;
-    const double mr3d = static_cast<double>(mr3);
-    A.v[0] = fma(mr3d, dx, A.v[0]);
-    A.v[1] = fma(mr3d, dy, A.v[1]);
-    A.v[2] = fma(mr3d, dz, A.v[2]);
-    const float fx = static_cast<float>(dx), fy = static_cast<float>(dy), fz = static_cast<float>(dz);
-    const float wx = J.vx - vxi, wy = J.vy - vyi, wz = J.vz - vzi;
-    const float alpha = 3.0f * fmaf(fz, wz, fmaf(fy, wy, fx * wx)) * rinv2;
-    B.v[3] = fmaf(mr3, fmaf(-alpha, fx, wx), B.v[3]);
-    B.v[4] = fmaf(mr3, fmaf(-alpha, fy, wy), B.v[4]);
-    B.v[5] = fmaf(mr3, fmaf(-alpha, fz, wz), B.v[5]);
-    B.v[6] -= mr;
+    const double s = fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2)));
+    const double y0 = static_cast<double>(__builtin_amdgcn_rsqf(static_cast<float>(s)));
+    const double e = fma(-(s * y0), y0, 1.0);
+    double rinv = fma(0.5 * y0, e, y0);
+    rinv = (J.idx == i) ? 0.0 : rinv;
+    const double rinv2 = rinv * rinv;
+    const double mr = J.m * rinv;
+    const double mr3 = mr * rinv2;
+    const double wx = J.vx - vxi, wy = J.vy - vyi, wz = J.vz - vzi;
+    const double alpha = 3.0 * fma(dz, wz, fma(dy, wy, dx * wx)) * rinv2;
+    A.v[0] = fma(mr3, dx, A.v[0]);
+    A.v[1] = fma(mr3, dy, A.v[1]);
+    A.v[2] = fma(mr3, dz, A.v[2]);
+    A.v[3] = fma(mr3, fma(-alpha, dx, wx), A.v[3]);
+    A.v[4] = fma(mr3, fma(-alpha, dy, wy), A.v[4]);
+    A.v[5] = fma(mr3, fma(-alpha, dz, wz), A.v[5]);
+    A.v[6] -= mr;
+}
+
+template <class P>
+__device__ __forceinline__ void pair(double xi, double yi, double zi, double vxi, double vyi, double vzi, int i,
+                                     const JRec<P>& J, double eps2, Acc64& A) {
+    if constexpr (P::kMixed) pair_mixed(xi, yi, zi, vxi, vyi, vzi, i, J, eps2, A);
+    else pair_fp64(xi, yi, zi, vxi, vyi, vzi, i, J, eps2, A);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -331,20 +332,6 @@ __device__ __forceinline__ void run_item(const Desc& c, const Item& it, LdsAll<P
     Acc64 A;
 #pragma unroll
     for (int q = 0; q < kOut; ++q) A.v[q] = 0.0;
-    // Mixed form: FP32 partials of the jerk and potential, folded into A
-    // every kFold pairs of this thread (across rounds when a round gives a
-    // thread fewer than kFold pairs) and at the end of the item.
-    Acc32 B;
-#pragma unroll
-    for (int q = 3; q < kOut; ++q) B.v[q] = 0.0f;
-    auto fold = [&]() {
-#pragma unroll
-        for (int q = 3; q < kOut; ++q) {
-            A.v[q] += static_cast<double>(B.v[q]);
-            B.v[q] = 0.0f;
-        }
-    };
-    int since_fold = 0;   // full rounds since the last fold (PER < kFold)
 
     for (int64_t base = it.j_begin; base < it.j_end; base += R) {
         const int64_t rest = it.j_end - base;
@@ -359,59 +346,20 @@ __device__ __forceinline__ void run_item(const Desc& c, const Item& it, LdsAll<P
                 typename P::Vel vxj, vyj, vzj;
                 typename P::Stored mj;
                 load_state<P, EAGER>(c, j, xj, yj, zj, vxj, vyj, vzj, mj);
-                lds.j[e] = JRec<P>{xj, yj, zj, vxj, vyj, vzj, mj, j};
+                lds.j[e] = JRec<P>{xj, yj, zj, vxj, vyj, vzj, static_cast<double>(mj), j};
             }
         }
         if (base + R < it.j_end) load_idx(base + R);   // in flight during this round's pairs
         __syncthreads();
-        if constexpr (P::kMixed) {
-            const double eps2 = c.eps2;
-            if (cnt == R) {
-                if constexpr (PER >= kFold) {
-#pragma unroll 1
-                    for (int f = 0; f < PER; f += kFold) {
+        const double eps2 = c.eps2;
+        if (cnt == R) {
 #pragma unroll 4
-                        for (int u = 0; u < kFold; ++u)
-                            pair_mixed(xi, yi, zi, vxi, vyi, vzi, i, lds.j[stream + (f + u) * S], eps2, A, B);
-                        fold();
-                    }
-                } else {
-#pragma unroll 4
-                    for (int u = 0; u < PER; ++u)
-                        pair_mixed(xi, yi, zi, vxi, vyi, vzi, i, lds.j[stream + u * S], eps2, A, B);
-                    if (++since_fold == kFold / PER) {
-                        fold();
-                        since_fold = 0;
-                    }
-                }
-            } else {
-                // the last, partial round of the item: at most PER pairs per thread
-                fold();
-                since_fold = 0;
-                constexpr int F = PER < kFold ? PER : kFold;
-#pragma unroll 1
-                for (int f = 0; f * S < cnt; f += F) {
-#pragma unroll 1
-                    for (int u = 0; u < F; ++u) {
-                        const int k = stream + (f + u) * S;
-                        if (k < cnt) pair_mixed(xi, yi, zi, vxi, vyi, vzi, i, lds.j[k], eps2, A, B);
-                    }
-                    fold();
-                }
-            }
+            for (int u = 0; u < PER; ++u) pair<P>(xi, yi, zi, vxi, vyi, vzi, i, lds.j[stream + u * S], eps2, A);
         } else {
-            const double eps2 = c.eps2;
-            if (cnt == R) {
-#pragma unroll 4
-                for (int u = 0; u < PER; ++u) pair_fp64(xi, yi, zi, vxi, vyi, vzi, i, lds.j[stream + u * S], eps2, A);
-            } else {
 #pragma unroll 1
-                for (int k = stream; k < cnt; k += S) pair_fp64(xi, yi, zi, vxi, vyi, vzi, i, lds.j[k], eps2, A);
-            }
+            for (int k = stream; k < cnt; k += S) pair<P>(xi, yi, zi, vxi, vyi, vzi, i, lds.j[k], eps2, A);
         }
     }
-
-    if constexpr (P::kMixed) fold();
 
     // Reduce the S j-streams of each i-slot in a fixed order, so results never
     // depend on timing.  T < 64: the 64 / T streams of a wave first, by a
@@ -609,17 +557,30 @@ __device__ __forceinline__ void store_rec(typename P::Rec* rec, int j, double t0
     rec[j] = r;
 }
 
+// An update row names a particle index that is not in [0, lim): the row is
+// dropped and the context's error word (pinned host memory, read by the host
+// after its next synchronisation) is set.  Indices that come from device
+// memory cannot be checked by the host before the launch.
+__device__ __forceinline__ bool row_index_ok(int32_t j, int32_t lim, int32_t* err) {
+    if (j >= 0 && j < lim) return true;
+    __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    return false;
+}
+
 // j-memory update (steps 1 and 6): rows [n][3] written into records.
 // idx == nullptr: row k goes to base + k.  t0 == nullptr: every t0 = t0_all.
+// idx != nullptr: rows whose index is outside [0, lim) are dropped (err set).
 template <class P>
 __global__ __launch_bounds__(kWG) void scatter_kernel(Desc dst, int n, const int32_t* idx, int base,
                                                       const double* t0, double t0_all, const double* m,
                                                       const double* x, const double* v, const double* a,
-                                                      const double* jerk) {
+                                                      const double* jerk, int32_t lim, int32_t* err) {
     typename P::Rec* rec = static_cast<typename P::Rec*>(const_cast<void*>(dst.rec));
-    for (int k = blockIdx.x * kWG + threadIdx.x; k < n; k += gridDim.x * kWG)
-        store_rec<P>(rec, idx ? idx[k] : base + k, t0 ? t0[k] : t0_all, m[k], x + 3 * k, v + 3 * k, a + 3 * k,
-                     jerk + 3 * k);
+    for (int k = blockIdx.x * kWG + threadIdx.x; k < n; k += gridDim.x * kWG) {
+        const int32_t j = idx ? idx[k] : base + k;
+        if (idx && !row_index_ok(j, lim, err)) continue;
+        store_rec<P>(rec, j, t0 ? t0[k] : t0_all, m[k], x + 3 * k, v + 3 * k, a + 3 * k, jerk + 3 * k);
+    }
 }
 
 // Resident rebuild: dt and pot in the new particle order.
@@ -658,6 +619,8 @@ struct DevRows {
     int n;
     const int32_t* idx;
     const double *t0, *m, *x, *v, *a, *jerk;
+    int32_t lim;      // valid indices are [0, lim)
+    int32_t* err;     // set when a row is dropped for its index
 };
 
 // Everything a force launch needs before it, in one launch on the compute
@@ -674,8 +637,11 @@ __global__ __launch_bounds__(kWG) void prep_kernel(PlanCopy pc, void* rec_base, 
     }
     typename P::Rec* rec = static_cast<typename P::Rec*>(rec_base);
     const int b = blockIdx.x - pc.copy_blocks, nb = gridDim.x - pc.copy_blocks;
-    for (int k = b * kWG + threadIdx.x; k < u.n; k += nb * kWG)
-        store_rec<P>(rec, u.idx[k], u.t0[k], u.m[k], u.x + 3 * k, u.v + 3 * k, u.a + 3 * k, u.jerk + 3 * k);
+    for (int k = b * kWG + threadIdx.x; k < u.n; k += nb * kWG) {
+        const int32_t j = u.idx[k];
+        if (!row_index_ok(j, u.lim, u.err)) continue;
+        store_rec<P>(rec, j, u.t0[k], u.m[k], u.x + 3 * k, u.v + 3 * k, u.a + 3 * k, u.jerk + 3 * k);
+    }
 }
 
 // Parameters of a graph-replayed step, in a pinned host slot that the host
@@ -686,15 +652,19 @@ struct GraphHdr {
     int64_t n_upd;        // update rows (device arrays below)
     const int32_t* idx;
     const double *t0, *m, *x, *v, *a, *jerk;
+    int64_t lim;          // valid update indices are [0, lim)
+    int32_t* err;         // set when a row is dropped for its index
 };
-static_assert(sizeof(GraphHdr) == 10 * 8, "GraphHdr is 10 words");
+constexpr int kGraphHdrWords = 12;
+static_assert(sizeof(GraphHdr) == kGraphHdrWords * 8, "GraphHdr is 12 words");
 
 // prep_kernel for graph replays: everything it needs comes from the header.
 template <class P>
 __global__ __launch_bounds__(kWG) void prep_graph_kernel(const GraphHdr* hdr, uint64_t* dst, void* rec_base,
                                                          int copy_blocks) {
-    __shared__ uint64_t h[10];   // the header, fetched once per work-group
-    if (threadIdx.x < 10) h[threadIdx.x] = host_word(reinterpret_cast<const uint64_t*>(hdr) + threadIdx.x);
+    __shared__ uint64_t h[kGraphHdrWords];   // the header, fetched once per work-group
+    if (threadIdx.x < kGraphHdrWords)
+        h[threadIdx.x] = host_word(reinterpret_cast<const uint64_t*>(hdr) + threadIdx.x);
     __syncthreads();
     if (static_cast<int>(blockIdx.x) < copy_blocks) {
         const int64_t n8 = static_cast<int64_t>(h[0]);
@@ -712,10 +682,15 @@ __global__ __launch_bounds__(kWG) void prep_graph_kernel(const GraphHdr* hdr, ui
     const double* v = reinterpret_cast<const double*>(h[7]);
     const double* a = reinterpret_cast<const double*>(h[8]);
     const double* jerk = reinterpret_cast<const double*>(h[9]);
+    const int32_t lim = static_cast<int32_t>(h[10]);
+    int32_t* err = reinterpret_cast<int32_t*>(h[11]);
     typename P::Rec* rec = static_cast<typename P::Rec*>(rec_base);
     const int b = blockIdx.x - copy_blocks, nb = gridDim.x - copy_blocks;
-    for (int k = b * kWG + threadIdx.x; k < n; k += nb * kWG)
-        store_rec<P>(rec, idx[k], t0[k], m[k], x + 3 * k, v + 3 * k, a + 3 * k, jerk + 3 * k);
+    for (int k = b * kWG + threadIdx.x; k < n; k += nb * kWG) {
+        const int32_t j = idx[k];
+        if (!row_index_ok(j, lim, err)) continue;
+        store_rec<P>(rec, j, t0[k], m[k], x + 3 * k, v + 3 * k, a + 3 * k, jerk + 3 * k);
+    }
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1319,7 +1294,7 @@ struct UpdEntry {
     void* rec;            // the cluster's records
     int64_t first_row;    // its first row in the launch
     const ht_row* rows;   // its rows (pinned host memory)
-    int64_t pad;
+    int64_t lim;          // its particle count: valid row indices are [0, lim)
 };
 
 __device__ __forceinline__ int find_upd(const UpdEntry* tab, int n_tab, int64_t r) {
@@ -1335,7 +1310,8 @@ __device__ __forceinline__ int find_upd(const UpdEntry* tab, int n_tab, int64_t 
 // (system-scope loads, see host_word), so an update costs one launch and no
 // device copy; every work-group keeps the table in LDS.
 template <class P>
-__global__ __launch_bounds__(kWG) void scatter_rows_kernel(const UpdEntry* __restrict__ tab, int n_tab, int64_t total) {
+__global__ __launch_bounds__(kWG) void scatter_rows_kernel(const UpdEntry* __restrict__ tab, int n_tab, int64_t total,
+                                                           int32_t* err) {
     static_assert(sizeof(ht_row) == 15 * 8, "ht_row is 15 words");
     static_assert(sizeof(UpdEntry) == 32, "UpdEntry is 4 words");
     __shared__ UpdEntry stab[kMaxBatch];
@@ -1353,6 +1329,7 @@ __global__ __launch_bounds__(kWG) void scatter_rows_kernel(const UpdEntry* __res
 #pragma unroll
         for (int q = 0; q < 14; ++q) f[q] = __builtin_bit_cast(double, raw[q + 1]);
         const int32_t idx = static_cast<int32_t>(static_cast<uint32_t>(raw[0]));
+        if (!row_index_ok(idx, static_cast<int32_t>(stab[k].lim), err)) continue;
         // f: t0, m, x[3], v[3], a[3], jerk[3]
         store_rec<P>(static_cast<typename P::Rec*>(stab[k].rec), idx, f[0], f[1], f + 2, f + 5, f + 8, f + 11);
     }
@@ -1449,6 +1426,7 @@ struct ht_ctx {
     static constexpr int kPlanSlots = 4;
     char* h_pinned = nullptr;
     char* h_out = nullptr;
+    int32_t* h_err = nullptr;   // set by a kernel that dropped an update row for its index
     hipEvent_t slot_free[kPlanSlots] = {};
     bool slot_pending[kPlanSlots] = {};
     int slot = 0;
@@ -1557,6 +1535,7 @@ struct ht_batch {
     int32_t last_items = 0;
     std::vector<Entry> tab;
     std::vector<UpdEntry> utab;
+    int32_t* h_err = nullptr;   // set by the row scatter when it dropped a row for its index
 };
 
 namespace {
@@ -1810,6 +1789,25 @@ int launch_force(hipStream_t stream, bool eager, Timing& tm, const Entry* d_tab,
     return HT_OK;
 }
 
+// A kernel dropped an update row whose particle index (read from device or
+// pinned memory) was outside [0, N): report it once, at the first
+// synchronisation that follows.
+int take_row_error(int32_t* w) {
+    if (w && __atomic_load_n(w, __ATOMIC_ACQUIRE) != 0) {
+        __atomic_store_n(w, 0, __ATOMIC_RELEASE);
+        return fail(HT_ERANGE, "an update row named a particle index outside [0, N); the row was dropped");
+    }
+    return HT_OK;
+}
+
+// Wait for the context's stream; every plan slot is free afterwards.  Returns
+// HT_ERANGE when a kernel dropped an update row since the last check.
+int ctx_sync(ht_ctx* c) {
+    HT_HIP(hipStreamSynchronize(c->stream));
+    c->slots_all_free();
+    return take_row_error(c->h_err);
+}
+
 int read_timing(hipStream_t stream, Timing& tm, double* force_ms, int64_t* launches, int64_t* pairs) {
     HT_HIP(hipStreamSynchronize(stream));
     double total = 0.0;
@@ -1918,8 +1916,8 @@ int force_to_host(ht_ctx* c, int32_t n_active, const int32_t* ids, double* acc, 
     HT_HIP(hipMemcpyAsync(h, dacc, n3, hipMemcpyDeviceToHost, c->stream));
     HT_HIP(hipMemcpyAsync(h + n3, djerk, n3, hipMemcpyDeviceToHost, c->stream));
     HT_HIP(hipMemcpyAsync(h + 2 * n3, dpot, n1, hipMemcpyDeviceToHost, c->stream));
-    HT_HIP(hipStreamSynchronize(c->stream));
-    c->slots_all_free();
+    rc = ctx_sync(c);
+    if (rc) return rc;
     std::memcpy(acc, h, n3);
     std::memcpy(jerk, h + n3, n3);
     std::memcpy(pot, h + 2 * n3, n1);
@@ -1951,16 +1949,17 @@ int upload_rows(ht_ctx* c, int32_t n, const int32_t* idx, int base, const double
         const int grid = (cnt + kWG - 1) / kWG;
         if (c->cfg.precision == HT_PREC_FP64)
             scatter_kernel<PrecFp64><<<grid, kWG, 0, c->stream>>>(d, cnt, idx ? s_idx : nullptr, base + k0,
-                                                                t0 ? s_t0 : nullptr, t0_all, s_m, s_x, s_v, s_a, s_j);
+                                                                t0 ? s_t0 : nullptr, t0_all, s_m, s_x, s_v, s_a, s_j,
+                                                                c->n, c->h_err);
         else
             scatter_kernel<PrecMixed><<<grid, kWG, 0, c->stream>>>(d, cnt, idx ? s_idx : nullptr, base + k0,
-                                                               t0 ? s_t0 : nullptr, t0_all, s_m, s_x, s_v, s_a, s_j);
+                                                               t0 ? s_t0 : nullptr, t0_all, s_m, s_x, s_v, s_a, s_j,
+                                                                c->n, c->h_err);
         HT_HIP(hipGetLastError());
         // the staging area is reused by the next chunk: copies are ordered on the stream, and
         // pageable host sources are consumed before hipMemcpyAsync returns
     }
-    HT_HIP(hipStreamSynchronize(c->stream));
-    return HT_OK;
+    return ctx_sync(c);
 }
 
 int validate_ids_unique(const ht_ctx* c, int32_t n, const int32_t* idx) {
@@ -2027,9 +2026,12 @@ int ht_create(ht_ctx** out, const ht_config* cfg, void* d_workspace, size_t work
     };
     take(ht_ctx::kPlanSlots * L.plan_bytes);
     const size_t out_at = take(static_cast<size_t>(cfg->active_max) * kOut * 8);
+    const size_t err_at = take(sizeof(int32_t));
     if (hipHostMalloc(reinterpret_cast<void**>(&c->h_pinned), o, hipHostMallocDefault) != hipSuccess)
         return cleanup(fail(HT_ENOMEM, "hipHostMalloc of %zu bytes failed", o));
     c->h_out = c->h_pinned + out_at;
+    c->h_err = reinterpret_cast<int32_t*>(c->h_pinned + err_at);
+    *c->h_err = 0;
     for (int k = 0; k < ht_ctx::kPlanSlots; ++k)
         if (hipEventCreateWithFlags(&c->slot_free[k], hipEventDisableTiming) != hipSuccess)
             return cleanup(fail(HT_EHIP, "hipEventCreate failed"));
@@ -2105,9 +2107,11 @@ int ht_set_j_particles_async(ht_ctx* c, int32_t n, const int32_t* d_idx, const d
     const Desc d = c->desc();
     const int grid = (n + kWG - 1) / kWG;
     if (c->cfg.precision == HT_PREC_FP64)
-        scatter_kernel<PrecFp64><<<grid, kWG, 0, c->stream>>>(d, n, d_idx, 0, d_t0, 0.0, d_m, d_x, d_v, d_a, d_jerk);
+        scatter_kernel<PrecFp64><<<grid, kWG, 0, c->stream>>>(d, n, d_idx, 0, d_t0, 0.0, d_m, d_x, d_v, d_a, d_jerk,
+                                                            c->n, c->h_err);
     else
-        scatter_kernel<PrecMixed><<<grid, kWG, 0, c->stream>>>(d, n, d_idx, 0, d_t0, 0.0, d_m, d_x, d_v, d_a, d_jerk);
+        scatter_kernel<PrecMixed><<<grid, kWG, 0, c->stream>>>(d, n, d_idx, 0, d_t0, 0.0, d_m, d_x, d_v, d_a, d_jerk,
+                                                            c->n, c->h_err);
     HT_HIP(hipGetLastError());
     return HT_OK;
 }
@@ -2161,7 +2165,8 @@ int ht_set_interaction_lists(ht_ctx* c, int32_t n_groups, const int64_t* group_f
     if (L > 0) {
         HT_HIP(hipMemcpyAsync(c->ws + c->L.off_entries, entries, static_cast<size_t>(L) * 4, hipMemcpyHostToDevice,
                               c->stream));
-        HT_HIP(hipStreamSynchronize(c->stream));
+        int rc = ctx_sync(c);
+        if (rc) return rc;
     }
     c->group_first.assign(group_first, group_first + n_groups + 1);
     c->list_off.assign(list_off, list_off + n_groups + 1);
@@ -2229,7 +2234,7 @@ int ht_step_async(ht_ctx* c, int32_t n_upd, const int32_t* d_idx, const double* 
     if (n_active > 0 && (!d_acc || !d_jerk_out || !d_pot)) return fail(HT_EINVAL, "output pointer is NULL");
     c->t_pred = t;
     c->predicted = true;
-    const DevRows u{n_upd, d_idx, d_t0, d_m, d_x, d_v, d_a, d_jerk};
+    const DevRows u{n_upd, d_idx, d_t0, d_m, d_x, d_v, d_a, d_jerk, c->n, c->h_err};
     return enqueue_step(c, u, c->cfg.predict_mode == HT_PREDICT_EAGER, n_active, ids, d_acc, d_jerk_out, d_pot,
                         false);
 }
@@ -2320,7 +2325,7 @@ int ht_step_graph(ht_ctx* c, int32_t n_upd, const int32_t* d_idx, const double* 
     if (!std::isfinite(t)) return fail(HT_EINVAL, "t not finite");
     if (n_active > 0 && (!d_acc || !d_jerk_out || !d_pot)) return fail(HT_EINVAL, "output pointer is NULL");
     if (n_active == 0) {   // nothing to replay: the update alone, as ht_step_async would do it
-        const DevRows u{n_upd, d_idx, d_t0, d_m, d_x, d_v, d_a, d_jerk};
+        const DevRows u{n_upd, d_idx, d_t0, d_m, d_x, d_v, d_a, d_jerk, c->n, c->h_err};
         c->t_pred = t;
         c->predicted = true;
         return enqueue_step(c, u, false, 0, ids, d_acc, d_jerk_out, d_pot, false);
@@ -2358,6 +2363,8 @@ int ht_step_graph(ht_ctx* c, int32_t n_upd, const int32_t* d_idx, const double* 
     h.v = d_v;
     h.a = d_a;
     h.jerk = d_jerk;
+    h.lim = c->n;
+    h.err = c->h_err;
     Timing& tm = c->tm;
     if (tm.enabled) {
         while (tm.pool.size() < tm.used + 2) {
@@ -2389,8 +2396,7 @@ int upload_group_offsets(ht_ctx* c) {
     HT_HIP(hipMemcpyAsync(c->d_loff, c->list_off.data(), b, hipMemcpyHostToDevice, c->stream));
     group_of_kernel<<<(c->n + kWG - 1) / kWG, kWG, 0, c->stream>>>(c->n, c->d_gfirst, c->n_groups, c->d_pgroup);
     HT_HIP(hipGetLastError());
-    HT_HIP(hipStreamSynchronize(c->stream));   // pageable sources
-    return HT_OK;
+    return ctx_sync(c);   // pageable sources
 }
 }  // namespace
 
@@ -2462,9 +2468,9 @@ int ht_state_set(ht_ctx* c, int32_t n, const double* t0, const double* dt, const
     HT_HIP(hipMemcpyAsync(c->ds.j, jerk, n3, hipMemcpyHostToDevice, c->stream));
     if (pot) HT_HIP(hipMemcpyAsync(c->ds.pot, pot, n1, hipMemcpyHostToDevice, c->stream));
     else HT_HIP(hipMemsetAsync(c->ds.pot, 0, n1, c->stream));
-    HT_HIP(hipStreamSynchronize(c->stream));   // pageable sources
-    c->slots_all_free();
     c->dev_n_active = -1;
+    rc = ctx_sync(c);   // pageable sources
+    if (rc) return rc;
     return HT_OK;
 }
 
@@ -2477,9 +2483,7 @@ int ht_state_get(ht_ctx* c, double* t0, double* dt, double* x, double* v, double
         {a, c->ds.a, n3}, {jerk, c->ds.j, n3}, {pot, c->ds.pot, n1}};
     for (const auto& k : cp)
         if (k.dst) HT_HIP(hipMemcpyAsync(k.dst, k.src, k.bytes, hipMemcpyDeviceToHost, c->stream));
-    HT_HIP(hipStreamSynchronize(c->stream));
-    c->slots_all_free();
-    return HT_OK;
+    return ctx_sync(c);
 }
 
 int ht_state_rebuild(ht_ctx* c, htd_tree* t, int32_t n_leaf, int32_t n_crit, double theta, double t_tree,
@@ -2489,8 +2493,7 @@ int ht_state_rebuild(ht_ctx* c, htd_tree* t, int32_t n_leaf, int32_t n_crit, dou
     if (c->n < 1) return fail(HT_ESTATE, "particles not set");
     if (!std::isfinite(t_tree)) return fail(HT_EINVAL, "t_tree not finite");
     const int32_t n = c->n;
-    HT_HIP(hipStreamSynchronize(c->stream));   // the state is complete before the builder reads it
-    c->slots_all_free();
+    if (int rc = ctx_sync(c)) return rc;   // the state is complete before the builder reads it
     if (int rc = htd_build(t, n, c->ds.x, c->ds.v, c->ds.a, c->ds.j, c->ds.m, n_leaf, n_crit, theta))
         return fail(rc == HTD_EINVAL ? HT_EINVAL : rc == HTD_ENOMEM ? HT_ENOMEM : HT_EHIP, "device tree build: %s",
                     htd_last_error());
@@ -2521,16 +2524,18 @@ int ht_state_rebuild(ht_ctx* c, htd_tree* t, int32_t n_leaf, int32_t n_crit, dou
     const int gn = (static_cast<int>(M) + kWG - 1) / kWG;
     if (c->cfg.precision == HT_PREC_FP64) {
         scatter_kernel<PrecFp64><<<grid, kWG, 0, c->stream>>>(d, n, nullptr, 0, nullptr, t_tree, c->ds.m, c->ds.x,
-                                                            c->ds.v, c->ds.a, c->ds.j);
+                                                            c->ds.v, c->ds.a, c->ds.j, n, c->h_err);
         if (M > 0)
             scatter_kernel<PrecFp64><<<gn, kWG, 0, c->stream>>>(d, static_cast<int>(M), nullptr, n, nullptr, t_tree,
-                                                              w.node_m, w.node_x, w.node_v, w.node_a, w.node_j);
+                                                              w.node_m, w.node_x, w.node_v, w.node_a, w.node_j,
+                                                              n, c->h_err);
     } else {
         scatter_kernel<PrecMixed><<<grid, kWG, 0, c->stream>>>(d, n, nullptr, 0, nullptr, t_tree, c->ds.m, c->ds.x,
-                                                             c->ds.v, c->ds.a, c->ds.j);
+                                                             c->ds.v, c->ds.a, c->ds.j, n, c->h_err);
         if (M > 0)
             scatter_kernel<PrecMixed><<<gn, kWG, 0, c->stream>>>(d, static_cast<int>(M), nullptr, n, nullptr, t_tree,
-                                                               w.node_m, w.node_x, w.node_v, w.node_a, w.node_j);
+                                                               w.node_m, w.node_x, w.node_v, w.node_a, w.node_j,
+                                                              n, c->h_err);
     }
     HT_HIP(hipGetLastError());
     HT_HIP(hipMemcpyAsync(c->ws + c->L.off_entries, w.entries, static_cast<size_t>(L) * 4, hipMemcpyDeviceToDevice,
@@ -2564,8 +2569,7 @@ int ht_dev_next_block(ht_ctx* c, double* t_next, int64_t* n_active, const int32_
     sched_count_kernel<<<e.nb, kWG, 0, c->stream>>>(e, nullptr, 0);
     sched_write_kernel<<<e.nb, kWG, 0, c->stream>>>(e, nullptr, 0);
     HT_HIP(hipGetLastError());
-    HT_HIP(hipStreamSynchronize(c->stream));
-    c->slots_all_free();
+    if (int rc = ctx_sync(c)) return rc;
     if (c->h_dout->below_floor) {
         c->h_dout->below_floor = 0;
         return fail(HT_ERANGE, "a corrected block step fell below 2^-40");
@@ -2953,6 +2957,9 @@ int ht_batch_create(ht_batch** out, int32_t device, void* stream, int32_t max_cl
     if (rc) return cleanup(rc);
     rc = ring_init(b->rows_ring, b->rows_bytes);
     if (rc) return cleanup(rc);
+    if (hipHostMalloc(reinterpret_cast<void**>(&b->h_err), sizeof(int32_t), hipHostMallocDefault) != hipSuccess)
+        return cleanup(fail(HT_ENOMEM, "hipHostMalloc of the error word failed"));
+    *b->h_err = 0;
     b->tab.reserve(max_clusters);
     b->utab.reserve(max_clusters);
     *out = b;
@@ -2964,6 +2971,7 @@ int ht_batch_destroy(ht_batch* b) {
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     ring_free(b->plan_ring);
     ring_free(b->rows_ring);
+    if (b->h_err) (void)hipHostFree(b->h_err);
     for (hipEvent_t e : b->tm.pool) (void)hipEventDestroy(e);
     if (b->own_ws && b->ws) (void)hipFree(b->ws);
     delete b;
@@ -3031,7 +3039,7 @@ int batch_update(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs, const int32_t*
             std::memcpy(dst, rows[k], static_cast<size_t>(n_rows[k]) * sizeof(ht_row));
             src = dst;
         }
-        b->utab.push_back(UpdEntry{ctxs[k]->ws + ctxs[k]->L.off_rec, first, src, 0});
+        b->utab.push_back(UpdEntry{ctxs[k]->ws + ctxs[k]->L.off_rec, first, src, ctxs[k]->n});
         first += n_rows[k];
     }
     std::memcpy(hs, b->utab.data(), b->utab.size() * sizeof(UpdEntry));
@@ -3039,9 +3047,9 @@ int batch_update(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs, const int32_t*
     const UpdEntry* h_tab = reinterpret_cast<const UpdEntry*>(hs);
     const int nt = static_cast<int>(b->utab.size());
     if (ctxs[0]->cfg.precision == HT_PREC_FP64)
-        scatter_rows_kernel<PrecFp64><<<grid, kWG, 0, b->stream>>>(h_tab, nt, total);
+        scatter_rows_kernel<PrecFp64><<<grid, kWG, 0, b->stream>>>(h_tab, nt, total, b->h_err);
     else
-        scatter_rows_kernel<PrecMixed><<<grid, kWG, 0, b->stream>>>(h_tab, nt, total);
+        scatter_rows_kernel<PrecMixed><<<grid, kWG, 0, b->stream>>>(h_tab, nt, total, b->h_err);
     HT_HIP(hipGetLastError());
     return ring_release(b->rows_ring, b->stream);   // the kernel is the slot's last reader
 }
@@ -3210,7 +3218,7 @@ int ht_batch_dev_next_block(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs, dou
         active[k] = c->h_active;
     }
     if (bad >= 0) return fail(HT_ERANGE, "ctx %d: a corrected block step fell below 2^-40", bad);
-    return HT_OK;
+    return take_row_error(b->h_err);
 }
 
 int ht_batch_dev_step(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs, const double* eta, const double* dt_tree) {
@@ -3256,6 +3264,7 @@ int ht_batch_sync(ht_batch* b) {
     HT_HIP(hipStreamSynchronize(b->stream));
     ring_all_free(b->plan_ring);
     ring_all_free(b->rows_ring);
+    if (int rc = take_row_error(b->h_err)) return rc;
     return HT_OK;
 }
 
@@ -3290,9 +3299,7 @@ extern "C" {
 
 int ht_sync(ht_ctx* c) {
     if (!c) return fail(HT_EINVAL, "ctx is NULL");
-    HT_HIP(hipStreamSynchronize(c->stream));
-    c->slots_all_free();
-    return HT_OK;
+    return ctx_sync(c);
 }
 
 int ht_set_timing(ht_ctx* c, int32_t enable) {
@@ -3306,7 +3313,10 @@ int ht_set_timing(ht_ctx* c, int32_t enable) {
 int ht_kernel_timing(ht_ctx* c, double* force_ms, int64_t* launches, int64_t* pairs) {
     if (!c || !force_ms || !launches || !pairs) return fail(HT_EINVAL, "NULL argument");
     int rc = read_timing(c->stream, c->tm, force_ms, launches, pairs);
-    if (rc == HT_OK) c->slots_all_free();
+    if (rc == HT_OK) {
+        c->slots_all_free();
+        rc = take_row_error(c->h_err);
+    }
     return rc;
 }
 
