@@ -317,6 +317,34 @@ int ht_batch_set_timing(ht_batch *b, int32_t enable);
 int ht_batch_kernel_timing(ht_batch *b, double *force_ms, int64_t *launches, int64_t *pairs);
 int ht_batch_last_stats(const ht_batch *b, int64_t *pairs, int32_t *work_items);
 
+/* ---------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the direct
+ * N^2 force of ht_force_direct_async, on caller-owned device arrays and with
+ * no context, that calls no allocating routine.
+ *
+ * d_x, d_v [n][3] (FP64): predicted positions and velocities; d_m [n]: masses
+ * (rounded to FP32 first in the mixed form, as the mixed j-records store
+ * them); d_active [n_active]: particle indices in [0, n), in device memory,
+ * so they cannot be checked before the launch: an index outside [0, n) gives
+ * NaN in its output row.  d_acc, d_jerk [n_active][3], d_pot [n_active]:
+ * outputs in active order.  precision: ht_precision (the pair arithmetic of
+ * that form).  The j-range 0..n-1 is cut into j_splits equal ranges (1 to
+ * 65535) summed by separate work-groups and then added in split order, so the
+ * result's bits depend on j_splits only.  With j_splits > 1 the partial sums
+ * go to one fixed device array of HT_NOALLOC_SCRATCH_BYTES per device, which
+ * the library holds until the process ends; a call needing more
+ * (j_splits * n_active * 56 bytes) fails with HT_ERANGE before any launch.
+ * Every call on a device shares that array: calls that overlap in time on one
+ * device (different streams, or threads) race and give wrong results.
+ * Asynchronous on `stream` (a hipStream_t; NULL is the null stream) of
+ * `device`, which must be the current device. */
+#define HT_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+int ht_force_direct_noalloc(int32_t device, void *stream, int32_t precision, int32_t n, const double *d_x,
+                            const double *d_v, const double *d_m, double eps2, int32_t n_active,
+                            const int32_t *d_active, int32_t j_splits, double *d_acc, double *d_jerk,
+                            double *d_pot);
+
 /* Block until the context's queued work has finished. */
 int ht_sync(ht_ctx *ctx);
 

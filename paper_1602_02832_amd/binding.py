@@ -148,6 +148,7 @@ def device_lib():
             "ht_batch_set_timing": [_vp, i],
             "ht_batch_kernel_timing": [_vp, _c_dp, _c_i64p, _c_i64p],
             "ht_batch_last_stats": [_vp, _c_i64p, _c_i32p],
+            "ht_force_direct_noalloc": [i, _vp, i, i, _vp, _vp, _vp, d, i, _vp, i, _vp, _vp, _vp],
             "htd_create": [ctypes.POINTER(_vp), i, _vp, i64],
             "htd_destroy": [_vp],
             "htd_build": [_vp, i64, _vp, _vp, _vp, _vp, _vp, i, i, d],
@@ -482,6 +483,20 @@ def force_batch_async(ctxs, actives, d_accs, d_jerks, d_pots):
     Q = (_vp * n)(*[_dptr(t) for t in d_pots])
     _check(device_lib().ht_force_batch_async(n, H, N, P, A, J, Q))
     return acts  # keep host arrays alive until the caller syncs
+
+
+def force_direct_noalloc(precision, d_x, d_v, d_m, eps2, d_active, j_splits, d_acc, d_jerk, d_pot, n=None,
+                         n_active=None, stream=None, device=0):
+    """ht_force_direct_noalloc: the direct sum on caller-owned device arrays
+    (torch tensors or addresses), partial sums in the library's fixed scratch
+    array; asynchronous on `stream` (a torch stream, a hipStream_t address or
+    None for the null stream)."""
+    n = int(d_m.shape[0]) if n is None else int(n)
+    n_active = int(d_active.shape[0]) if n_active is None else int(n_active)
+    st = getattr(stream, "cuda_stream", stream)
+    _check(device_lib().ht_force_direct_noalloc(int(device), st, HT_PREC[precision], n, _dptr(d_x), _dptr(d_v),
+                                                _dptr(d_m), float(eps2), n_active, _dptr(d_active), int(j_splits),
+                                                _dptr(d_acc), _dptr(d_jerk), _dptr(d_pot)))
 
 
 class Batch:

@@ -30,6 +30,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -3334,6 +3335,167 @@ int ht_last_stats(const ht_ctx* c, int64_t* pairs, int32_t* work_items) {
     if (!c) return fail(HT_EINVAL, "ctx is NULL");
     if (pairs) *pairs = c->last_pairs;
     if (work_items) *work_items = c->last_items;
+    return HT_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------------------
+// Direct sum with no allocation (ht_force_direct_noalloc): the force of the
+// original Hermite scheme (Section 2) on caller-owned device arrays of
+// predicted positions, velocities and masses.  The j-range is cut into
+// j_splits ranges summed by separate work-groups; their partial sums live in
+// `scratch`, one fixed array per device that the library holds until the
+// process ends, and a second kernel adds them in split order.  Nothing in it
+// must start at zero: every partial slot a call reads was written by that
+// call's first kernel.
+constexpr size_t kScratchBytes = HT_NOALLOC_SCRATCH_BYTES;   // per device
+
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};   // device address of `scratch` on each device
+
+// The device address of `scratch` on `device` (taken once per device, with
+// that device current; the array's name in host code is not that address).
+int scratch_on(int32_t device, double** out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[device]) {
+        int prev = 0;
+        HT_HIP(hipGetDevice(&prev));
+        HT_HIP(hipSetDevice(device));
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        const hipError_t back = hipSetDevice(prev);
+        if (e != hipSuccess) return fail(HT_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        if (back != hipSuccess) return fail(HT_EHIP, "hipSetDevice: %s", hipGetErrorString(back));
+        g_scratch[device] = static_cast<double*>(p);
+    }
+    *out = g_scratch[device];
+    return HT_OK;
+}
+
+// Work-group (tile, split): 256 active particles of one tile against the
+// split's j-range, staged through LDS 256 entries at a time; the same pair
+// arithmetic as the list force.  An active id outside [0, n) gives NaN in its
+// output row (the ids sit in device memory, so the host cannot check them).
+template <class P>
+__global__ __launch_bounds__(kWG) void noalloc_direct_kernel(int32_t n, const double* __restrict__ x,
+                                                             const double* __restrict__ v,
+                                                             const double* __restrict__ m, double eps2,
+                                                             int32_t n_active, const int32_t* __restrict__ active,
+                                                             int64_t per, double* part, double* acc, double* jerk,
+                                                             double* pot) {
+    using V = typename P::Vel;
+    using S = typename P::Stored;
+    __shared__ JRec<P> tile[kWG];
+    const int tid = threadIdx.x;
+    const int64_t q = static_cast<int64_t>(blockIdx.x) * kWG + tid;
+    const int split = blockIdx.y;
+    const bool has_q = q < n_active;
+    const int32_t i_raw = has_q ? active[q] : 0;
+    const bool ok = i_raw >= 0 && i_raw < n;
+    const int32_t i = ok ? i_raw : 0;
+    const double xi = x[3 * i], yi = x[3 * i + 1], zi = x[3 * i + 2];
+    const V vxi = static_cast<V>(v[3 * i]), vyi = static_cast<V>(v[3 * i + 1]), vzi = static_cast<V>(v[3 * i + 2]);
+    Acc64 A;
+#pragma unroll
+    for (int k = 0; k < kOut; ++k) A.v[k] = 0.0;
+    const int64_t jb = split * per, je = jb + per < n ? jb + per : n;
+    for (int64_t base = jb; base < je; base += kWG) {
+        const int cnt = je - base < kWG ? static_cast<int>(je - base) : kWG;
+        __syncthreads();
+        if (tid < cnt) {
+            const int64_t j = base + tid;
+            tile[tid] = JRec<P>{x[3 * j], x[3 * j + 1], x[3 * j + 2], static_cast<V>(v[3 * j]),
+                                static_cast<V>(v[3 * j + 1]), static_cast<V>(v[3 * j + 2]),
+                                static_cast<double>(static_cast<S>(m[j])),
+                                static_cast<int32_t>(j)};
+        }
+        __syncthreads();
+        for (int k = 0; k < cnt; ++k) pair<P>(xi, yi, zi, vxi, vyi, vzi, i, tile[k], eps2, A);
+    }
+    if (!has_q) return;
+    if (!ok) {
+#pragma unroll
+        for (int k = 0; k < kOut; ++k) A.v[k] = __builtin_nan("");
+    }
+    if (gridDim.y == 1) {
+        acc[3 * q] = A.v[0];
+        acc[3 * q + 1] = A.v[1];
+        acc[3 * q + 2] = A.v[2];
+        jerk[3 * q] = A.v[3];
+        jerk[3 * q + 1] = A.v[4];
+        jerk[3 * q + 2] = A.v[5];
+        pot[q] = A.v[6];
+        return;
+    }
+    double* p = part + (static_cast<int64_t>(split) * n_active + q) * kOut;
+#pragma unroll
+    for (int k = 0; k < kOut; ++k) p[k] = A.v[k];
+}
+
+// The split partials of every active particle, added in split order.
+__global__ __launch_bounds__(kWG) void noalloc_reduce_kernel(int32_t n_active, int32_t n_split,
+                                                             const double* __restrict__ part, double* acc,
+                                                             double* jerk, double* pot) {
+    const int64_t q = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
+    if (q >= n_active) return;
+    double A[kOut];
+    for (int k = 0; k < kOut; ++k) A[k] = part[q * kOut + k];
+    for (int s = 1; s < n_split; ++s)
+        for (int k = 0; k < kOut; ++k) A[k] += part[(static_cast<int64_t>(s) * n_active + q) * kOut + k];
+    acc[3 * q] = A[0];
+    acc[3 * q + 1] = A[1];
+    acc[3 * q + 2] = A[2];
+    jerk[3 * q] = A[3];
+    jerk[3 * q + 1] = A[4];
+    jerk[3 * q + 2] = A[5];
+    pot[q] = A[6];
+}
+
+}  // namespace
+
+extern "C" {
+
+int ht_force_direct_noalloc(int32_t device, void* stream, int32_t precision, int32_t n, const double* d_x,
+                            const double* d_v, const double* d_m, double eps2, int32_t n_active,
+                            const int32_t* d_active, int32_t j_splits, double* d_acc, double* d_jerk,
+                            double* d_pot) {
+    if (precision != HT_PREC_FP64 && precision != HT_PREC_MIXED) return fail(HT_EINVAL, "unknown precision");
+    if (device < 0 || device >= kMaxDevices) return fail(HT_EINVAL, "device %d outside [0, %d)", device, kMaxDevices);
+    if (n < 1 || n_active < 0) return fail(HT_EINVAL, "n must be >= 1 and n_active >= 0");
+    if (!(eps2 >= 0.0) || !std::isfinite(eps2)) return fail(HT_EINVAL, "eps2 must be finite and >= 0");
+    if (j_splits < 1 || j_splits > 65535) return fail(HT_EINVAL, "j_splits = %d outside [1, 65535]", j_splits);
+    if (n_active == 0) return HT_OK;
+    if (!d_x || !d_v || !d_m || !d_active || !d_acc || !d_jerk || !d_pot) return fail(HT_EINVAL, "NULL device array");
+    const size_t need = j_splits > 1 ? static_cast<size_t>(j_splits) * static_cast<size_t>(n_active) * kOut * 8 : 0;
+    if (need > kScratchBytes)
+        return fail(HT_ERANGE, "%d splits of %d active particles need %zu bytes of scratch; the library holds %zu",
+                    j_splits, n_active, need, kScratchBytes);
+    double* part = nullptr;
+    if (j_splits > 1) {
+        int rc = scratch_on(device, &part);
+        if (rc) return rc;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t per = (static_cast<int64_t>(n) + j_splits - 1) / j_splits;
+    const dim3 grid(static_cast<unsigned>((n_active + kWG - 1) / kWG), static_cast<unsigned>(j_splits));
+    if (precision == HT_PREC_FP64)
+        noalloc_direct_kernel<PrecFp64><<<grid, kWG, 0, s>>>(n, d_x, d_v, d_m, eps2, n_active, d_active, per, part,
+                                                             d_acc, d_jerk, d_pot);
+    else
+        noalloc_direct_kernel<PrecMixed><<<grid, kWG, 0, s>>>(n, d_x, d_v, d_m, eps2, n_active, d_active, per, part,
+                                                              d_acc, d_jerk, d_pot);
+    HT_HIP(hipGetLastError());
+    if (j_splits > 1) {
+        noalloc_reduce_kernel<<<(n_active + kWG - 1) / kWG, kWG, 0, s>>>(n_active, j_splits, part, d_acc, d_jerk,
+                                                                         d_pot);
+        HT_HIP(hipGetLastError());
+    }
     return HT_OK;
 }
 
