@@ -312,6 +312,37 @@ int ht_batch_dev_next_block(ht_batch *b, int32_t n_ctx, ht_ctx *const *ctxs, dou
                             const int32_t **active);
 int ht_batch_dev_step(ht_batch *b, int32_t n_ctx, ht_ctx *const *ctxs, const double *eta, const double *dt_tree);
 
+/* Batched device loop (Section 2, steps 2 and 4a-6 for many clusters): up
+ * to engine_steps engine steps of the resident contexts ctxs[0..n_ctx-1],
+ * queued on the batch's stream with no host round trip between them, in HIP
+ * graphs of 32 engine steps.  In every engine step each context that is still
+ * running takes one block step of its own: the scheduler of ht_dev_next_block,
+ * the work plan of the device planner (the host planner's items, so each
+ * context gets the bits of its own step-by-step run, alone or in any batch),
+ * one force launch over all contexts' items and one corrector launch for all
+ * of them.  Context k stops after its step at t_stop[k] (a tree time, where
+ * the caller rebuilds it), before a block time beyond t_stop[k], or after
+ * max_steps[k] steps, with eta[k] and dt_tree[k] as in ht_dev_step;
+ * max_steps[k] = 0 makes it sit out the call: no kernel and no host code of
+ * the call touches its state (it may be rebuilt meanwhile on another stream),
+ * and t_last[k] is NaN.  The work runs on the batch's stream; the contexts
+ * may live on other streams, and the caller makes sure that none of them has
+ * work in flight there (the call waits only for its own stream).  Keeping
+ * the same contexts from call to call (sitting out where needed) keeps the
+ * captured graph.
+ * Results: steps[k], t_last[k] (block time of its last step), particle_steps[k]
+ * and pairs[k] (pair interactions summed) per context; step_ms (room for
+ * engine_steps values) receives the wall time of every engine step in which
+ * some context stepped, and *n_step_ms their number.  Synchronous (one wait,
+ * at the end).  Needs fused prediction and whole-number gather costs;
+ * engine_steps in [1, 4096].  The tables and the graph are kept while the
+ * batch is called with the same contexts (same sizes and tunings).
+ * HT_ERANGE if a plan exceeded a context's capacity or a step fell below
+ * 2^-40: the steps before it stand. */
+int ht_batch_dev_run(ht_batch *b, int32_t n_ctx, ht_ctx *const *ctxs, const double *eta, const double *dt_tree,
+                     const double *t_stop, const int32_t *max_steps, int32_t engine_steps, int32_t *steps,
+                     double *t_last, int64_t *particle_steps, int64_t *pairs, double *step_ms, int32_t *n_step_ms);
+
 int ht_batch_sync(ht_batch *b);
 int ht_batch_set_timing(ht_batch *b, int32_t enable);
 int ht_batch_kernel_timing(ht_batch *b, double *force_ms, int64_t *launches, int64_t *pairs);

@@ -149,6 +149,8 @@ def device_lib():
             "ht_batch_kernel_timing": [_vp, _c_dp, _c_i64p, _c_i64p],
             "ht_batch_last_stats": [_vp, _c_i64p, _c_i32p],
             "ht_force_direct_noalloc": [i, _vp, i, i, _vp, _vp, _vp, d, i, _vp, i, _vp, _vp, _vp],
+            "ht_batch_dev_run": [_vp, i, _vp, _vp, _vp, _vp, _vp, i, _vp, _vp, _vp, _vp, _vp,
+                                 ctypes.POINTER(ctypes.c_int32)],
             "htd_create": [ctypes.POINTER(_vp), i, _vp, i64],
             "htd_destroy": [_vp],
             "htd_build": [_vp, i64, _vp, _vp, _vp, _vp, _vp, i, i, d],
@@ -562,6 +564,25 @@ class Batch:
     def dev_step_raw(self, n, handles, eta, dt_tree):
         """ht_batch_dev_step with every array given by address (eta, dt_tree: n float64)."""
         _check(_raw("ht_batch_dev_step", 5)(self._h.value, n, handles, eta, dt_tree))
+
+    def dev_run(self, handles, eta, dt_tree, t_stop, max_steps, engine_steps):
+        """ht_batch_dev_run over the contexts with these handles (uint64 array):
+        returns (steps, t_last, particle_steps, pairs, engine-step ms)."""
+        n = int(handles.shape[0])
+        handles = np.ascontiguousarray(handles, dtype=np.uint64)
+        eta, dt_tree, t_stop = (np.ascontiguousarray(u, dtype=np.float64) for u in (eta, dt_tree, t_stop))
+        max_steps = np.ascontiguousarray(max_steps, dtype=np.int32)
+        steps = np.empty(n, np.int32)
+        t_last = np.empty(n)
+        psteps = np.empty(n, np.int64)
+        pairs = np.empty(n, np.int64)
+        step_ms = np.empty(int(engine_steps))
+        n_ms = ctypes.c_int32()
+        _check(device_lib().ht_batch_dev_run(self._h, n, handles.ctypes.data, eta.ctypes.data, dt_tree.ctypes.data,
+                                             t_stop.ctypes.data, max_steps.ctypes.data, int(engine_steps),
+                                             steps.ctypes.data, t_last.ctypes.data, psteps.ctypes.data,
+                                             pairs.ctypes.data, step_ms.ctypes.data, ctypes.byref(n_ms)))
+        return steps, t_last, psteps, pairs, step_ms[:n_ms.value].copy()
 
     def force_async(self, ctxs, actives, d_accs, d_jerks, d_pots):
         n = len(ctxs)

@@ -30,6 +30,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -432,15 +433,16 @@ template <class P>
 struct WavesPerSimd { static constexpr int value = P::kMixed ? 4 : 3; };
 
 // Work-group g takes items g, g + grid, ...  The grid is normally the item
-// count; graph replays launch a fixed grid and pass n_items < 0, and the count
-// is read from the table.  (A shared atomic work counter was measured to cost
+// count; graph replays and device loops launch a fixed grid and pass
+// n_items < 0, and the count is read from counts[0] (the items of the whole
+// launch, written by the plan's delivery or by the device planner).  (A shared atomic work counter was measured to cost
 // about 1 us per item: device-scope atomics on one address serialise across
 // the eight XCDs.)
 template <class P, bool EAGER, bool DIRECT>
 __global__ __launch_bounds__(kWG, WavesPerSimd<P>::value) void force_kernel(const Entry* __restrict__ tab, int n_tab,
-                                                                          int64_t n_items) {
+                                                                          int64_t n_items, const int64_t* counts) {
     __shared__ LdsAll<P> lds;
-    if (n_items < 0) n_items = tab[0].n_items;
+    if (n_items < 0) n_items = counts[0];
     for (int64_t g = blockIdx.x; g < n_items; g += gridDim.x) {
         const int cl = find_entry(tab, n_tab, g, false);
         const Desc& c = tab[cl].d;
@@ -904,9 +906,10 @@ constexpr int kCorrBatch = 8;   // split partials loaded together by the correct
 
 template <class P>
 __global__ __launch_bounds__(kWG) void dev_correct_kernel(CorrEntry e0, const CorrEntry* tab, int n_tab,
-                                                          int64_t total) {
+                                                          int64_t total, const int64_t* d_total) {
 #pragma clang fp contract(off)
-    if (total < 0) total = e0.loop->n_corr;   // device loop (a single entry)
+    // device loops: the row count is the loop's (one entry) or the batch table's (d_total)
+    if (total < 0) total = d_total ? *d_total : e0.loop->n_corr;
     for (int64_t r = blockIdx.x * static_cast<int64_t>(kWG) + threadIdx.x; r < total;
          r += static_cast<int64_t>(gridDim.x) * kWG) {
         const CorrEntry* ep = &e0;
@@ -1101,7 +1104,7 @@ __device__ inline V plan_scan(V v, V* excl, V* s_wave) {
 // quantum (the costs are whole numbers when the gather cost is, so their sum
 // does not depend on the order of addition), in group order.  The order of the
 // items does not change any result.
-__global__ __launch_bounds__(kPlanWG) void dev_plan_kernel(PlanArgs A) {
+__device__ __forceinline__ void plan_body(const PlanArgs& A) {
     __shared__ int64_t s_w64[kPlanWG / 64];
     __shared__ double s_wd[kPlanWG / 64];
     __shared__ int8_t s_ft[260];   // the tile table, indexed per thread
@@ -1287,6 +1290,136 @@ __global__ __launch_bounds__(kPlanWG) void dev_plan_kernel(PlanArgs A) {
         e.n_items = io;
         e.n_rtiles = ro;
         L->pairs += pairs;
+    }
+}
+
+__global__ __launch_bounds__(kPlanWG) void dev_plan_kernel(PlanArgs A) { plan_body(A); }
+
+// ------------------------------------------------------------------------------------------------
+// Batched device loop (ht_batch_dev_run): the device loop of every context of
+// a batch in one chain of launches per engine step.  Each context keeps its
+// own loop state, scheduler, planner scratch, plan and partials; per engine
+// step the three scheduler passes run over all contexts' blocks, one planner
+// work-group per context plans that context's step, a one-work-group kernel
+// places the contexts' items and corrector rows one after another, and one
+// force launch and one corrector launch serve them all.  A context's plan is
+// the one it makes alone, so its bits are the same alone and in any batch.
+
+// One planner work-group per context.
+__global__ __launch_bounds__(kPlanWG) void dev_plan_batch_kernel(const PlanArgs* __restrict__ tab) {
+    plan_body(tab[blockIdx.x]);
+}
+
+// A context's loop state and scheduler results.
+struct LoopCtx {
+    DevLoop* loop;
+    DevOut* dout;
+};
+
+// Device words of a batched loop call.
+struct LoopCounts {
+    int64_t items, rtiles, rows;   // this engine step: work items, split tiles and corrector rows of all contexts
+    int64_t step;                  // engine steps in which some context stepped
+};
+
+// Per-call parameters of one context (pinned host memory, read by the init kernel).
+struct LoopParams {
+    double t_stop, eta, dt_tree;
+    int64_t max_steps;
+};
+static_assert(sizeof(LoopParams) == 4 * 8, "LoopParams is 4 words");
+
+// What a call reports per context (pinned host memory, written by the results kernel).
+struct LoopResult {
+    int64_t steps, psteps, pairs;
+    double t_cur;
+    int32_t err, below_floor;
+};
+
+constexpr int kLoopTabWG = 1024;   // threads of the table kernel (one per context: kMaxBatch)
+static_assert(kLoopTabWG >= kMaxBatch, "one table thread per context");
+
+// Start of a call: every context's loop state from its parameters, counts cleared.
+__global__ __launch_bounds__(kWG) void batch_loop_init_kernel(const LoopCtx* __restrict__ lc,
+                                                              const LoopParams* prm, int n, LoopCounts* cnt) {
+    const int k = blockIdx.x * kWG + threadIdx.x;
+    if (k == 0) *cnt = LoopCounts{};
+    if (k >= n) return;
+    const uint64_t* w = reinterpret_cast<const uint64_t*>(prm + k);
+    DevLoop z{};
+    z.t_stop = __builtin_bit_cast(double, host_word(w));
+    z.eta = __builtin_bit_cast(double, host_word(w + 1));
+    z.dt_tree = __builtin_bit_cast(double, host_word(w + 2));
+    z.max_steps = static_cast<int64_t>(host_word(w + 3));
+    z.halt = z.max_steps < 1;   // a context that sits out this call: no kernel touches its state
+    *lc[k].loop = z;
+    *lc[k].dout = DevOut{};
+}
+
+// Exclusive prefix sum over the kLoopTabWG threads of the work-group.
+__device__ inline int64_t tab_scan(int64_t v, int64_t* s_wave, int64_t* total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int64_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    __syncthreads();
+    if (lane == 63) s_wave[wave] = x;
+    __syncthreads();
+    int64_t before = 0, all = 0;
+    for (int w = 0; w < kLoopTabWG / 64; ++w) {
+        if (w < wave) before += s_wave[w];
+        all += s_wave[w];
+    }
+    *total = all;
+    return before + x - v;
+}
+
+// After the planners: each context's first item, first split tile and first
+// corrector row in the engine step's launches, and the step's totals; the
+// time of the step (wall clock) when some context takes one.
+__global__ __launch_bounds__(kLoopTabWG) void batch_loop_table_kernel(Entry* tab, CorrEntry* ctab,
+                                                                      const LoopCtx* __restrict__ lc, int n,
+                                                                      LoopCounts* cnt, int64_t* ts, int64_t ts_max) {
+    __shared__ int64_t s_wave[kLoopTabWG / 64];
+    const int k = threadIdx.x;
+    const bool on = k < n;
+    int64_t ti, tr, tc;
+    const int64_t ei = tab_scan(on ? tab[k].n_items : 0, s_wave, &ti);
+    const int64_t er = tab_scan(on ? tab[k].n_rtiles : 0, s_wave, &tr);
+    const int64_t ec = tab_scan(on ? lc[k].loop->n_corr : 0, s_wave, &tc);
+    if (on) {
+        tab[k].first_item = ei;
+        tab[k].first_rtile = er;
+        ctab[k].first_row = ec;
+    }
+    if (k == 0) {
+        cnt->items = ti;
+        cnt->rtiles = tr;
+        cnt->rows = tc;
+        if (tc > 0) {
+            const int64_t st = cnt->step;
+            if (st < ts_max) ts[st] = static_cast<int64_t>(wall_clock64());
+            cnt->step = st + 1;
+        }
+    }
+}
+
+// End of a call: every context's counts and state, and the step times, into pinned memory.
+__global__ __launch_bounds__(kWG) void batch_loop_results_kernel(const LoopCtx* __restrict__ lc, int n,
+                                                                 LoopResult* out, const LoopCounts* cnt,
+                                                                 const int64_t* ts, int64_t ts_max, int64_t* ts_out) {
+    const int k = blockIdx.x * kWG + threadIdx.x;
+    if (k < n) {
+        const DevLoop& L = *lc[k].loop;
+        out[k] = LoopResult{L.steps, L.psteps, L.pairs, L.t_cur, L.err, lc[k].dout->below_floor};
+    }
+    const int64_t m = cnt->step < ts_max ? cnt->step : ts_max;
+    for (int64_t q = k; q < m; q += static_cast<int64_t>(gridDim.x) * kWG) ts_out[1 + q] = ts[q];
+    if (k == 0) {
+        ts_out[0] = m;
+        ts_out[1 + m] = static_cast<int64_t>(wall_clock64());
     }
 }
 
@@ -1537,6 +1670,20 @@ struct ht_batch {
     std::vector<Entry> tab;
     std::vector<UpdEntry> utab;
     int32_t* h_err = nullptr;   // set by the row scatter when it dropped a row for its index
+    // batched device loop (ht_batch_dev_run): its tables sit in the workspace
+    // after the plan region; the graph of kLoopGraphSteps engine steps is
+    // captured for one set of contexts (and their sizes and tunings) and kept
+    // until the set changes
+    char* loop_ws = nullptr;
+    std::vector<ht_ctx*> loop_ctxs;
+    std::vector<double> loop_key;
+    int32_t loop_blocks = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t loop_graph = nullptr;
+    hipGraphExec_t loop_exec = nullptr;
+    LoopParams* h_lparams = nullptr;   // pinned: per-call parameters
+    LoopResult* h_lres = nullptr;      // pinned: per-call results
+    int64_t* h_ts = nullptr;           // pinned: engine-step times of the last call
 };
 
 namespace {
@@ -1775,11 +1922,11 @@ int launch_force(hipStream_t stream, bool eager, Timing& tm, const Entry* d_tab,
         tm.pairs += pairs;
     }
     if (direct) {
-        if (eager) force_kernel<P, true, true><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items);
-        else force_kernel<P, false, true><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items);
+        if (eager) force_kernel<P, true, true><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr);
+        else force_kernel<P, false, true><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr);
     } else {
-        if (eager) force_kernel<P, true, false><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items);
-        else force_kernel<P, false, false><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items);
+        if (eager) force_kernel<P, true, false><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr);
+        else force_kernel<P, false, false><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr);
     }
     HT_HIP(hipGetLastError());
     if (ev_b) HT_HIP(hipEventRecord(ev_b, stream));
@@ -2262,9 +2409,9 @@ int launch_correct(int precision, hipStream_t stream, const CorrEntry& e0, const
                    int64_t total) {
     const int grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((total + kWG - 1) / kWG, 65536)));
     if (precision == HT_PREC_FP64)
-        dev_correct_kernel<PrecFp64><<<grid, kWG, 0, stream>>>(e0, tab, n_tab, total);
+        dev_correct_kernel<PrecFp64><<<grid, kWG, 0, stream>>>(e0, tab, n_tab, total, nullptr);
     else
-        dev_correct_kernel<PrecMixed><<<grid, kWG, 0, stream>>>(e0, tab, n_tab, total);
+        dev_correct_kernel<PrecMixed><<<grid, kWG, 0, stream>>>(e0, tab, n_tab, total, nullptr);
     HT_HIP(hipGetLastError());
     return HT_OK;
 }
@@ -2294,7 +2441,7 @@ int build_step_graph(ht_ctx* c, int k) {
     prep_graph_kernel<P><<<kGraphCopyBlocks + kGraphScatterBlocks, kWG, 0, s>>>(c->h_hdr + k, d_plan,
                                                                              c->ws + c->L.off_rec,
                                                                              kGraphCopyBlocks);
-    force_kernel<P, false, false><<<kGraphForceGrid, kWG, 0, s>>>(d_tab, 1, -1);
+    force_kernel<P, false, false><<<kGraphForceGrid, kWG, 0, s>>>(d_tab, 1, -1, &d_tab->n_items);
     reduce_kernel<<<kGraphReduceGrid, kWG, 0, s>>>(d_tab, 1, -1);
     const hipError_t launch = hipGetLastError();
     hipGraph_t g = nullptr;
@@ -2616,6 +2763,57 @@ constexpr int kLoopForceGrid = 1024;  // fixed force grid of the device loop (4 
 constexpr int kLoopCorrGrid = 256;    // fixed corrector grid of the device loop (grid-stride)
 
 namespace {
+// The device planner's arguments for a context: its loop state, scheduler
+// results, planner scratch and plan region; the launch-table entry it writes
+// is `tab` (its own plan region's, or a slot of a batched loop's table).
+PlanArgs plan_args_of(const ht_ctx* c, Entry* tab) {
+    PlanArgs pa{};
+    pa.loop = c->d_loop;
+    pa.dout = c->d_dout;
+    pa.qmap = c->d_gk;
+    pa.active = c->ds.active;
+    pa.pgroup = c->d_pgroup;
+    pa.loff = c->d_loff;
+    pa.qk = c->d_qk;
+    pa.qg = c->d_qg;
+    pa.tiles = c->d_tiles;
+    char* plan = c->ws + c->L.off_plan;
+    pa.tab = tab;
+    pa.items = reinterpret_cast<Item*>(plan + align_up(kMaxBatch * sizeof(Entry)));
+    pa.rtiles = reinterpret_cast<RTile*>(plan + align_up(kMaxBatch * sizeof(Entry)) +
+                                         align_up(static_cast<size_t>(c->L.items_max) * sizeof(Item)));
+    pa.items_max = c->L.items_max;
+    pa.partial_max = c->L.partial_max;
+    pa.gather_cost = c->gather_cost;
+    pa.target_items = c->target_items;
+    pa.d = c->desc();
+    pa.d.active = c->ds.active;
+    pa.d.acc = c->ds.acc;
+    pa.d.jerk = c->ds.jerk;
+    pa.d.pot = c->ds.fpot;
+    std::memcpy(pa.first_tile, c->first_tile, sizeof(pa.first_tile));
+    return pa;
+}
+
+// The device loop's scheduler and corrector entries of a context.
+SchedEntry loop_sched_entry(const ht_ctx* c, int32_t first_block) {
+    SchedEntry se = sched_entry_of(c, first_block);
+    se.out = c->d_dout;
+    se.active_host = nullptr;
+    se.halt = &c->d_loop->halt;
+    return se;
+}
+
+CorrEntry loop_corr_entry(const ht_ctx* c, const PlanArgs& pa) {
+    CorrEntry ce = corr_entry_of(c, 0, 1.0, 1.0);   // eta and dt_tree come from the loop state
+    ce.out = c->d_dout;
+    ce.loop = c->d_loop;
+    ce.qmap = pa.qmap;
+    ce.rtiles = pa.rtiles;
+    ce.partial = pa.d.partial;
+    return ce;
+}
+
 // Capture kLoopGraphSteps device-loop steps into one graph.  Every launch
 // argument is fixed for the context's life (the call's parameters sit in the
 // loop state in device memory), except the work-plan tuning, on whose change
@@ -2630,41 +2828,9 @@ int build_loop_graph(ht_ctx* c) {
         c->loop_graph = nullptr;
     }
     if (!c->cap_stream) HT_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-    SchedEntry se = sched_entry_of(c, 0);
-    se.out = c->d_dout;
-    se.active_host = nullptr;
-    se.halt = &c->d_loop->halt;
-    CorrEntry ce = corr_entry_of(c, 0, 1.0, 1.0);   // eta and dt_tree come from the loop state
-    ce.out = c->d_dout;
-    ce.loop = c->d_loop;
-    PlanArgs pa{};
-    pa.loop = c->d_loop;
-    pa.dout = c->d_dout;
-    pa.qmap = c->d_gk;
-    pa.active = c->ds.active;
-    pa.pgroup = c->d_pgroup;
-    pa.loff = c->d_loff;
-    pa.qk = c->d_qk;
-    pa.qg = c->d_qg;
-    pa.tiles = c->d_tiles;
-    char* plan = c->ws + c->L.off_plan;
-    pa.tab = reinterpret_cast<Entry*>(plan);
-    pa.items = reinterpret_cast<Item*>(plan + align_up(kMaxBatch * sizeof(Entry)));
-    pa.rtiles = reinterpret_cast<RTile*>(plan + align_up(kMaxBatch * sizeof(Entry)) +
-                                         align_up(static_cast<size_t>(c->L.items_max) * sizeof(Item)));
-    pa.items_max = c->L.items_max;
-    pa.partial_max = c->L.partial_max;
-    pa.gather_cost = c->gather_cost;
-    pa.target_items = c->target_items;
-    pa.d = c->desc();
-    pa.d.active = c->ds.active;
-    pa.d.acc = c->ds.acc;
-    pa.d.jerk = c->ds.jerk;
-    pa.d.pot = c->ds.fpot;
-    std::memcpy(pa.first_tile, c->first_tile, sizeof(pa.first_tile));
-    ce.qmap = pa.qmap;
-    ce.rtiles = pa.rtiles;
-    ce.partial = pa.d.partial;
+    const SchedEntry se = loop_sched_entry(c, 0);
+    const PlanArgs pa = plan_args_of(c, reinterpret_cast<Entry*>(c->ws + c->L.off_plan));
+    const CorrEntry ce = loop_corr_entry(c, pa);
     const Entry* d_tab = pa.tab;
     hipStream_t s = c->cap_stream;
     HT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -2674,11 +2840,11 @@ int build_loop_graph(ht_ctx* c) {
         sched_write_kernel<<<se.nb, kWG, 0, s>>>(se, nullptr, 0);
         dev_plan_kernel<<<1, kPlanWG, 0, s>>>(pa);   // takes the step (or stops the loop) and plans it
         if (c->cfg.precision == HT_PREC_FP64) {
-            force_kernel<PrecFp64, false, false><<<kLoopForceGrid, kWG, 0, s>>>(d_tab, 1, -1);
-            dev_correct_kernel<PrecFp64><<<kLoopCorrGrid, kWG, 0, s>>>(ce, nullptr, 0, -1);   // sums the splits too
+            force_kernel<PrecFp64, false, false><<<kLoopForceGrid, kWG, 0, s>>>(d_tab, 1, -1, &d_tab->n_items);
+            dev_correct_kernel<PrecFp64><<<kLoopCorrGrid, kWG, 0, s>>>(ce, nullptr, 0, -1, nullptr);   // sums the splits too
         } else {
-            force_kernel<PrecMixed, false, false><<<kLoopForceGrid, kWG, 0, s>>>(d_tab, 1, -1);
-            dev_correct_kernel<PrecMixed><<<kLoopCorrGrid, kWG, 0, s>>>(ce, nullptr, 0, -1);
+            force_kernel<PrecMixed, false, false><<<kLoopForceGrid, kWG, 0, s>>>(d_tab, 1, -1, &d_tab->n_items);
+            dev_correct_kernel<PrecMixed><<<kLoopCorrGrid, kWG, 0, s>>>(ce, nullptr, 0, -1, nullptr);
         }
     }
     const hipError_t launch = hipGetLastError();
@@ -2857,6 +3023,33 @@ size_t batch_rows_bytes(int32_t max_clusters, int64_t max_rows) {
     return align_up(static_cast<size_t>(max_clusters) * sizeof(UpdEntry)) + static_cast<size_t>(max_rows) * sizeof(ht_row);
 }
 
+constexpr int kMaxLoopCallSteps = 4096;   // engine steps per ht_batch_dev_run call
+
+// The batched device loop's tables, one entry per context of the batch.
+struct LoopRegion {
+    size_t sched, plan, corr, tab, lctx, counts, ts, total;
+};
+
+LoopRegion loop_region(int32_t max_clusters) {
+    LoopRegion r{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    const size_t m = static_cast<size_t>(max_clusters);
+    r.sched = take(m * sizeof(SchedEntry));
+    r.plan = take(m * sizeof(PlanArgs));
+    r.corr = take(m * sizeof(CorrEntry));
+    r.tab = take(m * sizeof(Entry));
+    r.lctx = take(m * sizeof(LoopCtx));
+    r.counts = take(sizeof(LoopCounts));
+    r.ts = take(static_cast<size_t>(kMaxLoopCallSteps) * 8);
+    r.total = o;
+    return r;
+}
+
 bool batch_args_ok(int32_t max_clusters, int64_t max_items, int64_t max_active, int64_t max_rows) {
     return max_clusters >= 1 && max_clusters <= kMaxBatch && max_items >= 1 && max_active >= 1 && max_rows >= 1 &&
            max_items < (int64_t(1) << 31) && max_active < (int64_t(1) << 31) && max_rows < (int64_t(1) << 31);
@@ -2899,10 +3092,10 @@ void ring_all_free(PinnedRing& r) {
     for (bool& p : r.pending) p = false;
 }
 
-int check_member(const ht_batch* b, const ht_ctx* c, int32_t k, ht_ctx* const* ctxs) {
+int check_member(const ht_batch* b, const ht_ctx* c, int32_t k, ht_ctx* const* ctxs, bool same_stream = true) {
     if (!c) return fail(HT_EINVAL, "ctx %d is NULL", k);
     if (c->cfg.device != b->device) return fail(HT_EINVAL, "ctx %d is on another device", k);
-    if (c->stream != b->stream) return fail(HT_EINVAL, "ctx %d does not share the batch's stream", k);
+    if (same_stream && c->stream != b->stream) return fail(HT_EINVAL, "ctx %d does not share the batch's stream", k);
     if (c->cfg.precision != ctxs[0]->cfg.precision || c->cfg.predict_mode != ctxs[0]->cfg.predict_mode)
         return fail(HT_EINVAL, "ctx %d differs in precision or predict mode", k);
     for (int32_t q = 0; q < k; ++q)
@@ -2920,7 +3113,7 @@ int ht_batch_workspace_bytes(int32_t max_clusters, int64_t max_items, int64_t ma
         return fail(HT_EINVAL, "invalid batch capacities");
     // update rows are read by the scatter kernel from pinned host staging:
     // the device workspace holds the work plan only
-    *bytes = align_up(batch_plan_bytes(max_clusters, max_items, max_active));
+    *bytes = align_up(batch_plan_bytes(max_clusters, max_items, max_active)) + loop_region(max_clusters).total;
     return HT_OK;
 }
 
@@ -2954,6 +3147,7 @@ int ht_batch_create(ht_batch** out, int32_t device, void* stream, int32_t max_cl
         if (hipMalloc(&b->ws, need) != hipSuccess) return cleanup(fail(HT_ENOMEM, "hipMalloc of %zu bytes failed", need));
         b->own_ws = true;
     }
+    b->loop_ws = b->ws + b->plan_bytes;
     rc = ring_init(b->plan_ring, b->plan_bytes);
     if (rc) return cleanup(rc);
     rc = ring_init(b->rows_ring, b->rows_bytes);
@@ -2973,6 +3167,12 @@ int ht_batch_destroy(ht_batch* b) {
     ring_free(b->plan_ring);
     ring_free(b->rows_ring);
     if (b->h_err) (void)hipHostFree(b->h_err);
+    if (b->loop_exec) (void)hipGraphExecDestroy(b->loop_exec);
+    if (b->loop_graph) (void)hipGraphDestroy(b->loop_graph);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->h_lparams) (void)hipHostFree(b->h_lparams);
+    if (b->h_lres) (void)hipHostFree(b->h_lres);
+    if (b->h_ts) (void)hipHostFree(b->h_ts);
     for (hipEvent_t e : b->tm.pool) (void)hipEventDestroy(e);
     if (b->own_ws && b->ws) (void)hipFree(b->ws);
     delete b;
@@ -3258,6 +3458,198 @@ int ht_batch_dev_step(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs, const dou
         ctxs[k]->predicted = false;
     }
     return HT_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Capture kLoopGraphSteps engine steps of the batched device loop over the
+// n_ctx contexts whose tables sit in the batch's loop region.
+template <class P>
+int build_batch_loop_graph(ht_batch* b, int32_t n_ctx) {
+    if (b->loop_exec) {
+        (void)hipGraphExecDestroy(b->loop_exec);
+        b->loop_exec = nullptr;
+    }
+    if (b->loop_graph) {
+        (void)hipGraphDestroy(b->loop_graph);
+        b->loop_graph = nullptr;
+    }
+    if (!b->cap_stream) HT_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    const LoopRegion R = loop_region(b->max_clusters);
+    char* w = b->loop_ws;
+    const SchedEntry* d_sched = reinterpret_cast<const SchedEntry*>(w + R.sched);
+    const PlanArgs* d_plan = reinterpret_cast<const PlanArgs*>(w + R.plan);
+    CorrEntry* d_corr = reinterpret_cast<CorrEntry*>(w + R.corr);
+    Entry* d_tab = reinterpret_cast<Entry*>(w + R.tab);
+    const LoopCtx* d_lctx = reinterpret_cast<const LoopCtx*>(w + R.lctx);
+    LoopCounts* d_cnt = reinterpret_cast<LoopCounts*>(w + R.counts);
+    int64_t* d_ts = reinterpret_cast<int64_t*>(w + R.ts);
+    const SchedEntry none{};
+    const CorrEntry cnone{};
+    hipStream_t s = b->cap_stream;
+    HT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < kLoopGraphSteps; ++k) {
+        sched_min_kernel<<<b->loop_blocks, kWG, 0, s>>>(none, d_sched, n_ctx);
+        sched_count_kernel<<<b->loop_blocks, kWG, 0, s>>>(none, d_sched, n_ctx);
+        sched_write_kernel<<<b->loop_blocks, kWG, 0, s>>>(none, d_sched, n_ctx);
+        dev_plan_batch_kernel<<<n_ctx, kPlanWG, 0, s>>>(d_plan);   // each context takes its step (or stops) and plans it
+        batch_loop_table_kernel<<<1, kLoopTabWG, 0, s>>>(d_tab, d_corr, d_lctx, n_ctx, d_cnt, d_ts, kMaxLoopCallSteps);
+        force_kernel<P, false, false><<<kLoopForceGrid, kWG, 0, s>>>(d_tab, n_ctx, -1, &d_cnt->items);
+        dev_correct_kernel<P><<<kLoopCorrGrid, kWG, 0, s>>>(cnone, d_corr, n_ctx, -1, &d_cnt->rows);
+    }
+    const hipError_t launch = hipGetLastError();
+    hipGraph_t g = nullptr;
+    const hipError_t end = hipStreamEndCapture(s, &g);
+    if (launch != hipSuccess || end != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(HT_EHIP, "capturing the batched device-loop graph failed: %s",
+                    hipGetErrorString(launch != hipSuccess ? launch : end));
+    }
+    b->loop_graph = g;
+    HT_HIP(hipGraphInstantiate(&b->loop_exec, g, nullptr, nullptr, 0));
+    return HT_OK;
+}
+
+// The tables of the batched device loop for these contexts, and its graph,
+// unless the last call used the same contexts with the same sizes and tunings.
+int prepare_batch_loop(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs) {
+    std::vector<double> key;
+    key.reserve(static_cast<size_t>(n_ctx) * 3);
+    for (int32_t k = 0; k < n_ctx; ++k) {
+        key.push_back(static_cast<double>(ctxs[k]->n));
+        key.push_back(ctxs[k]->gather_cost);
+        key.push_back(ctxs[k]->target_items);
+    }
+    if (b->loop_exec && b->loop_ctxs.size() == static_cast<size_t>(n_ctx) &&
+        std::equal(b->loop_ctxs.begin(), b->loop_ctxs.end(), ctxs) && b->loop_key == key)
+        return HT_OK;
+    const LoopRegion R = loop_region(b->max_clusters);
+    char* w = b->loop_ws;
+    std::vector<SchedEntry> sched(n_ctx);
+    std::vector<PlanArgs> plan(n_ctx);
+    std::vector<CorrEntry> corr(n_ctx);
+    std::vector<LoopCtx> lctx(n_ctx);
+    std::vector<Entry> tab(n_ctx);
+    int32_t blocks = 0;
+    for (int32_t k = 0; k < n_ctx; ++k) {
+        const ht_ctx* c = ctxs[k];
+        sched[k] = loop_sched_entry(c, blocks);
+        blocks += sched[k].nb;
+        plan[k] = plan_args_of(c, reinterpret_cast<Entry*>(w + R.tab) + k);
+        corr[k] = loop_corr_entry(c, plan[k]);
+        lctx[k] = LoopCtx{c->d_loop, c->d_dout};
+        tab[k] = Entry{};
+    }
+    const size_t nk = static_cast<size_t>(n_ctx);
+    HT_HIP(hipMemcpyAsync(w + R.sched, sched.data(), nk * sizeof(SchedEntry), hipMemcpyHostToDevice, b->stream));
+    HT_HIP(hipMemcpyAsync(w + R.plan, plan.data(), nk * sizeof(PlanArgs), hipMemcpyHostToDevice, b->stream));
+    HT_HIP(hipMemcpyAsync(w + R.corr, corr.data(), nk * sizeof(CorrEntry), hipMemcpyHostToDevice, b->stream));
+    HT_HIP(hipMemcpyAsync(w + R.lctx, lctx.data(), nk * sizeof(LoopCtx), hipMemcpyHostToDevice, b->stream));
+    HT_HIP(hipMemcpyAsync(w + R.tab, tab.data(), nk * sizeof(Entry), hipMemcpyHostToDevice, b->stream));
+    HT_HIP(hipStreamSynchronize(b->stream));   // pageable sources
+    b->loop_blocks = blocks;
+    const int rc = ctxs[0]->cfg.precision == HT_PREC_FP64 ? build_batch_loop_graph<PrecFp64>(b, n_ctx)
+                                                           : build_batch_loop_graph<PrecMixed>(b, n_ctx);
+    if (rc) {
+        b->loop_ctxs.clear();
+        return rc;
+    }
+    b->loop_ctxs.assign(ctxs, ctxs + n_ctx);
+    b->loop_key = key;
+    return HT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ht_batch_dev_run(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs, const double* eta, const double* dt_tree,
+                     const double* t_stop, const int32_t* max_steps, int32_t engine_steps, int32_t* steps,
+                     double* t_last, int64_t* particle_steps, int64_t* pairs, double* step_ms,
+                     int32_t* n_step_ms) {
+    if (!b) return fail(HT_EINVAL, "batch is NULL");
+    if (n_ctx < 1 || n_ctx > b->max_clusters) return fail(HT_EINVAL, "n_ctx = %d outside [1, %d]", n_ctx, b->max_clusters);
+    if (!ctxs || !eta || !dt_tree || !t_stop || !max_steps || !steps || !t_last || !particle_steps || !pairs ||
+        !step_ms || !n_step_ms)
+        return fail(HT_EINVAL, "NULL argument");
+    if (engine_steps < 1 || engine_steps > kMaxLoopCallSteps)
+        return fail(HT_EINVAL, "engine_steps = %d outside [1, %d]", engine_steps, kMaxLoopCallSteps);
+    for (int32_t k = 0; k < n_ctx; ++k) {
+        ht_ctx* c = ctxs[k];
+        int rc = check_member(b, c, k, ctxs, false);
+        if (rc) return rc;
+        if (max_steps[k] < 0) return fail(HT_EINVAL, "ctx %d: max_steps < 0", k);
+        if (max_steps[k] == 0) continue;   // sits out: its host state may be in use elsewhere
+        if (!c->ds_mem) return fail(HT_ESTATE, "ctx %d: device state not enabled", k);
+        if (!c->have_lists) return fail(HT_ESTATE, "ctx %d: interaction lists not set", k);
+        if (c->cfg.predict_mode != HT_PREDICT_FUSED) return fail(HT_EINVAL, "ctx %d: the device loop needs fused prediction", k);
+        if (c->gather_cost != std::floor(c->gather_cost))
+            return fail(HT_EINVAL, "ctx %d: the device loop plans with a whole-number gather cost", k);
+        if (!(eta[k] > 0.0) || !(dt_tree[k] > 0.0) || !std::isfinite(t_stop[k]))
+            return fail(HT_EINVAL, "ctx %d: bad eta, dt_tree or t_stop", k);
+    }
+    int rc = prepare_batch_loop(b, n_ctx, ctxs);
+    if (rc) return rc;
+    if (!b->h_lparams) {
+        const size_t m = static_cast<size_t>(b->max_clusters);
+        if (hipHostMalloc(reinterpret_cast<void**>(&b->h_lparams), m * sizeof(LoopParams), hipHostMallocDefault) !=
+                hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void**>(&b->h_lres), m * sizeof(LoopResult), hipHostMallocDefault) !=
+                hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void**>(&b->h_ts), (kMaxLoopCallSteps + 2) * sizeof(int64_t),
+                          hipHostMallocDefault) != hipSuccess)
+            return fail(HT_ENOMEM, "hipHostMalloc for the batched device loop failed");
+    }
+    for (int32_t k = 0; k < n_ctx; ++k) {
+        b->h_lparams[k] = LoopParams{t_stop[k], eta[k], dt_tree[k], std::min<int64_t>(max_steps[k], engine_steps)};
+        if (max_steps[k] == 0) continue;
+        ctxs[k]->dev_n_active = -1;
+        ctxs[k]->slots_all_free();
+    }
+    const LoopRegion R = loop_region(b->max_clusters);
+    char* w = b->loop_ws;
+    const LoopCtx* d_lctx = reinterpret_cast<const LoopCtx*>(w + R.lctx);
+    LoopCounts* d_cnt = reinterpret_cast<LoopCounts*>(w + R.counts);
+    const int64_t* d_ts = reinterpret_cast<const int64_t*>(w + R.ts);
+    const int grid = (n_ctx + kWG - 1) / kWG;
+    batch_loop_init_kernel<<<grid, kWG, 0, b->stream>>>(d_lctx, b->h_lparams, n_ctx, d_cnt);
+    HT_HIP(hipGetLastError());
+    for (int32_t q = 0; q < engine_steps; q += kLoopGraphSteps) HT_HIP(hipGraphLaunch(b->loop_exec, b->stream));
+    batch_loop_results_kernel<<<grid, kWG, 0, b->stream>>>(d_lctx, n_ctx, b->h_lres, d_cnt, d_ts, kMaxLoopCallSteps,
+                                                          b->h_ts);
+    HT_HIP(hipGetLastError());
+    HT_HIP(hipStreamSynchronize(b->stream));
+    ring_all_free(b->plan_ring);
+    ring_all_free(b->rows_ring);
+    int bad = -1, bad_plan = -1;
+    for (int32_t k = 0; k < n_ctx; ++k) {
+        ht_ctx* c = ctxs[k];
+        const LoopResult& r = b->h_lres[k];
+        steps[k] = static_cast<int32_t>(r.steps);
+        particle_steps[k] = r.psteps;
+        pairs[k] = r.pairs;
+        if (max_steps[k] == 0) {
+            t_last[k] = std::numeric_limits<double>::quiet_NaN();
+            continue;
+        }
+        if (r.steps > 0) c->dev_t_next = r.t_cur;
+        t_last[k] = c->dev_t_next;
+        c->last_pairs = r.pairs;
+        c->predicted = false;
+        if (r.below_floor && bad < 0) bad = k;
+        if (r.err && bad_plan < 0) bad_plan = k;
+    }
+    int rate_khz = 0;
+    HT_HIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, b->device));
+    const int64_t m = std::min<int64_t>(b->h_ts[0], engine_steps);
+    for (int64_t q = 0; q < m; ++q)
+        step_ms[q] = static_cast<double>(b->h_ts[2 + q] - b->h_ts[1 + q]) / std::max(rate_khz, 1);
+    *n_step_ms = static_cast<int32_t>(m);
+    if (bad >= 0) return fail(HT_ERANGE, "ctx %d: a corrected block step fell below 2^-40", bad);
+    if (bad_plan >= 0) return fail(HT_ERANGE, "ctx %d: a device work plan exceeded the context's capacity", bad_plan);
+    return take_row_error(b->h_err);
 }
 
 int ht_batch_sync(ht_batch* b) {

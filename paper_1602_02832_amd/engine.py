@@ -12,6 +12,16 @@ engine step advances every resident cluster by one of its own block steps:
   4. each cluster corrects its particles on the host; clusters at a tree time
      rebuild their tree and lists.
 
+The resident engine can run as a device loop (``device_loop=True``): one
+``Engine.step`` call queues up to ``loop_steps`` engine steps (scheduler,
+device planner, one force launch and one corrector launch for all clusters
+per engine step, captured in HIP graphs) with no host round trip between
+them.  A cluster that reaches a tree time stops there; it is rebuilt on its
+own stream by a worker thread while later calls run the other clusters, and
+sits those calls out until its rebuild is done (the set of clusters in a
+call stays the same, so the captured graph is kept).  Each cluster's block
+steps, and their bits, are those of the step-by-step engine.
+
 The resident engine can split its clusters into lanes, each with a stream
 and a batch object of its own, stepped in turn: while the device works on
 one lane's step, the host waits for the next lane's scheduler and plans that
@@ -146,8 +156,21 @@ class Engine:
     """Advances a set of clusters one block step each per engine step."""
 
     def __init__(self, precision="mixed", device=0, max_clusters=256, max_active=1 << 21, max_items=1 << 20,
-                 max_rows=1 << 21, rebuild_workers=4, resident=False, device_tree=False, tree_n_max=0, lanes=None):
+                 max_rows=1 << 21, rebuild_workers=4, resident=False, device_tree=False, tree_n_max=0, lanes=None,
+                 device_loop=False, loop_steps=32):
         import torch
+
+        # device_loop (resident only): each step() call runs up to loop_steps engine steps on the
+        # device (ht_batch_dev_run); tree times are rebuilt between calls
+        self.device_loop = bool(device_loop)
+        self.loop_steps = int(loop_steps)
+        if self.device_loop and not resident:
+            raise ValueError("the device loop needs the resident engine")
+        if self.device_loop and not (1 <= self.loop_steps <= 4096):
+            raise ValueError("loop_steps must be in [1, 4096]")
+        self.engine_steps = 0   # engine steps taken (a device-loop call takes several)
+        self._loop_view = None  # device loop: (composition generation, clusters, arrays)
+        self._loop_gen = 0      # changes when clusters join or leave the device loop
 
         # resident: each cluster's particle state stays on the device; the block
         # scheduler and the corrector of all clusters run there in batched launches
@@ -172,6 +195,9 @@ class Engine:
         if self.n_lanes < 1 or (self.n_lanes > 1 and not self.resident):
             raise ValueError("more than one lane needs the resident engine")
         self.streams = [torch.cuda.Stream(device=device) for _ in range(self.n_lanes)]
+        # device loop: the clusters' contexts live on a stream of their own, so that a
+        # cluster's rebuild runs beside the batch's loop calls
+        self._ctx_stream = torch.cuda.Stream(device=device) if self.device_loop else None
         self.batches = [B.Batch(stream=st.cuda_stream, max_clusters=max_clusters, max_items=max_items,
                                 max_active=max_active, max_rows=max_rows, device=device) for st in self.streams]
         self.stream, self.batch = self.streams[0], self.batches[0]   # the host-driven engine's one lane
@@ -212,7 +238,8 @@ class Engine:
         shared = self.tree is not None and spec.n <= self.tree_n_max
         lane = self._next_lane                 # lanes in turn, fixed for the cluster's life
         self._next_lane = (lane + 1) % self.n_lanes
-        c = Cluster(spec, self.precision, self.streams[lane].cuda_stream, self.device, resident=self.resident,
+        stream = self._ctx_stream if self.device_loop else self.streams[lane]
+        c = Cluster(spec, self.precision, stream.cuda_stream, self.device, resident=self.resident,
                     tree=self.tree if shared else None, tree_lock=self.tree_lock if shared else None)
         c.lane = lane
         return c
@@ -225,10 +252,12 @@ class Engine:
             c.ctx.set_tuning(*self.tuning)
         self.clusters.append(c)
         self._gen += 1
+        self._loop_gen += 1
 
     def set_tuning(self, gather_cost: float, target_items: float):
         """Work-plan tuning (ht_set_tuning) for every resident and future cluster."""
         self.tuning = (float(gather_cost), float(target_items))
+        self.drain()
         for c in self.clusters:
             c.ctx.set_tuning(*self.tuning)
 
@@ -299,6 +328,8 @@ class Engine:
         that finished their run in this step."""
         t0 = time.perf_counter()
         self._collect_rebuilds()
+        if self.device_loop:
+            return self._step_loop(t0)
         if self.resident:
             views = self._lane_views()
             if not views:
@@ -389,6 +420,7 @@ class Engine:
         sub["correct"] += te - t2
         sub["bookkeeping"] += t3 - te
         self.step_ms.append(1e3 * dt)
+        self.engine_steps += 1
         self.wall += dt
         self.pairs += pairs
         self.equiv_pairs += int(sum(int(n) * (c.sim.n - 1) for c, n in zip(cl, n_act)))
@@ -467,10 +499,79 @@ class Engine:
         sub["plan_launch"] += t_plan
         sub["bookkeeping"] += dt - t_sync - t_plan
         self.step_ms.append(1e3 * dt)
+        self.engine_steps += 1
         self.wall += dt
         self.pairs += pairs
         self.equiv_pairs += equiv
         return finished
+
+    def _loop_clusters(self):
+        """The clusters of the device loop's calls (every unfinished one, also
+        while it is being rebuilt) and their fixed arrays, cached until a
+        cluster joins or leaves or gets a new context."""
+        lv = self._loop_view
+        if lv is not None and lv[0] == self._loop_gen:
+            return lv[1:]
+        lc = [c for c in self.clusters if not c.done]
+        handles = np.fromiter((c.sim.ctx.handle.value for c in lc), dtype=np.uint64, count=len(lc))
+        eta = np.fromiter((c.sim.eta for c in lc), dtype=np.float64, count=len(lc))
+        dtt = np.fromiter((c.sim.dt_tree for c in lc), dtype=np.float64, count=len(lc))
+        nm1 = np.fromiter((c.sim.n - 1 for c in lc), dtype=np.int64, count=len(lc))
+        self._loop_view = (self._loop_gen, lc, handles, eta, dtt, nm1)
+        return self._loop_view[1:]
+
+    def _step_loop(self, t0):
+        """Up to loop_steps engine steps on the device.  Every cluster stops at
+        its next tree time or at the end of its run; one stopped at a tree time
+        is handed to a rebuild worker and sits out the calls until it is done."""
+        lc, handles, eta, dtt, nm1 = self._loop_clusters()
+        if not lc:
+            if self.rebuilding:
+                self._collect_rebuilds(wait=True)
+            return []
+        busy = np.fromiter((c in self.rebuilding for c in lc), dtype=bool, count=len(lc))
+        if busy.all():                       # every cluster is being rebuilt: wait for one
+            next(iter(self.rebuilding.values())).result()
+            self._collect_rebuilds()
+            busy = np.fromiter((c in self.rebuilding for c in lc), dtype=bool, count=len(lc))
+        t_stop = np.array([(math.floor(c.sim.t / c.sim.dt_tree) + 1.0) * c.sim.dt_tree for c in lc])
+        left = np.array([0 if b else c.spec.steps - c.steps_done for c, b in zip(lc, busy)], dtype=np.int32)
+        steps, t_last, psteps, pr, step_ms = self.batch.dev_run(handles, eta, dtt, t_stop, left, self.loop_steps)
+        finished = []
+        changed = False
+        for k in np.flatnonzero(steps).tolist():
+            c = lc[k]
+            sim = c.sim
+            sim.t = float(t_last[k])
+            sim.n_block_steps += int(steps[k])
+            sim.n_particle_steps += int(psteps[k])
+            c.steps_done += int(steps[k])
+            c.active_sum += int(psteps[k])
+            if c.done:
+                finished.append(c)
+                changed = True
+            elif t_last[k] == t_stop[k]:     # tree time: rebuilt beside the next calls
+                if self.pool is not None:
+                    self.rebuilding[c] = self.pool.submit(self._loop_rebuild, c)
+                else:
+                    self._loop_rebuild(c)
+        if changed:
+            self._gen += 1
+            self._loop_gen += 1
+        dt = time.perf_counter() - t0
+        self.phase["device_wait"] += dt
+        self.engine_steps += len(step_ms)
+        self.step_ms.extend(step_ms.tolist())
+        self.wall += dt
+        self.pairs += int(pr.sum())
+        self.equiv_pairs += int(np.dot(psteps, nm1))
+        return finished
+
+    def _loop_rebuild(self, c):
+        h = c.sim.ctx.handle.value
+        c.sim.rebuild_resident()
+        if c.sim.ctx.handle.value != h:      # a larger context (host fallback): the loop's set changed
+            self._loop_gen += 1
 
     def drain(self):
         """Wait for rebuilds in flight."""
@@ -481,6 +582,7 @@ class Engine:
             self.rebuilding.pop(c).result()
         self.clusters.remove(c)
         self._gen += 1
+        self._loop_gen += 1
 
     def close(self):
         self.drain()

@@ -79,7 +79,7 @@ def run_engine(specs, **kw):
         eng.step()
     eng.drain()
     out = [state(c.sim) for c in clusters]
-    stats = (eng.pairs, len(eng.step_ms), [c.steps_done for c in clusters])
+    stats = (eng.pairs, eng.engine_steps, [c.steps_done for c in clusters])
     eng.close()
     return out, stats
 
@@ -290,3 +290,45 @@ def test_engine_many_clusters_alone_equals_in_batch(resident):
         alone, _ = run_engine([specs[k]], resident=resident)
         for f in FIELDS:
             assert np.array_equal(alone[0][f], together[k][f]), (k, f)
+
+
+def test_batched_device_loop_equals_resident_engine():
+    """The batched device loop (ht_batch_dev_run: scheduler, device planner,
+    one force and one corrector launch for all clusters per engine step,
+    graphs of 32 engine steps, no host round trip) gives every cluster the
+    bits of the step-by-step resident engine, through tree rebuilds on the
+    device, alone and in a mix, for calls of 7, 32 and 45 engine steps."""
+    say("engine: batched device loop vs resident engine")
+    specs = [E.RunSpec(key=k, n=n, seed=1100 + k, steps=70, n_crit=64) for k, n in enumerate((700, 2500, 1200, 4000))]
+    kw = dict(resident=True, device_tree=True, tree_n_max=4000)
+    ref, (_, _, done) = run_engine(specs, **kw)
+    assert done == [70] * 4
+    for loop_steps in (7, 32, 45):
+        got, (pairs, _, done) = run_engine(specs, device_loop=True, loop_steps=loop_steps, **kw)
+        assert done == [70] * 4 and pairs > 0
+        for k in range(len(specs)):
+            for f in FIELDS:
+                assert np.array_equal(ref[k][f], got[k][f]), (loop_steps, k, f)
+    alone, _ = run_engine([specs[2]], device_loop=True, loop_steps=32, **kw)
+    for f in FIELDS:
+        assert np.array_equal(alone[0][f], ref[2][f]), f
+
+
+def test_batched_device_loop_steps_match_oracle(oracle):
+    """Single engine steps of the batched device loop (host rebuilds, so the
+    tree's node data are at hand) against the oracle's list force."""
+    say("engine: batched device loop steps vs oracle")
+    specs = [E.RunSpec(key=k, n=n, seed=1200 + k, steps=10**6, n_crit=64, mass_seed=(1250 + k) if k % 2 else None)
+             for k, n in enumerate((600, 2100, 900))]
+    eng = E.Engine(max_clusters=8, max_active=1 << 15, max_items=1 << 15, max_rows=1 << 15, rebuild_workers=0,
+                   resident=True, device_loop=True, loop_steps=1)
+    for sp in specs:
+        eng.add(eng.new_cluster(sp))
+    checked = 0
+    for k in range(60):
+        if k % 4 == 0:
+            checked += oracle_checked_step(eng, oracle, f"device-loop engine step {k}")[0]
+        else:
+            eng.step()
+    eng.close()
+    assert checked >= 30, checked
