@@ -405,7 +405,7 @@ def bench_ensemble(args, torch):
             "kernel": "force_kernel<PrecMixed,false,false>", "avg_launch_ms": kms / max(nl, 1)},
     }
     eng.close()
-    print(json.dumps(res), flush=True)
+    return res
 
 
 def bench_served(args, torch):
@@ -431,7 +431,9 @@ def bench_served(args, torch):
         done = srv.run(reqs)
         span = time.perf_counter() - t
         out = dict(span=span, done=done, step_ms=list(eng.step_ms), pairs=eng.pairs, phase=dict(eng.phase),
-                   max_used=srv.max_used, max_waiting=srv.max_waiting, lanes=eng.n_lanes)
+                   max_used=srv.max_used, max_waiting=srv.max_waiting, lanes=eng.n_lanes,
+                   refused=len(srv.refused))
+        srv.close()
         eng.close()
         return out
 
@@ -464,8 +466,9 @@ def bench_served(args, torch):
         "request_latency_s": {"p50": float(np.percentile(resp, 50)), "p99": float(np.percentile(resp, 99))},
         "queue_delay_s": {"p50": float(np.percentile(queue, 50)), "p99": float(np.percentile(queue, 99))},
         "max_hbm_used_gb": run["max_used"] / 2**30, "max_waiting": run["max_waiting"], "phase_s": run["phase"],
+        "refused": run["refused"],
     }
-    print(json.dumps(res), flush=True)
+    return res
 
 
 def main():
@@ -501,6 +504,8 @@ def main():
     ap.add_argument("--hbm-gb", type=float, default=64.0, help="served workload: device-memory budget")
     ap.add_argument("--device-loop", action="store_true",
                     help="ensemble workload: run the resident engine as a batched device loop")
+    ap.add_argument("--no-engine-records", action="store_true",
+                    help="default workload: skip the short ensemble64 and served records")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (scale for the byte counters)")
     args = ap.parse_args()
@@ -523,9 +528,11 @@ def main():
     if args.calibrate_copy:
         return calibrate_copy(torch, args.calibrate_copy)
     if args.workload == "ensemble64":
-        return bench_ensemble(args, torch)
+        print(json.dumps(bench_ensemble(args, torch)), flush=True)
+        return
     if args.workload == "served":
-        return bench_served(args, torch)
+        print(json.dumps(bench_served(args, torch)), flush=True)
+        return
     cfg = W.config(args.workload)
     if args.n:
         cfg = W.config(args.workload, n=args.n, eps=4.0 / args.n)
@@ -782,6 +789,24 @@ def main():
     if cpu is not None:
         result["cpu_baseline"] = cpu
         result["cpu_oracle_other"] = cpu_extra
+    # the batched ensemble and the served stream, short forms (their own --workload runs are the long ones)
+    if not args.no_engine_records:
+        sub = argparse.Namespace(**vars(args))
+        sub.steps, sub.warmup, sub.tuning, sub.device_loop = 32, 8, "12,1024", True
+        ens = bench_ensemble(sub, torch)
+        result["ensemble64"] = {k: ens[k] for k in ("metric", "value", "unit", "ms_per_step", "p50_step_ms",
+                                                    "p99_step_ms", "equivalent_interactions_per_s", "steps",
+                                                    "warmup", "config")}
+        log(f"ensemble64 record: {ens['value']:.4g} interactions/s, {ens['ms_per_step']:.3f} ms per engine step")
+        sub = argparse.Namespace(**vars(args))
+        sub.requests, sub.tuning = 64, ""
+        srv = bench_served(sub, torch)
+        result["served"] = {k: srv[k] for k in ("metric", "value", "unit", "p50_step_ms", "p99_step_ms",
+                                                "interactions_per_s", "capacity_runs_per_s", "throughput_runs_per_s",
+                                                "request_latency_s", "queue_delay_s", "max_hbm_used_gb", "refused",
+                                                "config")}
+        log(f"served record: p50 {srv['p50_step_ms']:.3f} ms, p99 {srv['p99_step_ms']:.3f} ms per engine step, "
+            f"{srv['interactions_per_s']:.4g} interactions/s")
     print(json.dumps(result), flush=True)
 
 

@@ -209,6 +209,14 @@ int ht_step_graph(ht_ctx *ctx, int32_t n_upd, const int32_t *d_idx, const double
  * tree needs more nodes, groups or list entries than the context holds.
  * Synchronous. */
 int ht_state_enable(ht_ctx *ctx);
+/* Device bytes of the resident state of a context with this configuration,
+ * and ht_state_enable on caller-owned device memory of at least that many
+ * bytes (256-byte aligned, outliving the context), so that all of a
+ * cluster's device memory can come from the caller's allocator.  Either form
+ * also allocates 4 (n_max + 1) + 24 bytes of pinned host memory for the
+ * scheduler's results. */
+int ht_state_bytes(const ht_config *cfg, size_t *bytes);
+int ht_state_enable_ws(ht_ctx *ctx, void *d_mem, size_t bytes);
 int ht_state_set(ht_ctx *ctx, int32_t n, const double *t0, const double *dt, const double *m, const double *x,
                  const double *v, const double *a, const double *jerk, const double *pot);
 int ht_state_get(ht_ctx *ctx, double *t0, double *dt, double *x, double *v, double *a, double *jerk, double *pot);
@@ -375,6 +383,28 @@ int ht_force_direct_noalloc(int32_t device, void *stream, int32_t precision, int
                             const double *d_v, const double *d_m, double eps2, int32_t n_active,
                             const int32_t *d_active, int32_t j_splits, double *d_acc, double *d_jerk,
                             double *d_pot);
+
+/* ---------------------------------------------------------------------------
+ * Admission by device footprint (the served stream of cluster runs).  A pool
+ * is a budget of device bytes on one GPU and the reservations held against
+ * it; it allocates nothing itself.  ht_cluster_admit reserves what a cluster
+ * with this configuration will hold: ht_workspace_bytes, plus ht_state_bytes
+ * when resident (*bytes receives the figure).  HT_ENOMEM: it does not fit
+ * beside the reservations held now (the caller waits for a release);
+ * HT_ERANGE: it exceeds the whole budget and never fits (the caller refuses
+ * it).  ht_pool_reserve holds other device memory against the budget (for
+ * example a tree builder that clusters share, htd_device_bytes);
+ * ht_pool_resize records a reservation's new size (a cluster moved to a
+ * larger context, a builder that grew) and returns HT_ENOMEM when the pool is
+ * then over its budget (the size is recorded either way).  Thread-safe. */
+typedef struct ht_pool ht_pool;
+int ht_pool_create(ht_pool **out, int32_t device, size_t budget_bytes);
+int ht_pool_destroy(ht_pool *p);
+int ht_cluster_admit(ht_pool *p, const ht_config *cfg, int32_t resident, int64_t *id, size_t *bytes);
+int ht_pool_reserve(ht_pool *p, size_t bytes, int64_t *id);
+int ht_pool_resize(ht_pool *p, int64_t id, size_t bytes);
+int ht_cluster_release(ht_pool *p, int64_t id);
+int ht_pool_usage(ht_pool *p, size_t *used, size_t *budget, int32_t *n_held);
 
 /* Block until the context's queued work has finished. */
 int ht_sync(ht_ctx *ctx);

@@ -35,6 +35,7 @@
 #ifndef HTREE_TREE_H
 #define HTREE_TREE_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -90,6 +91,10 @@ int htd_device_view(const htd_tree *t, htd_view *out);
 /* Device time of the last build's phases in ms: keys, sort, cells (with the
  * size read-back), moments, lists, CSR assembly, and the total. ms[7]. */
 int htd_phase_ms(const htd_tree *t, double *ms);
+
+/* Device bytes the builder holds now (its arrays grow with the largest tree
+ * built so far), for admission by device footprint. */
+int htd_device_bytes(const htd_tree *t, size_t *bytes);
 
 const char *htd_last_error(void);
 

@@ -151,6 +151,16 @@ def device_lib():
             "ht_force_direct_noalloc": [i, _vp, i, i, _vp, _vp, _vp, d, i, _vp, i, _vp, _vp, _vp],
             "ht_batch_dev_run": [_vp, i, _vp, _vp, _vp, _vp, _vp, i, _vp, _vp, _vp, _vp, _vp,
                                  ctypes.POINTER(ctypes.c_int32)],
+            "ht_state_bytes": [ctypes.POINTER(HtConfig), ctypes.POINTER(ctypes.c_size_t)],
+            "ht_state_enable_ws": [_vp, _vp, ctypes.c_size_t],
+            "ht_pool_create": [ctypes.POINTER(_vp), i, ctypes.c_size_t],
+            "ht_pool_destroy": [_vp],
+            "ht_cluster_admit": [_vp, ctypes.POINTER(HtConfig), i, _c_i64p, ctypes.POINTER(ctypes.c_size_t)],
+            "ht_pool_reserve": [_vp, ctypes.c_size_t, _c_i64p],
+            "ht_pool_resize": [_vp, i64, ctypes.c_size_t],
+            "ht_cluster_release": [_vp, i64],
+            "ht_pool_usage": [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t), _c_i32p],
+            "htd_device_bytes": [_vp, ctypes.POINTER(ctypes.c_size_t)],
             "htd_create": [ctypes.POINTER(_vp), i, _vp, i64],
             "htd_destroy": [_vp],
             "htd_build": [_vp, i64, _vp, _vp, _vp, _vp, _vp, i, i, d],
@@ -284,6 +294,7 @@ class Context:
             device_lib().ht_destroy(self._h)
             self._h = None
             self._ws = None
+            self._state_ws = None
 
     def __del__(self):
         try:
@@ -371,8 +382,20 @@ class Context:
                                           _dptr(d_acc), _dptr(d_jerk), _dptr(d_pot)))
 
     # device-resident integration ------------------------------------------------
-    def state_enable(self):
-        _check(device_lib().ht_state_enable(self._h))
+    def state_enable(self, torch_memory=True):
+        """ht_state_enable: the resident FP64 state, by default in a torch
+        allocation of ht_state_bytes (ht_state_enable_ws), so that all of the
+        context's device memory comes from torch's allocator."""
+        if getattr(self, "_state_ws", None) is not None:
+            return
+        if torch_memory:
+            import torch
+            nbytes = state_bytes(self.cfg)
+            self._state_ws = torch.empty(nbytes, dtype=torch.uint8, device=f"cuda:{self.cfg.device}")
+            _check(device_lib().ht_state_enable_ws(self._h, self._state_ws.data_ptr(), nbytes))
+        else:
+            self._state_ws = False
+            _check(device_lib().ht_state_enable(self._h))
 
     def state_set(self, t0, dt, m, x, v, a, jerk, pot=None):
         """ht_state_set: full FP64 state (and the j-records) from host arrays."""
@@ -485,6 +508,69 @@ def force_batch_async(ctxs, actives, d_accs, d_jerks, d_pots):
     Q = (_vp * n)(*[_dptr(t) for t in d_pots])
     _check(device_lib().ht_force_batch_async(n, H, N, P, A, J, Q))
     return acts  # keep host arrays alive until the caller syncs
+
+
+def state_bytes(cfg) -> int:
+    """ht_state_bytes: device bytes of a resident state for this HtConfig."""
+    out = ctypes.c_size_t()
+    _check(device_lib().ht_state_bytes(ctypes.byref(cfg), ctypes.byref(out)))
+    return int(out.value)
+
+
+class Pool:
+    """Admission by device footprint (ht_pool): a budget of device bytes and
+    the reservations held against it.  admit() returns a reservation id, or
+    None when the cluster does not fit beside what is held now; it raises
+    HTError with code -2 when the cluster exceeds the whole budget."""
+
+    def __init__(self, budget_bytes, device=0):
+        self._h = _vp()
+        _check(device_lib().ht_pool_create(ctypes.byref(self._h), int(device), int(budget_bytes)))
+        self.budget = int(budget_bytes)
+
+    def admit(self, cfg, resident):
+        rid, nbytes = ctypes.c_int64(), ctypes.c_size_t()
+        rc = device_lib().ht_cluster_admit(self._h, ctypes.byref(cfg), int(bool(resident)), ctypes.byref(rid),
+                                           ctypes.byref(nbytes))
+        if rc == -3:
+            return None, int(nbytes.value)
+        _check(rc)
+        return int(rid.value), int(nbytes.value)
+
+    def reserve(self, nbytes):
+        rid = ctypes.c_int64()
+        rc = device_lib().ht_pool_reserve(self._h, int(nbytes), ctypes.byref(rid))
+        if rc == -3:
+            return None
+        _check(rc)
+        return int(rid.value)
+
+    def resize(self, rid, nbytes):
+        """True when the pool is within its budget afterwards (the size is recorded either way)."""
+        rc = device_lib().ht_pool_resize(self._h, int(rid), int(nbytes))
+        if rc == -3:
+            return False
+        _check(rc)
+        return True
+
+    def release(self, rid):
+        _check(device_lib().ht_cluster_release(self._h, int(rid)))
+
+    def usage(self):
+        used, budget, n = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_int32()
+        _check(device_lib().ht_pool_usage(self._h, ctypes.byref(used), ctypes.byref(budget), ctypes.byref(n)))
+        return int(used.value), int(budget.value), int(n.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            device_lib().ht_pool_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def force_direct_noalloc(precision, d_x, d_v, d_m, eps2, d_active, j_splits, d_acc, d_jerk, d_pot, n=None,
@@ -732,6 +818,12 @@ class DeviceTree:
         ms = np.zeros(7)
         _check_tree(device_lib().htd_phase_ms(self._h, _ptr(ms, ctypes.c_double)))
         return dict(zip(self.PHASES, ms.tolist()))
+
+    def device_bytes(self):
+        """Device bytes the builder holds now (htd_device_bytes)."""
+        out = ctypes.c_size_t()
+        _check_tree(device_lib().htd_device_bytes(self._h, ctypes.byref(out)))
+        return int(out.value)
 
     def close(self):
         if self._h:

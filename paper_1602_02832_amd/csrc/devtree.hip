@@ -1048,4 +1048,19 @@ int htd_phase_ms(const htd_tree* t, double* ms) {
     return 0;
 }
 
+int htd_device_bytes(const htd_tree* t, size_t* bytes) {
+    if (!t || !bytes) return fail(HTD_EINVAL, "NULL argument");
+    size_t b = 0;
+    auto add = [&](const auto& buf) { b += sizeof(*buf.p) * static_cast<size_t>(buf.cap); };
+    add(t->key_in), add(t->key), add(t->idx_in), add(t->idx), add(t->perm);
+    add(t->sx), add(t->sv), add(t->sa), add(t->sj), add(t->sm), add(t->lev);
+    add(t->ncell), add(t->cbase), add(t->nnode), add(t->nbase), add(t->gflag), add(t->gbase);
+    add(t->tmp), add(t->part), add(t->root), add(t->tot), add(t->cell);
+    add(t->nm), add(t->nx), add(t->nv), add(t->na), add(t->nj), add(t->nlev), add(t->ncid), add(t->nraw);
+    add(t->nbeg), add(t->nend), add(t->group_first), add(t->list_off), add(t->gstage), add(t->glen64);
+    add(t->glen), add(t->cut), add(t->stage), add(t->entries), add(t->ctr);
+    *bytes = b;
+    return 0;
+}
+
 }  // extern "C"

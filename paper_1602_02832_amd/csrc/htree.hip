@@ -1595,6 +1595,7 @@ struct ht_ctx {
     // buffers on the device, the scheduler's results in pinned host memory
     DevState ds{};
     char* ds_mem = nullptr;
+    bool own_ds = false;   // ds_mem allocated by the library (ht_state_enable), not the caller's
     // device loop (ht_dev_run): its state, the scheduler's results in device
     // memory, the group and list offsets and the planner's scratch
     DevLoop* d_loop = nullptr;
@@ -2205,7 +2206,7 @@ int ht_destroy(ht_ctx* c) {
     if (c->loop_graph) (void)hipGraphDestroy(c->loop_graph);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->h_hdr) (void)hipHostFree(c->h_hdr);
-    if (c->ds_mem) (void)hipFree(c->ds_mem);
+    if (c->ds_mem && c->own_ds) (void)hipFree(c->ds_mem);
     if (c->h_dout) (void)hipHostFree(c->h_dout);
     if (c->h_active) (void)hipHostFree(c->h_active);
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
@@ -2548,54 +2549,117 @@ int upload_group_offsets(ht_ctx* c) {
 }
 }  // namespace
 
-int ht_state_enable(ht_ctx* c) {
-    if (!c) return fail(HT_EINVAL, "ctx is NULL");
-    if (c->ds_mem) return HT_OK;
-    const size_t n = static_cast<size_t>(c->cfg.n_max);
+}  // extern "C"
+
+namespace {
+
+// Where the resident state's arrays sit in its one device allocation.
+struct StateLayout {
+    size_t x, v, a, j, t0, dt, m, pot, acc, jerk, fpot, act, bmin, bcnt;
+    size_t loop, dout, gf, lo, gk, qk, qg, tiles, pgroup;
+    size_t total;
+};
+
+StateLayout state_layout(const ht_config& cfg) {
+    const size_t n = static_cast<size_t>(cfg.n_max);
+    StateLayout S{};
     size_t o = 0;
     auto take = [&](size_t bytes) {
         const size_t at = o;
         o = align_up(o + bytes);
         return at;
     };
-    const size_t ox = take(n * 24), ov = take(n * 24), oa = take(n * 24), oj = take(n * 24);
-    const size_t ot0 = take(n * 8), odt = take(n * 8), om = take(n * 8), opot = take(n * 8);
-    const size_t oacc = take(n * 24), ojerk = take(n * 24), ofpot = take(n * 8), oact = take(n * 4);
-    const size_t obmin = take(kSchedBlocks * 8), obcnt = take(kSchedBlocks * 4);
-    const size_t g1 = static_cast<size_t>(c->cfg.group_max) + 1;
-    const size_t oloop = take(sizeof(DevLoop)), odout = take(sizeof(DevOut)), ogf = take(g1 * 8), olo = take(g1 * 8);
-    const size_t ogk = take(n * 4), oqk = take((n + 1) * 4), oqg = take(n * 4), otl = take(n * sizeof(DTile));
-    const size_t opg = take(n * 4);
-    if (hipMalloc(&c->ds_mem, o) != hipSuccess) {
-        c->ds_mem = nullptr;
-        return fail(HT_ENOMEM, "hipMalloc of %zu bytes for the device state failed", o);
-    }
-    char* b = c->ds_mem;
-    c->ds = DevState{reinterpret_cast<double*>(b + ox), reinterpret_cast<double*>(b + ov),
-                     reinterpret_cast<double*>(b + oa), reinterpret_cast<double*>(b + oj),
-                     reinterpret_cast<double*>(b + ot0), reinterpret_cast<double*>(b + odt),
-                     reinterpret_cast<double*>(b + om), reinterpret_cast<double*>(b + opot),
-                     reinterpret_cast<double*>(b + oacc), reinterpret_cast<double*>(b + ojerk),
-                     reinterpret_cast<double*>(b + ofpot), reinterpret_cast<int32_t*>(b + oact),
-                     reinterpret_cast<double*>(b + obmin), reinterpret_cast<int32_t*>(b + obcnt)};
-    c->d_loop = reinterpret_cast<DevLoop*>(b + oloop);
-    c->d_dout = reinterpret_cast<DevOut*>(b + odout);
-    c->d_gfirst = reinterpret_cast<int64_t*>(b + ogf);
-    c->d_loff = reinterpret_cast<int64_t*>(b + olo);
-    c->d_gk = reinterpret_cast<int32_t*>(b + ogk);
-    c->d_qk = reinterpret_cast<int32_t*>(b + oqk);
-    c->d_qg = reinterpret_cast<int32_t*>(b + oqg);
-    c->d_tiles = reinterpret_cast<DTile*>(b + otl);
-    c->d_pgroup = reinterpret_cast<int32_t*>(b + opg);
+    S.x = take(n * 24);
+    S.v = take(n * 24);
+    S.a = take(n * 24);
+    S.j = take(n * 24);
+    S.t0 = take(n * 8);
+    S.dt = take(n * 8);
+    S.m = take(n * 8);
+    S.pot = take(n * 8);
+    S.acc = take(n * 24);
+    S.jerk = take(n * 24);
+    S.fpot = take(n * 8);
+    S.act = take(n * 4);
+    S.bmin = take(kSchedBlocks * 8);
+    S.bcnt = take(kSchedBlocks * 4);
+    const size_t g1 = static_cast<size_t>(cfg.group_max) + 1;
+    S.loop = take(sizeof(DevLoop));
+    S.dout = take(sizeof(DevOut));
+    S.gf = take(g1 * 8);
+    S.lo = take(g1 * 8);
+    S.gk = take(n * 4);
+    S.qk = take((n + 1) * 4);
+    S.qg = take(n * 4);
+    S.tiles = take(n * sizeof(DTile));
+    S.pgroup = take(n * 4);
+    S.total = o;
+    return S;
+}
+
+// Point the context's resident state at `mem` (laid out by state_layout) and
+// allocate its pinned scheduler results.
+int state_attach(ht_ctx* c, char* mem, bool own) {
+    const StateLayout S = state_layout(c->cfg);
+    c->ds_mem = mem;
+    c->own_ds = own;
+    char* b = mem;
+    c->ds = DevState{reinterpret_cast<double*>(b + S.x), reinterpret_cast<double*>(b + S.v),
+                     reinterpret_cast<double*>(b + S.a), reinterpret_cast<double*>(b + S.j),
+                     reinterpret_cast<double*>(b + S.t0), reinterpret_cast<double*>(b + S.dt),
+                     reinterpret_cast<double*>(b + S.m), reinterpret_cast<double*>(b + S.pot),
+                     reinterpret_cast<double*>(b + S.acc), reinterpret_cast<double*>(b + S.jerk),
+                     reinterpret_cast<double*>(b + S.fpot), reinterpret_cast<int32_t*>(b + S.act),
+                     reinterpret_cast<double*>(b + S.bmin), reinterpret_cast<int32_t*>(b + S.bcnt)};
+    c->d_loop = reinterpret_cast<DevLoop*>(b + S.loop);
+    c->d_dout = reinterpret_cast<DevOut*>(b + S.dout);
+    c->d_gfirst = reinterpret_cast<int64_t*>(b + S.gf);
+    c->d_loff = reinterpret_cast<int64_t*>(b + S.lo);
+    c->d_gk = reinterpret_cast<int32_t*>(b + S.gk);
+    c->d_qk = reinterpret_cast<int32_t*>(b + S.qk);
+    c->d_qg = reinterpret_cast<int32_t*>(b + S.qg);
+    c->d_tiles = reinterpret_cast<DTile*>(b + S.tiles);
+    c->d_pgroup = reinterpret_cast<int32_t*>(b + S.pgroup);
     if (c->have_lists) {   // lists set before the state: their offsets for the device planner
         int rc = upload_group_offsets(c);
         if (rc) return rc;
     }
+    const size_t n = static_cast<size_t>(c->cfg.n_max);
     if (hipHostMalloc(reinterpret_cast<void**>(&c->h_dout), sizeof(DevOut), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&c->h_active), n * 4, hipHostMallocDefault) != hipSuccess)
         return fail(HT_ENOMEM, "hipHostMalloc for the scheduler results failed");
     std::memset(c->h_dout, 0, sizeof(DevOut));
     return HT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ht_state_bytes(const ht_config* cfg, size_t* bytes) {
+    if (!cfg || !bytes) return fail(HT_EINVAL, "NULL argument");
+    Layout L;
+    if (!layout_of(*cfg, L)) return fail(HT_EINVAL, "invalid configuration");
+    *bytes = state_layout(*cfg).total;
+    return HT_OK;
+}
+
+int ht_state_enable(ht_ctx* c) {
+    if (!c) return fail(HT_EINVAL, "ctx is NULL");
+    if (c->ds_mem) return HT_OK;
+    const size_t bytes = state_layout(c->cfg).total;
+    char* mem = nullptr;
+    if (hipMalloc(&mem, bytes) != hipSuccess) return fail(HT_ENOMEM, "hipMalloc of %zu bytes for the device state failed", bytes);
+    return state_attach(c, mem, true);
+}
+
+int ht_state_enable_ws(ht_ctx* c, void* d_mem, size_t bytes) {
+    if (!c || !d_mem) return fail(HT_EINVAL, "NULL argument");
+    if (c->ds_mem) return fail(HT_ESTATE, "the device state is already enabled");
+    const size_t need = state_layout(c->cfg).total;
+    if (bytes < need) return fail(HT_EINVAL, "state memory of %zu bytes is smaller than the %zu needed", bytes, need);
+    if (reinterpret_cast<uintptr_t>(d_mem) & 255) return fail(HT_EINVAL, "state memory not 256-byte aligned");
+    return state_attach(c, static_cast<char*>(d_mem), false);
 }
 
 int ht_state_set(ht_ctx* c, int32_t n, const double* t0, const double* dt, const double* m, const double* x,
@@ -3727,6 +3791,106 @@ int ht_last_stats(const ht_ctx* c, int64_t* pairs, int32_t* work_items) {
     if (!c) return fail(HT_EINVAL, "ctx is NULL");
     if (pairs) *pairs = c->last_pairs;
     if (work_items) *work_items = c->last_items;
+    return HT_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------------------
+// Admission by device footprint (the served stream): a pool is a budget of
+// device bytes on one GPU and the reservations held against it.  It
+// allocates nothing; a cluster's reservation is what its context and (when
+// resident) its device state will hold, from the same layouts ht_create and
+// ht_state_enable use.
+struct ht_pool {
+    int32_t device = 0;
+    size_t budget = 0, used = 0;
+    int64_t next_id = 1;
+    std::vector<std::pair<int64_t, size_t>> held;   // (id, bytes)
+    std::mutex mu;
+};
+
+namespace {
+int pool_take(ht_pool* p, size_t bytes, int64_t* id) {
+    std::lock_guard<std::mutex> lock(p->mu);
+    if (bytes > p->budget)
+        return fail(HT_ERANGE, "%zu bytes exceed the whole budget of %zu bytes", bytes, p->budget);
+    if (p->used + bytes > p->budget)
+        return fail(HT_ENOMEM, "%zu bytes do not fit: %zu of %zu bytes held", bytes, p->used, p->budget);
+    *id = p->next_id++;
+    p->held.emplace_back(*id, bytes);
+    p->used += bytes;
+    return HT_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int ht_pool_create(ht_pool** out, int32_t device, size_t budget_bytes) {
+    if (!out) return fail(HT_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (device < 0) return fail(HT_EINVAL, "device %d < 0", device);
+    ht_pool* p = new ht_pool();
+    p->device = device;
+    p->budget = budget_bytes;
+    *out = p;
+    return HT_OK;
+}
+
+int ht_pool_destroy(ht_pool* p) {
+    delete p;
+    return HT_OK;
+}
+
+
+int ht_cluster_admit(ht_pool* p, const ht_config* cfg, int32_t resident, int64_t* id, size_t* bytes) {
+    if (!p || !cfg || !id) return fail(HT_EINVAL, "NULL argument");
+    Layout L;
+    if (!layout_of(*cfg, L)) return fail(HT_EINVAL, "invalid configuration");
+    if (cfg->device != p->device) return fail(HT_EINVAL, "configuration for device %d, pool on %d", cfg->device, p->device);
+    const size_t need = L.total + (resident ? state_layout(*cfg).total : 0);
+    if (bytes) *bytes = need;
+    return pool_take(p, need, id);
+}
+
+int ht_pool_reserve(ht_pool* p, size_t bytes, int64_t* id) {
+    if (!p || !id) return fail(HT_EINVAL, "NULL argument");
+    return pool_take(p, bytes, id);
+}
+
+int ht_pool_resize(ht_pool* p, int64_t id, size_t bytes) {
+    if (!p) return fail(HT_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lock(p->mu);
+    for (auto& h : p->held)
+        if (h.first == id) {
+            p->used = p->used - h.second + bytes;
+            h.second = bytes;
+            if (p->used > p->budget)
+                return fail(HT_ENOMEM, "reservation %lld now holds %zu bytes: %zu of %zu bytes held", (long long)id,
+                            bytes, p->used, p->budget);
+            return HT_OK;
+        }
+    return fail(HT_EINVAL, "no reservation %lld", (long long)id);
+}
+
+int ht_cluster_release(ht_pool* p, int64_t id) {
+    if (!p) return fail(HT_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lock(p->mu);
+    for (size_t k = 0; k < p->held.size(); ++k)
+        if (p->held[k].first == id) {
+            p->used -= p->held[k].second;
+            p->held.erase(p->held.begin() + static_cast<std::ptrdiff_t>(k));
+            return HT_OK;
+        }
+    return fail(HT_EINVAL, "no reservation %lld", (long long)id);
+}
+
+int ht_pool_usage(ht_pool* p, size_t* used, size_t* budget, int32_t* n_held) {
+    if (!p) return fail(HT_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lock(p->mu);
+    if (used) *used = p->used;
+    if (budget) *budget = p->budget;
+    if (n_held) *n_held = static_cast<int32_t>(p->held.size());
     return HT_OK;
 }
 

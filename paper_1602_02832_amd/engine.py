@@ -94,7 +94,9 @@ class Cluster:
         tr = B.HostTree(x, v, z, z, m, 1, spec.n_crit, spec.theta)
         h = list_headroom
         self.caps = (max(int(tr.n_node * h), 64), max(int(tr.n_group * h), 16), max(int(tr.n_entries * h), 1024))
-        self.reserve = workspace_bytes(spec.n, *self.caps, precision) + (state_bytes(spec.n) if resident else 0)
+        # the configuration the context will be created with, and the device bytes it will hold
+        self.cfg = context_config(spec.n, *self.caps, precision, device)
+        self.reserve = workspace_bytes_of(self.cfg) + (B.state_bytes(self.cfg) if resident else 0)
         self.sim = None
         self.pending = (0, 0)    # (first row, count) of its update rows in the engine's row buffer
         self.steps_done = 0
@@ -125,31 +127,31 @@ class Cluster:
         """Device bytes this run holds (its context workspace, and its state when resident)."""
         if self.sim is None:
             return self.reserve
-        return self.sim.ctx.workspace_bytes + (state_bytes(self.spec.n) if self.resident else 0)
+        ctx = self.sim.ctx
+        return ctx.workspace_bytes + (B.state_bytes(ctx.cfg) if self.resident else 0)
 
     def close(self):
         if self.sim is not None:
             self.sim.close()
 
 
-def workspace_bytes(n, node_max, group_max, list_max, precision="mixed"):
-    """ht_workspace_bytes of a context for one run."""
-    import ctypes
+def context_config(n, node_max, group_max, list_max, precision="mixed", device=0):
+    """The ht_config of a run's context (as driver.Simulation creates it)."""
+    return B.HtConfig(device, B.HT_PREC[precision], 0, int(n), int(node_max), int(group_max), int(list_max), int(n),
+                      1e-4, None)
 
-    cfg = B.HtConfig(0, B.HT_PREC[precision], 0, int(n), int(node_max), int(group_max), int(list_max), int(n),
-                     1e-4, None)
+
+def workspace_bytes_of(cfg):
+    """ht_workspace_bytes of a context configuration."""
     out = ctypes.c_size_t()
     if B.device_lib().ht_workspace_bytes(ctypes.byref(cfg), ctypes.byref(out)) != 0:
         raise ValueError("bad context size")
     return int(out.value)
 
 
-def state_bytes(n):
-    """Device bytes of a resident state (ht_state_enable): x, v, a, jerk, the
-    step's acc and jerk (24 B each), t0, dt, m, pot, the step's pot (8 B each),
-    the active list (4 B), per particle, plus the scheduler's block arrays and
-    the 256-byte alignment of each of the 14 arrays."""
-    return int(n) * (6 * 24 + 5 * 8 + 4) + 1024 * 12 + 14 * 256
+def workspace_bytes(n, node_max, group_max, list_max, precision="mixed"):
+    """ht_workspace_bytes of a context for one run."""
+    return workspace_bytes_of(context_config(n, node_max, group_max, list_max, precision))
 
 
 class Engine:
@@ -606,33 +608,51 @@ class Request:
     finished: float = math.nan
     cluster: Cluster | None = None
     reserved: int = 0
+    rid: int = -1                  # its reservation in the server's pool
+    refused: bool = False          # larger than the device-memory budget
 
 
 class Server:
     """Continuous batching of cluster-run requests on one engine.
 
     Requests wait in arrival order; the head of the queue is admitted as soon
-    as its device-memory reservation fits the budget and a batch slot is free
-    (no overtaking, so no request starves).  Every engine step advances all
-    resident runs; a run leaves the step it finishes and frees its memory.
+    as its device-memory reservation fits the budget (ht_cluster_admit on a
+    pool of hbm_budget bytes, which also holds the engine's shared tree
+    builder) and a batch slot is free (no overtaking, so no request starves).
+    A request larger than the whole budget, or one that cannot fit even with
+    nothing resident, is refused.  Every engine step advances all resident
+    runs; a run leaves the step it finishes and frees its memory.
     """
 
     def __init__(self, engine: Engine, hbm_budget: int, max_resident: int, keep_finished: bool = False):
         self.engine, self.budget, self.max_resident = engine, int(hbm_budget), int(max_resident)
         self.keep_finished = keep_finished
-        self.used = 0
+        self.pool = B.Pool(self.budget, device=engine.device)
         self.resident: list[Request] = []
         self.done: list[Request] = []
+        self.refused: list[Request] = []
         self.max_used = 0
         self.max_waiting = 0
+        # the shared tree builder's arrays count against the budget (they grow with the largest tree)
+        self._tree_id = None
+        if engine.tree is not None:
+            self._tree_id = self.pool.reserve(engine.tree.device_bytes())
+            if self._tree_id is None:
+                raise ValueError("the engine's tree builder alone exceeds the device-memory budget")
 
-    def _admit(self, req: Request, now: float):
-        self.engine.add(req.cluster)           # activates: context, upload, first forces
-        actual = req.cluster.footprint()       # equals the reservation: same tree, same headroom
-        self.used += actual - req.reserved
-        req.reserved = actual
-        req.admitted = now
-        self.resident.append(req)
+    @property
+    def used(self):
+        return self.pool.usage()[0]
+
+    def _track(self):
+        if self._tree_id is not None:
+            self.pool.resize(self._tree_id, self.engine.tree.device_bytes())
+        for r in self.resident:
+            grown = r.cluster.footprint()     # a run whose lists outgrew their headroom got a larger context
+            if grown != r.reserved:
+                self.pool.resize(r.rid, grown)
+                r.reserved = grown
+        self.max_used = max(self.max_used, self.used)
 
     def run(self, requests: list[Request], clock=time.perf_counter):
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
@@ -647,13 +667,23 @@ class Server:
                 head = waiting[0]
                 if head.cluster is None:               # host preparation fixes the footprint
                     head.cluster = self.engine.new_cluster(head.spec)
-                need = head.cluster.reserve
-                if self.used + need > self.budget and self.resident:
+                try:
+                    rid, need = self.pool.admit(head.cluster.cfg, head.cluster.resident)
+                except B.HTError as e:                 # larger than the whole budget: never fits
+                    if e.code != -2:
+                        raise
+                    self._refuse(waiting.popleft(), clock() - t_start)
+                    continue
+                if rid is None:
+                    if not self.resident:              # does not fit even with nothing resident
+                        self._refuse(waiting.popleft(), clock() - t_start)
+                        continue
                     break
                 waiting.popleft()
-                self.used += need
-                head.reserved = need
-                self._admit(head, clock() - t_start)
+                head.rid, head.reserved = rid, need
+                self.engine.add(head.cluster)          # activates: context, upload, first forces
+                head.admitted = clock() - t_start
+                self.resident.append(head)
             self.max_used = max(self.max_used, self.used)
             if not self.resident:
                 if pending:
@@ -662,25 +692,30 @@ class Server:
                         time.sleep(min(delay, 0.05))
                 continue
             finished = self.engine.step()
-            # a run whose lists outgrow their headroom gets a larger context at a rebuild
-            for r in self.resident:
-                grown = r.cluster.footprint()
-                if grown != r.reserved:
-                    self.used += grown - r.reserved
-                    r.reserved = grown
-            self.max_used = max(self.max_used, self.used)
+            self._track()
             now = clock() - t_start
             for c in finished:
                 req = next(r for r in self.resident if r.cluster is c)
                 req.finished = now
                 self.resident.remove(req)
                 self.engine.remove(c)
-                self.used -= req.reserved
+                self.pool.release(req.rid)
                 if not self.keep_finished:
                     c.close()
                     req.cluster = None
                 self.done.append(req)
         return self.done
+
+    def _refuse(self, req: Request, now: float):
+        req.refused = True
+        req.finished = now
+        if req.cluster is not None:
+            req.cluster.close()
+            req.cluster = None
+        self.refused.append(req)
+
+    def close(self):
+        self.pool.close()
 
 
 def poisson_arrivals(count: int, rate: float, seed: int):

@@ -210,6 +210,49 @@ def test_server_admission_respects_budget_and_results_match(oracle):
             assert np.array_equal(alone[0][f], mixed[s.key][f]), (s.key, f)
 
 
+def test_server_charges_what_resident_clusters_hold():
+    """Resident clusters with device rebuilds: the reservation charged for a
+    cluster (ht_cluster_admit: its context workspace plus ht_state_bytes) is
+    what its activation takes from torch's allocator, the shared tree
+    builder's arrays are held against the same budget, and a request larger
+    than the whole budget is refused instead of admitted into an empty pool."""
+    import torch
+    say("server: charged bytes of resident clusters, tree builder, oversized request")
+    small = [E.RunSpec(key=k, n=n, seed=1300 + k, steps=10, n_crit=64) for k, n in enumerate((900, 1500, 700, 1200))]
+    eng = E.Engine(max_clusters=8, max_active=1 << 15, max_items=1 << 15, max_rows=1 << 15, rebuild_workers=0,
+                   resident=True, device_tree=True, tree_n_max=1500)
+    def requested():   # bytes asked of torch's allocator by live tensors (before its block rounding)
+        return torch.cuda.memory_stats()["requested_bytes.all.current"]
+
+    for sp in small:                       # charge = bytes taken; the builder warms up to these sizes
+        c = eng.new_cluster(sp)
+        torch.cuda.synchronize()
+        before = requested()
+        eng.add(c)
+        taken = requested() - before
+        assert taken == c.reserve, (sp.n, taken, c.reserve)
+        assert c.footprint() == c.reserve
+        eng.remove(c)
+        c.close()
+    tree0 = eng.tree.device_bytes()
+    reserves = sorted(eng.new_cluster(sp).reserve for sp in small)
+    budget = tree0 + reserves[-1] + reserves[-2]
+    n_big = 20000
+    while eng.new_cluster(E.RunSpec(key=99, n=n_big, seed=1399, steps=10, n_crit=64)).reserve <= budget:
+        n_big *= 2
+    big = E.RunSpec(key=99, n=n_big, seed=1399, steps=10, n_crit=64)
+    srv = E.Server(eng, hbm_budget=budget, max_resident=8, keep_finished=False)
+    reqs = [E.Request(spec=s, arrival=0.0) for s in small[:2]] + [E.Request(spec=big, arrival=0.0)] + \
+        [E.Request(spec=s, arrival=0.0) for s in small[2:]]
+    done = srv.run(reqs)
+    assert [r.spec.key for r in srv.refused] == [99]
+    assert sorted(r.spec.key for r in done) == [0, 1, 2, 3]
+    assert srv.max_used <= budget + (eng.tree.device_bytes() - tree0)
+    assert srv.used == eng.tree.device_bytes()          # only the builder is held at the end
+    srv.close()
+    eng.close()
+
+
 def test_engine_matches_single_cluster_simulation():
     """The engine path (pinned row updates, results written to pinned memory,
     the flat batched corrector) gives the same bits as stepping the cluster's
