@@ -272,13 +272,47 @@ def bench_tree_build(torch, B, x, v, m, cfg, reps=5):
             "host_threads": os.cpu_count(), "speedup": host_ms / walls[k]}
 
 
-def cpu_baseline(W, cfg, seconds):
-    """Oracle list force (FP64, OpenMP) on a bounded sample of the workload:
-    whole groups of the t = 0 tree, the oracle's own tree and lists."""
+def cpu_baseline(W, cfg, rec, warmup, seconds):
+    """The oracle (FP64, OpenMP over active particles), built for this host's
+    instruction set, on the timed window itself: the recorded snapshot, every
+    step's update rows applied in turn, and at every timed step the oracle's
+    prediction of the whole j-memory and its list force on the step's active
+    set.  The window is replayed until about `seconds` have been spent."""
     from oracle import oracle as O
 
     from paper_1602_02832_amd import binding as B
 
+    O.use_native_build()
+    snap = rec.snap
+    gf, lo, en = snap["lists"]
+    nm, nx, nv, na, nj = snap["node"]
+    t_node = np.full(nm.shape[0], snap["t_tree"])
+    spent, done_pairs, done_steps, passes = 0.0, 0, 0, 0
+    while spent < seconds and passes < 64:
+        t0, m, x, v, a, j = (snap[k].copy() for k in ("t0", "m", "x", "v", "a", "j"))
+        for k, (t, act, _) in enumerate(rec.steps):
+            if k > 0:
+                idx, u_t0, u_m, u_x, u_v, u_a, u_j = rec.steps[k - 1][2]
+                t0[idx], m[idx], x[idx], v[idx], a[idx], j[idx] = u_t0, u_m, u_x, u_v, u_a, u_j
+            if k < warmup:
+                continue
+            tw = time.perf_counter()
+            xp, vp = O.predict(t, t0, x, v, a, j)
+            nxp, nvp = O.predict(t, t_node, nx, nv, na, nj)
+            O.force_list(act, np.vstack([xp, nxp]), np.vstack([vp, nvp]), np.concatenate([m, nm]), cfg.eps2, gf, lo,
+                         en)
+            spent += time.perf_counter() - tw
+            g = np.searchsorted(gf, act, side="right") - 1
+            done_pairs += int((lo[g + 1] - lo[g]).sum())
+            done_steps += 1
+        passes += 1
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    base = dict(value=done_pairs / spent, unit="interactions/s", cores=threads, kind="oracle",
+                sample=f"the timed window's {len(rec.steps) - warmup} block steps replayed {passes} times "
+                       f"({done_steps} steps: prediction of all {rec.n + nm.shape[0]} j-entries and the list force "
+                       f"on each step's active set; {done_pairs:.3g} pairs, {spent:.1f} s)",
+                build=O.build_flags(native=True))
+    # the direct sum on a random sample of 1024 particles against all N, and the tree builds
     x, v, m = W.make_initial_conditions(cfg)
     z = np.zeros_like(x)
     t = time.perf_counter()
@@ -288,29 +322,11 @@ def cpu_baseline(W, cfg, seconds):
     B.HostTree(x, v, z, z, m, cfg.n_leaf, cfg.n_crit, cfg.theta)
     t_product_tree = time.perf_counter() - t
     xs, vs, ms = x[tr.perm], v[tr.perm], m[tr.perm]
-    XP, VP, MM = np.vstack([xs, tr.node_x]), np.vstack([vs, tr.node_v]), np.concatenate([ms, tr.node_m])
     rng = np.random.default_rng(99)
-    order = rng.permutation(tr.n_group)
-    gf, lo = tr.group_first, tr.list_off
-    done_pairs, spent, used, k = 0, 0.0, 0, 0
-    while spent < seconds and k < len(order):
-        g = order[k]
-        k += 1
-        ids = np.arange(gf[g], gf[g + 1], dtype=np.int32)
-        t = time.perf_counter()
-        O.force_list(ids, XP, VP, MM, cfg.eps2, gf, lo, tr.entries)
-        spent += time.perf_counter() - t
-        done_pairs += ids.size * int(lo[g + 1] - lo[g])
-        used += ids.size
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-    # the direct sum on a random sample of 1024 particles, against all N
     ids = np.sort(rng.choice(cfg.n, 1024, replace=False)).astype(np.int32)
     t = time.perf_counter()
     O.force_direct(ids, xs, vs, ms, cfg.eps2)
     t_direct = time.perf_counter() - t
-    base = dict(value=done_pairs / spent, unit="interactions/s", cores=threads, kind="oracle",
-                sample=f"list force on all {used} particles of {k} random groups of the t=0 tree "
-                       f"({done_pairs:.3g} pairs, {spent:.1f} s)")
     extra = dict(direct_interactions_per_s=1024 * (cfg.n - 1) / t_direct,
                  direct_sample=f"direct sum on 1024 random particles against all {cfg.n} ({t_direct:.2f} s)",
                  tree_build_s={"oracle": t_oracle_tree, "product_host_builder": t_product_tree},
@@ -716,7 +732,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle list force for about {args.cpu_seconds:.0f} s")
-        cpu, cpu_extra = cpu_baseline(W, cfg, args.cpu_seconds)
+        cpu, cpu_extra = cpu_baseline(W, cfg, rec, args.warmup, args.cpu_seconds)
         log(f"cpu baseline: {cpu['value']:.4g} interactions/s on {cpu['cores']} threads; direct "
             f"{cpu_extra['direct_interactions_per_s']:.4g}; tree build {cpu_extra['tree_build_s']}")
 

@@ -32,14 +32,36 @@ _u32p = ctypes.POINTER(ctypes.c_uint32)
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 
 
+# -O3 without contraction or fast-math: every result is the IEEE-rounded value of
+# the stated operation order, so optimisation level and instruction set change no
+# bit.  The default instruction set is portable; native=True builds for the
+# machine it runs on (the CPU baseline does, on the host it is timed on).
+FLAGS = ["-O3", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math", "-fopenmp"]
+
+
 def build(force: bool = True) -> str:
     """Compile oracle.c into liboracle.so (FP64, no contraction, OpenMP)."""
     if force or not os.path.exists(_LIB_PATH):
-        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
-               "-fopenmp", "-o", _LIB_PATH + ".tmp", _SRC, "-lm"]
+        cmd = ["gcc", *FLAGS, "-o", _LIB_PATH + ".tmp", _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
     return _LIB_PATH
+
+
+def use_native_build() -> str:
+    """Compile oracle.c for this machine's instruction set into a library of
+    its own and make it the one this module calls (the same bits: see FLAGS)."""
+    global _LIB_PATH, _lib
+    path = os.path.join(_HERE, "liboracle_native.so")
+    cmd = ["gcc", *FLAGS, "-march=native", "-o", path + ".tmp", _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(path + ".tmp", path)
+    _LIB_PATH, _lib = path, None
+    return path
+
+
+def build_flags(native: bool = False) -> str:
+    return " ".join(FLAGS + (["-march=native"] if native else []))
 
 
 def lib():
