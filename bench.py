@@ -127,10 +127,12 @@ class Recorded:
         self.steps.append((t, act.astype(np.int32), upd))
 
 
-def make_ctx(B, snap, n, precision, eps2, stream, predict_mode="fused"):
+def make_ctx(B, snap, n, precision, eps2, stream, predict_mode="fused", lists="csr"):
     ctx = B.Context(n_max=n, node_max=snap["n_node"] + 64, group_max=snap["n_group"] + 16,
                     list_max=snap["n_entries"] + 1024, active_max=n, eps2=eps2, precision=precision,
                     predict_mode=predict_mode, stream=stream)
+    if lists != "csr":
+        ctx.set_list_form(lists)
     load_snapshot(ctx, snap)
     return ctx
 
@@ -522,6 +524,8 @@ def main():
                     help="ensemble workload: run the resident engine as a batched device loop")
     ap.add_argument("--no-engine-records", action="store_true",
                     help="default workload: skip the short ensemble64 and served records")
+    ap.add_argument("--lists", choices=("csr", "runs"), default="csr",
+                    help="default workload: interaction-list form of the tree legs (the graph leg takes CSR)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (scale for the byte counters)")
     args = ap.parse_args()
@@ -663,10 +667,11 @@ def main():
     def leg(precision, direct=False):
         """The recorded steps once instrumented (latency, kernel time, pairs)
         and once clean (throughput), each from a fresh copy of the snapshot."""
-        ctx = make_ctx(B, rec.snap, rec.n, precision, cfg.eps2, sh)
+        lists = "csr" if direct else args.lists
+        ctx = make_ctx(B, rec.snap, rec.n, precision, cfg.eps2, sh, lists=lists)
         r = replay(torch, B, rec, ctx, stream, args.warmup, args.steps, direct=direct, instrument=True)
         ctx.close()
-        ctx = make_ctx(B, rec.snap, rec.n, precision, cfg.eps2, sh)
+        ctx = make_ctx(B, rec.snap, rec.n, precision, cfg.eps2, sh, lists=lists)
         r["instrumented_wall_s"] = r["wall_s"]
         r["wall_s"] = replay(torch, B, rec, ctx, stream, args.warmup, args.steps, direct=direct,
                              instrument=False)["wall_s"]
@@ -697,7 +702,7 @@ def main():
     # ---- the all-particle step at t = dt_tree
     all_active = None
     if not args.no_all_active:
-        ctx = make_ctx(B, rec_all.snap, rec_all.n, "mixed", cfg.eps2, sh)
+        ctx = make_ctx(B, rec_all.snap, rec_all.n, "mixed", cfg.eps2, sh, lists=args.lists)
         ids = np.arange(rec_all.n, dtype=np.int32)
         acc = torch.empty((rec_all.n, 3), dtype=torch.float64, device="cuda")
         jrk = torch.empty_like(acc)
@@ -771,7 +776,7 @@ def main():
                    "eta": cfg.eta, "n_crit": cfg.n_crit, "n_leaf": cfg.n_leaf,
                    "masses": f"salpeter 1:{cfg.mass_ratio:g}" if cfg.mass_seed is not None else "equal",
                    "window": f"{K} block steps after the rebuild at t={cfg.dt_tree}", "precision": "mixed",
-                   "predict": "fused"},
+                   "predict": "fused", "lists": args.lists},
         "p50_step_ms": float(np.percentile(lat, 50)),
         "p99_step_ms": float(np.percentile(lat, 99)),
         "active_per_step": {"min": int(n_act.min()), "median": float(np.median(n_act)), "max": int(n_act.max()),

@@ -127,6 +127,22 @@ int ht_set_nodes(ht_ctx *ctx, int32_t n_nodes, double t_tree, const double *m, c
 int ht_set_interaction_lists(ht_ctx *ctx, int32_t n_groups, const int64_t *group_first,
                              const int64_t *list_off, const int32_t *entries);
 
+/* Form of the interaction lists in device memory.  CSR (the default): one
+ * combined index per entry.  RUNS (Section 2's indirect addressing: a cell-
+ * index memory of start and count pairs, each group's nodes copied
+ * contiguously): at ht_set_interaction_lists every list's node entries are
+ * replaced, in list order, by copies of their records at consecutive indices
+ * from N + M on (library-owned device memory, 128 bytes per node entry), and
+ * each list is stored as runs of consecutive indices; the force kernel
+ * expands a round's runs in LDS.  The expanded lists are the CSR lists'
+ * records in the same order, so every result is the CSR form's, bit for bit.
+ * RUNS needs fused prediction and serves the single-context calls (ht_force,
+ * ht_force_async, ht_step_async, ht_dev_step); batched calls, graph steps,
+ * the device loops and device rebuilds take CSR only (HT_EINVAL).  Changing
+ * the form drops the lists: set them again. */
+typedef enum { HT_LISTS_CSR = 0, HT_LISTS_RUNS = 1 } ht_list_form;
+int ht_set_list_form(ht_ctx *ctx, int32_t form);
+
 /* Step 5 (predictor): predict particles and nodes to block time t. */
 int ht_predict(ht_ctx *ctx, double t);
 

@@ -152,6 +152,7 @@ def device_lib():
             "ht_batch_dev_run": [_vp, i, _vp, _vp, _vp, _vp, _vp, i, _vp, _vp, _vp, _vp, _vp,
                                  ctypes.POINTER(ctypes.c_int32)],
             "ht_state_bytes": [ctypes.POINTER(HtConfig), ctypes.POINTER(ctypes.c_size_t)],
+            "ht_set_list_form": [_vp, i],
             "ht_state_enable_ws": [_vp, _vp, ctypes.c_size_t],
             "ht_pool_create": [ctypes.POINTER(_vp), i, ctypes.c_size_t],
             "ht_pool_destroy": [_vp],
@@ -330,6 +331,11 @@ class Context:
         en = _arr(entries, np.int32)
         _check(device_lib().ht_set_interaction_lists(self._h, gf.shape[0] - 1, _ptr(gf, ctypes.c_int64),
                                                      _ptr(lo, ctypes.c_int64), _ptr(en, ctypes.c_int32)))
+
+    def set_list_form(self, form):
+        """ht_set_list_form: "csr" (default) or "runs" (run-length lists with the
+        groups' node copies); the lists must be set again afterwards."""
+        _check(device_lib().ht_set_list_form(self._h, {"csr": 0, "runs": 1}[form]))
 
     def predict(self, t):
         _check(device_lib().ht_predict(self._h, float(t)))

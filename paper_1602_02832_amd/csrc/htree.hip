@@ -33,6 +33,7 @@
 #include <limits>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "htree.h"
@@ -113,6 +114,18 @@ struct Desc {
     double* partial;    // split partial sums, kOut doubles per slot
     double t;
     double eps2;
+    // run-length lists (HT_LISTS_RUNS): run r covers list positions
+    // run_pos[r] .. run_pos[r+1]-1 with the combined indices run_start[r],
+    // run_start[r]+1, ...; indices from copy_base on are the groups' node copies
+    // (copy_rec[index - copy_base]); item_runs[k] is the run holding item k's
+    // first position
+    const int32_t* run_start;
+    const int64_t* run_pos;
+    const int64_t* item_runs;
+    const void* copy_rec;
+    int64_t n_runs;
+    int32_t copy_base;
+    int32_t pad;
 };
 
 // One unit of work: an i-tile of one group against a range of its list.
@@ -162,14 +175,14 @@ struct PrecMixed {
 };
 
 // One staged j of a round: predicted position and velocity, mass (as
-// stored, widened to FP64 once here rather than once per pair), combined
-// index.  Records (not one array per field) so that a thread reads an entry
+// stored: widened per pair, which keeps the mixed kernel within its 128
+// registers), combined index.  Records (not one array per field) so that a thread reads an entry
 // with a few 16-byte LDS loads at immediate offsets from one address.
 template <class P>
 struct alignas(16) JRec {
     double x, y, z;
     typename P::Vel vx, vy, vz;
-    double m;
+    typename P::Stored m;
     int32_t idx;
 };
 static_assert(sizeof(JRec<PrecMixed>) == 64 && sizeof(JRec<PrecFp64>) == 64, "staged records are 64 bytes");
@@ -179,6 +192,14 @@ union LdsAll {
     JRec<P> j[kRoundMax];
     double red[kOut * kWG];
 };
+
+// Run-length lists: the runs that overlap a round, as (first position in the
+// round, index at position 0 of the round).
+struct RunLds {
+    int32_t pos[kRoundMax];
+    int32_t off[kRoundMax];
+};
+struct NoRunLds {};
 
 // ------------------------------------------------------------------------------------------------
 // predictor (4th-order Hermite, Section 1/2): Taylor series to the jerk, FP64.
@@ -198,7 +219,8 @@ __device__ __forceinline__ void predict_rec(const typename P::Rec& r, double t, 
 }
 
 // Position, velocity (in the pair's precision) and mass of entry j at the block time.
-template <class P, bool EAGER>
+// RUNS: indices from copy_base on are node copies, in their own array.
+template <class P, bool EAGER, bool RUNS = false>
 __device__ __forceinline__ void load_state(const Desc& c, int j, double& x, double& y, double& z,
                                            typename P::Vel& vx, typename P::Vel& vy, typename P::Vel& vz,
                                            typename P::Stored& m) {
@@ -213,7 +235,11 @@ __device__ __forceinline__ void load_state(const Desc& c, int j, double& x, doub
         vz = r.vz;
         m = r.m;
     } else {
-        const typename P::Rec r = static_cast<const typename P::Rec*>(c.rec)[j];
+        const typename P::Rec* base = static_cast<const typename P::Rec*>(c.rec);
+        if constexpr (RUNS) {
+            if (j >= c.copy_base) base = static_cast<const typename P::Rec*>(c.copy_rec) - c.copy_base;
+        }
+        const typename P::Rec r = base[j];
         double dvx, dvy, dvz;
         predict_rec<P>(r, c.t, x, y, z, dvx, dvy, dvz);
         vx = static_cast<V>(dvx);
@@ -238,7 +264,7 @@ __device__ __forceinline__ void pair_fp64(double xi, double yi, double zi, doubl
     double rinv = rsqrt(s);
     rinv = (J.idx == i) ? 0.0 : rinv;
     const double rinv2 = rinv * rinv;
-    const double mr = J.m * rinv;
+    const double mr = static_cast<double>(J.m) * rinv;
     const double mr3 = mr * rinv2;
     const double alpha = 3.0 * (dx * wx + dy * wy + dz * wz) * rinv2;
     A.v[0] += mr3 * dx;
@@ -267,7 +293,7 @@ __device__ __forceinline__ void pair_mixed(double xi, double yi, double zi, doub
     double rinv = fma(0.5 * y0, e, y0);
     rinv = (J.idx == i) ? 0.0 : rinv;
     const double rinv2 = rinv * rinv;
-    const double mr = J.m * rinv;
+    const double mr = static_cast<double>(J.m) * rinv;
     const double mr3 = mr * rinv2;
     const double wx = J.vx - vxi, wy = J.vy - vyi, wz = J.vz - vzi;
     const double alpha = 3.0 * fma(dz, wz, fma(dy, wy, dx * wx)) * rinv2;
@@ -300,8 +326,8 @@ __device__ __forceinline__ void write_out(const Desc& c, int64_t o, const double
 
 // ------------------------------------------------------------------------------------------------
 // one work item with tile size T
-template <class P, bool EAGER, bool DIRECT, int T>
-__device__ __forceinline__ void run_item(const Desc& c, const Item& it, LdsAll<P>& lds) {
+template <class P, bool EAGER, bool DIRECT, bool RUNS, int T, class RL>
+__device__ __forceinline__ void run_item(const Desc& c, const Item& it, int64_t run0, LdsAll<P>& lds, RL& rl) {
     constexpr int G = round_mult(T);    // entries gathered per thread and round
     constexpr int R = kRound * G;       // entries per round
     constexpr int S = kWG / T;          // j-streams
@@ -322,7 +348,10 @@ __device__ __forceinline__ void run_item(const Desc& c, const Item& it, LdsAll<P
             jn[g] = e < it.j_end ? (DIRECT ? static_cast<int>(e) : c.entries[e]) : 0;
         }
     };
-    load_idx(it.j_begin);
+    // Run-length lists: the round's indices are expanded from its runs after the
+    // round's first barrier (run: the run holding the round's first position).
+    int64_t run = run0;
+    if constexpr (!RUNS) load_idx(it.j_begin);
     const int i = c.active[it.act_begin + (has_i ? islot : 0)];
 
     double xi, yi, zi;
@@ -339,6 +368,38 @@ __device__ __forceinline__ void run_item(const Desc& c, const Item& it, LdsAll<P
         const int64_t rest = it.j_end - base;
         const int cnt = rest < R ? static_cast<int>(rest) : R;
         __syncthreads();  // the previous round is no longer read
+        if constexpr (RUNS) {
+            // the runs overlapping [base, base + cnt) are run, run + 1, ...: at most cnt
+            int ov = 0;
+            for (int k = tid; k < cnt; k += kWG) {
+                const int64_t q = run + k;
+                if (q < c.n_runs) {
+                    const int64_t p = c.run_pos[q];
+                    if (p < base + cnt) {
+                        const int64_t p0 = p > base ? p : base;
+                        rl.pos[k] = static_cast<int32_t>(p0 - base);
+                        rl.off[k] = static_cast<int32_t>(c.run_start[q] + (p0 - p) - (p0 - base));
+                        ++ov;
+                    }
+                }
+            }
+            const int nr = __syncthreads_count(ov);   // the loaded runs are visible from here on
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int e = tid + g * kWG;
+                if (e < cnt) {   // the last loaded run starting at or before e
+                    int lo = 0, hi = nr;
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (rl.pos[mid] <= e) lo = mid; else hi = mid;
+                    }
+                    jn[g] = rl.off[lo] + e;
+                }
+            }
+            // the run holding the next round's first position
+            const int64_t nx = run + nr < c.n_runs ? c.run_pos[run + nr] : INT64_MAX;
+            run += nx == base + cnt ? nr : nr - 1;
+        }
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const int e = tid + g * kWG;
@@ -347,11 +408,13 @@ __device__ __forceinline__ void run_item(const Desc& c, const Item& it, LdsAll<P
                 double xj, yj, zj;
                 typename P::Vel vxj, vyj, vzj;
                 typename P::Stored mj;
-                load_state<P, EAGER>(c, j, xj, yj, zj, vxj, vyj, vzj, mj);
-                lds.j[e] = JRec<P>{xj, yj, zj, vxj, vyj, vzj, static_cast<double>(mj), j};
+                load_state<P, EAGER, RUNS>(c, j, xj, yj, zj, vxj, vyj, vzj, mj);
+                lds.j[e] = JRec<P>{xj, yj, zj, vxj, vyj, vzj, mj, j};
             }
         }
-        if (base + R < it.j_end) load_idx(base + R);   // in flight during this round's pairs
+        if constexpr (!RUNS) {
+            if (base + R < it.j_end) load_idx(base + R);   // in flight during this round's pairs
+        }
         __syncthreads();
         const double eps2 = c.eps2;
         if (cnt == R) {
@@ -428,9 +491,10 @@ __device__ __forceinline__ int find_entry(const Entry* tab, int n_tab, int64_t g
 }
 
 // Register budget: the mixed form fits 128 VGPRs (4 waves per SIMD) without
-// spilling; the FP64 form needs a little more and runs 3 waves per SIMD.
-template <class P>
-struct WavesPerSimd { static constexpr int value = P::kMixed ? 4 : 3; };
+// spilling; the FP64 form, and the run-length lists' expansion, need a little
+// more and run 3 waves per SIMD.
+template <class P, bool RUNS = false>
+struct WavesPerSimd { static constexpr int value = P::kMixed && !RUNS ? 4 : 3; };
 
 // Work-group g takes items g, g + grid, ...  The grid is normally the item
 // count; graph replays and device loops launch a fixed grid and pass
@@ -438,25 +502,29 @@ struct WavesPerSimd { static constexpr int value = P::kMixed ? 4 : 3; };
 // launch, written by the plan's delivery or by the device planner).  (A shared atomic work counter was measured to cost
 // about 1 us per item: device-scope atomics on one address serialise across
 // the eight XCDs.)
-template <class P, bool EAGER, bool DIRECT>
-__global__ __launch_bounds__(kWG, WavesPerSimd<P>::value) void force_kernel(const Entry* __restrict__ tab, int n_tab,
+template <class P, bool EAGER, bool DIRECT, bool RUNS = false>
+__global__ __launch_bounds__(kWG, (WavesPerSimd<P, RUNS>::value)) void force_kernel(const Entry* __restrict__ tab,
+                                                                                   int n_tab,
                                                                           int64_t n_items, const int64_t* counts) {
     __shared__ LdsAll<P> lds;
+    __shared__ typename std::conditional<RUNS, RunLds, NoRunLds>::type rl;
     if (n_items < 0) n_items = counts[0];
     for (int64_t g = blockIdx.x; g < n_items; g += gridDim.x) {
         const int cl = find_entry(tab, n_tab, g, false);
         const Desc& c = tab[cl].d;
-        const Item it = tab[cl].items[g - tab[cl].first_item];
+        const int64_t k = g - tab[cl].first_item;
+        const Item it = tab[cl].items[k];
+        const int64_t r0 = RUNS ? c.item_runs[k] : 0;
         switch (it.tile_log2) {
-            case 8: run_item<P, EAGER, DIRECT, 256>(c, it, lds); break;
-            case 7: run_item<P, EAGER, DIRECT, 128>(c, it, lds); break;
-            case 6: run_item<P, EAGER, DIRECT, 64>(c, it, lds); break;
-            case 5: run_item<P, EAGER, DIRECT, 32>(c, it, lds); break;
-            case 4: run_item<P, EAGER, DIRECT, 16>(c, it, lds); break;
-            case 3: run_item<P, EAGER, DIRECT, 8>(c, it, lds); break;
-            case 2: run_item<P, EAGER, DIRECT, 4>(c, it, lds); break;
-            case 1: run_item<P, EAGER, DIRECT, 2>(c, it, lds); break;
-            default: run_item<P, EAGER, DIRECT, 1>(c, it, lds); break;
+            case 8: run_item<P, EAGER, DIRECT, RUNS, 256>(c, it, r0, lds, rl); break;
+            case 7: run_item<P, EAGER, DIRECT, RUNS, 128>(c, it, r0, lds, rl); break;
+            case 6: run_item<P, EAGER, DIRECT, RUNS, 64>(c, it, r0, lds, rl); break;
+            case 5: run_item<P, EAGER, DIRECT, RUNS, 32>(c, it, r0, lds, rl); break;
+            case 4: run_item<P, EAGER, DIRECT, RUNS, 16>(c, it, r0, lds, rl); break;
+            case 3: run_item<P, EAGER, DIRECT, RUNS, 8>(c, it, r0, lds, rl); break;
+            case 2: run_item<P, EAGER, DIRECT, RUNS, 4>(c, it, r0, lds, rl); break;
+            case 1: run_item<P, EAGER, DIRECT, RUNS, 2>(c, it, r0, lds, rl); break;
+            default: run_item<P, EAGER, DIRECT, RUNS, 1>(c, it, r0, lds, rl); break;
         }
         __syncthreads();
     }
@@ -584,6 +652,18 @@ __global__ __launch_bounds__(kWG) void scatter_kernel(Desc dst, int n, const int
         if (idx && !row_index_ok(j, lim, err)) continue;
         store_rec<P>(rec, j, t0 ? t0[k] : t0_all, m[k], x + 3 * k, v + 3 * k, a + 3 * k, jerk + 3 * k);
     }
+}
+
+// Run-length lists: the groups' node copies, record by record (copy k is
+// record idx[k] of the combined memory).
+template <class P>
+__global__ __launch_bounds__(kWG) void copy_records_kernel(const void* src, const int32_t* __restrict__ idx, int64_t n,
+                                                           void* dst) {
+    const typename P::Rec* s = static_cast<const typename P::Rec*>(src);
+    typename P::Rec* d = static_cast<typename P::Rec*>(dst);
+    for (int64_t k = blockIdx.x * static_cast<int64_t>(kWG) + threadIdx.x; k < n;
+         k += static_cast<int64_t>(gridDim.x) * kWG)
+        d[k] = s[idx[k]];
 }
 
 // Resident rebuild: dt and pot in the new particle order.
@@ -1514,7 +1594,8 @@ bool layout_of(const ht_config& c, Layout& L) {
     L.partial_max = 2 * static_cast<int64_t>(c.active_max) + 65536;
     L.plan_bytes = align_up(kMaxBatch * sizeof(Entry)) + align_up(static_cast<size_t>(L.items_max) * sizeof(Item)) +
                    align_up(static_cast<size_t>(L.items_max) * sizeof(RTile)) +
-                   align_up(static_cast<size_t>(c.active_max) * 4) + 256;
+                   align_up(static_cast<size_t>(c.active_max) * 4) +
+                   align_up(static_cast<size_t>(L.items_max) * 8) + 256;   // item run cursors (run-length lists)
     L.off_plan = take(L.plan_bytes);
     L.off_partial = take(static_cast<size_t>(L.partial_max) * kOut * 8);
     L.off_out = take(static_cast<size_t>(c.active_max) * kOut * 8);
@@ -1611,6 +1692,19 @@ struct ht_ctx {
     int32_t* h_active = nullptr;
     double dev_t_next = 0.0;
     int64_t dev_n_active = -1;   // active set of the last ht_dev_next_block, -1 once stepped
+    // run-length lists (HT_LISTS_RUNS, set by ht_set_list_form): runs of
+    // consecutive combined indices over each list, the groups' node copies
+    // (indices copy_base.. in their own records), and the host's copy of the
+    // run positions for the planner's per-item run cursors
+    int32_t list_form = HT_LISTS_CSR;
+    int32_t* d_run_start = nullptr;
+    int64_t* d_run_pos = nullptr;
+    char* d_copy_rec = nullptr;
+    int32_t* d_copy_src = nullptr;
+    size_t run_cap = 0, copy_cap = 0;
+    int64_t n_runs = 0, n_copies = 0;
+    std::vector<int64_t> run_pos;
+    std::vector<int64_t> item_runs;
     // scratch for planning
     std::vector<Item> items;
     std::vector<RTile> rtiles;
@@ -1628,6 +1722,13 @@ struct ht_ctx {
         d.partial = dev<double>(L.off_partial);
         d.t = t_pred;
         d.eps2 = cfg.eps2;
+        if (list_form == HT_LISTS_RUNS) {
+            d.run_start = d_run_start;
+            d.run_pos = d_run_pos;
+            d.copy_rec = d_copy_rec;
+            d.n_runs = n_runs;
+            d.copy_base = n + n_nodes;
+        }
         return d;
     }
 
@@ -1833,6 +1934,14 @@ int plan(ht_ctx* c, int32_t n_active, const int32_t* ids, bool direct) {
         for (size_t q = 0; q < items.size(); ++q) out[count[kmax - keys[q]]++] = items[q];
         items.swap(out);
     }
+    c->item_runs.clear();
+    if (c->list_form == HT_LISTS_RUNS && !direct) {   // the run holding each item's first position
+        auto& ir = c->item_runs;
+        ir.resize(items.size());
+        for (size_t q = 0; q < items.size(); ++q)
+            ir[q] = static_cast<int64_t>(std::upper_bound(c->run_pos.begin(), c->run_pos.end(), items[q].j_begin) -
+                                         c->run_pos.begin()) - 1;
+    }
     c->last_pairs = pairs;
     c->last_items = static_cast<int32_t>(items.size());
     return HT_OK;
@@ -1864,13 +1973,20 @@ size_t pack_plan_into(ht_ctx* c, char* hs, char* dv, size_t at, int32_t n_active
     if (b_rt) std::memcpy(hs + o_rt, c->rtiles.data(), b_rt);
     std::memcpy(hs + o_act, ids, static_cast<size_t>(n_active) * 4);
     e.d = c->desc();
+    size_t end = o_act + static_cast<size_t>(n_active) * 4;
+    if (c->list_form == HT_LISTS_RUNS) {   // each item's first run, in item order
+        const size_t o_ir = align_up(end);
+        std::memcpy(hs + o_ir, c->item_runs.data(), c->item_runs.size() * 8);
+        e.d.item_runs = reinterpret_cast<const int64_t*>(dv + o_ir);
+        end = o_ir + c->item_runs.size() * 8;
+    }
     e.d.active = reinterpret_cast<const int32_t*>(dv + o_act);
     e.d.acc = acc;
     e.d.jerk = jerk;
     e.d.pot = pot;
     e.items = reinterpret_cast<const Item*>(dv + o_items);
     e.rtiles = reinterpret_cast<const RTile*>(dv + o_rt);
-    return o_act + static_cast<size_t>(n_active) * 4;
+    return end;
 }
 
 size_t pack_plan(ht_ctx* c, size_t at, int32_t n_active, const int32_t* ids, double* acc, double* jerk, double* pot,
@@ -1907,7 +2023,7 @@ int copy_plan(ht_ctx* c, size_t end) {
 
 template <class P>
 int launch_force(hipStream_t stream, bool eager, Timing& tm, const Entry* d_tab, int n_tab, int64_t n_items,
-                 int64_t n_rtiles, bool direct, int64_t pairs) {
+                 int64_t n_rtiles, bool direct, int64_t pairs, bool runs = false) {
     const int grid = grid_for(n_items);
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
     if (tm.enabled) {
@@ -1925,6 +2041,8 @@ int launch_force(hipStream_t stream, bool eager, Timing& tm, const Entry* d_tab,
     if (direct) {
         if (eager) force_kernel<P, true, true><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr);
         else force_kernel<P, false, true><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr);
+    } else if (runs) {
+        force_kernel<P, false, false, true><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr);
     } else {
         if (eager) force_kernel<P, true, false><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr);
         else force_kernel<P, false, false><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr);
@@ -2030,9 +2148,10 @@ int enqueue_step(ht_ctx* c, const DevRows& u, bool predict_eager, int32_t n_acti
     const Entry* d_tab = reinterpret_cast<const Entry*>(c->ws + c->L.off_plan);
     const int64_t ni = static_cast<int64_t>(c->items.size()), nr = static_cast<int64_t>(c->rtiles.size());
     const bool eager = c->cfg.predict_mode == HT_PREDICT_EAGER;
+    const bool runs = c->list_form == HT_LISTS_RUNS && !direct;
     rc = c->cfg.precision == HT_PREC_FP64
-             ? launch_force<PrecFp64>(c->stream, eager, c->tm, d_tab, 1, ni, nr, direct, c->last_pairs)
-             : launch_force<PrecMixed>(c->stream, eager, c->tm, d_tab, 1, ni, nr, direct, c->last_pairs);
+             ? launch_force<PrecFp64>(c->stream, eager, c->tm, d_tab, 1, ni, nr, direct, c->last_pairs, runs)
+             : launch_force<PrecMixed>(c->stream, eager, c->tm, d_tab, 1, ni, nr, direct, c->last_pairs, runs);
     if (rc) return rc;
     // The prep launch is the slot's only reader; marking the slot after the
     // whole step keeps the step's launches back to back on the host.
@@ -2210,6 +2329,10 @@ int ht_destroy(ht_ctx* c) {
     if (c->h_dout) (void)hipHostFree(c->h_dout);
     if (c->h_active) (void)hipHostFree(c->h_active);
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+    if (c->d_run_start) (void)hipFree(c->d_run_start);
+    if (c->d_run_pos) (void)hipFree(c->d_run_pos);
+    if (c->d_copy_rec) (void)hipFree(c->d_copy_rec);
+    if (c->d_copy_src) (void)hipFree(c->d_copy_src);
     if (c->own_ws && c->ws) (void)hipFree(c->ws);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
@@ -2287,6 +2410,77 @@ int ht_set_nodes(ht_ctx* c, int32_t n_nodes, double t_tree, const double* m, con
 
 namespace {
 int upload_group_offsets(ht_ctx* c);
+
+// Run-length form of the lists just set (Section 2's cell-index memory of
+// start and count pairs, with each group's nodes copied contiguously): the
+// node entries of every list, in list order, are replaced by copies of their
+// records at consecutive indices from N + M on, and the list becomes runs of
+// consecutive indices (Peano-Hilbert order makes neighbouring particles
+// neighbouring indices).  Expanded, the runs give back the lists' records in
+// the lists' order, so the force is the CSR form's, bit for bit.
+int build_runs(ht_ctx* c, const int32_t* entries) {
+    const int64_t L = c->list_off.back();
+    const int64_t base = static_cast<int64_t>(c->n) + c->n_nodes;
+    std::vector<int32_t> start, src;
+    std::vector<int64_t> pos;
+    int64_t prev = -2;
+    for (int64_t e = 0; e < L; ++e) {
+        const int32_t j = entries[e];
+        int64_t idx = j;
+        if (j >= c->n) {
+            idx = base + static_cast<int64_t>(src.size());
+            src.push_back(j);
+        }
+        if (idx != prev + 1) {
+            start.push_back(static_cast<int32_t>(idx));
+            pos.push_back(e);
+        }
+        prev = idx;
+    }
+    if (base + static_cast<int64_t>(src.size()) > INT32_MAX)
+        return fail(HT_ERANGE, "%zu node copies do not fit 32-bit indices", src.size());
+    const size_t nr = start.size(), nc = src.size();
+    if (nr > c->run_cap) {
+        if (c->d_run_start) (void)hipFree(c->d_run_start);
+        if (c->d_run_pos) (void)hipFree(c->d_run_pos);
+        c->d_run_start = nullptr;
+        c->d_run_pos = nullptr;
+        c->run_cap = 0;
+        if (hipMalloc(&c->d_run_start, nr * 4) != hipSuccess || hipMalloc(&c->d_run_pos, nr * 8) != hipSuccess)
+            return fail(HT_ENOMEM, "hipMalloc of %zu runs failed", nr);
+        c->run_cap = nr;
+    }
+    if (nc > c->copy_cap) {
+        if (c->d_copy_rec) (void)hipFree(c->d_copy_rec);
+        if (c->d_copy_src) (void)hipFree(c->d_copy_src);
+        c->d_copy_rec = nullptr;
+        c->d_copy_src = nullptr;
+        c->copy_cap = 0;
+        if (hipMalloc(&c->d_copy_rec, nc * 128) != hipSuccess || hipMalloc(&c->d_copy_src, nc * 4) != hipSuccess)
+            return fail(HT_ENOMEM, "hipMalloc of %zu node copies failed", nc);
+        c->copy_cap = nc;
+    }
+    if (nr) {
+        HT_HIP(hipMemcpyAsync(c->d_run_start, start.data(), nr * 4, hipMemcpyHostToDevice, c->stream));
+        HT_HIP(hipMemcpyAsync(c->d_run_pos, pos.data(), nr * 8, hipMemcpyHostToDevice, c->stream));
+    }
+    if (nc) {
+        HT_HIP(hipMemcpyAsync(c->d_copy_src, src.data(), nc * 4, hipMemcpyHostToDevice, c->stream));
+        const int grid = static_cast<int>(std::min<size_t>((nc + kWG - 1) / kWG, 65536));
+        const void* rec = c->ws + c->L.off_rec;
+        if (c->cfg.precision == HT_PREC_FP64)
+            copy_records_kernel<PrecFp64><<<grid, kWG, 0, c->stream>>>(rec, c->d_copy_src, static_cast<int64_t>(nc),
+                                                                       c->d_copy_rec);
+        else
+            copy_records_kernel<PrecMixed><<<grid, kWG, 0, c->stream>>>(rec, c->d_copy_src, static_cast<int64_t>(nc),
+                                                                        c->d_copy_rec);
+        HT_HIP(hipGetLastError());
+    }
+    c->run_pos = std::move(pos);
+    c->n_runs = static_cast<int64_t>(nr);
+    c->n_copies = static_cast<int64_t>(nc);
+    return ctx_sync(c);   // pageable sources
+}
 }  // namespace
 
 int ht_set_interaction_lists(ht_ctx* c, int32_t n_groups, const int64_t* group_first, const int64_t* list_off,
@@ -2321,6 +2515,10 @@ int ht_set_interaction_lists(ht_ctx* c, int32_t n_groups, const int64_t* group_f
     c->list_off.assign(list_off, list_off + n_groups + 1);
     c->n_groups = n_groups;
     c->n_entries = L;
+    if (c->list_form == HT_LISTS_RUNS) {
+        int rc = build_runs(c, entries);
+        if (rc) return rc;
+    }
     c->have_lists = true;
     if (c->ds_mem) return upload_group_offsets(c);
     return HT_OK;
@@ -2349,6 +2547,18 @@ int ht_predict_many(int32_t n_ctx, ht_ctx* const* ctxs, const double* t) {
     for (int32_t k = 0; k < n_ctx; ++k) {
         int rc = ht_predict(ctxs[k], t[k]);
         if (rc) return rc;
+    }
+    return HT_OK;
+}
+
+int ht_set_list_form(ht_ctx* c, int32_t form) {
+    if (!c) return fail(HT_EINVAL, "ctx is NULL");
+    if (form != HT_LISTS_CSR && form != HT_LISTS_RUNS) return fail(HT_EINVAL, "unknown list form %d", form);
+    if (form == HT_LISTS_RUNS && c->cfg.predict_mode != HT_PREDICT_FUSED)
+        return fail(HT_EINVAL, "run-length lists need fused prediction");
+    if (form != c->list_form) {
+        c->list_form = form;
+        c->have_lists = false;   // the lists must be set again, in the new form
     }
     return HT_OK;
 }
@@ -2466,6 +2676,7 @@ int ht_step_graph(ht_ctx* c, int32_t n_upd, const int32_t* d_idx, const double* 
                   int32_t n_active, const int32_t* ids, double* d_acc, double* d_jerk_out, double* d_pot) {
     if (!c) return fail(HT_EINVAL, "ctx is NULL");
     if (c->cfg.predict_mode != HT_PREDICT_FUSED) return fail(HT_EINVAL, "graph steps need fused prediction");
+    if (c->list_form != HT_LISTS_CSR) return fail(HT_EINVAL, "graph steps take CSR lists");
     if (!c->have_lists) return fail(HT_ESTATE, "interaction lists not set");
     int rc = check_dev_rows(c, n_upd, d_idx, d_t0, d_m, d_x, d_v, d_a, d_jerk);
     if (rc) return rc;
@@ -2704,6 +2915,7 @@ int ht_state_rebuild(ht_ctx* c, htd_tree* t, int32_t n_leaf, int32_t n_crit, dou
     if (!c->ds_mem) return fail(HT_ESTATE, "device state not enabled");
     if (c->n < 1) return fail(HT_ESTATE, "particles not set");
     if (!std::isfinite(t_tree)) return fail(HT_EINVAL, "t_tree not finite");
+    if (c->list_form != HT_LISTS_CSR) return fail(HT_EINVAL, "device rebuilds write CSR lists");
     const int32_t n = c->n;
     if (int rc = ctx_sync(c)) return rc;   // the state is complete before the builder reads it
     if (int rc = htd_build(t, n, c->ds.x, c->ds.v, c->ds.a, c->ds.j, c->ds.m, n_leaf, n_crit, theta))
@@ -2934,6 +3146,7 @@ int ht_dev_run(ht_ctx* c, double eta, double dt_tree, double t_stop, int32_t max
     if (!c->ds_mem) return fail(HT_ESTATE, "device state not enabled");
     if (!c->have_lists) return fail(HT_ESTATE, "interaction lists not set");
     if (c->cfg.predict_mode != HT_PREDICT_FUSED) return fail(HT_EINVAL, "the device loop needs fused prediction");
+    if (c->list_form != HT_LISTS_CSR) return fail(HT_EINVAL, "the device loop plans CSR lists");
     if (c->gather_cost != std::floor(c->gather_cost))
         return fail(HT_EINVAL, "the device loop plans with a whole-number gather cost (ht_set_tuning)");
     if (!(eta > 0.0) || !(dt_tree > 0.0) || !std::isfinite(t_stop)) return fail(HT_EINVAL, "bad eta, dt_tree or t_stop");
@@ -3014,6 +3227,8 @@ int ht_force_batch_async(int32_t n_ctx, ht_ctx* const* ctxs, const int32_t* n_ac
         if (c->stream != c0->stream) return fail(HT_EINVAL, "ctx %d does not share the stream of ctx 0", k);
         for (int32_t q = 0; q < k; ++q)
             if (ctxs[q] == c) return fail(HT_EINVAL, "ctx %d appears twice in the batch", k);
+        if (c->list_form != HT_LISTS_CSR)
+            return fail(HT_EINVAL, "ctx %d uses run-length lists, which batched calls do not take", k);
         if (!c->have_particles || !c->have_lists) return fail(HT_ESTATE, "ctx %d: lists not set", k);
         if (!c->predicted) return fail(HT_ESTATE, "ctx %d: not predicted", k);
         int rc = validate_active(c, n_active[k], ids[k]);
@@ -3160,6 +3375,7 @@ int check_member(const ht_batch* b, const ht_ctx* c, int32_t k, ht_ctx* const* c
     if (!c) return fail(HT_EINVAL, "ctx %d is NULL", k);
     if (c->cfg.device != b->device) return fail(HT_EINVAL, "ctx %d is on another device", k);
     if (same_stream && c->stream != b->stream) return fail(HT_EINVAL, "ctx %d does not share the batch's stream", k);
+    if (c->list_form != HT_LISTS_CSR) return fail(HT_EINVAL, "ctx %d uses run-length lists, which batched calls do not take", k);
     if (c->cfg.precision != ctxs[0]->cfg.precision || c->cfg.predict_mode != ctxs[0]->cfg.predict_mode)
         return fail(HT_EINVAL, "ctx %d differs in precision or predict mode", k);
     for (int32_t q = 0; q < k; ++q)
@@ -3968,7 +4184,7 @@ __global__ __launch_bounds__(kWG) void noalloc_direct_kernel(int32_t n, const do
             const int64_t j = base + tid;
             tile[tid] = JRec<P>{x[3 * j], x[3 * j + 1], x[3 * j + 2], static_cast<V>(v[3 * j]),
                                 static_cast<V>(v[3 * j + 1]), static_cast<V>(v[3 * j + 2]),
-                                static_cast<double>(static_cast<S>(m[j])),
+                                static_cast<S>(m[j]),
                                 static_cast<int32_t>(j)};
         }
         __syncthreads();

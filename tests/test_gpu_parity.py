@@ -490,3 +490,67 @@ def test_step_graph_replays_equal_step_async(prec):
         eager.set_interaction_lists(ptr.group_first, ptr.list_off, ptr.entries)
         out = tuple(torch.empty(s, dtype=torch.float64, device="cuda") for s in ((1, 3), (1, 3), (1,)))
         eager.step_graph(None, t, np.array([0], np.int32), *out)
+
+
+# ------------------------------------------------------------------------------------------ run-length lists
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_run_length_lists_equal_csr(oracle, prec):
+    """Run-length lists with per-group node copies (ht_set_list_form RUNS): the
+    same work items over the same records in the same order, so every output
+    equals the CSR form's bit for bit, for active sets that hit every tile size
+    (round boundaries inside runs, runs longer than a round, single-entry
+    runs), through a j-memory update and prediction in one call; and the
+    oracle agrees."""
+    import torch
+    say(f"run-length lists vs CSR ({prec})")
+    n = 7000
+    x, v, m = W.plummer(n, 61)
+    m = W.salpeter_masses(n, 62)
+    z = np.zeros((n, 3))
+    ptr = B.HostTree(x, v, z, z, m, 1, 300, 0.5)
+    x, v, m = x[ptr.perm], v[ptr.perm], m[ptr.perm]
+    t0, a, j = W.random_block_state(n, 63, 0.25)
+    ctxs = {}
+    for form in ("csr", "runs"):
+        c = make_ctx(prec, n, 2 * n, n, 2 * ptr.n_entries, 1e-4)
+        c.set_list_form(form)
+        c.set_j_particles(t0, m, x, v, a, j)
+        c.set_nodes(0.0, ptr.node_m, ptr.node_x, ptr.node_v, ptr.node_a, ptr.node_j)
+        c.set_interaction_lists(ptr.group_first, ptr.list_off, ptr.entries)
+        ctxs[form] = c
+    gf = ptr.group_first
+    # the mixed form stores a, jerk and m in FP32: the oracle gets them so
+    r = (lambda u: u.astype(np.float32).astype(np.float64)) if prec == "mixed" else (lambda u: u)
+    rng = np.random.default_rng(64)
+    counts = [1, 2, 3, 7, 9, 17, 33, 64, 65, 129, 257]
+    sel = [np.sort(rng.choice(np.arange(gf[g], gf[g + 1]), min(gf[g + 1] - gf[g], counts[g % len(counts)]),
+                              replace=False)) for g in range(ptr.n_group)]
+    dev = lambda u: torch.from_numpy(np.ascontiguousarray(u)).cuda()  # noqa: E731
+    t = 0.25
+    for step, ids in enumerate((np.concatenate(sel), np.arange(n), np.array([5]), np.arange(0, n, 13))):
+        ids = ids.astype(np.int32)
+        got = {}
+        for form, c in ctxs.items():
+            c.predict(t)
+            got[form] = c.force(ids)
+        for p_, q_ in zip(got["csr"], got["runs"]):
+            assert np.array_equal(p_, q_), (prec, step)
+        xp, vp = oracle.predict(t, t0, x, v, r(a), r(j))
+        nxp, nvp = oracle.predict(t, 0.0, ptr.node_x, ptr.node_v, r(ptr.node_a), r(ptr.node_j))
+        want = oracle.force_list(ids, np.vstack([xp, nxp]), np.vstack([vp, nvp]), r(np.concatenate([m, ptr.node_m])),
+                                 1e-4, gf, ptr.list_off, ptr.entries)
+        assert_close(f"runs step {step}", prec, got["runs"], want)
+    # an update and the force in one call (ht_step_async)
+    upd_ids = np.sort(rng.choice(n, 500, replace=False)).astype(np.int32)
+    upd = (500, dev(upd_ids), dev(np.full(500, 0.25)), dev(m[upd_ids]), dev(x[upd_ids] + 1e-4), dev(v[upd_ids]),
+           dev(a[upd_ids]), dev(j[upd_ids]))
+    act = np.sort(rng.choice(n, 900, replace=False)).astype(np.int32)
+    outs = {f: tuple(torch.empty(sh, dtype=torch.float64, device="cuda") for sh in ((900, 3), (900, 3), (900,)))
+            for f in ctxs}
+    for form, c in ctxs.items():
+        c.step_async(upd, 0.28125, act, *outs[form])
+        c.sync()
+    for p_, q_ in zip(outs["csr"], outs["runs"]):
+        assert torch.equal(p_, q_)
+    with pytest.raises(B.HTError):
+        B.force_batch_async([ctxs["runs"]], [act], [outs["runs"][0]], [outs["runs"][1]], [outs["runs"][2]])
