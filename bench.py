@@ -127,12 +127,14 @@ class Recorded:
         self.steps.append((t, act.astype(np.int32), upd))
 
 
-def make_ctx(B, snap, n, precision, eps2, stream, predict_mode="fused", lists="csr"):
+def make_ctx(B, snap, n, precision, eps2, stream, predict_mode="fused", lists="csr", placement=None):
     ctx = B.Context(n_max=n, node_max=snap["n_node"] + 64, group_max=snap["n_group"] + 16,
                     list_max=snap["n_entries"] + 1024, active_max=n, eps2=eps2, precision=precision,
                     predict_mode=predict_mode, stream=stream)
     if lists != "csr":
         ctx.set_list_form(lists)
+    if placement is not None:
+        ctx.set_placement(placement)
     load_snapshot(ctx, snap)
     return ctx
 
@@ -150,65 +152,73 @@ def device_updates(torch, rec):
     return out
 
 
-def replay(torch, B, rec, ctx, stream, warmup, steps, direct=False, instrument=True, graph=False):
+def replay(torch, B, rec, ctx, stream, warmup, steps, direct=False, mode="clean", graph=False):
     """Replay recorded steps; returns a timing dict for the last `steps` steps.
 
-    instrument=False: nothing but the steps between the two synchronisations
-    (the throughput figure).  instrument=True: a HIP event on the stream
-    before every step (step latency) and kernel timing events around every
-    force launch (kernel time), at some cost in throughput."""
+    mode "clean": nothing but the steps between the two synchronisations (the
+    throughput figure).  "latency": one HIP event on the stream before every
+    step, nothing else (step latency).  "kernel": HIP events around every
+    force launch (kernel time and launches), the per-step pairs and work
+    items, and the host time of each step call.  Addresses of the recorded
+    arrays (update rows on the device, active ids on the host) are taken
+    before the timed loop, as a driver that keeps them resident would."""
     dev_upd = device_updates(torch, rec)
     kmax = max(a.size for _, a, _ in rec.steps)
     acc = torch.empty((kmax, 3), dtype=torch.float64, device="cuda")
     jrk = torch.empty((kmax, 3), dtype=torch.float64, device="cuda")
     pot = torch.empty(kmax, dtype=torch.float64, device="cuda")
     out_ptrs = (acc.data_ptr(), jrk.data_ptr(), pot.data_ptr())
-    # device addresses of every step's update rows, taken before the timed loop
     upd_ptrs = [None] + [(u[0].shape[0],) + tuple(x.data_ptr() for x in u) for u in dev_upd[:-1]]
+    act_ptrs = [(a.size, a.ctypes.data) for _, a, _ in rec.steps]
+    times = [t for t, _, _ in rec.steps]
 
     def run_step(k):
-        t, act, _ = rec.steps[k]
-        upd = upd_ptrs[k]
         if direct:
+            upd = upd_ptrs[k]
             if upd is not None:
                 ctx.set_j_particles_async(*upd)
-            ctx.predict(t)
-            ctx.force_direct_async(act, *out_ptrs)
+            ctx.predict(times[k])
+            ctx.force_direct_async(rec.steps[k][1], *out_ptrs)
         elif graph:
-            ctx.step_graph(upd, t, act, *out_ptrs)
+            ctx.step_graph(upd_ptrs[k], times[k], rec.steps[k][1], *out_ptrs)
         else:
-            ctx.step_async(upd, t, act, *out_ptrs)
+            ctx.step_async(upd_ptrs[k], times[k], act_ptrs[k], *out_ptrs)
 
     for k in range(warmup):
         run_step(k)
     torch.cuda.synchronize()
-    if not instrument:
+    if mode == "clean":
         t_wall = time.perf_counter()
         for k in range(warmup, warmup + steps):
             run_step(k)
         torch.cuda.synchronize()
         return dict(wall_s=time.perf_counter() - t_wall)
+    if mode == "latency":
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        t_wall = time.perf_counter()
+        for q, k in enumerate(range(warmup, warmup + steps)):
+            evs[q].record(stream)
+            run_step(k)
+        evs[steps].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_wall
+        return dict(wall_s=wall, lat_ms=np.array([evs[q].elapsed_time(evs[q + 1]) for q in range(steps)]))
     ctx.set_timing(True)
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     pairs = 0
     per_step = []
     t_wall = time.perf_counter()
-    for q, k in enumerate(range(warmup, warmup + steps)):
-        evs[q].record(stream)
+    for k in range(warmup, warmup + steps):
         th = time.perf_counter()
         run_step(k)
         th = time.perf_counter() - th
         p, w = ctx.last_stats()
         pairs += p
         per_step.append((int(rec.steps[k][1].size), int(p), int(w), 1e6 * th))
-    evs[steps].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall
     kms, launches, kpairs = ctx.kernel_timing()
     ctx.set_timing(False)
-    lat = np.array([evs[q].elapsed_time(evs[q + 1]) for q in range(steps)])
-    return dict(wall_s=wall, pairs=pairs, kernel_ms=kms, launches=launches, kernel_pairs=kpairs, lat_ms=lat,
-                per_step=per_step)
+    return dict(wall_s=wall, pairs=pairs, kernel_ms=kms, launches=launches, kernel_pairs=kpairs, per_step=per_step)
 
 
 def algorithmic_bytes(rec, warmup):
@@ -524,6 +534,11 @@ def main():
                     help="ensemble workload: run the resident engine as a batched device loop")
     ap.add_argument("--no-engine-records", action="store_true",
                     help="default workload: skip the short ensemble64 and served records")
+    ap.add_argument("--graph-leg", action="store_true",
+                    help="default workload: also replay the window through ht_step_graph (logged only)")
+    ap.add_argument("--placement", type=int, default=None,
+                    help="default workload: work-item stretches over the XCDs (0: one per XCD, 1: off; "
+                         "default: the library's)")
     ap.add_argument("--lists", choices=("csr", "runs"), default="csr",
                     help="default workload: interaction-list form of the tree legs (the graph leg takes CSR)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -665,29 +680,37 @@ def main():
     stream = torch.cuda.Stream()
     sh = stream.cuda_stream
     def leg(precision, direct=False):
-        """The recorded steps once instrumented (latency, kernel time, pairs)
-        and once clean (throughput), each from a fresh copy of the snapshot."""
+        """The recorded steps three times, each from a fresh copy of the
+        snapshot: with kernel timing (kernel time, pairs, items), with one
+        event per step (step latency), and clean (throughput)."""
         lists = "csr" if direct else args.lists
-        ctx = make_ctx(B, rec.snap, rec.n, precision, cfg.eps2, sh, lists=lists)
-        r = replay(torch, B, rec, ctx, stream, args.warmup, args.steps, direct=direct, instrument=True)
+        ctx = make_ctx(B, rec.snap, rec.n, precision, cfg.eps2, sh, lists=lists, placement=args.placement)
+        r = replay(torch, B, rec, ctx, stream, args.warmup, args.steps, direct=direct, mode="kernel")
+        r["placement"] = ctx.placement()
+        r["kernel_wall_s"] = r.pop("wall_s")
         ctx.close()
-        ctx = make_ctx(B, rec.snap, rec.n, precision, cfg.eps2, sh, lists=lists)
-        r["instrumented_wall_s"] = r["wall_s"]
-        r["wall_s"] = replay(torch, B, rec, ctx, stream, args.warmup, args.steps, direct=direct,
-                             instrument=False)["wall_s"]
+        ctx = make_ctx(B, rec.snap, rec.n, precision, cfg.eps2, sh, lists=lists, placement=args.placement)
+        lt = replay(torch, B, rec, ctx, stream, args.warmup, args.steps, direct=direct, mode="latency")
+        r["lat_ms"], r["latency_wall_s"] = lt["lat_ms"], lt["wall_s"]
+        ctx.close()
+        ctx = make_ctx(B, rec.snap, rec.n, precision, cfg.eps2, sh, lists=lists, placement=args.placement)
+        r["wall_s"] = replay(torch, B, rec, ctx, stream, args.warmup, args.steps, direct=direct)["wall_s"]
         ctx.close()
         return r
 
     # ---- mixed tree (the headline)
     mixed = leg("mixed")
     log(f"mixed tree: {mixed['pairs'] / mixed['wall_s']:.4g} pairs/s, {1e3 * mixed['wall_s'] / args.steps:.3f} "
-        f"ms/step ({1e3 * mixed['instrumented_wall_s'] / args.steps:.3f} instrumented), kernel "
-        f"{mixed['kernel_ms']:.3f} ms over {mixed['launches']} launches")
-    # ---- the same steps replayed through the captured step graphs (ht_step_graph)
-    ctx = make_ctx(B, rec.snap, rec.n, "mixed", cfg.eps2, sh)
-    graph_wall = replay(torch, B, rec, ctx, stream, args.warmup, args.steps, instrument=False, graph=True)["wall_s"]
-    ctx.close()
-    log(f"mixed tree, graph replays: {mixed['pairs'] / graph_wall:.4g} pairs/s, {1e3 * graph_wall / args.steps:.3f} ms/step")
+        f"ms/step ({1e3 * mixed['latency_wall_s'] / args.steps:.3f} with step events, "
+        f"{1e3 * mixed['kernel_wall_s'] / args.steps:.3f} with kernel timing), kernel "
+        f"{mixed['kernel_ms']:.3f} ms over {mixed['launches']} launches; step latency p50 "
+        f"{np.percentile(mixed['lat_ms'], 50):.4f} ms")
+    if args.graph_leg:   # the same steps through the captured step graphs (ht_step_graph): log only
+        ctx = make_ctx(B, rec.snap, rec.n, "mixed", cfg.eps2, sh)
+        graph_wall = replay(torch, B, rec, ctx, stream, args.warmup, args.steps, graph=True)["wall_s"]
+        ctx.close()
+        log(f"mixed tree, graph replays: {mixed['pairs'] / graph_wall:.4g} pairs/s, "
+            f"{1e3 * graph_wall / args.steps:.3f} ms/step")
     # ---- direct N^2 on the same steps
     direct = None
     if not args.no_direct:
@@ -702,7 +725,7 @@ def main():
     # ---- the all-particle step at t = dt_tree
     all_active = None
     if not args.no_all_active:
-        ctx = make_ctx(B, rec_all.snap, rec_all.n, "mixed", cfg.eps2, sh, lists=args.lists)
+        ctx = make_ctx(B, rec_all.snap, rec_all.n, "mixed", cfg.eps2, sh, lists=args.lists, placement=args.placement)
         ids = np.arange(rec_all.n, dtype=np.int32)
         acc = torch.empty((rec_all.n, 3), dtype=torch.float64, device="cuda")
         jrk = torch.empty_like(acc)
@@ -765,8 +788,8 @@ def main():
         "steps": K,
         "warmup": args.warmup,
         "ms_per_step": 1e3 * mixed["wall_s"] / K,
-        "instrumented_ms_per_step": 1e3 * mixed["instrumented_wall_s"] / K,
-        "graph_replay": {"interactions_per_s": mixed["pairs"] / graph_wall, "ms_per_step": 1e3 * graph_wall / K},
+        "latency_replay_ms_per_step": 1e3 * mixed["latency_wall_s"] / K,
+        "kernel_replay_ms_per_step": 1e3 * mixed["kernel_wall_s"] / K,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -776,7 +799,8 @@ def main():
                    "eta": cfg.eta, "n_crit": cfg.n_crit, "n_leaf": cfg.n_leaf,
                    "masses": f"salpeter 1:{cfg.mass_ratio:g}" if cfg.mass_seed is not None else "equal",
                    "window": f"{K} block steps after the rebuild at t={cfg.dt_tree}", "precision": "mixed",
-                   "predict": "fused", "lists": args.lists},
+                   "predict": "fused", "lists": args.lists,
+                   "placement": {"runs": mixed["placement"][0], "xcds": mixed["placement"][1]}},
         "p50_step_ms": float(np.percentile(lat, 50)),
         "p99_step_ms": float(np.percentile(lat, 99)),
         "active_per_step": {"min": int(n_act.min()), "median": float(np.median(n_act)), "max": int(n_act.max()),

@@ -434,6 +434,22 @@ int ht_sync(ht_ctx *ctx);
  * changes). */
 int ht_set_tuning(ht_ctx *ctx, double gather_cost, double target_items);
 
+/* Placement of a call's work items over the XCDs of the device (each with
+ * its own L2; the paper's single pipeline array has no counterpart).  With
+ * runs > 1 the host planner of the single-context list calls (ht_force,
+ * ht_force_async, ht_step_async; not the direct sum) cuts the items, in
+ * the order of their groups along the space-filling curve, into `runs`
+ * stretches of equal modelled cost, orders each stretch longest first and
+ * launches the force kernel so that work-group b takes the items of stretch
+ * b % runs.  Work-groups go to the XCDs in turn, so with runs = the XCD count
+ * each stretch runs on one XCD, whose L2 then serves the records that
+ * neighbouring groups' lists share.  runs = 0: the device's XCD count; 1: off
+ * (one longest-first order over all items).  Results do not depend on the
+ * placement.  HT_EINVAL for runs outside [0, 16].  ht_get_placement returns
+ * the runs in use and the device's XCD count. */
+int ht_set_placement(ht_ctx *ctx, int32_t runs);
+int ht_get_placement(const ht_ctx *ctx, int32_t *runs, int32_t *n_xcc);
+
 /* Pair interactions the last force call summed (list entries x active
  * particles, self pairs included) and the number of work items it used. */
 int ht_last_stats(const ht_ctx *ctx, int64_t *pairs, int32_t *work_items);

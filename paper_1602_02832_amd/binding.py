@@ -153,6 +153,8 @@ def device_lib():
                                  ctypes.POINTER(ctypes.c_int32)],
             "ht_state_bytes": [ctypes.POINTER(HtConfig), ctypes.POINTER(ctypes.c_size_t)],
             "ht_set_list_form": [_vp, i],
+            "ht_set_placement": [_vp, i],
+            "ht_get_placement": [_vp, _c_i32p, _c_i32p],
             "ht_state_enable_ws": [_vp, _vp, ctypes.c_size_t],
             "ht_pool_create": [ctypes.POINTER(_vp), i, ctypes.c_size_t],
             "ht_pool_destroy": [_vp],
@@ -253,6 +255,9 @@ def _ptr(a, ctype):
     return a.ctypes.data_as(ctypes.POINTER(ctype)) if a is not None else None
 
 
+_NONE7 = (None,) * 7
+
+
 def _dptr(t):
     """Device address of a torch tensor (or an int address, or None)."""
     if t is None:
@@ -285,6 +290,7 @@ class Context:
         h = _vp()
         _check(L.ht_create(ctypes.byref(h), ctypes.byref(self.cfg), ws_ptr, self.workspace_bytes))
         self._h = h
+        self._step_async = L.ht_step_async
 
     @property
     def handle(self):
@@ -332,6 +338,17 @@ class Context:
         _check(device_lib().ht_set_interaction_lists(self._h, gf.shape[0] - 1, _ptr(gf, ctypes.c_int64),
                                                      _ptr(lo, ctypes.c_int64), _ptr(en, ctypes.c_int32)))
 
+    def set_placement(self, runs):
+        """ht_set_placement: work items in `runs` stretches, one per XCD (0: the
+        device's XCD count, 1: off)."""
+        _check(device_lib().ht_set_placement(self._h, int(runs)))
+
+    def placement(self):
+        """(runs in use, the device's XCD count)."""
+        r, x = ctypes.c_int32(), ctypes.c_int32()
+        _check(device_lib().ht_get_placement(self._h, ctypes.byref(r), ctypes.byref(x)))
+        return r.value, x.value
+
     def set_list_form(self, form):
         """ht_set_list_form: "csr" (default) or "runs" (run-length lists with the
         groups' node copies); the lists must be set again afterwards."""
@@ -368,14 +385,24 @@ class Context:
 
     def step_async(self, upd, t, active, d_acc, d_jerk, d_pot):
         """ht_step_async: upd = (n, d_idx, d_t0, d_m, d_x, d_v, d_a, d_jerk) or None
-        (device tensors or addresses)."""
-        active = _arr(active, np.int32)
-        if upd is None:
-            n_upd, ptrs = 0, (None,) * 7
+        (device tensors, or addresses when d_idx is an int); active = int32 ids,
+        or (count, host address) of int32 ids that the caller keeps alive until
+        the call returns; outputs as tensors or addresses.  Called once per
+        block step, so the marshalling takes the short way for addresses."""
+        if type(active) is tuple:
+            n_act, a_ptr = active
         else:
-            n_upd, ptrs = int(upd[0]), tuple(_dptr(u) for u in upd[1:])
-        _check(device_lib().ht_step_async(self._h, n_upd, *ptrs, float(t), active.shape[0], active.ctypes.data,
-                                          _dptr(d_acc), _dptr(d_jerk), _dptr(d_pot)))
+            active = _arr(active, np.int32)
+            n_act, a_ptr = active.shape[0], active.ctypes.data
+        if upd is None:
+            n_upd, ptrs = 0, _NONE7
+        else:
+            n_upd, ptrs = upd[0], (upd[1:] if type(upd[1]) is int else tuple(_dptr(u) for u in upd[1:]))
+        if type(d_acc) is not int:
+            d_acc, d_jerk, d_pot = _dptr(d_acc), _dptr(d_jerk), _dptr(d_pot)
+        rc = self._step_async(self._h, n_upd, *ptrs, t, n_act, a_ptr, d_acc, d_jerk, d_pot)
+        if rc:
+            _check(rc)
 
     def step_graph(self, upd, t, active, d_acc, d_jerk, d_pot):
         """ht_step_graph: as step_async, replayed through the context's HIP graphs."""

@@ -250,6 +250,48 @@ __device__ __forceinline__ void load_state(const Desc& c, int j, double& x, doub
 }
 
 // ------------------------------------------------------------------------------------------------
+// Lane exchange for pairwise trees within a wave, on the vector ALU: the
+// value of the lane OFF places above (OFF = 1, 2, ..., 32), for the lanes
+// 0..OFF-1 of the wave; other lanes get unspecified values.  OFF < 16 is a
+// DPP row shift (lanes 0..OFF-1 and their partners share a 16-lane row); 16
+// and 32 are the gfx950 swaps of 16-lane rows and 32-lane halves, whose
+// second result holds the upper row (half) in the lower one.  64-bit values
+// move as two 32-bit halves.  All lanes of the wave must be active.
+template <int OFF>
+__device__ __forceinline__ uint32_t lane_above_u32(uint32_t v) {
+    static_assert(OFF >= 1 && OFF <= 32 && (OFF & (OFF - 1)) == 0, "power-of-two lane offset");
+    if constexpr (OFF == 32) return __builtin_amdgcn_permlane32_swap(v, v, false, false)[1];
+    else if constexpr (OFF == 16) return __builtin_amdgcn_permlane16_swap(v, v, false, false)[1];
+    else return __builtin_amdgcn_update_dpp(0u, v, 0x100 + OFF, 0xf, 0xf, true);   // row_shl:OFF
+}
+
+template <int OFF, class V>
+__device__ __forceinline__ V lane_above(V v) {
+    static_assert(sizeof(V) == 4 || sizeof(V) == 8, "32- or 64-bit values");
+    if constexpr (sizeof(V) == 4) {
+        return __builtin_bit_cast(V, lane_above_u32<OFF>(__builtin_bit_cast(uint32_t, v)));
+    } else {
+        const uint64_t b = __builtin_bit_cast(uint64_t, v);
+        const uint32_t lo = lane_above_u32<OFF>(static_cast<uint32_t>(b));
+        const uint32_t hi = lane_above_u32<OFF>(static_cast<uint32_t>(b >> 32));
+        return __builtin_bit_cast(V, (static_cast<uint64_t>(hi) << 32) | lo);
+    }
+}
+
+// Pairwise tree over a wave, lane k combining with lane k + OFF for OFF =
+// FIRST, FIRST / 2, ..., LAST: with FIRST = 32 and LAST = 1 lane 0 ends with
+// the whole wave's reduction.
+template <int FIRST, int LAST, class V, class Op>
+__device__ __forceinline__ V wave_tree(V v, Op op) {
+    if constexpr (FIRST >= LAST) {
+        v = op(v, lane_above<FIRST>(v));
+        return wave_tree<FIRST / 2, LAST>(v, op);
+    } else {
+        return v;
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
 // pair interaction: r = x_j - x_i, w = v_j - v_i, s = r.r + eps^2
 //   a += m r s^-3/2,  jerk += m s^-3/2 (w - 3 (r.w)/s r),  pot -= m s^-1/2
 struct Acc64 {
@@ -428,16 +470,14 @@ __device__ __forceinline__ void run_item(const Desc& c, const Item& it, int64_t 
 
     // Reduce the S j-streams of each i-slot in a fixed order, so results never
     // depend on timing.  T < 64: the 64 / T streams of a wave first, by a
-    // pairwise tree of lane shuffles (stream s += stream s + h, h = 32/T, ...,
-    // 1), then the four waves in order through LDS.  T >= 64 (at most four
-    // streams, whole waves each): a pairwise tree in LDS.
+    // pairwise tree of lane exchanges (stream s += stream s + h, h = 32/T, ...,
+    // 1, i.e. lane offsets 32 down to T), then the four waves in order through
+    // LDS.  T >= 64 (at most four streams, whole waves each): a pairwise tree
+    // in LDS.
     if constexpr (T < 64) {
-        constexpr int W = 64 / T;   // streams per wave
+        auto add = [](double p, double q) { return p + q; };
 #pragma unroll
-        for (int h = W / 2; h >= 1; h /= 2) {
-#pragma unroll
-            for (int q = 0; q < kOut; ++q) A.v[q] += __shfl_down(A.v[q], h * T, 64);
-        }
+        for (int q = 0; q < kOut; ++q) A.v[q] = wave_tree<32, T>(A.v[q], add);
         const int lane = tid & 63, wave = tid >> 6;
         __syncthreads();
         if (lane < T) {
@@ -502,14 +542,28 @@ struct WavesPerSimd { static constexpr int value = P::kMixed && !RUNS ? 4 : 3; }
 // launch, written by the plan's delivery or by the device planner).  (A shared atomic work counter was measured to cost
 // about 1 us per item: device-scope atomics on one address serialise across
 // the eight XCDs.)
+// Placed plans (bins != nullptr): the items come in n_bins runs, run x being
+// items bins[x] .. bins[x+1]-1, and work-group b takes the items of run
+// b % n_bins from position b / n_bins on, in steps of grid / n_bins (the grid
+// is n_bins times the longest run).  Work-groups are handed to the XCDs in
+// turn, so each run stays on one XCD and its L2.
 template <class P, bool EAGER, bool DIRECT, bool RUNS = false>
 __global__ __launch_bounds__(kWG, (WavesPerSimd<P, RUNS>::value)) void force_kernel(const Entry* __restrict__ tab,
-                                                                                   int n_tab,
-                                                                          int64_t n_items, const int64_t* counts) {
+                                                                                   int n_tab, int64_t n_items,
+                                                                                   const int64_t* counts,
+                                                                                   const int64_t* bins = nullptr,
+                                                                                   int n_bins = 1) {
     __shared__ LdsAll<P> lds;
     __shared__ typename std::conditional<RUNS, RunLds, NoRunLds>::type rl;
     if (n_items < 0) n_items = counts[0];
-    for (int64_t g = blockIdx.x; g < n_items; g += gridDim.x) {
+    int64_t g0 = blockIdx.x, step = gridDim.x;
+    if (bins) {
+        const int x = static_cast<int>(blockIdx.x % static_cast<unsigned>(n_bins));
+        g0 = bins[x] + blockIdx.x / static_cast<unsigned>(n_bins);
+        step = gridDim.x / static_cast<unsigned>(n_bins);
+        n_items = bins[x + 1];
+    }
+    for (int64_t g = g0; g < n_items; g += step) {
         const int cl = find_entry(tab, n_tab, g, false);
         const Desc& c = tab[cl].d;
         const int64_t k = g - tab[cl].first_item;
@@ -800,7 +854,7 @@ struct DevOut {
 constexpr int kSchedBlocks = 1024;   // most scheduler blocks (contiguous particle ranges)
 
 __device__ __forceinline__ double block_min(double v, double* red) {
-    for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_down(v, o, 64));
+    v = wave_tree<32, 1>(v, [](double p, double q) { return fmin(p, q); });
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     __syncthreads();
     if (lane == 0) red[wave] = v;
@@ -865,7 +919,7 @@ __global__ __launch_bounds__(kWG) void sched_count_kernel(SchedEntry e0, const S
     const int64_t lo = b * e.chunk, hi = lo + e.chunk < e.n ? lo + e.chunk : e.n;
     int c = 0;
     for (int64_t i = lo + threadIdx.x; i < hi; i += kWG) c += e.t0[i] + e.dt[i] == t_next;
-    for (int o = 32; o >= 1; o >>= 1) c += __shfl_down(c, o, 64);
+    c = wave_tree<32, 1>(c, [](int p, int q) { return p + q; });
     if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = c;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -889,7 +943,7 @@ __global__ __launch_bounds__(kWG) void sched_write_kernel(SchedEntry e0, const S
     const double t_next = block_min(v, red);
     int64_t before = 0;
     for (int k = threadIdx.x; k < b; k += kWG) before += e.bcount[k];
-    for (int o = 32; o >= 1; o >>= 1) before += __shfl_down(before, o, 64);
+    before = wave_tree<32, 1>(before, [](int64_t p, int64_t q) { return p + q; });
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) part[wave] = before;
     __syncthreads();
@@ -1562,6 +1616,7 @@ int ceil_log2(int64_t v) {
 constexpr double kGatherCostDefault = 12.0;    // work-plan cost of one round's gather, in pairs per lane (measured best 8-16)
 constexpr double kTargetItemsDefault = 2048.0; // work items a call is split towards (2 per resident slot)
 constexpr int kStageRows = 1 << 16;  // rows per host->device upload chunk
+constexpr int kMaxBins = 16;         // runs of a placed plan (one per XCD)
 
 struct Layout {
     size_t jcap, stored, vel;
@@ -1595,7 +1650,8 @@ bool layout_of(const ht_config& c, Layout& L) {
     L.plan_bytes = align_up(kMaxBatch * sizeof(Entry)) + align_up(static_cast<size_t>(L.items_max) * sizeof(Item)) +
                    align_up(static_cast<size_t>(L.items_max) * sizeof(RTile)) +
                    align_up(static_cast<size_t>(c.active_max) * 4) +
-                   align_up(static_cast<size_t>(L.items_max) * 8) + 256;   // item run cursors (run-length lists)
+                   align_up(static_cast<size_t>(L.items_max) * 8) +   // item run cursors (run-length lists)
+                   align_up((kMaxBins + 1) * 8) + 256;                 // run offsets of a placed plan
     L.off_plan = take(L.plan_bytes);
     L.off_partial = take(static_cast<size_t>(L.partial_max) * kOut * 8);
     L.off_out = take(static_cast<size_t>(c.active_max) * kOut * 8);
@@ -1662,6 +1718,13 @@ struct ht_ctx {
     double gather_cost = kGatherCostDefault;
     double target_items = kTargetItemsDefault;
     int8_t first_tile[257] = {};   // least-cost tiling for the gather cost (tile_table)
+    // placement over XCDs (ht_set_placement): placement runs requested (1: off),
+    // the device's XCD count, and the last plan's run offsets and longest run
+    int32_t placement = 1, n_xcc = 1;
+    int32_t n_bins = 1;
+    int64_t bin_off[kMaxBins + 1] = {};
+    int64_t bin_max = 0;
+    std::vector<uint8_t> item_bin, sort_bins;
     // ht_step_graph: captured step graphs, one per pinned header slot, so the
     // host can fill headers while earlier replays are still running
     hipStream_t cap_stream = nullptr;
@@ -1849,7 +1912,7 @@ void tile_table(double gather_cost, int8_t* first_tile) {
     }
 }
 
-int plan(ht_ctx* c, int32_t n_active, const int32_t* ids, bool direct) {
+int plan(ht_ctx* c, int32_t n_active, const int32_t* ids, bool direct, bool place = false) {
     auto& items = c->items;
     auto& rtiles = c->rtiles;
     static thread_local std::vector<Tile> tiles;
@@ -1907,31 +1970,78 @@ int plan(ht_ctx* c, int32_t n_active, const int32_t* ids, bool direct) {
         if (attempt > 60) return fail(HT_ERANGE, "work plan exceeds the context's item capacity");
         quantum *= 2.0;
     }
+    // Placement (more than one run requested, list items): the items, still in
+    // group order, i.e. in space-filling order of their groups, are cut into
+    // n_bins runs of equal modelled cost, an item going to the run that holds
+    // the middle of its cost.  Neighbouring groups' lists share most of their
+    // nodes and many particles, so a run's items reuse each other's records in
+    // the L2 of the XCD that runs them; a long list's splits still spread over
+    // the runs.
+    const double gc = c->gather_cost;
+    auto item_cost = [gc](const Item& it) {
+        return static_cast<double>((it.j_end - it.j_begin + kRound - 1) / kRound) *
+               (gc + static_cast<double>(1 << it.tile_log2));
+    };
+    const int nb = (place && c->placement > 1 && !direct && items.size() > 1) ? c->placement : 1;
+    auto& ib = c->item_bin;
+    ib.assign(items.size(), 0);
+    if (nb > 1) {
+        double tot = 0.0, cum = 0.0;
+        for (const Item& it : items) tot += item_cost(it);
+        for (size_t q = 0; q < items.size(); ++q) {
+            const double w = item_cost(items[q]);
+            const int b = static_cast<int>(static_cast<double>(nb) * (cum + 0.5 * w) / tot);
+            ib[q] = static_cast<uint8_t>(std::min(std::max(b, 0), nb - 1));
+            cum += w;
+        }
+    }
     // Longest first, to 1/8 of an octave: a counting sort on the sign,
     // exponent and top three mantissa bits of the modelled cost (monotone in
     // the cost for positive doubles), equal keys in plan order, so the order
-    // is deterministic and linear in the number of items.
+    // is deterministic and linear in the number of items.  A placed plan is
+    // then ordered by run, stably, so each run is longest first.
     auto& keys = c->sort_keys;
     keys.resize(items.size());
     uint32_t kmin = UINT32_MAX, kmax = 0;
     for (size_t q = 0; q < items.size(); ++q) {
-        const Item& it = items[q];
-        const double cost = static_cast<double>((it.j_end - it.j_begin + kRound - 1) / kRound) *
-                            (c->gather_cost + static_cast<double>(1 << it.tile_log2));
+        const double cost = item_cost(items[q]);
         uint64_t bits;
         std::memcpy(&bits, &cost, 8);
         keys[q] = static_cast<uint32_t>(bits >> 49);
         kmin = std::min(kmin, keys[q]);
         kmax = std::max(kmax, keys[q]);
     }
+    auto& out = c->sort_items;
+    auto& ob = c->sort_bins;
     if (items.size() > 1 && kmax > kmin) {
         auto& count = c->sort_count;
         count.assign(static_cast<size_t>(kmax - kmin) + 2, 0);
         for (uint32_t k : keys) ++count[kmax - k + 1];   // bucket 0 = largest cost
         for (size_t b = 1; b < count.size(); ++b) count[b] += count[b - 1];
-        auto& out = c->sort_items;
         out.resize(items.size());
-        for (size_t q = 0; q < items.size(); ++q) out[count[kmax - keys[q]]++] = items[q];
+        ob.resize(items.size());
+        for (size_t q = 0; q < items.size(); ++q) {
+            const uint32_t at = count[kmax - keys[q]]++;
+            out[at] = items[q];
+            ob[at] = ib[q];
+        }
+        items.swap(out);
+        ib.swap(ob);
+    }
+    c->n_bins = nb;
+    if (nb > 1) {
+        int64_t* off = c->bin_off;
+        std::fill(off, off + nb + 1, 0);
+        for (uint8_t b : ib) ++off[b + 1];
+        c->bin_max = 0;
+        for (int b = 0; b < nb; ++b) {
+            c->bin_max = std::max(c->bin_max, off[b + 1]);
+            off[b + 1] += off[b];
+        }
+        int64_t at[kMaxBins];
+        std::copy(off, off + nb, at);
+        out.resize(items.size());
+        for (size_t q = 0; q < items.size(); ++q) out[at[ib[q]]++] = items[q];
         items.swap(out);
     }
     c->item_runs.clear();
@@ -2023,8 +2133,9 @@ int copy_plan(ht_ctx* c, size_t end) {
 
 template <class P>
 int launch_force(hipStream_t stream, bool eager, Timing& tm, const Entry* d_tab, int n_tab, int64_t n_items,
-                 int64_t n_rtiles, bool direct, int64_t pairs, bool runs = false) {
-    const int grid = grid_for(n_items);
+                 int64_t n_rtiles, bool direct, int64_t pairs, bool runs = false, const int64_t* d_bins = nullptr,
+                 int n_bins = 1, int64_t bin_max = 0) {
+    const int grid = d_bins ? static_cast<int>(n_bins * bin_max) : grid_for(n_items);
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
     if (tm.enabled) {
         while (tm.pool.size() < tm.used + 2) {
@@ -2042,10 +2153,12 @@ int launch_force(hipStream_t stream, bool eager, Timing& tm, const Entry* d_tab,
         if (eager) force_kernel<P, true, true><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr);
         else force_kernel<P, false, true><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr);
     } else if (runs) {
-        force_kernel<P, false, false, true><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr);
+        force_kernel<P, false, false, true><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr, d_bins, n_bins);
     } else {
-        if (eager) force_kernel<P, true, false><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr);
-        else force_kernel<P, false, false><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr);
+        if (eager)
+            force_kernel<P, true, false><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr, d_bins, n_bins);
+        else
+            force_kernel<P, false, false><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr, d_bins, n_bins);
     }
     HT_HIP(hipGetLastError());
     if (ev_b) HT_HIP(hipEventRecord(ev_b, stream));
@@ -2121,13 +2234,20 @@ int check_dev_rows(const ht_ctx* c, int32_t n, const int32_t* d_idx, const doubl
 int enqueue_step(ht_ctx* c, const DevRows& u, bool predict_eager, int32_t n_active, const int32_t* ids,
                  double* d_acc, double* d_jerk, double* d_pot, bool direct) {
     size_t end = 0;
+    const int64_t* d_bins = nullptr;
     if (n_active > 0) {
-        int rc = plan(c, n_active, ids, direct);
+        int rc = plan(c, n_active, ids, direct, true);
         if (rc) return rc;
         rc = c->slot_acquire();
         if (rc) return rc;
         Entry e{};
         end = pack_plan(c, sizeof(Entry), n_active, ids, d_acc, d_jerk, d_pot, e);
+        if (c->n_bins > 1) {   // the placed plan's run offsets
+            const size_t o_bins = align_up(end);
+            std::memcpy(c->plan_host() + o_bins, c->bin_off, static_cast<size_t>(c->n_bins + 1) * 8);
+            d_bins = reinterpret_cast<const int64_t*>(c->ws + c->L.off_plan + o_bins);
+            end = o_bins + static_cast<size_t>(c->n_bins + 1) * 8;
+        }
         e.first_item = 0;
         e.first_rtile = 0;
         e.n_items = static_cast<int64_t>(c->items.size());
@@ -2150,8 +2270,10 @@ int enqueue_step(ht_ctx* c, const DevRows& u, bool predict_eager, int32_t n_acti
     const bool eager = c->cfg.predict_mode == HT_PREDICT_EAGER;
     const bool runs = c->list_form == HT_LISTS_RUNS && !direct;
     rc = c->cfg.precision == HT_PREC_FP64
-             ? launch_force<PrecFp64>(c->stream, eager, c->tm, d_tab, 1, ni, nr, direct, c->last_pairs, runs)
-             : launch_force<PrecMixed>(c->stream, eager, c->tm, d_tab, 1, ni, nr, direct, c->last_pairs, runs);
+             ? launch_force<PrecFp64>(c->stream, eager, c->tm, d_tab, 1, ni, nr, direct, c->last_pairs, runs,
+                                      d_bins, c->n_bins, c->bin_max)
+             : launch_force<PrecMixed>(c->stream, eager, c->tm, d_tab, 1, ni, nr, direct, c->last_pairs, runs,
+                                       d_bins, c->n_bins, c->bin_max);
     if (rc) return rc;
     // The prep launch is the slot's only reader; marking the slot after the
     // whole step keeps the step's launches back to back on the host.
@@ -2269,6 +2391,9 @@ int ht_create(ht_ctx** out, const ht_config* cfg, void* d_workspace, size_t work
     ht_ctx* c = new ht_ctx();
     c->cfg = *cfg;
     c->L = L;
+    int xcc = 1;
+    if (hipDeviceGetAttribute(&xcc, hipDeviceAttributeNumberOfXccs, cfg->device) != hipSuccess || xcc < 1) xcc = 1;
+    c->n_xcc = std::min(xcc, kMaxBins);
     auto cleanup = [&](int rc) {
         ht_destroy(c);
         return rc;
@@ -4000,6 +4125,20 @@ int ht_set_tuning(ht_ctx* c, double gather_cost, double target_items) {
     c->gather_cost = gather_cost;
     c->target_items = target_items;
     tile_table(gather_cost, c->first_tile);
+    return HT_OK;
+}
+
+int ht_set_placement(ht_ctx* c, int32_t runs) {
+    if (!c) return fail(HT_EINVAL, "ctx is NULL");
+    if (runs < 0 || runs > kMaxBins) return fail(HT_EINVAL, "placement runs = %d outside [0, %d]", runs, kMaxBins);
+    c->placement = runs == 0 ? c->n_xcc : runs;
+    return HT_OK;
+}
+
+int ht_get_placement(const ht_ctx* c, int32_t* runs, int32_t* n_xcc) {
+    if (!c) return fail(HT_EINVAL, "ctx is NULL");
+    if (runs) *runs = c->placement;
+    if (n_xcc) *n_xcc = c->n_xcc;
     return HT_OK;
 }
 

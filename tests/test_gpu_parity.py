@@ -554,3 +554,51 @@ def test_run_length_lists_equal_csr(oracle, prec):
         assert torch.equal(p_, q_)
     with pytest.raises(B.HTError):
         B.force_batch_async([ctxs["runs"]], [act], [outs["runs"][0]], [outs["runs"][1]], [outs["runs"][2]])
+
+
+# ------------------------------------------------------------------------------------------ placement over XCDs
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_placement_does_not_change_results(oracle, prec):
+    """ht_set_placement only reorders and places the work items: the outputs
+    with one stretch per XCD (and with 3 and 16 stretches) equal the unplaced
+    plan's bit for bit, for active sets that hit every tile size, a single
+    active particle (one long list split over many items) and all particles;
+    the oracle agrees."""
+    say(f"placement ({prec})")
+    n = 6000
+    x, v, m = W.plummer(n, 71)
+    z = np.zeros((n, 3))
+    ptr = B.HostTree(x, v, z, z, m, 1, 300, 0.5)
+    x, v, m = x[ptr.perm], v[ptr.perm], m[ptr.perm]
+    t0, a, j = W.random_block_state(n, 72, 0.125)
+    ctxs = []
+    for runs in (1, 0, 3, 16):
+        c = make_ctx(prec, n, 2 * n, n, 2 * ptr.n_entries, 1e-4)
+        c.set_placement(runs)
+        c.set_j_particles(t0, m, x, v, a, j)
+        c.set_nodes(0.0, ptr.node_m, ptr.node_x, ptr.node_v, ptr.node_a, ptr.node_j)
+        c.set_interaction_lists(ptr.group_first, ptr.list_off, ptr.entries)
+        c.predict(0.125)
+        ctxs.append(c)
+    runs_used, xcds = ctxs[1].placement()
+    say(f"  device XCDs {xcds}, runs in use {runs_used}")
+    assert runs_used == xcds >= 1 and ctxs[0].placement()[0] == 1 and ctxs[3].placement()[0] == 16
+    with pytest.raises(B.HTError):
+        ctxs[0].set_placement(17)
+    gf = ptr.group_first
+    r = (lambda u: u.astype(np.float32).astype(np.float64)) if prec == "mixed" else (lambda u: u)
+    xp, vp = oracle.predict(0.125, t0, x, v, r(a), r(j))
+    nxp, nvp = oracle.predict(0.125, 0.0, ptr.node_x, ptr.node_v, r(ptr.node_a), r(ptr.node_j))
+    XP, VP, MJ = np.vstack([xp, nxp]), np.vstack([vp, nvp]), r(np.concatenate([m, ptr.node_m]))
+    rng = np.random.default_rng(73)
+    counts = [1, 2, 3, 5, 9, 17, 33, 65, 129, 257]
+    sel = [np.sort(rng.choice(np.arange(gf[g], gf[g + 1]), min(gf[g + 1] - gf[g], counts[g % len(counts)]),
+                              replace=False)) for g in range(ptr.n_group)]
+    for ids in (np.concatenate(sel), np.array([4321]), np.arange(n), np.arange(0, n, 7)):
+        ids = ids.astype(np.int32)
+        got = [c.force(ids) for c in ctxs]
+        for g in got[1:]:
+            for p_, q_ in zip(got[0], g):
+                assert np.array_equal(p_, q_), (prec, ids.size)
+        want = oracle.force_list(ids, XP, VP, MJ, 1e-4, gf, ptr.list_off, ptr.entries)
+        assert_close(f"placement n_active={ids.size}", prec, got[1], want)
