@@ -125,7 +125,11 @@ struct Desc {
     const void* copy_rec;
     int64_t n_runs;
     int32_t copy_base;
-    int32_t pad;
+    // 1: eps2 > 0 and every list holds each particle of its group exactly once
+    // (direct sums: every particle once), so the pair loop sums the self pair
+    // too, which adds exactly zero to acc and jerk, and the items that carry
+    // kSelfTerm take its potential term -m_i / eps back (no per-pair test)
+    int32_t self_once;
 };
 
 // One unit of work: an i-tile of one group against a range of its list.
@@ -135,8 +139,11 @@ struct Item {
     int64_t out;        // -1: final results; otherwise partial slot of i-slot 0
     int32_t act_begin;  // active-array position of i-slot 0
     int16_t n_i;        // valid i-slots (1..T)
-    int16_t tile_log2;  // T = 1 << tile_log2
+    int16_t tile_log2;  // T = 1 << (tile_log2 & kTileMask); kSelfTerm: the item holding the start of its
+                        // tile's list range, which takes the self pair's potential back
 };
+constexpr int16_t kTileMask = 0xff;
+constexpr int16_t kSelfTerm = 0x100;
 
 // The partial sums of one split i-tile: nsplit blocks of n_i slots.
 struct RTile {
@@ -174,15 +181,15 @@ struct PrecMixed {
     static constexpr bool kMixed = true;
 };
 
-// One staged j of a round: predicted position and velocity, mass (as
-// stored: widened per pair, which keeps the mixed kernel within its 128
-// registers), combined index.  Records (not one array per field) so that a thread reads an entry
-// with a few 16-byte LDS loads at immediate offsets from one address.
+// One staged j of a round: predicted position and velocity, mass (widened
+// once at staging), combined index.  Records (not one array per field) so
+// that a thread reads an entry with a few 16-byte LDS loads at immediate
+// offsets from one address.
 template <class P>
 struct alignas(16) JRec {
     double x, y, z;
     typename P::Vel vx, vy, vz;
-    typename P::Stored m;
+    double m;
     int32_t idx;
 };
 static_assert(sizeof(JRec<PrecMixed>) == 64 && sizeof(JRec<PrecFp64>) == 64, "staged records are 64 bytes");
@@ -298,15 +305,18 @@ struct Acc64 {
     double v[kOut];
 };
 
+// SKIP: the self pair (J.idx == i) is masked out; otherwise it is summed
+// like any other pair (see Desc::self_once).
+template <bool SKIP>
 __device__ __forceinline__ void pair_fp64(double xi, double yi, double zi, double vxi, double vyi, double vzi,
                                           int i, const JRec<PrecFp64>& J, double eps2, Acc64& A) {
     const double dx = J.x - xi, dy = J.y - yi, dz = J.z - zi;
     const double wx = J.vx - vxi, wy = J.vy - vyi, wz = J.vz - vzi;
     const double s = dx * dx + dy * dy + dz * dz + eps2;
     double rinv = rsqrt(s);
-    rinv = (J.idx == i) ? 0.0 : rinv;
+    if constexpr (SKIP) rinv = (J.idx == i) ? 0.0 : rinv;
     const double rinv2 = rinv * rinv;
-    const double mr = static_cast<double>(J.m) * rinv;
+    const double mr = J.m * rinv;
     const double mr3 = mr * rinv2;
     const double alpha = 3.0 * (dx * wx + dy * wy + dz * wz) * rinv2;
     A.v[0] += mr3 * dx;
@@ -326,6 +336,7 @@ __device__ __forceinline__ void pair_fp64(double xi, double yi, double zi, doubl
 // few hundredths of their magnitudes; with s^-3/2 and the jerk terms in FP32
 // (a few ulp each) such particles missed the 1e-5 jerk target, so only the
 // seed is FP32.  FP64 FMAs issue at the non-packed FP32 rate on this chip.
+template <bool SKIP>
 __device__ __forceinline__ void pair_mixed(double xi, double yi, double zi, double vxi, double vyi, double vzi,
                                            int i, const JRec<PrecMixed>& J, double eps2, Acc64& A) {
     const double dx = J.x - xi, dy = J.y - yi, dz = J.z - zi;
@@ -333,9 +344,9 @@ __device__ __forceinline__ void pair_mixed(double xi, double yi, double zi, doub
     const double y0 = static_cast<double>(__builtin_amdgcn_rsqf(static_cast<float>(s)));
     const double e = fma(-(s * y0), y0, 1.0);
     double rinv = fma(0.5 * y0, e, y0);
-    rinv = (J.idx == i) ? 0.0 : rinv;
+    if constexpr (SKIP) rinv = (J.idx == i) ? 0.0 : rinv;
     const double rinv2 = rinv * rinv;
-    const double mr = static_cast<double>(J.m) * rinv;
+    const double mr = J.m * rinv;
     const double mr3 = mr * rinv2;
     const double wx = J.vx - vxi, wy = J.vy - vyi, wz = J.vz - vzi;
     const double alpha = 3.0 * fma(dz, wz, fma(dy, wy, dx * wx)) * rinv2;
@@ -348,11 +359,11 @@ __device__ __forceinline__ void pair_mixed(double xi, double yi, double zi, doub
     A.v[6] -= mr;
 }
 
-template <class P>
+template <class P, bool SKIP = true>
 __device__ __forceinline__ void pair(double xi, double yi, double zi, double vxi, double vyi, double vzi, int i,
                                      const JRec<P>& J, double eps2, Acc64& A) {
-    if constexpr (P::kMixed) pair_mixed(xi, yi, zi, vxi, vyi, vzi, i, J, eps2, A);
-    else pair_fp64(xi, yi, zi, vxi, vyi, vzi, i, J, eps2, A);
+    if constexpr (P::kMixed) pair_mixed<SKIP>(xi, yi, zi, vxi, vyi, vzi, i, J, eps2, A);
+    else pair_fp64<SKIP>(xi, yi, zi, vxi, vyi, vzi, i, J, eps2, A);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -400,7 +411,6 @@ __device__ __forceinline__ void run_item(const Desc& c, const Item& it, int64_t 
     typename P::Vel vxi, vyi, vzi;
     typename P::Stored mi;
     load_state<P, EAGER>(c, i, xi, yi, zi, vxi, vyi, vzi, mi);
-    (void)mi;
 
     Acc64 A;
 #pragma unroll
@@ -451,7 +461,7 @@ __device__ __forceinline__ void run_item(const Desc& c, const Item& it, int64_t 
                 typename P::Vel vxj, vyj, vzj;
                 typename P::Stored mj;
                 load_state<P, EAGER, RUNS>(c, j, xj, yj, zj, vxj, vyj, vzj, mj);
-                lds.j[e] = JRec<P>{xj, yj, zj, vxj, vyj, vzj, mj, j};
+                lds.j[e] = JRec<P>{xj, yj, zj, vxj, vyj, vzj, static_cast<double>(mj), j};
             }
         }
         if constexpr (!RUNS) {
@@ -459,12 +469,23 @@ __device__ __forceinline__ void run_item(const Desc& c, const Item& it, int64_t 
         }
         __syncthreads();
         const double eps2 = c.eps2;
-        if (cnt == R) {
+        if (c.self_once) {
+            if (cnt == R) {
 #pragma unroll 4
-            for (int u = 0; u < PER; ++u) pair<P>(xi, yi, zi, vxi, vyi, vzi, i, lds.j[stream + u * S], eps2, A);
-        } else {
+                for (int u = 0; u < PER; ++u)
+                    pair<P, false>(xi, yi, zi, vxi, vyi, vzi, i, lds.j[stream + u * S], eps2, A);
+            } else {
 #pragma unroll 1
-            for (int k = stream; k < cnt; k += S) pair<P>(xi, yi, zi, vxi, vyi, vzi, i, lds.j[k], eps2, A);
+                for (int k = stream; k < cnt; k += S) pair<P, false>(xi, yi, zi, vxi, vyi, vzi, i, lds.j[k], eps2, A);
+            }
+        } else {
+            if (cnt == R) {
+#pragma unroll 4
+                for (int u = 0; u < PER; ++u) pair<P>(xi, yi, zi, vxi, vyi, vzi, i, lds.j[stream + u * S], eps2, A);
+            } else {
+#pragma unroll 1
+                for (int k = stream; k < cnt; k += S) pair<P>(xi, yi, zi, vxi, vyi, vzi, i, lds.j[k], eps2, A);
+            }
         }
     }
 
@@ -510,6 +531,16 @@ __device__ __forceinline__ void run_item(const Desc& c, const Item& it, int64_t 
         }
     }
     if (stream == 0 && has_i) {
+        if (c.self_once && (it.tile_log2 & kSelfTerm)) {
+            // the self pair's potential term, as the pair loop summed it (same
+            // inputs, same operations; its acc and jerk terms are exact zeros)
+            Acc64 Z;
+#pragma unroll
+            for (int q = 0; q < kOut; ++q) Z.v[q] = 0.0;
+            pair<P, false>(xi, yi, zi, vxi, vyi, vzi, i,
+                           JRec<P>{xi, yi, zi, vxi, vyi, vzi, static_cast<double>(mi), i}, c.eps2, Z);
+            A.v[6] -= Z.v[6];
+        }
         if (it.out < 0) {
             write_out(c, it.act_begin + islot, A.v);
         } else {
@@ -569,7 +600,7 @@ __global__ __launch_bounds__(kWG, (WavesPerSimd<P, RUNS>::value)) void force_ker
         const int64_t k = g - tab[cl].first_item;
         const Item it = tab[cl].items[k];
         const int64_t r0 = RUNS ? c.item_runs[k] : 0;
-        switch (it.tile_log2) {
+        switch (it.tile_log2 & kTileMask) {
             case 8: run_item<P, EAGER, DIRECT, RUNS, 256>(c, it, r0, lds, rl); break;
             case 7: run_item<P, EAGER, DIRECT, RUNS, 128>(c, it, r0, lds, rl); break;
             case 6: run_item<P, EAGER, DIRECT, RUNS, 64>(c, it, r0, lds, rl); break;
@@ -1398,14 +1429,15 @@ __device__ __forceinline__ void plan_body(const PlanArgs& A) {
         if (q < ntile) {
             const int16_t ni = static_cast<int16_t>(T.ni), tl = static_cast<int16_t>(T.tl);
             if (ns == 1) {
-                A.items[io + ei] = Item{T.jb, T.je, -1, T.tb, ni, tl};
+                A.items[io + ei] = Item{T.jb, T.je, -1, T.tb, ni, static_cast<int16_t>(tl | kSelfTerm)};
                 for (int32_t u = 0; u < T.ni; ++u) A.qmap[T.tb + u] = -1;
             } else {
                 for (int32_t u = 0; u < T.ni; ++u) A.qmap[T.tb + u] = static_cast<int32_t>(ro + er);
                 const int64_t pb = po + ep;
                 int64_t s = 0;
                 for (int64_t b = T.jb; b < T.je; b += per, ++s)
-                    A.items[io + ei + s] = Item{b, b + per < T.je ? b + per : T.je, pb + s * T.ni, T.tb, ni, tl};
+                    A.items[io + ei + s] = Item{b, b + per < T.je ? b + per : T.je, pb + s * T.ni, T.tb, ni,
+                                                static_cast<int16_t>(s == 0 ? tl | kSelfTerm : tl)};
                 A.rtiles[ro + er] = RTile{pb, T.tb, T.ni, static_cast<int32_t>(nsu), 0};
             }
         }
@@ -1751,6 +1783,10 @@ struct ht_ctx {
     hipGraph_t loop_graph = nullptr;      // kLoopGraphSteps device-loop steps, captured once
     hipGraphExec_t loop_exec = nullptr;
     double loop_tuning[2] = {-1.0, -1.0}; // the tuning the graph's planner launches carry
+    int32_t loop_self_once = -1;          // and the descriptor's self_once
+    // every list holds each particle of its group exactly once (checked when
+    // host lists are set; true for the device builder's lists by construction)
+    bool self_once_lists = false;
     DevOut* h_dout = nullptr;
     int32_t* h_active = nullptr;
     double dev_t_next = 0.0;
@@ -1785,6 +1821,7 @@ struct ht_ctx {
         d.partial = dev<double>(L.off_partial);
         d.t = t_pred;
         d.eps2 = cfg.eps2;
+        d.self_once = self_once_lists && cfg.eps2 > 0.0 ? 1 : 0;
         if (list_form == HT_LISTS_RUNS) {
             d.run_start = d_run_start;
             d.run_pos = d_run_pos;
@@ -1955,14 +1992,16 @@ int plan(ht_ctx* c, int32_t n_active, const int32_t* ids, bool direct, bool plac
             int64_t ns = attempt > 60 ? 1 : static_cast<int64_t>(std::ceil(t.cost / quantum));
             ns = std::max<int64_t>(1, std::min<int64_t>(ns, rounds));
             if (ns == 1) {
-                items.push_back(Item{t.jb, t.je, -1, t.tb, static_cast<int16_t>(t.ni), static_cast<int16_t>(t.tl)});
+                items.push_back(Item{t.jb, t.je, -1, t.tb, static_cast<int16_t>(t.ni),
+                                     static_cast<int16_t>(t.tl | kSelfTerm)});
                 continue;
             }
             const int64_t per = (rounds + ns - 1) / ns * rsz;   // entries per split, whole rounds
             int32_t nsu = 0;
             for (int64_t b = t.jb; b < t.je; b += per, ++nsu)
                 items.push_back(Item{b, std::min(t.je, b + per), pslots + static_cast<int64_t>(nsu) * t.ni, t.tb,
-                                     static_cast<int16_t>(t.ni), static_cast<int16_t>(t.tl)});
+                                     static_cast<int16_t>(t.ni),
+                                     static_cast<int16_t>(nsu == 0 ? t.tl | kSelfTerm : t.tl)});
             rtiles.push_back(RTile{pslots, t.tb, t.ni, nsu, 0});
             pslots += static_cast<int64_t>(nsu) * t.ni;
         }
@@ -1980,7 +2019,7 @@ int plan(ht_ctx* c, int32_t n_active, const int32_t* ids, bool direct, bool plac
     const double gc = c->gather_cost;
     auto item_cost = [gc](const Item& it) {
         return static_cast<double>((it.j_end - it.j_begin + kRound - 1) / kRound) *
-               (gc + static_cast<double>(1 << it.tile_log2));
+               (gc + static_cast<double>(1 << (it.tile_log2 & kTileMask)));
     };
     const int nb = (place && c->placement > 1 && !direct && items.size() > 1) ? c->placement : 1;
     auto& ib = c->item_bin;
@@ -2242,6 +2281,7 @@ int enqueue_step(ht_ctx* c, const DevRows& u, bool predict_eager, int32_t n_acti
         if (rc) return rc;
         Entry e{};
         end = pack_plan(c, sizeof(Entry), n_active, ids, d_acc, d_jerk, d_pot, e);
+        if (direct) e.d.self_once = c->cfg.eps2 > 0.0 ? 1 : 0;   // every particle once
         if (c->n_bins > 1) {   // the placed plan's run offsets
             const size_t o_bins = align_up(end);
             std::memcpy(c->plan_host() + o_bins, c->bin_off, static_cast<size_t>(c->n_bins + 1) * 8);
@@ -2640,6 +2680,20 @@ int ht_set_interaction_lists(ht_ctx* c, int32_t n_groups, const int64_t* group_f
     c->list_off.assign(list_off, list_off + n_groups + 1);
     c->n_groups = n_groups;
     c->n_entries = L;
+    {   // does every list hold each particle of its group exactly once?
+        std::vector<uint8_t> seen(static_cast<size_t>(c->n), 0);
+        bool once = true;
+        for (int32_t g = 0; g < n_groups && once; ++g)
+            for (int64_t e = list_off[g]; e < list_off[g + 1]; ++e) {
+                const int32_t j = entries[e];
+                if (j >= group_first[g] && j < group_first[g + 1] && seen[j]++) {
+                    once = false;
+                    break;
+                }
+            }
+        for (int32_t k = 0; k < c->n && once; ++k) once = seen[k] == 1;
+        c->self_once_lists = once;
+    }
     if (c->list_form == HT_LISTS_RUNS) {
         int rc = build_runs(c, entries);
         if (rc) return rc;
@@ -3104,6 +3158,7 @@ int ht_state_rebuild(ht_ctx* c, htd_tree* t, int32_t n_leaf, int32_t n_crit, dou
     c->n_entries = L;
     c->have_nodes = true;
     c->have_lists = true;
+    c->self_once_lists = true;   // the builder lists every particle of a group in its list once
     c->predicted = false;
     c->dev_n_active = -1;
     return HT_OK;
@@ -3260,6 +3315,7 @@ int build_loop_graph(ht_ctx* c) {
     HT_HIP(hipGraphInstantiate(&c->loop_exec, g, nullptr, nullptr, 0));
     c->loop_tuning[0] = c->gather_cost;
     c->loop_tuning[1] = c->target_items;
+    c->loop_self_once = c->desc().self_once;
     return HT_OK;
 }
 }  // namespace
@@ -3280,7 +3336,8 @@ int ht_dev_run(ht_ctx* c, double eta, double dt_tree, double t_stop, int32_t max
     *t_last = c->dev_t_next;
     *particle_steps = 0;
     c->dev_n_active = -1;
-    if (!c->loop_exec || c->loop_tuning[0] != c->gather_cost || c->loop_tuning[1] != c->target_items) {
+    if (!c->loop_exec || c->loop_tuning[0] != c->gather_cost || c->loop_tuning[1] != c->target_items ||
+        c->loop_self_once != c->desc().self_once) {
         int rc = build_loop_graph(c);
         if (rc) return rc;
     }
@@ -3926,6 +3983,7 @@ int prepare_batch_loop(ht_batch* b, int32_t n_ctx, ht_ctx* const* ctxs) {
         key.push_back(static_cast<double>(ctxs[k]->n));
         key.push_back(ctxs[k]->gather_cost);
         key.push_back(ctxs[k]->target_items);
+        key.push_back(static_cast<double>(ctxs[k]->desc().self_once));
     }
     if (b->loop_exec && b->loop_ctxs.size() == static_cast<size_t>(n_ctx) &&
         std::equal(b->loop_ctxs.begin(), b->loop_ctxs.end(), ctxs) && b->loop_key == key)
