@@ -837,7 +837,7 @@ def main():
     # the batched ensemble and the served stream, short forms (their own --workload runs are the long ones)
     if not args.no_engine_records:
         sub = argparse.Namespace(**vars(args))
-        sub.steps, sub.warmup, sub.tuning, sub.device_loop = 32, 8, "12,1024", True
+        sub.steps, sub.warmup, sub.tuning, sub.device_loop = 32, 8, "12,512", True
         ens = bench_ensemble(sub, torch)
         result["ensemble64"] = {k: ens[k] for k in ("metric", "value", "unit", "ms_per_step", "p50_step_ms",
                                                     "p99_step_ms", "equivalent_interactions_per_s", "steps",

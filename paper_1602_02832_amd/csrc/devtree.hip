@@ -22,6 +22,7 @@
 //      by its decision (the node, its particles, or its children), in place
 //      and in order, so the final array is the pre-order list.
 #include "htree_tree.h"
+#include "wave_ops.h"
 
 #include <hip/hip_runtime.h>
 
@@ -475,11 +476,7 @@ enum : int32_t { kKeep = 0, kParticle = 1, kNode = 2, kParticles = 3, kChildren 
 // Exclusive prefix sum over the work-group; returns the total.
 __device__ inline int32_t wg_scan(int32_t v, int32_t* excl, int32_t* s_wave) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int32_t x = v;
-    for (int o = 1; o < 64; o <<= 1) {
-        const int32_t y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
+    const int32_t x = wave_ops::scan_inclusive(v);
     if (lane == 63) s_wave[wave] = x;
     __syncthreads();
     int32_t before = 0, total = 0;

@@ -38,6 +38,7 @@
 
 #include "htree.h"
 #include "htree_tree.h"
+#include "wave_ops.h"
 
 namespace {
 
@@ -257,48 +258,6 @@ __device__ __forceinline__ void load_state(const Desc& c, int j, double& x, doub
 }
 
 // ------------------------------------------------------------------------------------------------
-// Lane exchange for pairwise trees within a wave, on the vector ALU: the
-// value of the lane OFF places above (OFF = 1, 2, ..., 32), for the lanes
-// 0..OFF-1 of the wave; other lanes get unspecified values.  OFF < 16 is a
-// DPP row shift (lanes 0..OFF-1 and their partners share a 16-lane row); 16
-// and 32 are the gfx950 swaps of 16-lane rows and 32-lane halves, whose
-// second result holds the upper row (half) in the lower one.  64-bit values
-// move as two 32-bit halves.  All lanes of the wave must be active.
-template <int OFF>
-__device__ __forceinline__ uint32_t lane_above_u32(uint32_t v) {
-    static_assert(OFF >= 1 && OFF <= 32 && (OFF & (OFF - 1)) == 0, "power-of-two lane offset");
-    if constexpr (OFF == 32) return __builtin_amdgcn_permlane32_swap(v, v, false, false)[1];
-    else if constexpr (OFF == 16) return __builtin_amdgcn_permlane16_swap(v, v, false, false)[1];
-    else return __builtin_amdgcn_update_dpp(0u, v, 0x100 + OFF, 0xf, 0xf, true);   // row_shl:OFF
-}
-
-template <int OFF, class V>
-__device__ __forceinline__ V lane_above(V v) {
-    static_assert(sizeof(V) == 4 || sizeof(V) == 8, "32- or 64-bit values");
-    if constexpr (sizeof(V) == 4) {
-        return __builtin_bit_cast(V, lane_above_u32<OFF>(__builtin_bit_cast(uint32_t, v)));
-    } else {
-        const uint64_t b = __builtin_bit_cast(uint64_t, v);
-        const uint32_t lo = lane_above_u32<OFF>(static_cast<uint32_t>(b));
-        const uint32_t hi = lane_above_u32<OFF>(static_cast<uint32_t>(b >> 32));
-        return __builtin_bit_cast(V, (static_cast<uint64_t>(hi) << 32) | lo);
-    }
-}
-
-// Pairwise tree over a wave, lane k combining with lane k + OFF for OFF =
-// FIRST, FIRST / 2, ..., LAST: with FIRST = 32 and LAST = 1 lane 0 ends with
-// the whole wave's reduction.
-template <int FIRST, int LAST, class V, class Op>
-__device__ __forceinline__ V wave_tree(V v, Op op) {
-    if constexpr (FIRST >= LAST) {
-        v = op(v, lane_above<FIRST>(v));
-        return wave_tree<FIRST / 2, LAST>(v, op);
-    } else {
-        return v;
-    }
-}
-
-// ------------------------------------------------------------------------------------------------
 // pair interaction: r = x_j - x_i, w = v_j - v_i, s = r.r + eps^2
 //   a += m r s^-3/2,  jerk += m s^-3/2 (w - 3 (r.w)/s r),  pot -= m s^-1/2
 struct Acc64 {
@@ -498,7 +457,7 @@ __device__ __forceinline__ void run_item(const Desc& c, const Item& it, int64_t 
     if constexpr (T < 64) {
         auto add = [](double p, double q) { return p + q; };
 #pragma unroll
-        for (int q = 0; q < kOut; ++q) A.v[q] = wave_tree<32, T>(A.v[q], add);
+        for (int q = 0; q < kOut; ++q) A.v[q] = wave_ops::tree<32, T>(A.v[q], add);
         const int lane = tid & 63, wave = tid >> 6;
         __syncthreads();
         if (lane < T) {
@@ -885,7 +844,7 @@ struct DevOut {
 constexpr int kSchedBlocks = 1024;   // most scheduler blocks (contiguous particle ranges)
 
 __device__ __forceinline__ double block_min(double v, double* red) {
-    v = wave_tree<32, 1>(v, [](double p, double q) { return fmin(p, q); });
+    v = wave_ops::tree<32, 1>(v, [](double p, double q) { return fmin(p, q); });
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     __syncthreads();
     if (lane == 0) red[wave] = v;
@@ -950,7 +909,7 @@ __global__ __launch_bounds__(kWG) void sched_count_kernel(SchedEntry e0, const S
     const int64_t lo = b * e.chunk, hi = lo + e.chunk < e.n ? lo + e.chunk : e.n;
     int c = 0;
     for (int64_t i = lo + threadIdx.x; i < hi; i += kWG) c += e.t0[i] + e.dt[i] == t_next;
-    c = wave_tree<32, 1>(c, [](int p, int q) { return p + q; });
+    c = wave_ops::tree<32, 1>(c, [](int p, int q) { return p + q; });
     if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = c;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -974,7 +933,7 @@ __global__ __launch_bounds__(kWG) void sched_write_kernel(SchedEntry e0, const S
     const double t_next = block_min(v, red);
     int64_t before = 0;
     for (int k = threadIdx.x; k < b; k += kWG) before += e.bcount[k];
-    before = wave_tree<32, 1>(before, [](int64_t p, int64_t q) { return p + q; });
+    before = wave_ops::tree<32, 1>(before, [](int64_t p, int64_t q) { return p + q; });
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) part[wave] = before;
     __syncthreads();
@@ -1246,11 +1205,7 @@ constexpr int kPlanWG = 512;
 template <class V>
 __device__ inline V plan_scan(V v, V* excl, V* s_wave) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    V x = v;
-    for (int o = 1; o < 64; o <<= 1) {
-        const V y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
+    const V x = wave_ops::scan_inclusive(v);
     if (lane == 63) s_wave[wave] = x;
     __syncthreads();
     V before = 0, total = 0;
@@ -1525,11 +1480,7 @@ __global__ __launch_bounds__(kWG) void batch_loop_init_kernel(const LoopCtx* __r
 // Exclusive prefix sum over the kLoopTabWG threads of the work-group.
 __device__ inline int64_t tab_scan(int64_t v, int64_t* s_wave, int64_t* total) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int64_t x = v;
-    for (int o = 1; o < 64; o <<= 1) {
-        const int64_t y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
+    const int64_t x = wave_ops::scan_inclusive(v);
     __syncthreads();
     if (lane == 63) s_wave[wave] = x;
     __syncthreads();
