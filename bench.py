@@ -54,12 +54,12 @@ METRIC_ENSEMBLE = "batched ensemble (64 Plummer clusters, N 4096-65536): Hermite
 # only for the kernel source and the window (steps, warmup) it was taken on:
 # anything else makes the figure null until the counters are taken again.
 TRAFFIC = {
-    "kernel_source_sha256": "d05622ed237002b6ab9170233ffafc50d63804ad1cd6a6c78b72fd064732fe00",
-    "steps": 64,
-    "warmup": 8,
-    "fetch_bytes_per_launch": 1.448e8,     # FETCH_SIZE 70685.2 KiB x 2.000
-    "write_bytes_per_launch": 5.466e5,     # WRITE_SIZE 533.8 KiB x 1.000
-    "fetch_scale": 2.000,                  # 1 GiB read by a plain copy reads 524300 KiB
+    "kernel_source_sha256": "5944367b12c66c2ed9da6a3310ec3f346b8dccab4087f1f779558d1d5608d30e",
+    "steps": 20,
+    "warmup": 5,
+    "fetch_bytes_per_launch": 1.16046e8,   # FETCH_SIZE 56663.2 KiB x 2.000
+    "write_bytes_per_launch": 2.5292e5,    # WRITE_SIZE 247.0 KiB x 1.000
+    "fetch_scale": 2.000,                  # 1 GiB read by a plain copy reads 524294.5 KiB
     "write_scale": 1.000,                  # 1 GiB written reads 1048576 KiB
     "profile": "profiles/force_kernel_mixed_plummer1m_traffic.md",
 }
