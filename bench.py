@@ -45,6 +45,7 @@ PEAK_FP32_TFLOPS = 157.3
 # 256 CU x 64 FMA lanes x 2 flop x 2.4 GHz: the non-packed FP32 (and FP64) issue
 # rate, which bounds this build (packed FP32 is not generated), reported beside it
 PEAK_NONPACKED_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, published
 METRIC = "Hermite acc+jerk interactions/s at N=2^20 vs direct; p99 block-step latency"
 METRIC_ENSEMBLE = "batched ensemble (64 Plummer clusters, N 4096-65536): Hermite acc+jerk interactions/s; p99 engine-step latency"
 # HBM traffic of the timed force kernel, from two rocprofv3 --pmc passes over
@@ -430,7 +431,7 @@ def bench_ensemble(args, torch):
             "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS, "peak_nonpacked": PEAK_NONPACKED_TFLOPS,
             "frac_nonpacked": achieved / PEAK_NONPACKED_TFLOPS, "traffic": None,
-            "kernel": "force_kernel<PrecMixed,false,false>", "avg_launch_ms": kms / max(nl, 1)},
+            "kernel": "force_kernel<PrecMixed,false,false,false>", "avg_launch_ms": kms / max(nl, 1)},
     }
     eng.close()
     return res
@@ -814,8 +815,15 @@ def main():
                      "frac_nonpacked": achieved / PEAK_NONPACKED_TFLOPS,
                      "traffic": measured_traffic(K, args.warmup),
                      "traffic_unit": "bytes/launch", "algorithmic_bytes": alg_bytes,
-                     "kernel": "force_kernel<PrecMixed,false,false>", "avg_launch_ms": kernel_avg_ms,
+                     "kernel": "force_kernel<PrecMixed,false,false,false>", "avg_launch_ms": kernel_avg_ms,
                      "pairs_per_launch": mixed["kernel_pairs"] / max(mixed["launches"], 1)},
+        # the same launches against HBM: the sparse steps that dominate the window are bound by the
+        # bytes their gathers fetch (algorithmic bytes per launch, and the measured traffic's rate)
+        "roofline_gather": {"bound": "hbm", "achieved": alg_bytes / (kernel_avg_ms * 1e-3) / 1e9,
+                            "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                            "frac": alg_bytes / (kernel_avg_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                            "traffic_rate": (None if measured_traffic(K, args.warmup) is None else
+                                             measured_traffic(K, args.warmup) / (kernel_avg_ms * 1e-3) / 1e9)},
     }
     if direct is not None:
         result["direct_interactions_per_s"] = direct["pairs"] / direct["wall_s"]
