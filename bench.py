@@ -128,12 +128,17 @@ class Recorded:
         self.steps.append((t, act.astype(np.int32), upd))
 
 
-def make_ctx(B, snap, n, precision, eps2, stream, predict_mode="fused", lists="csr", placement=None):
+def make_ctx(B, snap, n, precision, eps2, stream, predict_mode="fused", lists="csr", placement=None,
+             union_width=None, tuning=None):
     ctx = B.Context(n_max=n, node_max=snap["n_node"] + 64, group_max=snap["n_group"] + 16,
                     list_max=snap["n_entries"] + 1024, active_max=n, eps2=eps2, precision=precision,
                     predict_mode=predict_mode, stream=stream)
     if lists != "csr":
         ctx.set_list_form(lists)
+    if union_width is not None:
+        ctx.set_union_width(union_width)
+    if tuning is not None:
+        ctx.set_tuning(*tuning)
     if placement is not None:
         ctx.set_placement(placement)
     load_snapshot(ctx, snap)
@@ -525,8 +530,9 @@ def main():
     ap.add_argument("--requests", type=int, default=200, help="served workload: number of cluster runs")
     ap.add_argument("--max-resident", type=int, default=32, help="served workload: batch slots")
     ap.add_argument("--tuning", default="",
-                    help="engine workloads: plan tuning 'gather_cost,target_items' for every cluster "
-                         "(ensemble: instead of the autotune; default for served: the library's)")
+                    help="plan tuning 'gather_cost,target_items': every cluster of the engine workloads "
+                         "(ensemble: instead of the autotune; default for served: the library's), and the tree "
+                         "legs of the default workload")
     ap.add_argument("--lanes", type=int, default=0,
                     help="resident engine workloads: cluster lanes stepped out of phase (0: the engine's "
                          "default, one)")
@@ -540,7 +546,10 @@ def main():
     ap.add_argument("--placement", type=int, default=None,
                     help="default workload: work-item stretches over the XCDs (0: one per XCD, 1: off; "
                          "default: the library's)")
-    ap.add_argument("--lists", choices=("csr", "runs"), default="csr",
+    ap.add_argument("--predict", choices=("fused", "eager"), default="fused",
+                    help="default workload: prediction mode of the tree legs (eager: one pass per step, then the gather)")
+    ap.add_argument("--union-width", type=int, default=None, help="default workload: groups per union run (--lists union)")
+    ap.add_argument("--lists", choices=("csr", "runs", "union"), default="csr",
                     help="default workload: interaction-list form of the tree legs (the graph leg takes CSR)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (scale for the byte counters)")
@@ -680,21 +689,28 @@ def main():
 
     stream = torch.cuda.Stream()
     sh = stream.cuda_stream
+    # --tuning applies to the tree legs' contexts too (gather cost, target items)
+    ctx_tuning = parse_tuning(args.tuning) if args.tuning else None
+
     def leg(precision, direct=False):
         """The recorded steps three times, each from a fresh copy of the
         snapshot: with kernel timing (kernel time, pairs, items), with one
         event per step (step latency), and clean (throughput)."""
         lists = "csr" if direct else args.lists
-        ctx = make_ctx(B, rec.snap, rec.n, precision, cfg.eps2, sh, lists=lists, placement=args.placement)
+        pm = "fused" if direct else args.predict
+        ctx = make_ctx(B, rec.snap, rec.n, precision, cfg.eps2, sh, pm, lists=lists, placement=args.placement,
+                       union_width=args.union_width, tuning=ctx_tuning)
         r = replay(torch, B, rec, ctx, stream, args.warmup, args.steps, direct=direct, mode="kernel")
         r["placement"] = ctx.placement()
         r["kernel_wall_s"] = r.pop("wall_s")
         ctx.close()
-        ctx = make_ctx(B, rec.snap, rec.n, precision, cfg.eps2, sh, lists=lists, placement=args.placement)
+        ctx = make_ctx(B, rec.snap, rec.n, precision, cfg.eps2, sh, pm, lists=lists, placement=args.placement,
+                       union_width=args.union_width, tuning=ctx_tuning)
         lt = replay(torch, B, rec, ctx, stream, args.warmup, args.steps, direct=direct, mode="latency")
         r["lat_ms"], r["latency_wall_s"] = lt["lat_ms"], lt["wall_s"]
         ctx.close()
-        ctx = make_ctx(B, rec.snap, rec.n, precision, cfg.eps2, sh, lists=lists, placement=args.placement)
+        ctx = make_ctx(B, rec.snap, rec.n, precision, cfg.eps2, sh, pm, lists=lists, placement=args.placement,
+                       union_width=args.union_width, tuning=ctx_tuning)
         r["wall_s"] = replay(torch, B, rec, ctx, stream, args.warmup, args.steps, direct=direct)["wall_s"]
         ctx.close()
         return r
@@ -726,7 +742,8 @@ def main():
     # ---- the all-particle step at t = dt_tree
     all_active = None
     if not args.no_all_active:
-        ctx = make_ctx(B, rec_all.snap, rec_all.n, "mixed", cfg.eps2, sh, lists=args.lists, placement=args.placement)
+        ctx = make_ctx(B, rec_all.snap, rec_all.n, "mixed", cfg.eps2, sh, lists=args.lists, placement=args.placement,
+                       union_width=args.union_width)
         ids = np.arange(rec_all.n, dtype=np.int32)
         acc = torch.empty((rec_all.n, 3), dtype=torch.float64, device="cuda")
         jrk = torch.empty_like(acc)
@@ -800,7 +817,8 @@ def main():
                    "eta": cfg.eta, "n_crit": cfg.n_crit, "n_leaf": cfg.n_leaf,
                    "masses": f"salpeter 1:{cfg.mass_ratio:g}" if cfg.mass_seed is not None else "equal",
                    "window": f"{K} block steps after the rebuild at t={cfg.dt_tree}", "precision": "mixed",
-                   "predict": "fused", "lists": args.lists,
+                   "predict": args.predict, "lists": args.lists,
+                   "union_width": (args.union_width or 4) if args.lists == "union" else None,
                    "placement": {"runs": mixed["placement"][0], "xcds": mixed["placement"][1]}},
         "p50_step_ms": float(np.percentile(lat, 50)),
         "p99_step_ms": float(np.percentile(lat, 99)),

@@ -140,8 +140,28 @@ int ht_set_interaction_lists(ht_ctx *ctx, int32_t n_groups, const int64_t *group
  * ht_force_async, ht_step_async, ht_dev_step); batched calls, graph steps,
  * the device loops and device rebuilds take CSR only (HT_EINVAL).  Changing
  * the form drops the lists: set them again. */
-typedef enum { HT_LISTS_CSR = 0, HT_LISTS_RUNS = 1 } ht_list_form;
+typedef enum { HT_LISTS_CSR = 0, HT_LISTS_RUNS = 1, HT_LISTS_UNION = 2 } ht_list_form;
 int ht_set_list_form(ht_ctx *ctx, int32_t form);
+
+/* Union tiles (HT_LISTS_UNION).  Section 3, eq. (3): the force pipelines
+ * lose efficiency when a group has few active particles; here a gathered
+ * entry is shared among the active particles of several groups.  The lists
+ * are kept as CSR;
+ * at ht_set_interaction_lists the groups are also taken in runs of `width`
+ * consecutive groups (consecutive in the space-filling order, so their lists
+ * overlap), and each run gets the union of its members' lists (each entry
+ * once, in order of first appearance over the members in group order) with
+ * one bit per member whose own list holds the entry (library-owned device
+ * memory, 5 bytes per union entry).  Per call the planner covers a run's
+ * active particles either by the usual tiles of each group or by tiles over
+ * the run's union list, whichever its cost model finds cheaper; in a union
+ * tile a pair counts only where the entry's bit for the i-particle's group is
+ * set, so every particle sums exactly its own list, in another order (results
+ * agree with the CSR form to rounding, not bit for bit).  width: 2..8
+ * (HT_EINVAL otherwise), default 4; changing it drops the lists.  Pairs
+ * reported by ht_last_stats stay the list interactions.  Served calls as for
+ * RUNS. */
+int ht_set_union_width(ht_ctx *ctx, int32_t width);
 
 /* Step 5 (predictor): predict particles and nodes to block time t. */
 int ht_predict(ht_ctx *ctx, double t);

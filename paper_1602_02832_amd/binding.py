@@ -153,6 +153,7 @@ def device_lib():
                                  ctypes.POINTER(ctypes.c_int32)],
             "ht_state_bytes": [ctypes.POINTER(HtConfig), ctypes.POINTER(ctypes.c_size_t)],
             "ht_set_list_form": [_vp, i],
+            "ht_set_union_width": [_vp, i],
             "ht_set_placement": [_vp, i],
             "ht_get_placement": [_vp, _c_i32p, _c_i32p],
             "ht_state_enable_ws": [_vp, _vp, ctypes.c_size_t],
@@ -350,9 +351,14 @@ class Context:
         return r.value, x.value
 
     def set_list_form(self, form):
-        """ht_set_list_form: "csr" (default) or "runs" (run-length lists with the
-        groups' node copies); the lists must be set again afterwards."""
-        _check(device_lib().ht_set_list_form(self._h, {"csr": 0, "runs": 1}[form]))
+        """ht_set_list_form: "csr" (default), "runs" (run-length lists with the
+        groups' node copies) or "union" (union tiles over runs of groups); the
+        lists must be set again afterwards."""
+        _check(device_lib().ht_set_list_form(self._h, {"csr": 0, "runs": 1, "union": 2}[form]))
+
+    def set_union_width(self, width):
+        """ht_set_union_width: groups per run of the union tiles (2..8)."""
+        _check(device_lib().ht_set_union_width(self._h, int(width)))
 
     def predict(self, t):
         _check(device_lib().ht_predict(self._h, float(t)))

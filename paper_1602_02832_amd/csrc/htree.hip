@@ -131,6 +131,12 @@ struct Desc {
     // too, which adds exactly zero to acc and jerk, and the items that carry
     // kSelfTerm take its potential term -m_i / eps back (no per-pair test)
     int32_t self_once;
+    // union tiles (HT_LISTS_UNION): the union lists of runs of consecutive
+    // groups (entries) with a bit per member group whose own list holds the
+    // entry (mask); the member index of each active position (act_member)
+    const int32_t* u_entries;
+    const uint8_t* u_mask;
+    const uint8_t* act_member;
 };
 
 // One unit of work: an i-tile of one group against a range of its list.
@@ -141,10 +147,13 @@ struct Item {
     int32_t act_begin;  // active-array position of i-slot 0
     int16_t n_i;        // valid i-slots (1..T)
     int16_t tile_log2;  // T = 1 << (tile_log2 & kTileMask); kSelfTerm: the item holding the start of its
-                        // tile's list range, which takes the self pair's potential back
+                        // tile's list range, which takes the self pair's potential back; kUnion: the
+                        // range is in the union lists, and a pair counts only where the entry's mask
+                        // holds the i-slot's member bit
 };
 constexpr int16_t kTileMask = 0xff;
 constexpr int16_t kSelfTerm = 0x100;
+constexpr int16_t kUnion = 0x200;
 
 // The partial sums of one split i-tile: nsplit blocks of n_i slots.
 struct RTile {
@@ -192,6 +201,7 @@ struct alignas(16) JRec {
     typename P::Vel vx, vy, vz;
     double m;
     int32_t idx;
+    int32_t mask;   // union tiles: the member groups whose lists hold the entry
 };
 static_assert(sizeof(JRec<PrecMixed>) == 64 && sizeof(JRec<PrecFp64>) == 64, "staged records are 64 bytes");
 
@@ -266,14 +276,17 @@ struct Acc64 {
 
 // SKIP: the self pair (J.idx == i) is masked out; otherwise it is summed
 // like any other pair (see Desc::self_once).
-template <bool SKIP>
+// MASK (union tiles): the pair counts only where the entry's member mask
+// holds bit mb, the i-particle's group within the run.
+template <bool SKIP, bool MASK>
 __device__ __forceinline__ void pair_fp64(double xi, double yi, double zi, double vxi, double vyi, double vzi,
-                                          int i, const JRec<PrecFp64>& J, double eps2, Acc64& A) {
+                                          int i, const JRec<PrecFp64>& J, double eps2, Acc64& A, int mb) {
     const double dx = J.x - xi, dy = J.y - yi, dz = J.z - zi;
     const double wx = J.vx - vxi, wy = J.vy - vyi, wz = J.vz - vzi;
     const double s = dx * dx + dy * dy + dz * dz + eps2;
     double rinv = rsqrt(s);
     if constexpr (SKIP) rinv = (J.idx == i) ? 0.0 : rinv;
+    if constexpr (MASK) rinv = ((J.mask >> mb) & 1) ? rinv : 0.0;
     const double rinv2 = rinv * rinv;
     const double mr = J.m * rinv;
     const double mr3 = mr * rinv2;
@@ -295,15 +308,16 @@ __device__ __forceinline__ void pair_fp64(double xi, double yi, double zi, doubl
 // few hundredths of their magnitudes; with s^-3/2 and the jerk terms in FP32
 // (a few ulp each) such particles missed the 1e-5 jerk target, so only the
 // seed is FP32.  FP64 FMAs issue at the non-packed FP32 rate on this chip.
-template <bool SKIP>
+template <bool SKIP, bool MASK>
 __device__ __forceinline__ void pair_mixed(double xi, double yi, double zi, double vxi, double vyi, double vzi,
-                                           int i, const JRec<PrecMixed>& J, double eps2, Acc64& A) {
+                                           int i, const JRec<PrecMixed>& J, double eps2, Acc64& A, int mb) {
     const double dx = J.x - xi, dy = J.y - yi, dz = J.z - zi;
     const double s = fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2)));
     const double y0 = static_cast<double>(__builtin_amdgcn_rsqf(static_cast<float>(s)));
     const double e = fma(-(s * y0), y0, 1.0);
     double rinv = fma(0.5 * y0, e, y0);
     if constexpr (SKIP) rinv = (J.idx == i) ? 0.0 : rinv;
+    if constexpr (MASK) rinv = ((J.mask >> mb) & 1) ? rinv : 0.0;
     const double rinv2 = rinv * rinv;
     const double mr = J.m * rinv;
     const double mr3 = mr * rinv2;
@@ -318,11 +332,11 @@ __device__ __forceinline__ void pair_mixed(double xi, double yi, double zi, doub
     A.v[6] -= mr;
 }
 
-template <class P, bool SKIP = true>
+template <class P, bool SKIP = true, bool MASK = false>
 __device__ __forceinline__ void pair(double xi, double yi, double zi, double vxi, double vyi, double vzi, int i,
-                                     const JRec<P>& J, double eps2, Acc64& A) {
-    if constexpr (P::kMixed) pair_mixed<SKIP>(xi, yi, zi, vxi, vyi, vzi, i, J, eps2, A);
-    else pair_fp64<SKIP>(xi, yi, zi, vxi, vyi, vzi, i, J, eps2, A);
+                                     const JRec<P>& J, double eps2, Acc64& A, int mb = 0) {
+    if constexpr (P::kMixed) pair_mixed<SKIP, MASK>(xi, yi, zi, vxi, vyi, vzi, i, J, eps2, A, mb);
+    else pair_fp64<SKIP, MASK>(xi, yi, zi, vxi, vyi, vzi, i, J, eps2, A, mb);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -338,7 +352,7 @@ __device__ __forceinline__ void write_out(const Desc& c, int64_t o, const double
 
 // ------------------------------------------------------------------------------------------------
 // one work item with tile size T
-template <class P, bool EAGER, bool DIRECT, bool RUNS, int T, class RL>
+template <class P, bool EAGER, bool DIRECT, bool RUNS, int T, class RL, bool UNI = false>
 __device__ __forceinline__ void run_item(const Desc& c, const Item& it, int64_t run0, LdsAll<P>& lds, RL& rl) {
     constexpr int G = round_mult(T);    // entries gathered per thread and round
     constexpr int R = kRound * G;       // entries per round
@@ -352,12 +366,15 @@ __device__ __forceinline__ void run_item(const Desc& c, const Item& it, int64_t 
     // that a round's gather waits on one memory access (the record) instead of
     // two in a row (index, then record); the first round's are loaded beside
     // the i-particle's own record.
+    // Union tiles read the run's union list and each entry's member mask.
+    const bool uni = UNI && (it.tile_log2 & kUnion);
+    const int32_t* ent = uni ? c.u_entries : c.entries;
     int jn[G];
     auto load_idx = [&](int64_t b) {
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const int64_t e = b + tid + g * kWG;
-            jn[g] = e < it.j_end ? (DIRECT ? static_cast<int>(e) : c.entries[e]) : 0;
+            jn[g] = e < it.j_end ? (DIRECT ? static_cast<int>(e) : ent[e]) : 0;
         }
     };
     // Run-length lists: the round's indices are expanded from its runs after the
@@ -365,6 +382,7 @@ __device__ __forceinline__ void run_item(const Desc& c, const Item& it, int64_t 
     int64_t run = run0;
     if constexpr (!RUNS) load_idx(it.j_begin);
     const int i = c.active[it.act_begin + (has_i ? islot : 0)];
+    const int mb = uni ? static_cast<int>(c.act_member[it.act_begin + (has_i ? islot : 0)]) : 0;
 
     double xi, yi, zi;
     typename P::Vel vxi, vyi, vzi;
@@ -420,7 +438,20 @@ __device__ __forceinline__ void run_item(const Desc& c, const Item& it, int64_t 
                 typename P::Vel vxj, vyj, vzj;
                 typename P::Stored mj;
                 load_state<P, EAGER, RUNS>(c, j, xj, yj, zj, vxj, vyj, vzj, mj);
-                lds.j[e] = JRec<P>{xj, yj, zj, vxj, vyj, vzj, static_cast<double>(mj), j};
+                if constexpr (UNI) {   // the mask is loaded beside the record
+                    const int mask = uni ? static_cast<int>(c.u_mask[base + e]) : 0;
+                    lds.j[e] = JRec<P>{xj, yj, zj, vxj, vyj, vzj, static_cast<double>(mj), j, mask};
+                } else {   // the mask word is never read
+                    JRec<P>& r = lds.j[e];
+                    r.x = xj;
+                    r.y = yj;
+                    r.z = zj;
+                    r.vx = vxj;
+                    r.vy = vyj;
+                    r.vz = vzj;
+                    r.m = static_cast<double>(mj);
+                    r.idx = j;
+                }
             }
         }
         if constexpr (!RUNS) {
@@ -428,7 +459,32 @@ __device__ __forceinline__ void run_item(const Desc& c, const Item& it, int64_t 
         }
         __syncthreads();
         const double eps2 = c.eps2;
-        if (c.self_once) {
+        // the round's pairs: SK masks the self pair (not needed when every list
+        // holds each particle once), MK masks entries outside the i-particle's
+        // own list (union tiles)
+        auto pairs_of_round = [&](auto sk, auto mkt) {
+            constexpr bool SK = decltype(sk)::value, MK = decltype(mkt)::value;
+            if (cnt == R) {
+#pragma unroll 4
+                for (int u = 0; u < PER; ++u)
+                    pair<P, SK, MK>(xi, yi, zi, vxi, vyi, vzi, i, lds.j[stream + u * S], eps2, A, mb);
+            } else {
+#pragma unroll 1
+                for (int k = stream; k < cnt; k += S)
+                    pair<P, SK, MK>(xi, yi, zi, vxi, vyi, vzi, i, lds.j[k], eps2, A, mb);
+            }
+        };
+        using Yes = std::true_type;
+        using No = std::false_type;
+        if constexpr (UNI) {
+            if (uni) {
+                if (c.self_once) pairs_of_round(No{}, Yes{});
+                else pairs_of_round(Yes{}, Yes{});
+            } else {
+                if (c.self_once) pairs_of_round(No{}, No{});
+                else pairs_of_round(Yes{}, No{});
+            }
+        } else if (c.self_once) {
             if (cnt == R) {
 #pragma unroll 4
                 for (int u = 0; u < PER; ++u)
@@ -497,7 +553,7 @@ __device__ __forceinline__ void run_item(const Desc& c, const Item& it, int64_t 
 #pragma unroll
             for (int q = 0; q < kOut; ++q) Z.v[q] = 0.0;
             pair<P, false>(xi, yi, zi, vxi, vyi, vzi, i,
-                           JRec<P>{xi, yi, zi, vxi, vyi, vzi, static_cast<double>(mi), i}, c.eps2, Z);
+                           JRec<P>{xi, yi, zi, vxi, vyi, vzi, static_cast<double>(mi), i, 0}, c.eps2, Z);
             A.v[6] -= Z.v[6];
         }
         if (it.out < 0) {
@@ -523,8 +579,8 @@ __device__ __forceinline__ int find_entry(const Entry* tab, int n_tab, int64_t g
 // Register budget: the mixed form fits 128 VGPRs (4 waves per SIMD) without
 // spilling; the FP64 form, and the run-length lists' expansion, need a little
 // more and run 3 waves per SIMD.
-template <class P, bool RUNS = false>
-struct WavesPerSimd { static constexpr int value = P::kMixed && !RUNS ? 4 : 3; };
+template <class P, bool RUNS = false, bool UNI = false>
+struct WavesPerSimd { static constexpr int value = P::kMixed && !RUNS && !UNI ? 4 : 3; };
 
 // Work-group g takes items g, g + grid, ...  The grid is normally the item
 // count; graph replays and device loops launch a fixed grid and pass
@@ -537,8 +593,10 @@ struct WavesPerSimd { static constexpr int value = P::kMixed && !RUNS ? 4 : 3; }
 // b % n_bins from position b / n_bins on, in steps of grid / n_bins (the grid
 // is n_bins times the longest run).  Work-groups are handed to the XCDs in
 // turn, so each run stays on one XCD and its L2.
-template <class P, bool EAGER, bool DIRECT, bool RUNS = false>
-__global__ __launch_bounds__(kWG, (WavesPerSimd<P, RUNS>::value)) void force_kernel(const Entry* __restrict__ tab,
+// UNI: the plan holds union-tile items (a separate instantiation, so that the
+// plain kernel keeps its register budget).
+template <class P, bool EAGER, bool DIRECT, bool RUNS = false, bool UNI = false>
+__global__ __launch_bounds__(kWG, (WavesPerSimd<P, RUNS, UNI>::value)) void force_kernel(const Entry* __restrict__ tab,
                                                                                    int n_tab, int64_t n_items,
                                                                                    const int64_t* counts,
                                                                                    const int64_t* bins = nullptr,
@@ -560,15 +618,15 @@ __global__ __launch_bounds__(kWG, (WavesPerSimd<P, RUNS>::value)) void force_ker
         const Item it = tab[cl].items[k];
         const int64_t r0 = RUNS ? c.item_runs[k] : 0;
         switch (it.tile_log2 & kTileMask) {
-            case 8: run_item<P, EAGER, DIRECT, RUNS, 256>(c, it, r0, lds, rl); break;
-            case 7: run_item<P, EAGER, DIRECT, RUNS, 128>(c, it, r0, lds, rl); break;
-            case 6: run_item<P, EAGER, DIRECT, RUNS, 64>(c, it, r0, lds, rl); break;
-            case 5: run_item<P, EAGER, DIRECT, RUNS, 32>(c, it, r0, lds, rl); break;
-            case 4: run_item<P, EAGER, DIRECT, RUNS, 16>(c, it, r0, lds, rl); break;
-            case 3: run_item<P, EAGER, DIRECT, RUNS, 8>(c, it, r0, lds, rl); break;
-            case 2: run_item<P, EAGER, DIRECT, RUNS, 4>(c, it, r0, lds, rl); break;
-            case 1: run_item<P, EAGER, DIRECT, RUNS, 2>(c, it, r0, lds, rl); break;
-            default: run_item<P, EAGER, DIRECT, RUNS, 1>(c, it, r0, lds, rl); break;
+            case 8: run_item<P, EAGER, DIRECT, RUNS, 256, decltype(rl), UNI>(c, it, r0, lds, rl); break;
+            case 7: run_item<P, EAGER, DIRECT, RUNS, 128, decltype(rl), UNI>(c, it, r0, lds, rl); break;
+            case 6: run_item<P, EAGER, DIRECT, RUNS, 64, decltype(rl), UNI>(c, it, r0, lds, rl); break;
+            case 5: run_item<P, EAGER, DIRECT, RUNS, 32, decltype(rl), UNI>(c, it, r0, lds, rl); break;
+            case 4: run_item<P, EAGER, DIRECT, RUNS, 16, decltype(rl), UNI>(c, it, r0, lds, rl); break;
+            case 3: run_item<P, EAGER, DIRECT, RUNS, 8, decltype(rl), UNI>(c, it, r0, lds, rl); break;
+            case 2: run_item<P, EAGER, DIRECT, RUNS, 4, decltype(rl), UNI>(c, it, r0, lds, rl); break;
+            case 1: run_item<P, EAGER, DIRECT, RUNS, 2, decltype(rl), UNI>(c, it, r0, lds, rl); break;
+            default: run_item<P, EAGER, DIRECT, RUNS, 1, decltype(rl), UNI>(c, it, r0, lds, rl); break;
         }
         __syncthreads();
     }
@@ -1634,6 +1692,7 @@ bool layout_of(const ht_config& c, Layout& L) {
                    align_up(static_cast<size_t>(L.items_max) * sizeof(RTile)) +
                    align_up(static_cast<size_t>(c.active_max) * 4) +
                    align_up(static_cast<size_t>(L.items_max) * 8) +   // item run cursors (run-length lists)
+                   align_up(static_cast<size_t>(c.active_max)) +      // member indices (union tiles)
                    align_up((kMaxBins + 1) * 8) + 256;                 // run offsets of a placed plan
     L.off_plan = take(L.plan_bytes);
     L.off_partial = take(static_cast<size_t>(L.partial_max) * kOut * 8);
@@ -1755,6 +1814,17 @@ struct ht_ctx {
     int64_t n_runs = 0, n_copies = 0;
     std::vector<int64_t> run_pos;
     std::vector<int64_t> item_runs;
+    // union tiles (HT_LISTS_UNION, ht_set_union_width): runs of union_width
+    // consecutive groups, their union lists (entries and member masks on the
+    // device, offsets and lengths on the host) and the per-call member index
+    // of each active position
+    int32_t union_width = 4;
+    int32_t* d_uent = nullptr;
+    uint8_t* d_umask = nullptr;
+    size_t ucap = 0;
+    std::vector<int64_t> u_off;
+    std::vector<uint8_t> act_member;
+    int64_t union_items = 0;   // union-tile items in the last plan
     // scratch for planning
     std::vector<Item> items;
     std::vector<RTile> rtiles;
@@ -1773,6 +1843,10 @@ struct ht_ctx {
         d.t = t_pred;
         d.eps2 = cfg.eps2;
         d.self_once = self_once_lists && cfg.eps2 > 0.0 ? 1 : 0;
+        if (list_form == HT_LISTS_UNION) {
+            d.u_entries = d_uent;
+            d.u_mask = d_umask;
+        }
         if (list_form == HT_LISTS_RUNS) {
             d.run_start = d_run_start;
             d.run_pos = d_run_pos;
@@ -1873,6 +1947,7 @@ struct Tile {
     int32_t tb, ni;
     int tl;
     double cost;
+    bool uni;   // over a union list (union tiles)
 };
 
 // first_tile[r] (r = 1..256): log2 of the first tile in the least-cost cover
@@ -1907,29 +1982,82 @@ int plan(ht_ctx* c, int32_t n_active, const int32_t* ids, bool direct, bool plac
     tiles.clear();
     int64_t pairs = 0;
     double total = 0.0;
-    size_t g = 0;
-    int32_t k = 0;
-    while (k < n_active) {
-        int64_t ge = c->n, jb = 0, je = c->n;
-        if (!direct) {
-            while (c->group_first[g + 1] <= ids[k]) ++g;
-            ge = c->group_first[g + 1];
-            jb = c->list_off[g];
-            je = c->list_off[g + 1];
+    // the tiles of least modelled cost over a list of len entries for the
+    // active positions [tb, e), and what they cost
+    auto cover_cost = [c](int32_t n, int64_t len) {
+        const double rounds = static_cast<double>((len + kRound - 1) / kRound);
+        double cost = 0.0;
+        for (int32_t r = n; r > 0;) {
+            const int tl = r >= 256 ? 8 : c->first_tile[r];
+            cost += rounds * (c->gather_cost + static_cast<double>(1 << tl));
+            r -= std::min<int32_t>(r, 1 << tl);
         }
-        int32_t e = k;
-        while (e < n_active && ids[e] < ge) ++e;
-        for (int32_t tb = k; tb < e;) {
+        return cost;
+    };
+    auto cover = [&](int64_t jb, int64_t je, int32_t tb, int32_t e, bool uni) {
+        while (tb < e) {
             const int32_t r = e - tb;
             const int tl = r >= 256 ? 8 : c->first_tile[r];
             const int32_t ni = std::min<int32_t>(r, 1 << tl);
             const int64_t rounds = (je - jb + kRound - 1) / kRound;
             const double cost = static_cast<double>(rounds) * (c->gather_cost + static_cast<double>(1 << tl));
-            tiles.push_back(Tile{jb, je, tb, ni, tl, cost});
+            tiles.push_back(Tile{jb, je, tb, ni, tl, cost, uni});
             total += cost;
-            pairs += static_cast<int64_t>(ni) * (je - jb);
             tb += ni;
         }
+    };
+    const bool uni = c->list_form == HT_LISTS_UNION && !direct;
+    if (uni) c->act_member.assign(static_cast<size_t>(n_active), 0);
+    size_t g = 0;
+    int32_t k = 0;
+    while (k < n_active) {
+        if (direct) {
+            cover(0, c->n, k, n_active, false);
+            pairs += static_cast<int64_t>(n_active) * c->n;
+            break;
+        }
+        while (c->group_first[g + 1] <= ids[k]) ++g;
+        if (!uni) {
+            const int64_t ge = c->group_first[g + 1];
+            int32_t e = k;
+            while (e < n_active && ids[e] < ge) ++e;
+            cover(c->list_off[g], c->list_off[g + 1], k, e, false);
+            pairs += static_cast<int64_t>(e - k) * (c->list_off[g + 1] - c->list_off[g]);
+            k = e;
+            continue;
+        }
+        // union tiles: the run of groups holding group g, its members' active
+        // ranges, and the cheaper of per-group tiles and tiles over the union
+        const int32_t w = c->union_width;
+        const int32_t run = static_cast<int32_t>(g) / w;
+        const int32_t g0 = run * w, g1 = std::min<int32_t>(c->n_groups, g0 + w);
+        int32_t starts[9];
+        int32_t e = k;
+        double sep = 0.0;
+        int64_t run_pairs = 0;
+        for (int32_t q = g0; q < g1; ++q) {
+            starts[q - g0] = e;
+            const int64_t ge = c->group_first[q + 1];
+            const int32_t b0 = e;
+            while (e < n_active && ids[e] < ge) ++e;
+            const int64_t len = c->list_off[q + 1] - c->list_off[q];
+            if (e > b0) sep += cover_cost(e - b0, len);
+            run_pairs += static_cast<int64_t>(e - b0) * len;
+        }
+        starts[g1 - g0] = e;
+        const int64_t ub = c->u_off[run], ue = c->u_off[run + 1];
+        if (cover_cost(e - k, ue - ub) < sep) {
+            for (int32_t q = g0; q < g1; ++q)
+                for (int32_t a = starts[q - g0]; a < starts[q - g0 + 1]; ++a)
+                    c->act_member[a] = static_cast<uint8_t>(q - g0);
+            cover(ub, ue, k, e, true);
+        } else {
+            for (int32_t q = g0; q < g1; ++q)
+                if (starts[q - g0 + 1] > starts[q - g0])
+                    cover(c->list_off[q], c->list_off[q + 1], starts[q - g0], starts[q - g0 + 1], false);
+        }
+        pairs += run_pairs;
+        g = static_cast<size_t>(g1 - 1);
         k = e;
     }
     double quantum = total / c->target_items;
@@ -1944,7 +2072,7 @@ int plan(ht_ctx* c, int32_t n_active, const int32_t* ids, bool direct, bool plac
             ns = std::max<int64_t>(1, std::min<int64_t>(ns, rounds));
             if (ns == 1) {
                 items.push_back(Item{t.jb, t.je, -1, t.tb, static_cast<int16_t>(t.ni),
-                                     static_cast<int16_t>(t.tl | kSelfTerm)});
+                                     static_cast<int16_t>(t.tl | kSelfTerm | (t.uni ? kUnion : 0))});
                 continue;
             }
             const int64_t per = (rounds + ns - 1) / ns * rsz;   // entries per split, whole rounds
@@ -1952,7 +2080,8 @@ int plan(ht_ctx* c, int32_t n_active, const int32_t* ids, bool direct, bool plac
             for (int64_t b = t.jb; b < t.je; b += per, ++nsu)
                 items.push_back(Item{b, std::min(t.je, b + per), pslots + static_cast<int64_t>(nsu) * t.ni, t.tb,
                                      static_cast<int16_t>(t.ni),
-                                     static_cast<int16_t>(nsu == 0 ? t.tl | kSelfTerm : t.tl)});
+                                     static_cast<int16_t>((nsu == 0 ? t.tl | kSelfTerm : t.tl) |
+                                                          (t.uni ? kUnion : 0))});
             rtiles.push_back(RTile{pslots, t.tb, t.ni, nsu, 0});
             pslots += static_cast<int64_t>(nsu) * t.ni;
         }
@@ -2042,6 +2171,9 @@ int plan(ht_ctx* c, int32_t n_active, const int32_t* ids, bool direct, bool plac
             ir[q] = static_cast<int64_t>(std::upper_bound(c->run_pos.begin(), c->run_pos.end(), items[q].j_begin) -
                                          c->run_pos.begin()) - 1;
     }
+    c->union_items = 0;
+    if (uni)
+        for (const Item& it : items) c->union_items += (it.tile_log2 & kUnion) ? 1 : 0;
     c->last_pairs = pairs;
     c->last_items = static_cast<int32_t>(items.size());
     return HT_OK;
@@ -2079,6 +2211,12 @@ size_t pack_plan_into(ht_ctx* c, char* hs, char* dv, size_t at, int32_t n_active
         std::memcpy(hs + o_ir, c->item_runs.data(), c->item_runs.size() * 8);
         e.d.item_runs = reinterpret_cast<const int64_t*>(dv + o_ir);
         end = o_ir + c->item_runs.size() * 8;
+    }
+    if (c->list_form == HT_LISTS_UNION && c->act_member.size() == static_cast<size_t>(n_active)) {
+        const size_t o_am = align_up(end);   // each active position's member index in its run
+        std::memcpy(hs + o_am, c->act_member.data(), static_cast<size_t>(n_active));
+        e.d.act_member = reinterpret_cast<const uint8_t*>(dv + o_am);
+        end = o_am + static_cast<size_t>(n_active);
     }
     e.d.active = reinterpret_cast<const int32_t*>(dv + o_act);
     e.d.acc = acc;
@@ -2124,7 +2262,7 @@ int copy_plan(ht_ctx* c, size_t end) {
 template <class P>
 int launch_force(hipStream_t stream, bool eager, Timing& tm, const Entry* d_tab, int n_tab, int64_t n_items,
                  int64_t n_rtiles, bool direct, int64_t pairs, bool runs = false, const int64_t* d_bins = nullptr,
-                 int n_bins = 1, int64_t bin_max = 0) {
+                 int n_bins = 1, int64_t bin_max = 0, bool uni = false) {
     const int grid = d_bins ? static_cast<int>(n_bins * bin_max) : grid_for(n_items);
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
     if (tm.enabled) {
@@ -2144,6 +2282,9 @@ int launch_force(hipStream_t stream, bool eager, Timing& tm, const Entry* d_tab,
         else force_kernel<P, false, true><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr);
     } else if (runs) {
         force_kernel<P, false, false, true><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr, d_bins, n_bins);
+    } else if (uni) {
+        force_kernel<P, false, false, false, true><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr, d_bins,
+                                                                            n_bins);
     } else {
         if (eager)
             force_kernel<P, true, false><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr, d_bins, n_bins);
@@ -2262,9 +2403,9 @@ int enqueue_step(ht_ctx* c, const DevRows& u, bool predict_eager, int32_t n_acti
     const bool runs = c->list_form == HT_LISTS_RUNS && !direct;
     rc = c->cfg.precision == HT_PREC_FP64
              ? launch_force<PrecFp64>(c->stream, eager, c->tm, d_tab, 1, ni, nr, direct, c->last_pairs, runs,
-                                      d_bins, c->n_bins, c->bin_max)
+                                      d_bins, c->n_bins, c->bin_max, c->union_items > 0 && !direct)
              : launch_force<PrecMixed>(c->stream, eager, c->tm, d_tab, 1, ni, nr, direct, c->last_pairs, runs,
-                                       d_bins, c->n_bins, c->bin_max);
+                                       d_bins, c->n_bins, c->bin_max, c->union_items > 0 && !direct);
     if (rc) return rc;
     // The prep launch is the slot's only reader; marking the slot after the
     // whole step keeps the step's launches back to back on the host.
@@ -2449,6 +2590,8 @@ int ht_destroy(ht_ctx* c) {
     if (c->d_run_pos) (void)hipFree(c->d_run_pos);
     if (c->d_copy_rec) (void)hipFree(c->d_copy_rec);
     if (c->d_copy_src) (void)hipFree(c->d_copy_src);
+    if (c->d_uent) (void)hipFree(c->d_uent);
+    if (c->d_umask) (void)hipFree(c->d_umask);
     if (c->own_ws && c->ws) (void)hipFree(c->ws);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
@@ -2597,6 +2740,55 @@ int build_runs(ht_ctx* c, const int32_t* entries) {
     c->n_copies = static_cast<int64_t>(nc);
     return ctx_sync(c);   // pageable sources
 }
+// Union tiles: the groups in runs of union_width consecutive groups; each run's
+// union list holds every entry of its members' lists once, in order of first
+// appearance over the members in group order, with a bit per member whose list
+// holds it.  Host work linear in the lists' length.
+int build_unions(ht_ctx* c, int32_t n_groups, const int64_t* list_off, const int32_t* entries) {
+    const int32_t w = c->union_width;
+    const int32_t n_runs = (n_groups + w - 1) / w;
+    std::vector<int32_t> ue;
+    std::vector<uint8_t> um;
+    ue.reserve(static_cast<size_t>(list_off[n_groups]));
+    um.reserve(static_cast<size_t>(list_off[n_groups]));
+    std::vector<int64_t> pos(static_cast<size_t>(c->n) + c->n_nodes, -1);
+    c->u_off.assign(static_cast<size_t>(n_runs) + 1, 0);
+    for (int32_t r = 0; r < n_runs; ++r) {
+        const size_t start = ue.size();
+        for (int32_t q = 0; q < w && r * w + q < n_groups; ++q) {
+            const int32_t g = r * w + q;
+            for (int64_t e = list_off[g]; e < list_off[g + 1]; ++e) {
+                const int32_t j = entries[e];
+                if (pos[j] < 0) {
+                    pos[j] = static_cast<int64_t>(ue.size());
+                    ue.push_back(j);
+                    um.push_back(static_cast<uint8_t>(1u << q));
+                } else {
+                    um[pos[j]] = static_cast<uint8_t>(um[pos[j]] | (1u << q));
+                }
+            }
+        }
+        for (size_t k = start; k < ue.size(); ++k) pos[ue[k]] = -1;
+        c->u_off[r + 1] = static_cast<int64_t>(ue.size());
+    }
+    const size_t nu = ue.size();
+    if (nu > c->ucap) {
+        if (c->d_uent) (void)hipFree(c->d_uent);
+        if (c->d_umask) (void)hipFree(c->d_umask);
+        c->d_uent = nullptr;
+        c->d_umask = nullptr;
+        c->ucap = 0;
+        if (hipMalloc(&c->d_uent, nu * 4) != hipSuccess || hipMalloc(&c->d_umask, nu) != hipSuccess)
+            return fail(HT_ENOMEM, "hipMalloc of %zu union entries failed", nu);
+        c->ucap = nu;
+    }
+    if (nu) {
+        HT_HIP(hipMemcpyAsync(c->d_uent, ue.data(), nu * 4, hipMemcpyHostToDevice, c->stream));
+        HT_HIP(hipMemcpyAsync(c->d_umask, um.data(), nu, hipMemcpyHostToDevice, c->stream));
+    }
+    return ctx_sync(c);   // pageable sources
+}
+
 }  // namespace
 
 int ht_set_interaction_lists(ht_ctx* c, int32_t n_groups, const int64_t* group_first, const int64_t* list_off,
@@ -2649,6 +2841,10 @@ int ht_set_interaction_lists(ht_ctx* c, int32_t n_groups, const int64_t* group_f
         int rc = build_runs(c, entries);
         if (rc) return rc;
     }
+    if (c->list_form == HT_LISTS_UNION) {
+        int rc = build_unions(c, n_groups, list_off, entries);
+        if (rc) return rc;
+    }
     c->have_lists = true;
     if (c->ds_mem) return upload_group_offsets(c);
     return HT_OK;
@@ -2683,12 +2879,23 @@ int ht_predict_many(int32_t n_ctx, ht_ctx* const* ctxs, const double* t) {
 
 int ht_set_list_form(ht_ctx* c, int32_t form) {
     if (!c) return fail(HT_EINVAL, "ctx is NULL");
-    if (form != HT_LISTS_CSR && form != HT_LISTS_RUNS) return fail(HT_EINVAL, "unknown list form %d", form);
-    if (form == HT_LISTS_RUNS && c->cfg.predict_mode != HT_PREDICT_FUSED)
-        return fail(HT_EINVAL, "run-length lists need fused prediction");
+    if (form != HT_LISTS_CSR && form != HT_LISTS_RUNS && form != HT_LISTS_UNION)
+        return fail(HT_EINVAL, "unknown list form %d", form);
+    if (form != HT_LISTS_CSR && c->cfg.predict_mode != HT_PREDICT_FUSED)
+        return fail(HT_EINVAL, "run-length lists and union tiles need fused prediction");
     if (form != c->list_form) {
         c->list_form = form;
         c->have_lists = false;   // the lists must be set again, in the new form
+    }
+    return HT_OK;
+}
+
+int ht_set_union_width(ht_ctx* c, int32_t width) {
+    if (!c) return fail(HT_EINVAL, "ctx is NULL");
+    if (width < 2 || width > 8) return fail(HT_EINVAL, "union width %d outside [2, 8]", width);
+    if (width != c->union_width) {
+        c->union_width = width;
+        if (c->list_form == HT_LISTS_UNION) c->have_lists = false;   // set the lists again
     }
     return HT_OK;
 }
@@ -3361,7 +3568,7 @@ int ht_force_batch_async(int32_t n_ctx, ht_ctx* const* ctxs, const int32_t* n_ac
         for (int32_t q = 0; q < k; ++q)
             if (ctxs[q] == c) return fail(HT_EINVAL, "ctx %d appears twice in the batch", k);
         if (c->list_form != HT_LISTS_CSR)
-            return fail(HT_EINVAL, "ctx %d uses run-length lists, which batched calls do not take", k);
+            return fail(HT_EINVAL, "ctx %d does not use CSR lists, which batched calls need", k);
         if (!c->have_particles || !c->have_lists) return fail(HT_ESTATE, "ctx %d: lists not set", k);
         if (!c->predicted) return fail(HT_ESTATE, "ctx %d: not predicted", k);
         int rc = validate_active(c, n_active[k], ids[k]);
@@ -3508,7 +3715,7 @@ int check_member(const ht_batch* b, const ht_ctx* c, int32_t k, ht_ctx* const* c
     if (!c) return fail(HT_EINVAL, "ctx %d is NULL", k);
     if (c->cfg.device != b->device) return fail(HT_EINVAL, "ctx %d is on another device", k);
     if (same_stream && c->stream != b->stream) return fail(HT_EINVAL, "ctx %d does not share the batch's stream", k);
-    if (c->list_form != HT_LISTS_CSR) return fail(HT_EINVAL, "ctx %d uses run-length lists, which batched calls do not take", k);
+    if (c->list_form != HT_LISTS_CSR) return fail(HT_EINVAL, "ctx %d does not use CSR lists, which batched calls need", k);
     if (c->cfg.precision != ctxs[0]->cfg.precision || c->cfg.predict_mode != ctxs[0]->cfg.predict_mode)
         return fail(HT_EINVAL, "ctx %d differs in precision or predict mode", k);
     for (int32_t q = 0; q < k; ++q)
@@ -4333,7 +4540,7 @@ __global__ __launch_bounds__(kWG) void noalloc_direct_kernel(int32_t n, const do
             tile[tid] = JRec<P>{x[3 * j], x[3 * j + 1], x[3 * j + 2], static_cast<V>(v[3 * j]),
                                 static_cast<V>(v[3 * j + 1]), static_cast<V>(v[3 * j + 2]),
                                 static_cast<S>(m[j]),
-                                static_cast<int32_t>(j)};
+                                static_cast<int32_t>(j), 0};
         }
         __syncthreads();
         for (int k = 0; k < cnt; ++k) pair<P>(xi, yi, zi, vxi, vyi, vzi, i, tile[k], eps2, A);

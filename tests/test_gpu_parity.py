@@ -602,3 +602,104 @@ def test_placement_does_not_change_results(oracle, prec):
                 assert np.array_equal(p_, q_), (prec, ids.size)
         want = oracle.force_list(ids, XP, VP, MJ, 1e-4, gf, ptr.list_off, ptr.entries)
         assert_close(f"placement n_active={ids.size}", prec, got[1], want)
+
+
+# ------------------------------------------------------------------------------------------ union tiles
+@pytest.mark.parametrize("prec,width", [("fp64", 4), ("mixed", 2), ("mixed", 4), ("mixed", 8)])
+def test_union_tiles_match_oracle(oracle, prec, width):
+    """Union tiles (HT_LISTS_UNION): runs of `width` consecutive groups share
+    tiles over the union of their lists, each pair counted only where the
+    entry is in the i-particle's own list.  Every particle still sums exactly
+    its own list: checked against the oracle (and against the CSR form, to
+    rounding) for one active particle in every group (union tiles chosen
+    everywhere), a few per group, every tile size, all particles (per-group
+    tiles chosen), a single particle, and through ht_step_async with j-memory
+    updates; ε = 0 takes the masked self pair."""
+    import torch
+    say(f"union tiles ({prec}, width {width})")
+    n = 7000
+    x, v, m = W.plummer(n, 81)
+    m = W.salpeter_masses(n, 82)
+    z = np.zeros((n, 3))
+    ptr = B.HostTree(x, v, z, z, m, 1, 120, 0.5)
+    x, v, m = x[ptr.perm], v[ptr.perm], m[ptr.perm]
+    t0, a, j = W.random_block_state(n, 83, 0.25)
+    ctxs = {}
+    for form in ("csr", "union"):
+        c = make_ctx(prec, n, 2 * n, n, 2 * ptr.n_entries, 1e-4)
+        c.set_list_form(form)
+        if form == "union":
+            c.set_union_width(width)
+        c.set_j_particles(t0, m, x, v, a, j)
+        c.set_nodes(0.0, ptr.node_m, ptr.node_x, ptr.node_v, ptr.node_a, ptr.node_j)
+        c.set_interaction_lists(ptr.group_first, ptr.list_off, ptr.entries)
+        ctxs[form] = c
+    gf = ptr.group_first
+    r = (lambda u: u.astype(np.float32).astype(np.float64)) if prec == "mixed" else (lambda u: u)
+    rng = np.random.default_rng(84)
+    one = np.array([rng.integers(gf[g], gf[g + 1]) for g in range(ptr.n_group)])
+    counts = [1, 2, 3, 5, 9, 17, 33, 65, 129]
+    few = np.concatenate([np.sort(rng.choice(np.arange(gf[g], gf[g + 1]), min(gf[g + 1] - gf[g], counts[g % 9]),
+                                             replace=False)) for g in range(ptr.n_group)])
+    t = 0.25
+    tol = {"fp64": 1e-12, "mixed": 2e-6}[prec]
+    for step, ids in enumerate((one, few, np.arange(n), np.array([4321]))):
+        ids = ids.astype(np.int32)
+        got = {}
+        for form, c in ctxs.items():
+            c.predict(t)
+            got[form] = c.force(ids)
+        xp, vp = oracle.predict(t, t0, x, v, r(a), r(j))
+        nxp, nvp = oracle.predict(t, 0.0, ptr.node_x, ptr.node_v, r(ptr.node_a), r(ptr.node_j))
+        want = oracle.force_list(ids, np.vstack([xp, nxp]), np.vstack([vp, nvp]), r(np.concatenate([m, ptr.node_m])),
+                                 1e-4, gf, ptr.list_off, ptr.entries)
+        assert_close(f"union step {step}", prec, got["union"], want)
+        ea = errors(got["union"], got["csr"])
+        assert ea[0] <= tol, (step, ea)
+    # an update and the force in one call (ht_step_async)
+    dev = lambda u: torch.from_numpy(np.ascontiguousarray(u)).cuda()  # noqa: E731
+    upd_ids = np.sort(rng.choice(n, 600, replace=False)).astype(np.int32)
+    upd = (600, dev(upd_ids), dev(np.full(600, 0.25)), dev(m[upd_ids]), dev(x[upd_ids] + 1e-4), dev(v[upd_ids]),
+           dev(a[upd_ids]), dev(j[upd_ids]))
+    act = one.astype(np.int32)
+    outs = {f: tuple(torch.empty(sh, dtype=torch.float64, device="cuda") for sh in ((act.size, 3), (act.size, 3),
+                                                                                  (act.size,))) for f in ctxs}
+    for form, c in ctxs.items():
+        c.step_async(upd, 0.28125, act, *outs[form])
+        c.sync()
+    got = tuple(o.cpu().numpy() for o in outs["union"])
+    x2 = x.copy()
+    x2[upd_ids] += 1e-4
+    t02 = t0.copy()
+    t02[upd_ids] = 0.25
+    xp, vp = oracle.predict(0.28125, t02, x2, v, r(a), r(j))
+    nxp, nvp = oracle.predict(0.28125, 0.0, ptr.node_x, ptr.node_v, r(ptr.node_a), r(ptr.node_j))
+    want = oracle.force_list(act, np.vstack([xp, nxp]), np.vstack([vp, nvp]), r(np.concatenate([m, ptr.node_m])),
+                             1e-4, gf, ptr.list_off, ptr.entries)
+    assert_close("union step_async", prec, got, want)
+    with pytest.raises(B.HTError):
+        ctxs["union"].set_union_width(9)
+    with pytest.raises(B.HTError):
+        B.force_batch_async([ctxs["union"]], [act], [outs["union"][0]], [outs["union"][1]], [outs["union"][2]])
+
+
+def test_union_tiles_zero_softening(oracle):
+    """ε = 0: the self pair is masked by index inside union tiles too."""
+    say("union tiles, eps = 0")
+    n = 3000
+    x, v, m = W.plummer(n, 91)
+    z = np.zeros((n, 3))
+    ptr = B.HostTree(x, v, z, z, m, 1, 64, 0.5)
+    x, v, m = x[ptr.perm], v[ptr.perm], m[ptr.perm]
+    t0, a, j = W.random_block_state(n, 92, 0.125)
+    c = make_ctx("fp64", n, 2 * n, n, 2 * ptr.n_entries, 0.0)
+    c.set_list_form("union")
+    c.set_j_particles(t0, m, x, v, a, j)
+    c.set_nodes(0.0, ptr.node_m, ptr.node_x, ptr.node_v, ptr.node_a, ptr.node_j)
+    c.set_interaction_lists(ptr.group_first, ptr.list_off, ptr.entries)
+    c.predict(0.125)
+    gf = ptr.group_first
+    ids = np.array([gf[g] for g in range(ptr.n_group)], dtype=np.int32)
+    got = c.force(ids)
+    want = oracle_list_force(oracle, 0.125, ids, t0, m, x, v, a, j, ptr, 0.0)
+    assert_close("union eps=0", "fp64", got, want)
