@@ -23,6 +23,7 @@
 //
 // The pair sum is not a dense contraction (one rsqrt per pair), so it runs
 // on the vector ALUs; no matrix-core instructions are used.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -577,8 +578,8 @@ __device__ __forceinline__ int find_entry(const Entry* tab, int n_tab, int64_t g
 }
 
 // Register budget: the mixed form fits 128 VGPRs (4 waves per SIMD) without
-// spilling; the FP64 form, and the run-length lists' expansion, need a little
-// more and run 3 waves per SIMD.
+// spilling; the FP64 form, the run-length lists' expansion and the union
+// tiles' masked pairs need a little more and run 3 waves per SIMD.
 template <class P, bool RUNS = false, bool UNI = false>
 struct WavesPerSimd { static constexpr int value = P::kMixed && !RUNS && !UNI ? 4 : 3; };
 
@@ -2264,35 +2265,31 @@ int launch_force(hipStream_t stream, bool eager, Timing& tm, const Entry* d_tab,
                  int64_t n_rtiles, bool direct, int64_t pairs, bool runs = false, const int64_t* d_bins = nullptr,
                  int n_bins = 1, int64_t bin_max = 0, bool uni = false) {
     const int grid = d_bins ? static_cast<int>(n_bins * bin_max) : grid_for(n_items);
-    hipEvent_t ev_a = nullptr, ev_b = nullptr;
+    using Kern = void (*)(const Entry*, int, int64_t, const int64_t*, const int64_t*, int);
+    Kern kern;
+    if (direct) kern = eager ? force_kernel<P, true, true> : force_kernel<P, false, true>;
+    else if (runs) kern = force_kernel<P, false, false, true>;
+    else if (uni) kern = force_kernel<P, false, false, false, true>;
+    else kern = eager ? force_kernel<P, true, false> : force_kernel<P, false, false>;
+    const int64_t* counts = nullptr;
     if (tm.enabled) {
+        // Timing: the extended launch stamps the two events with the kernel's
+        // own start and end, so the time excludes the dispatch around it.
         while (tm.pool.size() < tm.used + 2) {
             hipEvent_t e;
             HT_HIP(hipEventCreate(&e));
             tm.pool.push_back(e);
         }
-        ev_a = tm.pool[tm.used];
-        ev_b = tm.pool[tm.used + 1];
+        hipEvent_t ev_a = tm.pool[tm.used], ev_b = tm.pool[tm.used + 1];
         tm.used += 2;
-        HT_HIP(hipEventRecord(ev_a, stream));
         tm.pairs += pairs;
-    }
-    if (direct) {
-        if (eager) force_kernel<P, true, true><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr);
-        else force_kernel<P, false, true><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr);
-    } else if (runs) {
-        force_kernel<P, false, false, true><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr, d_bins, n_bins);
-    } else if (uni) {
-        force_kernel<P, false, false, false, true><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr, d_bins,
-                                                                            n_bins);
+        void* args[] = {&d_tab, &n_tab, &n_items, &counts, &d_bins, &n_bins};
+        HT_HIP(hipExtLaunchKernel(reinterpret_cast<const void*>(kern), dim3(grid), dim3(kWG), args, 0, stream, ev_a,
+                                  ev_b, 0));
     } else {
-        if (eager)
-            force_kernel<P, true, false><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr, d_bins, n_bins);
-        else
-            force_kernel<P, false, false><<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, nullptr, d_bins, n_bins);
+        kern<<<grid, kWG, 0, stream>>>(d_tab, n_tab, n_items, counts, d_bins, n_bins);
+        HT_HIP(hipGetLastError());
     }
-    HT_HIP(hipGetLastError());
-    if (ev_b) HT_HIP(hipEventRecord(ev_b, stream));
     if (n_rtiles > 0) {
         reduce_kernel<<<grid_for(n_rtiles), kWG, 0, stream>>>(d_tab, n_tab, n_rtiles);
         HT_HIP(hipGetLastError());
