@@ -55,11 +55,11 @@ METRIC_ENSEMBLE = "batched ensemble (64 Plummer clusters, N 4096-65536): Hermite
 # only for the kernel source and the window (steps, warmup) it was taken on:
 # anything else makes the figure null until the counters are taken again.
 TRAFFIC = {
-    "kernel_source_sha256": "5944367b12c66c2ed9da6a3310ec3f346b8dccab4087f1f779558d1d5608d30e",
+    "kernel_source_sha256": "e8e1ffcf64e5e3cc0485cfa5a9e5c109e418caa1d7c833ff088543554add15ab",
     "steps": 20,
     "warmup": 5,
-    "fetch_bytes_per_launch": 1.16046e8,   # FETCH_SIZE 56663.2 KiB x 2.000
-    "write_bytes_per_launch": 2.5292e5,    # WRITE_SIZE 247.0 KiB x 1.000
+    "fetch_bytes_per_launch": 1.16097e8,   # FETCH_SIZE 56687.8 KiB x 2.000
+    "write_bytes_per_launch": 2.5293e5,    # WRITE_SIZE 247.0 KiB x 1.000
     "fetch_scale": 2.000,                  # 1 GiB read by a plain copy reads 524294.5 KiB
     "write_scale": 1.000,                  # 1 GiB written reads 1048576 KiB
     "profile": "profiles/force_kernel_mixed_plummer1m_traffic.md",
