@@ -43,7 +43,7 @@ FLOPS_PER_PAIR = 57          # Section 3 convention for force + jerk
 # MI355X's published FP32 vector peak (packed FP32 dual issue): the roofline's peak
 PEAK_FP32_TFLOPS = 157.3
 # 256 CU x 64 FMA lanes x 2 flop x 2.4 GHz: the non-packed FP32 (and FP64) issue
-# rate, which bounds this build (packed FP32 is not generated), reported beside it
+# rate, which bounds these kernels (they issue no packed FP32), reported beside it
 PEAK_NONPACKED_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, published
 METRIC = "Hermite acc+jerk interactions/s at N=2^20 vs direct; p99 block-step latency"
