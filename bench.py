@@ -129,7 +129,7 @@ class Recorded:
 
 
 def make_ctx(B, snap, n, precision, eps2, stream, predict_mode="fused", lists="csr", placement=None,
-             union_width=None, tuning=None, gather=None):
+             union_width=None, tuning=None):
     ctx = B.Context(n_max=n, node_max=snap["n_node"] + 64, group_max=snap["n_group"] + 16,
                     list_max=snap["n_entries"] + 1024, active_max=n, eps2=eps2, precision=precision,
                     predict_mode=predict_mode, stream=stream)
@@ -141,8 +141,6 @@ def make_ctx(B, snap, n, precision, eps2, stream, predict_mode="fused", lists="c
         ctx.set_tuning(*tuning)
     if placement is not None:
         ctx.set_placement(placement)
-    if gather is not None:
-        ctx.set_gather(gather)
     load_snapshot(ctx, snap)
     return ctx
 
@@ -551,8 +549,6 @@ def main():
     ap.add_argument("--predict", choices=("fused", "eager"), default="fused",
                     help="default workload: prediction mode of the tree legs (eager: one pass per step, then the gather)")
     ap.add_argument("--union-width", type=int, default=None, help="default workload: groups per union run (--lists union)")
-    ap.add_argument("--gather", choices=("registers", "lds", "lds2"), default=None,
-                    help="default workload: how the tree legs' force kernel gathers records (default: the library's)")
     ap.add_argument("--lists", choices=("csr", "runs", "union"), default="csr",
                     help="default workload: interaction-list form of the tree legs (the graph leg takes CSR)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -703,18 +699,18 @@ def main():
         lists = "csr" if direct else args.lists
         pm = "fused" if direct else args.predict
         ctx = make_ctx(B, rec.snap, rec.n, precision, cfg.eps2, sh, pm, lists=lists, placement=args.placement,
-                       union_width=args.union_width, tuning=ctx_tuning, gather=args.gather)
+                       union_width=args.union_width, tuning=ctx_tuning)
         r = replay(torch, B, rec, ctx, stream, args.warmup, args.steps, direct=direct, mode="kernel")
         r["placement"] = ctx.placement()
         r["kernel_wall_s"] = r.pop("wall_s")
         ctx.close()
         ctx = make_ctx(B, rec.snap, rec.n, precision, cfg.eps2, sh, pm, lists=lists, placement=args.placement,
-                       union_width=args.union_width, tuning=ctx_tuning, gather=args.gather)
+                       union_width=args.union_width, tuning=ctx_tuning)
         lt = replay(torch, B, rec, ctx, stream, args.warmup, args.steps, direct=direct, mode="latency")
         r["lat_ms"], r["latency_wall_s"] = lt["lat_ms"], lt["wall_s"]
         ctx.close()
         ctx = make_ctx(B, rec.snap, rec.n, precision, cfg.eps2, sh, pm, lists=lists, placement=args.placement,
-                       union_width=args.union_width, tuning=ctx_tuning, gather=args.gather)
+                       union_width=args.union_width, tuning=ctx_tuning)
         r["wall_s"] = replay(torch, B, rec, ctx, stream, args.warmup, args.steps, direct=direct)["wall_s"]
         ctx.close()
         return r
@@ -747,7 +743,7 @@ def main():
     all_active = None
     if not args.no_all_active:
         ctx = make_ctx(B, rec_all.snap, rec_all.n, "mixed", cfg.eps2, sh, lists=args.lists, placement=args.placement,
-                       union_width=args.union_width, gather=args.gather)
+                       union_width=args.union_width)
         ids = np.arange(rec_all.n, dtype=np.int32)
         acc = torch.empty((rec_all.n, 3), dtype=torch.float64, device="cuda")
         jrk = torch.empty_like(acc)
@@ -821,7 +817,7 @@ def main():
                    "eta": cfg.eta, "n_crit": cfg.n_crit, "n_leaf": cfg.n_leaf,
                    "masses": f"salpeter 1:{cfg.mass_ratio:g}" if cfg.mass_seed is not None else "equal",
                    "window": f"{K} block steps after the rebuild at t={cfg.dt_tree}", "precision": "mixed",
-                   "predict": args.predict, "lists": args.lists, "gather": args.gather or "library default",
+                   "predict": args.predict, "lists": args.lists,
                    "union_width": (args.union_width or 4) if args.lists == "union" else None,
                    "placement": {"runs": mixed["placement"][0], "xcds": mixed["placement"][1]}},
         "p50_step_ms": float(np.percentile(lat, 50)),

@@ -470,18 +470,6 @@ int ht_set_tuning(ht_ctx *ctx, double gather_cost, double target_items);
 int ht_set_placement(ht_ctx *ctx, int32_t runs);
 int ht_get_placement(const ht_ctx *ctx, int32_t *runs, int32_t *n_xcc);
 
-/* How the force kernel of the single-context list calls (ht_force,
- * ht_force_async, ht_step_async; fused prediction and CSR lists; not the
- * direct sum) moves the listed records (Section 2, steps 4a-5) from memory:
- * HT_GATHER_REGISTERS (default): each thread loads its entry's raw record
- * into registers, predicts it and stages it in LDS, one round after another;
- * HT_GATHER_LDS: the records of the next round are copied from memory
- * straight into LDS while the current round's pairs run.  Both sum the same
- * pairs in the same order: the results are bit-identical.  HT_EINVAL for
- * another mode. */
-typedef enum { HT_GATHER_REGISTERS = 0, HT_GATHER_LDS = 1 } ht_gather_mode;
-int ht_set_gather(ht_ctx *ctx, int32_t mode);
-
 /* Pair interactions the last force call summed (list entries x active
  * particles, self pairs included) and the number of work items it used. */
 int ht_last_stats(const ht_ctx *ctx, int64_t *pairs, int32_t *work_items);

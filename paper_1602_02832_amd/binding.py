@@ -155,7 +155,6 @@ def device_lib():
             "ht_set_list_form": [_vp, i],
             "ht_set_union_width": [_vp, i],
             "ht_set_placement": [_vp, i],
-            "ht_set_gather": [_vp, i],
             "ht_get_placement": [_vp, _c_i32p, _c_i32p],
             "ht_state_enable_ws": [_vp, _vp, ctypes.c_size_t],
             "ht_pool_create": [ctypes.POINTER(_vp), i, ctypes.c_size_t],
@@ -344,15 +343,6 @@ class Context:
         """ht_set_placement: work items in `runs` stretches, one per XCD (0: the
         device's XCD count, 1: off)."""
         _check(device_lib().ht_set_placement(self._h, int(runs)))
-
-    GATHER_MODES = {"registers": 0, "lds": 1, "lds2": 2}
-
-    def set_gather(self, mode):
-        """ht_set_gather: "registers" (default) or "lds" (the next round's
-        records copied straight into LDS during the current round's pairs)."""
-        if mode not in self.GATHER_MODES:
-            raise ValueError(f"gather mode {mode!r}: one of {sorted(self.GATHER_MODES)}")
-        _check(device_lib().ht_set_gather(self._h, self.GATHER_MODES[mode]))
 
     def placement(self):
         """(runs in use, the device's XCD count)."""

@@ -351,81 +351,6 @@ __device__ __forceinline__ void write_out(const Desc& c, int64_t o, const double
     c.pot[o] = v[6];
 }
 
-// The end of a work item: the S j-streams of each i-slot summed in a fixed
-// order, so results never depend on timing, then the self pair's potential
-// term (when the lists hold each particle once and this item carries it)
-// and the output or split-partial write.  red: LDS of kOut * kWG doubles,
-// free for use (the caller's staged records are no longer read).
-template <class P, int T>
-__device__ __forceinline__ void finish_item(const Desc& c, const Item& it, Acc64& A, double* red, double xi, double yi,
-                                            double zi, typename P::Vel vxi, typename P::Vel vyi, typename P::Vel vzi,
-                                            typename P::Stored mi, int i) {
-    constexpr int S = kWG / T;
-    const int tid = threadIdx.x;
-    const int islot = tid & (T - 1);
-    const int stream = tid / T;
-    const bool has_i = islot < it.n_i;
-    // T < 64: the 64 / T streams of a wave first, by a
-    // pairwise tree of lane exchanges (stream s += stream s + h, h = 32/T, ...,
-    // 1, i.e. lane offsets 32 down to T), then the four waves in order through
-    // LDS.  T >= 64 (at most four streams, whole waves each): a pairwise tree
-    // in LDS.
-    if constexpr (T < 64) {
-        auto add = [](double p, double q) { return p + q; };
-#pragma unroll
-        for (int q = 0; q < kOut; ++q) A.v[q] = wave_ops::tree<32, T>(A.v[q], add);
-        const int lane = tid & 63, wave = tid >> 6;
-        __syncthreads();
-        if (lane < T) {
-#pragma unroll
-            for (int q = 0; q < kOut; ++q) red[q * kWG + wave * T + lane] = A.v[q];
-        }
-        __syncthreads();
-        if (tid < T) {
-#pragma unroll
-            for (int q = 0; q < kOut; ++q)
-                A.v[q] = ((red[q * kWG + islot] + red[q * kWG + T + islot]) + red[q * kWG + 2 * T + islot]) +
-                         red[q * kWG + 3 * T + islot];
-        }
-    } else if constexpr (S > 1) {
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < kOut; ++q) red[q * kWG + tid] = A.v[q];
-#pragma unroll
-        for (int h = S / 2; h >= 1; h /= 2) {
-            __syncthreads();
-            if (stream < h) {
-#pragma unroll
-                for (int q = 0; q < kOut; ++q) red[q * kWG + tid] += red[q * kWG + tid + h * T];
-            }
-        }
-        __syncthreads();
-        if (stream == 0) {
-#pragma unroll
-            for (int q = 0; q < kOut; ++q) A.v[q] = red[q * kWG + islot];
-        }
-    }
-    if (stream == 0 && has_i) {
-        if (c.self_once && (it.tile_log2 & kSelfTerm)) {
-            // the self pair's potential term, as the pair loop summed it (same
-            // inputs, same operations; its acc and jerk terms are exact zeros)
-            Acc64 Z;
-#pragma unroll
-            for (int q = 0; q < kOut; ++q) Z.v[q] = 0.0;
-            pair<P, false>(xi, yi, zi, vxi, vyi, vzi, i,
-                           JRec<P>{xi, yi, zi, vxi, vyi, vzi, static_cast<double>(mi), i, 0}, c.eps2, Z);
-            A.v[6] -= Z.v[6];
-        }
-        if (it.out < 0) {
-            write_out(c, it.act_begin + islot, A.v);
-        } else {
-            double* p = c.partial + (it.out + islot) * kOut;
-#pragma unroll
-            for (int q = 0; q < kOut; ++q) p[q] = A.v[q];
-        }
-    }
-}
-
 // ------------------------------------------------------------------------------------------------
 // one work item with tile size T
 template <class P, bool EAGER, bool DIRECT, bool RUNS, int T, class RL, bool UNI = false>
@@ -580,170 +505,66 @@ __device__ __forceinline__ void run_item(const Desc& c, const Item& it, int64_t 
         }
     }
 
-    finish_item<P, T>(c, it, A, lds.red, xi, yi, zi, vxi, vyi, vzi, mi, i);
-}
-
-// ------------------------------------------------------------------------------------------------
-// LDS gather (fused prediction, CSR lists): the raw records of the next round
-// travel from memory straight into LDS (global_load_lds, one 16- or 4-byte
-// chunk per lane and instruction, no registers held) while the current
-// round's pairs run, so a round's gather overlaps the previous round's
-// arithmetic instead of following it.  Rounds are kRound entries, one per
-// thread; the pairs each thread sums, and their order, are those of run_item
-// (its two-entry rounds for small tiles visit the same entries in the same
-// order), so the results are bit-identical to it.
-//
-// Raw image of one wave's 64 records: chunk k of lane l at k * 1024 + l * 16
-// (the load's lane layout: lane l writes its bytes at the wave-uniform base
-// plus l times the chunk size); a mixed record's last 4 payload bytes in a
-// final 256-byte chunk.
-template <class P>
-struct RawImage {
-    static constexpr int kFull = P::kMixed ? 5 : 8;   // 16-byte chunks (mixed payload 84 B, FP64 128 B)
-    static constexpr int kTail = P::kMixed ? 4 : 0;   // bytes of the final chunk
-    static constexpr int kWave = 64 * (16 * kFull + kTail);
-};
-static_assert(offsetof(RecMixed, jz) == 80 && sizeof(float) == 4, "mixed payload ends at byte 84");
-
-typedef __attribute__((address_space(3))) void* LdsAddr;
-typedef __attribute__((address_space(1))) void* GlobalAddr;
-
-static_assert(sizeof(JRec<PrecMixed>) * kRound >= sizeof(double) * kOut * kWG, "reduction fits the staged records");
-
-// this lane's record j into the wave's raw image (wave_raw is wave-uniform)
-template <class P>
-__device__ __forceinline__ void gather_raw(const typename P::Rec* rec, int j, char* wave_raw) {
-    const char* src = reinterpret_cast<const char*>(rec + j);
+    // Reduce the S j-streams of each i-slot in a fixed order, so results never
+    // depend on timing.  T < 64: the 64 / T streams of a wave first, by a
+    // pairwise tree of lane exchanges (stream s += stream s + h, h = 32/T, ...,
+    // 1, i.e. lane offsets 32 down to T), then the four waves in order through
+    // LDS.  T >= 64 (at most four streams, whole waves each): a pairwise tree
+    // in LDS.
+    if constexpr (T < 64) {
+        auto add = [](double p, double q) { return p + q; };
 #pragma unroll
-    for (int k = 0; k < RawImage<P>::kFull; ++k)
-        __builtin_amdgcn_global_load_lds((GlobalAddr)(src + 16 * k), (LdsAddr)(wave_raw + 1024 * k), 16, 0, 0);
-    if constexpr (RawImage<P>::kTail > 0)
-        __builtin_amdgcn_global_load_lds((GlobalAddr)(src + 16 * RawImage<P>::kFull),
-                                         (LdsAddr)(wave_raw + 1024 * RawImage<P>::kFull), RawImage<P>::kTail, 0, 0);
-}
-
-// this lane's record back out of the wave's raw image (payload fields only)
-template <class P>
-__device__ __forceinline__ typename P::Rec raw_record(const char* wave_raw, int lane) {
-    typename P::Rec r;
-    uint4* d = reinterpret_cast<uint4*>(&r);
+        for (int q = 0; q < kOut; ++q) A.v[q] = wave_ops::tree<32, T>(A.v[q], add);
+        const int lane = tid & 63, wave = tid >> 6;
+        __syncthreads();
+        if (lane < T) {
 #pragma unroll
-    for (int k = 0; k < RawImage<P>::kFull; ++k) d[k] = *reinterpret_cast<const uint4*>(wave_raw + 1024 * k + 16 * lane);
-    if constexpr (RawImage<P>::kTail > 0)
-        reinterpret_cast<uint32_t*>(&r)[4 * RawImage<P>::kFull] =
-            *reinterpret_cast<const uint32_t*>(wave_raw + 1024 * RawImage<P>::kFull + 4 * lane);
-    return r;
-}
-
-// sj: the round's staged (predicted) records, reduction space afterwards;
-// raw: the raw images of the four waves.  Two LDS variables, so that the
-// compiler can tell the staged records' reads from the loads into the raw
-// images and does not wait for those before the pair loop.
-template <class P, int G2, int T>
-__device__ __forceinline__ void run_item_lds(const Desc& c, const Item& it, JRec<P>* sj, char* raw, int32_t* sidx) {
-    // entries per thread and round: one, or as in run_item (two for small tiles)
-    constexpr int G = G2 ? round_mult(T) : 1;
-    constexpr int R = kRound * G;
-    constexpr int S = kWG / T;   // j-streams
-    constexpr int PER = R / S;
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int islot = tid & (T - 1);
-    const int stream = tid / T;
-    const bool has_i = islot < it.n_i;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    // entry tid + g * kRound of a round: raw image in region g, this wave's
-    // part; list index in sidx[tid + g * kRound] (the same lane layout)
-    char* wave_raw = raw + wave * RawImage<P>::kWave;
-    const typename P::Rec* rec = static_cast<const typename P::Rec*>(c.rec);
-    const char* ent = reinterpret_cast<const char*>(c.entries);
-    // the list indices of the round starting at b into sidx (lanes past the
-    // item's end load nothing; their slots are never read)
-    auto indices_to_lds = [&](int64_t b) {
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int64_t e = b + tid + g * kRound;
-            if (e < it.j_end)
-                __builtin_amdgcn_global_load_lds((GlobalAddr)(ent + 4 * e),
-                                                 (LdsAddr)(sidx + g * kRound + wave * 64), 4, 0, 0);
+            for (int q = 0; q < kOut; ++q) lds.red[q * kWG + wave * T + lane] = A.v[q];
         }
-    };
-    // the records of the round starting at b into the raw images (the lane's
-    // index from sidx; record 0, never staged, past the item's end)
-    int j_cur[G];
-    auto records_to_lds = [&](int64_t b) {
+        __syncthreads();
+        if (tid < T) {
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            j_cur[g] = b + tid + g * kRound < it.j_end ? sidx[tid + g * kRound] : 0;
-            gather_raw<P>(rec, j_cur[g], wave_raw + g * 4 * RawImage<P>::kWave);
+            for (int q = 0; q < kOut; ++q)
+                A.v[q] = ((lds.red[q * kWG + islot] + lds.red[q * kWG + T + islot]) + lds.red[q * kWG + 2 * T + islot]) +
+                         lds.red[q * kWG + 3 * T + islot];
         }
-    };
-    // prologue: round 0's indices, then its records; round 1's indices
-    // (every round waits for its loads, so none is left outstanding when the
-    // item ends)
-    if (it.j_begin < it.j_end) {
-        indices_to_lds(it.j_begin);
-        __builtin_amdgcn_s_waitcnt(0);
-        records_to_lds(it.j_begin);   // each record load waits for its index's LDS read
-        indices_to_lds(it.j_begin + R);
+    } else if constexpr (S > 1) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kOut; ++q) lds.red[q * kWG + tid] = A.v[q];
+#pragma unroll
+        for (int h = S / 2; h >= 1; h /= 2) {
+            __syncthreads();
+            if (stream < h) {
+#pragma unroll
+                for (int q = 0; q < kOut; ++q) lds.red[q * kWG + tid] += lds.red[q * kWG + tid + h * T];
+            }
+        }
+        __syncthreads();
+        if (stream == 0) {
+#pragma unroll
+            for (int q = 0; q < kOut; ++q) A.v[q] = lds.red[q * kWG + islot];
+        }
     }
-    const int i = c.active[it.act_begin + (has_i ? islot : 0)];
-    double xi, yi, zi;
-    typename P::Vel vxi, vyi, vzi;
-    typename P::Stored mi;
-    load_state<P, false>(c, i, xi, yi, zi, vxi, vyi, vzi, mi);
-
-    Acc64 A;
+    if (stream == 0 && has_i) {
+        if (c.self_once && (it.tile_log2 & kSelfTerm)) {
+            // the self pair's potential term, as the pair loop summed it (same
+            // inputs, same operations; its acc and jerk terms are exact zeros)
+            Acc64 Z;
 #pragma unroll
-    for (int q = 0; q < kOut; ++q) A.v[q] = 0.0;
-    const double eps2 = c.eps2;
-    for (int64_t base = it.j_begin; base < it.j_end; base += R) {
-        const int64_t rest = it.j_end - base;
-        const int cnt = rest < R ? static_cast<int>(rest) : R;
-        __builtin_amdgcn_s_waitcnt(0);   // this wave's loads of the round have reached LDS
-        __syncthreads();                 // every wave's; the previous round's pairs are done
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int e = tid + g * kRound;
-            if (e < cnt) {
-                const typename P::Rec r = raw_record<P>(wave_raw + g * 4 * RawImage<P>::kWave, lane);
-                double x, y, z, vx, vy, vz;
-                predict_rec<P>(r, c.t, x, y, z, vx, vy, vz);
-                JRec<P>& J = sj[e];
-                J.x = x;
-                J.y = y;
-                J.z = z;
-                J.vx = static_cast<typename P::Vel>(vx);
-                J.vy = static_cast<typename P::Vel>(vy);
-                J.vz = static_cast<typename P::Vel>(vz);
-                J.m = static_cast<double>(r.m);
-                J.idx = j_cur[g];
-            }
+            for (int q = 0; q < kOut; ++q) Z.v[q] = 0.0;
+            pair<P, false>(xi, yi, zi, vxi, vyi, vzi, i,
+                           JRec<P>{xi, yi, zi, vxi, vyi, vzi, static_cast<double>(mi), i, 0}, c.eps2, Z);
+            A.v[6] -= Z.v[6];
         }
-        __syncthreads();   // the round is staged; the raw images are free
-        if (base + R < it.j_end) {   // the next round's records, in flight during this round's pairs
-            records_to_lds(base + R);
-            indices_to_lds(base + 2 * R);   // each lane rewrites only the slots it has just read
-        }
-        if (c.self_once) {
-            if (cnt == R) {
-#pragma unroll 4
-                for (int u = 0; u < PER; ++u)
-                    pair<P, false>(xi, yi, zi, vxi, vyi, vzi, i, sj[stream + u * S], eps2, A);
-            } else {
-#pragma unroll 1
-                for (int k = stream; k < cnt; k += S) pair<P, false>(xi, yi, zi, vxi, vyi, vzi, i, sj[k], eps2, A);
-            }
+        if (it.out < 0) {
+            write_out(c, it.act_begin + islot, A.v);
         } else {
-            if (cnt == R) {
-#pragma unroll 4
-                for (int u = 0; u < PER; ++u) pair<P>(xi, yi, zi, vxi, vyi, vzi, i, sj[stream + u * S], eps2, A);
-            } else {
-#pragma unroll 1
-                for (int k = stream; k < cnt; k += S) pair<P>(xi, yi, zi, vxi, vyi, vzi, i, sj[k], eps2, A);
-            }
+            double* p = c.partial + (it.out + islot) * kOut;
+#pragma unroll
+            for (int q = 0; q < kOut; ++q) p[q] = A.v[q];
         }
     }
-    finish_item<P, T>(c, it, A, reinterpret_cast<double*>(sj), xi, yi, zi, vxi, vyi, vzi, mi, i);
 }
 
 __device__ __forceinline__ int find_entry(const Entry* tab, int n_tab, int64_t g, bool rtile) {
@@ -807,44 +628,6 @@ __global__ __launch_bounds__(kWG, (WavesPerSimd<P, RUNS, UNI>::value)) void forc
             case 2: run_item<P, EAGER, DIRECT, RUNS, 4, decltype(rl), UNI>(c, it, r0, lds, rl); break;
             case 1: run_item<P, EAGER, DIRECT, RUNS, 2, decltype(rl), UNI>(c, it, r0, lds, rl); break;
             default: run_item<P, EAGER, DIRECT, RUNS, 1, decltype(rl), UNI>(c, it, r0, lds, rl); break;
-        }
-        __syncthreads();
-    }
-}
-
-// The LDS-gather form of force_kernel<P, false, false> (fused prediction,
-// CSR lists): same items, same work-group order, same results.
-template <class P, int G2>
-__global__ __launch_bounds__(kWG, (G2 ? 2 : WavesPerSimd<P>::value)) void force_kernel_lds(const Entry* __restrict__ tab, int n_tab,
-                                                                              int64_t n_items, const int64_t* counts,
-                                                                              const int64_t* bins = nullptr,
-                                                                              int n_bins = 1) {
-    constexpr int GM = G2 ? 2 : 1;   // most entries per thread and round
-    __shared__ JRec<P> sj[GM * kRound];
-    __shared__ __attribute__((aligned(16))) char raw[GM * 4 * RawImage<P>::kWave];
-    __shared__ int32_t sidx[GM * kRound];
-    if (n_items < 0) n_items = counts[0];
-    int64_t g0 = blockIdx.x, step = gridDim.x;
-    if (bins) {
-        const int x = static_cast<int>(blockIdx.x % static_cast<unsigned>(n_bins));
-        g0 = bins[x] + blockIdx.x / static_cast<unsigned>(n_bins);
-        step = gridDim.x / static_cast<unsigned>(n_bins);
-        n_items = bins[x + 1];
-    }
-    for (int64_t g = g0; g < n_items; g += step) {
-        const int cl = find_entry(tab, n_tab, g, false);
-        const Desc& c = tab[cl].d;
-        const Item it = tab[cl].items[g - tab[cl].first_item];
-        switch (it.tile_log2 & kTileMask) {
-            case 8: run_item_lds<P, G2, 256>(c, it, sj, raw, sidx); break;
-            case 7: run_item_lds<P, G2, 128>(c, it, sj, raw, sidx); break;
-            case 6: run_item_lds<P, G2, 64>(c, it, sj, raw, sidx); break;
-            case 5: run_item_lds<P, G2, 32>(c, it, sj, raw, sidx); break;
-            case 4: run_item_lds<P, G2, 16>(c, it, sj, raw, sidx); break;
-            case 3: run_item_lds<P, G2, 8>(c, it, sj, raw, sidx); break;
-            case 2: run_item_lds<P, G2, 4>(c, it, sj, raw, sidx); break;
-            case 1: run_item_lds<P, G2, 2>(c, it, sj, raw, sidx); break;
-            default: run_item_lds<P, G2, 1>(c, it, sj, raw, sidx); break;
         }
         __syncthreads();
     }
@@ -1981,7 +1764,6 @@ struct ht_ctx {
     // placement over XCDs (ht_set_placement): placement runs requested (1: off),
     // the device's XCD count, and the last plan's run offsets and longest run
     int32_t placement = 1, n_xcc = 1;
-    int32_t gather = HT_GATHER_REGISTERS;   // ht_set_gather
     int32_t n_bins = 1;
     int64_t bin_off[kMaxBins + 1] = {};
     int64_t bin_max = 0;
@@ -2481,15 +2263,14 @@ int copy_plan(ht_ctx* c, size_t end) {
 template <class P>
 int launch_force(hipStream_t stream, bool eager, Timing& tm, const Entry* d_tab, int n_tab, int64_t n_items,
                  int64_t n_rtiles, bool direct, int64_t pairs, bool runs = false, const int64_t* d_bins = nullptr,
-                 int n_bins = 1, int64_t bin_max = 0, bool uni = false, int lds_gather = 0) {
+                 int n_bins = 1, int64_t bin_max = 0, bool uni = false) {
     const int grid = d_bins ? static_cast<int>(n_bins * bin_max) : grid_for(n_items);
     using Kern = void (*)(const Entry*, int, int64_t, const int64_t*, const int64_t*, int);
     Kern kern;
     if (direct) kern = eager ? force_kernel<P, true, true> : force_kernel<P, false, true>;
     else if (runs) kern = force_kernel<P, false, false, true>;
     else if (uni) kern = force_kernel<P, false, false, false, true>;
-    else if (eager) kern = force_kernel<P, true, false>;
-    else kern = lds_gather == 2 ? force_kernel_lds<P, 1> : lds_gather == 1 ? force_kernel_lds<P, 0> : force_kernel<P, false, false>;
+    else kern = eager ? force_kernel<P, true, false> : force_kernel<P, false, false>;
     const int64_t* counts = nullptr;
     if (tm.enabled) {
         // Timing: the extended launch stamps the two events with the kernel's
@@ -2617,12 +2398,11 @@ int enqueue_step(ht_ctx* c, const DevRows& u, bool predict_eager, int32_t n_acti
     const int64_t ni = static_cast<int64_t>(c->items.size()), nr = static_cast<int64_t>(c->rtiles.size());
     const bool eager = c->cfg.predict_mode == HT_PREDICT_EAGER;
     const bool runs = c->list_form == HT_LISTS_RUNS && !direct;
-    const int lds_gather = c->gather;
     rc = c->cfg.precision == HT_PREC_FP64
              ? launch_force<PrecFp64>(c->stream, eager, c->tm, d_tab, 1, ni, nr, direct, c->last_pairs, runs,
-                                      d_bins, c->n_bins, c->bin_max, c->union_items > 0 && !direct, lds_gather)
+                                      d_bins, c->n_bins, c->bin_max, c->union_items > 0 && !direct)
              : launch_force<PrecMixed>(c->stream, eager, c->tm, d_tab, 1, ni, nr, direct, c->last_pairs, runs,
-                                       d_bins, c->n_bins, c->bin_max, c->union_items > 0 && !direct, lds_gather);
+                                       d_bins, c->n_bins, c->bin_max, c->union_items > 0 && !direct);
     if (rc) return rc;
     // The prep launch is the slot's only reader; marking the slot after the
     // whole step keeps the step's launches back to back on the host.
@@ -4565,13 +4345,6 @@ int ht_set_placement(ht_ctx* c, int32_t runs) {
     if (!c) return fail(HT_EINVAL, "ctx is NULL");
     if (runs < 0 || runs > kMaxBins) return fail(HT_EINVAL, "placement runs = %d outside [0, %d]", runs, kMaxBins);
     c->placement = runs == 0 ? c->n_xcc : runs;
-    return HT_OK;
-}
-
-int ht_set_gather(ht_ctx* c, int32_t mode) {
-    if (!c) return fail(HT_EINVAL, "ctx is NULL");
-    if (mode < 0 || mode > 2) return fail(HT_EINVAL, "gather mode %d unknown", mode);
-    c->gather = mode;
     return HT_OK;
 }
 

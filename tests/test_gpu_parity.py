@@ -604,86 +604,6 @@ def test_placement_does_not_change_results(oracle, prec):
         assert_close(f"placement n_active={ids.size}", prec, got[1], want)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_lds_gather_equals_registers(oracle, prec):
-    """ht_set_gather(HT_GATHER_LDS) copies the next round's records straight
-    into LDS while the current round's pairs run; it sums the same pairs in
-    the same order as the register gather, so the outputs are equal bit for
-    bit: active sets that hit every tile size, one active particle per group,
-    a single particle (one long list split over many items), every seventh
-    particle and all particles; with placement over the XCDs; through
-    ht_step_async with j-memory updates; and with zero softening (the self
-    pair masked by index).  The oracle agrees."""
-    import torch
-    say(f"LDS gather ({prec})")
-    n = 6000
-    x, v, m = W.plummer(n, 171)
-    m = W.salpeter_masses(n, 172)
-    z = np.zeros((n, 3))
-    ptr = B.HostTree(x, v, z, z, m, 1, 300, 0.5)
-    x, v, m = x[ptr.perm], v[ptr.perm], m[ptr.perm]
-    t0, a, j = W.random_block_state(n, 173, 0.125)
-    gf = ptr.group_first
-    r = (lambda u: u.astype(np.float32).astype(np.float64)) if prec == "mixed" else (lambda u: u)
-    rng = np.random.default_rng(174)
-    counts = [1, 2, 3, 5, 9, 17, 33, 65, 129, 257]
-    sel = np.concatenate([np.sort(rng.choice(np.arange(gf[g], gf[g + 1]), min(gf[g + 1] - gf[g], counts[g % 10]),
-                                             replace=False)) for g in range(ptr.n_group)])
-    one = np.array([rng.integers(gf[g], gf[g + 1]) for g in range(ptr.n_group)])
-    for eps2 in (1e-4, 0.0):
-        ctxs = {}
-        for name, mode, runs in (("registers", "registers", 1), ("lds", "lds", 1), ("lds placed", "lds", 0),
-                                 ("lds2", "lds2", 1)):
-            c = make_ctx(prec, n, 2 * n, n, 2 * ptr.n_entries, eps2)
-            c.set_gather(mode)
-            c.set_placement(runs)
-            c.set_j_particles(t0, m, x, v, a, j)
-            c.set_nodes(0.0, ptr.node_m, ptr.node_x, ptr.node_v, ptr.node_a, ptr.node_j)
-            c.set_interaction_lists(ptr.group_first, ptr.list_off, ptr.entries)
-            c.predict(0.125)
-            ctxs[name] = c
-        xp, vp = oracle.predict(0.125, t0, x, v, r(a), r(j))
-        nxp, nvp = oracle.predict(0.125, 0.0, ptr.node_x, ptr.node_v, r(ptr.node_a), r(ptr.node_j))
-        XP, VP, MJ = np.vstack([xp, nxp]), np.vstack([vp, nvp]), r(np.concatenate([m, ptr.node_m]))
-        for ids in (sel, one, np.array([4321]), np.arange(0, n, 7), np.arange(n)):
-            ids = ids.astype(np.int32)
-            got = {k: c.force(ids) for k, c in ctxs.items()}
-            for k in ("lds", "lds placed", "lds2"):
-                for p_, q_ in zip(got["registers"], got[k]):
-                    assert np.array_equal(p_, q_), (prec, eps2, k, ids.size)
-            if eps2 > 0.0 or prec == "fp64":   # the mixed form's tolerances assume softening
-                want = oracle.force_list(ids, XP, VP, MJ, eps2, gf, ptr.list_off, ptr.entries)
-                assert_close(f"lds gather eps2={eps2} n_active={ids.size}", prec, got["lds"], want)
-        if eps2 == 0.0:
-            continue
-        # an update and the force in one call (ht_step_async)
-        dev = lambda u: torch.from_numpy(np.ascontiguousarray(u)).cuda()  # noqa: E731
-        upd_ids = np.sort(rng.choice(n, 500, replace=False)).astype(np.int32)
-        upd = (500, dev(upd_ids), dev(np.full(500, 0.125)), dev(m[upd_ids]), dev(x[upd_ids] + 1e-4), dev(v[upd_ids]),
-               dev(a[upd_ids]), dev(j[upd_ids]))
-        act = sel.astype(np.int32)
-        outs = {}
-        for k, c in ctxs.items():
-            outs[k] = tuple(torch.empty(sh, dtype=torch.float64, device="cuda")
-                            for sh in ((act.size, 3), (act.size, 3), (act.size,)))
-            c.step_async(upd, 0.15625, act, *outs[k])
-            c.sync()
-        got = {k: tuple(o.cpu().numpy() for o in outs[k]) for k in outs}
-        for k in ("lds", "lds placed", "lds2"):
-            for p_, q_ in zip(got["registers"], got[k]):
-                assert np.array_equal(p_, q_), (prec, "step_async", k)
-        x2, t02 = x.copy(), t0.copy()
-        x2[upd_ids] += 1e-4
-        t02[upd_ids] = 0.125
-        xp, vp = oracle.predict(0.15625, t02, x2, v, r(a), r(j))
-        nxp, nvp = oracle.predict(0.15625, 0.0, ptr.node_x, ptr.node_v, r(ptr.node_a), r(ptr.node_j))
-        want = oracle.force_list(act, np.vstack([xp, nxp]), np.vstack([vp, nvp]), r(np.concatenate([m, ptr.node_m])),
-                                 eps2, gf, ptr.list_off, ptr.entries)
-        assert_close("lds gather step_async", prec, got["lds"], want)
-    with pytest.raises(ValueError):
-        ctxs["lds"].set_gather("shared")
-
-
 # ------------------------------------------------------------------------------------------ union tiles
 @pytest.mark.parametrize("prec,width", [("fp64", 4), ("mixed", 2), ("mixed", 4), ("mixed", 8)])
 def test_union_tiles_match_oracle(oracle, prec, width):
