@@ -336,6 +336,11 @@ class Context:
         gf = _arr(group_first, np.int64)
         lo = _arr(list_off, np.int64)
         en = _arr(entries, np.int32)
+        # the library reads G + 1 offsets of each kind and list_off[G] entries
+        if gf.ndim != 1 or gf.shape[0] < 1 or lo.shape != gf.shape:
+            raise ValueError(f"group_first {gf.shape} and list_off {lo.shape} must be one-dimensional, of equal length")
+        if en.ndim != 1 or lo[-1] > en.shape[0]:
+            raise ValueError(f"list_off ends at {int(lo[-1])} but entries holds {en.shape[0]}")
         _check(device_lib().ht_set_interaction_lists(self._h, gf.shape[0] - 1, _ptr(gf, ctypes.c_int64),
                                                      _ptr(lo, ctypes.c_int64), _ptr(en, ctypes.c_int32)))
 

@@ -292,6 +292,71 @@ def test_api_errors():
     assert e.value.code == -1
 
 
+def test_capacities_and_list_checks(oracle):
+    """Sizes beyond the context's capacities are refused with HT_ERANGE
+    (particles, nodes, groups, list entries) and malformed lists with
+    HT_EINVAL (offsets not starting at 0 or decreasing, groups not covering
+    0..N), all before anything is copied: the lists set before the refusals
+    stay in force and the forces still match the oracle.  Arrays of
+    mismatched lengths are refused by the binding before the call."""
+    say("capacities and list checks")
+    n = 300
+    x, v, m = W.plummer(n, 5)
+    z = np.zeros((n, 3))
+    ptr = B.HostTree(x, v, z, z, m, 1, 24, 0.5)
+    x, v, m = x[ptr.perm], v[ptr.perm], m[ptr.perm]
+    t0, a, j = W.random_block_state(n, 6, 0.125)
+    G, M, L = ptr.n_group, ptr.n_node, ptr.n_entries
+    assert G >= 2
+    c = make_ctx("fp64", n, M, G, L, 1e-4)
+    xn, vn, mn = np.vstack([x, x[:1]]), np.vstack([v, v[:1]]), np.concatenate([m, m[:1]])
+    codes = []
+
+    def refused(call, *args):
+        with pytest.raises(B.HTError) as e:
+            call(*args)
+        codes.append(e.value.code)
+
+    refused(c.set_j_particles, 0.0, mn, xn, vn, np.zeros((n + 1, 3)), np.zeros((n + 1, 3)))   # n_max + 1
+    c.set_j_particles(t0, m, x, v, a, j)
+    nm = np.concatenate([ptr.node_m, ptr.node_m[:1]])
+    n3 = [np.vstack([u, u[:1]]) for u in (ptr.node_x, ptr.node_v, ptr.node_a, ptr.node_j)]
+    refused(c.set_nodes, 0.0, nm, *n3)                                                          # node_max + 1
+    c.set_nodes(0.0, ptr.node_m, ptr.node_x, ptr.node_v, ptr.node_a, ptr.node_j)
+    gf, lo, en = ptr.group_first, ptr.list_off, ptr.entries
+    c.set_interaction_lists(gf, lo, en)
+    # one group split in two: G + 1 groups (each keeps a valid list)
+    g0 = int(np.argmax(np.diff(gf) >= 2))
+    gf2 = np.insert(gf, g0 + 1, gf[g0] + 1)
+    lo2 = np.insert(lo, g0 + 1, lo[g0 + 1])
+    refused(c.set_interaction_lists, gf2, lo2, en)                                             # group_max + 1
+    lo3 = lo.copy()
+    lo3[-1] += 1
+    refused(c.set_interaction_lists, gf, lo3, np.concatenate([en, en[:1]]))                    # list_max + 1
+    assert codes == [-2, -2, -2, -2], codes
+    codes.clear()
+    lo4 = lo.copy()
+    lo4[0] = 1
+    refused(c.set_interaction_lists, gf, lo4, en)                                              # offsets from 1
+    lo5 = lo.copy()
+    lo5[1], lo5[2] = lo[2], lo[1]
+    refused(c.set_interaction_lists, gf, lo5, en)                                              # decreasing
+    gf6 = gf.copy()
+    gf6[-1] = n - 1
+    refused(c.set_interaction_lists, gf6, lo, en)                                              # not up to N
+    assert codes == [-1, -1, -1], codes
+    with pytest.raises(ValueError):
+        c.set_interaction_lists(gf, lo[:-1], en)
+    with pytest.raises(ValueError):
+        c.set_interaction_lists(gf, lo, en[:-1])
+    # the lists set before the refusals are still in force
+    c.predict(0.125)
+    ids = np.arange(0, n, 3, dtype=np.int32)
+    got = c.force(ids)
+    want = oracle_list_force(oracle, 0.125, ids, t0, m, x, v, a, j, ptr, 1e-4)
+    assert_close("after refusals", "fp64", got, want)
+
+
 @pytest.mark.parametrize("path", ["async", "step", "graph"])
 def test_device_rows_out_of_range_are_dropped_and_reported(path):
     """Update rows whose particle indices sit in device memory are checked by
