@@ -259,13 +259,37 @@ def _ptr(a, ctype):
 _NONE7 = (None,) * 7
 
 
-def _dptr(t):
-    """Device address of a torch tensor (or an int address, or None)."""
+_TORCH_DTYPE = {"f64": "torch.float64", "i32": "torch.int32"}
+
+
+def _dptr(t, kind=None, count=0, what="array"):
+    """Device address of a torch tensor (or an int address, or None).  A
+    tensor must be a contiguous device tensor of `kind` ("f64", "i32") with
+    at least `count` elements, else ValueError: the library reads that many
+    from the address.  Int addresses are the caller's own and pass as they are."""
     if t is None:
         return None
     if isinstance(t, int):
         return t
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{what}: a contiguous device tensor is needed")
+    if kind is not None and str(t.dtype) != _TORCH_DTYPE[kind]:
+        raise ValueError(f"{what}: dtype {t.dtype}, expected {_TORCH_DTYPE[kind]}")
+    if t.numel() < count:
+        raise ValueError(f"{what}: {t.numel()} elements, the call reads {count}")
     return t.data_ptr()
+
+
+def _rows_ptrs(n, tensors):
+    """Addresses of update rows (idx, t0, m, x, v, a, jerk) for n rows."""
+    kinds = (("i32", 1, "idx"), ("f64", 1, "t0"), ("f64", 1, "m"), ("f64", 3, "x"), ("f64", 3, "v"),
+             ("f64", 3, "a"), ("f64", 3, "jerk"))
+    return tuple(_dptr(t, k, w * n, what) for t, (k, w, what) in zip(tensors, kinds))
+
+
+def _out_ptrs(n, d_acc, d_jerk, d_pot):
+    """Addresses of the outputs for n active particles."""
+    return (_dptr(d_acc, "f64", 3 * n, "acc"), _dptr(d_jerk, "f64", 3 * n, "jerk"), _dptr(d_pot, "f64", n, "pot"))
 
 
 # --------------------------------------------------------------------------------------------- device
@@ -316,13 +340,15 @@ class Context:
         t0 = _arr(np.broadcast_to(t0, (n,)), np.float64)
         x, v, a, jerk = (_arr(u, np.float64, (n, 3)) for u in (x, v, a, jerk))
         idx = None if idx is None else _arr(idx, np.int32)
+        if idx is not None and idx.shape != (n,):
+            raise ValueError(f"idx {idx.shape}: one index per row ({n})")
         d = ctypes.c_double
         _check(device_lib().ht_set_j_particles(self._h, n, _ptr(idx, ctypes.c_int32), _ptr(t0, d), _ptr(m, d),
                                                _ptr(x, d), _ptr(v, d), _ptr(a, d), _ptr(jerk, d)))
 
     def set_j_particles_async(self, n, d_idx, d_t0, d_m, d_x, d_v, d_a, d_jerk):
-        _check(device_lib().ht_set_j_particles_async(self._h, int(n), *(_dptr(t) for t in
-                                                                         (d_idx, d_t0, d_m, d_x, d_v, d_a, d_jerk))))
+        _check(device_lib().ht_set_j_particles_async(self._h, int(n),
+                                                     *_rows_ptrs(int(n), (d_idx, d_t0, d_m, d_x, d_v, d_a, d_jerk))))
 
     def set_nodes(self, t_tree, m, x, v, a, jerk):
         m = _arr(m, np.float64)
@@ -386,13 +412,13 @@ class Context:
 
     def force_async(self, active, d_acc, d_jerk, d_pot):
         active = _arr(active, np.int32)
-        _check(device_lib().ht_force_async(self._h, active.shape[0], _ptr(active, ctypes.c_int32), _dptr(d_acc),
-                                           _dptr(d_jerk), _dptr(d_pot)))
+        _check(device_lib().ht_force_async(self._h, active.shape[0], _ptr(active, ctypes.c_int32),
+                                           *_out_ptrs(active.shape[0], d_acc, d_jerk, d_pot)))
 
     def force_direct_async(self, active, d_acc, d_jerk, d_pot):
         active = _arr(active, np.int32)
         _check(device_lib().ht_force_direct_async(self._h, active.shape[0], _ptr(active, ctypes.c_int32),
-                                                  _dptr(d_acc), _dptr(d_jerk), _dptr(d_pot)))
+                                                  *_out_ptrs(active.shape[0], d_acc, d_jerk, d_pot)))
 
     def step_async(self, upd, t, active, d_acc, d_jerk, d_pot):
         """ht_step_async: upd = (n, d_idx, d_t0, d_m, d_x, d_v, d_a, d_jerk) or None
@@ -408,9 +434,9 @@ class Context:
         if upd is None:
             n_upd, ptrs = 0, _NONE7
         else:
-            n_upd, ptrs = upd[0], (upd[1:] if type(upd[1]) is int else tuple(_dptr(u) for u in upd[1:]))
+            n_upd, ptrs = upd[0], (upd[1:] if type(upd[1]) is int else _rows_ptrs(int(upd[0]), upd[1:]))
         if type(d_acc) is not int:
-            d_acc, d_jerk, d_pot = _dptr(d_acc), _dptr(d_jerk), _dptr(d_pot)
+            d_acc, d_jerk, d_pot = _out_ptrs(n_act, d_acc, d_jerk, d_pot)
         rc = self._step_async(self._h, n_upd, *ptrs, t, n_act, a_ptr, d_acc, d_jerk, d_pot)
         if rc:
             _check(rc)
@@ -421,9 +447,9 @@ class Context:
         if upd is None:
             n_upd, ptrs = 0, (None,) * 7
         else:
-            n_upd, ptrs = int(upd[0]), tuple(_dptr(u) for u in upd[1:])
+            n_upd, ptrs = int(upd[0]), _rows_ptrs(int(upd[0]), upd[1:])
         _check(device_lib().ht_step_graph(self._h, n_upd, *ptrs, float(t), active.shape[0], active.ctypes.data,
-                                          _dptr(d_acc), _dptr(d_jerk), _dptr(d_pot)))
+                                          *_out_ptrs(active.shape[0], d_acc, d_jerk, d_pot)))
 
     # device-resident integration ------------------------------------------------
     def state_enable(self, torch_memory=True):
@@ -547,9 +573,10 @@ def force_batch_async(ctxs, actives, d_accs, d_jerks, d_pots):
     H = (_vp * n)(*[c.handle for c in ctxs])
     N = (ctypes.c_int32 * n)(*[a.shape[0] for a in acts])
     P = (_c_i32p * n)(*[_ptr(a, ctypes.c_int32) for a in acts])
-    A = (_vp * n)(*[_dptr(t) for t in d_accs])
-    J = (_vp * n)(*[_dptr(t) for t in d_jerks])
-    Q = (_vp * n)(*[_dptr(t) for t in d_pots])
+    outs = [_out_ptrs(a.shape[0], *o) for a, o in zip(acts, zip(d_accs, d_jerks, d_pots))]
+    A = (_vp * n)(*[o[0] for o in outs])
+    J = (_vp * n)(*[o[1] for o in outs])
+    Q = (_vp * n)(*[o[2] for o in outs])
     _check(device_lib().ht_force_batch_async(n, H, N, P, A, J, Q))
     return acts  # keep host arrays alive until the caller syncs
 
@@ -626,9 +653,11 @@ def force_direct_noalloc(precision, d_x, d_v, d_m, eps2, d_active, j_splits, d_a
     n = int(d_m.shape[0]) if n is None else int(n)
     n_active = int(d_active.shape[0]) if n_active is None else int(n_active)
     st = getattr(stream, "cuda_stream", stream)
-    _check(device_lib().ht_force_direct_noalloc(int(device), st, HT_PREC[precision], n, _dptr(d_x), _dptr(d_v),
-                                                _dptr(d_m), float(eps2), n_active, _dptr(d_active), int(j_splits),
-                                                _dptr(d_acc), _dptr(d_jerk), _dptr(d_pot)))
+    _check(device_lib().ht_force_direct_noalloc(int(device), st, HT_PREC[precision], n,
+                                                _dptr(d_x, "f64", 3 * n, "x"), _dptr(d_v, "f64", 3 * n, "v"),
+                                                _dptr(d_m, "f64", n, "m"), float(eps2), n_active,
+                                                _dptr(d_active, "i32", n_active, "active"), int(j_splits),
+                                                *_out_ptrs(n_active, d_acc, d_jerk, d_pot)))
 
 
 class Batch:
@@ -720,9 +749,10 @@ class Batch:
         H = (_vp * n)(*[c.handle for c in ctxs])
         N = (ctypes.c_int32 * n)(*[a.shape[0] for a in acts])
         P = (_c_i32p * n)(*[_ptr(a, ctypes.c_int32) for a in acts])
-        A = (_vp * n)(*[_dptr(t) for t in d_accs])
-        J = (_vp * n)(*[_dptr(t) for t in d_jerks])
-        Q = (_vp * n)(*[_dptr(t) for t in d_pots])
+        outs = [_out_ptrs(a.shape[0], *o) for a, o in zip(acts, zip(d_accs, d_jerks, d_pots))]
+        A = (_vp * n)(*[o[0] for o in outs])
+        J = (_vp * n)(*[o[1] for o in outs])
+        Q = (_vp * n)(*[o[2] for o in outs])
         _check(device_lib().ht_batch_force_async(self._h, n, H, N, P, A, J, Q))
 
     def sync(self):

@@ -357,6 +357,53 @@ def test_capacities_and_list_checks(oracle):
     assert_close("after refusals", "fp64", got, want)
 
 
+def test_binding_refuses_mismatched_tensors():
+    """Device tensors handed to the binding are checked before the call (the
+    library reads counts the tensors must hold): too few elements, the wrong
+    dtype, a non-contiguous view or host memory raise ValueError and nothing
+    runs; the same call with proper tensors goes through."""
+    import torch
+    say("binding tensor checks")
+    n = 128
+    x, v, m = W.plummer(n, 9)
+    z = np.zeros((n, 3))
+    c = make_ctx("fp64", n, 0, 1, 1, 1e-4)
+    c.set_j_particles(0.0, m, x, v, z, z)
+    c.set_nodes(0.0, np.zeros(0), *(np.zeros((0, 3)) for _ in range(4)))
+    c.predict(0.0)
+    ids = np.arange(0, n, 2, dtype=np.int32)
+    k = ids.size
+    f64 = dict(dtype=torch.float64, device="cuda")
+    good = (torch.empty((k, 3), **f64), torch.empty((k, 3), **f64), torch.empty(k, **f64))
+    bad_outs = [
+        (torch.empty((k - 1, 3), **f64), good[1], good[2]),                 # too short
+        (good[0], good[1].float(), good[2]),                                 # float32
+        (good[0], torch.empty((3, 2 * k), **f64).t()[:k], good[2]),          # non-contiguous
+        (good[0], good[1], torch.empty(k, dtype=torch.float64)),             # host memory
+    ]
+    for outs in bad_outs:
+        with pytest.raises(ValueError):
+            c.force_direct_async(ids, *outs)
+        with pytest.raises(ValueError):
+            c.step_async(None, 0.0, ids, *outs)
+    dev = lambda u, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(u)).to(device="cuda", dtype=dt)  # noqa: E731
+    rows = (dev(np.arange(4), torch.int32), dev(np.zeros(4)), dev(m[:4]), dev(x[:4]), dev(v[:4]), dev(z[:4]),
+            dev(z[:4]))
+    with pytest.raises(ValueError):
+        c.set_j_particles_async(5, *rows)                                    # 5 rows from 4-row tensors
+    with pytest.raises(ValueError):
+        c.set_j_particles_async(4, rows[0].long(), *rows[1:])                # int64 indices
+    with pytest.raises(ValueError):
+        c.set_j_particles(0.0, m[:4], x[:4], v[:4], z[:4], z[:4], idx=np.arange(3, dtype=np.int32))
+    c.set_j_particles_async(4, *rows)
+    c.predict(0.0)
+    c.force_direct_async(ids, *good)
+    c.sync()
+    want = c.force_direct(ids)
+    for p_, q_ in zip(good, want):
+        assert np.array_equal(p_.cpu().numpy(), q_)
+
+
 @pytest.mark.parametrize("path", ["async", "step", "graph"])
 def test_device_rows_out_of_range_are_dropped_and_reported(path):
     """Update rows whose particle indices sit in device memory are checked by
