@@ -316,6 +316,7 @@ class Context:
         _check(L.ht_create(ctypes.byref(h), ctypes.byref(self.cfg), ws_ptr, self.workspace_bytes))
         self._h = h
         self._step_async = L.ht_step_async
+        self._n = 0   # particle count of the last full upload (the library writes that many in state_get)
 
     @property
     def handle(self):
@@ -345,6 +346,8 @@ class Context:
         d = ctypes.c_double
         _check(device_lib().ht_set_j_particles(self._h, n, _ptr(idx, ctypes.c_int32), _ptr(t0, d), _ptr(m, d),
                                                _ptr(x, d), _ptr(v, d), _ptr(a, d), _ptr(jerk, d)))
+        if idx is None:
+            self._n = n
 
     def set_j_particles_async(self, n, d_idx, d_t0, d_m, d_x, d_v, d_a, d_jerk):
         _check(device_lib().ht_set_j_particles_async(self._h, int(n),
@@ -474,10 +477,18 @@ class Context:
         arrs = [_arr(t0, np.float64), _arr(dt, np.float64), _arr(m, np.float64), _arr(x, np.float64, (n, 3)),
                 _arr(v, np.float64, (n, 3)), _arr(a, np.float64, (n, 3)), _arr(jerk, np.float64, (n, 3))]
         p = None if pot is None else _arr(pot, np.float64)
+        if any(u.shape != (n,) for u in arrs[:3] + ([p] if p is not None else [])):
+            raise ValueError(f"t0, dt, m (and pot) must hold {n} entries each")
         _check(device_lib().ht_state_set(self._h, n, *[_ptr(u, d) for u in arrs], _ptr(p, d)))
+        self._n = n
 
-    def state_get(self, n):
-        """ht_state_get: (t0, dt, x, v, a, jerk, pot) host copies of the device state."""
+    def state_get(self, n=None):
+        """ht_state_get: (t0, dt, x, v, a, jerk, pot) host copies of the device state
+        (its N entries; n, if given, must be N)."""
+        if n is None:
+            n = self._n
+        if n != self._n:
+            raise ValueError(f"the state holds {self._n} particles, not {n}")
         t0, dt, pot = np.empty(n), np.empty(n), np.empty(n)
         x, v, a, j = (np.empty((n, 3)) for _ in range(4))
         d = ctypes.c_double
@@ -514,6 +525,8 @@ class Context:
         """ht_state_rebuild: step 1 on the device for the resident state with the
         DeviceTree `tree`; returns perm (perm[new] = old), in `out` if given
         (int64, n entries; pinned memory makes the copy faster)."""
+        if n != self._n:
+            raise ValueError(f"the state holds {self._n} particles, not {n}")
         perm = np.empty(n, np.int64) if out is None else out
         if perm.dtype != np.int64 or perm.shape != (n,) or not perm.flags.c_contiguous:
             raise ValueError("out must be a contiguous int64 array of n entries")

@@ -42,6 +42,12 @@ def test_device_scheduler_matches_definition(n):
     got = c.state_get(n)
     for w, g in zip((t0, dt, x, v, a, j), got):
         assert np.array_equal(w, g)
+    # the binding refuses counts and arrays that do not match the state's N
+    with pytest.raises(ValueError):
+        c.state_get(n - 1)
+    with pytest.raises(ValueError):
+        c.state_set(t0, dt[:-1], m, x, v, a, j)
+    assert all(np.array_equal(w, g) for w, g in zip((t0, dt, x, v, a, j), c.state_get()))
     c.close()
 
 
