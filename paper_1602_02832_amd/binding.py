@@ -933,10 +933,22 @@ def hilbert_keys(q):
     return out
 
 
+def _host_f64(arr, shape, what):
+    """A C-contiguous float64 host array of the given shape, or ValueError (the
+    host library reads and writes these in place)."""
+    if not isinstance(arr, np.ndarray) or arr.dtype != np.float64 or not arr.flags.c_contiguous or arr.shape != shape:
+        raise ValueError(f"{what}: a C-contiguous float64 array of shape {shape} is needed")
+    return arr
+
+
 def next_block(t0, dt, out=None):
     """(t_next, active ids) of the next block step; t0, dt float64 [n]."""
     n = t0.shape[0]
+    _host_f64(t0, (n,), "t0")
+    _host_f64(dt, (n,), "dt")
     out = np.empty(n, np.int32) if out is None else out
+    if out.dtype != np.int32 or not out.flags.c_contiguous or out.shape[0] < n:
+        raise ValueError(f"out: a C-contiguous int32 array of at least {n} entries is needed")
     tn = ctypes.c_double()
     k = ctypes.c_int64()
     d = ctypes.c_double
@@ -952,8 +964,14 @@ def correct(ids, t1, eta, dt_tree, t0, dt, x, v, a, jerk, acc1, jerk1):
     ids = _arr(ids, np.int32)
     acc1 = _arr(acc1, np.float64, (-1, 3))
     jerk1 = _arr(jerk1, np.float64, (-1, 3))
-    for arr in (t0, dt, x, v, a, jerk):
-        assert arr.dtype == np.float64 and arr.flags.c_contiguous
+    n = t0.shape[0]
+    for arr, shape, what in ((t0, (n,), "t0"), (dt, (n,), "dt"), (x, (n, 3), "x"), (v, (n, 3), "v"),
+                             (a, (n, 3), "a"), (jerk, (n, 3), "jerk")):
+        _host_f64(arr, shape, what)
+    if acc1.shape != (ids.shape[0], 3) or jerk1.shape != (ids.shape[0], 3):
+        raise ValueError("acc1 and jerk1 need one row per id")
+    if ids.size and (ids.min() < 0 or ids.max() >= n):
+        raise ValueError(f"ids outside [0, {n})")
     d = ctypes.c_double
     rc = host_lib().htb_correct(ids.shape[0], _ptr(ids, ctypes.c_int32), float(t1), float(eta), float(dt_tree),
                                 _ptr(t0, d), _ptr(dt, d), _ptr(x, d), _ptr(v, d), _ptr(a, d), _ptr(jerk, d),
@@ -966,9 +984,11 @@ def correct(ids, t1, eta, dt_tree, t0, dt, x, v, a, jerk, acc1, jerk1):
 
 def cluster_struct(n, eta, dt_tree, t0, dt, x, v, a, jerk, m, pot, active):
     """HtbCluster pointing at the given arrays (which must stay alive and in place)."""
-    for arr in (t0, dt, x, v, a, jerk, m, pot):
-        assert arr.dtype == np.float64 and arr.flags.c_contiguous
-    assert active.dtype == np.int32 and active.flags.c_contiguous
+    for arr, shape, what in ((t0, (n,), "t0"), (dt, (n,), "dt"), (x, (n, 3), "x"), (v, (n, 3), "v"),
+                             (a, (n, 3), "a"), (jerk, (n, 3), "jerk"), (m, (n,), "m"), (pot, (n,), "pot")):
+        _host_f64(arr, shape, what)
+    if active.dtype != np.int32 or not active.flags.c_contiguous or active.shape[0] < n:
+        raise ValueError(f"active: a C-contiguous int32 array of at least {n} entries is needed")
     d = ctypes.c_double
     return HtbCluster(int(n), float(eta), float(dt_tree), _ptr(t0, d), _ptr(dt, d), _ptr(x, d), _ptr(v, d), _ptr(a, d),
                       _ptr(jerk, d), _ptr(m, d), _ptr(pot, d), _ptr(active, ctypes.c_int32), 0, 0.0)

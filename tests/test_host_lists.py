@@ -176,6 +176,42 @@ def _structs(cls):
 SIZES = (1, 3, 50, 8191, 8192, 8193, 20000, 40000)
 
 
+def test_host_wrappers_refuse_mismatched_arrays():
+    """The host corrector and scheduler work in place on the caller's arrays:
+    the binding refuses the wrong dtype, a non-contiguous view, mismatched
+    lengths, a too-short output and ids outside the arrays (the library would
+    read or write past them), and leaves the arrays untouched."""
+    n = 16
+    rng = np.random.default_rng(5)
+    t0, dt = np.zeros(n), np.full(n, 1.0 / 64)
+    x, v, a, j = rng.normal(size=(4, n, 3))
+    keep = [u.copy() for u in (t0, dt, x, v, a, j)]
+    ids = np.arange(4, dtype=np.int32)
+    a1, j1 = rng.normal(size=(2, 4, 3))
+    bad = [
+        dict(ids=np.array([0, n], dtype=np.int32)),                   # id past the arrays
+        dict(ids=np.array([-1], dtype=np.int32), a1=a1[:1], j1=j1[:1]),
+        dict(dt=dt[:-1]),                                             # short dt
+        dict(x=x.astype(np.float32)),                                 # float32
+        dict(v=np.asfortranarray(v)),                                 # not C-contiguous
+        dict(a1=a1[:3]),                                              # one acc row short
+    ]
+    for b in bad:
+        args = dict(ids=ids, t0=t0, dt=dt, x=x, v=v, a=a, j=j, a1=a1, j1=j1)
+        args.update(b)
+        with pytest.raises(ValueError):
+            B.correct(args["ids"], 1.0 / 64, 0.01, 1.0 / 8, args["t0"], args["dt"], args["x"], args["v"], args["a"],
+                      args["j"], args["a1"], args["j1"])
+    for w, g in zip(keep, (t0, dt, x, v, a, j)):
+        assert np.array_equal(w, g)
+    with pytest.raises(ValueError):
+        B.next_block(t0, dt.astype(np.float32))
+    with pytest.raises(ValueError):
+        B.next_block(t0, dt, out=np.empty(n - 1, np.int32))
+    tn, act = B.next_block(t0, dt)
+    assert tn == 1.0 / 64 and np.array_equal(act, np.arange(n))
+
+
 def test_next_block_many_matches_definition():
     """Batched next block (chunked across threads) vs the definition, per cluster:
     t_next = min(t0 + dt), the due particles in ascending order."""
