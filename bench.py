@@ -55,11 +55,11 @@ METRIC_ENSEMBLE = "batched ensemble (64 Plummer clusters, N 4096-65536): Hermite
 # only for the kernel source and the window (steps, warmup) it was taken on:
 # anything else makes the figure null until the counters are taken again.
 TRAFFIC = {
-    "kernel_source_sha256": "e8e1ffcf64e5e3cc0485cfa5a9e5c109e418caa1d7c833ff088543554add15ab",
+    "kernel_source_sha256": "f75cb0057275a324bd018934f3e91a513de77c7cec83f517ee5f0b78d63e4abc",
     "steps": 20,
     "warmup": 5,
-    "fetch_bytes_per_launch": 1.16097e8,   # FETCH_SIZE 56687.8 KiB x 2.000
-    "write_bytes_per_launch": 2.5293e5,    # WRITE_SIZE 247.0 KiB x 1.000
+    "fetch_bytes_per_launch": 1.16099e8,   # FETCH_SIZE 56689.2 KiB x 2.000
+    "write_bytes_per_launch": 2.5291e5,    # WRITE_SIZE 247.0 KiB x 1.000
     "fetch_scale": 2.000,                  # 1 GiB read by a plain copy reads 524294.5 KiB
     "write_scale": 1.000,                  # 1 GiB written reads 1048576 KiB
     "profile": "profiles/force_kernel_mixed_plummer1m_traffic.md",
